@@ -1,0 +1,38 @@
+"""CPU oracle for the coupled guiding-center / Boris pusher (TEST INFRASTRUCTURE).
+
+This package is the plain, slow, float64 definition against which the HIP
+path is checked.  Only the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark may import it; the product path never does.
+
+It shares no code with the HIP path.  Inputs (fields, particles) come from the
+separate ``workloads`` package, which holds no arithmetic of the method.
+
+Layout of the oracle:
+  fields.py   field providers: bilinear interpolation with a linear shape
+              function and its gradient on a staggered periodic grid (Sec. 4,
+              opening paragraph), plus closed-form providers used by the pins.
+  pusher.py   the local quantities (b, v_E, kappa, E_par, curvature terms),
+              the switch S (Sec. 4.1), the relativistic Boris push (Sec. 2.1),
+              the guiding-center leapfrog with and without curvature
+              (Sec. 2.2.1, 2.2.2), the variable conversions of the coupled
+              scheme (Sec. 3.1) and the multi-step driver.
+  loss.py     mean kinetic energy and its gradient by reverse-mode autograd of
+              the oracle itself (the oracle gradient of the adjoint checks).
+
+All arithmetic is IEEE binary64 with correctly rounded +, -, *, /, sqrt and
+no fused multiply-add: every product and sum is a separate torch operation.
+"""
+from .fields import (GridFields, UniformFields, LinearFields, CircularFields,
+                     FieldSample, YEE, COLLOCATED)
+from .pusher import (Params, State, ST_NONFINITE, ST_KAPPA, ST_QUAD, ST_BZERO,
+                     ST_FPRES, local, gamma_gca, v_curv, switch_gca, boris,
+                     gca_step, step, push, wrap, min_image, parallel_update)
+from .loss import kinetic_energy, push_gradients
+
+__all__ = [
+    "GridFields", "UniformFields", "LinearFields", "CircularFields",
+    "FieldSample", "YEE", "COLLOCATED", "Params", "State", "ST_NONFINITE",
+    "ST_KAPPA", "ST_QUAD", "ST_BZERO", "ST_FPRES", "local", "gamma_gca",
+    "v_curv", "switch_gca", "boris", "gca_step", "step", "push", "wrap",
+    "min_image", "parallel_update", "kinetic_energy", "push_gradients",
+]

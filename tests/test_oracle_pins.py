@@ -1,0 +1,553 @@
+"""Pins of the CPU oracle against closed forms, invariants and the paper's
+discrete equations.  No GPU.  Each test names what fixes the expected value.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle.fields import YEE, COLLOCATED, FieldSample
+
+F64 = torch.float64
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def T(*v):
+    return torch.tensor(v, dtype=F64)
+
+
+def params(**kw):
+    base = dict(dt=1.0, c=0.45, f_rho=0.4, f_E=1.0, curvature=True, n_iter=4,
+                Lx=1.0e6, Ly=1.0e6, dl=1.0)
+    base.update(kw)
+    return O.Params(**base)
+
+
+def state(x, y, ux, uy, uz, qm, xp=None, yp=None):
+    x, y = T(*x), T(*y)
+    return O.State(x, y, x.clone() if xp is None else T(*xp),
+                   y.clone() if yp is None else T(*yp), T(*ux), T(*uy), T(*uz),
+                   T(*qm), torch.zeros(len(x), dtype=torch.uint8))
+
+
+# ---------------------------------------------------------------- golden
+
+
+def test_golden_parameters_match_defaults():
+    """Defaults equal the values the paper fixes (Sec. 4.1, Sec. 2.2)."""
+    g = json.load(open(os.path.join(HERE, "golden", "paper_parameters.json")))
+    p = O.Params()
+    assert p.f_rho == g["sr_switch_thresholds"]["f_rho"]
+    assert p.f_E == g["sr_switch_thresholds"]["f_E"]
+    assert g["fixed_point_iterations"]["min"] <= p.n_iter <= g["fixed_point_iterations"]["max"]
+    assert p.fp_tol == g["fixed_point_iterations"]["abs_iteration_error"]
+
+
+# ---------------------------------------------------------------- P-1 interpolation
+
+
+@pytest.mark.parametrize("stagger", [YEE, COLLOCATED])
+def test_interp_reproduces_linear_fields(stagger):
+    """Bilinear W reproduces fields linear in x, y exactly (values and gradients)."""
+    rng = np.random.default_rng(1)
+    lin = O.LinearFields(E0=rng.normal(size=3), GE=rng.normal(size=(3, 2)),
+                         B0=rng.normal(size=3), GB=rng.normal(size=(3, 2)))
+    nx, ny, dx, dy = 40, 30, 0.5, 0.25
+    F = lin.sample_grid(nx, ny, dx, dy, stagger)
+    g = O.GridFields(F, dx, dy, stagger)
+    X = torch.as_tensor(rng.uniform(2 * dx, (nx - 3) * dx, 500))
+    Y = torch.as_tensor(rng.uniform(2 * dy, (ny - 3) * dy, 500))
+    a, b = g(X, Y), lin(X, Y)
+    for u, v in zip(a.E + a.B, b.E + b.B):
+        assert torch.allclose(u, v, rtol=0, atol=1e-12)
+    for j in range(2):
+        for u, v in zip(a.dB[j], b.dB[j]):
+            assert torch.allclose(u, v, rtol=0, atol=1e-11)
+
+
+def test_interp_partition_of_unity_and_periodicity():
+    """sum W = 1 (constant field exact), sum grad W = 0, and X ~ X + L."""
+    nx, ny = 16, 12
+    F = np.empty((6, ny, nx))
+    for k in range(6):
+        F[k] = 0.1 * (k + 1)
+    g = O.GridFields(F, 1.0, 1.0, YEE)
+    rng = np.random.default_rng(2)
+    X = torch.as_tensor(rng.uniform(-3, nx + 3, 300))
+    Y = torch.as_tensor(rng.uniform(-3, ny + 3, 300))
+    s = g(X, Y)
+    for k, v in enumerate(s.E + s.B):
+        assert torch.allclose(v, torch.full_like(v, 0.1 * (k + 1)), rtol=1e-15, atol=1e-15)
+    for j in range(2):
+        for v in s.dB[j]:
+            assert torch.all(v.abs() < 1e-15)
+    Fr = rng.normal(size=(6, ny, nx))
+    g = O.GridFields(Fr, 1.0, 1.0, YEE)
+    X = torch.as_tensor(rng.uniform(0, nx, 100))
+    Y = torch.as_tensor(rng.uniform(0, ny, 100))
+    s1, s2 = g(X, Y), g(X + nx, Y - 2 * ny)
+    for u, v in zip(s1.E + s1.B, s2.E + s2.B):
+        assert torch.allclose(u, v, rtol=0, atol=1e-12)
+
+
+def test_interp_at_nodes_returns_node_values():
+    """At a component's own node the gather returns that node's value (Yee offsets)."""
+    rng = np.random.default_rng(3)
+    nx, ny = 8, 6
+    F = rng.normal(size=(6, ny, nx))
+    g = O.GridFields(F, 1.0, 1.0, YEE)
+    for k in range(6):
+        sx, sy = YEE[k]
+        for (i, j) in [(0, 0), (3, 2), (7, 5)]:
+            X, Y = T(i + sx), T(j + sy)
+            v = g.component(k, X, Y, False)[0]
+            assert float(v) == F[k, j, i]
+
+
+# ---------------------------------------------------------------- switch (Sec. 4.1)
+
+
+def test_switch_thresholds_strict():
+    """S = 0 iff rho~/dl < f_rho and E/B < f_E (strict); B = 0 -> Boris."""
+    c = 0.5
+    p = params(c=c, f_rho=0.25, f_E=0.5, dl=1.0)
+    # particle at rest: Gamma = 1, rho~ = c^2/(|qm| B) = 0.25/|qm| with B = 1
+    s = O.UniformFields([0.0, 0.0, 0.0], [0.0, 0.0, 1.0])(T(0.0, 0.0, 0.0), T(0.0, 0.0, 0.0))
+    qm = T(-1.0, -1.0000001, 1.0000001)
+    z = torch.zeros(3, dtype=F64)
+    g = O.switch_gca(s, z, z, z, qm, p)
+    assert g.tolist() == [False, True, True]
+    # E/B exactly at f_E -> Boris; just below -> GCA
+    X = T(0.0, 0.0)
+    for E, want in [(0.5, False), (0.4999999, True)]:
+        s = O.UniformFields([E, 0.0, 0.0], [0.0, 0.0, 1.0])(X, X)
+        g = O.switch_gca(s, X * 0, X * 0, X * 0, T(-10.0, -10.0), p)
+        assert g.tolist() == [want, want]
+    s = O.UniformFields([0.0, 0.0, 0.0], [0.0, 0.0, 0.0])(X, X)
+    assert O.switch_gca(s, X * 0, X * 0, X * 0, T(-1e9, 1e9), p).tolist() == [False, False]
+
+
+def test_switch_gyro_radius_uses_full_gamma():
+    """rho~ grows with the Lorentz factor of the full u: a fast particle switches to Boris."""
+    c = 0.45
+    p = params(c=c, f_rho=0.4)
+    s = O.UniformFields([0.0, 0.0, 0.0], [0.0, 0.0, 1.0])(T(0.0, 0.0), T(0.0, 0.0))
+    qm = T(-1.0, -1.0)
+    # rho~/dl = c^2 Gamma / |qm| ; threshold Gamma* = 0.4/0.2025
+    gstar = 0.4 / (c * c)
+    u = [c * math.sqrt((0.99 * gstar) ** 2 - 1), c * math.sqrt((1.01 * gstar) ** 2 - 1)]
+    g = O.switch_gca(s, T(*u), T(0.0, 0.0), T(0.0, 0.0), qm, p)
+    assert g.tolist() == [True, False]
+
+
+# ---------------------------------------------------------------- P-2 Boris
+
+
+def run(prov, st, p, n):
+    traj = []
+    for _ in range(n):
+        st, S, _ = O.step(prov, st, p)
+        traj.append(st)
+    return st, traj
+
+
+def test_boris_uniform_B_exact_gyration():
+    """Uniform B, E = 0: |u| and u_par conserved; rotation angle 2 atan(|t|);
+    positions on a circle of radius (dt |u_perp|/Gamma)/(2 sin(theta/2))."""
+    c, B0, qm, dt = 0.45, 1.0, -0.3, 1.0
+    p = params(c=c, f_rho=0.0, dt=dt)   # f_rho = 0: always Boris
+    prov = O.UniformFields([0, 0, 0], [0, 0, B0])
+    uperp, upar = 0.2, 0.1
+    st = state([10.0], [10.0], [uperp], [0.0], [upar], [qm])
+    gam = math.sqrt(1 + (uperp ** 2 + upar ** 2) / c ** 2)
+    tmag = abs(qm) * dt * B0 / (2 * c * gam)
+    theta = 2 * math.atan(tmag)
+    r = (dt * uperp / gam) / (2 * math.sin(theta / 2))
+    st_end, traj = run(prov, st, p, 200)
+    us = torch.stack([torch.stack([s.ux, s.uy, s.uz]) for s in traj])[:, :, 0]
+    assert torch.allclose(us.norm(dim=1), torch.full((200,), math.hypot(uperp, upar), dtype=F64), rtol=1e-13)
+    assert torch.all((us[:, 2] - upar).abs() < 1e-15)
+    ang = torch.atan2(us[:, 1], us[:, 0])
+    d = torch.remainder(ang[1:] - ang[:-1] + math.pi, 2 * math.pi) - math.pi
+    # electrons (qm < 0) in +z B rotate counter-clockwise
+    assert torch.allclose(d, torch.full_like(d, theta), rtol=1e-11)
+    P = np.array([[float(s.x), float(s.y)] for s in traj])
+    # circumcentre of three points
+    (ax, ay), (bx, by), (cx, cy) = P[0], P[7], P[19]
+    dd = 2 * (ax * (by - cy) + bx * (cy - ay) + cx * (ay - by))
+    ux_ = ((ax**2 + ay**2) * (by - cy) + (bx**2 + by**2) * (cy - ay) + (cx**2 + cy**2) * (ay - by)) / dd
+    uy_ = ((ax**2 + ay**2) * (cx - bx) + (bx**2 + by**2) * (ax - cx) + (cx**2 + cy**2) * (bx - ax)) / dd
+    rad = np.hypot(P[:, 0] - ux_, P[:, 1] - uy_)
+    assert np.allclose(rad, r, rtol=1e-9)
+
+
+def test_boris_constant_E_acceleration():
+    """B = 0, constant E: u grows by (q/m) dt E per step."""
+    p = params(f_rho=0.4)
+    E = [0.01, -0.02, 0.005]
+    prov = O.UniformFields(E, [0, 0, 0])
+    qm = -0.7
+    st = state([5.0], [5.0], [0.0], [0.0], [0.0], [qm])
+    st_end, traj = run(prov, st, p, 100)
+    for comp, e in zip(("ux", "uy", "uz"), E):
+        got = float(getattr(st_end, comp)[0])
+        assert abs(got - 100 * qm * p.dt * e) < 1e-13
+
+
+def test_boris_ExB_drift():
+    """Resolved gyration in uniform E x B: mean velocity -> c E x B / B^2."""
+    c, B0, E0 = 0.45, 1.0, 0.02
+    p = params(c=c, f_rho=0.0, dt=0.05)
+    prov = O.UniformFields([E0, 0, 0], [0, 0, B0])
+    qm = -1.0
+    st = state([100.0], [100.0], [0.0], [0.0], [0.0], [qm])
+    omega = abs(qm) * B0 / c
+    steps = int(round(40 * 2 * math.pi / omega / p.dt))
+    y0 = 100.0
+    st_end, _ = run(prov, st, p, steps)
+    vy = (float(st_end.y) - y0) / (steps * p.dt)
+    vE = -c * E0 / B0            # c E x B / B^2, x_hat x z_hat = -y_hat
+    assert abs(vy - vE) < 0.03 * abs(vE)
+    assert abs(float(st_end.x) - 100.0) < 3 * (c * E0 / B0) / omega * 10
+
+
+def test_boris_gradB_drift():
+    """Boris branch, B = B0 (1 + g y) z: gyro-averaged drift
+    (c u_perp^2/(2 (q/m) Gamma B^2)) b x grad B."""
+    c, B0, g = 0.45, 1.0, 1e-2
+    dt = 0.02
+    p = params(c=c, f_rho=0.0, dt=dt)
+    # Bz = B0 (1 + g (y - 500)): the particle gyrates around y = 500, far from the wrap
+    prov = O.LinearFields([0, 0, 0], np.zeros((3, 2)), [0, 0, B0 * (1 - 500 * g)],
+                          [[0, 0], [0, 0], [0, B0 * g]])
+    qm, uperp = -1.0, 0.1
+    gam = math.sqrt(1 + uperp ** 2 / c ** 2)
+    theta = 2 * math.atan(abs(qm) * dt * B0 / (2 * c * gam))
+    per = 2 * math.pi / theta                       # steps per discrete gyration
+    n_orb = 40
+    steps = int(round((n_orb + 1) * per))
+    st = state([500.0], [500.0], [uperp], [0.0], [0.0], [qm])
+    _, traj = run(prov, st, p, steps)
+    xs = np.array([float(s.x) for s in traj])
+    w = int(round(per))
+    x_first = xs[:w].mean()
+    x_last = xs[int(round(n_orb * per)):int(round(n_orb * per)) + w].mean()
+    vx = (x_last - x_first) / (int(round(n_orb * per)) * dt)
+    # b x grad B = z x (B0 g y_hat) = -B0 g x_hat ; guiding centre sits near y ~ 500
+    v_expect = (c * uperp ** 2 / (2 * qm * gam * B0 ** 2)) * (-B0 * g)
+    assert abs(vx - v_expect) < 0.05 * abs(v_expect)
+
+
+def test_gca_no_gradB_drift_at_zero_upar():
+    """The paper's reduced GCA keeps no grad-B drift: with u_par = 0, E = 0 the centre stays put."""
+    c, B0, g = 0.45, 1.0, 1e-2
+    p = params(c=c, f_rho=1e9, dt=1.0)
+    prov = O.LinearFields([0, 0, 0], np.zeros((3, 2)), [0, 0, B0], [[0, 0], [0, 0], [0, B0 * g]])
+    st = state([3.0], [4.0], [0.05], [0.0], [0.0], [-100.0])
+    st2, _ = run(prov, st, p, 5)
+    assert float(st2.x) == 3.0 and float(st2.y) == 4.0
+
+
+# ---------------------------------------------------------------- P-3 GCA, uniform fields
+
+
+def _uniform_gca_expect(E, B, u, qm, c, dt):
+    """Closed form of one step in uniform fields (paper eqs. dRdtcase2disc,
+    dupardtcase2disc with all gradients zero): u_par += (q/m) dt E_par and
+    R += dt (u_par b / Gamma + v_E), Gamma = kappa sqrt(1 + (u_par^2 + u_perp_g^2)/c^2)."""
+    E, B, u = map(lambda a: np.array(a, dtype=np.float64), (E, B, u))
+    Bm = np.linalg.norm(B)
+    b = B / Bm
+    vE = c * np.cross(E, B) / Bm ** 2
+    kap = 1 / math.sqrt(1 - vE @ vE / c ** 2)
+    gf = math.sqrt(1 + u @ u / c ** 2)
+    upar = u @ b
+    uperp = u - upar * b - vE * gf
+    upar_new = upar + qm * dt * (E @ b)
+    gam = kap * math.sqrt(1 + (upar_new ** 2 + uperp @ uperp) / c ** 2)
+    dR = dt * (upar_new * b / gam + vE)
+    u_new = upar_new * b + vE * gam + uperp
+    return dR, u_new
+
+
+@pytest.mark.parametrize("curv", [True, False])
+def test_gca_uniform_fields_closed_form(curv):
+    c, dt = 0.45, 1.0
+    p = params(c=c, f_rho=1e9, f_E=1e9, curvature=curv, dt=dt, n_iter=4)
+    E = [0.03, -0.05, 0.01]
+    B = [0.2, 0.4, 0.8]
+    u = [0.05, 0.1, -0.02]
+    qm = -3.0
+    prov = O.UniformFields(E, B)
+    st = state([7.0], [9.0], *[[v] for v in u], [qm])
+    st2, S, _ = O.step(prov, st, p)
+    assert not bool(S[0])
+    dR, u_new = _uniform_gca_expect(E, B, u, qm, c, dt)
+    assert abs(float(st2.x) - 7.0 - dR[0]) < 1e-14
+    assert abs(float(st2.y) - 9.0 - dR[1]) < 1e-14
+    got = np.array([float(st2.ux), float(st2.uy), float(st2.uz)])
+    assert np.allclose(got, u_new, rtol=0, atol=1e-14)
+    assert float(st2.xp) == 7.0 and float(st2.yp) == 9.0
+
+
+def test_gca_pure_drift_round_trip():
+    """u = kappa v_E (u_par = 0, mu = 0) is reproduced after a step in uniform ideal fields."""
+    c = 0.45
+    p = params(c=c, f_rho=1e9, f_E=1e9)
+    E = np.array([0.0, 0.3, 0.0])
+    B = np.array([0.0, 0.0, 1.0])
+    vE = c * np.cross(E, B) / (B @ B)
+    kap = 1 / math.sqrt(1 - vE @ vE / c ** 2)
+    u = kap * vE
+    prov = O.UniformFields(E, B)
+    st = state([1.0], [2.0], [u[0]], [u[1]], [u[2]], [-50.0])
+    st2, _, _ = O.step(prov, st, p)
+    got = np.array([float(st2.ux), float(st2.uy), float(st2.uz)])
+    assert np.allclose(got, u, rtol=1e-14, atol=1e-16)
+    assert abs(float(st2.x) - 1.0 - p.dt * vE[0]) < 1e-14
+
+
+def test_gca_E0_preserves_speed():
+    """E = 0, uniform B: decompose/reconstruct keeps u exactly up to rounding."""
+    p = params(f_rho=1e9)
+    prov = O.UniformFields([0, 0, 0], [0.3, -0.2, 0.9])
+    st = state([1.0], [2.0], [0.1], [-0.2], [0.15], [-20.0])
+    st2, traj = run(prov, st, p, 50)
+    u0 = np.array([0.1, -0.2, 0.15])
+    got = np.array([float(st2.ux), float(st2.uy), float(st2.uz)])
+    assert np.allclose(got, u0, rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- P-4 parallel update
+
+
+def _curved_local(seed=0):
+    """local() quantities at a few points of a curved field with E."""
+    rng = np.random.default_rng(seed)
+    lin = O.LinearFields(E0=[0.01, -0.02, 0.0], GE=np.zeros((3, 2)),
+                         B0=[0.3, 0.2, 1.0], GB=0.05 * rng.normal(size=(3, 2)))
+    X = torch.as_tensor(rng.uniform(-3, 3, 16))
+    Y = torch.as_tensor(rng.uniform(-3, 3, 16))
+    return lin, X, Y
+
+
+def test_parallel_update_satisfies_discrete_equation():
+    """u_par^{n+1/2} from the quadratic satisfies eq. dupardtcase2disc with
+    Gamma(R^n, u_par^{n+1/2}) from eq. lfacgca2."""
+    c, dt = 0.45, 1.0
+    p = params(c=c, dt=dt)
+    lin, X, Y = _curved_local()
+    L = O.local(lin, X, Y, p)
+    assert torch.all(L.C.abs() > 0)
+    rng = np.random.default_rng(5)
+    upar = torch.as_tensor(rng.normal(0, 0.5, 16))
+    mu = torch.as_tensor(rng.uniform(0, 0.05, 16))
+    qm = torch.full((16,), -2.0, dtype=F64)
+    un, fl = O.parallel_update(L, upar, mu, qm, p)
+    assert torch.all(fl == 0)
+    g0 = O.gamma_gca(L, upar, mu, p)
+    g1 = O.gamma_gca(L, un, mu, p)
+    lhs = (un - upar) / dt
+    rhs = qm * L.Epar + 0.5 * (upar + un) * L.A + 0.5 * (g0 + g1) * L.C
+    assert torch.allclose(lhs, rhs, rtol=1e-12, atol=1e-14)
+
+
+def test_parallel_update_no_curvature_terms_closed_form():
+    """With A = C = 0 the root is Gamma = kappa sqrt(1 + ((u')^2 + 2 mu B kappa)/c^2) and
+    u_par^{n+1/2} = u_par + (q/m) dt E_par."""
+    from types import SimpleNamespace
+    p = params()
+    n = 5
+    z = torch.zeros(n, dtype=F64)
+    L = SimpleNamespace(A=z, C=z, B=torch.full((n,), 1.3, dtype=F64),
+                        kappa=torch.full((n,), 1.1, dtype=F64),
+                        Epar=torch.linspace(-0.1, 0.1, n, dtype=F64))
+    upar = torch.linspace(-1, 1, n, dtype=F64)
+    mu = torch.full((n,), 0.01, dtype=F64)
+    qm = torch.full((n,), -2.0, dtype=F64)
+    un, fl = O.parallel_update(L, upar, mu, qm, p)
+    assert torch.all(fl == 0)
+    assert torch.allclose(un, upar + qm * p.dt * L.Epar, rtol=0, atol=1e-15)
+
+
+def test_parallel_update_fallback_flag():
+    """k1 >= 0 (curvature kick exceeding c) has no admissible root: flagged, finite result."""
+    from types import SimpleNamespace
+    p = params()
+    one = torch.ones(1, dtype=F64)
+    L = SimpleNamespace(A=0 * one, C=10.0 * one, B=one, kappa=one, Epar=0 * one)
+    un, fl = O.parallel_update(L, 0.1 * one, 0 * one, -one, p)
+    assert int(fl[0]) == O.ST_QUAD and torch.isfinite(un).all()
+
+
+# ---------------------------------------------------------------- P-5 curvature
+
+
+def test_curvature_vector_circular_field():
+    """B = B0 e_phi: (b.grad)b = -r_hat/r; v_c = c u_par^2/(q/m B Gamma r) z_hat for E = 0."""
+    c = 0.45
+    p = params(c=c)
+    prov = O.CircularFields(B0=2.0, xc=0.0, yc=0.0)
+    th = torch.linspace(0.1, 6.0, 9, dtype=F64)
+    r = torch.linspace(3.0, 11.0, 9, dtype=F64)
+    X, Y = r * torch.cos(th), r * torch.sin(th)
+    L = O.local(prov, X, Y, p)
+    assert torch.allclose(L.bgb[0], -torch.cos(th) / r, atol=1e-14)
+    assert torch.allclose(L.bgb[1], -torch.sin(th) / r, atol=1e-14)
+    assert torch.all(L.bgb[2].abs() < 1e-15)
+    upar = torch.full_like(r, 0.3)
+    mu = torch.zeros_like(r)
+    gam = O.gamma_gca(L, upar, mu, p)
+    qm = -5.0
+    vc = O.v_curv(L, upar, gam, torch.full_like(r, 1 / qm), p)
+    expect = c * upar ** 2 / (qm * 2.0 * gam * r)
+    assert torch.allclose(vc[2], expect, rtol=1e-13)
+    assert torch.all(vc[0].abs() < 1e-16) and torch.all(vc[1].abs() < 1e-16)
+
+
+def test_grad_b_matches_finite_differences():
+    """d_j b_i from the chain rule equals finite differences of b = B/|B|, and so
+    do (b.grad)b and (v_E.grad)b."""
+    c = 0.45
+    p = params(c=c)
+    rng = np.random.default_rng(7)
+    lin = O.LinearFields(E0=[0.02, 0.01, -0.03], GE=0.01 * rng.normal(size=(3, 2)),
+                         B0=[0.5, -0.3, 1.0], GB=0.1 * rng.normal(size=(3, 2)))
+    X = torch.as_tensor(rng.uniform(-1, 1, 8))
+    Y = torch.as_tensor(rng.uniform(-1, 1, 8))
+    L = O.local(lin, X, Y, p)
+    h = 1e-6
+
+    def bvec(X, Y):
+        s = lin(X, Y)
+        Bm = torch.sqrt(sum(v * v for v in s.B))
+        return [v / Bm for v in s.B]
+    dbx = [(a - b) / (2 * h) for a, b in zip(bvec(X + h, Y), bvec(X - h, Y))]
+    dby = [(a - b) / (2 * h) for a, b in zip(bvec(X, Y + h), bvec(X, Y - h))]
+    bx, by, _ = L.b
+    vx, vy, _ = L.vE
+    for i in range(3):
+        assert torch.allclose(L.bgb[i], bx * dbx[i] + by * dby[i], atol=1e-9)
+        assert torch.allclose(L.vgb[i], vx * dbx[i] + vy * dby[i], atol=1e-9)
+
+
+# ---------------------------------------------------------------- P-6 fixed point
+
+
+def test_fixed_point_converges_to_trapezoidal_solution():
+    """With many iterations R^{n+1} satisfies eq. dRdtcase2disc to rounding, and the
+    K = 4 result is within the contraction estimate of it."""
+    from workloads import make_config
+    cfg = make_config("harris64")
+    prov = O.GridFields(cfg.fields(), 1.0, 1.0, cfg.stagger)
+    ens = cfg.particles(n=256)
+    st = O.State.from_numpy(ens)
+    p60 = params(Lx=cfg.Lx, Ly=cfg.Ly, n_iter=60, f_rho=1e9, f_E=1e9)
+    Lx = cfg.Lx
+    # only particles whose first step is well inside GCA validity (E < B at x^n)
+    st2, _, res = O.step(prov, st, p60)
+    ok = res < 1e-13
+    assert ok.float().mean() > 0.9
+    # evaluate the trapezoidal equation at the returned R^{n+1} (unwrapped)
+    dx = O.min_image(st2.x - st.x, Lx)
+    dy = O.min_image(st2.y - st.y, cfg.Ly)
+    Rx, Ry = st.x + dx, st.y + dy
+    # reconstruct u_par^{n+1/2} and mu the same way the step does
+    from oracle.pusher import _drift_terms
+    Rhx = st.x - 0.5 * O.min_image(st.x - st.xp, Lx)
+    Rhy = st.y - 0.5 * O.min_image(st.y - st.yp, cfg.Ly)
+    Lh = O.local(prov, Rhx, Rhy, p60)
+    upar = (st.ux * Lh.b[0] + st.uy * Lh.b[1]) + st.uz * Lh.b[2]
+    gf = torch.sqrt(1 + (st.ux ** 2 + st.uy ** 2 + st.uz ** 2) / p60.c2)
+    vc = O.v_curv(Lh, upar, gf, 1 / st.qm, p60)
+    up = [(u - upar * b) - (v + w) * gf for u, b, v, w in
+          zip((st.ux, st.uy, st.uz), Lh.b, Lh.vE, vc)]
+    mu = 0.5 * (up[0] ** 2 + up[1] ** 2 + up[2] ** 2) * Lh.inv_B / Lh.kappa
+    Ln = O.local(prov, st.x, st.y, p60)
+    un, _ = O.parallel_update(Ln, upar, mu, st.qm, p60)
+    L1 = O.local(prov, Rx, Ry, p60)
+    F0 = _drift_terms(Ln, un, mu, 1 / st.qm, p60)
+    F1 = _drift_terms(L1, un, mu, 1 / st.qm, p60)
+    Hx = Rx - st.x - 0.5 * p60.dt * (F0[0] + F1[0])
+    Hy = Ry - st.y - 0.5 * p60.dt * (F0[1] + F1[1])
+    assert torch.all(Hx[ok].abs() < 1e-12) and torch.all(Hy[ok].abs() < 1e-12)
+    # K = 4 agrees with the converged solution to within the reported residual scale
+    p4 = params(Lx=cfg.Lx, Ly=cfg.Ly, n_iter=4, f_rho=1e9, f_E=1e9)
+    st4, _, res4 = O.step(prov, st, p4)
+    d4 = torch.maximum(O.min_image(st4.x - st2.x, Lx).abs(), O.min_image(st4.y - st2.y, cfg.Ly).abs())
+    assert torch.all(d4[ok] <= 2 * res4[ok] + 1e-14)
+
+
+# ---------------------------------------------------------------- P-7 order of accuracy
+
+
+def _final_pos(prov, st0, p, T_end):
+    n = int(round(T_end / p.dt))
+    st, _ = run(prov, st0.clone(), p, n)
+    return np.array([float(st.x), float(st.y)])
+
+
+def test_boris_second_order():
+    """Boris is second order: successive refinement differences shrink by ~4.
+    Uniform B; u^{-1/2} is the exact four-velocity half a step before t = 0
+    (a rotation by -omega dt/2), so the start is consistent at every dt."""
+    c, qm, B0 = 0.45, -0.2, 1.0
+    prov = O.UniformFields([0.0, 0.0, 0.0], [0.0, 0.0, B0])
+    u0 = np.array([0.2, 0.05, 0.03])
+    gam = math.sqrt(1 + u0 @ u0 / c ** 2)
+    om = abs(qm) * B0 / (c * gam)     # electrons in +z B turn counter-clockwise
+    xs = []
+    for dt in (0.4, 0.2, 0.1):
+        a = -om * dt / 2
+        ux = u0[0] * math.cos(a) - u0[1] * math.sin(a)
+        uy = u0[0] * math.sin(a) + u0[1] * math.cos(a)
+        st0 = state([50.0], [50.0], [ux], [uy], [u0[2]], [qm])
+        xs.append(_final_pos(prov, st0, params(f_rho=0.0, dt=dt), 40.0))
+    d1, d2 = np.linalg.norm(xs[0] - xs[1]), np.linalg.norm(xs[1] - xs[2])
+    assert 3.5 < d1 / d2 < 4.5
+
+
+@pytest.mark.parametrize("curv", [True, False])
+def test_gca_second_order(curv):
+    """Guiding-center leapfrog is second order for a pure E x B drift in a
+    non-uniform B (u = kappa v_E, so the per-step conversions are exact):
+    refinement differences shrink by ~4."""
+    lin = O.LinearFields([0.1, 0.05, 0.0], np.zeros((3, 2)), [0.0, 0.0, 1.0 - 0.01 * 500],
+                         [[0, 0], [0, 0], [0.004, 0.01]])
+    X = T(500.0)
+    L0 = O.local(lin, X, X, params())
+    u = [float(L0.kappa * v) for v in L0.vE]
+    xs = []
+    for dt in (0.8, 0.4, 0.2):
+        st0 = state([500.0], [500.0], [u[0]], [u[1]], [u[2]], [-100.0],
+                    xp=[500.0 - dt * float(L0.vE[0])], yp=[500.0 - dt * float(L0.vE[1])])
+        p = params(f_rho=1e9, f_E=1e9, dt=dt, n_iter=40, curvature=curv)
+        xs.append(_final_pos(lin, st0, p, 40.0))
+    d = [np.linalg.norm(xs[i] - xs[i + 1]) for i in range(2)]
+    assert 3.5 < d[0] / d[1] < 4.5
+
+
+# ---------------------------------------------------------------- status flags
+
+
+def test_kappa_clamp_flag():
+    """E > B inside the guiding-center branch (forced by f_E) clamps kappa and flags it."""
+    p = params(f_rho=1e9, f_E=1e9)
+    prov = O.UniformFields([0.0, 2.0, 0.0], [0.0, 0.0, 1.0])
+    st = state([1.0], [1.0], [0.0], [0.0], [0.0], [-100.0])
+    st2, _, _ = O.step(prov, st, p)
+    assert int(st2.status[0]) & O.ST_KAPPA
+
+
+def test_wrap_and_min_image():
+    L = 64.0
+    x = T(-1e-17, 0.0, 63.999999, 64.0, 130.5, -64.5)
+    w = O.wrap(x, L)
+    assert torch.all((w >= 0) & (w < L))
+    assert torch.allclose(w[2:], T(63.999999, 0.0, 2.5, 63.5))
+    d = T(31.9, 32.0, -32.0, 40.0, -40.0)
+    assert O.min_image(d, L).tolist() == [31.9, -32.0, -32.0, -24.0, 24.0]
