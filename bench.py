@@ -1,0 +1,194 @@
+"""Benchmark: particle-steps/s of the coupled guiding-center/Boris push on one
+MI355X, with the HBM roofline fraction of the push kernel and the CPU oracle
+timed beside it.
+
+Workload (default): a 4096 x 4096 periodic double Harris sheet with guide
+field, tearing perturbation, inflow E and reconnection E_z at the X points
+(fields in binary64, 805 MB); 1e7 electrons (half Maxwell-Juttner theta = 1,
+half a Gamma^-2 power law to 1e4), about 70 % in the guiding-center regime;
+binary64 plain path, curvature terms on, K = 4 fixed-point iterations,
+cell-sorted every 4 steps, LDS-tiled kernel.  A step is one time step of the
+whole population: cell sort (every 4th step), switch, per-regime queues,
+Boris and guiding-center updates.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/sec at 1e7 particles (fwd, fwd+adjoint) + % HBM peak"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
+FP64_VECTOR_PEAK_TF = 78.6      # MI355X FP64 vector, AMD published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def push_bytes_per_step(n: int, nx: int, ny: int, form: int) -> int:
+    """Algorithmic HBM bytes of one push launch: the state read and written once
+    (x, y, xp, yp as binary64; u as binary64 or binary32; the status byte) plus
+    the field grid read once (6 components per node)."""
+    ub = 8 if form == 0 else 4
+    fb = 8 if form == 0 else 4
+    state = n * 2 * (4 * 8 + 3 * ub + 1)
+    fields = nx * ny * 6 * fb
+    return state + fields
+
+
+def cpu_baseline(cfg, F, ens, budget_s: float = 12.0):
+    """The CPU oracle (torch float64) on a bounded sample of the same workload."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    n = 20000
+    rng = np.random.default_rng(5)
+    sub = ens.subset(np.sort(rng.choice(ens.n, n, replace=False)))
+    p = O.Params(dt=cfg.dt, c=cfg.c, f_rho=cfg.f_rho, f_E=cfg.f_E, curvature=True,
+                 n_iter=cfg.n_iter, Lx=cfg.Lx, Ly=cfg.Ly, dl=math.sqrt(cfg.dx * cfg.dy))
+    prov = O.GridFields(F, cfg.dx, cfg.dy, cfg.stagger)
+    st = O.State.from_numpy(sub)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        st, _, _ = O.step(prov, st, p)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= cfg.steps:
+            break
+    return {"value": n * steps / el, "unit": "particle-steps/s",
+            "cores": int(torch.get_num_threads()), "kind": "oracle",
+            "sample": f"{n} random particles of the workload x {steps} steps "
+                      f"({el:.1f} s, torch CPU float64)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--config", default="harris4096")
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--kernel", type=int, default=0)
+    ap.add_argument("--sort-every", type=int, default=4)
+    ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--f-rho", type=float, default=None)
+    ap.add_argument("--f-E", type=float, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    a = ap.parse_args()
+
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the pusher has no "
+              "cross-GPU work in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2007_14401_amd import gcb, state
+    from workloads import make_config
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    over = {}
+    if a.f_rho is not None:
+        over["f_rho"] = a.f_rho
+    if a.f_E is not None:
+        over["f_E"] = a.f_E
+    cfg = make_config(a.config, **over)
+    n = cfg.n if a.n is None else a.n
+    log(f"[bench] generating {cfg.name}: {cfg.nx}x{cfg.ny}, n={n}")
+    F = cfg.fields()
+    ens = cfg.particles(n=n)
+
+    dev = torch.device("cuda:0")
+    ctx = gcb.gcb_create(0)
+    desc = gcb.grid_desc(cfg.nx, cfg.ny, cfg.dx, cfg.dy, cfg.stagger, gcb.GCB_F64)
+    gcb.gcb_load_fields(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
+    t = state.to_device(ens, dev, per_particle_qm=False)
+    parts = gcb.particles(t)
+    prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                     curvature=cfg.curvature, n_iter=cfg.n_iter, sort_every=a.sort_every,
+                     kernel=a.kernel, tile=a.tile)
+
+    log(f"[bench] warmup {a.warmup} steps")
+    st = gcb.gcb_push(ctx, parts, prm, a.warmup, want_stats=True)
+    log(f"[bench] warmup stats {st}")
+    torch.cuda.synchronize()
+
+    gcb.gcb_set_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gcb.gcb_push(ctx, parts, prm, a.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, cnt = gcb.gcb_get_timing(ctx)
+    gcb.gcb_set_timing(ctx, False)
+    wall = t1 - t0
+    log(f"[bench] timed {a.steps} steps in {wall:.3f} s; kernel ms {ms} launches {cnt}")
+
+    st = gcb.gcb_push(ctx, parts, prm, 1, want_stats=True)
+    gca_frac = st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])
+
+    push_ms = ms[gcb.GCB_TIMER_PUSH] / max(1, cnt[gcb.GCB_TIMER_PUSH])
+    sort_ms = ms[gcb.GCB_TIMER_SORT] / max(1, cnt[gcb.GCB_TIMER_SORT])
+    bytes_step = push_bytes_per_step(n, cfg.nx, cfg.ny, 0)
+    achieved = bytes_step / (push_ms * 1e-3) / 1e9
+    value = n * a.steps / wall
+
+    if a.copy_calib:
+        x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny} periodic double Harris sheet "
+                               f"(guide 0.1 B0, tearing, inflow E, reconnection Ez at X points),"
+                               f" {n} electrons MJ theta=1 + Gamma^-2 power law to 1e4, "
+                               f"binary64 plain path, curvature on, K={cfg.n_iter}",
+                   "particles": n, "grid": [cfg.nx, cfg.ny], "form": "f64",
+                   "kernel": ["auto", "global", "tiled"][a.kernel],
+                   "sort_every": a.sort_every, "tile": a.tile,
+                   "gca_fraction": round(gca_frac, 4)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_push_tiled" if a.kernel != 1 else "k_push_global",
+                     "kernel_ms": push_ms, "algorithmic_bytes_per_launch": bytes_step},
+        "sort_ms_per_sort": sort_ms,
+    }
+    if not a.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(cfg, F, ens)
+    gcb.gcb_destroy(ctx)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * gcb.h -- C ABI of libgcb, an MI355X (gfx950) implementation of the coupled
+ * guiding-center / Boris particle pusher of Bacchini, Ripperda, Philippov &
+ * Parfrey, "A coupled guiding center-Boris particle pusher for magnetized
+ * plasmas in compact-object magnetospheres" (arXiv:2007.14401).
+ *
+ * Problem (Sec. 4, opening paragraph; Sec. 3.1): test particles that do not
+ * act back on the fields are advanced through static E and B given on a grid.
+ * At every step each particle is tested against the switch of Sec. 4.1 and
+ * advanced either with the relativistic Boris push (Sec. 2.1) or with the
+ * guiding-center leapfrog (Sec. 2.2.1 without, Sec. 2.2.2 with curvature
+ * terms), converting to guiding-center variables and back (Sec. 3.1).
+ *
+ * Conventions shared by every entry point
+ *   - Gaussian units with explicit c.  u is the spatial part of the
+ *     four-velocity in velocity units (u = Gamma v), Gamma = sqrt(1+u^2/c^2).
+ *   - 2D3V: positions (x, y) on a periodic box [0, nx*dx) x [0, ny*dy);
+ *     u, E and B have three components; nothing depends on z.
+ *   - Leapfrog staggering (Sec. 2.1): x^n at integer levels, u^{n-1/2} at
+ *     half levels; the state also carries the previous position x^{n-1},
+ *     needed for the midpoint R^{n-1/2} of the variable conversion (Sec. 3.1).
+ *   - All array arguments of gcb_push / gcb_push_backward /
+ *     gcb_kinetic_energy are DEVICE pointers on the context's device, owned
+ *     by the caller, 8-byte aligned.  Field arrays handed to gcb_load_fields
+ *     may be host or device pointers (see `src`).
+ *   - Streams are passed as `void*` holding a hipStream_t (NULL = the null
+ *     stream).  Work is enqueued on that stream; calls return without a
+ *     device synchronisation unless stats or timings are requested.
+ *   - Every int-returning call returns GCB_OK (0) or a negative code and
+ *     never aborts; gcb_last_error(ctx) gives a message.  Arguments are
+ *     validated before any device work is enqueued.
+ *   - One context per host thread; a context is bound to one device.
+ */
+#ifndef GCB_H
+#define GCB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define GCB_OK            0
+#define GCB_EINVAL       -1   /* invalid argument (null pointer, bad size, bad enum) */
+#define GCB_ENOFIELDS    -2   /* gcb_push before gcb_load_fields */
+#define GCB_ENOMEM       -3   /* device allocation failed */
+#define GCB_EHIP         -4   /* a HIP runtime call failed (message has the HIP error) */
+#define GCB_EUNSUPPORTED -5   /* valid request this build cannot serve */
+
+/* precision of the device copy of the fields (gcb_grid_desc.dtype) */
+#define GCB_F64 0
+#define GCB_F32 1
+
+/* arithmetic form (gcb_params.form) */
+#define GCB_FORM_F64   0   /* everything in binary64; state u is double */
+#define GCB_FORM_MIXED 1   /* binary32 bulk arithmetic, binary64 positions and
+                              selected quantities; state u is float; needs
+                              fields loaded with dtype GCB_F32 */
+
+/* where field arrays live (gcb_load_fields.src) */
+#define GCB_HOST   0
+#define GCB_DEVICE 1
+
+/* kernel choice (gcb_params.kernel) */
+#define GCB_KERNEL_AUTO   0   /* tiled when sort_every > 0 and the grid allows it */
+#define GCB_KERNEL_GLOBAL 1   /* one lane per particle, gathers through the caches */
+#define GCB_KERNEL_TILED  2   /* cell-sorted particles, LDS field tiles, per-regime queues */
+
+/* sticky per-particle status bits (gcb_particles.status) */
+#define GCB_ST_NONFINITE 1    /* a non-finite position or four-velocity was produced   */
+#define GCB_ST_KAPPA     2    /* v_E >= c at a guiding-center evaluation; 1 - v_E^2/c^2
+                                 clamped to 1e-12                                        */
+#define GCB_ST_QUAD      4    /* parallel update (Sec. 2.2.2) had no admissible root     */
+#define GCB_ST_BZERO     8    /* B = 0 at a guiding-center evaluation point              */
+#define GCB_ST_FPRES    16    /* last fixed-point increment |R^K - R^{K-1}| > fp_tol      */
+#define GCB_ST_HALO     32    /* informational: a gather fell outside the LDS tile window
+                                 and was served from global memory (same values)         */
+
+typedef struct gcb_ctx gcb_ctx;
+
+/* Create a context bound to HIP device `device`.  *out receives the context
+   (NULL on failure).  Returns GCB_EHIP if the device cannot be used. */
+int gcb_create(gcb_ctx** out, int device);
+
+/* Free all device memory owned by the context.  NULL is accepted. */
+void gcb_destroy(gcb_ctx* ctx);
+
+/* Message for the last failed call on this context (or, for ctx == NULL, on
+   this thread).  The string is owned by the library and valid until the next
+   call on the same context/thread. */
+const char* gcb_last_error(const gcb_ctx* ctx);
+
+/* Grid of the static fields.  Field component k (order Ex, Ey, Ez, Bx, By,
+   Bz) has its nodes at ((i + stagger[k][0]) dx, (j + stagger[k][1]) dy),
+   i in [0,nx), j in [0,ny), periodic.  The paper gathers fields at a particle
+   with a linear shape function from the surrounding nodes and gradients by
+   differentiating it (Sec. 4, opening paragraph): bilinear interpolation on
+   each component's own lattice.  The cell size of the switch is
+   dl = sqrt(dx dy) (Sec. 3, effective cell size). */
+typedef struct {
+    int32_t nx, ny;          /* >= 2 each */
+    double  dx, dy;          /* > 0 */
+    double  stagger[6][2];   /* offsets in cells, each in [0, 1) */
+    int32_t dtype;           /* GCB_F64 or GCB_F32: precision of the device copy */
+} gcb_grid_desc;
+
+/* Copy the six field components into context-owned device storage
+   (node-interleaved, converted to desc->dtype).  E[c] and B[c] point to
+   nx*ny doubles in row-major order, element [j*nx + i].  src says whether
+   they are host (GCB_HOST) or device (GCB_DEVICE) pointers; the caller keeps
+   ownership.  Replaces previously loaded fields.  Enqueued on `stream`;
+   host sources are copied before the call returns. */
+int gcb_load_fields(gcb_ctx* ctx, const gcb_grid_desc* desc,
+                    const double* const E[3], const double* const B[3],
+                    int32_t src, void* stream);
+
+/* Parameters of a push (Sec. 2.2, 3, 4.1). */
+typedef struct {
+    double  dt;          /* time step, > 0 */
+    double  c;           /* speed of light, > 0 */
+    double  qm;          /* q/m used when particles.qm == NULL (signed, != 0) */
+    double  f_rho;       /* switch threshold on rho~/dl (Sec. 4.1; 0.4 there) */
+    double  f_E;         /* switch threshold on E/B (Sec. 4.1; 1 there) */
+    double  fp_tol;      /* iteration-error threshold for GCB_ST_FPRES (1e-7, Sec. 2.2.1) */
+    int32_t curvature;   /* 1: Sec. 2.2.2 scheme (curvature drift and acceleration);
+                            0: Sec. 2.2.1 scheme */
+    int32_t n_iter;      /* K >= 1 fixed-point iterations for R^{n+1} (3-4 in Sec. 2.2) */
+    int32_t form;        /* GCB_FORM_F64 or GCB_FORM_MIXED */
+    int32_t sort_every;  /* cell-sort the particles every this many steps
+                            (0 = never; the tiled kernel needs > 0) */
+    int32_t kernel;      /* GCB_KERNEL_* */
+    int32_t tile;        /* tile edge in cells for the tiled kernel (0 = 32) */
+} gcb_params;
+
+/* Particle state, structure of arrays, caller-owned device memory of length n.
+   gcb_push updates it in place; when sorting is on, all arrays (including qm,
+   id and status) are permuted together, so `id` is how a caller follows a
+   particle. */
+typedef struct {
+    int64_t  n;            /* number of particles, >= 0 */
+    double  *x, *y;        /* x^n, wrapped into the box */
+    double  *xp, *yp;      /* x^{n-1} (any periodic image) */
+    void    *ux, *uy, *uz; /* u^{n-1/2}: double (GCB_FORM_F64) or float (GCB_FORM_MIXED) */
+    double  *qm;           /* optional per-particle q/m (NULL: params.qm) */
+    int32_t *id;           /* optional particle ids (NULL: none); values in [0, n)
+                              when a switch trace is requested */
+    uint8_t *status;       /* required: sticky GCB_ST_* bits, OR-ed by every step */
+} gcb_particles;
+
+typedef struct {
+    int64_t gca_steps;       /* particle-steps taken with the guiding-center system */
+    int64_t boris_steps;     /* particle-steps taken with the Boris push */
+    int64_t flagged;         /* particles with any status bit other than GCB_ST_HALO at the end */
+    int64_t halo_misses;     /* particle-steps with a gather outside the LDS window */
+    double  max_fp_residual; /* max over guiding-center steps of |R^K - R^{K-1}|_inf */
+} gcb_stats;
+
+/* Advance the particles by n_steps steps of the coupled scheme (Sec. 3.1):
+   per particle and step, decide S from the fields at x^n (Sec. 4.1), then
+   Boris (S = 1) or guiding-center leapfrog (S = 0), then store x^{n+1},
+   x^n (as the previous position) and u^{n+1/2}.
+   s_trace (nullable, device, n_steps*n bytes): s_trace[step*n + k] = S for
+   the particle with id k (or array slot k if id == NULL and sorting is off).
+   stats (nullable, host): filled after a device synchronisation. */
+int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm,
+             int32_t n_steps, uint8_t* s_trace, gcb_stats* stats, void* stream);
+
+/* Reverse-mode derivative of n_steps pushes started from `start` (which is
+   not modified), with every switch decision held at its forward value.
+   lam_end[7]: device arrays of length n with dL/d(x, y, xp, yp, ux, uy, uz)
+   at the end of the segment (double).  lam_start[7]: output, the same
+   derivatives at the segment start (double, overwritten).  dE[3], dB[3]:
+   device float arrays of nx*ny elements, element [j*nx+i] of component k,
+   ACCUMULATED (+=) with dL/dF at every node.  Only GCB_FORM_F64 with
+   fields loaded as GCB_F64.  The forward steps are recomputed internally
+   (unsorted); needs n_steps * n * 56 bytes of context scratch. */
+int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start,
+                      const gcb_params* prm, int32_t n_steps,
+                      const double* const lam_end[7], double* const lam_start[7],
+                      float* const dE[3], float* const dB[3], void* stream);
+
+/* Mean kinetic energy per unit mass L = (1/n) sum (Gamma - 1) c^2 of the
+   state (the loss of the differentiation workload).  out (device, 1 double)
+   receives L.  lam_u (nullable, 3 device double arrays of length n) receives
+   dL/du = u / (n Gamma). */
+int gcb_kinetic_energy(gcb_ctx* ctx, const gcb_particles* p,
+                       const gcb_params* prm, double* out,
+                       double* const lam_u[3], void* stream);
+
+/* Kernel timing with HIP events recorded around every launch on the launch
+   stream.  gcb_set_timing(ctx, 1) clears and enables; gcb_get_timing
+   synchronises on the recorded events and returns, for each kernel class,
+   the summed milliseconds and the launch count. */
+#define GCB_TIMER_PUSH     0   /* push kernels (one launch per step) */
+#define GCB_TIMER_SORT     1   /* every kernel of a cell-sort        */
+#define GCB_TIMER_BACKWARD 2   /* adjoint kernels                    */
+#define GCB_TIMER_OTHER    3
+#define GCB_NTIMERS        4
+int gcb_set_timing(gcb_ctx* ctx, int32_t enabled);
+int gcb_get_timing(gcb_ctx* ctx, double ms[GCB_NTIMERS], int64_t launches[GCB_NTIMERS]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GCB_H */

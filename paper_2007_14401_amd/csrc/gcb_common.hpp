@@ -1,0 +1,74 @@
+// Definitions shared by the device code and the host launchers of libgcb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gcb {
+
+enum : uint32_t {
+    ST_NONFINITE = 1,
+    ST_KAPPA = 2,
+    ST_QUAD = 4,
+    ST_BZERO = 8,
+    ST_FPRES = 16,
+    ST_HALO = 32,
+};
+
+// 1 - v_E^2/c^2 is clamped to this floor where the drift reaches c.
+constexpr double kKappaFloor = 1.0e-12;
+// |1 - (dt/2) v_E.(b.grad)b| below this: no division in the parallel update.
+constexpr double kDFloor = 1.0e-12;
+
+// 2D Yee lattice offsets (cells) of Ex, Ey, Ez, Bx, By, Bz.
+__device__ constexpr double kYeeStagger[6][2] = {
+    {0.5, 0.0}, {0.0, 0.5}, {0.0, 0.0}, {0.0, 0.5}, {0.5, 0.0}, {0.5, 0.5}};
+
+// Per-launch constants, passed by value as a kernel argument.
+struct PushConst {
+    double dt, c, c2, inv_c2;
+    double f_rho, f_E, inv_dl, fp_tol;
+    double inv_dx, inv_dy, Lx, Ly;
+    double qm;               // used when the per-particle array is absent
+    double stagger[6][2];
+    int32_t nx, ny;
+    int32_t curvature, n_iter;
+};
+
+// Register copy of one particle's state.
+struct ParticleRegs {
+    double x, y, xp, yp;
+    double ux, uy, uz;
+    double qm;
+};
+
+// Device pointers of a structure-of-arrays particle state.
+template <typename U>
+struct ParticlePtrs {
+    double* x;
+    double* y;
+    double* xp;
+    double* yp;
+    U* ux;
+    U* uy;
+    U* uz;
+    double* qm;      // may be null
+    int32_t* id;     // may be null
+    uint8_t* status;
+};
+
+// Accumulators filled by the push kernels when statistics are requested.
+struct DevStats {
+    unsigned long long gca_steps;
+    unsigned long long boris_steps;
+    unsigned long long halo_misses;
+    unsigned long long max_res_bits;   // bit pattern of a non-negative double
+};
+
+__device__ __forceinline__ int wrap_index(int i, int n) {
+    if ((unsigned)i < (unsigned)n) return i;
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+}  // namespace gcb

@@ -1,0 +1,554 @@
+// C ABI of libgcb (declared in include/gcb.h): argument validation, device
+// memory owned by the context, the step loop and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gcb.h"
+#include "gcb_internal.h"
+
+using namespace gcb;
+
+namespace {
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct TimedLaunch {
+    int cls;
+    hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct gcb_ctx {
+    int device = 0;
+    std::string err;
+    // fields
+    bool have_fields = false;
+    int nx = 0, ny = 0;
+    double dx = 1.0, dy = 1.0;
+    double stagger[6][2] = {};
+    int dtype = GCB_F64;
+    bool yee = false;
+    DevBuf fields;
+    // scratch
+    DevBuf sort_keys, sort_idx, sort_keys2, sort_idx2, sort_hist, sort_scan, tile_count,
+        tile_start;
+    DevBuf pscratch;     // sorted copy of the particle state
+    DevBuf stats;        // DevStats + flagged counter
+    DevBuf ke_partial;
+    DevBuf adj_states, adj_lam, adj_grad, adj_trace;
+    // timing
+    bool timing = false;
+    std::vector<TimedLaunch> launches;
+    double ms[GCB_NTIMERS] = {};
+    int64_t count[GCB_NTIMERS] = {};
+};
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+int fail(gcb_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_thread_err = buf;
+    return code;
+}
+
+#define GCB_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(ctx, GCB_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+int ensure(gcb_ctx* ctx, DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return GCB_OK;
+    if (b.ptr) {
+        hipError_t e = hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return fail(ctx, GCB_EHIP, "hipFree: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) {
+        b.ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, GCB_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes,
+                    hipGetErrorString(e));
+    }
+    b.cap = bytes;
+    return GCB_OK;
+}
+
+void release(DevBuf& b) {
+    if (b.ptr) (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.cap = 0;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// record a timing event pair around a launch sequence
+struct Timer {
+    gcb_ctx* ctx;
+    hipStream_t s;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer(gcb_ctx* c, hipStream_t st, int k) : ctx(c), s(st), cls(k) {
+        if (!ctx->timing) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            ctx->timing = false;
+            return;
+        }
+        (void)hipEventRecord(a, s);
+    }
+    void done() {
+        if (!a) return;
+        (void)hipEventRecord(b, s);
+        ctx->launches.push_back({cls, a, b});
+        a = b = nullptr;
+    }
+};
+
+const double kYee[6][2] = {{0.5, 0.0}, {0.0, 0.5}, {0.0, 0.0},
+                           {0.0, 0.5}, {0.5, 0.0}, {0.5, 0.5}};
+
+int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
+    if (!prm) return fail(ctx, GCB_EINVAL, "params is NULL");
+    if (!finite_pos(prm->dt)) return fail(ctx, GCB_EINVAL, "dt must be finite and > 0");
+    if (!finite_pos(prm->c)) return fail(ctx, GCB_EINVAL, "c must be finite and > 0");
+    if (!(prm->f_rho >= 0.0) || !(prm->f_E >= 0.0))
+        return fail(ctx, GCB_EINVAL, "f_rho and f_E must be >= 0");
+    if (!(prm->fp_tol >= 0.0)) return fail(ctx, GCB_EINVAL, "fp_tol must be >= 0");
+    if (prm->curvature != 0 && prm->curvature != 1)
+        return fail(ctx, GCB_EINVAL, "curvature must be 0 or 1");
+    if (prm->n_iter < 1 || prm->n_iter > 64)
+        return fail(ctx, GCB_EINVAL, "n_iter must be in [1, 64]");
+    if (prm->form != GCB_FORM_F64 && prm->form != GCB_FORM_MIXED)
+        return fail(ctx, GCB_EINVAL, "unknown form %d", prm->form);
+    if (prm->sort_every < 0) return fail(ctx, GCB_EINVAL, "sort_every must be >= 0");
+    if (prm->kernel < GCB_KERNEL_AUTO || prm->kernel > GCB_KERNEL_TILED)
+        return fail(ctx, GCB_EINVAL, "unknown kernel %d", prm->kernel);
+    if (prm->tile < 0 || prm->tile == 1 || prm->tile > 256)
+        return fail(ctx, GCB_EINVAL, "tile must be 0 or in [2, 256]");
+    return GCB_OK;
+}
+
+int validate_particles(gcb_ctx* ctx, const gcb_particles* p, const gcb_params* prm) {
+    if (!p) return fail(ctx, GCB_EINVAL, "particles is NULL");
+    if (p->n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");
+    if (p->n >= (int64_t)1 << 31) return fail(ctx, GCB_EINVAL, "n must be < 2^31");
+    if (p->n == 0) return GCB_OK;
+    if (!p->x || !p->y || !p->xp || !p->yp || !p->ux || !p->uy || !p->uz || !p->status)
+        return fail(ctx, GCB_EINVAL, "particle arrays x, y, xp, yp, ux, uy, uz, status "
+                                     "must be non-NULL");
+    const uintptr_t m8 = (uintptr_t)p->x | (uintptr_t)p->y | (uintptr_t)p->xp |
+                         (uintptr_t)p->yp | (uintptr_t)p->qm;
+    if (m8 & 7) return fail(ctx, GCB_EINVAL, "double arrays must be 8-byte aligned");
+    const size_t ua = prm->form == GCB_FORM_F64 ? 8 : 4;
+    if (((uintptr_t)p->ux | (uintptr_t)p->uy | (uintptr_t)p->uz) & (ua - 1))
+        return fail(ctx, GCB_EINVAL, "u arrays misaligned for their element type");
+    if ((uintptr_t)p->id & 3) return fail(ctx, GCB_EINVAL, "id array misaligned");
+    if (!p->qm && !(std::isfinite(prm->qm) && prm->qm != 0.0))
+        return fail(ctx, GCB_EINVAL, "params.qm must be finite and non-zero when "
+                                     "particles.qm is NULL");
+    return GCB_OK;
+}
+
+template <typename U>
+ParticlePtrs<U> ptrs_of(const gcb_particles* p) {
+    ParticlePtrs<U> r;
+    r.x = p->x;
+    r.y = p->y;
+    r.xp = p->xp;
+    r.yp = p->yp;
+    r.ux = static_cast<U*>(p->ux);
+    r.uy = static_cast<U*>(p->uy);
+    r.uz = static_cast<U*>(p->uz);
+    r.qm = p->qm;
+    r.id = p->id;
+    r.status = p->status;
+    return r;
+}
+
+// carve a scratch copy of the state (same shape as `like`) out of one buffer
+template <typename U>
+int scratch_state(gcb_ctx* ctx, const ParticlePtrs<U>& like, int64_t n, ParticlePtrs<U>& out) {
+    const size_t nd = (size_t)n * sizeof(double), nu = (size_t)n * sizeof(U);
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t bytes = 4 * up(nd) + 3 * up(nu) + up(n) + (like.qm ? up(nd) : 0) +
+                   (like.id ? up((size_t)n * 4) : 0);
+    int rc = ensure(ctx, ctx->pscratch, bytes);
+    if (rc) return rc;
+    char* b = static_cast<char*>(ctx->pscratch.ptr);
+    auto take = [&](size_t s) {
+        char* r = b;
+        b += up(s);
+        return r;
+    };
+    out.x = reinterpret_cast<double*>(take(nd));
+    out.y = reinterpret_cast<double*>(take(nd));
+    out.xp = reinterpret_cast<double*>(take(nd));
+    out.yp = reinterpret_cast<double*>(take(nd));
+    out.ux = reinterpret_cast<U*>(take(nu));
+    out.uy = reinterpret_cast<U*>(take(nu));
+    out.uz = reinterpret_cast<U*>(take(nu));
+    out.status = reinterpret_cast<uint8_t*>(take(n));
+    out.qm = like.qm ? reinterpret_cast<double*>(take(nd)) : nullptr;
+    out.id = like.id ? reinterpret_cast<int32_t*>(take((size_t)n * 4)) : nullptr;
+    return GCB_OK;
+}
+
+PushConst make_const(const gcb_ctx* ctx, const gcb_params* prm) {
+    PushConst pc;
+    pc.dt = prm->dt;
+    pc.c = prm->c;
+    pc.c2 = prm->c * prm->c;
+    pc.inv_c2 = 1.0 / (prm->c * prm->c);
+    pc.f_rho = prm->f_rho;
+    pc.f_E = prm->f_E;
+    pc.inv_dl = 1.0 / std::sqrt(ctx->dx * ctx->dy);
+    pc.fp_tol = prm->fp_tol;
+    pc.inv_dx = 1.0 / ctx->dx;
+    pc.inv_dy = 1.0 / ctx->dy;
+    pc.Lx = ctx->nx * ctx->dx;
+    pc.Ly = ctx->ny * ctx->dy;
+    pc.qm = prm->qm;
+    std::memcpy(pc.stagger, ctx->stagger, sizeof(pc.stagger));
+    pc.nx = ctx->nx;
+    pc.ny = ctx->ny;
+    pc.curvature = prm->curvature;
+    pc.n_iter = prm->n_iter;
+    return pc;
+}
+
+TileGeom make_geom(const gcb_ctx* ctx, const gcb_params* prm) {
+    TileGeom g;
+    g.tile = prm->tile ? prm->tile : 32;
+    const double inv_min = std::max(1.0 / ctx->dx, 1.0 / ctx->dy);
+    const int se = prm->sort_every > 0 ? prm->sort_every : 1;
+    g.halo = (int)std::ceil(se * prm->c * prm->dt * inv_min) + 1;
+    g.ntx = (ctx->nx + g.tile - 1) / g.tile;
+    g.nty = (ctx->ny + g.tile - 1) / g.tile;
+    g.window = g.tile + 2 * g.halo;
+    return g;
+}
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+int prepare_sort(gcb_ctx* ctx, int64_t n, const TileGeom& g, SortBuffers& sb) {
+    const int ntiles = g.ntx * g.nty;
+    int rc;
+    if ((rc = ensure(ctx, ctx->sort_keys, (size_t)n * 4))) return rc;
+    if ((rc = ensure(ctx, ctx->sort_idx, (size_t)n * 4))) return rc;
+    if ((rc = ensure(ctx, ctx->sort_keys2, (size_t)n * 4))) return rc;
+    if ((rc = ensure(ctx, ctx->sort_idx2, (size_t)n * 4))) return rc;
+    const int64_t nh = sort_hist_elems(n);
+    if ((rc = ensure(ctx, ctx->sort_hist, (size_t)nh * 4))) return rc;
+    const int64_t ns = std::max(sort_scan_tmp_elems(nh), sort_scan_tmp_elems(ntiles + 1));
+    if ((rc = ensure(ctx, ctx->sort_scan, (size_t)ns * 4))) return rc;
+    if ((rc = ensure(ctx, ctx->tile_count, (size_t)(ntiles + 1) * 4))) return rc;
+    if ((rc = ensure(ctx, ctx->tile_start, (size_t)(ntiles + 1) * 4))) return rc;
+    sb.keys = static_cast<uint32_t*>(ctx->sort_keys.ptr);
+    sb.idx = static_cast<uint32_t*>(ctx->sort_idx.ptr);
+    sb.keys2 = static_cast<uint32_t*>(ctx->sort_keys2.ptr);
+    sb.idx2 = static_cast<uint32_t*>(ctx->sort_idx2.ptr);
+    sb.hist = static_cast<uint32_t*>(ctx->sort_hist.ptr);
+    sb.scan_tmp = static_cast<uint32_t*>(ctx->sort_scan.ptr);
+    sb.tile_count = static_cast<int32_t*>(ctx->tile_count.ptr);
+    sb.tile_start = static_cast<int32_t*>(ctx->tile_start.ptr);
+    return GCB_OK;
+}
+
+template <typename U>
+int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_steps,
+             uint8_t* s_trace, DevStats* dstats, hipStream_t stream) {
+    const int64_t n = p->n;
+    const PushConst pc = make_const(ctx, prm);
+    const TileGeom g = make_geom(ctx, prm);
+    const size_t esz = prm->form == GCB_FORM_F64 ? sizeof(double) : sizeof(float);
+    const bool tiled_ok = prm->sort_every > 0 && tiled_lds_bytes(g.window, esz) <= kMaxLds;
+    PushKind kind;
+    if (prm->kernel == GCB_KERNEL_TILED) {
+        if (!tiled_ok)
+            return fail(ctx, GCB_EUNSUPPORTED,
+                        "tiled kernel needs sort_every > 0 and a tile window that fits in "
+                        "LDS (window %d nodes)", g.window);
+        kind = PushKind::Tiled;
+    } else if (prm->kernel == GCB_KERNEL_GLOBAL) {
+        kind = PushKind::Global;
+    } else {
+        kind = tiled_ok ? PushKind::Tiled : PushKind::Global;
+    }
+    ParticlePtrs<U> user = ptrs_of<U>(p);
+    ParticlePtrs<U> scr{};
+    SortBuffers sb{};
+    int rc;
+    if (prm->sort_every > 0 && n > 0) {
+        if ((rc = prepare_sort(ctx, n, g, sb))) return rc;
+        if ((rc = scratch_state<U>(ctx, user, n, scr))) return rc;
+    }
+    for (int32_t step = 0; step < n_steps; ++step) {
+        ParticlePtrs<U> src = user;
+        if (prm->sort_every > 0 && n > 0 && step % prm->sort_every == 0) {
+            Timer t(ctx, stream, GCB_TIMER_SORT);
+            GCB_HIP(launch_cell_sort(user.x, user.y, n, pc.inv_dx, pc.inv_dy, g, sb, stream));
+            GCB_HIP(launch_permute<U>(user, scr, sb.idx, n, stream));
+            t.done();
+            src = scr;
+        }
+        PushLaunch L;
+        L.kind = kind;
+        L.yee = ctx->yee;
+        L.fields = ctx->fields.ptr;
+        L.n = n;
+        L.tile_start = sb.tile_start;
+        L.geom = g;
+        L.trace = s_trace ? s_trace + (int64_t)step * n : nullptr;
+        L.stats = dstats;
+        Timer t(ctx, stream, GCB_TIMER_PUSH);
+        hipError_t e;
+        if constexpr (sizeof(U) == sizeof(double))
+            e = launch_push_f64(L, src, user, pc, stream);
+        else
+            e = launch_push_mixed(L, src, user, pc, stream);
+        if (e != hipSuccess)
+            return fail(ctx, GCB_EHIP, "push kernel launch failed: %s", hipGetErrorString(e));
+        t.done();
+    }
+    return GCB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gcb_create(gcb_ctx** out, int device) {
+    if (!out) return fail(nullptr, GCB_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(nullptr, GCB_EHIP, "no HIP device available (%s)",
+                    e == hipSuccess ? "count 0" : hipGetErrorString(e));
+    }
+    if (device < 0 || device >= ndev)
+        return fail(nullptr, GCB_EINVAL, "device %d out of range [0, %d)", device, ndev);
+    e = hipSetDevice(device);
+    if (e != hipSuccess)
+        return fail(nullptr, GCB_EHIP, "hipSetDevice(%d): %s", device, hipGetErrorString(e));
+    gcb_ctx* c = new (std::nothrow) gcb_ctx();
+    if (!c) return fail(nullptr, GCB_ENOMEM, "out of host memory");
+    c->device = device;
+    *out = c;
+    return GCB_OK;
+}
+
+void gcb_destroy(gcb_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (auto& l : ctx->launches) {
+        (void)hipEventDestroy(l.start);
+        (void)hipEventDestroy(l.stop);
+    }
+    DevBuf* bufs[] = {&ctx->fields,     &ctx->sort_keys,  &ctx->sort_idx,  &ctx->sort_keys2,
+                      &ctx->sort_idx2,  &ctx->sort_hist,  &ctx->sort_scan, &ctx->tile_count,
+                      &ctx->tile_start, &ctx->pscratch,   &ctx->stats,     &ctx->ke_partial,
+                      &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace};
+    for (DevBuf* b : bufs) release(*b);
+    delete ctx;
+}
+
+const char* gcb_last_error(const gcb_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_thread_err.c_str();
+}
+
+int gcb_load_fields(gcb_ctx* ctx, const gcb_grid_desc* d, const double* const E[3],
+                    const double* const B[3], int32_t src, void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    if (!d || !E || !B) return fail(ctx, GCB_EINVAL, "desc, E and B must be non-NULL");
+    if (d->nx < 2 || d->ny < 2) return fail(ctx, GCB_EINVAL, "nx and ny must be >= 2");
+    if ((int64_t)d->nx * d->ny * 6 >= ((int64_t)1 << 34))
+        return fail(ctx, GCB_EINVAL, "grid too large");
+    if (!finite_pos(d->dx) || !finite_pos(d->dy))
+        return fail(ctx, GCB_EINVAL, "dx and dy must be finite and > 0");
+    for (int k = 0; k < 6; ++k)
+        for (int a = 0; a < 2; ++a)
+            if (!(d->stagger[k][a] >= 0.0 && d->stagger[k][a] < 1.0))
+                return fail(ctx, GCB_EINVAL, "stagger offsets must be in [0, 1)");
+    if (d->dtype != GCB_F64 && d->dtype != GCB_F32)
+        return fail(ctx, GCB_EINVAL, "unknown dtype %d", d->dtype);
+    if (src != GCB_HOST && src != GCB_DEVICE)
+        return fail(ctx, GCB_EINVAL, "src must be GCB_HOST or GCB_DEVICE");
+    const double* comps[6] = {E[0], E[1], E[2], B[0], B[1], B[2]};
+    for (int k = 0; k < 6; ++k)
+        if (!comps[k]) return fail(ctx, GCB_EINVAL, "field component %d is NULL", k);
+    GCB_HIP(hipSetDevice(ctx->device));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const int64_t nodes = (int64_t)d->nx * d->ny;
+    const size_t esz = d->dtype == GCB_F64 ? 8 : 4;
+    ctx->have_fields = false;
+    int rc = ensure(ctx, ctx->fields, (size_t)nodes * 6 * esz);
+    if (rc) return rc;
+    if (src == GCB_HOST) {
+        DevBuf tmp;
+        rc = ensure(ctx, tmp, (size_t)nodes * 6 * sizeof(double));
+        if (rc) return rc;
+        const double* dcomps[6];
+        for (int k = 0; k < 6; ++k) {
+            double* dst = static_cast<double*>(tmp.ptr) + k * nodes;
+            hipError_t e = hipMemcpyAsync(dst, comps[k], nodes * sizeof(double),
+                                          hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) {
+                release(tmp);
+                return fail(ctx, GCB_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+            }
+            dcomps[k] = dst;
+        }
+        hipError_t e = launch_interleave_fields(dcomps, d->nx, d->ny, ctx->fields.ptr,
+                                                d->dtype == GCB_F32, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        release(tmp);
+        if (e != hipSuccess)
+            return fail(ctx, GCB_EHIP, "field conversion: %s", hipGetErrorString(e));
+    } else {
+        GCB_HIP(launch_interleave_fields(comps, d->nx, d->ny, ctx->fields.ptr,
+                                         d->dtype == GCB_F32, stream));
+    }
+    ctx->nx = d->nx;
+    ctx->ny = d->ny;
+    ctx->dx = d->dx;
+    ctx->dy = d->dy;
+    std::memcpy(ctx->stagger, d->stagger, sizeof(ctx->stagger));
+    ctx->dtype = d->dtype;
+    ctx->yee = std::memcmp(d->stagger, kYee, sizeof(kYee)) == 0;
+    ctx->have_fields = true;
+    return GCB_OK;
+}
+
+int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_steps,
+             uint8_t* s_trace, gcb_stats* stats, void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    int rc;
+    if ((rc = validate_params(ctx, prm))) return rc;
+    if ((rc = validate_particles(ctx, p, prm))) return rc;
+    if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
+    if (!ctx->have_fields) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields was not called");
+    if (prm->form == GCB_FORM_F64 && ctx->dtype != GCB_F64)
+        return fail(ctx, GCB_EINVAL, "GCB_FORM_F64 needs fields loaded as GCB_F64");
+    if (prm->form == GCB_FORM_MIXED && ctx->dtype != GCB_F32)
+        return fail(ctx, GCB_EINVAL, "GCB_FORM_MIXED needs fields loaded as GCB_F32");
+    if (s_trace && p->n > 0 && !p->id && prm->sort_every > 0)
+        return fail(ctx, GCB_EINVAL, "a switch trace with sorting needs particle ids");
+    GCB_HIP(hipSetDevice(ctx->device));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    DevStats* dstats = nullptr;
+    if (stats) {
+        if ((rc = ensure(ctx, ctx->stats, sizeof(DevStats) + 16))) return rc;
+        dstats = static_cast<DevStats*>(ctx->stats.ptr);
+        GCB_HIP(hipMemsetAsync(dstats, 0, sizeof(DevStats) + 16, stream));
+    }
+    if (prm->form == GCB_FORM_F64)
+        rc = run_push<double>(ctx, p, prm, n_steps, s_trace, dstats, stream);
+    else
+        rc = run_push<float>(ctx, p, prm, n_steps, s_trace, dstats, stream);
+    if (rc) return rc;
+    if (stats) {
+        unsigned long long* flagged =
+            reinterpret_cast<unsigned long long*>(static_cast<char*>(ctx->stats.ptr) +
+                                                  sizeof(DevStats));
+        GCB_HIP(launch_count_flagged(p->status, p->n, flagged, stream));
+        unsigned long long host[5];
+        GCB_HIP(hipMemcpyAsync(host, ctx->stats.ptr, sizeof(host), hipMemcpyDeviceToHost,
+                               stream));
+        GCB_HIP(hipStreamSynchronize(stream));
+        stats->gca_steps = (int64_t)host[0];
+        stats->boris_steps = (int64_t)host[1];
+        stats->halo_misses = (int64_t)host[2];
+        double m;
+        std::memcpy(&m, &host[3], sizeof(m));
+        stats->max_fp_residual = m;
+        stats->flagged = (int64_t)host[4];
+    }
+    return GCB_OK;
+}
+
+int gcb_kinetic_energy(gcb_ctx* ctx, const gcb_particles* p, const gcb_params* prm,
+                       double* out, double* const lam_u[3], void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    int rc;
+    if ((rc = validate_params(ctx, prm))) return rc;
+    if (!p || p->n < 0) return fail(ctx, GCB_EINVAL, "invalid particles");
+    if (!out) return fail(ctx, GCB_EINVAL, "out is NULL");
+    if (p->n > 0 && (!p->ux || !p->uy || !p->uz))
+        return fail(ctx, GCB_EINVAL, "u arrays must be non-NULL");
+    if (lam_u && p->n > 0 && (!lam_u[0] || !lam_u[1] || !lam_u[2]))
+        return fail(ctx, GCB_EINVAL, "lam_u entries must be non-NULL");
+    GCB_HIP(hipSetDevice(ctx->device));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if ((rc = ensure(ctx, ctx->ke_partial, kinetic_partial_elems(p->n) * sizeof(double))))
+        return rc;
+    Timer t(ctx, stream, GCB_TIMER_OTHER);
+    GCB_HIP(launch_kinetic_energy(p->ux, p->uy, p->uz, prm->form == GCB_FORM_MIXED, p->n,
+                                  prm->c, out, lam_u ? lam_u[0] : nullptr,
+                                  lam_u ? lam_u[1] : nullptr, lam_u ? lam_u[2] : nullptr,
+                                  static_cast<double*>(ctx->ke_partial.ptr), stream));
+    t.done();
+    return GCB_OK;
+}
+
+int gcb_set_timing(gcb_ctx* ctx, int32_t enabled) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    for (auto& l : ctx->launches) {
+        (void)hipEventDestroy(l.start);
+        (void)hipEventDestroy(l.stop);
+    }
+    ctx->launches.clear();
+    for (int k = 0; k < GCB_NTIMERS; ++k) {
+        ctx->ms[k] = 0.0;
+        ctx->count[k] = 0;
+    }
+    ctx->timing = enabled != 0;
+    return GCB_OK;
+}
+
+int gcb_get_timing(gcb_ctx* ctx, double ms[GCB_NTIMERS], int64_t launches[GCB_NTIMERS]) {
+    if (!ctx || !ms || !launches) return fail(ctx, GCB_EINVAL, "NULL argument");
+    GCB_HIP(hipSetDevice(ctx->device));
+    for (auto& l : ctx->launches) {
+        GCB_HIP(hipEventSynchronize(l.stop));
+        float t = 0.f;
+        GCB_HIP(hipEventElapsedTime(&t, l.start, l.stop));
+        ctx->ms[l.cls] += t;
+        ctx->count[l.cls] += 1;
+        (void)hipEventDestroy(l.start);
+        (void)hipEventDestroy(l.stop);
+    }
+    ctx->launches.clear();
+    for (int k = 0; k < GCB_NTIMERS; ++k) {
+        ms[k] = ctx->ms[k];
+        launches[k] = ctx->count[k];
+    }
+    return GCB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Host-side interface between the C ABI (gcb_host.hip) and the kernel
+// translation units.  Each launcher enqueues its kernels on `stream` and
+// returns the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gcb_common.hpp"
+
+namespace gcb {
+
+// Geometry of the tiled launch.
+struct TileGeom {
+    int tile;       // tile edge in cells
+    int halo;       // extra nodes on each side of the tile in the LDS window
+    int ntx, nty;   // tiles along x and y
+    int window;     // tile + 2*halo nodes per side
+};
+
+// Which kernel does the work of one step.
+enum class PushKind { Global, Tiled };
+
+struct PushLaunch {
+    PushKind kind;
+    bool yee;              // compile-time Yee offsets
+    const void* fields;    // node-interleaved device fields (double or float)
+    int64_t n;
+    const int32_t* tile_start;   // tiled: ntiles + 1 offsets
+    TileGeom geom;
+    uint8_t* trace;        // nullable: trace row of this step
+    DevStats* stats;       // nullable
+};
+
+// binary64 form (fields double, u double)
+hipError_t launch_push_f64(const PushLaunch& L, const ParticlePtrs<double>& in,
+                           const ParticlePtrs<double>& out, const PushConst& pc,
+                           hipStream_t stream);
+
+// mixed form (fields float, u float)
+hipError_t launch_push_mixed(const PushLaunch& L, const ParticlePtrs<float>& in,
+                             const ParticlePtrs<float>& out, const PushConst& pc,
+                             hipStream_t stream);
+
+// LDS bytes the tiled kernel needs for a window of `window` nodes per side.
+size_t tiled_lds_bytes(int window, size_t elem_bytes);
+constexpr int kQueueMax = 2048;   // particles compacted per pass in a tile
+
+// ---------------------------------------------------------------------------
+// cell sort
+
+struct SortBuffers {
+    uint32_t* keys;      // n
+    uint32_t* idx;       // n
+    uint32_t* keys2;     // n
+    uint32_t* idx2;      // n
+    uint32_t* hist;      // 256 * nblocks (+ scan workspace)
+    uint32_t* scan_tmp;  // scan block sums
+    int32_t* tile_count; // ntiles + 1
+    int32_t* tile_start; // ntiles + 1
+};
+
+int64_t sort_hist_elems(int64_t n);   // elements of `hist`
+int64_t sort_scan_tmp_elems(int64_t n_scan);
+
+// Compute tile keys from positions, sort (stable), produce tile_start and the
+// permutation idx (sorted slot -> source slot).
+hipError_t launch_cell_sort(const double* x, const double* y, int64_t n, double inv_dx,
+                            double inv_dy, const TileGeom& g, const SortBuffers& b,
+                            hipStream_t stream);
+
+// Gather every array of the state through the permutation.
+template <typename U>
+hipError_t launch_permute(const ParticlePtrs<U>& src, const ParticlePtrs<U>& dst,
+                          const uint32_t* perm, int64_t n, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// fields
+
+hipError_t launch_interleave_fields(const double* const comps[6], int nx, int ny,
+                                    void* dst, bool to_float, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// reductions
+
+hipError_t launch_kinetic_energy(const void* ux, const void* uy, const void* uz,
+                                 bool u_float, int64_t n, double c, double* out,
+                                 double* lam_x, double* lam_y, double* lam_z,
+                                 double* partial, hipStream_t stream);
+int64_t kinetic_partial_elems(int64_t n);
+
+hipError_t launch_count_flagged(const uint8_t* status, int64_t n,
+                                unsigned long long* out, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// adjoint
+
+struct AdjointLaunch {
+    bool yee;
+    const double* fields;   // node-interleaved binary64
+    int64_t n;
+    const double* state;    // per-step saved states: 7 arrays of n (x,y,xp,yp,ux,uy,uz)
+    const double* qm;       // nullable
+    const uint8_t* strace;  // per-particle S of this step (1 = Boris)
+    float* grad_fields;     // node-interleaved float gradient accumulators
+};
+
+hipError_t launch_adjoint_step(const AdjointLaunch& L, double* lam /*7*n in/out*/,
+                               const PushConst& pc, hipStream_t stream);
+
+hipError_t launch_deinterleave_add(const float* grad_fields, int nx, int ny,
+                                   float* const out[6], hipStream_t stream);
+
+}  // namespace gcb

@@ -1,0 +1,226 @@
+"""ctypes binding of libgcb (include/gcb.h).  Argument marshalling only.
+
+The functions carry the C names.  Arrays are torch tensors on the context's
+device (or host numpy arrays where the C call accepts host memory); their
+data pointers are handed to the library unchanged.  Every failing call raises
+GcbError with the library's message.  If libgcb.so has not been built the
+import fails loudly: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("GCB_LIBRARY", os.path.join(_HERE, "libgcb.so"))
+
+GCB_OK, GCB_EINVAL, GCB_ENOFIELDS, GCB_ENOMEM, GCB_EHIP, GCB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GCB_F64, GCB_F32 = 0, 1
+GCB_FORM_F64, GCB_FORM_MIXED = 0, 1
+GCB_HOST, GCB_DEVICE = 0, 1
+GCB_KERNEL_AUTO, GCB_KERNEL_GLOBAL, GCB_KERNEL_TILED = 0, 1, 2
+GCB_ST_NONFINITE, GCB_ST_KAPPA, GCB_ST_QUAD, GCB_ST_BZERO, GCB_ST_FPRES, GCB_ST_HALO = 1, 2, 4, 8, 16, 32
+GCB_TIMER_PUSH, GCB_TIMER_SORT, GCB_TIMER_BACKWARD, GCB_TIMER_OTHER = 0, 1, 2, 3
+GCB_NTIMERS = 4
+
+YEE_STAGGER = ((0.5, 0.0), (0.0, 0.5), (0.0, 0.0), (0.0, 0.5), (0.5, 0.0), (0.5, 0.5))
+
+
+class GcbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gcb error {code}: {msg}")
+        self.code = code
+
+
+class gcb_grid_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double),
+                ("dy", C.c_double), ("stagger", (C.c_double * 2) * 6),
+                ("dtype", C.c_int32)]
+
+
+class gcb_params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("c", C.c_double), ("qm", C.c_double),
+                ("f_rho", C.c_double), ("f_E", C.c_double), ("fp_tol", C.c_double),
+                ("curvature", C.c_int32), ("n_iter", C.c_int32), ("form", C.c_int32),
+                ("sort_every", C.c_int32), ("kernel", C.c_int32), ("tile", C.c_int32)]
+
+
+class gcb_particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p),
+                ("xp", C.c_void_p), ("yp", C.c_void_p), ("ux", C.c_void_p),
+                ("uy", C.c_void_p), ("uz", C.c_void_p), ("qm", C.c_void_p),
+                ("id", C.c_void_p), ("status", C.c_void_p)]
+
+
+class gcb_stats(C.Structure):
+    _fields_ = [("gca_steps", C.c_int64), ("boris_steps", C.c_int64),
+                ("flagged", C.c_int64), ("halo_misses", C.c_int64),
+                ("max_fp_residual", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "gcb_create": (C.c_int, [C.POINTER(P), C.c_int]),
+        "gcb_destroy": (None, [P]),
+        "gcb_last_error": (C.c_char_p, [P]),
+        "gcb_load_fields": (C.c_int, [P, C.POINTER(gcb_grid_desc), C.POINTER(P * 3),
+                                      C.POINTER(P * 3), C.c_int32, P]),
+        "gcb_push": (C.c_int, [P, C.POINTER(gcb_particles), C.POINTER(gcb_params),
+                               C.c_int32, P, C.POINTER(gcb_stats), P]),
+        "gcb_push_backward": (C.c_int, [P, C.POINTER(gcb_particles), C.POINTER(gcb_params),
+                                        C.c_int32, C.POINTER(P * 7), C.POINTER(P * 7),
+                                        C.POINTER(P * 3), C.POINTER(P * 3), P]),
+        "gcb_kinetic_energy": (C.c_int, [P, C.POINTER(gcb_particles), C.POINTER(gcb_params),
+                                         P, C.POINTER(P * 3), P]),
+        "gcb_set_timing": (C.c_int, [P, C.c_int32]),
+        "gcb_get_timing": (C.c_int, [P, C.POINTER(C.c_double * GCB_NTIMERS),
+                                     C.POINTER(C.c_int64 * GCB_NTIMERS)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("gcb_create", "gcb_destroy", "gcb_last_error", "gcb_load_fields", "gcb_push",
+            "gcb_push_backward", "gcb_kinetic_energy", "gcb_set_timing", "gcb_get_timing")
+
+
+def lib():
+    return _lib
+
+
+def _ptr(a):
+    """Data pointer of a torch tensor / numpy array, or None."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _check(rc: int, ctx=None):
+    if rc != GCB_OK:
+        msg = _lib.gcb_last_error(ctx)
+        raise GcbError(rc, msg.decode() if msg else "")
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def gcb_create(device: int = 0):
+    h = C.c_void_p()
+    _check(_lib.gcb_create(C.byref(h), int(device)))
+    return h
+
+
+def gcb_destroy(ctx) -> None:
+    _lib.gcb_destroy(ctx)
+
+
+def gcb_last_error(ctx=None) -> str:
+    m = _lib.gcb_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def grid_desc(nx, ny, dx=1.0, dy=1.0, stagger=YEE_STAGGER, dtype=GCB_F64) -> gcb_grid_desc:
+    d = gcb_grid_desc()
+    d.nx, d.ny, d.dx, d.dy, d.dtype = int(nx), int(ny), float(dx), float(dy), int(dtype)
+    for k in range(6):
+        d.stagger[k][0] = float(stagger[k][0])
+        d.stagger[k][1] = float(stagger[k][1])
+    return d
+
+
+def gcb_load_fields(ctx, desc: gcb_grid_desc, E, B, src=None, stream=None) -> None:
+    """E, B: sequences of three (ny, nx) float64 arrays (numpy host or torch device)."""
+    if src is None:
+        src = GCB_HOST if isinstance(E[0], np.ndarray) else GCB_DEVICE
+    for a in list(E) + list(B):
+        if isinstance(a, np.ndarray):
+            assert a.dtype == np.float64 and a.flags.c_contiguous
+        else:
+            import torch
+            assert a.dtype == torch.float64 and a.is_contiguous()
+    Ea = (C.c_void_p * 3)(*[_ptr(a) for a in E])
+    Ba = (C.c_void_p * 3)(*[_ptr(a) for a in B])
+    sp = None if src == GCB_HOST and stream is None else _stream_ptr(stream)
+    _check(_lib.gcb_load_fields(ctx, C.byref(desc), C.byref(Ea), C.byref(Ba), int(src), sp), ctx)
+
+
+def params(dt=1.0, c=0.45, qm=-1.0, f_rho=0.4, f_E=1.0, fp_tol=1e-7, curvature=1,
+           n_iter=4, form=GCB_FORM_F64, sort_every=0, kernel=GCB_KERNEL_AUTO,
+           tile=0) -> gcb_params:
+    p = gcb_params()
+    p.dt, p.c, p.qm, p.f_rho, p.f_E, p.fp_tol = dt, c, qm, f_rho, f_E, fp_tol
+    p.curvature, p.n_iter, p.form = int(curvature), int(n_iter), int(form)
+    p.sort_every, p.kernel, p.tile = int(sort_every), int(kernel), int(tile)
+    return p
+
+
+def particles(t: dict) -> gcb_particles:
+    """Build the struct from a dict of tensors x, y, xp, yp, ux, uy, uz, status
+    and optional qm, id."""
+    p = gcb_particles()
+    p.n = int(t["x"].shape[0])
+    for k in ("x", "y", "xp", "yp", "ux", "uy", "uz", "status"):
+        setattr(p, k, _ptr(t[k]))
+    p.qm = _ptr(t.get("qm"))
+    p.id = _ptr(t.get("id"))
+    return p
+
+
+def gcb_push(ctx, parts: gcb_particles, prm: gcb_params, n_steps: int, s_trace=None,
+             want_stats: bool = False, stream=None):
+    st = gcb_stats() if want_stats else None
+    rc = _lib.gcb_push(ctx, C.byref(parts), C.byref(prm), int(n_steps), _ptr(s_trace),
+                       C.byref(st) if st is not None else None, _stream_ptr(stream))
+    _check(rc, ctx)
+    if st is None:
+        return None
+    return {k: getattr(st, k) for k, _ in gcb_stats._fields_}
+
+
+def gcb_push_backward(ctx, start: gcb_particles, prm: gcb_params, n_steps: int, lam_end,
+                      lam_start, dE, dB, stream=None) -> None:
+    le = (C.c_void_p * 7)(*[_ptr(a) for a in lam_end])
+    ls = (C.c_void_p * 7)(*[_ptr(a) for a in lam_start])
+    de = (C.c_void_p * 3)(*[_ptr(a) for a in dE])
+    db = (C.c_void_p * 3)(*[_ptr(a) for a in dB])
+    _check(_lib.gcb_push_backward(ctx, C.byref(start), C.byref(prm), int(n_steps),
+                                  C.byref(le), C.byref(ls), C.byref(de), C.byref(db),
+                                  _stream_ptr(stream)), ctx)
+
+
+def gcb_kinetic_energy(ctx, parts: gcb_particles, prm: gcb_params, out, lam_u=None,
+                       stream=None) -> None:
+    lu = (C.c_void_p * 3)(*[_ptr(a) for a in lam_u]) if lam_u is not None else None
+    _check(_lib.gcb_kinetic_energy(ctx, C.byref(parts), C.byref(prm), _ptr(out),
+                                   C.byref(lu) if lu is not None else None,
+                                   _stream_ptr(stream)), ctx)
+
+
+def gcb_set_timing(ctx, enabled: bool) -> None:
+    _check(_lib.gcb_set_timing(ctx, 1 if enabled else 0), ctx)
+
+
+def gcb_get_timing(ctx):
+    ms = (C.c_double * GCB_NTIMERS)()
+    cnt = (C.c_int64 * GCB_NTIMERS)()
+    _check(_lib.gcb_get_timing(ctx, C.byref(ms), C.byref(cnt)), ctx)
+    return list(ms), list(cnt)

@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every entry point include/gcb.h
+declares; host-side argument checks work without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gcb.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gcb_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("gcb_load_fields", "gcb_push", "gcb_push_backward", "gcb_create",
+                 "gcb_destroy", "gcb_last_error"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2007_14401_amd import gcb
+    lib = C.CDLL(gcb.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(gcb.EXPORTED) == set(declared_functions())
+
+
+def test_null_arguments_rejected_without_device():
+    from paper_2007_14401_amd import gcb
+    lib = gcb.lib()
+    assert lib.gcb_create(None, 0) == gcb.GCB_EINVAL
+    assert "NULL" in gcb.gcb_last_error(None)
+    assert lib.gcb_push(None, None, None, 1, None, None, None) == gcb.GCB_EINVAL
+    assert lib.gcb_load_fields(None, None, None, None, 0, None) == gcb.GCB_EINVAL
+    assert lib.gcb_push_backward(None, None, None, 1, None, None, None, None, None) in (
+        gcb.GCB_EINVAL, gcb.GCB_EUNSUPPORTED)
+    assert lib.gcb_kinetic_energy(None, None, None, None, None, None) == gcb.GCB_EINVAL
+    assert lib.gcb_set_timing(None, 1) == gcb.GCB_EINVAL
+    lib.gcb_destroy(None)
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2007_14401_amd import gcb
+    with pytest.raises(gcb.GcbError) as e:
+        gcb.gcb_create(0)
+    assert e.value.code in (gcb.GCB_EHIP, gcb.GCB_EINVAL)
+
+
+def test_params_struct_layout_matches_header():
+    """ctypes mirrors of the C structs have the sizes the header implies."""
+    from paper_2007_14401_amd import gcb
+    assert C.sizeof(gcb.gcb_params) == 6 * 8 + 6 * 4
+    assert C.sizeof(gcb.gcb_particles) == 8 + 10 * 8
+    assert C.sizeof(gcb.gcb_grid_desc) == 4 + 4 + 8 + 8 + 96 + 8
+    assert C.sizeof(gcb.gcb_stats) == 5 * 8

@@ -27,7 +27,7 @@ from .particles import (Ensemble, initial_state, maxwell_juttner_u,
 # Chosen with the CPU oracle's switch on the harris4096 initial state so that
 # 70 % of the particles start in the guiding-center regime
 # (oracle/calibrate_qm.py prints the fraction for a given value).
-MIX_QM = -2.33
+MIX_QM = -1.89
 
 
 @dataclass(frozen=True)
