@@ -22,6 +22,8 @@ from typing import NamedTuple
 import numpy as np
 import torch
 
+from .ieee import sqrt
+
 F64 = torch.float64
 
 YEE = ((0.5, 0.0), (0.0, 0.5), (0.0, 0.0), (0.0, 0.5), (0.5, 0.0), (0.5, 0.5))
@@ -155,7 +157,7 @@ class CircularFields:
         dx = X - self.xc
         dy = Y - self.yc
         r2 = dx * dx + dy * dy
-        r = torch.sqrt(r2)
+        r = sqrt(r2)
         r3 = r2 * r
         Bx = -self.B0 * dy / r
         By = self.B0 * dx / r

@@ -40,6 +40,8 @@ from types import SimpleNamespace
 
 import torch
 
+from .ieee import sqrt
+
 F64 = torch.float64
 
 # sticky per-particle status bits
@@ -134,7 +136,7 @@ def local(prov, X, Y, p: Params):
     Ex, Ey, Ez = s.E
     Bx, By, Bz = s.B
     B2 = (Bx * Bx + By * By) + Bz * Bz
-    B = torch.sqrt(B2)
+    B = sqrt(B2)
     bzero = B == 0.0
     inv_B = torch.where(bzero, 0.0, 1.0 / torch.where(bzero, 1.0, B))
     bx, by, bz = Bx * inv_B, By * inv_B, Bz * inv_B
@@ -147,7 +149,7 @@ def local(prov, X, Y, p: Params):
     om = 1.0 - vE2 * p.inv_c2
     kflag = om < KAPPA_FLOOR
     om = torch.where(kflag, KAPPA_FLOOR, om)
-    kappa = 1.0 / torch.sqrt(om)
+    kappa = 1.0 / sqrt(om)
     Epar = (Ex * bx + Ey * by) + Ez * bz
     # d_j b_i = (d_j B_i - b_i d_j|B|)/B with d_j|B| = b . d_j B
     db = []
@@ -171,7 +173,7 @@ def local(prov, X, Y, p: Params):
 def gamma_gca(L, upar, mu, p: Params):
     """Gamma(R, u_par) = kappa sqrt(1 + (u_par^2 + 2 mu B kappa / m)/c^2) (eq. lfacgca2)."""
     uperp2 = ((2.0 * mu) * L.B) * L.kappa
-    return L.kappa * torch.sqrt(1.0 + (upar * upar + uperp2) * p.inv_c2)
+    return L.kappa * sqrt(1.0 + (upar * upar + uperp2) * p.inv_c2)
 
 
 def v_curv(L, upar, gam, inv_qm, p: Params):
@@ -198,11 +200,11 @@ def switch_gca(s, ux, uy, uz, qm, p: Params):
     """
     Ex, Ey, Ez = s.E
     Bx, By, Bz = s.B
-    B = torch.sqrt((Bx * Bx + By * By) + Bz * Bz)
-    E = torch.sqrt((Ex * Ex + Ey * Ey) + Ez * Ez)
+    B = sqrt((Bx * Bx + By * By) + Bz * Bz)
+    E = sqrt((Ex * Ex + Ey * Ey) + Ez * Ez)
     pos = B > 0.0
     inv_B = torch.where(pos, 1.0 / torch.where(pos, B, 1.0), 0.0)
-    gf = torch.sqrt(1.0 + ((ux * ux + uy * uy) + uz * uz) * p.inv_c2)
+    gf = sqrt(1.0 + ((ux * ux + uy * uy) + uz * uz) * p.inv_c2)
     inv_absqm = torch.abs(1.0 / qm)
     rho = ((p.c2 * gf) * inv_B) * inv_absqm
     return pos & (rho * (1.0 / p.dl) < p.f_rho) & (E * inv_B < p.f_E)
@@ -218,7 +220,7 @@ def boris(E, B, ux, uy, uz, qm, p: Params):
     Bx, By, Bz = B
     hq = (qm * p.dt) * 0.5
     umx, umy, umz = ux + hq * Ex, uy + hq * Ey, uz + hq * Ez
-    gm = torch.sqrt(1.0 + ((umx * umx + umy * umy) + umz * umz) * p.inv_c2)
+    gm = sqrt(1.0 + ((umx * umx + umy * umy) + umz * umz) * p.inv_c2)
     f = hq / (p.c * gm)
     tx, ty, tz = f * Bx, f * By, f * Bz
     t2 = (tx * tx + ty * ty) + tz * tz
@@ -237,7 +239,7 @@ def boris(E, B, ux, uy, uz, qm, p: Params):
 def boris_step(s, st: State, p: Params):
     """Full Boris step: new (x, y, u); x^{n+1} = x^n + dt u^{n+1/2}/Gamma^{n+1/2}."""
     ux, uy, uz = boris(s.E, s.B, st.ux, st.uy, st.uz, st.qm, p)
-    gn = torch.sqrt(1.0 + ((ux * ux + uy * uy) + uz * uz) * p.inv_c2)
+    gn = sqrt(1.0 + ((ux * ux + uy * uy) + uz * uz) * p.inv_c2)
     inv_g = 1.0 / gn
     xn = st.x + p.dt * (ux * inv_g)
     yn = st.y + p.dt * (uy * inv_g)
@@ -270,7 +272,7 @@ def parallel_update(Ln, upar, mu, qm, p: Params):
     disc = k2 * k2 - (4.0 * k1) * k3
     dok = torch.abs(D) >= D_FLOOR
     ok = (k1 < 0.0) & (disc >= 0.0) & dok
-    sq = torch.sqrt(torch.where(disc >= 0.0, disc, 0.0))
+    sq = sqrt(torch.where(disc >= 0.0, disc, 0.0))
     # positive root without cancellation: (k2 + sq)/(-2 k1) if k2 >= 0,
     # else 2 k3/(sq - k2)
     pos_k2 = k2 >= 0.0
@@ -317,7 +319,7 @@ def gca_step(prov, st: State, p: Params):
     flags |= Lh.flags
     bx, by, bz = Lh.b
     upar = (ux * bx + uy * by) + uz * bz
-    gf = torch.sqrt(1.0 + ((ux * ux + uy * uy) + uz * uz) * p.inv_c2)
+    gf = sqrt(1.0 + ((ux * ux + uy * uy) + uz * uz) * p.inv_c2)
     if p.curvature:
         vc = v_curv(Lh, upar, gf, inv_qm, p)
     else:
@@ -328,7 +330,7 @@ def gca_step(prov, st: State, p: Params):
     upz = (uz - upar * bz) - (Lh.vE[2] + vc[2]) * gf
     up2 = (upx * upx + upy * upy) + upz * upz
     mu = ((0.5 * up2) * Lh.inv_B) / Lh.kappa
-    nu = torch.sqrt(up2)
+    nu = sqrt(up2)
     inv_nu = torch.where(nu > 0.0, 1.0 / torch.where(nu > 0.0, nu, 1.0), 0.0)
     bpx, bpy, bpz = upx * inv_nu, upy * inv_nu, upz * inv_nu
 
@@ -367,7 +369,7 @@ def gca_step(prov, st: State, p: Params):
     else:
         z = torch.zeros_like(x)
         vcm = (z, z, z)
-    um = torch.sqrt(((2.0 * mu) * Lm.B) * Lm.kappa)
+    um = sqrt(((2.0 * mu) * Lm.B) * Lm.kappa)
     bmx, bmy, bmz = Lm.b
     uxn = (upn * bmx + (Lm.vE[0] + vcm[0]) * gr) + um * bpx
     uyn = (upn * bmy + (Lm.vE[1] + vcm[1]) * gr) + um * bpy
