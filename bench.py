@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--kernel", type=int, default=0)
     ap.add_argument("--sort-every", type=int, default=4)
-    ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--tile", type=int, default=24)
     ap.add_argument("--f-rho", type=float, default=None)
     ap.add_argument("--f-E", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")

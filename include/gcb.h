@@ -130,7 +130,7 @@ typedef struct {
     int32_t sort_every;  /* cell-sort the particles every this many steps
                             (0 = never; the tiled kernel needs > 0) */
     int32_t kernel;      /* GCB_KERNEL_* */
-    int32_t tile;        /* tile edge in cells for the tiled kernel (0 = 32) */
+    int32_t tile;        /* tile edge in cells for the tiled kernel (0 = 24) */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.

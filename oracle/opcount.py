@@ -1,0 +1,95 @@
+"""Count the floating-point operations of one oracle step per particle
+(TEST INFRASTRUCTURE; a script that calls only the oracle).
+
+Every elementwise torch arithmetic call made by the oracle is intercepted and
+charged (number of output elements) x (flops per element): add, sub, mul, div,
+sqrt, neg, abs, floor, comparisons and where/maximum each count as one
+operation per element; integer index arithmetic is not counted.  Running one
+step with the switch forced to one branch (f_rho = 0: every particle Boris;
+f_rho = f_E = inf: every particle guiding center) and dividing by the number
+of particles gives the per-branch counts used for the arithmetic roofline.
+
+    python -m oracle.opcount
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+from torch.overrides import TorchFunctionMode
+
+from workloads import make_config
+
+from .fields import GridFields
+from .pusher import Params, State, step
+
+_ARITH = {
+    "add", "__add__", "__radd__", "sub", "__sub__", "__rsub__", "mul", "__mul__",
+    "__rmul__", "div", "__truediv__", "__rtruediv__", "true_divide", "sqrt", "neg",
+    "__neg__", "abs", "floor", "maximum", "where", "lt", "le", "gt", "ge", "eq", "ne",
+    "__lt__", "__le__", "__gt__", "__ge__", "__eq__", "__ne__", "remainder",
+}
+
+
+class _Count(TorchFunctionMode):
+    def __init__(self):
+        super().__init__()
+        self.flops = 0
+        self.by = {}
+
+    def __torch_function__(self, func, types, args=(), kwargs=None):
+        out = func(*args, **(kwargs or {}))
+        name = getattr(func, "__name__", "")
+        if name in _ARITH and isinstance(out, torch.Tensor) and out.is_floating_point():
+            self.flops += out.numel()
+            self.by[name] = self.by.get(name, 0) + out.numel()
+        elif name in _ARITH and isinstance(out, torch.Tensor) and out.dtype == torch.bool:
+            # comparisons on floating inputs
+            if any(isinstance(a, torch.Tensor) and a.is_floating_point() for a in args):
+                self.flops += out.numel()
+                self.by[name] = self.by.get(name, 0) + out.numel()
+        return out
+
+
+def count(cfg_name="harris4096", n=4096, **over):
+    cfg = make_config(cfg_name)
+    F = cfg.fields()
+    ens = cfg.particles(n=n)
+    p = Params(dt=cfg.dt, c=cfg.c, f_rho=cfg.f_rho, f_E=cfg.f_E, curvature=True,
+               n_iter=cfg.n_iter, Lx=cfg.Lx, Ly=cfg.Ly, dl=math.sqrt(cfg.dx * cfg.dy))
+    for k, v in over.items():
+        setattr(p, k, v)
+    prov = GridFields(F, cfg.dx, cfg.dy, cfg.stagger)
+    st = State.from_numpy(ens)
+    # the sqrt of the oracle goes through numpy; count it explicitly
+    import oracle.ieee as ieee
+    orig = ieee.sqrt
+    calls = {"n": 0}
+
+    def counting_sqrt(x):
+        calls["n"] += x.numel()
+        return orig(x)
+    ieee.sqrt = counting_sqrt
+    import oracle.pusher as pusher
+    pusher.sqrt = counting_sqrt
+    try:
+        with _Count() as c:
+            _, S, _ = step(prov, st, p)
+    finally:
+        ieee.sqrt = orig
+        pusher.sqrt = orig
+    return (c.flops + calls["n"]) / n, c.by, calls["n"] / n
+
+
+def main():
+    b, _, bs = count(f_rho=0.0)
+    g, by, gs = count(f_rho=math.inf, f_E=math.inf)
+    print(f"Boris branch:           {b:8.1f} flops/particle-step ({bs:.1f} sqrt)")
+    print(f"Guiding-center branch:  {g:8.1f} flops/particle-step ({gs:.1f} sqrt), K=4, curvature")
+    g3, _, _ = count(f_rho=math.inf, f_E=math.inf, n_iter=3)
+    print(f"Guiding-center, K=3:    {g3:8.1f}")
+
+
+if __name__ == "__main__":
+    main()

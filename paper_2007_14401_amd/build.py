@@ -16,12 +16,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libgcb.so")
+LIB = os.environ.get("GCB_LIB_OUT", os.path.join(HERE, "libgcb.so"))
+BUILD = os.environ.get("GCB_BUILD_DIR", BUILD)
 
 ARCH = os.environ.get("GCB_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+          *os.environ.get("GCB_HIPCC_FLAGS", "").split()]
 UNITS = {
     "gcb_host.hip": ["-ffp-contract=off"],
     "gcb_push_f64.hip": ["-ffp-contract=off"],

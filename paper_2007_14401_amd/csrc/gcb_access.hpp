@@ -1,5 +1,13 @@
 // Field sources for the gather: the node-interleaved device array in HBM,
 // and the LDS window of a tile with a global-memory fallback.
+//
+// Two interfaces:
+//   quad(k, i, j, ...)   the 2x2 node values of component k around cell (i, j)
+//                        (any lattice offsets; used with a runtime stagger table)
+//   locate(...)/load4()  the 2D Yee lattice: the six components use four
+//                        weight sets (x offset 0 or 1/2, y offset 0 or 1/2);
+//                        locate() resolves the four 2x2 stencils once per
+//                        gather point, load4() fetches one component.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,6 +16,27 @@
 #include "gcb_common.hpp"
 
 namespace gcb {
+
+// Loader of the LDS window: node (0,0) of each weight set at off[set].
+template <typename T>
+struct LdsLoad {
+    const T* lds;
+    const int* off;
+    int W6;
+    __device__ __forceinline__ void load4(int set, int k, double& f00, double& f10,
+                                          double& f01, double& f11) const {
+        const T* p = lds + off[set] + k;
+        f00 = (double)p[0];
+        f10 = (double)p[6];
+        f01 = (double)p[W6];
+        f11 = (double)p[W6 + 6];
+    }
+};
+
+// Weight-set indices of the Yee lattice: bit 0 = x offset 1/2, bit 1 = y offset 1/2.
+// Ex (1/2,0) -> 1, Ey (0,1/2) -> 2, Ez (0,0) -> 0, Bx (0,1/2) -> 2, By (1/2,0) -> 1,
+// Bz (1/2,1/2) -> 3.
+__device__ constexpr int kYeeSet[6] = {1, 2, 0, 2, 1, 3};
 
 // Device layout of the fields: node-interleaved, F[(j*nx + i)*6 + k], with k
 // the component (Ex, Ey, Ez, Bx, By, Bz) at that component's own node (i, j).
@@ -31,6 +60,44 @@ struct GlobalAcc {
         f10 = (double)r0[i1 * 6 + k];
         f01 = (double)r1[i0 * 6 + k];
         f11 = (double)r1[i1 * 6 + k];
+    }
+
+    // Yee stencils: ia/ib = floor of the x coordinate for offsets 0 and 1/2,
+    // ja/jb likewise in y.
+    struct Loc {
+        const T* row[2][2];   // [y set][row 0/1]
+        int col[2][2];        // [x set][column 0/1], in elements
+    };
+
+    __device__ __forceinline__ void locate(int ia, int ib, int ja, int jb, Loc& L) const {
+        const int xi[2] = {ia, ib};
+        const int yj[2] = {ja, jb};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int c0 = wrap_index(xi[s], nx);
+            const int c1 = (c0 + 1 == nx) ? 0 : c0 + 1;
+            L.col[s][0] = c0 * 6;
+            L.col[s][1] = c1 * 6;
+            const int r0 = wrap_index(yj[s], ny);
+            const int r1 = (r0 + 1 == ny) ? 0 : r0 + 1;
+            L.row[s][0] = F + (size_t)r0 * nx * 6;
+            L.row[s][1] = F + (size_t)r1 * nx * 6;
+        }
+    }
+
+};
+
+// Loader of the global array for one located gather point.
+template <typename T>
+struct GlobalLoad {
+    const typename GlobalAcc<T>::Loc& L;
+    __device__ __forceinline__ void load4(int set, int k, double& f00, double& f10,
+                                          double& f01, double& f11) const {
+        const int sx = set & 1, sy = set >> 1;
+        f00 = (double)L.row[sy][0][L.col[sx][0] + k];
+        f10 = (double)L.row[sy][0][L.col[sx][1] + k];
+        f01 = (double)L.row[sy][1][L.col[sx][0] + k];
+        f11 = (double)L.row[sy][1][L.col[sx][1] + k];
     }
 };
 
@@ -62,6 +129,35 @@ struct TileAcc {
             GlobalAcc<T> g{F, nx, ny};
             g.quad(k, i, j, f00, f10, f01, f11);
         }
+    }
+
+    // Resolve the Yee stencils of a gather point.  Returns true and fills
+    // `off` (LDS element offset of node (0,0) per weight set) when all four
+    // stencils lie inside the window; otherwise fills the global fallback.
+    // ib <= ia and jb <= ja (the 1/2-offset lattice's floor is never larger).
+    __device__ __forceinline__ bool locate(int ia, int ib, int ja, int jb, int off[4],
+                                           typename GlobalAcc<T>::Loc& g) const {
+        int da = ia - oi;
+        int ea = ja - oj;
+        if (da < 0 || da > W - 2) da += (da < 0) ? nx : -nx;
+        if (ea < 0 || ea > W - 2) ea += (ea < 0) ? ny : -ny;
+        const int sa = ia - ib, sb = ja - jb;   // 0 or 1 for finite coordinates
+        const int db = da - sa;
+        const int eb = ea - sb;
+        const bool in = (unsigned)sa <= 1u && (unsigned)sb <= 1u && db >= 0 && eb >= 0 &&
+                        da <= W - 2 && ea <= W - 2;
+        if (in) {
+            const int W6 = W * 6;
+            off[0] = __mul24(ea, W6) + __mul24(da, 6);
+            off[1] = __mul24(ea, W6) + __mul24(db, 6);
+            off[2] = __mul24(eb, W6) + __mul24(da, 6);
+            off[3] = __mul24(eb, W6) + __mul24(db, 6);
+        } else {
+            miss = true;
+            GlobalAcc<T> gl{F, nx, ny};
+            gl.locate(ia, ib, ja, jb, g);
+        }
+        return in;
     }
 };
 

@@ -41,8 +41,7 @@ struct gcb_ctx {
     bool yee = false;
     DevBuf fields;
     // scratch
-    DevBuf sort_keys, sort_idx, sort_keys2, sort_idx2, sort_hist, sort_scan, tile_count,
-        tile_start;
+    DevBuf sort_keys, sort_idx, sort_keys2, sort_idx2, sort_hist, sort_scan, tile_start;
     DevBuf pscratch;     // sorted copy of the particle state
     DevBuf stats;        // DevStats + flagged counter
     DevBuf ke_partial;
@@ -242,7 +241,7 @@ PushConst make_const(const gcb_ctx* ctx, const gcb_params* prm) {
 
 TileGeom make_geom(const gcb_ctx* ctx, const gcb_params* prm) {
     TileGeom g;
-    g.tile = prm->tile ? prm->tile : 32;
+    g.tile = prm->tile ? prm->tile : 24;
     const double inv_min = std::max(1.0 / ctx->dx, 1.0 / ctx->dy);
     const int se = prm->sort_every > 0 ? prm->sort_every : 1;
     g.halo = (int)std::ceil(se * prm->c * prm->dt * inv_min) + 1;
@@ -265,7 +264,6 @@ int prepare_sort(gcb_ctx* ctx, int64_t n, const TileGeom& g, SortBuffers& sb) {
     if ((rc = ensure(ctx, ctx->sort_hist, (size_t)nh * 4))) return rc;
     const int64_t ns = std::max(sort_scan_tmp_elems(nh), sort_scan_tmp_elems(ntiles + 1));
     if ((rc = ensure(ctx, ctx->sort_scan, (size_t)ns * 4))) return rc;
-    if ((rc = ensure(ctx, ctx->tile_count, (size_t)(ntiles + 1) * 4))) return rc;
     if ((rc = ensure(ctx, ctx->tile_start, (size_t)(ntiles + 1) * 4))) return rc;
     sb.keys = static_cast<uint32_t*>(ctx->sort_keys.ptr);
     sb.idx = static_cast<uint32_t*>(ctx->sort_idx.ptr);
@@ -273,7 +271,6 @@ int prepare_sort(gcb_ctx* ctx, int64_t n, const TileGeom& g, SortBuffers& sb) {
     sb.idx2 = static_cast<uint32_t*>(ctx->sort_idx2.ptr);
     sb.hist = static_cast<uint32_t*>(ctx->sort_hist.ptr);
     sb.scan_tmp = static_cast<uint32_t*>(ctx->sort_scan.ptr);
-    sb.tile_count = static_cast<int32_t*>(ctx->tile_count.ptr);
     sb.tile_start = static_cast<int32_t*>(ctx->tile_start.ptr);
     return GCB_OK;
 }
@@ -371,7 +368,7 @@ void gcb_destroy(gcb_ctx* ctx) {
         (void)hipEventDestroy(l.stop);
     }
     DevBuf* bufs[] = {&ctx->fields,     &ctx->sort_keys,  &ctx->sort_idx,  &ctx->sort_keys2,
-                      &ctx->sort_idx2,  &ctx->sort_hist,  &ctx->sort_scan, &ctx->tile_count,
+                      &ctx->sort_idx2,  &ctx->sort_hist,  &ctx->sort_scan,
                       &ctx->tile_start, &ctx->pscratch,   &ctx->stats,     &ctx->ke_partial,
                       &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace};
     for (DevBuf* b : bufs) release(*b);

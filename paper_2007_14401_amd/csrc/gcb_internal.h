@@ -56,7 +56,6 @@ struct SortBuffers {
     uint32_t* idx2;      // n
     uint32_t* hist;      // 256 * nblocks (+ scan workspace)
     uint32_t* scan_tmp;  // scan block sums
-    int32_t* tile_count; // ntiles + 1
     int32_t* tile_start; // ntiles + 1
 };
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gcb_access.hpp"
 #include "gcb_common.hpp"
 
 namespace gcb {
@@ -46,28 +47,84 @@ __device__ __forceinline__ void interp_comp(const Acc& acc, int k, double gx, do
     }
 }
 
-// All six components at (X, Y); B gradients when kGrad.  kYee selects the
-// compile-time 2D Yee offsets (identical values to the runtime table when the
-// table holds them; the compiler then shares the weight sets of Ex/By and
-// Ey/Bx).
+// The six components from four located 2x2 stencils (2D Yee lattice): the
+// same operations as interp_comp, with the floor/weight computations shared
+// by the components of one weight set.
+template <bool kGrad, class Loader>
+__device__ __forceinline__ void interp_yee(const Loader& ld, const double wx[2],
+                                           const double wy[2], double inv_dx, double inv_dy,
+                                           Sample& s) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int set = kYeeSet[k];
+        const double ax = 1.0 - wx[set & 1];
+        const double ay = 1.0 - wy[set >> 1];
+        const double bx = wx[set & 1];
+        const double by = wy[set >> 1];
+        double f00, f10, f01, f11;
+        ld.load4(set, k, f00, f10, f01, f11);
+        const double val =
+            (((ax * ay) * f00 + (bx * ay) * f10) + (ax * by) * f01) + (bx * by) * f11;
+        if (k < 3) {
+            s.E[k] = val;
+        } else {
+            s.B[k - 3] = val;
+            if (kGrad) {
+                s.dBx[k - 3] = (ay * (f10 - f00) + by * (f11 - f01)) * inv_dx;
+                s.dBy[k - 3] = (ax * (f01 - f00) + bx * (f11 - f10)) * inv_dy;
+            }
+        }
+    }
+}
+
+template <bool kGrad, typename T>
+__device__ __forceinline__ void yee_fetch(const GlobalAcc<T>& acc, int ia, int ib, int ja,
+                                          int jb, const double wx[2], const double wy[2],
+                                          const PushConst& pc, Sample& s) {
+    typename GlobalAcc<T>::Loc g;
+    acc.locate(ia, ib, ja, jb, g);
+    interp_yee<kGrad>(GlobalLoad<T>{g}, wx, wy, pc.inv_dx, pc.inv_dy, s);
+}
+
+template <bool kGrad, typename T>
+__device__ __forceinline__ void yee_fetch(const TileAcc<T>& acc, int ia, int ib, int ja,
+                                          int jb, const double wx[2], const double wy[2],
+                                          const PushConst& pc, Sample& s) {
+    int off[4];
+    typename GlobalAcc<T>::Loc g;
+    if (acc.locate(ia, ib, ja, jb, off, g))
+        interp_yee<kGrad>(LdsLoad<T>{acc.lds, off, acc.W * 6}, wx, wy, pc.inv_dx, pc.inv_dy,
+                          s);
+    else
+        interp_yee<kGrad>(GlobalLoad<T>{g}, wx, wy, pc.inv_dx, pc.inv_dy, s);
+}
+
+// All six components at (X, Y); B gradients when kGrad.  kYee: the 2D Yee
+// offsets (the values of the runtime table when it holds them).
 template <bool kGrad, bool kYee, class Acc>
 __device__ __forceinline__ void gather(const Acc& acc, const PushConst& pc, double X,
                                        double Y, Sample& s) {
     const double gx = X * pc.inv_dx;
     const double gy = Y * pc.inv_dy;
-    double d0, d1;
+    if constexpr (kYee) {
+        // lattice coordinate minus the offset: offset 0 leaves it unchanged
+        const double xb = gx - 0.5;
+        const double yb = gy - 0.5;
+        const double fxa = floor(gx), fxb = floor(xb);
+        const double fya = floor(gy), fyb = floor(yb);
+        const double wx[2] = {gx - fxa, xb - fxb};
+        const double wy[2] = {gy - fya, yb - fyb};
+        yee_fetch<kGrad>(acc, (int)fxa, (int)fxb, (int)fya, (int)fyb, wx, wy, pc, s);
+    } else {
+        double d0, d1;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double sx = kYee ? kYeeStagger[k][0] : pc.stagger[k][0];
-        const double sy = kYee ? kYeeStagger[k][1] : pc.stagger[k][1];
-        interp_comp<false>(acc, k, gx, gy, sx, sy, pc.inv_dx, pc.inv_dy, s.E[k], d0, d1);
-    }
+        for (int k = 0; k < 3; ++k)
+            interp_comp<false>(acc, k, gx, gy, pc.stagger[k][0], pc.stagger[k][1],
+                               pc.inv_dx, pc.inv_dy, s.E[k], d0, d1);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double sx = kYee ? kYeeStagger[k + 3][0] : pc.stagger[k + 3][0];
-        const double sy = kYee ? kYeeStagger[k + 3][1] : pc.stagger[k + 3][1];
-        interp_comp<kGrad>(acc, k + 3, gx, gy, sx, sy, pc.inv_dx, pc.inv_dy, s.B[k],
-                           s.dBx[k], s.dBy[k]);
+        for (int k = 0; k < 3; ++k)
+            interp_comp<kGrad>(acc, k + 3, gx, gy, pc.stagger[k + 3][0], pc.stagger[k + 3][1],
+                               pc.inv_dx, pc.inv_dy, s.B[k], s.dBx[k], s.dBy[k]);
     }
 }
 

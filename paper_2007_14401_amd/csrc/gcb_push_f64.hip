@@ -21,6 +21,11 @@ namespace {
 
 constexpr int kWG = 256;
 
+// Minimum waves per SIMD the tiled kernel is compiled for (register budget).
+#ifndef GCB_TILED_MIN_WAVES
+#define GCB_TILED_MIN_WAVES 3
+#endif
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off, 64));
@@ -118,7 +123,7 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<double> in,
 }
 
 template <bool kYee>
-__global__ __launch_bounds__(kWG) void k_push_tiled(ParticlePtrs<double> in,
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(GCB_TILED_MIN_WAVES))) void k_push_tiled(ParticlePtrs<double> in,
                                                      ParticlePtrs<double> out,
                                                      const int32_t* __restrict__ tile_start,
                                                      TileGeom g, int chunk,

@@ -3,12 +3,12 @@
 // kernel can stage one field window per workgroup.
 //
 // Pipeline (all on the caller's stream):
-//   k_tile_keys   key = tile index of (x, y); idx = slot; per-tile counts
+//   k_tile_keys   key = tile index of (x, y); idx = slot
 //   LSD radix sort of (key, idx), 8 bits per pass, stable:
 //     k_radix_hist     per-block digit histogram, digit-major [256][nblocks]
 //     scan             exclusive scan of the histogram (3 kernels)
 //     k_radix_scatter  wave-level multisplit ranks -> stable scatter
-//   scan of the per-tile counts -> tile_start
+//   k_tile_bounds tile_start from the boundaries of the sorted keys
 //   k_permute     gather every state array through idx
 #include <hip/hip_runtime.h>
 
@@ -27,8 +27,7 @@ __global__ __launch_bounds__(kSortWG) void k_tile_keys(const double* __restrict_
                                                        const double* __restrict__ y,
                                                        int64_t n, double inv_dx,
                                                        double inv_dy, TileGeom g,
-                                                       uint32_t* keys, uint32_t* idx,
-                                                       int32_t* tile_count) {
+                                                       uint32_t* keys, uint32_t* idx) {
     const int64_t p = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
     if (p >= n) return;
     const double gx = floor(x[p] * inv_dx);
@@ -41,7 +40,18 @@ __global__ __launch_bounds__(kSortWG) void k_tile_keys(const double* __restrict_
     const uint32_t key = (uint32_t)(ty * g.ntx + tx);
     keys[p] = key;
     idx[p] = (uint32_t)p;
-    atomicAdd(&tile_count[key], 1);
+}
+
+// tile_start[t] = first sorted slot whose key is >= t, for t in [0, ntiles]:
+// every slot i writes the starts of the tiles in (key[i-1], key[i]].
+__global__ __launch_bounds__(kSortWG) void k_tile_bounds(const uint32_t* __restrict__ keys,
+                                                         int64_t n, int ntiles,
+                                                         int32_t* tile_start) {
+    const int64_t i = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
+    if (i > n) return;
+    const int lo = i == 0 ? -1 : (int)keys[i - 1];
+    const int hi = i == n ? ntiles : (int)keys[i];
+    for (int t = lo + 1; t <= hi; ++t) tile_start[t] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(kSortWG) void k_radix_hist(const uint32_t* __restrict__ keys,
@@ -243,24 +253,22 @@ hipError_t launch_cell_sort(const double* x, const double* y, int64_t n, double 
                             double inv_dy, const TileGeom& g, const SortBuffers& b,
                             hipStream_t stream) {
     const int ntiles = g.ntx * g.nty;
-    hipError_t e = hipMemsetAsync(b.tile_count, 0, sizeof(int32_t) * (ntiles + 1), stream);
-    if (e != hipSuccess) return e;
+    uint32_t* kin = b.keys;
+    uint32_t* iin = b.idx;
     if (n > 0) {
         const unsigned blocks = (unsigned)((n + kSortWG - 1) / kSortWG);
         hipLaunchKernelGGL(k_tile_keys, dim3(blocks), dim3(kSortWG), 0, stream, x, y, n,
-                           inv_dx, inv_dy, g, b.keys, b.idx, b.tile_count);
+                           inv_dx, inv_dy, g, b.keys, b.idx);
         int nbits = 0;
         while ((1 << nbits) < ntiles) ++nbits;
         const int nblocks = (int)((n + kItems - 1) / kItems);
         const int64_t nh = 256ll * nblocks;
-        uint32_t* kin = b.keys;
-        uint32_t* iin = b.idx;
         uint32_t* kout = b.keys2;
         uint32_t* iout = b.idx2;
         for (int shift = 0; shift < nbits; shift += 8) {
             hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortWG), 0, stream, kin, n,
                                shift, nblocks, b.hist);
-            e = scan_exclusive(b.hist, b.hist, nh, b.scan_tmp, stream);
+            hipError_t e = scan_exclusive(b.hist, b.hist, nh, b.scan_tmp, stream);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortWG), 0, stream, kin,
                                iin, n, shift, nblocks, b.hist, kout, iout);
@@ -269,14 +277,15 @@ hipError_t launch_cell_sort(const double* x, const double* y, int64_t n, double 
         }
         // the sorted permutation must end in b.idx
         if (iin != b.idx) {
-            e = hipMemcpyAsync(b.idx, iin, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice,
-                               stream);
+            hipError_t e = hipMemcpyAsync(b.idx, iin, sizeof(uint32_t) * n,
+                                          hipMemcpyDeviceToDevice, stream);
             if (e != hipSuccess) return e;
         }
     }
-    return scan_exclusive(reinterpret_cast<const uint32_t*>(b.tile_count),
-                          reinterpret_cast<uint32_t*>(b.tile_start), ntiles + 1, b.scan_tmp,
-                          stream);
+    const unsigned blocks = (unsigned)((n + 1 + kSortWG - 1) / kSortWG);
+    hipLaunchKernelGGL(k_tile_bounds, dim3(blocks), dim3(kSortWG), 0, stream, kin, n, ntiles,
+                       b.tile_start);
+    return hipGetLastError();
 }
 
 template <typename U>
