@@ -29,6 +29,11 @@ if ROOT not in sys.path:
 METRIC = "particle-steps/sec at 1e7 particles (fwd, fwd+adjoint) + % HBM peak"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
 FP64_VECTOR_PEAK_TF = 78.6      # MI355X FP64 vector, AMD published
+# Floating-point operations of one oracle step per particle and branch (K = 4,
+# curvature terms on), counted by `python -m oracle.opcount`: every elementwise
+# add, sub, mul, div, sqrt, floor, comparison and select of the definition.
+FLOPS_BORIS = 287.0
+FLOPS_GCA = 2216.0
 
 
 def log(*a):
@@ -86,6 +91,7 @@ def main():
     ap.add_argument("--f-rho", type=float, default=None)
     ap.add_argument("--f-E", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -115,39 +121,62 @@ def main():
     ens = cfg.particles(n=n)
 
     dev = torch.device("cuda:0")
-    ctx = gcb.gcb_create(0)
-    desc = gcb.grid_desc(cfg.nx, cfg.ny, cfg.dx, cfg.dy, cfg.stagger, gcb.GCB_F64)
-    gcb.gcb_load_fields(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
-    t = state.to_device(ens, dev, per_particle_qm=False)
-    parts = gcb.particles(t)
-    prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
-                     curvature=cfg.curvature, n_iter=cfg.n_iter, sort_every=a.sort_every,
-                     kernel=a.kernel, tile=a.tile)
 
-    log(f"[bench] warmup {a.warmup} steps")
-    st = gcb.gcb_push(ctx, parts, prm, a.warmup, want_stats=True)
-    log(f"[bench] warmup stats {st}")
-    torch.cuda.synchronize()
+    def time_form(form: int, fields_dtype: int, steps: int, warmup: int):
+        """Time `steps` pushes of the whole population in one form."""
+        ctx = gcb.gcb_create(0)
+        try:
+            desc = gcb.grid_desc(cfg.nx, cfg.ny, cfg.dx, cfg.dy, cfg.stagger, fields_dtype)
+            gcb.gcb_load_fields(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
+            t = state.to_device(ens, dev, form=form, per_particle_qm=False)
+            parts = gcb.particles(t)
+            prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                             curvature=cfg.curvature, n_iter=cfg.n_iter, form=form,
+                             sort_every=a.sort_every, kernel=a.kernel, tile=a.tile)
+            log(f"[bench] form {form}: warmup {warmup} steps")
+            st = gcb.gcb_push(ctx, parts, prm, warmup, want_stats=True)
+            log(f"[bench] warmup stats {st}")
+            gcb.gcb_set_timing(ctx, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gcb.gcb_push(ctx, parts, prm, steps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ms, cnt = gcb.gcb_get_timing(ctx)
+            gcb.gcb_set_timing(ctx, False)
+            log(f"[bench] form {form}: {steps} steps in {t1 - t0:.3f} s; kernel ms {ms} "
+                f"launches {cnt}")
+            st = gcb.gcb_push(ctx, parts, prm, 1, want_stats=True)
+            torch.cuda.synchronize()
+            del t
+            return {"wall": t1 - t0,
+                    "push_ms": ms[gcb.GCB_TIMER_PUSH] / max(1, cnt[gcb.GCB_TIMER_PUSH]),
+                    "sort_ms": ms[gcb.GCB_TIMER_SORT] / max(1, cnt[gcb.GCB_TIMER_SORT]),
+                    "gca_frac": st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])}
+        finally:
+            gcb.gcb_destroy(ctx)
+            torch.cuda.empty_cache()
 
-    gcb.gcb_set_timing(ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gcb.gcb_push(ctx, parts, prm, a.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms, cnt = gcb.gcb_get_timing(ctx)
-    gcb.gcb_set_timing(ctx, False)
-    wall = t1 - t0
-    log(f"[bench] timed {a.steps} steps in {wall:.3f} s; kernel ms {ms} launches {cnt}")
-
-    st = gcb.gcb_push(ctx, parts, prm, 1, want_stats=True)
-    gca_frac = st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])
-
-    push_ms = ms[gcb.GCB_TIMER_PUSH] / max(1, cnt[gcb.GCB_TIMER_PUSH])
-    sort_ms = ms[gcb.GCB_TIMER_SORT] / max(1, cnt[gcb.GCB_TIMER_SORT])
+    r64 = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup)
+    wall, push_ms, sort_ms, gca_frac = r64["wall"], r64["push_ms"], r64["sort_ms"], r64["gca_frac"]
     bytes_step = push_bytes_per_step(n, cfg.nx, cfg.ny, 0)
     achieved = bytes_step / (push_ms * 1e-3) / 1e9
     value = n * a.steps / wall
+    flops = FLOPS_GCA * gca_frac + FLOPS_BORIS * (1.0 - gca_frac)
+
+    forms = {}
+    if not a.no_mixed:
+        rm = time_form(gcb.GCB_FORM_MIXED, gcb.GCB_F32, a.steps, a.warmup)
+        bm = push_bytes_per_step(n, cfg.nx, cfg.ny, 1)
+        forms["mixed"] = {
+            "value": n * a.steps / rm["wall"], "unit": "particle-steps/s",
+            "ms_per_step": rm["wall"] * 1e3 / a.steps, "kernel_ms": rm["push_ms"],
+            "sort_ms_per_sort": rm["sort_ms"],
+            "hbm_achieved_GBs": bm / (rm["push_ms"] * 1e-3) / 1e9,
+            "hbm_frac": bm / (rm["push_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": bm,
+            "speedup_vs_f64": (n * a.steps / rm["wall"]) / value,
+            "dtype": "f32 bulk, f64 positions"}
 
     if a.copy_calib:
         x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -155,6 +184,7 @@ def main():
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
+        del x, y
 
     res = {
         "metric": METRIC,
@@ -180,13 +210,17 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_push_tiled" if a.kernel != 1 else "k_push_global",
-                     "kernel_ms": push_ms, "algorithmic_bytes_per_launch": bytes_step},
+                     "kernel_ms": push_ms, "algorithmic_bytes_per_launch": bytes_step,
+                     "alu_achieved_TFLOPs": flops * n / (push_ms * 1e-3) / 1e12,
+                     "alu_peak_TFLOPs": FP64_VECTOR_PEAK_TF,
+                     "alu_frac": flops * n / (push_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TF,
+                     "algorithmic_flops_per_particle_step": flops},
         "sort_ms_per_sort": sort_ms,
+        "forms": forms,
     }
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(cfg, F, ens)
-    gcb.gcb_destroy(ctx)
     print(json.dumps(res), flush=True)
 
 

@@ -23,13 +23,14 @@ struct LdsLoad {
     const T* lds;
     const int* off;
     int W6;
-    __device__ __forceinline__ void load4(int set, int k, double& f00, double& f10,
-                                          double& f01, double& f11) const {
+    template <typename R>
+    __device__ __forceinline__ void load4(int set, int k, R& f00, R& f10, R& f01,
+                                          R& f11) const {
         const T* p = lds + off[set] + k;
-        f00 = (double)p[0];
-        f10 = (double)p[6];
-        f01 = (double)p[W6];
-        f11 = (double)p[W6 + 6];
+        f00 = (R)p[0];
+        f10 = (R)p[6];
+        f01 = (R)p[W6];
+        f11 = (R)p[W6 + 6];
     }
 };
 
@@ -91,13 +92,14 @@ struct GlobalAcc {
 template <typename T>
 struct GlobalLoad {
     const typename GlobalAcc<T>::Loc& L;
-    __device__ __forceinline__ void load4(int set, int k, double& f00, double& f10,
-                                          double& f01, double& f11) const {
+    template <typename R>
+    __device__ __forceinline__ void load4(int set, int k, R& f00, R& f10, R& f01,
+                                          R& f11) const {
         const int sx = set & 1, sy = set >> 1;
-        f00 = (double)L.row[sy][0][L.col[sx][0] + k];
-        f10 = (double)L.row[sy][0][L.col[sx][1] + k];
-        f01 = (double)L.row[sy][1][L.col[sx][0] + k];
-        f11 = (double)L.row[sy][1][L.col[sx][1] + k];
+        f00 = (R)L.row[sy][0][L.col[sx][0] + k];
+        f10 = (R)L.row[sy][0][L.col[sx][1] + k];
+        f01 = (R)L.row[sy][1][L.col[sx][0] + k];
+        f11 = (R)L.row[sy][1][L.col[sx][1] + k];
     }
 };
 

@@ -1,0 +1,566 @@
+// Per-particle arithmetic of the coupled guiding-center / Boris pusher (device
+// code), templated on the bulk arithmetic type R.
+//
+// R = double: the binary64 form.  Every expression is evaluated in a fixed
+//   order with separate multiplies and adds (its translation unit is compiled
+//   with -ffp-contract=off), so results are reproducible bit for bit.
+// R = float: the mixed form.  Bulk arithmetic in binary32; positions, their
+//   increments' accumulation, midpoints and the periodic wrap stay binary64;
+//   binary64 is also used for the Lorentz factor of ultra-relativistic
+//   particles (u^2/c^2 > 1e6), for 1 - v_E^2/c^2 when E/B > 0.9 (written as
+//   ((B^2 - E^2) B^2 + (E.B)^2)/B^4, free of the cancellation of 1 - v_E^2),
+//   and for the switch test when a ratio lies within 1e-4 of its threshold.
+//
+// The field source is a template parameter: the same arithmetic serves
+// gathers from the LDS tile window and from global memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "gcb_access.hpp"
+#include "gcb_common.hpp"
+
+namespace gcb {
+
+template <typename R>
+constexpr bool kMixed = std::is_same<R, float>::value;
+
+// Constants of a launch in the bulk type.
+template <typename R>
+struct Consts {
+    R dt, h, c, c2, inv_c2, f_rho, f_E, inv_dl, inv_dx, inv_dy;
+};
+
+template <typename R>
+__device__ __forceinline__ Consts<R> make_consts(const PushConst& pc) {
+    Consts<R> k;
+    k.dt = (R)pc.dt;
+    k.h = (R)(0.5 * pc.dt);
+    k.c = (R)pc.c;
+    k.c2 = (R)pc.c2;
+    k.inv_c2 = (R)pc.inv_c2;
+    k.f_rho = (R)pc.f_rho;
+    k.f_E = (R)pc.f_E;
+    k.inv_dl = (R)pc.inv_dl;
+    k.inv_dx = (R)pc.inv_dx;
+    k.inv_dy = (R)pc.inv_dy;
+    return k;
+}
+
+// Register copy of one particle's state: positions binary64, u in R.
+template <typename R>
+struct Regs {
+    double x, y, xp, yp;
+    R ux, uy, uz;
+    double qm;
+};
+
+// ---------------------------------------------------------------------------
+// Gather (Sec. 4, opening paragraph): linear shape function on the 2x2 nodes
+// of each component's own lattice; gradients by differentiating it.
+
+template <typename R>
+struct Sample {
+    R E[3], B[3];
+    R dBx[3], dBy[3];   // d B_i / dx, d B_i / dy
+};
+
+// One component at grid coordinates (gx, gy) = (X/dx, Y/dy) with lattice
+// offset (sx, sy) in cells (runtime stagger table).
+template <typename R, bool kGrad, class Acc>
+__device__ __forceinline__ void interp_comp(const Acc& acc, int k, double gx, double gy,
+                                            double sx, double sy, const Consts<R>& K, R& val,
+                                            R& ddx, R& ddy) {
+    const double xi = gx - sx;
+    const double eta = gy - sy;
+    const double fi = floor(xi);
+    const double fj = floor(eta);
+    const R wx = (R)(xi - fi);
+    const R wy = (R)(eta - fj);
+    double f00d, f10d, f01d, f11d;
+    acc.quad(k, (int)fi, (int)fj, f00d, f10d, f01d, f11d);
+    const R f00 = (R)f00d, f10 = (R)f10d, f01 = (R)f01d, f11 = (R)f11d;
+    const R ax = (R)1 - wx;
+    const R ay = (R)1 - wy;
+    val = (((ax * ay) * f00 + (wx * ay) * f10) + (ax * wy) * f01) + (wx * wy) * f11;
+    if (kGrad) {
+        ddx = (ay * (f10 - f00) + wy * (f11 - f01)) * K.inv_dx;
+        ddy = (ax * (f01 - f00) + wx * (f11 - f10)) * K.inv_dy;
+    }
+}
+
+// The six components from four located 2x2 stencils (2D Yee lattice): the
+// same operations as interp_comp, with the floor/weight computations shared
+// by the components of one weight set.
+template <typename R, bool kGrad, class Loader>
+__device__ __forceinline__ void interp_yee(const Loader& ld, const R wx[2], const R wy[2],
+                                           const Consts<R>& K, Sample<R>& s) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int set = kYeeSet[k];
+        const R bx = wx[set & 1];
+        const R by = wy[set >> 1];
+        const R ax = (R)1 - bx;
+        const R ay = (R)1 - by;
+        R f00, f10, f01, f11;
+        ld.template load4<R>(set, k, f00, f10, f01, f11);
+        const R val = (((ax * ay) * f00 + (bx * ay) * f10) + (ax * by) * f01) + (bx * by) * f11;
+        if (k < 3) {
+            s.E[k] = val;
+        } else {
+            s.B[k - 3] = val;
+            if (kGrad) {
+                s.dBx[k - 3] = (ay * (f10 - f00) + by * (f11 - f01)) * K.inv_dx;
+                s.dBy[k - 3] = (ax * (f01 - f00) + bx * (f11 - f10)) * K.inv_dy;
+            }
+        }
+    }
+}
+
+template <typename R, bool kGrad, typename T>
+__device__ __forceinline__ void yee_fetch(const GlobalAcc<T>& acc, int ia, int ib, int ja,
+                                          int jb, const R wx[2], const R wy[2],
+                                          const Consts<R>& K, Sample<R>& s) {
+    typename GlobalAcc<T>::Loc g;
+    acc.locate(ia, ib, ja, jb, g);
+    interp_yee<R, kGrad>(GlobalLoad<T>{g}, wx, wy, K, s);
+}
+
+template <typename R, bool kGrad, typename T>
+__device__ __forceinline__ void yee_fetch(const TileAcc<T>& acc, int ia, int ib, int ja,
+                                          int jb, const R wx[2], const R wy[2],
+                                          const Consts<R>& K, Sample<R>& s) {
+    int off[4];
+    typename GlobalAcc<T>::Loc g;
+    if (acc.locate(ia, ib, ja, jb, off, g))
+        interp_yee<R, kGrad>(LdsLoad<T>{acc.lds, off, acc.W * 6}, wx, wy, K, s);
+    else
+        interp_yee<R, kGrad>(GlobalLoad<T>{g}, wx, wy, K, s);
+}
+
+// All six components at (X, Y); B gradients when kGrad.  kYee: the 2D Yee
+// offsets (the values of the runtime table when it holds them).  Lattice
+// coordinates and weights are formed in binary64 from the binary64 position.
+template <typename R, bool kGrad, bool kYee, class Acc>
+__device__ __forceinline__ void gather(const Acc& acc, const PushConst& pc,
+                                       const Consts<R>& K, double X, double Y, Sample<R>& s) {
+    const double gx = X * pc.inv_dx;
+    const double gy = Y * pc.inv_dy;
+    if constexpr (kYee) {
+        // lattice coordinate minus the offset: offset 0 leaves it unchanged
+        const double xb = gx - 0.5;
+        const double yb = gy - 0.5;
+        const double fxa = floor(gx), fxb = floor(xb);
+        const double fya = floor(gy), fyb = floor(yb);
+        const R wx[2] = {(R)(gx - fxa), (R)(xb - fxb)};
+        const R wy[2] = {(R)(gy - fya), (R)(yb - fyb)};
+        yee_fetch<R, kGrad>(acc, (int)fxa, (int)fxb, (int)fya, (int)fyb, wx, wy, K, s);
+    } else {
+        R d0, d1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            interp_comp<R, false>(acc, k, gx, gy, pc.stagger[k][0], pc.stagger[k][1], K,
+                                  s.E[k], d0, d1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            interp_comp<R, kGrad>(acc, k + 3, gx, gy, pc.stagger[k + 3][0],
+                                  pc.stagger[k + 3][1], K, s.B[k], s.dBx[k], s.dBy[k]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Local guiding-center quantities (Sec. 2.2): b, v_E = c E x B / B^2,
+// kappa = (1 - v_E^2/c^2)^(-1/2), E_par, d_j b_i by the chain rule,
+// (b.grad)b, (v_E.grad)b, A = v_E.(b.grad)b, C = v_E.(v_E.grad)b.
+
+template <typename R>
+struct Local {
+    R B, inv_B;
+    R b[3], vE[3];
+    R kappa, Epar;
+    R bgb[3], vgb[3];
+    R A, C;
+};
+
+template <typename R>
+__device__ __forceinline__ uint32_t local_from_sample(const Sample<R>& s, const Consts<R>& K,
+                                                      Local<R>& L) {
+    uint32_t flags = 0;
+    const R Ex = s.E[0], Ey = s.E[1], Ez = s.E[2];
+    const R Bx = s.B[0], By = s.B[1], Bz = s.B[2];
+    const R B2 = (Bx * Bx + By * By) + Bz * Bz;
+    const R B = sqrt(B2);
+    const bool bzero = (B == (R)0);
+    const R inv_B = bzero ? (R)0 : (R)1 / B;
+    if (bzero) flags |= ST_BZERO;
+    L.B = B;
+    L.inv_B = inv_B;
+    const R bx = Bx * inv_B, by = By * inv_B, bz = Bz * inv_B;
+    L.b[0] = bx; L.b[1] = by; L.b[2] = bz;
+    const R sc = K.c * (inv_B * inv_B);
+    const R vEx = sc * (Ey * Bz - Ez * By);
+    const R vEy = sc * (Ez * Bx - Ex * Bz);
+    const R vEz = sc * (Ex * By - Ey * Bx);
+    L.vE[0] = vEx; L.vE[1] = vEy; L.vE[2] = vEz;
+    const R vE2 = (vEx * vEx + vEy * vEy) + vEz * vEz;
+    if constexpr (kMixed<R>) {
+        double om;
+        if (vE2 * K.inv_c2 > 0.81f && !bzero) {
+            // E/B > 0.9: 1 - v_E^2/c^2 = ((B^2 - E^2) B^2 + (E.B)^2) / B^4 in binary64
+            const double ex = Ex, ey = Ey, ez = Ez, qx = Bx, qy = By, qz = Bz;
+            const double b2 = (qx * qx + qy * qy) + qz * qz;
+            const double e2 = (ex * ex + ey * ey) + ez * ez;
+            const double eb = (ex * qx + ey * qy) + ez * qz;
+            om = ((b2 - e2) * b2 + eb * eb) / (b2 * b2);
+        } else {
+            om = (double)((R)1 - vE2 * K.inv_c2);
+        }
+        if (om < kKappaFloor) {
+            om = kKappaFloor;
+            flags |= ST_KAPPA;
+        }
+        L.kappa = (R)(1.0 / sqrt(om));
+    } else {
+        R om = (R)1 - vE2 * K.inv_c2;
+        if (om < (R)kKappaFloor) {
+            om = (R)kKappaFloor;
+            flags |= ST_KAPPA;
+        }
+        L.kappa = (R)1 / sqrt(om);
+    }
+    L.Epar = (Ex * bx + Ey * by) + Ez * bz;
+    // d_j b_i = (d_j B_i - b_i (b . d_j B)) / B
+    const R dnx = (bx * s.dBx[0] + by * s.dBx[1]) + bz * s.dBx[2];
+    const R dny = (bx * s.dBy[0] + by * s.dBy[1]) + bz * s.dBy[2];
+    R dbx[3], dby[3];
+    dbx[0] = (s.dBx[0] - bx * dnx) * inv_B;
+    dbx[1] = (s.dBx[1] - by * dnx) * inv_B;
+    dbx[2] = (s.dBx[2] - bz * dnx) * inv_B;
+    dby[0] = (s.dBy[0] - bx * dny) * inv_B;
+    dby[1] = (s.dBy[1] - by * dny) * inv_B;
+    dby[2] = (s.dBy[2] - bz * dny) * inv_B;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        L.bgb[i] = bx * dbx[i] + by * dby[i];
+        L.vgb[i] = vEx * dbx[i] + vEy * dby[i];
+    }
+    L.A = (vEx * L.bgb[0] + vEy * L.bgb[1]) + vEz * L.bgb[2];
+    L.C = (vEx * L.vgb[0] + vEy * L.vgb[1]) + vEz * L.vgb[2];
+    return flags;
+}
+
+// Gamma(R, u_par) = kappa sqrt(1 + (u_par^2 + 2 mu B kappa/m)/c^2)  (eq. lfacgca2)
+template <typename R>
+__device__ __forceinline__ R gamma_gca(const Local<R>& L, R upar, R mu, const Consts<R>& K) {
+    const R uperp2 = (((R)2 * mu) * L.B) * L.kappa;
+    const R arg = (R)1 + (upar * upar + uperp2) * K.inv_c2;
+    if constexpr (kMixed<R>) {
+        if (arg > 1.0e6f) {   // ultra-relativistic: binary64
+            const double a = 1.0 + ((double)upar * (double)upar + (double)uperp2) *
+                                       (1.0 / ((double)K.c * (double)K.c));
+            return (R)((double)L.kappa * sqrt(a));
+        }
+    }
+    return L.kappa * sqrt(arg);
+}
+
+// Curvature drift (eq. curvdrift):
+// (m c kappa^2 / (q B)) b x [ (u_par^2/Gamma)(b.grad)b + u_par (v_E.grad)b ]
+template <typename R>
+__device__ __forceinline__ void v_curv(const Local<R>& L, R upar, R gam, R inv_qm,
+                                       const Consts<R>& K, R vc[3]) {
+    const R pre = ((K.c * L.kappa) * L.kappa) * (L.inv_B * inv_qm);
+    const R a1 = (upar * upar) / gam;
+    const R w0 = a1 * L.bgb[0] + upar * L.vgb[0];
+    const R w1 = a1 * L.bgb[1] + upar * L.vgb[1];
+    const R w2 = a1 * L.bgb[2] + upar * L.vgb[2];
+    vc[0] = pre * (L.b[1] * w2 - L.b[2] * w1);
+    vc[1] = pre * (L.b[2] * w0 - L.b[0] * w2);
+    vc[2] = pre * (L.b[0] * w1 - L.b[1] * w0);
+}
+
+// Lorentz factor of the full four-velocity
+template <typename R>
+__device__ __forceinline__ R gamma_full(R ux, R uy, R uz, const Consts<R>& K) {
+    const R arg = (R)1 + ((ux * ux + uy * uy) + uz * uz) * K.inv_c2;
+    if constexpr (kMixed<R>) {
+        if (arg > 1.0e6f) {
+            const double a = 1.0 + (((double)ux * ux + (double)uy * uy) + (double)uz * uz) *
+                                       (1.0 / ((double)K.c * (double)K.c));
+            return (R)sqrt(a);
+        }
+    }
+    return sqrt(arg);
+}
+
+// ---------------------------------------------------------------------------
+// Switch (Sec. 3 criteria, Sec. 4.1): guiding center iff B > 0,
+// rho~/dl < f_rho and E/B < f_E, with rho~ = c^2 Gamma / (|q/m| B).
+
+__device__ __forceinline__ bool switch_gca_f64(const double E[3], const double Bv[3],
+                                               double ux, double uy, double uz, double qm,
+                                               const PushConst& pc) {
+    const double B = sqrt((Bv[0] * Bv[0] + Bv[1] * Bv[1]) + Bv[2] * Bv[2]);
+    const double E_ = sqrt((E[0] * E[0] + E[1] * E[1]) + E[2] * E[2]);
+    const bool pos = B > 0.0;
+    const double inv_B = pos ? 1.0 / B : 0.0;
+    const double gf = sqrt(1.0 + ((ux * ux + uy * uy) + uz * uz) * pc.inv_c2);
+    const double inv_absqm = fabs(1.0 / qm);
+    const double rho = ((pc.c2 * gf) * inv_B) * inv_absqm;
+    return pos && (rho * pc.inv_dl < pc.f_rho) && (E_ * inv_B < pc.f_E);
+}
+
+template <typename R>
+__device__ __forceinline__ bool switch_gca(const R E[3], const R Bv[3], R ux, R uy, R uz,
+                                           double qm, const PushConst& pc,
+                                           const Consts<R>& K) {
+    if constexpr (!kMixed<R>) {
+        return switch_gca_f64(E, Bv, ux, uy, uz, qm, pc);
+    } else {
+        const R B = sqrt((Bv[0] * Bv[0] + Bv[1] * Bv[1]) + Bv[2] * Bv[2]);
+        const R E_ = sqrt((E[0] * E[0] + E[1] * E[1]) + E[2] * E[2]);
+        const bool pos = B > (R)0;
+        const R inv_B = pos ? (R)1 / B : (R)0;
+        const R gf = gamma_full(ux, uy, uz, K);
+        const R inv_absqm = fabs((R)1 / (R)qm);
+        const R rr = (((K.c2 * gf) * inv_B) * inv_absqm) * K.inv_dl;
+        const R er = E_ * inv_B;
+        // near a threshold the test is repeated in binary64
+        const bool near = fabs(rr - K.f_rho) <= 1.0e-4f * K.f_rho ||
+                          fabs(er - K.f_E) <= 1.0e-4f * K.f_E;
+        if (near) {
+            const double Ed[3] = {E[0], E[1], E[2]};
+            const double Bd[3] = {Bv[0], Bv[1], Bv[2]};
+            return switch_gca_f64(Ed, Bd, ux, uy, uz, qm, pc);
+        }
+        return pos && (rr < K.f_rho) && (er < K.f_E);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Periodic box (binary64)
+
+__device__ __forceinline__ double wrap(double x, double L) {
+    double w = x - L * floor(x / L);
+    if (w < 0.0) w = w + L;
+    if (w >= L) w = w - L;
+    return w;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) {
+    return d - L * floor(d / L + 0.5);
+}
+
+// ---------------------------------------------------------------------------
+// Relativistic Boris push (Sec. 2.1), fields at x^n
+
+template <typename R>
+__device__ __forceinline__ void boris(const R E[3], const R Bv[3], R& ux, R& uy, R& uz,
+                                      R qm, const Consts<R>& K) {
+    const R hq = (qm * K.dt) * (R)0.5;
+    const R umx = ux + hq * E[0], umy = uy + hq * E[1], umz = uz + hq * E[2];
+    const R gm = gamma_full(umx, umy, umz, K);
+    const R f = hq / (K.c * gm);
+    const R tx = f * Bv[0], ty = f * Bv[1], tz = f * Bv[2];
+    const R t2 = (tx * tx + ty * ty) + tz * tz;
+    const R g = (R)2 / ((R)1 + t2);
+    const R sx = g * tx, sy = g * ty, sz = g * tz;
+    const R upx = umx + (umy * tz - umz * ty);
+    const R upy = umy + (umz * tx - umx * tz);
+    const R upz = umz + (umx * ty - umy * tx);
+    const R uqx = umx + (upy * sz - upz * sy);
+    const R uqy = umy + (upz * sx - upx * sz);
+    const R uqz = umz + (upx * sy - upy * sx);
+    ux = uqx + hq * E[0];
+    uy = uqy + hq * E[1];
+    uz = uqz + hq * E[2];
+}
+
+// Full-orbit step: u^{n-1/2} -> u^{n+1/2}, x^{n+1} = x^n + dt u/Gamma.
+template <typename R>
+__device__ __forceinline__ void boris_step(const Sample<R>& s, Regs<R>& r, const PushConst& pc,
+                                           const Consts<R>& K) {
+    boris(s.E, s.B, r.ux, r.uy, r.uz, (R)r.qm, K);
+    const R gn = gamma_full(r.ux, r.uy, r.uz, K);
+    const R inv_g = (R)1 / gn;
+    const double xn = r.x + pc.dt * (double)(r.ux * inv_g);
+    const double yn = r.y + pc.dt * (double)(r.uy * inv_g);
+    r.xp = r.x;
+    r.yp = r.y;
+    r.x = wrap(xn, pc.Lx);
+    r.y = wrap(yn, pc.Ly);
+}
+
+// ---------------------------------------------------------------------------
+// Guiding-center leapfrog (Sec. 2.2.1 / 2.2.2) inside the coupled step (Sec. 3.1)
+
+// u_par^{n-1/2} -> u_par^{n+1/2} at R^n.  With curvature: the positive root
+// of k1 G^2 + k2 G + k3 = 0 for G = Gamma(R^n, u_par^{n+1/2}), evaluated
+// without cancellation, then eq. dupardtcase2discsol.
+template <typename R>
+__device__ __forceinline__ R parallel_update(const Local<R>& Ln, R upar, R mu, R qm,
+                                             bool curvature, const Consts<R>& K,
+                                             uint32_t& flags) {
+    const R dtqm = qm * K.dt;
+    if (!curvature) return upar + dtqm * Ln.Epar;
+    const R h = K.h;
+    const R A = Ln.A, C = Ln.C;
+    const R G0 = gamma_gca(Ln, upar, mu, K);
+    const R upr = (upar * ((R)1 + h * A) + dtqm * Ln.Epar) + (h * G0) * C;
+    const R D = (R)1 - h * A;
+    const R DD = D * D;
+    const R k1 = (h * h) * (C * C) - (K.c2 * DD) / (Ln.kappa * Ln.kappa);
+    const R k2 = (upr * K.dt) * C;
+    const R k3 = upr * upr + (K.c2 + (((R)2 * mu) * Ln.B) * Ln.kappa) * DD;
+    const R disc = k2 * k2 - ((R)4 * k1) * k3;
+    const bool dok = fabs(D) >= (R)kDFloor;
+    bool ok = (k1 < (R)0) && (disc >= (R)0) && dok;
+    const R sq = sqrt(disc >= (R)0 ? disc : (R)0);
+    const bool pos_k2 = k2 >= (R)0;
+    const R num = pos_k2 ? k2 + sq : (R)2 * k3;
+    R den = pos_k2 ? (R)(-2) * k1 : sq - k2;
+    den = (ok && den > (R)0) ? den : (R)1;
+    const R gp = num / den;
+    ok = ok && (gp > (R)0) && isfinite(gp);
+    const R Ds = dok ? D : (R)1;
+    if (ok) return (upr + (h * gp) * C) / Ds;
+    flags |= ST_QUAD;
+    if (dok) {
+        const R gfb = gamma_gca(Ln, upr / Ds, mu, K);
+        return (upr + (h * gfb) * C) / Ds;
+    }
+    return upar + dtqm * Ln.Epar;
+}
+
+// x, y components of u_par b / Gamma + v_E + v_c at a point.
+template <typename R>
+__device__ __forceinline__ void drift_terms(const Local<R>& L, R upn, R mu, R inv_qm,
+                                            bool curvature, const Consts<R>& K, R& Fx,
+                                            R& Fy) {
+    const R g = gamma_gca(L, upn, mu, K);
+    const R a = upn / g;
+    if (curvature) {
+        R vc[3];
+        v_curv(L, upn, g, inv_qm, K, vc);
+        Fx = (a * L.b[0] + L.vE[0]) + vc[0];
+        Fy = (a * L.b[1] + L.vE[1]) + vc[1];
+    } else {
+        Fx = a * L.b[0] + L.vE[0];
+        Fy = a * L.b[1] + L.vE[1];
+    }
+}
+
+__device__ __forceinline__ double nan_max(double a, double b) {
+    if (a != a) return a;
+    if (b != b) return b;
+    return a > b ? a : b;
+}
+
+// One guiding-center step.  sn is the gather (with gradients) at x^n.
+// Returns status flags; res receives |R^K - R^{K-1}|_inf.
+template <typename R, bool kYee, class Acc>
+__device__ __forceinline__ uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
+                                             const PushConst& pc, const Consts<R>& K,
+                                             double& res) {
+    uint32_t flags = 0;
+    const bool curv = pc.curvature != 0;
+    const double x = r.x, y = r.y;
+    const R ux = r.ux, uy = r.uy, uz = r.uz;
+    const R qm = (R)r.qm;
+    const R inv_qm = (R)1 / qm;
+
+    // 1. guiding-center variables at R^{n-1/2} = (x^n + x^{n-1})/2
+    R upar, mu, bpx, bpy, bpz;
+    {
+        const double Rhx = x - 0.5 * min_image(x - r.xp, pc.Lx);
+        const double Rhy = y - 0.5 * min_image(y - r.yp, pc.Ly);
+        Sample<R> sh;
+        gather<R, true, kYee>(acc, pc, K, Rhx, Rhy, sh);
+        Local<R> Lh;
+        flags |= local_from_sample(sh, K, Lh);
+        upar = (ux * Lh.b[0] + uy * Lh.b[1]) + uz * Lh.b[2];
+        const R gf = gamma_full(ux, uy, uz, K);
+        R vc[3] = {(R)0, (R)0, (R)0};
+        if (curv) v_curv(Lh, upar, gf, inv_qm, K, vc);
+        const R upx = (ux - upar * Lh.b[0]) - (Lh.vE[0] + vc[0]) * gf;
+        const R upy = (uy - upar * Lh.b[1]) - (Lh.vE[1] + vc[1]) * gf;
+        const R upz = (uz - upar * Lh.b[2]) - (Lh.vE[2] + vc[2]) * gf;
+        const R up2 = (upx * upx + upy * upy) + upz * upz;
+        mu = (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        const R nu = sqrt(up2);
+        const R inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
+        bpx = upx * inv_nu;
+        bpy = upy * inv_nu;
+        bpz = upz * inv_nu;
+    }
+
+    // 2.-3. local quantities at R^n = x^n and the parallel update
+    R upn, Fnx, Fny;
+    {
+        Local<R> Ln;
+        flags |= local_from_sample(sn, K, Ln);
+        upn = parallel_update(Ln, upar, mu, qm, curv, K, flags);
+        drift_terms(Ln, upn, mu, inv_qm, curv, K, Fnx, Fny);
+    }
+
+    // 4. R^{n+1}: K fixed-point iterations R^{k+1} = R^k - H(R^k), R^0 = R^n
+    //    (positions binary64, drift velocities in R)
+    double Rx = x, Ry = y;
+    res = 0.0;
+    for (int k = 0; k < pc.n_iter; ++k) {
+        R Fkx, Fky;
+        if (k == 0) {
+            Fkx = Fnx;
+            Fky = Fny;
+        } else {
+            Sample<R> sk;
+            gather<R, true, kYee>(acc, pc, K, Rx, Ry, sk);
+            Local<R> Lk;
+            flags |= local_from_sample(sk, K, Lk);
+            drift_terms(Lk, upn, mu, inv_qm, curv, K, Fkx, Fky);
+        }
+        const double Rx_new = x + (double)(K.h * (Fnx + Fkx));
+        const double Ry_new = y + (double)(K.h * (Fny + Fky));
+        res = nan_max(fabs(Rx_new - Rx), fabs(Ry_new - Ry));
+        Rx = Rx_new;
+        Ry = Ry_new;
+    }
+    if (res > pc.fp_tol) flags |= ST_FPRES;
+
+    // 5. particle variables at R^{n+1/2} = (R^n + R^{n+1})/2, gyration
+    //    direction held fixed
+    {
+        const double Rmx = x + 0.5 * (Rx - x);
+        const double Rmy = y + 0.5 * (Ry - y);
+        Sample<R> sm;
+        gather<R, true, kYee>(acc, pc, K, Rmx, Rmy, sm);
+        Local<R> Lm;
+        flags |= local_from_sample(sm, K, Lm);
+        const R gr = gamma_gca(Lm, upn, mu, K);
+        R vc[3] = {(R)0, (R)0, (R)0};
+        if (curv) v_curv(Lm, upn, gr, inv_qm, K, vc);
+        const R um = sqrt((((R)2 * mu) * Lm.B) * Lm.kappa);
+        r.ux = (upn * Lm.b[0] + (Lm.vE[0] + vc[0]) * gr) + um * bpx;
+        r.uy = (upn * Lm.b[1] + (Lm.vE[1] + vc[1]) * gr) + um * bpy;
+        r.uz = (upn * Lm.b[2] + (Lm.vE[2] + vc[2]) * gr) + um * bpz;
+    }
+
+    // 6. store
+    r.xp = x;
+    r.yp = y;
+    r.x = wrap(Rx, pc.Lx);
+    r.y = wrap(Ry, pc.Ly);
+    return flags;
+}
+
+template <typename R>
+__device__ __forceinline__ uint32_t finite_flag(const Regs<R>& r) {
+    const bool ok = isfinite(r.x) && isfinite(r.y) && isfinite(r.ux) && isfinite(r.uy) &&
+                    isfinite(r.uz);
+    return ok ? 0u : (uint32_t)ST_NONFINITE;
+}
+
+}  // namespace gcb

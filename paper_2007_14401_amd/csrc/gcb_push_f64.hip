@@ -1,247 +1,13 @@
-// Push kernels of the binary64 form.
-//
-// k_push_global: one lane per particle, any particle order, gathers through
-//   the cache hierarchy from the node-interleaved field array.
-// k_push_tiled: one workgroup per tile of cell-sorted particles.  The tile's
-//   field window (tile + halo, all six components) is staged once in LDS;
-//   then, per pass of up to kQueueMax particles, every lane evaluates the
-//   switch for its particle and the workgroup builds two queues in LDS
-//   (guiding-center first, Boris from the back), so that each wavefront of the
-//   update pass runs a single branch of the coupled step.
-//
-// Compiled with -ffp-contract=off: see gcb_math_f64.hpp.
-#include <hip/hip_runtime.h>
-
-#include "gcb_access.hpp"
-#include "gcb_internal.h"
-#include "gcb_math_f64.hpp"
-
-namespace gcb {
-namespace {
-
-constexpr int kWG = 256;
+// Push kernels of the binary64 form (compiled with -ffp-contract=off, so the
+// arithmetic is evaluated exactly as written in gcb_math.hpp).
+#include "gcb_push_kernels.hpp"
 
 // Minimum waves per SIMD the tiled kernel is compiled for (register budget).
 #ifndef GCB_TILED_MIN_WAVES
 #define GCB_TILED_MIN_WAVES 3
 #endif
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-__device__ __forceinline__ void flush_stats(DevStats* st, unsigned gca, unsigned boris,
-                                            unsigned halo, double maxres) {
-    // wave-level reduction, one atomic per wave and counter
-    unsigned long long g = gca, b = boris, h = halo;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        g += __shfl_xor(g, off, 64);
-        b += __shfl_xor(b, off, 64);
-        h += __shfl_xor(h, off, 64);
-    }
-    const double m = wave_max(maxres);
-    if ((threadIdx.x & 63) == 0) {
-        if (g) atomicAdd(&st->gca_steps, g);
-        if (b) atomicAdd(&st->boris_steps, b);
-        if (h) atomicAdd(&st->halo_misses, h);
-        if (m > 0.0) atomicMax(&st->max_res_bits, (unsigned long long)__double_as_longlong(m));
-    }
-}
-
-__device__ __forceinline__ void load_particle(const ParticlePtrs<double>& in, int64_t p,
-                                              double qm_default, ParticleRegs& r) {
-    r.x = in.x[p];
-    r.y = in.y[p];
-    r.xp = in.xp[p];
-    r.yp = in.yp[p];
-    r.ux = in.ux[p];
-    r.uy = in.uy[p];
-    r.uz = in.uz[p];
-    r.qm = in.qm ? in.qm[p] : qm_default;
-}
-
-__device__ __forceinline__ void store_particle(const ParticlePtrs<double>& in,
-                                               const ParticlePtrs<double>& out, int64_t p,
-                                               const ParticleRegs& r, uint32_t flags) {
-    out.x[p] = r.x;
-    out.y[p] = r.y;
-    out.xp[p] = r.xp;
-    out.yp[p] = r.yp;
-    out.ux[p] = r.ux;
-    out.uy[p] = r.uy;
-    out.uz[p] = r.uz;
-    out.status[p] = (uint8_t)(in.status[p] | flags);
-    if (out.x != in.x) {   // out-of-place step after a sort: carry the rest along
-        if (in.qm) out.qm[p] = r.qm;
-        if (in.id) out.id[p] = in.id[p];
-    }
-}
-
-// one coupled step for a particle already in registers; sample at x^n given
-template <bool kYee, class Acc>
-__device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, ParticleRegs& r,
-                                                   const PushConst& pc, double& res) {
-    uint32_t fl = 0;
-    res = 0.0;
-    if (gca) {
-        Sample s;
-        gather<true, kYee>(acc, pc, r.x, r.y, s);
-        fl = gca_step<kYee>(acc, s, r, pc, res);
-    } else {
-        Sample s;
-        gather<false, kYee>(acc, pc, r.x, r.y, s);
-        boris_step(s, r, pc);
-    }
-    return fl | finite_flag(r);
-}
-
-template <bool kYee>
-__global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<double> in,
-                                                      ParticlePtrs<double> out, int64_t n,
-                                                      const double* __restrict__ F,
-                                                      PushConst pc, uint8_t* trace,
-                                                      DevStats* stats) {
-    const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    const bool active = p < n;
-    bool gca = false;
-    double res = 0.0;
-    if (active) {
-        GlobalAcc<double> acc{F, pc.nx, pc.ny};
-        ParticleRegs r;
-        load_particle(in, p, pc.qm, r);
-        Sample s;
-        gather<false, kYee>(acc, pc, r.x, r.y, s);
-        gca = switch_gca(s.E, s.B, r.ux, r.uy, r.uz, r.qm, pc);
-        const uint32_t fl = coupled_update<kYee>(acc, gca, r, pc, res);
-        store_particle(in, out, p, r, fl);
-        if (trace) trace[in.id ? (int64_t)in.id[p] : p] = gca ? 0 : 1;
-    }
-    if (stats) flush_stats(stats, active && gca, active && !gca, 0, res);
-}
-
-template <bool kYee>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(GCB_TILED_MIN_WAVES))) void k_push_tiled(ParticlePtrs<double> in,
-                                                     ParticlePtrs<double> out,
-                                                     const int32_t* __restrict__ tile_start,
-                                                     TileGeom g, int chunk,
-                                                     const double* __restrict__ F,
-                                                     PushConst pc, uint8_t* trace,
-                                                     DevStats* stats) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int wave_g[kWG / 64];
-    __shared__ int wave_b[kWG / 64];
-
-    const int ntiles = g.ntx * g.nty;
-    // consecutive tiles on the same XCD: workgroups are dealt to the 8 XCDs
-    // round-robin, so workgroup b runs on XCD b % 8
-    const int tile = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
-    if (tile >= ntiles) return;
-    const int W = g.window;
-    double* lds = reinterpret_cast<double*>(smem);
-    uint16_t* queue = reinterpret_cast<uint16_t*>(smem + (size_t)W * W * 6 * sizeof(double));
-
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int tx = tile % g.ntx;
-    const int ty = tile / g.ntx;
-    const int oi = tx * g.tile - g.halo;
-    const int oj = ty * g.tile - g.halo;
-
-    // stage the window: one row (W records of 6 values) per wave iteration
-    for (int rr = wave; rr < W; rr += kWG / 64) {
-        const int gj = wrap_index(oj + rr, pc.ny);
-        const double* grow = F + (size_t)gj * pc.nx * 6;
-        double* lrow = lds + (size_t)rr * W * 6;
-        for (int e = lane; e < W * 6; e += 64) {
-            const int c = e / 6;
-            const int k = e - c * 6;
-            const int gi = wrap_index(oi + c, pc.nx);
-            lrow[e] = grow[gi * 6 + k];
-        }
-    }
-    __syncthreads();
-
-    TileAcc<double> acc{lds, F, pc.nx, pc.ny, oi, oj, W, false};
-    const int64_t p0 = tile_start[tile];
-    const int64_t p1 = tile_start[tile + 1];
-    unsigned cnt_g = 0, cnt_b = 0, cnt_h = 0;
-    double maxres = 0.0;
-    const unsigned long long lt = (1ull << lane) - 1ull;
-
-    for (int64_t base = p0; base < p1; base += kQueueMax) {
-        const int m = (int)((p1 - base) < kQueueMax ? (p1 - base) : kQueueMax);
-        // pass 1: switch decision, stable split into the two queues
-        int nG = 0, nB = 0;
-        for (int t0 = 0; t0 < m; t0 += kWG) {
-            const int t = t0 + (int)threadIdx.x;
-            const bool valid = t < m;
-            bool gca = false;
-            if (valid) {
-                const int64_t p = base + t;
-                const double x = in.x[p], y = in.y[p];
-                const double qm = in.qm ? in.qm[p] : pc.qm;
-                Sample s;
-                gather<false, kYee>(acc, pc, x, y, s);
-                gca = switch_gca(s.E, s.B, in.ux[p], in.uy[p], in.uz[p], qm, pc);
-            }
-            const unsigned long long bg = __ballot(valid && gca);
-            const unsigned long long bb = __ballot(valid && !gca);
-            if (lane == 0) {
-                wave_g[wave] = __popcll(bg);
-                wave_b[wave] = __popcll(bb);
-            }
-            __syncthreads();
-            int offg = nG, offb = nB, totg = 0, totb = 0;
-#pragma unroll
-            for (int w = 0; w < kWG / 64; ++w) {
-                if (w < wave) {
-                    offg += wave_g[w];
-                    offb += wave_b[w];
-                }
-                totg += wave_g[w];
-                totb += wave_b[w];
-            }
-            if (valid) {
-                if (gca)
-                    queue[offg + __popcll(bg & lt)] = (uint16_t)t;
-                else
-                    queue[m - 1 - (offb + __popcll(bb & lt))] = (uint16_t)t;
-            }
-            nG += totg;
-            nB += totb;
-            __syncthreads();
-        }
-        // pass 2: guiding-center queue, then Boris queue
-        for (int q = threadIdx.x; q < m; q += kWG) {
-            const int64_t p = base + queue[q];
-            const bool gca = q < nG;
-            ParticleRegs r;
-            load_particle(in, p, pc.qm, r);
-            acc.miss = false;
-            double res;
-            uint32_t fl = coupled_update<kYee>(acc, gca, r, pc, res);
-            if (acc.miss) {
-                fl |= ST_HALO;
-                ++cnt_h;
-            }
-            store_particle(in, out, p, r, fl);
-            if (trace) trace[in.id ? (int64_t)in.id[p] : p] = gca ? 0 : 1;
-            if (gca) {
-                ++cnt_g;
-                maxres = nan_max(maxres, res);
-            } else {
-                ++cnt_b;
-            }
-        }
-        __syncthreads();
-    }
-    if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
-}
-
-}  // namespace
+namespace gcb {
 
 size_t tiled_lds_bytes(int window, size_t elem_bytes) {
     size_t f = (size_t)window * window * 6 * elem_bytes;
@@ -252,33 +18,7 @@ size_t tiled_lds_bytes(int window, size_t elem_bytes) {
 hipError_t launch_push_f64(const PushLaunch& L, const ParticlePtrs<double>& in,
                            const ParticlePtrs<double>& out, const PushConst& pc,
                            hipStream_t stream) {
-    if (L.n == 0) return hipSuccess;
-    const double* F = static_cast<const double*>(L.fields);
-    if (L.kind == PushKind::Global) {
-        const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
-        if (L.yee)
-            hipLaunchKernelGGL(k_push_global<true>, dim3(blocks), dim3(kWG), 0, stream, in,
-                               out, L.n, F, pc, L.trace, L.stats);
-        else
-            hipLaunchKernelGGL(k_push_global<false>, dim3(blocks), dim3(kWG), 0, stream, in,
-                               out, L.n, F, pc, L.trace, L.stats);
-        return hipGetLastError();
-    }
-    const int ntiles = L.geom.ntx * L.geom.nty;
-    const int chunk = (ntiles + 7) / 8;
-    const size_t lds = tiled_lds_bytes(L.geom.window, sizeof(double));
-    if (L.yee) {
-        hipFuncSetAttribute((const void*)k_push_tiled<true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_push_tiled<true>, dim3(8 * chunk), dim3(kWG), lds, stream, in,
-                           out, L.tile_start, L.geom, chunk, F, pc, L.trace, L.stats);
-    } else {
-        hipFuncSetAttribute((const void*)k_push_tiled<false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_push_tiled<false>, dim3(8 * chunk), dim3(kWG), lds, stream, in,
-                           out, L.tile_start, L.geom, chunk, F, pc, L.trace, L.stats);
-    }
-    return hipGetLastError();
+    return kern::launch_push<double, double, GCB_TILED_MIN_WAVES>(L, in, out, pc, stream);
 }
 
 }  // namespace gcb

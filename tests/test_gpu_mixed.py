@@ -1,0 +1,135 @@
+"""Mixed-precision form (binary32 fields and bulk arithmetic, binary64
+positions and selected quantities) against the binary64 CPU oracle.
+
+Stated tolerance (one step, from the arithmetic): inputs are rounded to
+binary32 (relative 6e-8) and a guiding-center step chains about 30 dependent
+rounding stages plus the conditioning of kappa near E -> B, so per-step
+relative errors of u of order 1e-6 are expected; positions stay binary64 and
+move by at most about c dt per step, so their one-step error is below 1e-6
+cells.  Asserted: median relative u error <= 1e-5, 99th percentile <= 1e-3,
+max position error <= 1e-4 cells, switch mismatches <= 0.2 % of particles.
+
+Over many steps chaotic orbits amplify these differences; the multi-step
+report (full-size workload) is measured and recorded, with loose bounds.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import GpuRun, log, run_oracle
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _errors(got, ref, cfg, idx=None):
+    u_g = np.stack([np.asarray(got[k], dtype=np.float64) for k in ("ux", "uy", "uz")])
+    u_r = np.stack([getattr(ref, k).numpy() for k in ("ux", "uy", "uz")])
+    if idx is not None:
+        u_r = u_r[:, idx]
+    du = np.max(np.abs(u_g - u_r), axis=0) / np.maximum(np.max(np.abs(u_r), axis=0), cfg.c)
+    dx = []
+    for k, L in (("x", cfg.Lx), ("y", cfg.Ly)):
+        a = np.asarray(got[k])
+        b = getattr(ref, k).numpy() if idx is None else getattr(ref, k).numpy()[idx]
+        d = np.abs(a - b)
+        dx.append(np.minimum(d, L - d))
+    dx = np.max(np.stack(dx), axis=0)
+    return du, dx
+
+
+def _run_mixed(cfg, F, ens, steps, trace, **kw):
+    from paper_2007_14401_amd import gcb, state
+    run = GpuRun(cfg, F, dtype=gcb.GCB_F32)
+    try:
+        t = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED)
+        tr, st = run.push(t, steps, trace=trace, stats=True, form=gcb.GCB_FORM_MIXED, **kw)
+        return t, tr, st
+    finally:
+        run.close()
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(1, 0, 0), (2, 1, 16), (2, 4, 24)])
+def test_mixed_one_step(kernel, sort_every, tile):
+    from paper_2007_14401_amd import state
+    cfg = make_config("harris64")
+    F = cfg.fields()
+    ens = cfg.particles(n=8192)
+    t, tr, _ = _run_mixed(cfg, F, ens, 1, True, kernel=kernel, sort_every=sort_every, tile=tile)
+    got = state.unsort(t)
+    ref, rtr, _ = run_oracle(cfg, F, ens, 1, trace=True)
+    du, dx = _errors(got, ref, cfg)
+    mism = float((tr.cpu().numpy() != rtr.numpy()).mean())
+    log(f"mixed one step kernel={kernel}: u median {np.median(du):.2e} p99 "
+        f"{np.quantile(du, 0.99):.2e} max {du.max():.2e}; x max {dx.max():.2e}; "
+        f"S mismatch {mism:.2e}")
+    assert np.median(du) <= 1e-5
+    assert np.quantile(du, 0.99) <= 1e-3
+    assert dx.max() <= 1e-4
+    assert mism <= 2e-3
+
+
+def test_mixed_deterministic():
+    cfg = make_config("harris64")
+    F = cfg.fields()
+    ens = cfg.particles(n=5000)
+    outs = []
+    for _ in range(2):
+        t, _, _ = _run_mixed(cfg, F, ens, 10, False, kernel=2, sort_every=2, tile=16)
+        outs.append({k: v.cpu().numpy().copy() for k, v in t.items() if v is not None})
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k].view(np.uint8), outs[1][k].view(np.uint8)), k
+
+
+def _report(n_total, steps, sample_n=2000):
+    from paper_2007_14401_amd import state
+    cfg = make_config("harris4096")
+    log(f"mixed report: generating {n_total} particles")
+    F = cfg.fields()
+    ens = cfg.particles(n=n_total)
+    t, tr, st = _run_mixed(cfg, F, ens, steps, True, kernel=2, sort_every=4, tile=32)
+    ids = t["id"].cpu().numpy()
+    rng = np.random.default_rng(123)
+    sample = np.sort(rng.choice(ens.n, sample_n, replace=False))
+    pos = np.empty(ens.n, dtype=np.int64)
+    pos[ids] = np.arange(ens.n)
+    got = {k: (v.cpu().numpy()[pos[sample]] if v is not None else None) for k, v in t.items()}
+    trs = tr[:, torch.as_tensor(sample, device=tr.device)].cpu().numpy()
+    del t, tr
+    torch.cuda.empty_cache()
+    log("mixed report: oracle on the sample")
+    sub = ens.subset(sample)
+    del ens
+    ref, rtr, _ = run_oracle(cfg, F, sub, steps, trace=True)
+    du, dx = _errors(got, ref, cfg)
+    mism_steps = float((trs != rtr.numpy()).mean())
+    first = np.argmax(trs != rtr.numpy(), axis=0)
+    ever = (trs != rtr.numpy()).any(axis=0)
+    rep = {
+        "particles": n_total, "steps": steps, "sample": sample_n,
+        "u_rel_err": {"median": float(np.median(du)), "p99": float(np.quantile(du, 0.99)),
+                      "max": float(du.max())},
+        "x_abs_err_cells": {"median": float(np.median(dx)), "p99": float(np.quantile(dx, 0.99)),
+                            "max": float(dx.max())},
+        "switch_mismatch_fraction_particle_steps": mism_steps,
+        "particles_with_any_switch_mismatch": float(ever.mean()),
+        "u_rel_err_median_no_mismatch": float(np.median(du[~ever])) if (~ever).any() else None,
+        "gca_fraction": st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"]),
+    }
+    log("mixed report " + json.dumps(rep))
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", f"mixed_report_{n_total}.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    return rep
+
+
+def test_mixed_precision_report_1e7():
+    """Full-size workload (4096^2, 1e7 particles, 100 steps), mixed form."""
+    rep = _report(10_000_000, 100)
+    assert rep["u_rel_err"]["median"] <= 1e-3
+    assert rep["switch_mismatch_fraction_particle_steps"] <= 1e-2
