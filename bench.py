@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--f-E", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -157,6 +159,47 @@ def main():
             gcb.gcb_destroy(ctx)
             torch.cuda.empty_cache()
 
+    def time_fwd_adjoint(steps: int, checkpoint: int):
+        """Forward + reverse pass of the differentiable push (loss: mean final
+        kinetic energy; gradients to the E/B grids and the initial state)."""
+        from paper_2007_14401_amd import autograd as A
+        pctx = A.PushContext(0)
+        try:
+            Ft = torch.as_tensor(F, dtype=torch.float64, device=dev)
+            E = Ft[:3].contiguous().requires_grad_(True)
+            B = Ft[3:].contiguous().requires_grad_(True)
+            del Ft
+            names = ("x", "y", "xp", "yp", "ux", "uy", "uz")
+            st = {k: torch.as_tensor(getattr(ens, k), dtype=torch.float64, device=dev)
+                  .requires_grad_(True) for k in names}
+            prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                             curvature=cfg.curvature, n_iter=cfg.n_iter)
+            # warm-up: two steps forward and backward
+            out = A.push(E, B, *[st[k] for k in names], None, pctx, prm, 2, checkpoint)
+            A.kinetic_energy(out[4], out[5], out[6], pctx, prm).backward()
+            for v in list(st.values()) + [E, B]:
+                v.grad = None
+            gcb.gcb_set_timing(pctx.ctx, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = A.push(E, B, *[st[k] for k in names], None, pctx, prm, steps, checkpoint)
+            L = A.kinetic_energy(out[4], out[5], out[6], pctx, prm)
+            L.backward()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ms, cnt = gcb.gcb_get_timing(pctx.ctx)
+            gcb.gcb_set_timing(pctx.ctx, False)
+            log(f"[bench] fwd+adjoint: {steps} steps in {t1 - t0:.3f} s; kernel ms {ms}")
+            return {"value": n * steps / (t1 - t0), "unit": "particle-steps/s",
+                    "steps": steps, "checkpoint": checkpoint, "seconds": t1 - t0,
+                    "forward_push_ms_per_step": ms[gcb.GCB_TIMER_PUSH] / max(1, steps),
+                    "backward_ms_per_step": ms[gcb.GCB_TIMER_BACKWARD] / max(1, steps),
+                    "kernel": "k_push_global + k_adjoint_step (unsorted, binary64)",
+                    "loss": float(L)}
+        finally:
+            pctx.close()
+            torch.cuda.empty_cache()
+
     r64 = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup)
     wall, push_ms, sort_ms, gca_frac = r64["wall"], r64["push_ms"], r64["sort_ms"], r64["gca_frac"]
     bytes_step = push_bytes_per_step(n, cfg.nx, cfg.ny, 0)
@@ -177,6 +220,10 @@ def main():
             "algorithmic_bytes_per_launch": bm,
             "speedup_vs_f64": (n * a.steps / rm["wall"]) / value,
             "dtype": "f32 bulk, f64 positions"}
+
+    if not a.no_adjoint:
+        forms["fwd_adjoint"] = time_fwd_adjoint(a.adjoint_steps, 32)
+        forms["fwd_adjoint"]["speed_vs_f64_forward"] = forms["fwd_adjoint"]["value"] / value
 
     if a.copy_calib:
         x = torch.empty(1 << 27, dtype=torch.float64, device=dev)

@@ -131,6 +131,10 @@ typedef struct {
                             (0 = never; the tiled kernel needs > 0) */
     int32_t kernel;      /* GCB_KERNEL_* */
     int32_t tile;        /* tile edge in cells for the tiled kernel (0 = 24) */
+    int32_t replay;      /* 1: take every switch decision from s_trace (written by an
+                            earlier gcb_push over the same particles) instead of
+                            evaluating the switch; the push is then the map that
+                            gcb_push_backward differentiates, with S held fixed */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.
@@ -161,7 +165,8 @@ typedef struct {
    Boris (S = 1) or guiding-center leapfrog (S = 0), then store x^{n+1},
    x^n (as the previous position) and u^{n+1/2}.
    s_trace (nullable, device, n_steps*n bytes): s_trace[step*n + k] = S for
-   the particle with id k (or array slot k if id == NULL and sorting is off).
+   the particle with id k (or array slot k if id == NULL and sorting is off);
+   written, or read when params.replay is 1 (then it must be non-NULL).
    stats (nullable, host): filled after a device synchronisation. */
 int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm,
              int32_t n_steps, uint8_t* s_trace, gcb_stats* stats, void* stream);

@@ -1,0 +1,128 @@
+"""torch.autograd wrappers of the push and of the kinetic-energy loss.
+
+GcbPush runs n_steps binary64 pushes through libgcb in segments of
+`checkpoint` steps, keeping only each segment's start state; its backward
+walks the segments in reverse and calls gcb_push_backward on each, which
+recomputes the segment's forward steps and applies the hand-written adjoint
+with the switch decisions held at their forward values.  Gradients reach the
+E and B grids (accumulated in binary32 on the device, returned as float64)
+and the initial state (x, y, xp, yp, u).
+
+KineticEnergy is the mean (Gamma - 1) c^2 of a state, computed by the
+library's reduction kernel; its backward uses dL/du = u/(n Gamma).
+
+Argument marshalling and segment bookkeeping only: every step of the push and
+of its derivative runs in the library's kernels.  Sorting is not used here
+(the adjoint recomputes steps unsorted, with identical arithmetic).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import gcb
+
+_NAMES = ("x", "y", "xp", "yp", "ux", "uy", "uz")
+
+
+class PushContext:
+    """A libgcb context with binary64 fields taken from device tensors."""
+
+    def __init__(self, device: int = 0):
+        self.ctx = gcb.gcb_create(device)
+
+    def load(self, E: torch.Tensor, B: torch.Tensor, dx=1.0, dy=1.0,
+             stagger=gcb.YEE_STAGGER):
+        ny, nx = int(E.shape[1]), int(E.shape[2])
+        desc = gcb.grid_desc(nx, ny, dx, dy, stagger, gcb.GCB_F64)
+        Ec = [E[i].detach().contiguous() for i in range(3)]
+        Bc = [B[i].detach().contiguous() for i in range(3)]
+        gcb.gcb_load_fields(self.ctx, desc, Ec, Bc, src=gcb.GCB_DEVICE)
+        torch.cuda.current_stream().synchronize()
+        self.shape = (ny, nx)
+
+    def close(self):
+        if self.ctx is not None:
+            gcb.gcb_destroy(self.ctx)
+            self.ctx = None
+
+
+def _parts(st: dict, qm):
+    d = dict(st)
+    d["qm"] = qm
+    d["id"] = None
+    return gcb.particles(d)
+
+
+class GcbPush(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, E, B, x, y, xp, yp, ux, uy, uz, qm, pctx: PushContext, prm,
+                n_steps: int, checkpoint: int):
+        pctx.load(E, B)
+        n = x.shape[0]
+        st = {k: v.detach().clone() for k, v in zip(_NAMES, (x, y, xp, yp, ux, uy, uz))}
+        st["status"] = torch.zeros(n, dtype=torch.uint8, device=x.device)
+        qmd = qm.detach() if qm is not None else None
+        segs = []
+        done = 0
+        while done < n_steps:
+            k = min(checkpoint, n_steps - done)
+            segs.append(({kk: v.clone() for kk, v in st.items() if kk != "status"}, k))
+            gcb.gcb_push(pctx.ctx, _parts(st, qmd), prm, k)
+            done += k
+        ctx.pctx, ctx.prm, ctx.segs, ctx.qm = pctx, prm, segs, qmd
+        ctx.shape = tuple(E.shape)
+        return tuple(st[k] for k in _NAMES)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        pctx, prm = ctx.pctx, ctx.prm
+        ref = ctx.segs[0][0]["x"] if ctx.segs else None
+        dev = ref.device if ref is not None else torch.device("cuda")
+        n = ref.shape[0] if ref is not None else 0
+        lam = [g.contiguous() if g is not None else torch.zeros(n, dtype=torch.float64, device=dev)
+               for g in grads]
+        dE = torch.zeros(ctx.shape, dtype=torch.float32, device=dev)
+        dB = torch.zeros(ctx.shape, dtype=torch.float32, device=dev)
+        for start, k in reversed(ctx.segs):
+            st = dict(start)
+            st["status"] = torch.zeros(n, dtype=torch.uint8, device=dev)
+            out = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(7)]
+            gcb.gcb_push_backward(pctx.ctx, _parts(st, ctx.qm), prm, k, lam, out,
+                                  [dE[0], dE[1], dE[2]], [dB[0], dB[1], dB[2]])
+            lam = out
+        return (dE.double(), dB.double(), *lam, None, None, None, None, None)
+
+
+def push(E, B, x, y, xp, yp, ux, uy, uz, qm, pctx, prm, n_steps, checkpoint=32):
+    """Differentiable push; returns the final (x, y, xp, yp, ux, uy, uz).
+
+    The particles are not cell-sorted here (sort_every is forced to 0), so the
+    outputs stay in input order."""
+    prm = gcb.gcb_params.from_buffer_copy(prm)
+    prm.sort_every = 0
+    if prm.kernel == gcb.GCB_KERNEL_TILED:
+        prm.kernel = gcb.GCB_KERNEL_AUTO
+    return GcbPush.apply(E, B, x, y, xp, yp, ux, uy, uz, qm, pctx, prm, int(n_steps),
+                         int(checkpoint))
+
+
+class KineticEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, ux, uy, uz, pctx: PushContext, prm):
+        n = ux.shape[0]
+        st = {"x": ux, "y": ux, "xp": ux, "yp": ux, "ux": ux.detach(), "uy": uy.detach(),
+              "uz": uz.detach(), "status": torch.zeros(n, dtype=torch.uint8, device=ux.device)}
+        out = torch.zeros(1, dtype=torch.float64, device=ux.device)
+        lam = [torch.empty_like(ux) for _ in range(3)]
+        gcb.gcb_kinetic_energy(pctx.ctx, gcb.particles(st), prm, out, lam)
+        ctx.save_for_backward(*lam)
+        return out[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        lx, ly, lz = ctx.saved_tensors
+        return g * lx, g * ly, g * lz, None, None
+
+
+def kinetic_energy(ux, uy, uz, pctx, prm):
+    return KineticEnergy.apply(ux, uy, uz, pctx, prm)

@@ -17,6 +17,15 @@
 
 namespace gcb {
 
+// 24-bit integer multiply (small non-negative operands)
+GCB_HD int mul24(int a, int b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __mul24(a, b);
+#else
+    return a * b;
+#endif
+}
+
 // Loader of the LDS window: node (0,0) of each weight set at off[set].
 template <typename T>
 struct LdsLoad {
@@ -24,7 +33,7 @@ struct LdsLoad {
     const int* off;
     int W6;
     template <typename R>
-    __device__ __forceinline__ void load4(int set, int k, R& f00, R& f10, R& f01,
+    GCB_HD void load4(int set, int k, R& f00, R& f10, R& f01,
                                           R& f11) const {
         const T* p = lds + off[set] + k;
         f00 = (R)p[0];
@@ -37,7 +46,7 @@ struct LdsLoad {
 // Weight-set indices of the Yee lattice: bit 0 = x offset 1/2, bit 1 = y offset 1/2.
 // Ex (1/2,0) -> 1, Ey (0,1/2) -> 2, Ez (0,0) -> 0, Bx (0,1/2) -> 2, By (1/2,0) -> 1,
 // Bz (1/2,1/2) -> 3.
-__device__ constexpr int kYeeSet[6] = {1, 2, 0, 2, 1, 3};
+constexpr int kYeeSet[6] = {1, 2, 0, 2, 1, 3};
 
 // Device layout of the fields: node-interleaved, F[(j*nx + i)*6 + k], with k
 // the component (Ex, Ey, Ez, Bx, By, Bz) at that component's own node (i, j).
@@ -49,7 +58,7 @@ struct GlobalAcc {
     const T* __restrict__ F;
     int nx, ny;
 
-    __device__ __forceinline__ void quad(int k, int i, int j, double& f00, double& f10,
+    GCB_HD void quad(int k, int i, int j, double& f00, double& f10,
                                          double& f01, double& f11) const {
         const int i0 = wrap_index(i, nx);
         const int j0 = wrap_index(j, ny);
@@ -70,7 +79,7 @@ struct GlobalAcc {
         int col[2][2];        // [x set][column 0/1], in elements
     };
 
-    __device__ __forceinline__ void locate(int ia, int ib, int ja, int jb, Loc& L) const {
+    GCB_HD void locate(int ia, int ib, int ja, int jb, Loc& L) const {
         const int xi[2] = {ia, ib};
         const int yj[2] = {ja, jb};
 #pragma unroll
@@ -93,7 +102,7 @@ template <typename T>
 struct GlobalLoad {
     const typename GlobalAcc<T>::Loc& L;
     template <typename R>
-    __device__ __forceinline__ void load4(int set, int k, R& f00, R& f10, R& f01,
+    GCB_HD void load4(int set, int k, R& f00, R& f10, R& f01,
                                           R& f11) const {
         const int sx = set & 1, sy = set >> 1;
         f00 = (R)L.row[sy][0][L.col[sx][0] + k];
@@ -113,7 +122,7 @@ struct TileAcc {
     int nx, ny, oi, oj, W;
     mutable bool miss;
 
-    __device__ __forceinline__ void quad(int k, int i, int j, double& f00, double& f10,
+    GCB_HD void quad(int k, int i, int j, double& f00, double& f10,
                                          double& f01, double& f11) const {
         int di = i - oi;
         int dj = j - oj;
@@ -137,7 +146,7 @@ struct TileAcc {
     // `off` (LDS element offset of node (0,0) per weight set) when all four
     // stencils lie inside the window; otherwise fills the global fallback.
     // ib <= ia and jb <= ja (the 1/2-offset lattice's floor is never larger).
-    __device__ __forceinline__ bool locate(int ia, int ib, int ja, int jb, int off[4],
+    GCB_HD bool locate(int ia, int ib, int ja, int jb, int off[4],
                                            typename GlobalAcc<T>::Loc& g) const {
         int da = ia - oi;
         int ea = ja - oj;
@@ -150,10 +159,10 @@ struct TileAcc {
                         da <= W - 2 && ea <= W - 2;
         if (in) {
             const int W6 = W * 6;
-            off[0] = __mul24(ea, W6) + __mul24(da, 6);
-            off[1] = __mul24(ea, W6) + __mul24(db, 6);
-            off[2] = __mul24(eb, W6) + __mul24(da, 6);
-            off[3] = __mul24(eb, W6) + __mul24(db, 6);
+            off[0] = mul24(ea, W6) + mul24(da, 6);
+            off[1] = mul24(ea, W6) + mul24(db, 6);
+            off[2] = mul24(eb, W6) + mul24(da, 6);
+            off[3] = mul24(eb, W6) + mul24(db, 6);
         } else {
             miss = true;
             GlobalAcc<T> gl{F, nx, ny};

@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Per-particle arithmetic is compiled for the device and, for host-side
+// checks of the same code, for the host.
+#define GCB_HD __host__ __device__ __forceinline__
+
 namespace gcb {
 
 enum : uint32_t {
@@ -21,7 +25,7 @@ constexpr double kKappaFloor = 1.0e-12;
 constexpr double kDFloor = 1.0e-12;
 
 // 2D Yee lattice offsets (cells) of Ex, Ey, Ez, Bx, By, Bz.
-__device__ constexpr double kYeeStagger[6][2] = {
+constexpr double kYeeStagger[6][2] = {
     {0.5, 0.0}, {0.0, 0.5}, {0.0, 0.0}, {0.0, 0.5}, {0.5, 0.0}, {0.5, 0.5}};
 
 // Per-launch constants, passed by value as a kernel argument.
@@ -65,7 +69,7 @@ struct DevStats {
     unsigned long long max_res_bits;   // bit pattern of a non-negative double
 };
 
-__device__ __forceinline__ int wrap_index(int i, int n) {
+GCB_HD int wrap_index(int i, int n) {
     if ((unsigned)i < (unsigned)n) return i;
     int r = i % n;
     return r < 0 ? r + n : r;

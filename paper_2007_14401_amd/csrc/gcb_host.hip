@@ -45,7 +45,7 @@ struct gcb_ctx {
     DevBuf pscratch;     // sorted copy of the particle state
     DevBuf stats;        // DevStats + flagged counter
     DevBuf ke_partial;
-    DevBuf adj_states, adj_lam, adj_grad, adj_trace;
+    DevBuf adj_states, adj_lam, adj_grad, adj_trace, adj_work;
     // timing
     bool timing = false;
     std::vector<TimedLaunch> launches;
@@ -148,6 +148,8 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EINVAL, "unknown kernel %d", prm->kernel);
     if (prm->tile < 0 || prm->tile == 1 || prm->tile > 256)
         return fail(ctx, GCB_EINVAL, "tile must be 0 or in [2, 256]");
+    if (prm->replay != 0 && prm->replay != 1)
+        return fail(ctx, GCB_EINVAL, "replay must be 0 or 1");
     return GCB_OK;
 }
 
@@ -320,6 +322,7 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         L.tile_start = sb.tile_start;
         L.geom = g;
         L.trace = s_trace ? s_trace + (int64_t)step * n : nullptr;
+        L.replay = prm->replay != 0;
         L.stats = dstats;
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
@@ -370,7 +373,8 @@ void gcb_destroy(gcb_ctx* ctx) {
     DevBuf* bufs[] = {&ctx->fields,     &ctx->sort_keys,  &ctx->sort_idx,  &ctx->sort_keys2,
                       &ctx->sort_idx2,  &ctx->sort_hist,  &ctx->sort_scan,
                       &ctx->tile_start, &ctx->pscratch,   &ctx->stats,     &ctx->ke_partial,
-                      &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace};
+                      &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace,
+                      &ctx->adj_work};
     for (DevBuf* b : bufs) release(*b);
     delete ctx;
 }
@@ -456,6 +460,8 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         return fail(ctx, GCB_EINVAL, "GCB_FORM_MIXED needs fields loaded as GCB_F32");
     if (s_trace && p->n > 0 && !p->id && prm->sort_every > 0)
         return fail(ctx, GCB_EINVAL, "a switch trace with sorting needs particle ids");
+    if (prm->replay && !s_trace && p->n > 0 && n_steps > 0)
+        return fail(ctx, GCB_EINVAL, "replay needs the switch trace s_trace");
     GCB_HIP(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DevStats* dstats = nullptr;
@@ -486,6 +492,111 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         stats->max_fp_residual = m;
         stats->flagged = (int64_t)host[4];
     }
+    return GCB_OK;
+}
+
+int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params* prm,
+                      int32_t n_steps, const double* const lam_end[7],
+                      double* const lam_start[7], float* const dE[3], float* const dB[3],
+                      void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    int rc;
+    if ((rc = validate_params(ctx, prm))) return rc;
+    if ((rc = validate_particles(ctx, start, prm))) return rc;
+    if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
+    if (!lam_end || !lam_start || !dE || !dB)
+        return fail(ctx, GCB_EINVAL, "lam_end, lam_start, dE and dB must be non-NULL");
+    const int64_t n = start->n;
+    for (int c = 0; c < 7; ++c)
+        if (n > 0 && (!lam_end[c] || !lam_start[c]))
+            return fail(ctx, GCB_EINVAL, "adjoint array %d is NULL", c);
+    for (int c = 0; c < 3; ++c)
+        if (!dE[c] || !dB[c]) return fail(ctx, GCB_EINVAL, "dE/dB component %d is NULL", c);
+    if (!ctx->have_fields) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields was not called");
+    if (prm->form != GCB_FORM_F64 || ctx->dtype != GCB_F64)
+        return fail(ctx, GCB_EUNSUPPORTED, "the adjoint needs GCB_FORM_F64 and binary64 fields");
+    if (prm->n_iter > 8)
+        return fail(ctx, GCB_EUNSUPPORTED, "the adjoint supports n_iter <= 8");
+    GCB_HIP(hipSetDevice(ctx->device));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const size_t nd = (size_t)n * sizeof(double);
+    const size_t nodes = (size_t)ctx->nx * ctx->ny;
+    if ((rc = ensure(ctx, ctx->adj_states, (size_t)n_steps * 7 * nd))) return rc;
+    if ((rc = ensure(ctx, ctx->adj_trace, (size_t)n_steps * n))) return rc;
+    if ((rc = ensure(ctx, ctx->adj_lam, 7 * nd))) return rc;
+    if ((rc = ensure(ctx, ctx->adj_work, 7 * nd + (size_t)n))) return rc;
+    if ((rc = ensure(ctx, ctx->adj_grad, nodes * 6 * sizeof(float)))) return rc;
+    double* work = static_cast<double*>(ctx->adj_work.ptr);
+    uint8_t* wstatus = reinterpret_cast<uint8_t*>(work + 7 * (size_t)n);
+    double* states = static_cast<double*>(ctx->adj_states.ptr);
+    uint8_t* trace = static_cast<uint8_t*>(ctx->adj_trace.ptr);
+    double* lam = static_cast<double*>(ctx->adj_lam.ptr);
+    float* grad = static_cast<float*>(ctx->adj_grad.ptr);
+    const double* src[7] = {start->x, start->y, start->xp, start->yp,
+                            static_cast<const double*>(start->ux),
+                            static_cast<const double*>(start->uy),
+                            static_cast<const double*>(start->uz)};
+    Timer t(ctx, stream, GCB_TIMER_BACKWARD);
+    if (n > 0) {
+        for (int c = 0; c < 7; ++c)
+            GCB_HIP(hipMemcpyAsync(work + c * (size_t)n, src[c], nd, hipMemcpyDeviceToDevice,
+                                   stream));
+        GCB_HIP(hipMemsetAsync(wstatus, 0, (size_t)n, stream));
+    }
+    ParticlePtrs<double> w;
+    w.x = work;
+    w.y = work + n;
+    w.xp = work + 2 * n;
+    w.yp = work + 3 * n;
+    w.ux = work + 4 * n;
+    w.uy = work + 5 * n;
+    w.uz = work + 6 * n;
+    w.qm = start->qm;
+    w.id = nullptr;
+    w.status = wstatus;
+    const PushConst pc = make_const(ctx, prm);
+    // forward recomputation, keeping each step's start state and decisions
+    for (int32_t s = 0; s < n_steps && n > 0; ++s) {
+        GCB_HIP(hipMemcpyAsync(states + (size_t)s * 7 * n, work, 7 * nd,
+                               hipMemcpyDeviceToDevice, stream));
+        PushLaunch L;
+        L.kind = PushKind::Global;
+        L.yee = ctx->yee;
+        L.fields = ctx->fields.ptr;
+        L.n = n;
+        L.tile_start = nullptr;
+        L.geom = TileGeom{};
+        L.trace = trace + (size_t)s * n;
+        L.replay = false;
+        L.stats = nullptr;
+        GCB_HIP(launch_push_f64(L, w, w, pc, stream));
+    }
+    // reverse sweep
+    for (int c = 0; c < 7 && n > 0; ++c)
+        GCB_HIP(hipMemcpyAsync(lam + c * (size_t)n, lam_end[c], nd, hipMemcpyDeviceToDevice,
+                               stream));
+    GCB_HIP(hipMemsetAsync(grad, 0, nodes * 6 * sizeof(float), stream));
+    for (int32_t s = n_steps - 1; s >= 0 && n > 0; --s) {
+        AdjointLaunch A;
+        A.yee = ctx->yee;
+        A.fields = static_cast<const double*>(ctx->fields.ptr);
+        A.n = n;
+        A.state = states + (size_t)s * 7 * n;
+        A.qm = start->qm;
+        A.strace = trace + (size_t)s * n;
+        A.grad_fields = grad;
+        GCB_HIP(launch_adjoint_step(A, lam, pc, stream));
+    }
+    for (int c = 0; c < 7 && n > 0; ++c)
+        GCB_HIP(hipMemcpyAsync(lam_start[c], lam + c * (size_t)n, nd, hipMemcpyDeviceToDevice,
+                               stream));
+    if (n_steps == 0 && n > 0)
+        for (int c = 0; c < 7; ++c)
+            GCB_HIP(hipMemcpyAsync(lam_start[c], lam_end[c], nd, hipMemcpyDeviceToDevice,
+                                   stream));
+    float* const outs[6] = {dE[0], dE[1], dE[2], dB[0], dB[1], dB[2]};
+    GCB_HIP(launch_deinterleave_add(grad, ctx->nx, ctx->ny, outs, stream));
+    t.done();
     return GCB_OK;
 }
 

@@ -29,6 +29,7 @@ struct PushLaunch {
     const int32_t* tile_start;   // tiled: ntiles + 1 offsets
     TileGeom geom;
     uint8_t* trace;        // nullable: trace row of this step
+    bool replay;           // read the decisions from `trace` instead of writing them
     DevStats* stats;       // nullable
 };
 

@@ -35,7 +35,7 @@ struct Consts {
 };
 
 template <typename R>
-__device__ __forceinline__ Consts<R> make_consts(const PushConst& pc) {
+GCB_HD Consts<R> make_consts(const PushConst& pc) {
     Consts<R> k;
     k.dt = (R)pc.dt;
     k.h = (R)(0.5 * pc.dt);
@@ -71,7 +71,7 @@ struct Sample {
 // One component at grid coordinates (gx, gy) = (X/dx, Y/dy) with lattice
 // offset (sx, sy) in cells (runtime stagger table).
 template <typename R, bool kGrad, class Acc>
-__device__ __forceinline__ void interp_comp(const Acc& acc, int k, double gx, double gy,
+GCB_HD void interp_comp(const Acc& acc, int k, double gx, double gy,
                                             double sx, double sy, const Consts<R>& K, R& val,
                                             R& ddx, R& ddy) {
     const double xi = gx - sx;
@@ -96,7 +96,7 @@ __device__ __forceinline__ void interp_comp(const Acc& acc, int k, double gx, do
 // same operations as interp_comp, with the floor/weight computations shared
 // by the components of one weight set.
 template <typename R, bool kGrad, class Loader>
-__device__ __forceinline__ void interp_yee(const Loader& ld, const R wx[2], const R wy[2],
+GCB_HD void interp_yee(const Loader& ld, const R wx[2], const R wy[2],
                                            const Consts<R>& K, Sample<R>& s) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -121,7 +121,7 @@ __device__ __forceinline__ void interp_yee(const Loader& ld, const R wx[2], cons
 }
 
 template <typename R, bool kGrad, typename T>
-__device__ __forceinline__ void yee_fetch(const GlobalAcc<T>& acc, int ia, int ib, int ja,
+GCB_HD void yee_fetch(const GlobalAcc<T>& acc, int ia, int ib, int ja,
                                           int jb, const R wx[2], const R wy[2],
                                           const Consts<R>& K, Sample<R>& s) {
     typename GlobalAcc<T>::Loc g;
@@ -130,7 +130,7 @@ __device__ __forceinline__ void yee_fetch(const GlobalAcc<T>& acc, int ia, int i
 }
 
 template <typename R, bool kGrad, typename T>
-__device__ __forceinline__ void yee_fetch(const TileAcc<T>& acc, int ia, int ib, int ja,
+GCB_HD void yee_fetch(const TileAcc<T>& acc, int ia, int ib, int ja,
                                           int jb, const R wx[2], const R wy[2],
                                           const Consts<R>& K, Sample<R>& s) {
     int off[4];
@@ -145,7 +145,7 @@ __device__ __forceinline__ void yee_fetch(const TileAcc<T>& acc, int ia, int ib,
 // offsets (the values of the runtime table when it holds them).  Lattice
 // coordinates and weights are formed in binary64 from the binary64 position.
 template <typename R, bool kGrad, bool kYee, class Acc>
-__device__ __forceinline__ void gather(const Acc& acc, const PushConst& pc,
+GCB_HD void gather(const Acc& acc, const PushConst& pc,
                                        const Consts<R>& K, double X, double Y, Sample<R>& s) {
     const double gx = X * pc.inv_dx;
     const double gy = Y * pc.inv_dy;
@@ -186,7 +186,7 @@ struct Local {
 };
 
 template <typename R>
-__device__ __forceinline__ uint32_t local_from_sample(const Sample<R>& s, const Consts<R>& K,
+GCB_HD uint32_t local_from_sample(const Sample<R>& s, const Consts<R>& K,
                                                       Local<R>& L) {
     uint32_t flags = 0;
     const R Ex = s.E[0], Ey = s.E[1], Ez = s.E[2];
@@ -254,7 +254,7 @@ __device__ __forceinline__ uint32_t local_from_sample(const Sample<R>& s, const 
 
 // Gamma(R, u_par) = kappa sqrt(1 + (u_par^2 + 2 mu B kappa/m)/c^2)  (eq. lfacgca2)
 template <typename R>
-__device__ __forceinline__ R gamma_gca(const Local<R>& L, R upar, R mu, const Consts<R>& K) {
+GCB_HD R gamma_gca(const Local<R>& L, R upar, R mu, const Consts<R>& K) {
     const R uperp2 = (((R)2 * mu) * L.B) * L.kappa;
     const R arg = (R)1 + (upar * upar + uperp2) * K.inv_c2;
     if constexpr (kMixed<R>) {
@@ -270,7 +270,7 @@ __device__ __forceinline__ R gamma_gca(const Local<R>& L, R upar, R mu, const Co
 // Curvature drift (eq. curvdrift):
 // (m c kappa^2 / (q B)) b x [ (u_par^2/Gamma)(b.grad)b + u_par (v_E.grad)b ]
 template <typename R>
-__device__ __forceinline__ void v_curv(const Local<R>& L, R upar, R gam, R inv_qm,
+GCB_HD void v_curv(const Local<R>& L, R upar, R gam, R inv_qm,
                                        const Consts<R>& K, R vc[3]) {
     const R pre = ((K.c * L.kappa) * L.kappa) * (L.inv_B * inv_qm);
     const R a1 = (upar * upar) / gam;
@@ -284,7 +284,7 @@ __device__ __forceinline__ void v_curv(const Local<R>& L, R upar, R gam, R inv_q
 
 // Lorentz factor of the full four-velocity
 template <typename R>
-__device__ __forceinline__ R gamma_full(R ux, R uy, R uz, const Consts<R>& K) {
+GCB_HD R gamma_full(R ux, R uy, R uz, const Consts<R>& K) {
     const R arg = (R)1 + ((ux * ux + uy * uy) + uz * uz) * K.inv_c2;
     if constexpr (kMixed<R>) {
         if (arg > 1.0e6f) {
@@ -300,7 +300,7 @@ __device__ __forceinline__ R gamma_full(R ux, R uy, R uz, const Consts<R>& K) {
 // Switch (Sec. 3 criteria, Sec. 4.1): guiding center iff B > 0,
 // rho~/dl < f_rho and E/B < f_E, with rho~ = c^2 Gamma / (|q/m| B).
 
-__device__ __forceinline__ bool switch_gca_f64(const double E[3], const double Bv[3],
+GCB_HD bool switch_gca_f64(const double E[3], const double Bv[3],
                                                double ux, double uy, double uz, double qm,
                                                const PushConst& pc) {
     const double B = sqrt((Bv[0] * Bv[0] + Bv[1] * Bv[1]) + Bv[2] * Bv[2]);
@@ -314,7 +314,7 @@ __device__ __forceinline__ bool switch_gca_f64(const double E[3], const double B
 }
 
 template <typename R>
-__device__ __forceinline__ bool switch_gca(const R E[3], const R Bv[3], R ux, R uy, R uz,
+GCB_HD bool switch_gca(const R E[3], const R Bv[3], R ux, R uy, R uz,
                                            double qm, const PushConst& pc,
                                            const Consts<R>& K) {
     if constexpr (!kMixed<R>) {
@@ -343,14 +343,14 @@ __device__ __forceinline__ bool switch_gca(const R E[3], const R Bv[3], R ux, R 
 // ---------------------------------------------------------------------------
 // Periodic box (binary64)
 
-__device__ __forceinline__ double wrap(double x, double L) {
+GCB_HD double wrap(double x, double L) {
     double w = x - L * floor(x / L);
     if (w < 0.0) w = w + L;
     if (w >= L) w = w - L;
     return w;
 }
 
-__device__ __forceinline__ double min_image(double d, double L) {
+GCB_HD double min_image(double d, double L) {
     return d - L * floor(d / L + 0.5);
 }
 
@@ -358,7 +358,7 @@ __device__ __forceinline__ double min_image(double d, double L) {
 // Relativistic Boris push (Sec. 2.1), fields at x^n
 
 template <typename R>
-__device__ __forceinline__ void boris(const R E[3], const R Bv[3], R& ux, R& uy, R& uz,
+GCB_HD void boris(const R E[3], const R Bv[3], R& ux, R& uy, R& uz,
                                       R qm, const Consts<R>& K) {
     const R hq = (qm * K.dt) * (R)0.5;
     const R umx = ux + hq * E[0], umy = uy + hq * E[1], umz = uz + hq * E[2];
@@ -381,7 +381,7 @@ __device__ __forceinline__ void boris(const R E[3], const R Bv[3], R& ux, R& uy,
 
 // Full-orbit step: u^{n-1/2} -> u^{n+1/2}, x^{n+1} = x^n + dt u/Gamma.
 template <typename R>
-__device__ __forceinline__ void boris_step(const Sample<R>& s, Regs<R>& r, const PushConst& pc,
+GCB_HD void boris_step(const Sample<R>& s, Regs<R>& r, const PushConst& pc,
                                            const Consts<R>& K) {
     boris(s.E, s.B, r.ux, r.uy, r.uz, (R)r.qm, K);
     const R gn = gamma_full(r.ux, r.uy, r.uz, K);
@@ -401,7 +401,7 @@ __device__ __forceinline__ void boris_step(const Sample<R>& s, Regs<R>& r, const
 // of k1 G^2 + k2 G + k3 = 0 for G = Gamma(R^n, u_par^{n+1/2}), evaluated
 // without cancellation, then eq. dupardtcase2discsol.
 template <typename R>
-__device__ __forceinline__ R parallel_update(const Local<R>& Ln, R upar, R mu, R qm,
+GCB_HD R parallel_update(const Local<R>& Ln, R upar, R mu, R qm,
                                              bool curvature, const Consts<R>& K,
                                              uint32_t& flags) {
     const R dtqm = qm * K.dt;
@@ -424,7 +424,7 @@ __device__ __forceinline__ R parallel_update(const Local<R>& Ln, R upar, R mu, R
     R den = pos_k2 ? (R)(-2) * k1 : sq - k2;
     den = (ok && den > (R)0) ? den : (R)1;
     const R gp = num / den;
-    ok = ok && (gp > (R)0) && isfinite(gp);
+    ok = ok && (gp > (R)0) && __builtin_isfinite(gp);
     const R Ds = dok ? D : (R)1;
     if (ok) return (upr + (h * gp) * C) / Ds;
     flags |= ST_QUAD;
@@ -437,7 +437,7 @@ __device__ __forceinline__ R parallel_update(const Local<R>& Ln, R upar, R mu, R
 
 // x, y components of u_par b / Gamma + v_E + v_c at a point.
 template <typename R>
-__device__ __forceinline__ void drift_terms(const Local<R>& L, R upn, R mu, R inv_qm,
+GCB_HD void drift_terms(const Local<R>& L, R upn, R mu, R inv_qm,
                                             bool curvature, const Consts<R>& K, R& Fx,
                                             R& Fy) {
     const R g = gamma_gca(L, upn, mu, K);
@@ -453,7 +453,7 @@ __device__ __forceinline__ void drift_terms(const Local<R>& L, R upn, R mu, R in
     }
 }
 
-__device__ __forceinline__ double nan_max(double a, double b) {
+GCB_HD double nan_max(double a, double b) {
     if (a != a) return a;
     if (b != b) return b;
     return a > b ? a : b;
@@ -462,7 +462,7 @@ __device__ __forceinline__ double nan_max(double a, double b) {
 // One guiding-center step.  sn is the gather (with gradients) at x^n.
 // Returns status flags; res receives |R^K - R^{K-1}|_inf.
 template <typename R, bool kYee, class Acc>
-__device__ __forceinline__ uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
+GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
                                              const PushConst& pc, const Consts<R>& K,
                                              double& res) {
     uint32_t flags = 0;
@@ -557,9 +557,9 @@ __device__ __forceinline__ uint32_t gca_step(const Acc& acc, const Sample<R>& sn
 }
 
 template <typename R>
-__device__ __forceinline__ uint32_t finite_flag(const Regs<R>& r) {
-    const bool ok = isfinite(r.x) && isfinite(r.y) && isfinite(r.ux) && isfinite(r.uy) &&
-                    isfinite(r.uz);
+GCB_HD uint32_t finite_flag(const Regs<R>& r) {
+    const bool ok = __builtin_isfinite(r.x) && __builtin_isfinite(r.y) && __builtin_isfinite(r.ux) && __builtin_isfinite(r.uy) &&
+                    __builtin_isfinite(r.uz);
     return ok ? 0u : (uint32_t)ST_NONFINITE;
 }
 

@@ -104,7 +104,7 @@ template <typename R, typename T, bool kYee>
 __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, ParticlePtrs<R> out,
                                                       int64_t n, const T* __restrict__ F,
                                                       PushConst pc, uint8_t* trace,
-                                                      DevStats* stats) {
+                                                      bool replay, DevStats* stats) {
     const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
     const bool active = p < n;
     bool gca = false;
@@ -114,12 +114,17 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
         GlobalAcc<T> acc{F, pc.nx, pc.ny};
         Regs<R> r;
         load_particle(in, p, pc.qm, r);
-        Sample<R> s;
-        gather<R, false, kYee>(acc, pc, K, r.x, r.y, s);
-        gca = switch_gca(s.E, s.B, r.ux, r.uy, r.uz, r.qm, pc, K);
+        const int64_t ti = in.id ? (int64_t)in.id[p] : p;
+        if (replay) {
+            gca = trace[ti] == 0;
+        } else {
+            Sample<R> s;
+            gather<R, false, kYee>(acc, pc, K, r.x, r.y, s);
+            gca = switch_gca(s.E, s.B, r.ux, r.uy, r.uz, r.qm, pc, K);
+        }
         const uint32_t fl = coupled_update<R, kYee>(acc, gca, r, pc, K, res);
         store_particle(in, out, p, r, fl);
-        if (trace) trace[in.id ? (int64_t)in.id[p] : p] = gca ? 0 : 1;
+        if (trace && !replay) trace[ti] = gca ? 0 : 1;
     }
     if (stats) flush_stats(stats, active && gca, active && !gca, 0, res);
 }
@@ -128,7 +133,7 @@ template <typename R, typename T, bool kYee, int kMinWaves>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict__ tile_start,
              TileGeom g, int chunk, const T* __restrict__ F, PushConst pc, uint8_t* trace,
-             DevStats* stats) {
+             bool replay, DevStats* stats) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int wave_g[kWG / 64];
     __shared__ int wave_b[kWG / 64];
@@ -182,11 +187,15 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict_
             bool gca = false;
             if (valid) {
                 const int64_t p = base + t;
-                const double x = in.x[p], y = in.y[p];
-                const double qm = in.qm ? in.qm[p] : pc.qm;
-                Sample<R> s;
-                gather<R, false, kYee>(acc, pc, K, x, y, s);
-                gca = switch_gca(s.E, s.B, in.ux[p], in.uy[p], in.uz[p], qm, pc, K);
+                if (replay) {
+                    gca = trace[in.id ? (int64_t)in.id[p] : p] == 0;
+                } else {
+                    const double x = in.x[p], y = in.y[p];
+                    const double qm = in.qm ? in.qm[p] : pc.qm;
+                    Sample<R> s;
+                    gather<R, false, kYee>(acc, pc, K, x, y, s);
+                    gca = switch_gca(s.E, s.B, in.ux[p], in.uy[p], in.uz[p], qm, pc, K);
+                }
             }
             const unsigned long long bg = __ballot(valid && gca);
             const unsigned long long bb = __ballot(valid && !gca);
@@ -229,7 +238,7 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict_
                 ++cnt_h;
             }
             store_particle(in, out, p, r, fl);
-            if (trace) trace[in.id ? (int64_t)in.id[p] : p] = gca ? 0 : 1;
+            if (trace && !replay) trace[in.id ? (int64_t)in.id[p] : p] = gca ? 0 : 1;
             if (gca) {
                 ++cnt_g;
                 maxres = nan_max(maxres, res);
@@ -251,10 +260,10 @@ hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
         const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
         if (L.yee)
             hipLaunchKernelGGL((k_push_global<R, T, true>), dim3(blocks), dim3(kWG), 0, stream,
-                               in, out, L.n, F, pc, L.trace, L.stats);
+                               in, out, L.n, F, pc, L.trace, L.replay, L.stats);
         else
             hipLaunchKernelGGL((k_push_global<R, T, false>), dim3(blocks), dim3(kWG), 0,
-                               stream, in, out, L.n, F, pc, L.trace, L.stats);
+                               stream, in, out, L.n, F, pc, L.trace, L.replay, L.stats);
         return hipGetLastError();
     }
     const int ntiles = L.geom.ntx * L.geom.nty;
@@ -265,13 +274,15 @@ hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
-                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.stats);
+                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay,
+                           L.stats);
     } else {
         auto kfn = k_push_tiled<R, T, false, kMinWaves>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
-                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.stats);
+                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay,
+                           L.stats);
     }
     return hipGetLastError();
 }

@@ -1,0 +1,207 @@
+"""Hand-written adjoint (gcb_push_backward, GcbPush autograd) against the
+oracle gradient and against central finite differences of the GPU forward.
+
+Tolerances (from the arithmetic):
+  * state cotangents are binary64 recurrences evaluated in a different order
+    than the oracle's autograd: relative agreement 1e-8 (max norm per array)
+    after tens of steps;
+  * field cotangents are accumulated in binary32 (atomic adds of binary64
+    contributions rounded to binary32): agreement 2e-5 of the largest entry;
+  * finite differences (full-size differentiation workload): central
+    differences of the binary64 forward with the switch decisions replayed
+    from the base run, h = 1e-6 (1e-9 for grid nodes) relative, formed from
+    the per-particle kinetic-energy differences KE_p(+h) - KE_p(-h) summed
+    over particles (the mean over 1e6 particles would bury a single particle's
+    change in the rounding of the total); samples whose difference quotient
+    changes by more than 1e-3 when h is divided by 10 (outside the linear
+    regime of a chaotic orbit) are discarded; the rest must agree with the
+    adjoint to 1e-3.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_util import log, oracle_params
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+NAMES = ("x", "y", "xp", "yp", "ux", "uy", "uz")
+
+
+def _tensors(ens):
+    return {k: torch.as_tensor(np.ascontiguousarray(getattr(ens, k)), dtype=torch.float64,
+                               device=DEV) for k in NAMES}
+
+
+def _fields(F):
+    t = torch.as_tensor(F, dtype=torch.float64, device=DEV)
+    return t[:3].contiguous(), t[3:].contiguous()
+
+
+def _grad_gpu(cfg, F, ens, steps, checkpoint, curvature=1):
+    from paper_2007_14401_amd import autograd as A, gcb
+    pctx = A.PushContext(0)
+    try:
+        E, B = _fields(F)
+        E.requires_grad_(True)
+        B.requires_grad_(True)
+        st = _tensors(ens)
+        for k in NAMES:
+            st[k].requires_grad_(True)
+        qm = torch.as_tensor(ens.qm, dtype=torch.float64, device=DEV)
+        prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                         curvature=curvature, n_iter=cfg.n_iter)
+        out = A.push(E, B, *[st[k] for k in NAMES], qm, pctx, prm, steps, checkpoint)
+        L = A.kinetic_energy(out[4], out[5], out[6], pctx, prm)
+        L.backward()
+        torch.cuda.synchronize()
+        g = {k: st[k].grad.cpu().numpy() for k in NAMES}
+        gF = torch.cat([E.grad, B.grad]).cpu().numpy()
+        return float(L), g, gF
+    finally:
+        pctx.close()
+
+
+@pytest.mark.parametrize("curvature", [1, 0])
+def test_adjoint_matches_oracle_gradient(curvature):
+    cfg = make_config("harris64", curvature=curvature)
+    F = cfg.fields()
+    ens = cfg.particles(n=400, seed_offset=21)
+    steps = 24
+    Lg, g, gF = _grad_gpu(cfg, F, ens, steps, 8, curvature)
+    st0 = O.State.from_numpy(ens)
+    ref = O.push_gradients(F, cfg.dx, cfg.dy, cfg.stagger, st0, oracle_params(cfg), steps)
+    assert abs(Lg - ref["loss"]) <= 1e-12 * abs(ref["loss"])
+    tr = ref["trace"]
+    assert 0 < int(tr.sum()) < tr.numel()
+    for k in NAMES:
+        a, b = g[k], ref["d" + k].numpy()
+        err = np.max(np.abs(a - b)) / np.max(np.abs(b))
+        log(f"curv={curvature} d{k}: max-norm rel err {err:.2e}")
+        assert err <= 1e-8, (k, err)
+    b = ref["dF"].numpy()
+    err = np.max(np.abs(gF - b)) / np.max(np.abs(b))
+    log(f"curv={curvature} dF: max-norm rel err {err:.2e}")
+    assert err <= 2e-5
+
+
+def test_checkpoint_segments_do_not_change_gradients():
+    cfg = make_config("harris64")
+    F = cfg.fields()
+    ens = cfg.particles(n=300, seed_offset=4)
+    _, g1, f1 = _grad_gpu(cfg, F, ens, 20, 20)
+    _, g2, f2 = _grad_gpu(cfg, F, ens, 20, 3)
+    for k in NAMES:
+        assert np.array_equal(g1[k], g2[k]), k
+    assert np.max(np.abs(f1 - f2)) <= 1e-6 * np.max(np.abs(f1))
+
+
+def _c4_fd(steps, n_nodes, n_u, node_h, min_nodes, min_u):
+    """Central differences of the push with replayed switch decisions against
+    the adjoint on the differentiation workload (1024^2 grid, 1e6 particles)."""
+    from paper_2007_14401_amd import gcb
+    cfg = make_config("harris1024")
+    log(f"c4 ({steps} steps): inputs")
+    F = cfg.fields()
+    ens = cfg.particles()
+    n = ens.n
+    log(f"c4 ({steps} steps): adjoint")
+    L0, g, gF = _grad_gpu(cfg, F, ens, steps, 32)
+
+    ctx = gcb.gcb_create(0)
+    desc = gcb.grid_desc(cfg.nx, cfg.ny, cfg.dx, cfg.dy, cfg.stagger, gcb.GCB_F64)
+    kw = dict(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+              curvature=cfg.curvature, n_iter=cfg.n_iter)
+    prm = gcb.params(**kw)
+    prm_replay = gcb.params(replay=1, **kw)
+    qm = torch.as_tensor(ens.qm, dtype=torch.float64, device=DEV)
+    base = _tensors(ens)
+    trace = torch.empty((steps, n), dtype=torch.uint8, device=DEV)
+    out = torch.zeros(1, dtype=torch.float64, device=DEV)
+    inv_c2 = 1.0 / (cfg.c * cfg.c)
+
+    def ke_vec(st):
+        u2 = (st["ux"] * st["ux"] + st["uy"] * st["uy"]) + st["uz"] * st["uz"]
+        return (torch.sqrt(1.0 + u2 * inv_c2) - 1.0) * (cfg.c * cfg.c)
+
+    def loss(Fp, pert=None, replay=True):
+        gcb.gcb_load_fields(ctx, desc, [Fp[0], Fp[1], Fp[2]], [Fp[3], Fp[4], Fp[5]])
+        st = {k: v.clone() for k, v in base.items()}
+        if pert is not None:
+            k, i, d = pert
+            st[k][i] += d
+        st["status"] = torch.zeros(n, dtype=torch.uint8, device=DEV)
+        st["qm"] = qm
+        st["id"] = None
+        parts = gcb.particles(st)
+        gcb.gcb_push(ctx, parts, prm_replay if replay else prm, steps, s_trace=trace)
+        gcb.gcb_kinetic_energy(ctx, parts, prm, out)
+        torch.cuda.synchronize()
+        return float(out), ke_vec(st)
+
+    try:
+        Lb, _ = loss(F, replay=False)       # records the decisions in `trace`
+        Lr, _ = loss(F)
+        assert Lr == Lb                        # replaying them reproduces the run
+        assert abs(Lb - L0) <= 1e-13 * abs(L0)
+        rng = np.random.default_rng(99)
+        checked = {"node": 0, "u": 0}
+        skipped = {"node": 0, "u": 0}
+
+        def fd(mk, h):
+            (_, kp), (_, km) = mk(+h), mk(-h)
+            return float(torch.sum(kp - km)) / n / (2 * h)
+
+        def judge(kind, adj, mk, h):
+            v = fd(mk, h)
+            if abs(v - adj) <= 1e-3 * abs(adj):
+                checked[kind] += 1
+                return
+            v2 = fd(mk, h / 10)
+            if abs(v2 - v) > 1e-3 * abs(v):
+                skipped[kind] += 1     # outside the linear regime
+                return
+            raise AssertionError((kind, adj, v, v2))
+
+        flat = np.abs(gF).reshape(-1)
+        cand = np.nonzero(flat > 1e-4 * flat.max())[0]
+        for fl in rng.choice(cand, n_nodes, replace=False):
+            k, j, i = np.unravel_index(fl, F.shape)
+
+            def mk(d, k=k, j=j, i=i):
+                Fp = F.copy()
+                Fp[k, j, i] += d
+                return loss(Fp)
+            judge("node", float(gF[k, j, i]), mk, node_h * max(1.0, abs(F[k, j, i])))
+        gcb.gcb_load_fields(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
+        for p in rng.choice(n, n_u, replace=False):
+            comp = ("ux", "uy", "uz")[int(rng.integers(3))]
+            u = float(getattr(ens, comp)[p])
+
+            def mk(d, comp=comp, p=p):
+                return loss(F, (comp, int(p), d))
+            judge("u", float(g[comp][p]), mk, 1e-6 * max(cfg.c, abs(u)))
+        log(f"c4 ({steps} steps) finite differences: checked {checked}, "
+            f"outside the linear regime {skipped}")
+        assert checked["node"] >= min_nodes and checked["u"] >= min_u
+    finally:
+        gcb.gcb_destroy(ctx)
+
+
+def test_c4_finite_differences_full_horizon():
+    """512 steps (checkpoint every 32): 32 initial four-velocity components."""
+    _c4_fd(512, 0, 32, 1e-6, 0, 24)
+
+
+def test_c4_finite_differences_grid_nodes():
+    """Grid-node cotangents at full size over one checkpoint segment (32
+    steps): over 512 steps a node perturbation reaches hundreds of particle-
+    steps on chaotic orbits, and the guiding-center map is discontinuous in
+    position (the bilinear gradient of B jumps across cell lines), so almost
+    every difference quotient leaves the linear regime."""
+    _c4_fd(32, 64, 0, 1e-7, 48, 0)

@@ -274,3 +274,24 @@ def test_argument_validation(h64):
         assert e.value.code == gcb.GCB_ENOFIELDS
     finally:
         gcb.gcb_destroy(ctx)
+
+
+@pytest.mark.parametrize("kernel,sort_every", [(1, 0), (2, 3)])
+def test_replayed_switch_decisions_reproduce_the_run(h64, kernel, sort_every):
+    """A push with params.replay = 1 reads S from the trace of an earlier push
+    and reproduces it bit for bit."""
+    cfg, F, run = h64
+    ens = cfg.particles(n=2500, seed_offset=8)
+    t1 = _state(ens)
+    tr, _ = run.push(t1, 15, trace=True, kernel=kernel, sort_every=sort_every, tile=16)
+    t2 = _state(ens)
+    from paper_2007_14401_amd import gcb
+    prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                     curvature=cfg.curvature, n_iter=cfg.n_iter, kernel=kernel,
+                     sort_every=sort_every, tile=16, replay=1)
+    tr_copy = tr.clone()
+    gcb.gcb_push(run.ctx, gcb.particles(t2), prm, 15, s_trace=tr)
+    torch.cuda.synchronize()
+    assert torch.equal(tr, tr_copy)            # replay reads, does not write
+    for k in ("x", "y", "xp", "yp", "ux", "uy", "uz", "status", "id"):
+        assert torch.equal(t1[k], t2[k]), k
