@@ -103,6 +103,7 @@ def main():
               "cross-GPU work in this build", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     from paper_2007_14401_amd import gcb, state
@@ -170,7 +171,12 @@ def main():
             B = Ft[3:].contiguous().requires_grad_(True)
             del Ft
             names = ("x", "y", "xp", "yp", "ux", "uy", "uz")
-            st = {k: torch.as_tensor(getattr(ens, k), dtype=torch.float64, device=dev)
+            # initial positions cell-sorted (row-major cells), as the workload states;
+            # the differentiable push itself does not re-sort
+            cell = (np.floor(ens.y / cfg.dy).astype(np.int64) * cfg.nx
+                    + np.floor(ens.x / cfg.dx).astype(np.int64))
+            order = np.argsort(cell, kind="stable")
+            st = {k: torch.as_tensor(getattr(ens, k)[order], dtype=torch.float64, device=dev)
                   .requires_grad_(True) for k in names}
             prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
                              curvature=cfg.curvature, n_iter=cfg.n_iter)

@@ -30,15 +30,22 @@ struct AtomicSink {
     }
 };
 
-template <bool kYee>
-__global__ __launch_bounds__(kWG) void k_adjoint_step(const double* __restrict__ st,
+// One regime per launch: lanes whose particle took the other branch at this
+// step return at once, so no wavefront executes both reverse branches.
+#ifndef GCB_ADJ_MIN_WAVES
+#define GCB_ADJ_MIN_WAVES 1
+#endif
+
+template <bool kYee, bool kBoris>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(GCB_ADJ_MIN_WAVES))) void
+k_adjoint_step(const double* __restrict__ st,
                                                        const double* __restrict__ qm_arr,
                                                        const uint8_t* __restrict__ S,
                                                        double* lam, int64_t n,
                                                        const double* __restrict__ F,
                                                        PushConst pc, float* grad) {
     const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (p >= n) return;
+    if (p >= n || (S[p] != 0) != kBoris) return;
     double s[7], l[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
@@ -49,7 +56,7 @@ __global__ __launch_bounds__(kWG) void k_adjoint_step(const double* __restrict__
     const GlobalAcc<double> acc{F, pc.nx, pc.ny};
     AtomicSink sink{grad, pc.nx, pc.ny};
     const Consts<double> K = make_consts<double>(pc);
-    if (S[p])
+    if (kBoris)
         adj::boris_step_vjp<kYee>(acc, sink, pc, K, s, qm, l);
     else
         adj::gca_step_vjp<kYee>(acc, sink, pc, K, s, qm, l);
@@ -63,12 +70,17 @@ hipError_t launch_adjoint_step(const AdjointLaunch& L, double* lam, const PushCo
                                hipStream_t stream) {
     if (L.n == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
-    if (L.yee)
-        hipLaunchKernelGGL(k_adjoint_step<true>, dim3(blocks), dim3(kWG), 0, stream, L.state,
-                           L.qm, L.strace, lam, L.n, L.fields, pc, L.grad_fields);
-    else
-        hipLaunchKernelGGL(k_adjoint_step<false>, dim3(blocks), dim3(kWG), 0, stream, L.state,
-                           L.qm, L.strace, lam, L.n, L.fields, pc, L.grad_fields);
+    if (L.yee) {
+        hipLaunchKernelGGL((k_adjoint_step<true, false>), dim3(blocks), dim3(kWG), 0, stream,
+                           L.state, L.qm, L.strace, lam, L.n, L.fields, pc, L.grad_fields);
+        hipLaunchKernelGGL((k_adjoint_step<true, true>), dim3(blocks), dim3(kWG), 0, stream,
+                           L.state, L.qm, L.strace, lam, L.n, L.fields, pc, L.grad_fields);
+    } else {
+        hipLaunchKernelGGL((k_adjoint_step<false, false>), dim3(blocks), dim3(kWG), 0, stream,
+                           L.state, L.qm, L.strace, lam, L.n, L.fields, pc, L.grad_fields);
+        hipLaunchKernelGGL((k_adjoint_step<false, true>), dim3(blocks), dim3(kWG), 0, stream,
+                           L.state, L.qm, L.strace, lam, L.n, L.fields, pc, L.grad_fields);
+    }
     return hipGetLastError();
 }
 
