@@ -4,9 +4,11 @@
 // Every building block of the forward step in gcb_math.hpp has a hand-written
 // adjoint here; a block's adjoint recomputes the forward values it needs from
 // its inputs.  Cotangents are accumulated (+=) into the *Bar structures.
-//   gather_vjp       linear shape function: node cotangents (to a sink) and
-//                    the position cotangent, including the mixed second
-//                    derivative of W carried by the B-gradient cotangents
+//   gather_vjp       linear shape function: the position cotangent,
+//                    including the mixed second derivative of W carried by
+//                    the B-gradient cotangents; the gather point and its
+//                    cotangents go to a sink
+//   scatter_sample   node cotangents of one recorded gather point
 //   local_vjp        b, v_E, kappa, E_par, d_j b_i, (b.grad)b, (v_E.grad)b
 //   gamma_vjp        Gamma(R, u_par) (eq. lfacgca2)
 //   vcurv_vjp        curvature drift (eq. curvdrift)
@@ -60,12 +62,43 @@ GCB_HD void cross_vjp(const double a[3], const double b[3], const double zb[3], 
 // ---------------------------------------------------------------------------
 // gather
 
-// Cotangents of the six interpolated components and of the B gradients at
-// (X, Y): node cotangents go to `sink.add(k, i, j, g)` (global node indices,
-// any periodic image), the position cotangent to (Xb, Yb).
+// Node cotangents of one gather point: the cotangents of the six interpolated
+// components and of the B gradients at (X, Y) spread over the four nodes of
+// each component's cell, `add(k, i, j, g)` with global node indices (any
+// periodic image).
+template <class Add>
+GCB_HD void scatter_sample(Add& add, const PushConst& pc, bool yee, double X, double Y,
+                           const SampleBar& sb) {
+    const double gx = X * pc.inv_dx;
+    const double gy = Y * pc.inv_dy;
+    const double idx = pc.inv_dx, idy = pc.inv_dy;
+    for (int k = 0; k < 6; ++k) {
+        const double sx = yee ? kYeeStagger[k][0] : pc.stagger[k][0];
+        const double sy = yee ? kYeeStagger[k][1] : pc.stagger[k][1];
+        const double vb = k < 3 ? sb.E[k] : sb.B[k - 3];
+        const double dxb = k < 3 ? 0.0 : sb.dBx[k - 3];
+        const double dyb = k < 3 ? 0.0 : sb.dBy[k - 3];
+        if (vb == 0.0 && dxb == 0.0 && dyb == 0.0) continue;
+        const double xi = gx - sx, eta = gy - sy;
+        const double fi = floor(xi), fj = floor(eta);
+        const double wx = xi - fi, wy = eta - fj;
+        const int i = (int)fi, j = (int)fj;
+        const double ax = 1.0 - wx, ay = 1.0 - wy;
+        add(k, i, j, vb * (ax * ay) - dxb * (ay * idx) - dyb * (ax * idy));
+        add(k, i + 1, j, vb * (wx * ay) + dxb * (ay * idx) - dyb * (wx * idy));
+        add(k, i, j + 1, vb * (ax * wy) - dxb * (wy * idx) + dyb * (ax * idy));
+        add(k, i + 1, j + 1, vb * (wx * wy) + dxb * (wy * idx) + dyb * (wx * idy));
+    }
+}
+
+// Cotangent of the gather at (X, Y): the position cotangent, including the
+// mixed second derivative of W carried by the B-gradient cotangents, is added
+// to (Xb, Yb); the gather point and its cotangents go to `sink.sample`, which
+// owns the node cotangents (scatter_sample spreads them).
 template <class Acc, class Sink>
 GCB_HD void gather_vjp(const Acc& acc, Sink& sink, const PushConst& pc, bool yee, double X,
                        double Y, const SampleBar& sb, double& Xb, double& Yb) {
+    sink.sample(X, Y, sb);
     const double gx = X * pc.inv_dx;
     const double gy = Y * pc.inv_dy;
     const double idx = pc.inv_dx, idy = pc.inv_dy;
@@ -83,10 +116,6 @@ GCB_HD void gather_vjp(const Acc& acc, Sink& sink, const PushConst& pc, bool yee
         double f00, f10, f01, f11;
         acc.quad(k, i, j, f00, f10, f01, f11);
         const double ax = 1.0 - wx, ay = 1.0 - wy;
-        sink.add(k, i, j, vb * (ax * ay) - dxb * (ay * idx) - dyb * (ax * idy));
-        sink.add(k, i + 1, j, vb * (wx * ay) + dxb * (ay * idx) - dyb * (wx * idy));
-        sink.add(k, i, j + 1, vb * (ax * wy) - dxb * (wy * idx) + dyb * (ax * idy));
-        sink.add(k, i + 1, j + 1, vb * (wx * wy) + dxb * (wy * idx) + dyb * (wx * idy));
         const double cross = (((f11 - f01) - f10) + f00) * (idx * idy);
         Xb += vb * ((ay * (f10 - f00) + wy * (f11 - f01)) * idx) + dyb * cross;
         Yb += vb * ((ax * (f01 - f00) + wx * (f11 - f10)) * idy) + dxb * cross;
@@ -415,6 +444,13 @@ GCB_HD void local_bar_to_position(const Acc& acc, Sink& sink, const PushConst& p
 }
 
 constexpr int kMaxAdjIter = 8;   // fixed-point iterations the adjoint supports
+
+// Number of gather points whose cotangents gca_step_vjp hands to its sink:
+// R^{n+1/2}, the iterates R^1..R^{K-1}, R^n and R^{n-1/2}.
+GCB_HD int gca_vjp_samples(int n_iter) {
+    const int Kit = n_iter < kMaxAdjIter ? n_iter : kMaxAdjIter;
+    return (Kit > 1 ? Kit - 1 : 0) + 3;
+}
 
 template <bool kYee, class Acc, class Sink>
 GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const KD& K,

@@ -45,7 +45,7 @@ struct gcb_ctx {
     DevBuf pscratch;     // sorted copy of the particle state
     DevBuf stats;        // DevStats + flagged counter
     DevBuf ke_partial;
-    DevBuf adj_states, adj_lam, adj_grad, adj_trace, adj_work;
+    DevBuf adj_states, adj_lam, adj_grad, adj_trace, adj_work, adj_samples;
     // timing
     bool timing = false;
     std::vector<TimedLaunch> launches;
@@ -374,7 +374,7 @@ void gcb_destroy(gcb_ctx* ctx) {
                       &ctx->sort_idx2,  &ctx->sort_hist,  &ctx->sort_scan,
                       &ctx->tile_start, &ctx->pscratch,   &ctx->stats,     &ctx->ke_partial,
                       &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace,
-                      &ctx->adj_work};
+                      &ctx->adj_work,   &ctx->adj_samples};
     for (DevBuf* b : bufs) release(*b);
     delete ctx;
 }
@@ -526,6 +526,7 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
     if ((rc = ensure(ctx, ctx->adj_lam, 7 * nd))) return rc;
     if ((rc = ensure(ctx, ctx->adj_work, 7 * nd + (size_t)n))) return rc;
     if ((rc = ensure(ctx, ctx->adj_grad, nodes * 6 * sizeof(float)))) return rc;
+    if ((rc = ensure(ctx, ctx->adj_samples, adjoint_sample_bytes(n, prm->n_iter)))) return rc;
     double* work = static_cast<double*>(ctx->adj_work.ptr);
     uint8_t* wstatus = reinterpret_cast<uint8_t*>(work + 7 * (size_t)n);
     double* states = static_cast<double*>(ctx->adj_states.ptr);
@@ -585,6 +586,7 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
         A.qm = start->qm;
         A.strace = trace + (size_t)s * n;
         A.grad_fields = grad;
+        A.samples = ctx->adj_samples.ptr;
         GCB_HIP(launch_adjoint_step(A, lam, pc, stream));
     }
     for (int c = 0; c < 7 && n > 0; ++c)

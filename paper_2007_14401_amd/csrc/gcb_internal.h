@@ -103,7 +103,10 @@ struct AdjointLaunch {
     const double* qm;       // nullable
     const uint8_t* strace;  // per-particle S of this step (1 = Boris)
     float* grad_fields;     // node-interleaved float gradient accumulators
+    void* samples;          // adjoint_sample_bytes(n, n_iter) of scratch
 };
+
+size_t adjoint_sample_bytes(int64_t n, int n_iter);
 
 hipError_t launch_adjoint_step(const AdjointLaunch& L, double* lam /*7*n in/out*/,
                                const PushConst& pc, hipStream_t stream);
