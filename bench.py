@@ -35,6 +35,15 @@ FP64_VECTOR_PEAK_TF = 78.6      # MI355X FP64 vector, AMD published
 FLOPS_BORIS = 287.0
 FLOPS_GCA = 2216.0
 
+# Hardware-counter record of the binary64 push kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs, calibrated against a plain device copy); it is used only
+# while the kernel sources still hash to the value it was taken with.
+COUNTER_RECORD = os.path.join(ROOT, "profiles", "k_push_tiled_f64_harris4096.md")
+KERNEL_SOURCES = tuple(os.path.join("paper_2007_14401_amd", "csrc", f) for f in (
+    "gcb_common.hpp", "gcb_access.hpp", "gcb_math.hpp", "gcb_push_kernels.hpp",
+    "gcb_push_f64.hip", "gcb_push_mixed.hip", "gcb_sort.hip", "gcb_host.hip",
+    "gcb_internal.h")) + (os.path.join("paper_2007_14401_amd", "build.py"),)
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -49,6 +58,40 @@ def push_bytes_per_step(n: int, nx: int, ny: int, form: int) -> int:
     state = n * 2 * (4 * 8 + 3 * ub + 1)
     fields = nx * ny * 6 * fb
     return state + fields
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        h.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_record(path: str = COUNTER_RECORD):
+    """The `<!-- counters: {...} -->` line of a committed profile summary."""
+    import re
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"<!-- counters: (\{.*?\}) -->", text)
+    return json.loads(m.group(1)) if m else None
+
+
+def measured_traffic(workload: str, n: int, sort_every: int, tile: int):
+    """HBM bytes per launch of the binary64 push from the counter record, or
+    None when there is none for this launch or the kernel changed since."""
+    rec = counter_record()
+    if not rec:
+        return None
+    if (rec.get("sources_sha256") != kernel_sources_sha256() or rec.get("workload") != workload
+            or rec.get("n") != n or rec.get("sort_every") != sort_every
+            or rec.get("tile") != tile):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def cpu_baseline(cfg, F, ens, budget_s: float = 12.0):
@@ -212,6 +255,8 @@ def main():
     achieved = bytes_step / (push_ms * 1e-3) / 1e9
     value = n * a.steps / wall
     flops = FLOPS_GCA * gca_frac + FLOPS_BORIS * (1.0 - gca_frac)
+    alu_tf = flops * n / (push_ms * 1e-3) / 1e12
+    traffic = measured_traffic(cfg.name, n, a.sort_every, a.tile)
 
     forms = {}
     if not a.no_mixed:
@@ -260,14 +305,20 @@ def main():
                    "kernel": ["auto", "global", "tiled"][a.kernel],
                    "sort_every": a.sort_every, "tile": a.tile,
                    "gca_fraction": round(gca_frac, 4)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        # the push issues far more binary64 vector instructions per byte than the
+        # HBM can feed: it is bound by the vector ALU, so that is the roofline;
+        # the HBM figures of the same launch sit beside it
+        "roofline": {"bound": "alu", "achieved": alu_tf, "peak": FP64_VECTOR_PEAK_TF,
+                     "unit": "TFLOP/s", "frac": alu_tf / FP64_VECTOR_PEAK_TF,
+                     "traffic": traffic,
                      "kernel": "k_push_tiled" if a.kernel != 1 else "k_push_global",
-                     "kernel_ms": push_ms, "algorithmic_bytes_per_launch": bytes_step,
-                     "alu_achieved_TFLOPs": flops * n / (push_ms * 1e-3) / 1e12,
-                     "alu_peak_TFLOPs": FP64_VECTOR_PEAK_TF,
-                     "alu_frac": flops * n / (push_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TF,
-                     "algorithmic_flops_per_particle_step": flops},
+                     "kernel_ms": push_ms,
+                     "algorithmic_flops_per_particle_step": flops,
+                     "algorithmic_flops_per_launch": flops * n,
+                     "hbm_achieved_GBs": achieved, "hbm_peak_GBs": HBM_PEAK_GBS,
+                     "hbm_frac": achieved / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": bytes_step,
+                     "traffic_over_algorithmic": (traffic / bytes_step) if traffic else None},
         "sort_ms_per_sort": sort_ms,
         "forms": forms,
     }

@@ -276,6 +276,25 @@ def test_argument_validation(h64):
         gcb.gcb_destroy(ctx)
 
 
+@pytest.mark.parametrize("tile", [16, 24])
+def test_cell_sort_order(h64, tile):
+    """The cell sort is a stable sort by tile (row-major tiles): after one
+    step with sort_every = 1 the particles sit in that order of their start
+    positions (bit-exact index work; the 64-cell grid leaves a ragged last
+    tile for tile = 24)."""
+    cfg, F, run = h64
+    ens = cfg.particles(n=4096 + 37, seed_offset=11)
+    t = _state(ens)
+    run.push(t, 1, kernel=2, sort_every=1, tile=tile)
+    cx = np.floor(ens.x / cfg.dx).astype(np.int64)
+    cy = np.floor(ens.y / cfg.dy).astype(np.int64)
+    ntx = -(-cfg.nx // tile)
+    key = (cy // tile) * ntx + cx // tile
+    want = np.argsort(key, kind="stable")
+    got = t["id"].cpu().numpy()
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("kernel,sort_every", [(1, 0), (2, 3)])
 def test_replayed_switch_decisions_reproduce_the_run(h64, kernel, sort_every):
     """A push with params.replay = 1 reads S from the trace of an earlier push
