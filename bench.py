@@ -94,13 +94,15 @@ def measured_traffic(workload: str, n: int, sort_every: int, tile: int):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def cpu_baseline(cfg, F, ens, budget_s: float = 12.0):
-    """The CPU oracle (torch float64) on a bounded sample of the same workload."""
+def cpu_baseline(cfg, F, ens, budget_s: float = 20.0):
+    """The CPU oracle (torch float64) on a bounded sample of the same workload:
+    a random subset of the particles, pushed for up to the workload's step
+    count or about `budget_s` seconds."""
     import numpy as np
     import torch
 
     import oracle as O
-    n = 20000
+    n = 60000
     rng = np.random.default_rng(5)
     sub = ens.subset(np.sort(rng.choice(ens.n, n, replace=False)))
     p = O.Params(dt=cfg.dt, c=cfg.c, f_rho=cfg.f_rho, f_E=cfg.f_E, curvature=True,

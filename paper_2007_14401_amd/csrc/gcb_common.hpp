@@ -61,8 +61,12 @@ struct ParticlePtrs {
     uint8_t* status;
 };
 
-// Accumulators filled by the push kernels when statistics are requested.
-struct DevStats {
+// Accumulators filled by the push kernels when statistics are requested:
+// kStatSlots copies, one cache line each; workgroup b adds to slot
+// b % kStatSlots so that the atomics of a launch spread over many L2 lines,
+// and the host sums the slots.
+constexpr int kStatSlots = 512;
+struct alignas(64) DevStats {
     unsigned long long gca_steps;
     unsigned long long boris_steps;
     unsigned long long halo_misses;

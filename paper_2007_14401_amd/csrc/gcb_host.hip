@@ -465,10 +465,11 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     GCB_HIP(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DevStats* dstats = nullptr;
+    constexpr size_t kStatBytes = kStatSlots * sizeof(DevStats) + sizeof(DevStats);
     if (stats) {
-        if ((rc = ensure(ctx, ctx->stats, sizeof(DevStats) + 16))) return rc;
+        if ((rc = ensure(ctx, ctx->stats, kStatBytes))) return rc;
         dstats = static_cast<DevStats*>(ctx->stats.ptr);
-        GCB_HIP(hipMemsetAsync(dstats, 0, sizeof(DevStats) + 16, stream));
+        GCB_HIP(hipMemsetAsync(dstats, 0, kStatBytes, stream));
     }
     if (prm->form == GCB_FORM_F64)
         rc = run_push<double>(ctx, p, prm, n_steps, s_trace, dstats, stream);
@@ -476,21 +477,29 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         rc = run_push<float>(ctx, p, prm, n_steps, s_trace, dstats, stream);
     if (rc) return rc;
     if (stats) {
+        // the flagged count goes to the first word after the slots
         unsigned long long* flagged =
-            reinterpret_cast<unsigned long long*>(static_cast<char*>(ctx->stats.ptr) +
-                                                  sizeof(DevStats));
+            reinterpret_cast<unsigned long long*>(dstats + kStatSlots);
         GCB_HIP(launch_count_flagged(p->status, p->n, flagged, stream));
-        unsigned long long host[5];
-        GCB_HIP(hipMemcpyAsync(host, ctx->stats.ptr, sizeof(host), hipMemcpyDeviceToHost,
+        std::vector<DevStats> host(kStatSlots + 1);
+        GCB_HIP(hipMemcpyAsync(host.data(), ctx->stats.ptr, kStatBytes, hipMemcpyDeviceToHost,
                                stream));
         GCB_HIP(hipStreamSynchronize(stream));
-        stats->gca_steps = (int64_t)host[0];
-        stats->boris_steps = (int64_t)host[1];
-        stats->halo_misses = (int64_t)host[2];
+        unsigned long long g = 0, b = 0, h = 0, mbits = 0;
+        for (int s = 0; s < kStatSlots; ++s) {
+            g += host[s].gca_steps;
+            b += host[s].boris_steps;
+            h += host[s].halo_misses;
+            // non-negative doubles order like their bit patterns
+            mbits = host[s].max_res_bits > mbits ? host[s].max_res_bits : mbits;
+        }
+        stats->gca_steps = (int64_t)g;
+        stats->boris_steps = (int64_t)b;
+        stats->halo_misses = (int64_t)h;
         double m;
-        std::memcpy(&m, &host[3], sizeof(m));
+        std::memcpy(&m, &mbits, sizeof(m));
         stats->max_fp_residual = m;
-        stats->flagged = (int64_t)host[4];
+        stats->flagged = (int64_t)host[kStatSlots].gca_steps;
     }
     return GCB_OK;
 }

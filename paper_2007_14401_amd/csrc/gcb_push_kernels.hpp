@@ -42,6 +42,7 @@ __device__ __forceinline__ void flush_stats(DevStats* st, unsigned gca, unsigned
         h += __shfl_xor(h, off, 64);
     }
     const double m = wave_max(maxres);
+    st += blockIdx.x % kStatSlots;
     if ((threadIdx.x & 63) == 0) {
         if (g) atomicAdd(&st->gca_steps, g);
         if (b) atomicAdd(&st->boris_steps, b);
