@@ -38,7 +38,7 @@ FLOPS_GCA = 2216.0
 # Hardware-counter record of the binary64 push kernel (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, calibrated against a plain device copy); it is used only
 # while the kernel sources still hash to the value it was taken with.
-COUNTER_RECORD = os.path.join(ROOT, "profiles", "k_push_tiled_f64_harris4096.md")
+COUNTER_RECORD = os.path.join(ROOT, "profiles", "k_push_tiled_harris4096.md")
 KERNEL_SOURCES = tuple(os.path.join("paper_2007_14401_amd", "csrc", f) for f in (
     "gcb_common.hpp", "gcb_access.hpp", "gcb_math.hpp", "gcb_push_kernels.hpp",
     "gcb_push_f64.hip", "gcb_push_mixed.hip", "gcb_sort.hip", "gcb_host.hip",
