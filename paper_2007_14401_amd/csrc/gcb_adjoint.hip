@@ -5,16 +5,21 @@
 // arithmetic as gcb_push) while the start state of every step and its switch
 // decisions are kept; then, per step in reverse order, two kernels (one per
 // regime) map the cotangents of the step outputs to those of its inputs and
-// record every gather point with its cotangents, and a scatter kernel spreads
-// the recorded cotangents over the nodes of a binary32 node-interleaved grid
-// (global atomics), which is finally added to the caller's dE/dB arrays.
+// record every gather point with its cotangents.  After a batch of steps a
+// scatter kernel spreads the recorded cotangents over the nodes of a binary32
+// node-interleaved grid (global atomics), which is finally added to the
+// caller's dE/dB arrays.
 //
 // The scatter is a kernel of its own because atomics on this hardware count
 // against the same wait counter as loads: inside the register-heavy adjoint
 // kernel (one wave per SIMD) every gather would wait for the atomics issued
-// before it.  The scatter kernel is light, runs many waves per SIMD, and sums a
-// particle's gather points of one step in a 4x4 node window per component
-// before touching memory, so most of the per-point atomics merge.
+// before it.  The scatter kernel is light and runs several waves per SIMD; it
+// sums one particle's gather points of all steps of the batch in a 4x4 node
+// window per component, kept in registers, and writes a window with one
+// atomic per non-zero node only when a point falls outside it (the window
+// then moves) and at the end.  A guiding-center particle drifts a small
+// fraction of a cell per step, so its windows seldom move and the atomics of
+// a whole batch merge; atomic throughput is what bounds the scatter.
 // Compiled with -ffp-contract=off like the forward binary64 path.
 #include <hip/hip_runtime.h>
 
@@ -83,117 +88,151 @@ __global__ __launch_bounds__(kWG) void k_adjoint_step(const double* __restrict__
 }
 
 constexpr int kScatterWG = 256;
+constexpr int kNoOrigin = -0x40000000;   // window not placed yet
 
-__device__ __forceinline__ void node_atomic(float* g, int nx, int ny, int k, int i, int j,
-                                            double v) {
-    if (v == 0.0) return;
-    const int i0 = wrap_index(i, nx);
-    const int j0 = wrap_index(j, ny);
-    atomicAdd(&g[((size_t)j0 * nx + i0) * 6 + k], (float)v);
-}
-
-// Node cotangents of the recorded gather points (one Boris point, or
-// gca_slots guiding-center points, per particle).  Per component the points'
-// 2x2 stencils are summed in a 4x4 window around the first point's cell and
-// the window is written with one atomic per non-zero node; a stencil outside
-// the window (a point more than one cell away, or across the periodic seam)
-// goes straight to memory.
+// Node cotangents of the gather points recorded over a batch of nb steps
+// (per step one Boris point or `slots` guiding-center points per particle;
+// step b of the batch at records (b*slots + q)).  Per component a 4x4 node
+// window with origin (ox, oy) sums the points' 2x2 stencils; a stencil that
+// does not fit sends the window to memory (one atomic per non-zero node) and
+// moves it there.
 template <bool kYee>
-__global__ __launch_bounds__(kScatterWG) void k_scatter_samples(
+__global__ __launch_bounds__(kScatterWG) void k_scatter_batch(
     const double* __restrict__ X, const double* __restrict__ Y, const float* __restrict__ bar,
-    const uint8_t* __restrict__ S, int64_t n, int gca_slots, PushConst pc, float* grad) {
+    const uint8_t* __restrict__ S, int64_t n, int nb, int slots, PushConst pc, float* grad) {
     const int64_t p = (int64_t)blockIdx.x * kScatterWG + threadIdx.x;
     if (p >= n) return;
-    const int ns = S[p] ? 1 : gca_slots;
     const double idx = pc.inv_dx, idy = pc.inv_dy;
+    float w[6][16];
+    int ox[6], oy[6];
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const double sx = kYee ? kYeeStagger[k][0] : pc.stagger[k][0];
-        const double sy = kYee ? kYeeStagger[k][1] : pc.stagger[k][1];
-        int i0 = 0, j0 = 0;
-        double w[4][4];
+        ox[k] = kNoOrigin;
+        oy[k] = kNoOrigin;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int e = 0; e < 16; ++e) w[k][e] = 0.0f;
+    }
+    auto flush = [&](int k) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) w[a][b] = 0.0;
-        for (int q = 0; q < ns; ++q) {
-            const int64_t o = (int64_t)q * n + p;
-            const float* bq = bar + (int64_t)q * 12 * n + p;
-            const double vb = (double)bq[k * n];
-            const double dxb = k < 3 ? 0.0 : (double)bq[(3 + k) * n];
-            const double dyb = k < 3 ? 0.0 : (double)bq[(6 + k) * n];
-            const double xi = X[o] * idx - sx, eta = Y[o] * idy - sy;
-            const double fi = floor(xi), fj = floor(eta);
-            const int i = (int)fi, j = (int)fj;
-            if (q == 0) {
-                i0 = i;
-                j0 = j;
-            }
-            if (vb == 0.0 && dxb == 0.0 && dyb == 0.0) continue;
-            const double wx = xi - fi, wy = eta - fj;
-            const double ax = 1.0 - wx, ay = 1.0 - wy;
-            const double c00 = vb * (ax * ay) - dxb * (ay * idx) - dyb * (ax * idy);
-            const double c10 = vb * (wx * ay) + dxb * (ay * idx) - dyb * (wx * idy);
-            const double c01 = vb * (ax * wy) - dxb * (wy * idx) + dyb * (ax * idy);
-            const double c11 = vb * (wx * wy) + dxb * (wy * idx) + dyb * (wx * idy);
-            const int di = i - i0, dj = j - j0;
-            if (di >= -1 && di <= 1 && dj >= -1 && dj <= 1) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int ra = a - 1 - di;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int rb = b - 1 - dj;
-                        const double v = ra == 0 ? (rb == 0 ? c00 : rb == 1 ? c01 : 0.0)
-                                       : ra == 1 ? (rb == 0 ? c10 : rb == 1 ? c11 : 0.0)
-                                                 : 0.0;
-                        w[a][b] += v;
-                    }
-                }
-            } else {
-                node_atomic(grad, pc.nx, pc.ny, k, i, j, c00);
-                node_atomic(grad, pc.nx, pc.ny, k, i + 1, j, c10);
-                node_atomic(grad, pc.nx, pc.ny, k, i, j + 1, c01);
-                node_atomic(grad, pc.nx, pc.ny, k, i + 1, j + 1, c11);
+        for (int e = 0; e < 16; ++e) {
+            if (w[k][e] != 0.0f) {
+                const int i = wrap_index((int)((unsigned)ox[k] + (unsigned)(e >> 2)), pc.nx);
+                const int j = wrap_index((int)((unsigned)oy[k] + (unsigned)(e & 3)), pc.ny);
+                atomicAdd(&grad[((size_t)j * pc.nx + i) * 6 + k], w[k][e]);
+                w[k][e] = 0.0f;
             }
         }
+    };
+    for (int b = nb - 1; b >= 0; --b) {
+        const int ns = S[(int64_t)b * n + p] ? 1 : slots;
+        for (int q = 0; q < ns; ++q) {
+            const int64_t r = (int64_t)b * slots + q;
+            const double gx = X[r * n + p] * idx;
+            const double gy = Y[r * n + p] * idy;
+            const float* bq = bar + r * 12 * n + p;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int k = 0; k < 6; ++k) {
+                const double vb = (double)bq[k * n];
+                const double dxb = k < 3 ? 0.0 : (double)bq[(3 + k) * n];
+                const double dyb = k < 3 ? 0.0 : (double)bq[(6 + k) * n];
+                if (vb == 0.0 && dxb == 0.0 && dyb == 0.0) continue;
+                const double sx = kYee ? kYeeStagger[k][0] : pc.stagger[k][0];
+                const double sy = kYee ? kYeeStagger[k][1] : pc.stagger[k][1];
+                const double xi = gx - sx, eta = gy - sy;
+                const double fi = floor(xi), fj = floor(eta);
+                const int i = (int)fi, j = (int)fj;
+                const double wx = xi - fi, wy = eta - fj;
+                const double ax = 1.0 - wx, ay = 1.0 - wy;
+                const float c00 = (float)(vb * (ax * ay) - dxb * (ay * idx) - dyb * (ax * idy));
+                const float c10 = (float)(vb * (wx * ay) + dxb * (ay * idx) - dyb * (wx * idy));
+                const float c01 = (float)(vb * (ax * wy) - dxb * (wy * idx) + dyb * (ax * idy));
+                const float c11 = (float)(vb * (wx * wy) + dxb * (wy * idx) + dyb * (wx * idy));
+                // offsets in unsigned arithmetic: any cell index is allowed
+                unsigned du = (unsigned)i - (unsigned)ox[k], dv = (unsigned)j - (unsigned)oy[k];
+                if (du > 2u || dv > 2u) {
+                    flush(k);
+                    ox[k] = (int)((unsigned)i - 1u);
+                    oy[k] = (int)((unsigned)j - 1u);
+                    du = 1u;
+                    dv = 1u;
+                }
+                const int di = (int)du, dj = (int)dv;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) node_atomic(grad, pc.nx, pc.ny, k, i0 - 1 + a, j0 - 1 + b, w[a][b]);
+                for (int e = 0; e < 16; ++e) {
+                    const int ra = (e >> 2) - di, rb = (e & 3) - dj;
+                    const float v = ra == 0 ? (rb == 0 ? c00 : rb == 1 ? c01 : 0.0f)
+                                  : ra == 1 ? (rb == 0 ? c10 : rb == 1 ? c11 : 0.0f)
+                                            : 0.0f;
+                    w[k][e] += v;
+                }
+            }
+        }
     }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) flush(k);
 }
 
 }  // namespace
 
-size_t adjoint_sample_bytes(int64_t n, int n_iter) {
-    return (size_t)adj::gca_vjp_samples(n_iter) * (size_t)n * (2 * sizeof(double) + 12 * sizeof(float));
+int adjoint_slots(int n_iter) { return adj::gca_vjp_samples(n_iter); }
+
+size_t adjoint_record_bytes(int64_t n, int n_iter, int steps) {
+    return (size_t)steps * adjoint_slots(n_iter) * (size_t)n *
+           (2 * sizeof(double) + 12 * sizeof(float));
 }
+
+namespace {
+struct RecordArrays {
+    double* X;
+    double* Y;
+    float* bar;
+};
+
+RecordArrays record_arrays(void* records, int64_t n, int slots, int batch) {
+    RecordArrays r;
+    r.X = static_cast<double*>(records);
+    r.Y = r.X + (size_t)batch * slots * n;
+    r.bar = reinterpret_cast<float*>(r.Y + (size_t)batch * slots * n);
+    return r;
+}
+}  // namespace
 
 hipError_t launch_adjoint_step(const AdjointLaunch& L, double* lam, const PushConst& pc,
                                hipStream_t stream) {
     if (L.n == 0) return hipSuccess;
-    const int slots = adj::gca_vjp_samples(pc.n_iter);
-    double* X = static_cast<double*>(L.samples);
-    double* Y = X + (size_t)slots * L.n;
-    float* bar = reinterpret_cast<float*>(Y + (size_t)slots * L.n);
-    const RecordSink rec{X, Y, bar, L.n, 0, 0};
+    const int slots = adjoint_slots(pc.n_iter);
+    const RecordArrays ra = record_arrays(L.records, L.n, slots, L.batch);
+    const size_t off = (size_t)L.batch_slot * slots * L.n;
+    const RecordSink rec{ra.X + off, ra.Y + off, ra.bar + 12 * off, L.n, 0, 0};
     const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
-    const unsigned sblocks = (unsigned)((L.n + kScatterWG - 1) / kScatterWG);
     if (L.yee) {
         hipLaunchKernelGGL((k_adjoint_step<true, false>), dim3(blocks), dim3(kWG), 0, stream,
                            L.state, L.qm, L.strace, lam, L.n, L.fields, pc, rec);
         hipLaunchKernelGGL((k_adjoint_step<true, true>), dim3(blocks), dim3(kWG), 0, stream,
                            L.state, L.qm, L.strace, lam, L.n, L.fields, pc, rec);
-        hipLaunchKernelGGL((k_scatter_samples<true>), dim3(sblocks), dim3(kScatterWG), 0,
-                           stream, X, Y, bar, L.strace, L.n, slots, pc, L.grad_fields);
     } else {
         hipLaunchKernelGGL((k_adjoint_step<false, false>), dim3(blocks), dim3(kWG), 0, stream,
                            L.state, L.qm, L.strace, lam, L.n, L.fields, pc, rec);
         hipLaunchKernelGGL((k_adjoint_step<false, true>), dim3(blocks), dim3(kWG), 0, stream,
                            L.state, L.qm, L.strace, lam, L.n, L.fields, pc, rec);
-        hipLaunchKernelGGL((k_scatter_samples<false>), dim3(sblocks), dim3(kScatterWG), 0,
-                           stream, X, Y, bar, L.strace, L.n, slots, pc, L.grad_fields);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_scatter(const AdjointLaunch& L, const uint8_t* strace_first, int nb,
+                                  const PushConst& pc, hipStream_t stream) {
+    if (L.n == 0 || nb <= 0) return hipSuccess;
+    const int slots = adjoint_slots(pc.n_iter);
+    const RecordArrays ra = record_arrays(L.records, L.n, slots, L.batch);
+    const unsigned blocks = (unsigned)((L.n + kScatterWG - 1) / kScatterWG);
+    if (L.yee)
+        hipLaunchKernelGGL((k_scatter_batch<true>), dim3(blocks), dim3(kScatterWG), 0, stream,
+                           ra.X, ra.Y, ra.bar, strace_first, L.n, nb, slots, pc,
+                           L.grad_fields);
+    else
+        hipLaunchKernelGGL((k_scatter_batch<false>), dim3(blocks), dim3(kScatterWG), 0, stream,
+                           ra.X, ra.Y, ra.bar, strace_first, L.n, nb, slots, pc,
+                           L.grad_fields);
     return hipGetLastError();
 }
 

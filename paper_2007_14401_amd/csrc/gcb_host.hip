@@ -535,7 +535,14 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
     if ((rc = ensure(ctx, ctx->adj_lam, 7 * nd))) return rc;
     if ((rc = ensure(ctx, ctx->adj_work, 7 * nd + (size_t)n))) return rc;
     if ((rc = ensure(ctx, ctx->adj_grad, nodes * 6 * sizeof(float)))) return rc;
-    if ((rc = ensure(ctx, ctx->adj_samples, adjoint_sample_bytes(n, prm->n_iter)))) return rc;
+    // gather-point records of up to kMaxBatch steps, within kRecordBudget
+    constexpr int kMaxBatch = 8;
+    constexpr size_t kRecordBudget = 32ull << 30;
+    const size_t per_step = adjoint_record_bytes(n, prm->n_iter, 1);
+    int batch = per_step > 0 ? (int)std::min<size_t>(kMaxBatch, kRecordBudget / per_step) : 1;
+    batch = std::max(1, std::min(batch, std::max(1, (int)n_steps)));
+    if ((rc = ensure(ctx, ctx->adj_samples, adjoint_record_bytes(n, prm->n_iter, batch))))
+        return rc;
     double* work = static_cast<double*>(ctx->adj_work.ptr);
     uint8_t* wstatus = reinterpret_cast<uint8_t*>(work + 7 * (size_t)n);
     double* states = static_cast<double*>(ctx->adj_states.ptr);
@@ -586,17 +593,25 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
         GCB_HIP(hipMemcpyAsync(lam + c * (size_t)n, lam_end[c], nd, hipMemcpyDeviceToDevice,
                                stream));
     GCB_HIP(hipMemsetAsync(grad, 0, nodes * 6 * sizeof(float), stream));
-    for (int32_t s = n_steps - 1; s >= 0 && n > 0; --s) {
+    // steps in reverse order, in batches [s_lo, s_hi) of at most `batch` steps:
+    // the vector-Jacobian products of the batch's steps, then one scatter
+    for (int32_t s_hi = n_steps; s_hi > 0 && n > 0; s_hi -= batch) {
+        const int32_t s_lo = std::max<int32_t>(0, s_hi - batch);
         AdjointLaunch A;
         A.yee = ctx->yee;
         A.fields = static_cast<const double*>(ctx->fields.ptr);
         A.n = n;
-        A.state = states + (size_t)s * 7 * n;
         A.qm = start->qm;
-        A.strace = trace + (size_t)s * n;
         A.grad_fields = grad;
-        A.samples = ctx->adj_samples.ptr;
-        GCB_HIP(launch_adjoint_step(A, lam, pc, stream));
+        A.records = ctx->adj_samples.ptr;
+        A.batch = batch;
+        for (int32_t s = s_hi - 1; s >= s_lo; --s) {
+            A.state = states + (size_t)s * 7 * n;
+            A.strace = trace + (size_t)s * n;
+            A.batch_slot = s - s_lo;
+            GCB_HIP(launch_adjoint_step(A, lam, pc, stream));
+        }
+        GCB_HIP(launch_adjoint_scatter(A, trace + (size_t)s_lo * n, s_hi - s_lo, pc, stream));
     }
     for (int c = 0; c < 7 && n > 0; ++c)
         GCB_HIP(hipMemcpyAsync(lam_start[c], lam + c * (size_t)n, nd, hipMemcpyDeviceToDevice,

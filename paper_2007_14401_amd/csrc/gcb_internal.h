@@ -99,17 +99,30 @@ struct AdjointLaunch {
     bool yee;
     const double* fields;   // node-interleaved binary64
     int64_t n;
-    const double* state;    // per-step saved states: 7 arrays of n (x,y,xp,yp,ux,uy,uz)
+    const double* state;    // the step's saved start state: 7 arrays of n (x,y,xp,yp,ux,uy,uz)
     const double* qm;       // nullable
     const uint8_t* strace;  // per-particle S of this step (1 = Boris)
     float* grad_fields;     // node-interleaved float gradient accumulators
-    void* samples;          // adjoint_sample_bytes(n, n_iter) of scratch
+    void* records;          // adjoint_record_bytes(n, n_iter, batch) of scratch
+    int batch;              // steps whose gather points the records hold
+    int batch_slot;         // this step's place in the batch
 };
 
-size_t adjoint_sample_bytes(int64_t n, int n_iter);
+// gather points recorded per particle and guiding-center step
+int adjoint_slots(int n_iter);
+size_t adjoint_record_bytes(int64_t n, int n_iter, int steps);
 
+// One step of the reverse sweep: lam (7*n, in/out) from the cotangents of
+// the step's outputs to those of its inputs; the step's gather points go to
+// batch slot L.batch_slot of the records.
 hipError_t launch_adjoint_step(const AdjointLaunch& L, double* lam /*7*n in/out*/,
                                const PushConst& pc, hipStream_t stream);
+
+// Node cotangents of the first nb batch slots into L.grad_fields; strace_first
+// is the switch trace of the step in slot 0 (the later slots follow at
+// strides of n).
+hipError_t launch_adjoint_scatter(const AdjointLaunch& L, const uint8_t* strace_first, int nb,
+                                  const PushConst& pc, hipStream_t stream);
 
 hipError_t launch_deinterleave_add(const float* grad_fields, int nx, int ny,
                                    float* const out[6], hipStream_t stream);
