@@ -26,20 +26,21 @@ GCB_HD int mul24(int a, int b) {
 #endif
 }
 
-// Loader of the LDS window: node (0,0) of each weight set at off[set].
+// Loader of the LDS window (component planes of W x W nodes): node (0,0) of
+// each weight set at element off[set] of a plane.
 template <typename T>
 struct LdsLoad {
     const T* lds;
     const int* off;
-    int W6;
+    int W, WW;
     template <typename R>
     GCB_HD void load4(int set, int k, R& f00, R& f10, R& f01,
                                           R& f11) const {
-        const T* p = lds + off[set] + k;
+        const T* p = lds + mul24(k, WW) + off[set];
         f00 = (R)p[0];
-        f10 = (R)p[6];
-        f01 = (R)p[W6];
-        f11 = (R)p[W6 + 6];
+        f10 = (R)p[1];
+        f01 = (R)p[W];
+        f11 = (R)p[W + 1];
     }
 };
 
@@ -113,8 +114,12 @@ struct GlobalLoad {
 };
 
 // W x W nodes of all six components staged in LDS, covering global nodes
-// [oi, oi + W) x [oj, oj + W) (periodic).  A stencil that does not fit in the
-// window is read from global memory instead (same values) and noted in `miss`.
+// [oi, oi + W) x [oj, oj + W) (periodic), one plane per component
+// (lds[(k*W + j)*W + i]): the lanes of a wavefront gather at scattered nodes,
+// and in component planes neighbouring nodes sit in neighbouring banks, where
+// the 6-value node records of the global layout would fold them onto a
+// quarter of the banks.  A stencil that does not fit in the window is read
+// from global memory instead (same values) and noted in `miss`.
 template <typename T>
 struct TileAcc {
     const T* lds;
@@ -130,11 +135,11 @@ struct TileAcc {
         if ((unsigned)di >= lim) di += (di < 0) ? nx : -nx;
         if ((unsigned)dj >= lim) dj += (dj < 0) ? ny : -ny;
         if ((unsigned)di < lim && (unsigned)dj < lim) {
-            const T* r0 = lds + (dj * W + di) * 6 + k;
+            const T* r0 = lds + (k * W + dj) * W + di;
             f00 = (double)r0[0];
-            f10 = (double)r0[6];
-            f01 = (double)r0[W * 6];
-            f11 = (double)r0[W * 6 + 6];
+            f10 = (double)r0[1];
+            f01 = (double)r0[W];
+            f11 = (double)r0[W + 1];
         } else {
             miss = true;
             GlobalAcc<T> g{F, nx, ny};
@@ -158,11 +163,10 @@ struct TileAcc {
         const bool in = (unsigned)sa <= 1u && (unsigned)sb <= 1u && db >= 0 && eb >= 0 &&
                         da <= W - 2 && ea <= W - 2;
         if (in) {
-            const int W6 = W * 6;
-            off[0] = mul24(ea, W6) + mul24(da, 6);
-            off[1] = mul24(ea, W6) + mul24(db, 6);
-            off[2] = mul24(eb, W6) + mul24(da, 6);
-            off[3] = mul24(eb, W6) + mul24(db, 6);
+            off[0] = mul24(ea, W) + da;
+            off[1] = mul24(ea, W) + db;
+            off[2] = mul24(eb, W) + da;
+            off[3] = mul24(eb, W) + db;
         } else {
             miss = true;
             GlobalAcc<T> gl{F, nx, ny};

@@ -136,7 +136,7 @@ GCB_HD void yee_fetch(const TileAcc<T>& acc, int ia, int ib, int ja,
     int off[4];
     typename GlobalAcc<T>::Loc g;
     if (acc.locate(ia, ib, ja, jb, off, g))
-        interp_yee<R, kGrad>(LdsLoad<T>{acc.lds, off, acc.W * 6}, wx, wy, K, s);
+        interp_yee<R, kGrad>(LdsLoad<T>{acc.lds, off, acc.W, acc.W * acc.W}, wx, wy, K, s);
     else
         interp_yee<R, kGrad>(GlobalLoad<T>{g}, wx, wy, K, s);
 }

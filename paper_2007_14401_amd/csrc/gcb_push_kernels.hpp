@@ -156,16 +156,16 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict_
     const int oi = tx * g.tile - g.halo;
     const int oj = ty * g.tile - g.halo;
 
-    // stage the window: one row (W records of 6 values) per wave iteration
+    // stage the window: one row (W records of 6 values, read contiguously)
+    // per wave iteration, written to the six component planes
     for (int rr = wave; rr < W; rr += kWG / 64) {
         const int gj = wrap_index(oj + rr, pc.ny);
         const T* grow = F + (size_t)gj * pc.nx * 6;
-        T* lrow = lds + (size_t)rr * W * 6;
         for (int e = lane; e < W * 6; e += 64) {
             const int c = e / 6;
             const int k = e - c * 6;
             const int gi = wrap_index(oi + c, pc.nx);
-            lrow[e] = grow[gi * 6 + k];
+            lds[(k * W + rr) * W + c] = grow[gi * 6 + k];
         }
     }
     __syncthreads();
