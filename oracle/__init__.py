@@ -18,6 +18,11 @@ Layout of the oracle:
               scheme (Sec. 3.1) and the multi-step driver.
   loss.py     mean kinetic energy and its gradient by reverse-mode autograd of
               the oracle itself (the oracle gradient of the adjoint checks).
+  gr.py       the general-relativistic coupled scheme (Sec. 2.3, 2.4, 3.2) in
+              Kerr-Schild coordinates: metric functions and derivatives, the
+              (r, theta) grid gather, the local-frame half pushes, the
+              implicit-midpoint geodesic iterations, the guiding-center step,
+              the switch with the proper cell length, and the driver.
 
 All arithmetic is IEEE binary64 with correctly rounded +, -, *, /, sqrt and
 no fused multiply-add: every product and sum is a separate torch operation.

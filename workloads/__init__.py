@@ -15,9 +15,12 @@ from .harris import YEE_STAGGER, COLLOCATED, COMPONENTS, harris_fields
 from .particles import (maxwell_juttner_u, power_law_gamma, isotropic_dirs,
                         initial_state, Ensemble)
 from .configs import CONFIGS, make_config, Config
+from .gr import (GR_CONFIGS, GRConfig, GREnsemble, make_gr_config, magnetosphere_fields,
+                 magnetosphere_particles)
 
 __all__ = [
     "YEE_STAGGER", "COLLOCATED", "COMPONENTS", "harris_fields",
     "maxwell_juttner_u", "power_law_gamma", "isotropic_dirs", "initial_state",
-    "Ensemble", "CONFIGS", "make_config", "Config",
+    "Ensemble", "CONFIGS", "make_config", "Config", "GR_CONFIGS", "GRConfig",
+    "GREnsemble", "make_gr_config", "magnetosphere_fields", "magnetosphere_particles",
 ]
