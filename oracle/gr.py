@@ -135,7 +135,9 @@ class KerrSchild:
         m.alpha = 1.0 / sq
         m.beta_r = z / opz
         m.gu_rr = 1.0 / opz + (a2 * s2) / rho2
-        m.gu_rph = a / rho2
+        # torch divides a float by a tensor as reciprocal-then-multiply (two
+        # roundings); a tensor numerator gives the IEEE quotient
+        m.gu_rph = torch.full_like(rho2, a) / rho2
         m.gu_thth = 1.0 / rho2
         m.gu_phph = 1.0 / (rho2 * s2)
         m.gd_rr = opz
@@ -217,9 +219,12 @@ class GRGrid:
         self.inv_dth = 1.0 / self.dth
 
     def cell(self, r, th):
-        """Clamped cell indices and weights of points (r, theta)."""
+        """Clamped cell indices and weights of points (r, theta); a NaN
+        coordinate is taken at the lower edge."""
         rc = torch.clamp(r, self.r_min, self.r_max)
         tc = torch.clamp(th, 0.0, math.pi)
+        rc = torch.where(torch.isnan(rc), self.r_min, rc)
+        tc = torch.where(torch.isnan(tc), 0.0, tc)
         xi = (rc - self.r_min) * self.inv_dr
         eta = tc * self.inv_dth
         i = torch.clamp(torch.floor(xi), max=self.nr - 1)
