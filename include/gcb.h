@@ -76,6 +76,8 @@ extern "C" {
 #define GCB_ST_FPRES    16    /* last fixed-point increment |R^K - R^{K-1}| > fp_tol      */
 #define GCB_ST_HALO     32    /* informational: a gather fell outside the LDS tile window
                                  and was served from global memory (same values)         */
+#define GCB_ST_OUT      64    /* curved-spacetime push: the particle left the (r, theta)
+                                 domain and is no longer advanced                        */
 
 typedef struct gcb_ctx gcb_ctx;
 
@@ -192,6 +194,65 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start,
 int gcb_kinetic_energy(gcb_ctx* ctx, const gcb_particles* p,
                        const gcb_params* prm, double* out,
                        double* const lam_u[3], void* stream);
+
+/* ---------------------------------------------------------------------------
+   Curved spacetime (Sec. 2.3, 2.4, 3.2): the coupled scheme in Kerr
+   spacetime (M = 1, spin a) in spherical Kerr-Schild coordinates, geometrized
+   units (c = G = 1).  The fields are axisymmetric and static.
+
+   Grid: D^i and B^i (contravariant components along r, theta, phi) on the
+   nodes r = r_min + i dr, theta = j dth of a uniform grid, i in [0, nr],
+   j in [0, nth], dr = (r_max - r_min)/nr, dth = pi/nth, all six components
+   at the nodes, gathered with the linear shape function (bilinear in r and
+   theta; points beyond the grid take the value at its nearest edge).  The
+   cell length of the switch is dl = sqrt(proper area of the particle's cell)
+   (Sec. 3, eq. volint over the (r, theta) 2-metric; 2 x 2 Gauss-Legendre). */
+typedef struct {
+    int32_t nr, nth;        /* cells along r and theta, >= 1 */
+    double  r_min, r_max;   /* 0 < r_min < r_max */
+    double  spin;           /* Kerr a, |a| < 1 */
+    int32_t dtype;          /* GCB_F64 */
+} gcb_gr_desc;
+
+/* Load D[3] = (D^r, D^th, D^ph) and B[3] = (B^r, B^th, B^ph): each an array
+   of (nth+1)*(nr+1) doubles, element [j*(nr+1) + i] at node (i, j), host
+   (GCB_HOST) or device (GCB_DEVICE) memory, caller-owned.  Builds the
+   node-interleaved device copy and the table of cell lengths.  Replaces
+   earlier curved-spacetime fields; the flat-space fields are independent. */
+int gcb_load_fields_gr(gcb_ctx* ctx, const gcb_gr_desc* desc,
+                       const double* const D[3], const double* const B[3],
+                       int32_t src, void* stream);
+
+/* Particle state of the curved-spacetime push, structure of arrays,
+   caller-owned device memory of length n: position x^i = (r, theta, phi) and
+   covariant four-velocity u_i at the same time level (Sec. 3.2, not
+   staggered).  Updated in place, never reordered; phi is kept in [0, 2 pi). */
+typedef struct {
+    int64_t  n;
+    double  *r, *th, *ph;
+    double  *ur, *uth, *uph;
+    double  *qm;            /* optional per-particle q/m (NULL: params.qm) */
+    uint8_t *status;        /* required: sticky GCB_ST_* bits */
+} gcb_gr_particles;
+
+/* Advance by n_steps coupled steps (Sec. 3.2): per particle and step, the
+   switch at x^n with Gamma of the full u (guiding center iff B > 0,
+   Gamma/(|q/m| B dl) < f_rho and D/B < f_E), then either the full-orbit step
+   of Sec. 2.3 (half Lorentz push in the local frame of the normal observer,
+   implicit-midpoint geodesic update by n_iter fixed-point iterations, half
+   push) or the guiding-center step of Sec. 2.4 (half parallel push,
+   implicit-midpoint update of (R, u_par) by n_iter iterations, half push,
+   u rebuilt at R^{n+1} with the gyration direction of the step start).
+   Reads dt, qm, f_rho, f_E, fp_tol, n_iter of params (c is 1 here; form must
+   be GCB_FORM_F64; replay must be 0; the other fields are ignored).
+   A particle whose new position leaves r_min <= r < r_max, 0 <= theta <= pi
+   gets GCB_ST_OUT and keeps its state from then on.
+   s_trace (nullable, device, n_steps*n bytes): s_trace[step*n + k] = 0
+   (guiding center), 1 (full orbit) or 2 (not advanced) for array slot k.
+   stats (nullable, host): as for gcb_push; max_fp_residual covers both
+   branches (both iterate); flagged counts GCB_ST_OUT too. */
+int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm,
+                int32_t n_steps, uint8_t* s_trace, gcb_stats* stats, void* stream);
 
 /* Kernel timing with HIP events recorded around every launch on the launch
    stream.  gcb_set_timing(ctx, 1) clears and enables; gcb_get_timing

@@ -31,6 +31,7 @@ UNITS = {
     "gcb_push_mixed.hip": [],
     "gcb_sort.hip": ["-ffp-contract=off"],
     "gcb_util.hip": ["-ffp-contract=off"],
+    "gcb_gr.hip": ["-ffp-contract=off"],
 }
 
 

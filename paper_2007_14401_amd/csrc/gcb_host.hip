@@ -40,6 +40,11 @@ struct gcb_ctx {
     int dtype = GCB_F64;
     bool yee = false;
     DevBuf fields;
+    // curved-spacetime fields
+    bool have_gr = false;
+    gr::GrConst gr{};
+    double gr_dr = 0.0, gr_dth = 0.0;
+    DevBuf gr_fields, gr_dl;
     // scratch
     DevBuf sort_keys, sort_idx, sort_keys2, sort_idx2, sort_hist, sort_scan, tile_start;
     DevBuf pscratch;     // sorted copy of the particle state
@@ -374,7 +379,7 @@ void gcb_destroy(gcb_ctx* ctx) {
                       &ctx->sort_idx2,  &ctx->sort_hist,  &ctx->sort_scan,
                       &ctx->tile_start, &ctx->pscratch,   &ctx->stats,     &ctx->ke_partial,
                       &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace,
-                      &ctx->adj_work,   &ctx->adj_samples};
+                      &ctx->adj_work,   &ctx->adj_samples, &ctx->gr_fields, &ctx->gr_dl};
     for (DevBuf* b : bufs) release(*b);
     delete ctx;
 }
@@ -623,6 +628,140 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
     float* const outs[6] = {dE[0], dE[1], dE[2], dB[0], dB[1], dB[2]};
     GCB_HIP(launch_deinterleave_add(grad, ctx->nx, ctx->ny, outs, stream));
     t.done();
+    return GCB_OK;
+}
+
+int gcb_load_fields_gr(gcb_ctx* ctx, const gcb_gr_desc* d, const double* const D[3],
+                       const double* const B[3], int32_t src, void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    if (!d || !D || !B) return fail(ctx, GCB_EINVAL, "desc, D and B must be non-NULL");
+    if (d->nr < 1 || d->nth < 1) return fail(ctx, GCB_EINVAL, "nr and nth must be >= 1");
+    if ((int64_t)(d->nr + 1) * (d->nth + 1) * 6 >= ((int64_t)1 << 34))
+        return fail(ctx, GCB_EINVAL, "grid too large");
+    if (!(std::isfinite(d->r_min) && std::isfinite(d->r_max) && d->r_min > 0.0 &&
+          d->r_max > d->r_min))
+        return fail(ctx, GCB_EINVAL, "need 0 < r_min < r_max (finite)");
+    if (!(std::fabs(d->spin) < 1.0)) return fail(ctx, GCB_EINVAL, "need |spin| < 1");
+    if (d->dtype != GCB_F64) return fail(ctx, GCB_EUNSUPPORTED, "curved-spacetime fields are GCB_F64");
+    if (src != GCB_HOST && src != GCB_DEVICE)
+        return fail(ctx, GCB_EINVAL, "src must be GCB_HOST or GCB_DEVICE");
+    const double* comps[6] = {D[0], D[1], D[2], B[0], B[1], B[2]};
+    for (int k = 0; k < 6; ++k)
+        if (!comps[k]) return fail(ctx, GCB_EINVAL, "field component %d is NULL", k);
+    GCB_HIP(hipSetDevice(ctx->device));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const int nxn = d->nr + 1, nyn = d->nth + 1;
+    const int64_t nodes = (int64_t)nxn * nyn;
+    ctx->have_gr = false;
+    int rc = ensure(ctx, ctx->gr_fields, (size_t)nodes * 6 * sizeof(double));
+    if (rc) return rc;
+    if ((rc = ensure(ctx, ctx->gr_dl, (size_t)d->nr * d->nth * sizeof(double)))) return rc;
+    if (src == GCB_HOST) {
+        DevBuf tmp;
+        rc = ensure(ctx, tmp, (size_t)nodes * 6 * sizeof(double));
+        if (rc) return rc;
+        const double* dcomps[6];
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < 6 && e == hipSuccess; ++k) {
+            double* dst = static_cast<double*>(tmp.ptr) + k * nodes;
+            e = hipMemcpyAsync(dst, comps[k], nodes * sizeof(double), hipMemcpyHostToDevice,
+                               stream);
+            dcomps[k] = dst;
+        }
+        if (e == hipSuccess)
+            e = launch_interleave_fields(dcomps, nxn, nyn, ctx->gr_fields.ptr, false, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        release(tmp);
+        if (e != hipSuccess)
+            return fail(ctx, GCB_EHIP, "field conversion: %s", hipGetErrorString(e));
+    } else {
+        GCB_HIP(launch_interleave_fields(comps, nxn, nyn, ctx->gr_fields.ptr, false, stream));
+    }
+    gr::GrConst g{};
+    g.a = d->spin;
+    g.r_min = d->r_min;
+    g.r_max = d->r_max;
+    g.nr = d->nr;
+    g.nth = d->nth;
+    const double dr = (d->r_max - d->r_min) / d->nr;
+    const double dth = gr::kPi / d->nth;
+    g.inv_dr = 1.0 / dr;
+    g.inv_dth = 1.0 / dth;
+    GCB_HIP(launch_gr_cell_lengths(g, dr, dth, static_cast<double*>(ctx->gr_dl.ptr), stream));
+    ctx->gr = g;
+    ctx->gr_dr = dr;
+    ctx->gr_dth = dth;
+    ctx->have_gr = true;
+    return GCB_OK;
+}
+
+int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_t n_steps,
+                uint8_t* s_trace, gcb_stats* stats, void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    if (!prm) return fail(ctx, GCB_EINVAL, "params is NULL");
+    if (!p) return fail(ctx, GCB_EINVAL, "particles is NULL");
+    if (!finite_pos(prm->dt)) return fail(ctx, GCB_EINVAL, "dt must be finite and > 0");
+    if (!(prm->f_rho >= 0.0) || !(prm->f_E >= 0.0))
+        return fail(ctx, GCB_EINVAL, "f_rho and f_E must be >= 0");
+    if (!(prm->fp_tol >= 0.0)) return fail(ctx, GCB_EINVAL, "fp_tol must be >= 0");
+    if (prm->n_iter < 1 || prm->n_iter > 64)
+        return fail(ctx, GCB_EINVAL, "n_iter must be in [1, 64]");
+    if (prm->form != GCB_FORM_F64)
+        return fail(ctx, GCB_EUNSUPPORTED, "the curved-spacetime push is GCB_FORM_F64");
+    if (prm->replay) return fail(ctx, GCB_EUNSUPPORTED, "replay is not supported here");
+    if (p->n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");
+    if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
+    if (p->n > 0 && (!p->r || !p->th || !p->ph || !p->ur || !p->uth || !p->uph || !p->status))
+        return fail(ctx, GCB_EINVAL, "particle arrays must be non-NULL");
+    if (p->n > 0 && !p->qm && !(std::isfinite(prm->qm) && prm->qm != 0.0))
+        return fail(ctx, GCB_EINVAL, "params.qm must be finite and non-zero");
+    if (!ctx->have_gr) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields_gr was not called");
+    GCB_HIP(hipSetDevice(ctx->device));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    DevStats* dstats = nullptr;
+    constexpr size_t kStatBytes = kStatSlots * sizeof(DevStats) + sizeof(DevStats);
+    if (stats) {
+        int rc;
+        if ((rc = ensure(ctx, ctx->stats, kStatBytes))) return rc;
+        dstats = static_cast<DevStats*>(ctx->stats.ptr);
+        GCB_HIP(hipMemsetAsync(dstats, 0, kStatBytes, stream));
+    }
+    gr::GrConst g = ctx->gr;
+    g.dt = prm->dt;
+    g.qm = prm->qm;
+    g.f_rho = prm->f_rho;
+    g.f_E = prm->f_E;
+    g.fp_tol = prm->fp_tol;
+    g.n_iter = prm->n_iter;
+    GrPtrs ptrs{p->r, p->th, p->ph, p->ur, p->uth, p->uph, p->qm, p->status};
+    {
+        Timer t(ctx, stream, GCB_TIMER_PUSH);
+        GCB_HIP(launch_gr_push(ptrs, p->n, n_steps, static_cast<const double*>(ctx->gr_fields.ptr),
+                               static_cast<const double*>(ctx->gr_dl.ptr), g, s_trace, dstats,
+                               stream));
+        t.done();
+    }
+    if (stats) {
+        unsigned long long* flagged = reinterpret_cast<unsigned long long*>(dstats + kStatSlots);
+        GCB_HIP(launch_count_flagged(p->status, p->n, flagged, stream));
+        std::vector<DevStats> host(kStatSlots + 1);
+        GCB_HIP(hipMemcpyAsync(host.data(), ctx->stats.ptr, kStatBytes, hipMemcpyDeviceToHost,
+                               stream));
+        GCB_HIP(hipStreamSynchronize(stream));
+        unsigned long long gsum = 0, bsum = 0, mbits = 0;
+        for (int s = 0; s < kStatSlots; ++s) {
+            gsum += host[s].gca_steps;
+            bsum += host[s].boris_steps;
+            mbits = host[s].max_res_bits > mbits ? host[s].max_res_bits : mbits;
+        }
+        stats->gca_steps = (int64_t)gsum;
+        stats->boris_steps = (int64_t)bsum;
+        stats->halo_misses = 0;
+        double m;
+        std::memcpy(&m, &mbits, sizeof(m));
+        stats->max_fp_residual = m;
+        stats->flagged = (int64_t)host[kStatSlots].gca_steps;
+    }
     return GCB_OK;
 }
 

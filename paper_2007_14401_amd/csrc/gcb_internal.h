@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "gcb_common.hpp"
+#include "gcb_gr.hpp"
 
 namespace gcb {
 
@@ -126,5 +127,19 @@ hipError_t launch_adjoint_scatter(const AdjointLaunch& L, const uint8_t* strace_
 
 hipError_t launch_deinterleave_add(const float* grad_fields, int nx, int ny,
                                    float* const out[6], hipStream_t stream);
+
+// curved-spacetime push (gcb_gr.hip)
+struct GrPtrs {
+    double *r, *th, *ph;
+    double *ur, *uth, *uph;
+    const double* qm;   // nullable
+    uint8_t* status;
+};
+
+hipError_t launch_gr_cell_lengths(const gr::GrConst& g, double dr, double dth, double* dl,
+                                  hipStream_t stream);
+hipError_t launch_gr_push(const GrPtrs& p, int64_t n, int n_steps, const double* F,
+                          const double* dl, const gr::GrConst& g, uint8_t* trace,
+                          DevStats* stats, hipStream_t stream);
 
 }  // namespace gcb

@@ -22,6 +22,7 @@ GCB_FORM_F64, GCB_FORM_MIXED = 0, 1
 GCB_HOST, GCB_DEVICE = 0, 1
 GCB_KERNEL_AUTO, GCB_KERNEL_GLOBAL, GCB_KERNEL_TILED = 0, 1, 2
 GCB_ST_NONFINITE, GCB_ST_KAPPA, GCB_ST_QUAD, GCB_ST_BZERO, GCB_ST_FPRES, GCB_ST_HALO = 1, 2, 4, 8, 16, 32
+GCB_ST_OUT = 64
 GCB_TIMER_PUSH, GCB_TIMER_SORT, GCB_TIMER_BACKWARD, GCB_TIMER_OTHER = 0, 1, 2, 3
 GCB_NTIMERS = 4
 
@@ -61,6 +62,17 @@ class gcb_stats(C.Structure):
                 ("max_fp_residual", C.c_double)]
 
 
+class gcb_gr_desc(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nth", C.c_int32), ("r_min", C.c_double),
+                ("r_max", C.c_double), ("spin", C.c_double), ("dtype", C.c_int32)]
+
+
+class gcb_gr_particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("r", C.c_void_p), ("th", C.c_void_p), ("ph", C.c_void_p),
+                ("ur", C.c_void_p), ("uth", C.c_void_p), ("uph", C.c_void_p),
+                ("qm", C.c_void_p), ("status", C.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -80,6 +92,10 @@ def _load():
                                         C.POINTER(P * 3), C.POINTER(P * 3), P]),
         "gcb_kinetic_energy": (C.c_int, [P, C.POINTER(gcb_particles), C.POINTER(gcb_params),
                                          P, C.POINTER(P * 3), P]),
+        "gcb_load_fields_gr": (C.c_int, [P, C.POINTER(gcb_gr_desc), C.POINTER(P * 3),
+                                         C.POINTER(P * 3), C.c_int32, P]),
+        "gcb_push_gr": (C.c_int, [P, C.POINTER(gcb_gr_particles), C.POINTER(gcb_params),
+                                  C.c_int32, P, C.POINTER(gcb_stats), P]),
         "gcb_set_timing": (C.c_int, [P, C.c_int32]),
         "gcb_get_timing": (C.c_int, [P, C.POINTER(C.c_double * GCB_NTIMERS),
                                      C.POINTER(C.c_int64 * GCB_NTIMERS)]),
@@ -93,7 +109,8 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("gcb_create", "gcb_destroy", "gcb_last_error", "gcb_load_fields", "gcb_push",
-            "gcb_push_backward", "gcb_kinetic_energy", "gcb_set_timing", "gcb_get_timing")
+            "gcb_push_backward", "gcb_kinetic_energy", "gcb_set_timing", "gcb_get_timing",
+            "gcb_load_fields_gr", "gcb_push_gr")
 
 
 def lib():
@@ -215,6 +232,49 @@ def gcb_kinetic_energy(ctx, parts: gcb_particles, prm: gcb_params, out, lam_u=No
     _check(_lib.gcb_kinetic_energy(ctx, C.byref(parts), C.byref(prm), _ptr(out),
                                    C.byref(lu) if lu is not None else None,
                                    _stream_ptr(stream)), ctx)
+
+
+def gr_desc(nr, nth, r_min, r_max, spin, dtype=GCB_F64) -> gcb_gr_desc:
+    d = gcb_gr_desc()
+    d.nr, d.nth, d.r_min, d.r_max, d.spin, d.dtype = (int(nr), int(nth), float(r_min),
+                                                      float(r_max), float(spin), int(dtype))
+    return d
+
+
+def gcb_load_fields_gr(ctx, desc: gcb_gr_desc, D, B, src=None, stream=None) -> None:
+    """D, B: sequences of three (nth+1, nr+1) float64 arrays (numpy host or torch device)."""
+    if src is None:
+        src = GCB_HOST if isinstance(D[0], np.ndarray) else GCB_DEVICE
+    for a in list(D) + list(B):
+        if isinstance(a, np.ndarray):
+            assert a.dtype == np.float64 and a.flags.c_contiguous
+    Da = (C.c_void_p * 3)(*[_ptr(a) for a in D])
+    Ba = (C.c_void_p * 3)(*[_ptr(a) for a in B])
+    sp = None if src == GCB_HOST and stream is None else _stream_ptr(stream)
+    _check(_lib.gcb_load_fields_gr(ctx, C.byref(desc), C.byref(Da), C.byref(Ba), int(src), sp),
+           ctx)
+
+
+def gr_particles(t: dict) -> gcb_gr_particles:
+    """Build the struct from a dict of tensors r, th, ph, ur, uth, uph, status
+    and optional qm."""
+    p = gcb_gr_particles()
+    p.n = int(t["r"].shape[0])
+    for k in ("r", "th", "ph", "ur", "uth", "uph", "status"):
+        setattr(p, k, _ptr(t[k]))
+    p.qm = _ptr(t.get("qm"))
+    return p
+
+
+def gcb_push_gr(ctx, parts: gcb_gr_particles, prm: gcb_params, n_steps: int, s_trace=None,
+                want_stats: bool = False, stream=None):
+    st = gcb_stats() if want_stats else None
+    rc = _lib.gcb_push_gr(ctx, C.byref(parts), C.byref(prm), int(n_steps), _ptr(s_trace),
+                          C.byref(st) if st is not None else None, _stream_ptr(stream))
+    _check(rc, ctx)
+    if st is None:
+        return None
+    return {k: getattr(st, k) for k, _ in gcb_stats._fields_}
 
 
 def gcb_set_timing(ctx, enabled: bool) -> None:

@@ -42,6 +42,8 @@ def test_null_arguments_rejected_without_device():
         gcb.GCB_EINVAL, gcb.GCB_EUNSUPPORTED)
     assert lib.gcb_kinetic_energy(None, None, None, None, None, None) == gcb.GCB_EINVAL
     assert lib.gcb_set_timing(None, 1) == gcb.GCB_EINVAL
+    assert lib.gcb_load_fields_gr(None, None, None, None, 0, None) == gcb.GCB_EINVAL
+    assert lib.gcb_push_gr(None, None, None, 1, None, None, None) == gcb.GCB_EINVAL
     lib.gcb_destroy(None)
 
 
@@ -62,3 +64,5 @@ def test_params_struct_layout_matches_header():
     assert C.sizeof(gcb.gcb_particles) == 8 + 10 * 8
     assert C.sizeof(gcb.gcb_grid_desc) == 4 + 4 + 8 + 8 + 96 + 8
     assert C.sizeof(gcb.gcb_stats) == 5 * 8
+    assert C.sizeof(gcb.gcb_gr_desc) == 4 + 4 + 3 * 8 + 8
+    assert C.sizeof(gcb.gcb_gr_particles) == 8 + 8 * 8
