@@ -460,6 +460,14 @@ GCB_HD uint32_t grgca_step(const T* __restrict__ F, const GrConst& g, double x[3
 
 // One coupled step (Sec. 3.2) of one particle.  Returns S: 0 guiding
 // center, 1 full orbit, 2 not advanced (outside the domain).
+//
+// The two branches share their skeleton -- metric and fields at x^n, K
+// midpoint iterations that each need the metric and its derivatives and the
+// geodesic force G, metric and fields at x^{n+1} -- so they are evaluated in
+// one pass: a wavefront whose lanes took different branches then runs the
+// shared metric evaluations once, and only the branch-specific parts
+// diverge.  Per lane the operations are exactly those of greom_step /
+// grgca_step above (same values, same order).
 template <typename T>
 GCB_HD int coupled_step(const T* __restrict__ F, const double* __restrict__ dl_table,
                         const GrConst& g, double x[3], double u[3], double qm, uint8_t& status,
@@ -469,26 +477,113 @@ GCB_HD int coupled_step(const T* __restrict__ F, const double* __restrict__ dl_t
         if (!inside(g, x[0], x[1])) status |= kStOut;
         return 2;
     }
-    Metric m;
-    kerr_schild<false>(g.a, x[0], x[1], m);
-    GrSample f;
-    grid_sample(F, g, x[0], x[1], f);
+    Metric m0;
+    kerr_schild<false>(g.a, x[0], x[1], m0);
+    GrSample f0;
+    grid_sample(F, g, x[0], x[1], f0);
     int ci, cj;
     double wx, wy;
     grid_cell(g, x[0], x[1], ci, cj, wx, wy);
     const double dl = dl_table[(size_t)cj * g.nr + ci];
-    const bool gca = switch_gca(m, f, u, qm, dl, g);
-    double xn[3] = {x[0], x[1], x[2]};
-    double un[3] = {u[0], u[1], u[2]};
-    uint32_t fl = gca ? grgca_step(F, g, xn, un, qm, res) : greom_step(F, g, xn, un, qm, res);
+    const bool gca = switch_gca(m0, f0, u, qm, dl, g);
+
+    uint32_t fl = 0;
+    // guiding-center state: mu, gyration direction, u_par after the half push
+    double mu = 0.0, bperp[3] = {0.0, 0.0, 0.0}, p1 = 0.0, pk = 0.0;
+    // full-orbit state: u after the half push, the iterate u''
+    double u1[3] = {u[0], u[1], u[2]}, uk[3];
+    if (gca) {
+        GcLocal L0;
+        fl |= gc_local(m0, f0, L0);
+        const double Gf = gamma_of(m0, u);
+        const double upar = (L0.b_up[0] * u[0] + L0.b_up[1] * u[1]) + L0.b_up[2] * u[2];
+        double uperp[3];
+        for (int i = 0; i < 3; ++i) uperp[i] = (u[i] - upar * L0.b_dn[i]) - L0.vE[i] * Gf;
+        const double up2 = norm2_cov(m0, uperp);
+        mu = ((0.5 * up2) / L0.B) / L0.kappa;
+        if (!(L0.B > 0.0)) mu = 0.0;
+        const double nu = sqrt(up2);
+        const double inv_nu = nu > 0.0 ? 1.0 / nu : 0.0;
+        for (int i = 0; i < 3; ++i) bperp[i] = uperp[i] * inv_nu;
+        p1 = upar + (qm * (m0.alpha * (0.5 * g.dt))) * L0.Dpar;
+        pk = p1;
+    } else {
+        half_push(m0, f0, u1, qm, g.dt);
+    }
+    for (int i = 0; i < 3; ++i) uk[i] = u1[i];
+
+    double Xk[3] = {x[0], x[1], x[2]};
+    for (int k = 0; k < g.n_iter; ++k) {
+        double Xb[3];
+        for (int i = 0; i < 3; ++i) Xb[i] = 0.5 * (Xk[i] + x[i]);
+        Metric mb;
+        kerr_schild<true>(g.a, Xb[0], Xb[1], mb);
+        double V[3], ub[3], Gam;
+        double bup0 = 0.0, bup1 = 0.0;
+        if (gca) {
+            const double pb = 0.5 * (pk + p1);
+            GrSample fb;
+            grid_sample(F, g, Xb[0], Xb[1], fb);
+            GcLocal Lb;
+            fl |= gc_local(mb, fb, Lb);
+            Gam = gamma_gc(Lb, pb, mu);
+            double vu[3];
+            raise(mb, Lb.vE, vu);
+            V[0] = mb.alpha * (pb * (Lb.b_up[0] / Gam) + vu[0]) - mb.beta_r;
+            V[1] = mb.alpha * (pb * (Lb.b_up[1] / Gam) + vu[1]);
+            V[2] = mb.alpha * (pb * (Lb.b_up[2] / Gam) + vu[2]);
+            const double upg = sqrt(((2.0 * mu) * Lb.kappa) * Lb.B);
+            for (int i = 0; i < 3; ++i)
+                ub[i] = (pb * Lb.b_dn[i] + Lb.vE[i] * Gam) + upg * bperp[i];
+            bup0 = Lb.b_up[0];
+            bup1 = Lb.b_up[1];
+        } else {
+            for (int i = 0; i < 3; ++i) ub[i] = 0.5 * (uk[i] + u1[i]);
+            Gam = gamma_of(mb, ub);
+            geo_V(mb, ub, Gam, V);
+        }
+        double G[2];
+        geo_G(mb, ub, Gam, G);
+        double Xn[3];
+        for (int i = 0; i < 3; ++i) Xn[i] = x[i] + g.dt * V[i];
+        res = max_nan(max_nan(fabs(Xn[0] - Xk[0]), fabs(Xn[1] - Xk[1])), fabs(Xn[2] - Xk[2]));
+        for (int i = 0; i < 3; ++i) Xk[i] = Xn[i];
+        if (gca) {
+            const double Gb = G[0] * bup0 + G[1] * bup1;
+            pk = p1 + g.dt * Gb;
+        } else {
+            uk[0] = u1[0] + g.dt * G[0];
+            uk[1] = u1[1] + g.dt * G[1];
+            uk[2] = u1[2];
+        }
+    }
+
+    Metric m1;
+    kerr_schild<false>(g.a, Xk[0], Xk[1], m1);
+    GrSample f1;
+    grid_sample(F, g, Xk[0], Xk[1], f1);
+    double un[3];
+    if (gca) {
+        GcLocal L1;
+        fl |= gc_local(m1, f1, L1);
+        const double upar1 = pk + (qm * (m1.alpha * (0.5 * g.dt))) * L1.Dpar;
+        const double Gam1 = gamma_gc(L1, upar1, mu);
+        const double upg1 = sqrt(((2.0 * mu) * L1.kappa) * L1.B);
+        for (int i = 0; i < 3; ++i)
+            un[i] = (upar1 * L1.b_dn[i] + L1.vE[i] * Gam1) + upg1 * bperp[i];
+    } else {
+        half_push(m1, f1, uk, qm, g.dt);
+        for (int i = 0; i < 3; ++i) un[i] = uk[i];
+    }
+
     if (res > g.fp_tol) fl |= ST_FPRES;
     bool fin = true;
-    for (int i = 0; i < 3; ++i) fin = fin && __builtin_isfinite(xn[i]) && __builtin_isfinite(un[i]);
+    for (int i = 0; i < 3; ++i) fin = fin && __builtin_isfinite(Xk[i]) && __builtin_isfinite(un[i]);
     if (!fin) fl |= ST_NONFINITE;
-    if (!inside(g, xn[0], xn[1])) fl |= kStOut;
-    x[0] = xn[0];
-    x[1] = xn[1];
-    x[2] = wrap_phi(xn[2]);
+    if (!inside(g, Xk[0], Xk[1])) fl |= kStOut;
+    x[0] = Xk[0];
+    x[1] = Xk[1];
+    x[2] = wrap_phi(Xk[2]);
     for (int i = 0; i < 3; ++i) u[i] = un[i];
     status = (uint8_t)(status | fl);
     return gca ? 0 : 1;
