@@ -34,6 +34,10 @@ FP64_VECTOR_PEAK_TF = 78.6      # MI355X FP64 vector, AMD published
 # add, sub, mul, div, sqrt, floor, comparison and select of the definition.
 FLOPS_BORIS = 287.0
 FLOPS_GCA = 2216.0
+# The same count for one step of the curved-spacetime scheme (K = 4), the
+# switch part included.
+FLOPS_GR_ORBIT = 1611.0
+FLOPS_GR_GCA = 2218.0
 
 # Hardware-counter record of the binary64 push kernel (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, calibrated against a plain device copy); it is used only
@@ -139,6 +143,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=100)
+    ap.add_argument("--no-gr", action="store_true")
+    ap.add_argument("--gr-steps", type=int, default=40)
+    ap.add_argument("--gr-warmup", type=int, default=4)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -251,6 +258,52 @@ def main():
             pctx.close()
             torch.cuda.empty_cache()
 
+    def time_gr(steps: int, warmup: int):
+        """Curved-spacetime push: Kerr a = 0.9, 512 x 512 (r, theta) grid,
+        1e7 particles (the workload's own size), binary64."""
+        from workloads import make_gr_config
+        gcfg = make_gr_config("grbh512")
+        log(f"[bench] curved spacetime: generating {gcfg.name}, n={gcfg.n}")
+        GF = gcfg.fields()
+        ge = gcfg.particles()
+        ctx = gcb.gcb_create(0)
+        try:
+            desc = gcb.gr_desc(gcfg.nr, gcfg.nth, gcfg.r_min, gcfg.r_max, gcfg.a)
+            gcb.gcb_load_fields_gr(ctx, desc, [GF[0], GF[1], GF[2]], [GF[3], GF[4], GF[5]])
+            t = {k: torch.as_tensor(getattr(ge, k), dtype=torch.float64, device=dev)
+                 for k in ("r", "th", "ph", "ur", "uth", "uph")}
+            t["status"] = torch.zeros(ge.n, dtype=torch.uint8, device=dev)
+            parts = gcb.gr_particles(t)
+            prm = gcb.params(dt=gcfg.dt, c=1.0, qm=gcfg.qm, f_rho=gcfg.f_rho, f_E=gcfg.f_E,
+                             n_iter=gcfg.n_iter)
+            st = gcb.gcb_push_gr(ctx, parts, prm, warmup, want_stats=True)
+            frac = st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])
+            gcb.gcb_set_timing(ctx, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gcb.gcb_push_gr(ctx, parts, prm, steps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ms, cnt = gcb.gcb_get_timing(ctx)
+            gcb.gcb_set_timing(ctx, False)
+            kms = ms[gcb.GCB_TIMER_PUSH] / steps
+            fl = FLOPS_GR_GCA * frac + FLOPS_GR_ORBIT * (1.0 - frac)
+            tf = fl * ge.n / (kms * 1e-3) / 1e12
+            log(f"[bench] curved spacetime: {steps} steps in {t1 - t0:.3f} s")
+            return {"value": ge.n * steps / (t1 - t0), "unit": "particle-steps/s",
+                    "workload": f"{gcfg.name}: Kerr a={gcfg.a} Kerr-Schild, "
+                                f"{gcfg.nr}x{gcfg.nth} (r, theta) grid r in "
+                                f"[{gcfg.r_min}, {gcfg.r_max}], split monopole with an "
+                                f"equatorial current sheet, {ge.n} particles, binary64",
+                    "steps": steps, "ms_per_step": (t1 - t0) * 1e3 / steps,
+                    "kernel_ms_per_step": kms, "gca_fraction": frac,
+                    "algorithmic_flops_per_particle_step": fl,
+                    "alu_achieved_TFLOPs": tf, "alu_frac": tf / FP64_VECTOR_PEAK_TF,
+                    "kernel": "k_push_gr (one lane per particle, 8 steps per launch)"}
+        finally:
+            gcb.gcb_destroy(ctx)
+            torch.cuda.empty_cache()
+
     r64 = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup)
     wall, push_ms, sort_ms, gca_frac = r64["wall"], r64["push_ms"], r64["sort_ms"], r64["gca_frac"]
     bytes_step = push_bytes_per_step(n, cfg.nx, cfg.ny, 0)
@@ -273,6 +326,9 @@ def main():
             "algorithmic_bytes_per_launch": bm,
             "speedup_vs_f64": (n * a.steps / rm["wall"]) / value,
             "dtype": "f32 bulk, f64 positions"}
+
+    if not a.no_gr:
+        forms["gr"] = time_gr(a.gr_steps, a.gr_warmup)
 
     if not a.no_adjoint:
         forms["fwd_adjoint"] = time_fwd_adjoint(a.adjoint_steps, 32)

@@ -82,6 +82,48 @@ def count(cfg_name="harris4096", n=4096, **over):
     return (c.flops + calls["n"]) / n, c.by, calls["n"] / n
 
 
+def count_gr(cfg_name="grbh512", n=4096):
+    """Per-branch operations of one curved-spacetime step: the switch part
+    (metric, gather and switch at x^n) plus one branch, per particle."""
+    import oracle.gr as gr
+    from workloads import make_gr_config
+    cfg = make_gr_config(cfg_name)
+    F = cfg.fields()
+    e = cfg.particles(n=n)
+    grid = gr.GRGrid(F, cfg.r_min, cfg.r_max)
+    met = gr.KerrSchild(cfg.a)
+    p = gr.GRParams(dt=cfg.dt, f_rho=cfg.f_rho, f_E=cfg.f_E, n_iter=cfg.n_iter)
+    st = gr.GRState.from_numpy(e)
+    dl = gr.cell_lengths(met, grid)
+    x = (st.r, st.th, st.ph)
+    u = (st.ur, st.uth, st.uph)
+    import oracle.ieee as ieee
+    orig = ieee.sqrt
+    calls = {"n": 0}
+
+    def counting_sqrt(v):
+        calls["n"] += v.numel()
+        return orig(v)
+    gr.sqrt = counting_sqrt
+    out = {}
+    try:
+        def switch_part():
+            ci, cj, _, _ = grid.cell(x[0], x[1])
+            return gr.switch_gca(met.at(x[0], x[1]), *grid.sample(x[0], x[1]), u, st.qm,
+                                 dl[cj, ci], p)
+
+        for name, fn in (("switch", switch_part),
+                         ("full orbit", lambda: gr.greom_step(met, grid, x, u, st.qm, p)),
+                         ("guiding center", lambda: gr.grgca_step(met, grid, x, u, st.qm, p))):
+            calls["n"] = 0
+            with _Count() as c:
+                fn()
+            out[name] = ((c.flops + calls["n"]) / n, calls["n"] / n)
+    finally:
+        gr.sqrt = orig
+    return out
+
+
 def main():
     b, _, bs = count(f_rho=0.0)
     g, by, gs = count(f_rho=math.inf, f_E=math.inf)
@@ -89,6 +131,12 @@ def main():
     print(f"Guiding-center branch:  {g:8.1f} flops/particle-step ({gs:.1f} sqrt), K=4, curvature")
     g3, _, _ = count(f_rho=math.inf, f_E=math.inf, n_iter=3)
     print(f"Guiding-center, K=3:    {g3:8.1f}")
+    gr_counts = count_gr()
+    sw = gr_counts["switch"][0]
+    for k in ("full orbit", "guiding center"):
+        f, sq = gr_counts[k]
+        print(f"curved spacetime, {k:15s} {sw + f:8.1f} flops/particle-step "
+              f"(switch {sw:.1f} + branch {f:.1f}; {sq:.1f} sqrt in the branch), K=4")
 
 
 if __name__ == "__main__":

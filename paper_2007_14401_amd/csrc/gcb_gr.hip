@@ -30,7 +30,12 @@ __device__ __forceinline__ double wave_max_nan(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(kGrWG) void k_gr_push(GrPtrs p, int64_t n, int s0, int ns,
+#ifndef GCB_GR_MIN_WAVES
+#define GCB_GR_MIN_WAVES 2
+#endif
+
+__global__ __launch_bounds__(kGrWG) __attribute__((amdgpu_waves_per_eu(GCB_GR_MIN_WAVES))) void
+k_gr_push(GrPtrs p, int64_t n, int s0, int ns,
                                                    const double* __restrict__ F,
                                                    const double* __restrict__ dl,
                                                    gr::GrConst g, uint8_t* trace,
