@@ -258,9 +258,10 @@ def main():
             pctx.close()
             torch.cuda.empty_cache()
 
-    def time_gr(steps: int, warmup: int):
+    def time_gr(steps: int, warmup: int, mixed: bool = False):
         """Curved-spacetime push: Kerr a = 0.9, 512 x 512 (r, theta) grid,
-        1e7 particles (the workload's own size), binary64."""
+        1e7 particles (the workload's own size), binary64 or the precision
+        form."""
         from workloads import make_gr_config
         gcfg = make_gr_config("grbh512")
         log(f"[bench] curved spacetime: generating {gcfg.name}, n={gcfg.n}")
@@ -268,14 +269,18 @@ def main():
         ge = gcfg.particles()
         ctx = gcb.gcb_create(0)
         try:
-            desc = gcb.gr_desc(gcfg.nr, gcfg.nth, gcfg.r_min, gcfg.r_max, gcfg.a)
+            desc = gcb.gr_desc(gcfg.nr, gcfg.nth, gcfg.r_min, gcfg.r_max, gcfg.a,
+                               gcb.GCB_F32 if mixed else gcb.GCB_F64)
             gcb.gcb_load_fields_gr(ctx, desc, [GF[0], GF[1], GF[2]], [GF[3], GF[4], GF[5]])
-            t = {k: torch.as_tensor(getattr(ge, k), dtype=torch.float64, device=dev)
+            t = {k: torch.as_tensor(getattr(ge, k), device=dev,
+                                    dtype=torch.float32 if (mixed and k[0] == "u")
+                                    else torch.float64)
                  for k in ("r", "th", "ph", "ur", "uth", "uph")}
             t["status"] = torch.zeros(ge.n, dtype=torch.uint8, device=dev)
             parts = gcb.gr_particles(t)
             prm = gcb.params(dt=gcfg.dt, c=1.0, qm=gcfg.qm, f_rho=gcfg.f_rho, f_E=gcfg.f_E,
-                             n_iter=gcfg.n_iter)
+                             n_iter=gcfg.n_iter,
+                             form=gcb.GCB_FORM_MIXED if mixed else gcb.GCB_FORM_F64)
             st = gcb.gcb_push_gr(ctx, parts, prm, warmup, want_stats=True)
             frac = st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])
             gcb.gcb_set_timing(ctx, True)
@@ -294,7 +299,8 @@ def main():
                     "workload": f"{gcfg.name}: Kerr a={gcfg.a} Kerr-Schild, "
                                 f"{gcfg.nr}x{gcfg.nth} (r, theta) grid r in "
                                 f"[{gcfg.r_min}, {gcfg.r_max}], split monopole with an "
-                                f"equatorial current sheet, {ge.n} particles, binary64",
+                                f"equatorial current sheet, {ge.n} particles, "
+                                + ("binary32 bulk, binary64 positions" if mixed else "binary64"),
                     "steps": steps, "ms_per_step": (t1 - t0) * 1e3 / steps,
                     "kernel_ms_per_step": kms, "gca_fraction": frac,
                     "algorithmic_flops_per_particle_step": fl,
@@ -329,6 +335,10 @@ def main():
 
     if not a.no_gr:
         forms["gr"] = time_gr(a.gr_steps, a.gr_warmup)
+        if not a.no_mixed:
+            forms["gr_mixed"] = time_gr(a.gr_steps, a.gr_warmup, mixed=True)
+            forms["gr_mixed"]["speedup_vs_gr_f64"] = (forms["gr_mixed"]["value"]
+                                                      / forms["gr"]["value"])
 
     if not a.no_adjoint:
         forms["fwd_adjoint"] = time_fwd_adjoint(a.adjoint_steps, 32)

@@ -211,7 +211,7 @@ typedef struct {
     int32_t nr, nth;        /* cells along r and theta, >= 1 */
     double  r_min, r_max;   /* 0 < r_min < r_max */
     double  spin;           /* Kerr a, |a| < 1 */
-    int32_t dtype;          /* GCB_F64 */
+    int32_t dtype;          /* GCB_F64 (plain path) or GCB_F32 (precision form) */
 } gcb_gr_desc;
 
 /* Load D[3] = (D^r, D^th, D^ph) and B[3] = (B^r, B^th, B^ph): each an array
@@ -230,7 +230,7 @@ int gcb_load_fields_gr(gcb_ctx* ctx, const gcb_gr_desc* desc,
 typedef struct {
     int64_t  n;
     double  *r, *th, *ph;
-    double  *ur, *uth, *uph;
+    void    *ur, *uth, *uph;  /* double (GCB_FORM_F64) or float (GCB_FORM_MIXED) */
     double  *qm;            /* optional per-particle q/m (NULL: params.qm) */
     uint8_t *status;        /* required: sticky GCB_ST_* bits */
 } gcb_gr_particles;
@@ -243,8 +243,12 @@ typedef struct {
    push) or the guiding-center step of Sec. 2.4 (half parallel push,
    implicit-midpoint update of (R, u_par) by n_iter iterations, half push,
    u rebuilt at R^{n+1} with the gyration direction of the step start).
-   Reads dt, qm, f_rho, f_E, fp_tol, n_iter of params (c is 1 here; form must
-   be GCB_FORM_F64; replay must be 0; the other fields are ignored).
+   Reads dt, qm, f_rho, f_E, fp_tol, n_iter and form of params (c is 1 here;
+   replay must be 0; the other fields are ignored).  GCB_FORM_F64 needs
+   fields loaded as GCB_F64; GCB_FORM_MIXED (binary32 fields, metric,
+   four-velocity and bulk arithmetic, binary64 positions, and binary64 for
+   Gamma when |u|^2 > 1e6, for 1 - v_E^2 when v_E^2 > 0.81 and for a switch
+   ratio within a relative 1e-4 of its threshold) needs GCB_F32 fields.
    A particle whose new position leaves r_min <= r < r_max, 0 <= theta <= pi
    gets GCB_ST_OUT and keeps its state from then on.
    s_trace (nullable, device, n_steps*n bytes): s_trace[step*n + k] = 0

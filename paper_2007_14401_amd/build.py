@@ -32,6 +32,7 @@ UNITS = {
     "gcb_sort.hip": ["-ffp-contract=off"],
     "gcb_util.hip": ["-ffp-contract=off"],
     "gcb_gr.hip": ["-ffp-contract=off"],
+    "gcb_gr_mixed.hip": [],
 }
 
 

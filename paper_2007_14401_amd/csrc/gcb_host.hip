@@ -42,6 +42,7 @@ struct gcb_ctx {
     DevBuf fields;
     // curved-spacetime fields
     bool have_gr = false;
+    int gr_dtype = GCB_F64;
     gr::GrConst gr{};
     double gr_dr = 0.0, gr_dth = 0.0;
     DevBuf gr_fields, gr_dl;
@@ -642,7 +643,8 @@ int gcb_load_fields_gr(gcb_ctx* ctx, const gcb_gr_desc* d, const double* const D
           d->r_max > d->r_min))
         return fail(ctx, GCB_EINVAL, "need 0 < r_min < r_max (finite)");
     if (!(std::fabs(d->spin) < 1.0)) return fail(ctx, GCB_EINVAL, "need |spin| < 1");
-    if (d->dtype != GCB_F64) return fail(ctx, GCB_EUNSUPPORTED, "curved-spacetime fields are GCB_F64");
+    if (d->dtype != GCB_F64 && d->dtype != GCB_F32)
+        return fail(ctx, GCB_EINVAL, "unknown dtype %d", d->dtype);
     if (src != GCB_HOST && src != GCB_DEVICE)
         return fail(ctx, GCB_EINVAL, "src must be GCB_HOST or GCB_DEVICE");
     const double* comps[6] = {D[0], D[1], D[2], B[0], B[1], B[2]};
@@ -653,7 +655,8 @@ int gcb_load_fields_gr(gcb_ctx* ctx, const gcb_gr_desc* d, const double* const D
     const int nxn = d->nr + 1, nyn = d->nth + 1;
     const int64_t nodes = (int64_t)nxn * nyn;
     ctx->have_gr = false;
-    int rc = ensure(ctx, ctx->gr_fields, (size_t)nodes * 6 * sizeof(double));
+    const size_t esz = d->dtype == GCB_F64 ? sizeof(double) : sizeof(float);
+    int rc = ensure(ctx, ctx->gr_fields, (size_t)nodes * 6 * esz);
     if (rc) return rc;
     if ((rc = ensure(ctx, ctx->gr_dl, (size_t)d->nr * d->nth * sizeof(double)))) return rc;
     if (src == GCB_HOST) {
@@ -669,13 +672,15 @@ int gcb_load_fields_gr(gcb_ctx* ctx, const gcb_gr_desc* d, const double* const D
             dcomps[k] = dst;
         }
         if (e == hipSuccess)
-            e = launch_interleave_fields(dcomps, nxn, nyn, ctx->gr_fields.ptr, false, stream);
+            e = launch_interleave_fields(dcomps, nxn, nyn, ctx->gr_fields.ptr,
+                                         d->dtype == GCB_F32, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         release(tmp);
         if (e != hipSuccess)
             return fail(ctx, GCB_EHIP, "field conversion: %s", hipGetErrorString(e));
     } else {
-        GCB_HIP(launch_interleave_fields(comps, nxn, nyn, ctx->gr_fields.ptr, false, stream));
+        GCB_HIP(launch_interleave_fields(comps, nxn, nyn, ctx->gr_fields.ptr,
+                                         d->dtype == GCB_F32, stream));
     }
     gr::GrConst g{};
     g.a = d->spin;
@@ -689,6 +694,7 @@ int gcb_load_fields_gr(gcb_ctx* ctx, const gcb_gr_desc* d, const double* const D
     g.inv_dth = 1.0 / dth;
     GCB_HIP(launch_gr_cell_lengths(g, dr, dth, static_cast<double*>(ctx->gr_dl.ptr), stream));
     ctx->gr = g;
+    ctx->gr_dtype = d->dtype;
     ctx->gr_dr = dr;
     ctx->gr_dth = dth;
     ctx->have_gr = true;
@@ -706,8 +712,8 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     if (!(prm->fp_tol >= 0.0)) return fail(ctx, GCB_EINVAL, "fp_tol must be >= 0");
     if (prm->n_iter < 1 || prm->n_iter > 64)
         return fail(ctx, GCB_EINVAL, "n_iter must be in [1, 64]");
-    if (prm->form != GCB_FORM_F64)
-        return fail(ctx, GCB_EUNSUPPORTED, "the curved-spacetime push is GCB_FORM_F64");
+    if (prm->form != GCB_FORM_F64 && prm->form != GCB_FORM_MIXED)
+        return fail(ctx, GCB_EINVAL, "unknown form %d", prm->form);
     if (prm->replay) return fail(ctx, GCB_EUNSUPPORTED, "replay is not supported here");
     if (p->n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");
     if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
@@ -716,6 +722,10 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     if (p->n > 0 && !p->qm && !(std::isfinite(prm->qm) && prm->qm != 0.0))
         return fail(ctx, GCB_EINVAL, "params.qm must be finite and non-zero");
     if (!ctx->have_gr) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields_gr was not called");
+    if (prm->form == GCB_FORM_F64 && ctx->gr_dtype != GCB_F64)
+        return fail(ctx, GCB_EINVAL, "GCB_FORM_F64 needs fields loaded as GCB_F64");
+    if (prm->form == GCB_FORM_MIXED && ctx->gr_dtype != GCB_F32)
+        return fail(ctx, GCB_EINVAL, "GCB_FORM_MIXED needs fields loaded as GCB_F32");
     GCB_HIP(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DevStats* dstats = nullptr;
@@ -736,9 +746,15 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     GrPtrs ptrs{p->r, p->th, p->ph, p->ur, p->uth, p->uph, p->qm, p->status};
     {
         Timer t(ctx, stream, GCB_TIMER_PUSH);
-        GCB_HIP(launch_gr_push(ptrs, p->n, n_steps, static_cast<const double*>(ctx->gr_fields.ptr),
-                               static_cast<const double*>(ctx->gr_dl.ptr), g, s_trace, dstats,
-                               stream));
+        const double* dl = static_cast<const double*>(ctx->gr_dl.ptr);
+        if (prm->form == GCB_FORM_F64)
+            GCB_HIP(launch_gr_push_f64(ptrs, p->n, n_steps,
+                                       static_cast<const double*>(ctx->gr_fields.ptr), dl, g,
+                                       s_trace, dstats, stream));
+        else
+            GCB_HIP(launch_gr_push_mixed(ptrs, p->n, n_steps,
+                                         static_cast<const float*>(ctx->gr_fields.ptr), dl, g,
+                                         s_trace, dstats, stream));
         t.done();
     }
     if (stats) {

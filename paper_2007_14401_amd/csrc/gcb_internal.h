@@ -131,15 +131,18 @@ hipError_t launch_deinterleave_add(const float* grad_fields, int nx, int ny,
 // curved-spacetime push (gcb_gr.hip)
 struct GrPtrs {
     double *r, *th, *ph;
-    double *ur, *uth, *uph;
-    const double* qm;   // nullable
+    void *ur, *uth, *uph;   // double (binary64 form) or float (precision form)
+    const double* qm;       // nullable
     uint8_t* status;
 };
 
 hipError_t launch_gr_cell_lengths(const gr::GrConst& g, double dr, double dth, double* dl,
                                   hipStream_t stream);
-hipError_t launch_gr_push(const GrPtrs& p, int64_t n, int n_steps, const double* F,
-                          const double* dl, const gr::GrConst& g, uint8_t* trace,
-                          DevStats* stats, hipStream_t stream);
+hipError_t launch_gr_push_f64(const GrPtrs& p, int64_t n, int n_steps, const double* F,
+                              const double* dl, const gr::GrConst& g, uint8_t* trace,
+                              DevStats* stats, hipStream_t stream);
+hipError_t launch_gr_push_mixed(const GrPtrs& p, int64_t n, int n_steps, const float* F,
+                                const double* dl, const gr::GrConst& g, uint8_t* trace,
+                                DevStats* stats, hipStream_t stream);
 
 }  // namespace gcb

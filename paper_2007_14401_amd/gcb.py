@@ -242,6 +242,7 @@ def gr_desc(nr, nth, r_min, r_max, spin, dtype=GCB_F64) -> gcb_gr_desc:
 
 
 def gcb_load_fields_gr(ctx, desc: gcb_gr_desc, D, B, src=None, stream=None) -> None:
+    # D, B are always binary64; desc.dtype selects the device copy
     """D, B: sequences of three (nth+1, nr+1) float64 arrays (numpy host or torch device)."""
     if src is None:
         src = GCB_HOST if isinstance(D[0], np.ndarray) else GCB_DEVICE
