@@ -146,6 +146,7 @@ def main():
     ap.add_argument("--no-gr", action="store_true")
     ap.add_argument("--gr-steps", type=int, default=40)
     ap.add_argument("--gr-warmup", type=int, default=4)
+    ap.add_argument("--gr-sort-every", type=int, default=16)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -277,9 +278,10 @@ def main():
                                     else torch.float64)
                  for k in ("r", "th", "ph", "ur", "uth", "uph")}
             t["status"] = torch.zeros(ge.n, dtype=torch.uint8, device=dev)
+            t["id"] = torch.arange(ge.n, dtype=torch.int32, device=dev)
             parts = gcb.gr_particles(t)
             prm = gcb.params(dt=gcfg.dt, c=1.0, qm=gcfg.qm, f_rho=gcfg.f_rho, f_E=gcfg.f_E,
-                             n_iter=gcfg.n_iter,
+                             n_iter=gcfg.n_iter, sort_every=a.gr_sort_every,
                              form=gcb.GCB_FORM_MIXED if mixed else gcb.GCB_FORM_F64)
             st = gcb.gcb_push_gr(ctx, parts, prm, warmup, want_stats=True)
             frac = st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])
@@ -292,6 +294,7 @@ def main():
             ms, cnt = gcb.gcb_get_timing(ctx)
             gcb.gcb_set_timing(ctx, False)
             kms = ms[gcb.GCB_TIMER_PUSH] / steps
+            sort_ms = ms[gcb.GCB_TIMER_SORT] / max(1, cnt[gcb.GCB_TIMER_SORT])
             fl = FLOPS_GR_GCA * frac + FLOPS_GR_ORBIT * (1.0 - frac)
             tf = fl * ge.n / (kms * 1e-3) / 1e12
             log(f"[bench] curved spacetime: {steps} steps in {t1 - t0:.3f} s")
@@ -303,9 +306,11 @@ def main():
                                 + ("binary32 bulk, binary64 positions" if mixed else "binary64"),
                     "steps": steps, "ms_per_step": (t1 - t0) * 1e3 / steps,
                     "kernel_ms_per_step": kms, "gca_fraction": frac,
+                    "sort_every": a.gr_sort_every, "sort_ms_per_sort": sort_ms,
                     "algorithmic_flops_per_particle_step": fl,
                     "alu_achieved_TFLOPs": tf, "alu_frac": tf / FP64_VECTOR_PEAK_TF,
-                    "kernel": "k_push_gr (one lane per particle, 8 steps per launch)"}
+                    "kernel": "k_gr_push (one lane per particle, 8 steps per launch), "
+                              "(r, theta) tile sort every sort_every steps"}
         finally:
             gcb.gcb_destroy(ctx)
             torch.cuda.empty_cache()

@@ -226,12 +226,17 @@ int gcb_load_fields_gr(gcb_ctx* ctx, const gcb_gr_desc* desc,
 /* Particle state of the curved-spacetime push, structure of arrays,
    caller-owned device memory of length n: position x^i = (r, theta, phi) and
    covariant four-velocity u_i at the same time level (Sec. 3.2, not
-   staggered).  Updated in place, never reordered; phi is kept in [0, 2 pi). */
+   staggered).  Updated in place; with params.sort_every > 0 all arrays
+   (including qm, id and status) are permuted together into (r, theta) tile
+   order every sort_every steps, so `id` is how a caller follows a particle.
+   phi is kept in [0, 2 pi). */
 typedef struct {
     int64_t  n;
     double  *r, *th, *ph;
     void    *ur, *uth, *uph;  /* double (GCB_FORM_F64) or float (GCB_FORM_MIXED) */
     double  *qm;            /* optional per-particle q/m (NULL: params.qm) */
+    int32_t *id;            /* optional particle ids, permuted with the sort; values in
+                               [0, n) when a switch trace is requested with sorting */
     uint8_t *status;        /* required: sticky GCB_ST_* bits */
 } gcb_gr_particles;
 
@@ -243,8 +248,8 @@ typedef struct {
    push) or the guiding-center step of Sec. 2.4 (half parallel push,
    implicit-midpoint update of (R, u_par) by n_iter iterations, half push,
    u rebuilt at R^{n+1} with the gyration direction of the step start).
-   Reads dt, qm, f_rho, f_E, fp_tol, n_iter and form of params (c is 1 here;
-   replay must be 0; the other fields are ignored).  GCB_FORM_F64 needs
+   Reads dt, qm, f_rho, f_E, fp_tol, n_iter, form and sort_every of params
+   (c is 1 here; replay must be 0; the other fields are ignored).  GCB_FORM_F64 needs
    fields loaded as GCB_F64; GCB_FORM_MIXED (binary32 fields, metric,
    four-velocity and bulk arithmetic, binary64 positions, and binary64 for
    Gamma when |u|^2 > 1e6, for 1 - v_E^2 when v_E^2 > 0.81 and for a switch
@@ -252,7 +257,8 @@ typedef struct {
    A particle whose new position leaves r_min <= r < r_max, 0 <= theta <= pi
    gets GCB_ST_OUT and keeps its state from then on.
    s_trace (nullable, device, n_steps*n bytes): s_trace[step*n + k] = 0
-   (guiding center), 1 (full orbit) or 2 (not advanced) for array slot k.
+   (guiding center), 1 (full orbit) or 2 (not advanced) for the particle
+   with id k (or array slot k when id is NULL; sorting then needs ids).
    stats (nullable, host): as for gcb_push; max_fp_residual covers both
    branches (both iterate); flagged counts GCB_ST_OUT too. */
 int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm,

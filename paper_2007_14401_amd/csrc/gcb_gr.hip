@@ -26,10 +26,12 @@ hipError_t launch_gr_cell_lengths(const gr::GrConst& g, double dr, double dth, d
     return hipGetLastError();
 }
 
-hipError_t launch_gr_push_f64(const GrPtrs& p, int64_t n, int n_steps, const double* F,
-                              const double* dl, const gr::GrConst& g, uint8_t* trace,
-                              DevStats* stats, hipStream_t stream) {
-    return grk::launch<double, double>(p, n, n_steps, F, dl, g, trace, stats, stream);
+hipError_t launch_gr_push_f64(const GrPtrs& in, const GrPtrs& out, int64_t n, int n_steps,
+                              const double* F, const double* dl, const gr::GrConst& g,
+                              uint8_t* trace, int trace_step0, DevStats* stats,
+                              hipStream_t stream) {
+    return grk::launch<double, double>(in, out, n, n_steps, F, dl, g, trace, trace_step0, stats,
+                                       stream);
 }
 
 }  // namespace gcb

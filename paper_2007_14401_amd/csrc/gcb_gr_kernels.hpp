@@ -25,37 +25,43 @@ __device__ __forceinline__ double wave_max_nan(double v) {
     return v;
 }
 
+// ns steps of particle slot k: read from `in`, written to `out` (the same
+// arrays, or a sorted copy and the caller's arrays, which then also receive
+// q/m and the id)
 template <typename R, typename T>
 __global__ __launch_bounds__(kGrWG) __attribute__((amdgpu_waves_per_eu(2))) void
-k_gr_push(GrPtrs p, int64_t n, int s0, int ns, const T* __restrict__ F,
+k_gr_push(GrPtrs in, GrPtrs out, int64_t n, int s0, int ns, const T* __restrict__ F,
           const double* __restrict__ dl, gr::GrConst g, uint8_t* trace, DevStats* stats) {
     const int64_t k = (int64_t)blockIdx.x * kGrWG + threadIdx.x;
     const bool active = k < n;
     unsigned cnt_g = 0, cnt_b = 0;
     double maxres = 0.0;
     if (active) {
-        double x[3] = {p.r[k], p.th[k], p.ph[k]};
-        R* ur = static_cast<R*>(p.ur);
-        R* uth = static_cast<R*>(p.uth);
-        R* uph = static_cast<R*>(p.uph);
-        R u[3] = {ur[k], uth[k], uph[k]};
-        const double qm = p.qm ? p.qm[k] : g.qm;
-        uint8_t st = p.status[k];
+        double x[3] = {in.r[k], in.th[k], in.ph[k]};
+        R u[3] = {static_cast<const R*>(in.ur)[k], static_cast<const R*>(in.uth)[k],
+                  static_cast<const R*>(in.uph)[k]};
+        const double qm = in.qm ? in.qm[k] : g.qm;
+        const int32_t pid = in.id ? in.id[k] : (int32_t)k;
+        uint8_t st = in.status[k];
         for (int s = 0; s < ns; ++s) {
             double res;
             const int S = gr::coupled_step(F, dl, g, x, u, qm, st, res);
-            if (trace) trace[(size_t)(s0 + s) * n + k] = (uint8_t)S;
+            if (trace) trace[(size_t)(s0 + s) * n + pid] = (uint8_t)S;
             cnt_g += S == 0;
             cnt_b += S == 1;
             maxres = gr::max_nan(maxres, res);
         }
-        p.r[k] = x[0];
-        p.th[k] = x[1];
-        p.ph[k] = x[2];
-        ur[k] = u[0];
-        uth[k] = u[1];
-        uph[k] = u[2];
-        p.status[k] = st;
+        out.r[k] = x[0];
+        out.th[k] = x[1];
+        out.ph[k] = x[2];
+        static_cast<R*>(out.ur)[k] = u[0];
+        static_cast<R*>(out.uth)[k] = u[1];
+        static_cast<R*>(out.uph)[k] = u[2];
+        out.status[k] = st;
+        if (out.r != in.r) {
+            if (in.qm) const_cast<double*>(out.qm)[k] = qm;
+            if (in.id) out.id[k] = pid;
+        }
     }
     if (stats) {
         unsigned long long a = cnt_g, b = cnt_b;
@@ -76,14 +82,16 @@ k_gr_push(GrPtrs p, int64_t n, int s0, int ns, const T* __restrict__ F,
 
 
 template <typename R, typename T>
-hipError_t launch(const GrPtrs& p, int64_t n, int n_steps, const T* F, const double* dl,
-                  const gr::GrConst& g, uint8_t* trace, DevStats* stats, hipStream_t stream) {
+hipError_t launch(const GrPtrs& in, const GrPtrs& out, int64_t n, int n_steps, const T* F,
+                  const double* dl, const gr::GrConst& g, uint8_t* trace, int trace_step0,
+                  DevStats* stats, hipStream_t stream) {
     if (n == 0 || n_steps == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n + kGrWG - 1) / kGrWG);
     for (int s0 = 0; s0 < n_steps; s0 += kGrStepsPerLaunch) {
         const int ns = n_steps - s0 < kGrStepsPerLaunch ? n_steps - s0 : kGrStepsPerLaunch;
-        hipLaunchKernelGGL((k_gr_push<R, T>), dim3(blocks), dim3(kGrWG), 0, stream, p, n, s0, ns,
-                           F, dl, g, trace, stats);
+        hipLaunchKernelGGL((k_gr_push<R, T>), dim3(blocks), dim3(kGrWG), 0, stream,
+                           s0 == 0 ? in : out, out, n, trace_step0 + s0, ns, F, dl, g, trace,
+                           stats);
     }
     return hipGetLastError();
 }

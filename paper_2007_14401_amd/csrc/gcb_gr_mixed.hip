@@ -8,10 +8,12 @@
 
 namespace gcb {
 
-hipError_t launch_gr_push_mixed(const GrPtrs& p, int64_t n, int n_steps, const float* F,
-                                const double* dl, const gr::GrConst& g, uint8_t* trace,
-                                DevStats* stats, hipStream_t stream) {
-    return grk::launch<float, float>(p, n, n_steps, F, dl, g, trace, stats, stream);
+hipError_t launch_gr_push_mixed(const GrPtrs& in, const GrPtrs& out, int64_t n, int n_steps,
+                                const float* F, const double* dl, const gr::GrConst& g,
+                                uint8_t* trace, int trace_step0, DevStats* stats,
+                                hipStream_t stream) {
+    return grk::launch<float, float>(in, out, n, n_steps, F, dl, g, trace, trace_step0, stats,
+                                     stream);
 }
 
 }  // namespace gcb

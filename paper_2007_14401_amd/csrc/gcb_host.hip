@@ -45,7 +45,7 @@ struct gcb_ctx {
     int gr_dtype = GCB_F64;
     gr::GrConst gr{};
     double gr_dr = 0.0, gr_dth = 0.0;
-    DevBuf gr_fields, gr_dl;
+    DevBuf gr_fields, gr_dl, gr_pscratch;
     // scratch
     DevBuf sort_keys, sort_idx, sort_keys2, sort_idx2, sort_hist, sort_scan, tile_start;
     DevBuf pscratch;     // sorted copy of the particle state
@@ -380,7 +380,8 @@ void gcb_destroy(gcb_ctx* ctx) {
                       &ctx->sort_idx2,  &ctx->sort_hist,  &ctx->sort_scan,
                       &ctx->tile_start, &ctx->pscratch,   &ctx->stats,     &ctx->ke_partial,
                       &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace,
-                      &ctx->adj_work,   &ctx->adj_samples, &ctx->gr_fields, &ctx->gr_dl};
+                      &ctx->adj_work,   &ctx->adj_samples, &ctx->gr_fields, &ctx->gr_dl,
+                      &ctx->gr_pscratch};
     for (DevBuf* b : bufs) release(*b);
     delete ctx;
 }
@@ -721,6 +722,10 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
         return fail(ctx, GCB_EINVAL, "particle arrays must be non-NULL");
     if (p->n > 0 && !p->qm && !(std::isfinite(prm->qm) && prm->qm != 0.0))
         return fail(ctx, GCB_EINVAL, "params.qm must be finite and non-zero");
+    if (prm->sort_every < 0) return fail(ctx, GCB_EINVAL, "sort_every must be >= 0");
+    if (s_trace && p->n > 0 && !p->id && prm->sort_every > 0)
+        return fail(ctx, GCB_EINVAL, "a switch trace with sorting needs particle ids");
+    if (p->n > ((int64_t)1 << 31) - 1) return fail(ctx, GCB_EINVAL, "n too large");
     if (!ctx->have_gr) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields_gr was not called");
     if (prm->form == GCB_FORM_F64 && ctx->gr_dtype != GCB_F64)
         return fail(ctx, GCB_EINVAL, "GCB_FORM_F64 needs fields loaded as GCB_F64");
@@ -743,18 +748,60 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     g.f_E = prm->f_E;
     g.fp_tol = prm->fp_tol;
     g.n_iter = prm->n_iter;
-    GrPtrs ptrs{p->r, p->th, p->ph, p->ur, p->uth, p->uph, p->qm, p->status};
-    {
-        Timer t(ctx, stream, GCB_TIMER_PUSH);
-        const double* dl = static_cast<const double*>(ctx->gr_dl.ptr);
+    GrPtrs ptrs{p->r, p->th, p->ph, p->ur, p->uth, p->uph, p->qm, p->id, p->status};
+    const double* dl = static_cast<const double*>(ctx->gr_dl.ptr);
+    auto push = [&](const GrPtrs& in, const GrPtrs& out, int ns, int step0) {
         if (prm->form == GCB_FORM_F64)
-            GCB_HIP(launch_gr_push_f64(ptrs, p->n, n_steps,
-                                       static_cast<const double*>(ctx->gr_fields.ptr), dl, g,
-                                       s_trace, dstats, stream));
-        else
-            GCB_HIP(launch_gr_push_mixed(ptrs, p->n, n_steps,
-                                         static_cast<const float*>(ctx->gr_fields.ptr), dl, g,
-                                         s_trace, dstats, stream));
+            return launch_gr_push_f64(in, out, p->n, ns,
+                                      static_cast<const double*>(ctx->gr_fields.ptr), dl, g,
+                                      s_trace, step0, dstats, stream);
+        return launch_gr_push_mixed(in, out, p->n, ns,
+                                    static_cast<const float*>(ctx->gr_fields.ptr), dl, g, s_trace,
+                                    step0, dstats, stream);
+    };
+    if (prm->sort_every > 0 && p->n > 0 && n_steps > 0) {
+        // every sort_every steps: sort by (r, theta) tiles of kGrTile^2 cells
+        // into a scratch copy, then push from the copy back into the caller's
+        // arrays (which end up in tile order, `id` and `qm` carried along)
+        constexpr int kGrTile = 16;
+        const int64_t n = p->n;
+        const size_t ub = prm->form == GCB_FORM_F64 ? sizeof(double) : sizeof(float);
+        SortBuffers sb;
+        TileGeom one{};
+        one.tile = 1;
+        one.ntx = one.nty = 1;
+        int rc;
+        if ((rc = prepare_sort(ctx, n, one, sb))) return rc;
+        const size_t bytes = (size_t)n * (3 * sizeof(double) + 3 * ub + sizeof(double) +
+                                          sizeof(int32_t) + 1);
+        if ((rc = ensure(ctx, ctx->gr_pscratch, bytes))) return rc;
+        char* base = static_cast<char*>(ctx->gr_pscratch.ptr);
+        GrPtrs sc;
+        sc.r = reinterpret_cast<double*>(base);
+        sc.th = sc.r + n;
+        sc.ph = sc.th + n;
+        sc.qm = p->qm ? sc.ph + n : nullptr;
+        char* c = reinterpret_cast<char*>(sc.ph + 2 * n);
+        sc.ur = c;
+        sc.uth = c + n * ub;
+        sc.uph = c + 2 * n * ub;
+        sc.id = p->id ? reinterpret_cast<int32_t*>(c + 3 * n * ub) : nullptr;
+        sc.status = reinterpret_cast<uint8_t*>(c + 3 * n * ub + n * sizeof(int32_t));
+        for (int32_t s0 = 0; s0 < n_steps; s0 += prm->sort_every) {
+            const int ns = std::min<int32_t>(prm->sort_every, n_steps - s0);
+            {
+                Timer t(ctx, stream, GCB_TIMER_SORT);
+                GCB_HIP(launch_gr_cell_sort(p->r, p->th, n, g, kGrTile, sb, stream));
+                GCB_HIP(launch_gr_permute(ptrs, sc, ub, sb.idx, n, stream));
+                t.done();
+            }
+            Timer t(ctx, stream, GCB_TIMER_PUSH);
+            GCB_HIP(push(sc, ptrs, ns, s0));
+            t.done();
+        }
+    } else {
+        Timer t(ctx, stream, GCB_TIMER_PUSH);
+        GCB_HIP(push(ptrs, ptrs, n_steps, 0));
         t.done();
     }
     if (stats) {

@@ -10,6 +10,8 @@
 //     k_radix_scatter  wave-level multisplit ranks -> stable scatter
 //   k_tile_bounds tile_start from the boundaries of the sorted keys
 //   k_permute     gather every state array through idx
+//   k_gr_tile_keys, k_gr_permute: the same for the curved-spacetime state
+//                 ((r, theta) tiles of the grid cells)
 #include <hip/hip_runtime.h>
 
 #include "gcb_internal.h"
@@ -52,6 +54,39 @@ __global__ __launch_bounds__(kSortWG) void k_tile_bounds(const uint32_t* __restr
     const int lo = i == 0 ? -1 : (int)keys[i - 1];
     const int hi = i == n ? ntiles : (int)keys[i];
     for (int t = lo + 1; t <= hi; ++t) tile_start[t] = (int32_t)i;
+}
+
+// key = (r, theta) tile of the particle's grid cell, row-major tiles
+__global__ __launch_bounds__(kSortWG) void k_gr_tile_keys(const double* __restrict__ r,
+                                                          const double* __restrict__ th,
+                                                          int64_t n, gr::GrConst g, int tile,
+                                                          int ntx, uint32_t* keys,
+                                                          uint32_t* idx) {
+    const int64_t p = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
+    if (p >= n) return;
+    int i, j;
+    double wx, wy;
+    gr::grid_cell(g, r[p], th[p], i, j, wx, wy);
+    keys[p] = (uint32_t)((j / tile) * ntx + i / tile);
+    idx[p] = (uint32_t)p;
+}
+
+template <typename U>
+__global__ __launch_bounds__(kSortWG) void k_gr_permute(GrPtrs src, GrPtrs dst,
+                                                        const uint32_t* __restrict__ perm,
+                                                        int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
+    if (i >= n) return;
+    const int64_t s = perm[i];
+    dst.r[i] = src.r[s];
+    dst.th[i] = src.th[s];
+    dst.ph[i] = src.ph[s];
+    static_cast<U*>(dst.ur)[i] = static_cast<const U*>(src.ur)[s];
+    static_cast<U*>(dst.uth)[i] = static_cast<const U*>(src.uth)[s];
+    static_cast<U*>(dst.uph)[i] = static_cast<const U*>(src.uph)[s];
+    if (src.qm) const_cast<double*>(dst.qm)[i] = src.qm[s];
+    if (src.id) dst.id[i] = src.id[s];
+    dst.status[i] = src.status[s];
 }
 
 __global__ __launch_bounds__(kSortWG) void k_radix_hist(const uint32_t* __restrict__ keys,
@@ -249,42 +284,86 @@ int64_t sort_hist_elems(int64_t n) {
 
 int64_t sort_scan_tmp_elems(int64_t n_scan) { return (n_scan + kScanItems - 1) / kScanItems + 1; }
 
+namespace {
+
+// Stable LSD radix sort of (b.keys, b.idx) on the low nbits of the keys;
+// the sorted keys end in *kfinal and the permutation in b.idx.
+hipError_t radix_sort(int64_t n, int nbits, const SortBuffers& b, hipStream_t stream,
+                      uint32_t** kfinal) {
+    uint32_t* kin = b.keys;
+    uint32_t* iin = b.idx;
+    *kfinal = kin;
+    if (n == 0) return hipSuccess;
+    const int nblocks = (int)((n + kItems - 1) / kItems);
+    const int64_t nh = 256ll * nblocks;
+    uint32_t* kout = b.keys2;
+    uint32_t* iout = b.idx2;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortWG), 0, stream, kin, n, shift,
+                           nblocks, b.hist);
+        hipError_t e = scan_exclusive(b.hist, b.hist, nh, b.scan_tmp, stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortWG), 0, stream, kin, iin, n,
+                           shift, nblocks, b.hist, kout, iout);
+        uint32_t* t = kin; kin = kout; kout = t;
+        t = iin; iin = iout; iout = t;
+    }
+    // the sorted permutation must end in b.idx
+    if (iin != b.idx) {
+        hipError_t e = hipMemcpyAsync(b.idx, iin, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice,
+                                      stream);
+        if (e != hipSuccess) return e;
+    }
+    *kfinal = kin;
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_cell_sort(const double* x, const double* y, int64_t n, double inv_dx,
                             double inv_dy, const TileGeom& g, const SortBuffers& b,
                             hipStream_t stream) {
     const int ntiles = g.ntx * g.nty;
-    uint32_t* kin = b.keys;
-    uint32_t* iin = b.idx;
     if (n > 0) {
         const unsigned blocks = (unsigned)((n + kSortWG - 1) / kSortWG);
         hipLaunchKernelGGL(k_tile_keys, dim3(blocks), dim3(kSortWG), 0, stream, x, y, n,
                            inv_dx, inv_dy, g, b.keys, b.idx);
-        int nbits = 0;
-        while ((1 << nbits) < ntiles) ++nbits;
-        const int nblocks = (int)((n + kItems - 1) / kItems);
-        const int64_t nh = 256ll * nblocks;
-        uint32_t* kout = b.keys2;
-        uint32_t* iout = b.idx2;
-        for (int shift = 0; shift < nbits; shift += 8) {
-            hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortWG), 0, stream, kin, n,
-                               shift, nblocks, b.hist);
-            hipError_t e = scan_exclusive(b.hist, b.hist, nh, b.scan_tmp, stream);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortWG), 0, stream, kin,
-                               iin, n, shift, nblocks, b.hist, kout, iout);
-            uint32_t* t = kin; kin = kout; kout = t;
-            t = iin; iin = iout; iout = t;
-        }
-        // the sorted permutation must end in b.idx
-        if (iin != b.idx) {
-            hipError_t e = hipMemcpyAsync(b.idx, iin, sizeof(uint32_t) * n,
-                                          hipMemcpyDeviceToDevice, stream);
-            if (e != hipSuccess) return e;
-        }
     }
+    int nbits = 0;
+    while ((1 << nbits) < ntiles) ++nbits;
+    uint32_t* kin = b.keys;
+    hipError_t e = radix_sort(n, nbits, b, stream, &kin);
+    if (e != hipSuccess) return e;
     const unsigned blocks = (unsigned)((n + 1 + kSortWG - 1) / kSortWG);
     hipLaunchKernelGGL(k_tile_bounds, dim3(blocks), dim3(kSortWG), 0, stream, kin, n, ntiles,
                        b.tile_start);
+    return hipGetLastError();
+}
+
+hipError_t launch_gr_cell_sort(const double* r, const double* th, int64_t n,
+                               const gr::GrConst& g, int tile, const SortBuffers& b,
+                               hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const int ntx = (g.nr + tile - 1) / tile, nty = (g.nth + tile - 1) / tile;
+    const unsigned blocks = (unsigned)((n + kSortWG - 1) / kSortWG);
+    hipLaunchKernelGGL(k_gr_tile_keys, dim3(blocks), dim3(kSortWG), 0, stream, r, th, n, g, tile,
+                       ntx, b.keys, b.idx);
+    int nbits = 0;
+    while ((1 << nbits) < ntx * nty) ++nbits;
+    uint32_t* kin = b.keys;
+    return radix_sort(n, nbits, b, stream, &kin);
+}
+
+hipError_t launch_gr_permute(const GrPtrs& src, const GrPtrs& dst, size_t u_bytes,
+                             const uint32_t* perm, int64_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n + kSortWG - 1) / kSortWG);
+    if (u_bytes == sizeof(double))
+        hipLaunchKernelGGL(k_gr_permute<double>, dim3(blocks), dim3(kSortWG), 0, stream, src,
+                           dst, perm, n);
+    else
+        hipLaunchKernelGGL(k_gr_permute<float>, dim3(blocks), dim3(kSortWG), 0, stream, src,
+                           dst, perm, n);
     return hipGetLastError();
 }
 

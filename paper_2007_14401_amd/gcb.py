@@ -70,7 +70,7 @@ class gcb_gr_desc(C.Structure):
 class gcb_gr_particles(C.Structure):
     _fields_ = [("n", C.c_int64), ("r", C.c_void_p), ("th", C.c_void_p), ("ph", C.c_void_p),
                 ("ur", C.c_void_p), ("uth", C.c_void_p), ("uph", C.c_void_p),
-                ("qm", C.c_void_p), ("status", C.c_void_p)]
+                ("qm", C.c_void_p), ("id", C.c_void_p), ("status", C.c_void_p)]
 
 
 def _load():
@@ -258,12 +258,13 @@ def gcb_load_fields_gr(ctx, desc: gcb_gr_desc, D, B, src=None, stream=None) -> N
 
 def gr_particles(t: dict) -> gcb_gr_particles:
     """Build the struct from a dict of tensors r, th, ph, ur, uth, uph, status
-    and optional qm."""
+    and optional qm, id."""
     p = gcb_gr_particles()
     p.n = int(t["r"].shape[0])
     for k in ("r", "th", "ph", "ur", "uth", "uph", "status"):
         setattr(p, k, _ptr(t[k]))
     p.qm = _ptr(t.get("qm"))
+    p.id = _ptr(t.get("id"))
     return p
 
 

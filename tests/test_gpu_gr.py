@@ -54,11 +54,12 @@ class GrRun:
         self.gcb.gcb_destroy(self.ctx)
 
 
-def to_device(e, per_particle_qm=True, mixed=False):
+def to_device(e, per_particle_qm=True, mixed=False, with_id=False):
     t = {k: torch.as_tensor(np.ascontiguousarray(getattr(e, k)),
                             dtype=torch.float32 if (mixed and k[0] == "u") else torch.float64,
                             device=DEV) for k in NAMES}
     t["status"] = torch.zeros(e.n, dtype=torch.uint8, device=DEV)
+    t["id"] = torch.arange(e.n, dtype=torch.int32, device=DEV) if with_id else None
     t["qm"] = (torch.as_tensor(e.qm, dtype=torch.float64, device=DEV)
                if per_particle_qm else None)
     return t
@@ -152,6 +153,26 @@ def test_gr_scalar_qm(g64):
     tr, _ = run.push(t, 8)
     ref, S, _ = run_oracle(cfg, F, e, 8)
     compare(t, ref, tr, S, what="gr scalar q/m")
+
+
+@pytest.mark.parametrize("sort_every,steps", [(1, 3), (3, 10), (8, 17)])
+def test_gr_sorted(g64, sort_every, steps):
+    """With params.sort_every the particles are permuted into (r, theta) tile
+    order (ids, q/m and status carried along); each particle's arithmetic is
+    unchanged, so after undoing the permutation by id the state and the
+    trace (indexed by id) equal the oracle's bit for bit."""
+    cfg, F, run = g64
+    e = cfg.particles(n=2500, seed_offset=12)
+    t = to_device(e, with_id=True)
+    tr, _ = run.push(t, steps, sort_every=sort_every)
+    ids = t["id"].cpu().numpy()
+    assert np.array_equal(np.sort(ids), np.arange(e.n))
+    order = np.argsort(ids)
+    got = {k: v[torch.as_tensor(order, device=DEV)] for k, v in t.items() if v is not None}
+    ref, S, _ = run_oracle(cfg, F, e, steps)
+    compare(got, ref, tr, S, what=f"gr sorted every {sort_every}")
+    # the stored order is the tile order of the positions at the last sort
+    assert not np.array_equal(ids, np.arange(e.n))
 
 
 def test_gr_edge_cases(g64):
