@@ -101,30 +101,63 @@ def measured_traffic(workload: str, n: int, sort_every: int, tile: int):
 def cpu_baseline(cfg, F, ens, budget_s: float = 20.0):
     """The CPU oracle (torch float64) on a bounded sample of the same workload:
     a random subset of the particles, pushed for up to the workload's step
-    count or about `budget_s` seconds."""
+    count or about `budget_s` seconds with all host threads, then a smaller
+    subset on one thread."""
     import numpy as np
     import torch
 
     import oracle as O
-    n = 60000
-    rng = np.random.default_rng(5)
-    sub = ens.subset(np.sort(rng.choice(ens.n, n, replace=False)))
     p = O.Params(dt=cfg.dt, c=cfg.c, f_rho=cfg.f_rho, f_E=cfg.f_E, curvature=True,
                  n_iter=cfg.n_iter, Lx=cfg.Lx, Ly=cfg.Ly, dl=math.sqrt(cfg.dx * cfg.dy))
     prov = O.GridFields(F, cfg.dx, cfg.dy, cfg.stagger)
-    st = O.State.from_numpy(sub)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        st, _, _ = O.step(prov, st, p)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or steps >= cfg.steps:
-            break
-    return {"value": n * steps / el, "unit": "particle-steps/s",
-            "cores": int(torch.get_num_threads()), "kind": "oracle",
+    rng = np.random.default_rng(5)
+
+    def run(n, budget):
+        sub = ens.subset(np.sort(rng.choice(ens.n, n, replace=False)))
+        st = O.State.from_numpy(sub)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            st, _, _ = O.step(prov, st, p)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget or steps >= cfg.steps:
+                break
+        return n * steps / el, steps, el
+
+    threads = int(torch.get_num_threads())
+    n = 60000
+    v, steps, el = run(n, budget_s)
+    torch.set_num_threads(1)
+    try:
+        n1 = 4000
+        v1, steps1, el1 = run(n1, 0.25 * budget_s)
+    finally:
+        torch.set_num_threads(threads)
+    return {"value": v, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} random particles of the workload x {steps} steps "
-                      f"({el:.1f} s, torch CPU float64)"}
+                      f"({el:.1f} s, torch CPU float64, {threads} threads)",
+            "single_thread": {"value": v1, "sample": f"{n1} particles x {steps1} steps "
+                                                     f"({el1:.1f} s, 1 thread)"}}
+
+
+def copy_bandwidth(dev, gib: float = 1.0, reps: int = 5) -> float:
+    """Measured device-to-device copy rate (read + write bytes per second) of a
+    gib-GiB buffer: the practical HBM ceiling beside the published peak."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / el / 1e9
 
 
 def main():
@@ -349,6 +382,7 @@ def main():
         forms["fwd_adjoint"] = time_fwd_adjoint(a.adjoint_steps, 32)
         forms["fwd_adjoint"]["speed_vs_f64_forward"] = forms["fwd_adjoint"]["value"] / value
 
+    copy_gbs = copy_bandwidth(dev)
     if a.copy_calib:
         x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
@@ -389,6 +423,7 @@ def main():
                      "algorithmic_flops_per_particle_step": flops,
                      "algorithmic_flops_per_launch": flops * n,
                      "hbm_achieved_GBs": achieved, "hbm_peak_GBs": HBM_PEAK_GBS,
+                     "hbm_copy_measured_GBs": copy_gbs,
                      "hbm_frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": bytes_step,
                      "traffic_over_algorithmic": (traffic / bytes_step) if traffic else None},

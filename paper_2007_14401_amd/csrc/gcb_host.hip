@@ -311,7 +311,16 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         if ((rc = prepare_sort(ctx, n, g, sb))) return rc;
         if ((rc = scratch_state<U>(ctx, user, n, scr))) return rc;
     }
-    for (int32_t step = 0; step < n_steps; ++step) {
+    // the global kernel keeps a particle in registers for up to
+    // kGlobalStepsPerLaunch steps (not past the next sort)
+    constexpr int32_t kGlobalStepsPerLaunch = 16;
+    for (int32_t step = 0; step < n_steps;) {
+        int32_t ns = 1;
+        if (kind == PushKind::Global) {
+            ns = std::min(kGlobalStepsPerLaunch, n_steps - step);
+            if (prm->sort_every > 0)
+                ns = std::min(ns, prm->sort_every - step % prm->sort_every);
+        }
         ParticlePtrs<U> src = user;
         if (prm->sort_every > 0 && n > 0 && step % prm->sort_every == 0) {
             Timer t(ctx, stream, GCB_TIMER_SORT);
@@ -330,6 +339,7 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         L.trace = s_trace ? s_trace + (int64_t)step * n : nullptr;
         L.replay = prm->replay != 0;
         L.stats = dstats;
+        L.steps = ns;
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))
@@ -339,6 +349,7 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         if (e != hipSuccess)
             return fail(ctx, GCB_EHIP, "push kernel launch failed: %s", hipGetErrorString(e));
         t.done();
+        step += ns;
     }
     return GCB_OK;
 }

@@ -32,6 +32,7 @@ struct PushLaunch {
     uint8_t* trace;        // nullable: trace row of this step
     bool replay;           // read the decisions from `trace` instead of writing them
     DevStats* stats;       // nullable
+    int steps = 1;         // global kernel: steps per launch (trace: steps*n bytes)
 };
 
 // binary64 form (fields double, u double)

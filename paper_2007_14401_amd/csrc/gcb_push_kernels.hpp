@@ -101,33 +101,47 @@ __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Reg
     return fl | finite_flag(r);
 }
 
+// ns steps of one particle per lane (the particle stays in registers between
+// them); trace (per step n bytes) is indexed by id when ids are present
 template <typename R, typename T, bool kYee>
 __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, ParticlePtrs<R> out,
-                                                      int64_t n, const T* __restrict__ F,
+                                                      int64_t n, int ns, const T* __restrict__ F,
                                                       PushConst pc, uint8_t* trace,
                                                       bool replay, DevStats* stats) {
     const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
     const bool active = p < n;
-    bool gca = false;
-    double res = 0.0;
+    unsigned cnt_g = 0, cnt_b = 0;
+    double maxres = 0.0;
     if (active) {
         const Consts<R> K = make_consts<R>(pc);
         GlobalAcc<T> acc{F, pc.nx, pc.ny};
         Regs<R> r;
         load_particle(in, p, pc.qm, r);
         const int64_t ti = in.id ? (int64_t)in.id[p] : p;
-        if (replay) {
-            gca = trace[ti] == 0;
-        } else {
-            Sample<R> s;
-            gather<R, false, kYee>(acc, pc, K, r.x, r.y, s);
-            gca = switch_gca(s.E, s.B, r.ux, r.uy, r.uz, r.qm, pc, K);
+        uint32_t fl = 0;
+        for (int s = 0; s < ns; ++s) {
+            uint8_t* tr = trace ? trace + (size_t)s * n : nullptr;
+            bool gca;
+            if (replay) {
+                gca = tr[ti] == 0;
+            } else {
+                Sample<R> smp;
+                gather<R, false, kYee>(acc, pc, K, r.x, r.y, smp);
+                gca = switch_gca(smp.E, smp.B, r.ux, r.uy, r.uz, r.qm, pc, K);
+            }
+            double res;
+            fl |= coupled_update<R, kYee>(acc, gca, r, pc, K, res);
+            if (tr && !replay) tr[ti] = gca ? 0 : 1;
+            if (gca) {
+                ++cnt_g;
+                maxres = nan_max(maxres, res);
+            } else {
+                ++cnt_b;
+            }
         }
-        const uint32_t fl = coupled_update<R, kYee>(acc, gca, r, pc, K, res);
         store_particle(in, out, p, r, fl);
-        if (trace && !replay) trace[ti] = gca ? 0 : 1;
     }
-    if (stats) flush_stats(stats, active && gca, active && !gca, 0, res);
+    if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
 template <typename R, typename T, bool kYee, int kMinWaves>
@@ -259,12 +273,13 @@ hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
     const T* F = static_cast<const T*>(L.fields);
     if (L.kind == PushKind::Global) {
         const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
+        const int ns = L.steps > 0 ? L.steps : 1;
         if (L.yee)
             hipLaunchKernelGGL((k_push_global<R, T, true>), dim3(blocks), dim3(kWG), 0, stream,
-                               in, out, L.n, F, pc, L.trace, L.replay, L.stats);
+                               in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
         else
             hipLaunchKernelGGL((k_push_global<R, T, false>), dim3(blocks), dim3(kWG), 0,
-                               stream, in, out, L.n, F, pc, L.trace, L.replay, L.stats);
+                               stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
         return hipGetLastError();
     }
     const int ntiles = L.geom.ntx * L.geom.nty;

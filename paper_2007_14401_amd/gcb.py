@@ -13,6 +13,14 @@ import os
 
 import numpy as np
 
+try:
+    # torch ships its own HIP runtime; loading it before libgcb.so makes the
+    # library bind to that same runtime (two runtimes in one process do not
+    # share devices or memory)
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("GCB_LIBRARY", os.path.join(_HERE, "libgcb.so"))
 
@@ -142,6 +150,13 @@ def _stream_ptr(stream):
 
 
 def gcb_create(device: int = 0):
+    # let torch set up its HIP context first: the caller's tensors live there
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     h = C.c_void_p()
     _check(_lib.gcb_create(C.byref(h), int(device)))
     return h
