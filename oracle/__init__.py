@@ -18,6 +18,12 @@ Layout of the oracle:
               scheme (Sec. 3.1) and the multi-step driver.
   loss.py     mean kinetic energy and its gradient by reverse-mode autograd of
               the oracle itself (the oracle gradient of the adjoint checks).
+  fields3d.py the 3D gather: trilinear interpolation with a linear shape
+              function and its gradient on a staggered periodic 3D grid, plus
+              closed-form 3D providers used by the pins.
+  pusher3d.py the coupled step in three dimensions (trilinear gather,
+              gradients along z, three-component guiding-center position);
+              reuses the dimension-free functions of pusher.py.
   gr.py       the general-relativistic coupled scheme (Sec. 2.3, 2.4, 3.2) in
               Kerr-Schild coordinates: metric functions and derivatives, the
               (r, theta) grid gather, the local-frame half pushes, the
@@ -33,6 +39,9 @@ from .pusher import (Params, State, ST_NONFINITE, ST_KAPPA, ST_QUAD, ST_BZERO,
                      ST_FPRES, local, gamma_gca, v_curv, switch_gca, boris,
                      gca_step, step, push, wrap, min_image, parallel_update)
 from .loss import kinetic_energy, push_gradients
+from .fields3d import (GridFields3, UniformFields3, LinearFields3, CircularFieldsXZ,
+                       FieldSample3, YEE3, COLLOCATED3)
+from .pusher3d import Params3, State3, local3, boris_step3, gca_step3, step3, push3
 
 __all__ = [
     "GridFields", "UniformFields", "LinearFields", "CircularFields",
@@ -40,4 +49,7 @@ __all__ = [
     "ST_KAPPA", "ST_QUAD", "ST_BZERO", "ST_FPRES", "local", "gamma_gca",
     "v_curv", "switch_gca", "boris", "gca_step", "step", "push", "wrap",
     "min_image", "parallel_update", "kinetic_energy", "push_gradients",
+    "GridFields3", "UniformFields3", "LinearFields3", "CircularFieldsXZ", "FieldSample3",
+    "YEE3", "COLLOCATED3", "Params3", "State3", "local3", "boris_step3", "gca_step3",
+    "step3", "push3",
 ]

@@ -15,6 +15,8 @@ from .harris import YEE_STAGGER, COLLOCATED, COMPONENTS, harris_fields
 from .particles import (maxwell_juttner_u, power_law_gamma, isotropic_dirs,
                         initial_state, Ensemble)
 from .configs import CONFIGS, make_config, Config
+from .harris3d import YEE3_STAGGER, harris3d_fields
+from .configs3d import CONFIGS3, Config3, Ensemble3, initial_state3, make_config3
 from .gr import (GR_CONFIGS, GRConfig, GREnsemble, make_gr_config, magnetosphere_fields,
                  magnetosphere_particles)
 
@@ -23,4 +25,6 @@ __all__ = [
     "maxwell_juttner_u", "power_law_gamma", "isotropic_dirs", "initial_state",
     "Ensemble", "CONFIGS", "make_config", "Config", "GR_CONFIGS", "GRConfig",
     "GREnsemble", "make_gr_config", "magnetosphere_fields", "magnetosphere_particles",
+    "YEE3_STAGGER", "harris3d_fields", "CONFIGS3", "Config3", "Ensemble3",
+    "initial_state3", "make_config3",
 ]
