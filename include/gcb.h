@@ -264,6 +264,54 @@ typedef struct {
 int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm,
                 int32_t n_steps, uint8_t* s_trace, gcb_stats* stats, void* stream);
 
+/* ---------------------------------------------------------------------------
+   Three dimensions: the coupled scheme of gcb_push (same equations, switch,
+   params and status bits) on a periodic 3D box [0, nx dx) x [0, ny dy) x
+   [0, nz dz).  The gather is the linear shape function in three dimensions
+   (Sec. 4, opening paragraph): trilinear interpolation on the 2 x 2 x 2 nodes
+   of each component's own lattice, summed z plane by z plane, with gradients
+   along x, y and z; (b.grad)b and (v_E.grad)b then include the z
+   derivatives, and the guiding-center position R has three components.
+   The cell size of the switch is dl = (dx dy dz)^(1/3) (Sec. 3, effective
+   cell size).  The adjoint (gcb_push_backward) is two-dimensional only. */
+typedef struct {
+    int32_t n[3];            /* nx, ny, nz: nodes per axis, each in [2, 2^24] */
+    int32_t dtype;           /* GCB_F64 or GCB_F32: precision of the device copy */
+    double  d[3];            /* dx, dy, dz > 0 */
+    double  stagger[6][3];   /* offsets in cells, each in [0, 1); the 3D Yee
+                                lattice is Ex (1/2,0,0), Ey (0,1/2,0), Ez (0,0,1/2),
+                                Bx (0,1/2,1/2), By (1/2,0,1/2), Bz (1/2,1/2,0) */
+} gcb_grid3_desc;
+
+/* Copy the six components into context-owned device storage (node
+   interleaved, converted to desc->dtype).  E[c] and B[c] point to nx*ny*nz
+   doubles, element [(l*ny + j)*nx + i] at node (i, j, l), host (GCB_HOST) or
+   device (GCB_DEVICE) memory, caller-owned.  Replaces earlier 3D fields; the
+   2D and curved-spacetime fields are independent.  Host sources are copied
+   before the call returns. */
+int gcb_load_fields_3d(gcb_ctx* ctx, const gcb_grid3_desc* desc,
+                       const double* const E[3], const double* const B[3],
+                       int32_t src, void* stream);
+
+/* 3D particle state: gcb_particles with z and its previous value. */
+typedef struct {
+    int64_t  n;
+    double  *x, *y, *z;      /* x^n, wrapped into the box */
+    double  *xp, *yp, *zp;   /* x^{n-1} (any periodic image) */
+    void    *ux, *uy, *uz;   /* u^{n-1/2}: double (GCB_FORM_F64) or float (GCB_FORM_MIXED) */
+    double  *qm;             /* optional per-particle q/m (NULL: params.qm) */
+    int32_t *id;             /* optional particle ids; values in [0, n) when a switch
+                                trace is requested with sorting */
+    uint8_t *status;         /* required: sticky GCB_ST_* bits */
+} gcb_particles3;
+
+/* Advance by n_steps coupled steps in 3D.  Arguments, sorting (cubic tiles of
+   params.tile cells, 0 = 6; the LDS window holds (tile + 2 halo)^3 nodes of
+   six components and must fit in 160 KiB for the tiled kernel), switch trace,
+   replay and stats behave as for gcb_push. */
+int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm,
+                int32_t n_steps, uint8_t* s_trace, gcb_stats* stats, void* stream);
+
 /* Kernel timing with HIP events recorded around every launch on the launch
    stream.  gcb_set_timing(ctx, 1) clears and enables; gcb_get_timing
    synchronises on the recorded events and returns, for each kernel class,

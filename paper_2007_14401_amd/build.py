@@ -33,6 +33,8 @@ UNITS = {
     "gcb_util.hip": ["-ffp-contract=off"],
     "gcb_gr.hip": ["-ffp-contract=off"],
     "gcb_gr_mixed.hip": [],
+    "gcb_push3_f64.hip": ["-ffp-contract=off"],
+    "gcb_push3_mixed.hip": [],
 }
 
 

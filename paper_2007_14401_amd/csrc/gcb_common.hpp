@@ -39,13 +39,6 @@ struct PushConst {
     int32_t curvature, n_iter;
 };
 
-// Register copy of one particle's state.
-struct ParticleRegs {
-    double x, y, xp, yp;
-    double ux, uy, uz;
-    double qm;
-};
-
 // Device pointers of a structure-of-arrays particle state.
 template <typename U>
 struct ParticlePtrs {
@@ -59,6 +52,23 @@ struct ParticlePtrs {
     double* qm;      // may be null
     int32_t* id;     // may be null
     uint8_t* status;
+};
+
+// 3D lattice: the constants of a 2D launch (physics, x and y geometry, the
+// x and y lattice offsets in b.stagger) plus the z geometry.
+struct PushConst3 {
+    PushConst b;
+    double inv_dz, Lz;
+    double sz[6];            // z offsets of the lattices, in cells
+    int32_t nz, pad_;
+};
+
+// 3D state: the 2D arrays plus z and its previous value.
+template <typename U>
+struct ParticlePtrs3 {
+    ParticlePtrs<U> b;
+    double* z;
+    double* zp;
 };
 
 // Accumulators filled by the push kernels when statistics are requested:

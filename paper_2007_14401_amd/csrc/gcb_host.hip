@@ -46,6 +46,14 @@ struct gcb_ctx {
     gr::GrConst gr{};
     double gr_dr = 0.0, gr_dth = 0.0;
     DevBuf gr_fields, gr_dl, gr_pscratch;
+    // 3D fields
+    bool have_f3 = false;
+    int n3[3] = {};
+    double d3[3] = {1.0, 1.0, 1.0};
+    double stagger3[6][3] = {};
+    int dtype3 = GCB_F64;
+    bool yee3 = false;
+    DevBuf fields3;
     // scratch
     DevBuf sort_keys, sort_idx, sort_keys2, sort_idx2, sort_hist, sort_scan, tile_start;
     DevBuf pscratch;     // sorted copy of the particle state
@@ -135,6 +143,8 @@ struct Timer {
 
 const double kYee[6][2] = {{0.5, 0.0}, {0.0, 0.5}, {0.0, 0.0},
                            {0.0, 0.5}, {0.5, 0.0}, {0.5, 0.5}};
+const double kYee3[6][3] = {{0.5, 0.0, 0.0}, {0.0, 0.5, 0.0}, {0.0, 0.0, 0.5},
+                            {0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0}};
 
 int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
     if (!prm) return fail(ctx, GCB_EINVAL, "params is NULL");
@@ -196,12 +206,14 @@ ParticlePtrs<U> ptrs_of(const gcb_particles* p) {
     return r;
 }
 
-// carve a scratch copy of the state (same shape as `like`) out of one buffer
+// carve a scratch copy of the state (same shape as `like`) out of one
+// buffer, plus n_extra more double arrays of n
 template <typename U>
-int scratch_state(gcb_ctx* ctx, const ParticlePtrs<U>& like, int64_t n, ParticlePtrs<U>& out) {
+int scratch_state(gcb_ctx* ctx, const ParticlePtrs<U>& like, int64_t n, ParticlePtrs<U>& out,
+                  int n_extra = 0, double** extra = nullptr) {
     const size_t nd = (size_t)n * sizeof(double), nu = (size_t)n * sizeof(U);
     auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    size_t bytes = 4 * up(nd) + 3 * up(nu) + up(n) + (like.qm ? up(nd) : 0) +
+    size_t bytes = (4 + n_extra) * up(nd) + 3 * up(nu) + up(n) + (like.qm ? up(nd) : 0) +
                    (like.id ? up((size_t)n * 4) : 0);
     int rc = ensure(ctx, ctx->pscratch, bytes);
     if (rc) return rc;
@@ -221,30 +233,73 @@ int scratch_state(gcb_ctx* ctx, const ParticlePtrs<U>& like, int64_t n, Particle
     out.status = reinterpret_cast<uint8_t*>(take(n));
     out.qm = like.qm ? reinterpret_cast<double*>(take(nd)) : nullptr;
     out.id = like.id ? reinterpret_cast<int32_t*>(take((size_t)n * 4)) : nullptr;
+    for (int e = 0; e < n_extra; ++e) extra[e] = reinterpret_cast<double*>(take(nd));
     return GCB_OK;
 }
 
-PushConst make_const(const gcb_ctx* ctx, const gcb_params* prm) {
-    PushConst pc;
+// the physics constants of a launch (geometry left to the caller)
+PushConst physics_const(const gcb_params* prm) {
+    PushConst pc{};
     pc.dt = prm->dt;
     pc.c = prm->c;
     pc.c2 = prm->c * prm->c;
     pc.inv_c2 = 1.0 / (prm->c * prm->c);
     pc.f_rho = prm->f_rho;
     pc.f_E = prm->f_E;
-    pc.inv_dl = 1.0 / std::sqrt(ctx->dx * ctx->dy);
     pc.fp_tol = prm->fp_tol;
+    pc.qm = prm->qm;
+    pc.curvature = prm->curvature;
+    pc.n_iter = prm->n_iter;
+    return pc;
+}
+
+PushConst make_const(const gcb_ctx* ctx, const gcb_params* prm) {
+    PushConst pc = physics_const(prm);
+    pc.inv_dl = 1.0 / std::sqrt(ctx->dx * ctx->dy);
     pc.inv_dx = 1.0 / ctx->dx;
     pc.inv_dy = 1.0 / ctx->dy;
     pc.Lx = ctx->nx * ctx->dx;
     pc.Ly = ctx->ny * ctx->dy;
-    pc.qm = prm->qm;
     std::memcpy(pc.stagger, ctx->stagger, sizeof(pc.stagger));
     pc.nx = ctx->nx;
     pc.ny = ctx->ny;
-    pc.curvature = prm->curvature;
-    pc.n_iter = prm->n_iter;
     return pc;
+}
+
+// 3D: the effective cell size of the switch is (dx dy dz)^(1/3) (Sec. 3)
+PushConst3 make_const3(const gcb_ctx* ctx, const gcb_params* prm) {
+    PushConst3 pc{};
+    pc.b = physics_const(prm);
+    pc.b.inv_dl = 1.0 / std::cbrt((ctx->d3[0] * ctx->d3[1]) * ctx->d3[2]);
+    pc.b.inv_dx = 1.0 / ctx->d3[0];
+    pc.b.inv_dy = 1.0 / ctx->d3[1];
+    pc.inv_dz = 1.0 / ctx->d3[2];
+    pc.b.Lx = ctx->n3[0] * ctx->d3[0];
+    pc.b.Ly = ctx->n3[1] * ctx->d3[1];
+    pc.Lz = ctx->n3[2] * ctx->d3[2];
+    for (int k = 0; k < 6; ++k) {
+        pc.b.stagger[k][0] = ctx->stagger3[k][0];
+        pc.b.stagger[k][1] = ctx->stagger3[k][1];
+        pc.sz[k] = ctx->stagger3[k][2];
+    }
+    pc.b.nx = ctx->n3[0];
+    pc.b.ny = ctx->n3[1];
+    pc.nz = ctx->n3[2];
+    return pc;
+}
+
+TileGeom3 make_geom3(const gcb_ctx* ctx, const gcb_params* prm) {
+    TileGeom3 g;
+    g.tile = prm->tile ? prm->tile : 6;
+    const double inv_min =
+        std::max(1.0 / ctx->d3[0], std::max(1.0 / ctx->d3[1], 1.0 / ctx->d3[2]));
+    const int se = prm->sort_every > 0 ? prm->sort_every : 1;
+    g.halo = (int)std::ceil(se * prm->c * prm->dt * inv_min) + 1;
+    g.ntx = (ctx->n3[0] + g.tile - 1) / g.tile;
+    g.nty = (ctx->n3[1] + g.tile - 1) / g.tile;
+    g.ntz = (ctx->n3[2] + g.tile - 1) / g.tile;
+    g.window = g.tile + 2 * g.halo;
+    return g;
 }
 
 TileGeom make_geom(const gcb_ctx* ctx, const gcb_params* prm) {
@@ -261,8 +316,7 @@ TileGeom make_geom(const gcb_ctx* ctx, const gcb_params* prm) {
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-int prepare_sort(gcb_ctx* ctx, int64_t n, const TileGeom& g, SortBuffers& sb) {
-    const int ntiles = g.ntx * g.nty;
+int prepare_sort(gcb_ctx* ctx, int64_t n, int ntiles, SortBuffers& sb) {
     int rc;
     if ((rc = ensure(ctx, ctx->sort_keys, (size_t)n * 4))) return rc;
     if ((rc = ensure(ctx, ctx->sort_idx, (size_t)n * 4))) return rc;
@@ -283,6 +337,94 @@ int prepare_sort(gcb_ctx* ctx, int64_t n, const TileGeom& g, SortBuffers& sb) {
     return GCB_OK;
 }
 
+constexpr size_t kStatBytes = kStatSlots * sizeof(DevStats) + sizeof(DevStats);
+
+// zero the device accumulators of a push that reports statistics
+int stats_begin(gcb_ctx* ctx, const gcb_stats* stats, hipStream_t stream, DevStats** dstats) {
+    *dstats = nullptr;
+    if (!stats) return GCB_OK;
+    int rc;
+    if ((rc = ensure(ctx, ctx->stats, kStatBytes))) return rc;
+    *dstats = static_cast<DevStats*>(ctx->stats.ptr);
+    GCB_HIP(hipMemsetAsync(*dstats, 0, kStatBytes, stream));
+    return GCB_OK;
+}
+
+// count the flagged particles, copy the accumulators back and sum the slots
+int stats_end(gcb_ctx* ctx, const uint8_t* status, int64_t n, gcb_stats* stats,
+              hipStream_t stream) {
+    if (!stats) return GCB_OK;
+    DevStats* dstats = static_cast<DevStats*>(ctx->stats.ptr);
+    // the flagged count goes to the first word after the slots
+    unsigned long long* flagged = reinterpret_cast<unsigned long long*>(dstats + kStatSlots);
+    GCB_HIP(launch_count_flagged(status, n, flagged, stream));
+    std::vector<DevStats> host(kStatSlots + 1);
+    GCB_HIP(hipMemcpyAsync(host.data(), dstats, kStatBytes, hipMemcpyDeviceToHost, stream));
+    GCB_HIP(hipStreamSynchronize(stream));
+    unsigned long long g = 0, b = 0, h = 0, mbits = 0;
+    for (int s = 0; s < kStatSlots; ++s) {
+        g += host[s].gca_steps;
+        b += host[s].boris_steps;
+        h += host[s].halo_misses;
+        // non-negative doubles order like their bit patterns
+        mbits = host[s].max_res_bits > mbits ? host[s].max_res_bits : mbits;
+    }
+    stats->gca_steps = (int64_t)g;
+    stats->boris_steps = (int64_t)b;
+    stats->halo_misses = (int64_t)h;
+    double m;
+    std::memcpy(&m, &mbits, sizeof(m));
+    stats->max_fp_residual = m;
+    stats->flagged = (int64_t)host[kStatSlots].gca_steps;
+    return GCB_OK;
+}
+
+// Copy six field components of rows*row_len nodes each (host or device
+// arrays of doubles) into `dst`, node-interleaved, as float if requested.
+int upload_interleaved(gcb_ctx* ctx, const double* const comps[6], int row_len, int rows,
+                       DevBuf& dst, bool to_float, int32_t src, hipStream_t stream) {
+    const int64_t nodes = (int64_t)row_len * rows;
+    int rc = ensure(ctx, dst, (size_t)nodes * 6 * (to_float ? sizeof(float) : sizeof(double)));
+    if (rc) return rc;
+    if (src == GCB_DEVICE) {
+        GCB_HIP(launch_interleave_fields(comps, row_len, rows, dst.ptr, to_float, stream));
+        return GCB_OK;
+    }
+    DevBuf tmp;
+    rc = ensure(ctx, tmp, (size_t)nodes * 6 * sizeof(double));
+    if (rc) return rc;
+    const double* dcomps[6];
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 6 && e == hipSuccess; ++k) {
+        double* d = static_cast<double*>(tmp.ptr) + k * nodes;
+        e = hipMemcpyAsync(d, comps[k], nodes * sizeof(double), hipMemcpyHostToDevice, stream);
+        dcomps[k] = d;
+    }
+    if (e == hipSuccess)
+        e = launch_interleave_fields(dcomps, row_len, rows, dst.ptr, to_float, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    release(tmp);
+    if (e != hipSuccess) return fail(ctx, GCB_EHIP, "field conversion: %s", hipGetErrorString(e));
+    return GCB_OK;
+}
+
+// kind of kernel for a request (tiled needs sorting and a window that fits)
+int choose_kind(gcb_ctx* ctx, const gcb_params* prm, bool tiled_ok, int window,
+                PushKind* kind) {
+    if (prm->kernel == GCB_KERNEL_TILED) {
+        if (!tiled_ok)
+            return fail(ctx, GCB_EUNSUPPORTED,
+                        "tiled kernel needs sort_every > 0 and a tile window that fits in "
+                        "LDS (window %d nodes)", window);
+        *kind = PushKind::Tiled;
+    } else if (prm->kernel == GCB_KERNEL_GLOBAL) {
+        *kind = PushKind::Global;
+    } else {
+        *kind = tiled_ok ? PushKind::Tiled : PushKind::Global;
+    }
+    return GCB_OK;
+}
+
 template <typename U>
 int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_steps,
              uint8_t* s_trace, DevStats* dstats, hipStream_t stream) {
@@ -292,23 +434,13 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     const size_t esz = prm->form == GCB_FORM_F64 ? sizeof(double) : sizeof(float);
     const bool tiled_ok = prm->sort_every > 0 && tiled_lds_bytes(g.window, esz) <= kMaxLds;
     PushKind kind;
-    if (prm->kernel == GCB_KERNEL_TILED) {
-        if (!tiled_ok)
-            return fail(ctx, GCB_EUNSUPPORTED,
-                        "tiled kernel needs sort_every > 0 and a tile window that fits in "
-                        "LDS (window %d nodes)", g.window);
-        kind = PushKind::Tiled;
-    } else if (prm->kernel == GCB_KERNEL_GLOBAL) {
-        kind = PushKind::Global;
-    } else {
-        kind = tiled_ok ? PushKind::Tiled : PushKind::Global;
-    }
+    int rc;
+    if ((rc = choose_kind(ctx, prm, tiled_ok, g.window, &kind))) return rc;
     ParticlePtrs<U> user = ptrs_of<U>(p);
     ParticlePtrs<U> scr{};
     SortBuffers sb{};
-    int rc;
     if (prm->sort_every > 0 && n > 0) {
-        if ((rc = prepare_sort(ctx, n, g, sb))) return rc;
+        if ((rc = prepare_sort(ctx, n, g.ntx * g.nty, sb))) return rc;
         if ((rc = scratch_state<U>(ctx, user, n, scr))) return rc;
     }
     // the global kernel keeps a particle in registers for up to
@@ -346,6 +478,89 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
             e = launch_push_f64(L, src, user, pc, stream);
         else
             e = launch_push_mixed(L, src, user, pc, stream);
+        if (e != hipSuccess)
+            return fail(ctx, GCB_EHIP, "push kernel launch failed: %s", hipGetErrorString(e));
+        t.done();
+        step += ns;
+    }
+    return GCB_OK;
+}
+
+template <typename U>
+ParticlePtrs3<U> ptrs3_of(const gcb_particles3* p) {
+    ParticlePtrs3<U> r;
+    r.b.x = p->x;
+    r.b.y = p->y;
+    r.b.xp = p->xp;
+    r.b.yp = p->yp;
+    r.b.ux = static_cast<U*>(p->ux);
+    r.b.uy = static_cast<U*>(p->uy);
+    r.b.uz = static_cast<U*>(p->uz);
+    r.b.qm = p->qm;
+    r.b.id = p->id;
+    r.b.status = p->status;
+    r.z = p->z;
+    r.zp = p->zp;
+    return r;
+}
+
+template <typename U>
+int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_steps,
+              uint8_t* s_trace, DevStats* dstats, hipStream_t stream) {
+    const int64_t n = p->n;
+    const PushConst3 pc = make_const3(ctx, prm);
+    const TileGeom3 g = make_geom3(ctx, prm);
+    const size_t esz = prm->form == GCB_FORM_F64 ? sizeof(double) : sizeof(float);
+    const bool tiled_ok = prm->sort_every > 0 && tiled3_lds_bytes(g.window, esz) <= kMaxLds;
+    PushKind kind;
+    int rc;
+    if ((rc = choose_kind(ctx, prm, tiled_ok, g.window, &kind))) return rc;
+    ParticlePtrs3<U> user = ptrs3_of<U>(p);
+    ParticlePtrs3<U> scr{};
+    SortBuffers sb{};
+    if (prm->sort_every > 0 && n > 0) {
+        if ((rc = prepare_sort(ctx, n, g.ntx * g.nty * g.ntz, sb))) return rc;
+        double* zz[2];
+        if ((rc = scratch_state<U>(ctx, user.b, n, scr.b, 2, zz))) return rc;
+        scr.z = zz[0];
+        scr.zp = zz[1];
+    }
+    // the global kernel keeps a particle in registers for up to
+    // kGlobalStepsPerLaunch steps (not past the next sort)
+    constexpr int32_t kGlobalStepsPerLaunch = 16;
+    for (int32_t step = 0; step < n_steps;) {
+        int32_t ns = 1;
+        if (kind == PushKind::Global) {
+            ns = std::min(kGlobalStepsPerLaunch, n_steps - step);
+            if (prm->sort_every > 0)
+                ns = std::min(ns, prm->sort_every - step % prm->sort_every);
+        }
+        ParticlePtrs3<U> src = user;
+        if (prm->sort_every > 0 && n > 0 && step % prm->sort_every == 0) {
+            Timer t(ctx, stream, GCB_TIMER_SORT);
+            GCB_HIP(launch_cell_sort3(user.b.x, user.b.y, user.z, n, pc.b.inv_dx, pc.b.inv_dy,
+                                      pc.inv_dz, g, sb, stream));
+            GCB_HIP(launch_permute3<U>(user, scr, sb.idx, n, stream));
+            t.done();
+            src = scr;
+        }
+        Push3Launch L;
+        L.kind = kind;
+        L.yee = ctx->yee3;
+        L.fields = ctx->fields3.ptr;
+        L.n = n;
+        L.tile_start = sb.tile_start;
+        L.geom = g;
+        L.trace = s_trace ? s_trace + (int64_t)step * n : nullptr;
+        L.replay = prm->replay != 0;
+        L.stats = dstats;
+        L.steps = ns;
+        Timer t(ctx, stream, GCB_TIMER_PUSH);
+        hipError_t e;
+        if constexpr (sizeof(U) == sizeof(double))
+            e = launch_push3_f64(L, src, user, pc, stream);
+        else
+            e = launch_push3_mixed(L, src, user, pc, stream);
         if (e != hipSuccess)
             return fail(ctx, GCB_EHIP, "push kernel launch failed: %s", hipGetErrorString(e));
         t.done();
@@ -392,7 +607,7 @@ void gcb_destroy(gcb_ctx* ctx) {
                       &ctx->tile_start, &ctx->pscratch,   &ctx->stats,     &ctx->ke_partial,
                       &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace,
                       &ctx->adj_work,   &ctx->adj_samples, &ctx->gr_fields, &ctx->gr_dl,
-                      &ctx->gr_pscratch};
+                      &ctx->gr_pscratch, &ctx->fields3};
     for (DevBuf* b : bufs) release(*b);
     delete ctx;
 }
@@ -423,36 +638,10 @@ int gcb_load_fields(gcb_ctx* ctx, const gcb_grid_desc* d, const double* const E[
         if (!comps[k]) return fail(ctx, GCB_EINVAL, "field component %d is NULL", k);
     GCB_HIP(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(stream_);
-    const int64_t nodes = (int64_t)d->nx * d->ny;
-    const size_t esz = d->dtype == GCB_F64 ? 8 : 4;
     ctx->have_fields = false;
-    int rc = ensure(ctx, ctx->fields, (size_t)nodes * 6 * esz);
+    int rc = upload_interleaved(ctx, comps, d->nx, d->ny, ctx->fields, d->dtype == GCB_F32, src,
+                                stream);
     if (rc) return rc;
-    if (src == GCB_HOST) {
-        DevBuf tmp;
-        rc = ensure(ctx, tmp, (size_t)nodes * 6 * sizeof(double));
-        if (rc) return rc;
-        const double* dcomps[6];
-        for (int k = 0; k < 6; ++k) {
-            double* dst = static_cast<double*>(tmp.ptr) + k * nodes;
-            hipError_t e = hipMemcpyAsync(dst, comps[k], nodes * sizeof(double),
-                                          hipMemcpyHostToDevice, stream);
-            if (e != hipSuccess) {
-                release(tmp);
-                return fail(ctx, GCB_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
-            }
-            dcomps[k] = dst;
-        }
-        hipError_t e = launch_interleave_fields(dcomps, d->nx, d->ny, ctx->fields.ptr,
-                                                d->dtype == GCB_F32, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        release(tmp);
-        if (e != hipSuccess)
-            return fail(ctx, GCB_EHIP, "field conversion: %s", hipGetErrorString(e));
-    } else {
-        GCB_HIP(launch_interleave_fields(comps, d->nx, d->ny, ctx->fields.ptr,
-                                         d->dtype == GCB_F32, stream));
-    }
     ctx->nx = d->nx;
     ctx->ny = d->ny;
     ctx->dx = d->dx;
@@ -482,44 +671,14 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         return fail(ctx, GCB_EINVAL, "replay needs the switch trace s_trace");
     GCB_HIP(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(stream_);
-    DevStats* dstats = nullptr;
-    constexpr size_t kStatBytes = kStatSlots * sizeof(DevStats) + sizeof(DevStats);
-    if (stats) {
-        if ((rc = ensure(ctx, ctx->stats, kStatBytes))) return rc;
-        dstats = static_cast<DevStats*>(ctx->stats.ptr);
-        GCB_HIP(hipMemsetAsync(dstats, 0, kStatBytes, stream));
-    }
+    DevStats* dstats;
+    if ((rc = stats_begin(ctx, stats, stream, &dstats))) return rc;
     if (prm->form == GCB_FORM_F64)
         rc = run_push<double>(ctx, p, prm, n_steps, s_trace, dstats, stream);
     else
         rc = run_push<float>(ctx, p, prm, n_steps, s_trace, dstats, stream);
     if (rc) return rc;
-    if (stats) {
-        // the flagged count goes to the first word after the slots
-        unsigned long long* flagged =
-            reinterpret_cast<unsigned long long*>(dstats + kStatSlots);
-        GCB_HIP(launch_count_flagged(p->status, p->n, flagged, stream));
-        std::vector<DevStats> host(kStatSlots + 1);
-        GCB_HIP(hipMemcpyAsync(host.data(), ctx->stats.ptr, kStatBytes, hipMemcpyDeviceToHost,
-                               stream));
-        GCB_HIP(hipStreamSynchronize(stream));
-        unsigned long long g = 0, b = 0, h = 0, mbits = 0;
-        for (int s = 0; s < kStatSlots; ++s) {
-            g += host[s].gca_steps;
-            b += host[s].boris_steps;
-            h += host[s].halo_misses;
-            // non-negative doubles order like their bit patterns
-            mbits = host[s].max_res_bits > mbits ? host[s].max_res_bits : mbits;
-        }
-        stats->gca_steps = (int64_t)g;
-        stats->boris_steps = (int64_t)b;
-        stats->halo_misses = (int64_t)h;
-        double m;
-        std::memcpy(&m, &mbits, sizeof(m));
-        stats->max_fp_residual = m;
-        stats->flagged = (int64_t)host[kStatSlots].gca_steps;
-    }
-    return GCB_OK;
+    return stats_end(ctx, p->status, p->n, stats, stream);
 }
 
 int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params* prm,
@@ -665,35 +824,11 @@ int gcb_load_fields_gr(gcb_ctx* ctx, const gcb_gr_desc* d, const double* const D
     GCB_HIP(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     const int nxn = d->nr + 1, nyn = d->nth + 1;
-    const int64_t nodes = (int64_t)nxn * nyn;
     ctx->have_gr = false;
-    const size_t esz = d->dtype == GCB_F64 ? sizeof(double) : sizeof(float);
-    int rc = ensure(ctx, ctx->gr_fields, (size_t)nodes * 6 * esz);
+    int rc = upload_interleaved(ctx, comps, nxn, nyn, ctx->gr_fields, d->dtype == GCB_F32, src,
+                                stream);
     if (rc) return rc;
     if ((rc = ensure(ctx, ctx->gr_dl, (size_t)d->nr * d->nth * sizeof(double)))) return rc;
-    if (src == GCB_HOST) {
-        DevBuf tmp;
-        rc = ensure(ctx, tmp, (size_t)nodes * 6 * sizeof(double));
-        if (rc) return rc;
-        const double* dcomps[6];
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < 6 && e == hipSuccess; ++k) {
-            double* dst = static_cast<double*>(tmp.ptr) + k * nodes;
-            e = hipMemcpyAsync(dst, comps[k], nodes * sizeof(double), hipMemcpyHostToDevice,
-                               stream);
-            dcomps[k] = dst;
-        }
-        if (e == hipSuccess)
-            e = launch_interleave_fields(dcomps, nxn, nyn, ctx->gr_fields.ptr,
-                                         d->dtype == GCB_F32, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        release(tmp);
-        if (e != hipSuccess)
-            return fail(ctx, GCB_EHIP, "field conversion: %s", hipGetErrorString(e));
-    } else {
-        GCB_HIP(launch_interleave_fields(comps, nxn, nyn, ctx->gr_fields.ptr,
-                                         d->dtype == GCB_F32, stream));
-    }
     gr::GrConst g{};
     g.a = d->spin;
     g.r_min = d->r_min;
@@ -744,13 +879,10 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
         return fail(ctx, GCB_EINVAL, "GCB_FORM_MIXED needs fields loaded as GCB_F32");
     GCB_HIP(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(stream_);
-    DevStats* dstats = nullptr;
-    constexpr size_t kStatBytes = kStatSlots * sizeof(DevStats) + sizeof(DevStats);
-    if (stats) {
-        int rc;
-        if ((rc = ensure(ctx, ctx->stats, kStatBytes))) return rc;
-        dstats = static_cast<DevStats*>(ctx->stats.ptr);
-        GCB_HIP(hipMemsetAsync(dstats, 0, kStatBytes, stream));
+    DevStats* dstats;
+    {
+        const int rc = stats_begin(ctx, stats, stream, &dstats);
+        if (rc) return rc;
     }
     gr::GrConst g = ctx->gr;
     g.dt = prm->dt;
@@ -778,11 +910,8 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
         const int64_t n = p->n;
         const size_t ub = prm->form == GCB_FORM_F64 ? sizeof(double) : sizeof(float);
         SortBuffers sb;
-        TileGeom one{};
-        one.tile = 1;
-        one.ntx = one.nty = 1;
         int rc;
-        if ((rc = prepare_sort(ctx, n, one, sb))) return rc;
+        if ((rc = prepare_sort(ctx, n, 1, sb))) return rc;
         const size_t bytes = (size_t)n * (3 * sizeof(double) + 3 * ub + sizeof(double) +
                                           sizeof(int32_t) + 1);
         if ((rc = ensure(ctx, ctx->gr_pscratch, bytes))) return rc;
@@ -815,28 +944,83 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
         GCB_HIP(push(ptrs, ptrs, n_steps, 0));
         t.done();
     }
-    if (stats) {
-        unsigned long long* flagged = reinterpret_cast<unsigned long long*>(dstats + kStatSlots);
-        GCB_HIP(launch_count_flagged(p->status, p->n, flagged, stream));
-        std::vector<DevStats> host(kStatSlots + 1);
-        GCB_HIP(hipMemcpyAsync(host.data(), ctx->stats.ptr, kStatBytes, hipMemcpyDeviceToHost,
-                               stream));
-        GCB_HIP(hipStreamSynchronize(stream));
-        unsigned long long gsum = 0, bsum = 0, mbits = 0;
-        for (int s = 0; s < kStatSlots; ++s) {
-            gsum += host[s].gca_steps;
-            bsum += host[s].boris_steps;
-            mbits = host[s].max_res_bits > mbits ? host[s].max_res_bits : mbits;
-        }
-        stats->gca_steps = (int64_t)gsum;
-        stats->boris_steps = (int64_t)bsum;
-        stats->halo_misses = 0;
-        double m;
-        std::memcpy(&m, &mbits, sizeof(m));
-        stats->max_fp_residual = m;
-        stats->flagged = (int64_t)host[kStatSlots].gca_steps;
+    return stats_end(ctx, p->status, p->n, stats, stream);
+}
+
+int gcb_load_fields_3d(gcb_ctx* ctx, const gcb_grid3_desc* d, const double* const E[3],
+                       const double* const B[3], int32_t src, void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    if (!d || !E || !B) return fail(ctx, GCB_EINVAL, "desc, E and B must be non-NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (d->n[a] < 2 || d->n[a] > (1 << 24))
+            return fail(ctx, GCB_EINVAL, "grid sizes must be in [2, 2^24]");
+        if (!finite_pos(d->d[a])) return fail(ctx, GCB_EINVAL, "cell sizes must be finite and > 0");
     }
+    if ((int64_t)d->n[0] * d->n[1] * d->n[2] * 6 >= ((int64_t)1 << 34))
+        return fail(ctx, GCB_EINVAL, "grid too large");
+    for (int k = 0; k < 6; ++k)
+        for (int a = 0; a < 3; ++a)
+            if (!(d->stagger[k][a] >= 0.0 && d->stagger[k][a] < 1.0))
+                return fail(ctx, GCB_EINVAL, "stagger offsets must be in [0, 1)");
+    if (d->dtype != GCB_F64 && d->dtype != GCB_F32)
+        return fail(ctx, GCB_EINVAL, "unknown dtype %d", d->dtype);
+    if (src != GCB_HOST && src != GCB_DEVICE)
+        return fail(ctx, GCB_EINVAL, "src must be GCB_HOST or GCB_DEVICE");
+    const double* comps[6] = {E[0], E[1], E[2], B[0], B[1], B[2]};
+    for (int k = 0; k < 6; ++k)
+        if (!comps[k]) return fail(ctx, GCB_EINVAL, "field component %d is NULL", k);
+    GCB_HIP(hipSetDevice(ctx->device));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    ctx->have_f3 = false;
+    // rows of nx nodes, one per (j, l), l slowest: the 2D interleave of ny*nz rows
+    const int rc = upload_interleaved(ctx, comps, d->n[0], d->n[1] * d->n[2], ctx->fields3,
+                                      d->dtype == GCB_F32, src, stream);
+    if (rc) return rc;
+    for (int a = 0; a < 3; ++a) {
+        ctx->n3[a] = d->n[a];
+        ctx->d3[a] = d->d[a];
+    }
+    std::memcpy(ctx->stagger3, d->stagger, sizeof(ctx->stagger3));
+    ctx->dtype3 = d->dtype;
+    ctx->yee3 = std::memcmp(d->stagger, kYee3, sizeof(kYee3)) == 0;
+    ctx->have_f3 = true;
     return GCB_OK;
+}
+
+int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_steps,
+                uint8_t* s_trace, gcb_stats* stats, void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    if (!p) return fail(ctx, GCB_EINVAL, "particles is NULL");
+    int rc;
+    if ((rc = validate_params(ctx, prm))) return rc;
+    // the 2D checks on the x, y, u, qm, id and status arrays, then z
+    gcb_particles view{p->n, p->x, p->y, p->xp, p->yp, p->ux, p->uy, p->uz, p->qm, p->id,
+                       p->status};
+    if ((rc = validate_particles(ctx, &view, prm))) return rc;
+    if (p->n > 0 && (!p->z || !p->zp))
+        return fail(ctx, GCB_EINVAL, "particle arrays z, zp must be non-NULL");
+    if (((uintptr_t)p->z | (uintptr_t)p->zp) & 7)
+        return fail(ctx, GCB_EINVAL, "double arrays must be 8-byte aligned");
+    if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
+    if (!ctx->have_f3) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields_3d was not called");
+    if (prm->form == GCB_FORM_F64 && ctx->dtype3 != GCB_F64)
+        return fail(ctx, GCB_EINVAL, "GCB_FORM_F64 needs fields loaded as GCB_F64");
+    if (prm->form == GCB_FORM_MIXED && ctx->dtype3 != GCB_F32)
+        return fail(ctx, GCB_EINVAL, "GCB_FORM_MIXED needs fields loaded as GCB_F32");
+    if (s_trace && p->n > 0 && !p->id && prm->sort_every > 0)
+        return fail(ctx, GCB_EINVAL, "a switch trace with sorting needs particle ids");
+    if (prm->replay && !s_trace && p->n > 0 && n_steps > 0)
+        return fail(ctx, GCB_EINVAL, "replay needs the switch trace s_trace");
+    GCB_HIP(hipSetDevice(ctx->device));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    DevStats* dstats;
+    if ((rc = stats_begin(ctx, stats, stream, &dstats))) return rc;
+    if (prm->form == GCB_FORM_F64)
+        rc = run_push3<double>(ctx, p, prm, n_steps, s_trace, dstats, stream);
+    else
+        rc = run_push3<float>(ctx, p, prm, n_steps, s_trace, dstats, stream);
+    if (rc) return rc;
+    return stats_end(ctx, p->status, p->n, stats, stream);
 }
 
 int gcb_kinetic_energy(gcb_ctx* ctx, const gcb_particles* p, const gcb_params* prm,

@@ -50,6 +50,39 @@ size_t tiled_lds_bytes(int window, size_t elem_bytes);
 constexpr int kQueueMax = 2048;   // particles compacted per pass in a tile
 
 // ---------------------------------------------------------------------------
+// 3D push
+
+struct TileGeom3 {
+    int tile;            // cubic tile edge in cells
+    int halo;            // extra nodes on each side of the tile in the LDS window
+    int ntx, nty, ntz;   // tiles along x, y, z
+    int window;          // tile + 2*halo nodes per side
+};
+
+struct Push3Launch {
+    PushKind kind;
+    bool yee;              // compile-time 3D Yee offsets
+    const void* fields;    // node-interleaved device fields (double or float)
+    int64_t n;
+    const int32_t* tile_start;   // tiled: ntiles + 1 offsets
+    TileGeom3 geom;
+    uint8_t* trace;        // nullable: trace row of the launch's first step
+    bool replay;
+    DevStats* stats;       // nullable
+    int steps = 1;         // global kernel: steps per launch
+};
+
+hipError_t launch_push3_f64(const Push3Launch& L, const ParticlePtrs3<double>& in,
+                            const ParticlePtrs3<double>& out, const PushConst3& pc,
+                            hipStream_t stream);
+hipError_t launch_push3_mixed(const Push3Launch& L, const ParticlePtrs3<float>& in,
+                              const ParticlePtrs3<float>& out, const PushConst3& pc,
+                              hipStream_t stream);
+
+// LDS bytes of the 3D tiled kernel for a window of `window` nodes per side.
+size_t tiled3_lds_bytes(int window, size_t elem_bytes);
+
+// ---------------------------------------------------------------------------
 // cell sort
 
 struct SortBuffers {
@@ -75,6 +108,15 @@ hipError_t launch_cell_sort(const double* x, const double* y, int64_t n, double 
 template <typename U>
 hipError_t launch_permute(const ParticlePtrs<U>& src, const ParticlePtrs<U>& dst,
                           const uint32_t* perm, int64_t n, hipStream_t stream);
+
+// The same for the 3D state: keys are the cubic tiles of (x, y, z), row-major
+// (x fastest).
+hipError_t launch_cell_sort3(const double* x, const double* y, const double* z, int64_t n,
+                             double inv_dx, double inv_dy, double inv_dz, const TileGeom3& g,
+                             const SortBuffers& b, hipStream_t stream);
+template <typename U>
+hipError_t launch_permute3(const ParticlePtrs3<U>& src, const ParticlePtrs3<U>& dst,
+                           const uint32_t* perm, int64_t n, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // fields

@@ -185,12 +185,12 @@ struct Local {
     R A, C;
 };
 
+// b, v_E, kappa and E_par from E and B at the point.
 template <typename R>
-GCB_HD uint32_t local_from_sample(const Sample<R>& s, const Consts<R>& K,
-                                                      Local<R>& L) {
+GCB_HD uint32_t local_fields(const R E[3], const R Bv[3], const Consts<R>& K, Local<R>& L) {
     uint32_t flags = 0;
-    const R Ex = s.E[0], Ey = s.E[1], Ez = s.E[2];
-    const R Bx = s.B[0], By = s.B[1], Bz = s.B[2];
+    const R Ex = E[0], Ey = E[1], Ez = E[2];
+    const R Bx = Bv[0], By = Bv[1], Bz = Bv[2];
     const R B2 = (Bx * Bx + By * By) + Bz * Bz;
     const R B = sqrt(B2);
     const bool bzero = (B == (R)0);
@@ -232,23 +232,38 @@ GCB_HD uint32_t local_from_sample(const Sample<R>& s, const Consts<R>& K,
         L.kappa = (R)1 / sqrt(om);
     }
     L.Epar = (Ex * bx + Ey * by) + Ez * bz;
-    // d_j b_i = (d_j B_i - b_i (b . d_j B)) / B
-    const R dnx = (bx * s.dBx[0] + by * s.dBx[1]) + bz * s.dBx[2];
-    const R dny = (bx * s.dBy[0] + by * s.dBy[1]) + bz * s.dBy[2];
+    return flags;
+}
+
+// d_j b_i = (d_j B_i - b_i (b . d_j B)) / B for one direction j, from the
+// gradient dB[i] = d_j B_i.
+template <typename R>
+GCB_HD void db_along(const Local<R>& L, const R dB[3], R db[3]) {
+    const R dn = (L.b[0] * dB[0] + L.b[1] * dB[1]) + L.b[2] * dB[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) db[i] = (dB[i] - L.b[i] * dn) * L.inv_B;
+}
+
+// A = v_E.(b.grad)b and C = v_E.(v_E.grad)b from L.bgb and L.vgb.
+template <typename R>
+GCB_HD void curvature_scalars(Local<R>& L) {
+    L.A = (L.vE[0] * L.bgb[0] + L.vE[1] * L.bgb[1]) + L.vE[2] * L.bgb[2];
+    L.C = (L.vE[0] * L.vgb[0] + L.vE[1] * L.vgb[1]) + L.vE[2] * L.vgb[2];
+}
+
+// 2D: gradients along x and y only.
+template <typename R>
+GCB_HD uint32_t local_from_sample(const Sample<R>& s, const Consts<R>& K, Local<R>& L) {
+    const uint32_t flags = local_fields(s.E, s.B, K, L);
     R dbx[3], dby[3];
-    dbx[0] = (s.dBx[0] - bx * dnx) * inv_B;
-    dbx[1] = (s.dBx[1] - by * dnx) * inv_B;
-    dbx[2] = (s.dBx[2] - bz * dnx) * inv_B;
-    dby[0] = (s.dBy[0] - bx * dny) * inv_B;
-    dby[1] = (s.dBy[1] - by * dny) * inv_B;
-    dby[2] = (s.dBy[2] - bz * dny) * inv_B;
+    db_along(L, s.dBx, dbx);
+    db_along(L, s.dBy, dby);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        L.bgb[i] = bx * dbx[i] + by * dby[i];
-        L.vgb[i] = vEx * dbx[i] + vEy * dby[i];
+        L.bgb[i] = L.b[0] * dbx[i] + L.b[1] * dby[i];
+        L.vgb[i] = L.vE[0] * dbx[i] + L.vE[1] * dby[i];
     }
-    L.A = (vEx * L.bgb[0] + vEy * L.bgb[1]) + vEz * L.bgb[2];
-    L.C = (vEx * L.vgb[0] + vEy * L.vgb[1]) + vEz * L.vgb[2];
+    curvature_scalars(L);
     return flags;
 }
 

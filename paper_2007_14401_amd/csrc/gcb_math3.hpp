@@ -1,0 +1,326 @@
+// Per-particle arithmetic of the coupled pusher in three dimensions, templated
+// on the bulk type R like gcb_math.hpp (binary64, or the mixed form with
+// binary64 positions).  The equations are the 2D ones; what changes is the
+// trilinear gather with gradients along z, d_j b over j = x, y, z, and the
+// three-component guiding-center position.  The Boris push, the switch, the
+// parallel update and the curvature drift are the 2D functions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gcb_access3.hpp"
+#include "gcb_math.hpp"
+
+namespace gcb {
+
+template <typename R>
+struct Consts3 : Consts<R> {
+    R inv_dz;
+};
+
+template <typename R>
+GCB_HD Consts3<R> make_consts3(const PushConst3& pc) {
+    Consts3<R> k;
+    static_cast<Consts<R>&>(k) = make_consts<R>(pc.b);
+    k.inv_dz = (R)pc.inv_dz;
+    return k;
+}
+
+template <typename R>
+struct Regs3 {
+    double x, y, z, xp, yp, zp;
+    R ux, uy, uz;
+    double qm;
+};
+
+template <typename R>
+struct Sample3 {
+    R E[3], B[3];
+    R dBx[3], dBy[3], dBz[3];   // d B_i / dx, dy, dz
+};
+
+// ---------------------------------------------------------------------------
+// Gather (Sec. 4, opening paragraph): linear shape function on the 2x2x2
+// nodes of each component's lattice, summed plane by plane (the bilinear
+// expression of each z plane, then the two planes weighted along z);
+// gradients by differentiating it.  f[dz*4 + dy*2 + dx].
+
+template <typename R>
+GCB_HD void trilerp(const R f[8], R wx, R wy, R wz, const Consts3<R>& K, bool grad, R& val,
+                    R& ddx, R& ddy, R& ddz) {
+    const R ax = (R)1 - wx, ay = (R)1 - wy, az = (R)1 - wz;
+    const R v0 = (((ax * ay) * f[0] + (wx * ay) * f[1]) + (ax * wy) * f[2]) + (wx * wy) * f[3];
+    const R v1 = (((ax * ay) * f[4] + (wx * ay) * f[5]) + (ax * wy) * f[6]) + (wx * wy) * f[7];
+    val = az * v0 + wz * v1;
+    if (grad) {
+        const R g0 = ay * (f[1] - f[0]) + wy * (f[3] - f[2]);
+        const R g1 = ay * (f[5] - f[4]) + wy * (f[7] - f[6]);
+        const R h0 = ax * (f[2] - f[0]) + wx * (f[3] - f[1]);
+        const R h1 = ax * (f[6] - f[4]) + wx * (f[7] - f[5]);
+        ddx = (az * g0 + wz * g1) * K.inv_dx;
+        ddy = (az * h0 + wz * h1) * K.inv_dy;
+        ddz = (v1 - v0) * K.inv_dz;
+    }
+}
+
+template <typename R, bool kGrad>
+GCB_HD void store_comp(int k, R val, R ddx, R ddy, R ddz, Sample3<R>& s) {
+    if (k < 3) {
+        s.E[k] = val;
+    } else {
+        s.B[k - 3] = val;
+        if (kGrad) {
+            s.dBx[k - 3] = ddx;
+            s.dBy[k - 3] = ddy;
+            s.dBz[k - 3] = ddz;
+        }
+    }
+}
+
+// the six components from the located Yee stencils
+template <typename R, bool kGrad, class Loader>
+GCB_HD void interp3_yee(const Loader& ld, const R wx[2], const R wy[2], const R wz[2],
+                        const Consts3<R>& K, Sample3<R>& s) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int set = kYee3Set[k];
+        R f[8];
+        ld.template load8<R>(set, k, f);
+        R val, ddx, ddy, ddz;
+        trilerp(f, wx[set & 1], wy[(set >> 1) & 1], wz[set >> 2], K, kGrad && k >= 3, val, ddx,
+                ddy, ddz);
+        store_comp<R, kGrad>(k, val, ddx, ddy, ddz, s);
+    }
+}
+
+template <typename R, bool kGrad, typename T>
+GCB_HD void yee3_fetch(const GlobalAcc3<T>& acc, const int fl[3][2], const R wx[2],
+                       const R wy[2], const R wz[2], const Consts3<R>& K, Sample3<R>& s) {
+    typename GlobalAcc3<T>::Loc L;
+    acc.locate(fl, L);
+    interp3_yee<R, kGrad>(GlobalLoad3<T>{acc, L}, wx, wy, wz, K, s);
+}
+
+template <typename R, bool kGrad, typename T>
+GCB_HD void yee3_fetch(const TileAcc3<T>& acc, const int fl[3][2], const R wx[2],
+                       const R wy[2], const R wz[2], const Consts3<R>& K, Sample3<R>& s) {
+    int off[8];
+    typename GlobalAcc3<T>::Loc L;
+    if (acc.locate(fl, off, L)) {
+        const int W = acc.W;
+        interp3_yee<R, kGrad>(LdsLoad3<T>{acc.lds, off, W, W * W, W * W * W}, wx, wy, wz, K,
+                              s);
+    } else {
+        interp3_yee<R, kGrad>(GlobalLoad3<T>{acc.g, L}, wx, wy, wz, K, s);
+    }
+}
+
+// All six components at (X, Y, Z); B gradients when kGrad.  kYee: the 3D Yee
+// offsets.  Lattice coordinates and weights in binary64 from the positions.
+template <typename R, bool kGrad, bool kYee, class Acc>
+GCB_HD void gather3(const Acc& acc, const PushConst3& pc, const Consts3<R>& K, double X,
+                    double Y, double Z, Sample3<R>& s) {
+    const double g[3] = {X * pc.b.inv_dx, Y * pc.b.inv_dy, Z * pc.inv_dz};
+    if constexpr (kYee) {
+        // lattice coordinate minus the offset: offset 0 leaves it unchanged
+        int fl[3][2];
+        R w[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double h = g[a] - 0.5;
+            const double fa = floor(g[a]), fb = floor(h);
+            fl[a][0] = (int)fa;
+            fl[a][1] = (int)fb;
+            w[a][0] = (R)(g[a] - fa);
+            w[a][1] = (R)(h - fb);
+        }
+        yee3_fetch<R, kGrad>(acc, fl, w[0], w[1], w[2], K, s);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double xi = g[0] - pc.b.stagger[k][0];
+            const double eta = g[1] - pc.b.stagger[k][1];
+            const double zeta = g[2] - pc.sz[k];
+            const double fi = floor(xi), fj = floor(eta), fk = floor(zeta);
+            R f[8];
+            acc.template oct<R>(k, (int)fi, (int)fj, (int)fk, f);
+            R val, ddx, ddy, ddz;
+            trilerp(f, (R)(xi - fi), (R)(eta - fj), (R)(zeta - fk), K, kGrad && k >= 3, val,
+                    ddx, ddy, ddz);
+            store_comp<R, kGrad>(k, val, ddx, ddy, ddz, s);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Local guiding-center quantities (Sec. 2.2) with gradients along x, y, z:
+// (b.grad)b = b_x d_x b + b_y d_y b + b_z d_z b, (v_E.grad)b likewise.
+
+template <typename R>
+GCB_HD uint32_t local_from_sample(const Sample3<R>& s, const Consts<R>& K, Local<R>& L) {
+    const uint32_t flags = local_fields(s.E, s.B, K, L);
+    R dbx[3], dby[3], dbz[3];
+    db_along(L, s.dBx, dbx);
+    db_along(L, s.dBy, dby);
+    db_along(L, s.dBz, dbz);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        L.bgb[i] = (L.b[0] * dbx[i] + L.b[1] * dby[i]) + L.b[2] * dbz[i];
+        L.vgb[i] = (L.vE[0] * dbx[i] + L.vE[1] * dby[i]) + L.vE[2] * dbz[i];
+    }
+    curvature_scalars(L);
+    return flags;
+}
+
+// u_par b / Gamma + v_E + v_c at a point, three components
+template <typename R>
+GCB_HD void drift_terms3(const Local<R>& L, R upn, R mu, R inv_qm, bool curvature,
+                         const Consts<R>& K, R F[3]) {
+    const R g = gamma_gca(L, upn, mu, K);
+    const R a = upn / g;
+    if (curvature) {
+        R vc[3];
+        v_curv(L, upn, g, inv_qm, K, vc);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) F[i] = (a * L.b[i] + L.vE[i]) + vc[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) F[i] = a * L.b[i] + L.vE[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Full-orbit step (Sec. 2.1): u^{n-1/2} -> u^{n+1/2}, x^{n+1} = x^n + dt u/Gamma.
+template <typename R>
+GCB_HD void boris_step3(const Sample3<R>& s, Regs3<R>& r, const PushConst3& pc,
+                        const Consts<R>& K) {
+    boris(s.E, s.B, r.ux, r.uy, r.uz, (R)r.qm, K);
+    const R gn = gamma_full(r.ux, r.uy, r.uz, K);
+    const R inv_g = (R)1 / gn;
+    const double xn = r.x + pc.b.dt * (double)(r.ux * inv_g);
+    const double yn = r.y + pc.b.dt * (double)(r.uy * inv_g);
+    const double zn = r.z + pc.b.dt * (double)(r.uz * inv_g);
+    r.xp = r.x;
+    r.yp = r.y;
+    r.zp = r.z;
+    r.x = wrap(xn, pc.b.Lx);
+    r.y = wrap(yn, pc.b.Ly);
+    r.z = wrap(zn, pc.Lz);
+}
+
+// One guiding-center step (Sec. 2.2.1 / 2.2.2 inside the coupled step of
+// Sec. 3.1).  sn is the gather (with gradients) at x^n.  Returns status
+// flags; res receives |R^K - R^{K-1}|_inf over the three components.
+template <typename R, bool kYee, class Acc>
+GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
+                          const PushConst3& pc, const Consts3<R>& K, double& res) {
+    uint32_t flags = 0;
+    const bool curv = pc.b.curvature != 0;
+    const double x[3] = {r.x, r.y, r.z};
+    const double xprev[3] = {r.xp, r.yp, r.zp};
+    const double box[3] = {pc.b.Lx, pc.b.Ly, pc.Lz};
+    const R ux = r.ux, uy = r.uy, uz = r.uz;
+    const R qm = (R)r.qm;
+    const R inv_qm = (R)1 / qm;
+
+    // 1. guiding-center variables at R^{n-1/2} = (x^n + x^{n-1})/2
+    R upar, mu, bp[3];
+    {
+        double Rh[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Rh[a] = x[a] - 0.5 * min_image(x[a] - xprev[a], box[a]);
+        Sample3<R> sh;
+        gather3<R, true, kYee>(acc, pc, K, Rh[0], Rh[1], Rh[2], sh);
+        Local<R> Lh;
+        flags |= local_from_sample(sh, K, Lh);
+        upar = (ux * Lh.b[0] + uy * Lh.b[1]) + uz * Lh.b[2];
+        const R gf = gamma_full(ux, uy, uz, K);
+        R vc[3] = {(R)0, (R)0, (R)0};
+        if (curv) v_curv(Lh, upar, gf, inv_qm, K, vc);
+        const R upx = (ux - upar * Lh.b[0]) - (Lh.vE[0] + vc[0]) * gf;
+        const R upy = (uy - upar * Lh.b[1]) - (Lh.vE[1] + vc[1]) * gf;
+        const R upz = (uz - upar * Lh.b[2]) - (Lh.vE[2] + vc[2]) * gf;
+        const R up2 = (upx * upx + upy * upy) + upz * upz;
+        mu = (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        const R nu = sqrt(up2);
+        const R inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
+        bp[0] = upx * inv_nu;
+        bp[1] = upy * inv_nu;
+        bp[2] = upz * inv_nu;
+    }
+
+    // 2.-3. local quantities at R^n = x^n and the parallel update
+    R upn, Fn[3];
+    {
+        Local<R> Ln;
+        flags |= local_from_sample(sn, K, Ln);
+        upn = parallel_update(Ln, upar, mu, qm, curv, K, flags);
+        drift_terms3(Ln, upn, mu, inv_qm, curv, K, Fn);
+    }
+
+    // 4. R^{n+1}: K fixed-point iterations R^{k+1} = R^k - H(R^k), R^0 = R^n
+    double Rp[3] = {x[0], x[1], x[2]};
+    res = 0.0;
+    for (int k = 0; k < pc.b.n_iter; ++k) {
+        R Fk[3];
+        if (k == 0) {
+            Fk[0] = Fn[0];
+            Fk[1] = Fn[1];
+            Fk[2] = Fn[2];
+        } else {
+            Sample3<R> sk;
+            gather3<R, true, kYee>(acc, pc, K, Rp[0], Rp[1], Rp[2], sk);
+            Local<R> Lk;
+            flags |= local_from_sample(sk, K, Lk);
+            drift_terms3(Lk, upn, mu, inv_qm, curv, K, Fk);
+        }
+        double d[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double Rn = x[a] + (double)(K.h * (Fn[a] + Fk[a]));
+            d[a] = fabs(Rn - Rp[a]);
+            Rp[a] = Rn;
+        }
+        res = nan_max(nan_max(d[0], d[1]), d[2]);
+    }
+    if (res > pc.b.fp_tol) flags |= ST_FPRES;
+
+    // 5. particle variables at R^{n+1/2} = (R^n + R^{n+1})/2, gyration
+    //    direction held fixed
+    {
+        double Rm[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Rm[a] = x[a] + 0.5 * (Rp[a] - x[a]);
+        Sample3<R> sm;
+        gather3<R, true, kYee>(acc, pc, K, Rm[0], Rm[1], Rm[2], sm);
+        Local<R> Lm;
+        flags |= local_from_sample(sm, K, Lm);
+        const R gr = gamma_gca(Lm, upn, mu, K);
+        R vc[3] = {(R)0, (R)0, (R)0};
+        if (curv) v_curv(Lm, upn, gr, inv_qm, K, vc);
+        const R um = sqrt((((R)2 * mu) * Lm.B) * Lm.kappa);
+        r.ux = (upn * Lm.b[0] + (Lm.vE[0] + vc[0]) * gr) + um * bp[0];
+        r.uy = (upn * Lm.b[1] + (Lm.vE[1] + vc[1]) * gr) + um * bp[1];
+        r.uz = (upn * Lm.b[2] + (Lm.vE[2] + vc[2]) * gr) + um * bp[2];
+    }
+
+    // 6. store
+    r.xp = x[0];
+    r.yp = x[1];
+    r.zp = x[2];
+    r.x = wrap(Rp[0], pc.b.Lx);
+    r.y = wrap(Rp[1], pc.b.Ly);
+    r.z = wrap(Rp[2], pc.Lz);
+    return flags;
+}
+
+template <typename R>
+GCB_HD uint32_t finite_flag3(const Regs3<R>& r) {
+    const bool ok = __builtin_isfinite(r.x) && __builtin_isfinite(r.y) &&
+                    __builtin_isfinite(r.z) && __builtin_isfinite(r.ux) &&
+                    __builtin_isfinite(r.uy) && __builtin_isfinite(r.uz);
+    return ok ? 0u : (uint32_t)ST_NONFINITE;
+}
+
+}  // namespace gcb

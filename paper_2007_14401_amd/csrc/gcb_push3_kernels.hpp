@@ -1,0 +1,243 @@
+// 3D push kernels, templated like the 2D ones on the bulk type R and the
+// field storage type T.
+//
+// k_push3_global: one lane per particle, up to `ns` steps per launch with the
+//   particle in registers, gathers through the caches.
+// k_push3_tiled: one workgroup per cubic tile of cell-sorted particles; the
+//   tile's field window (tile + halo per side, W^3 nodes of six components)
+//   is staged once in LDS, then the per-regime queues of the 2D kernel.
+//
+// Included by exactly one translation unit per form.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gcb_access3.hpp"
+#include "gcb_internal.h"
+#include "gcb_math3.hpp"
+#include "gcb_push_kernels.hpp"
+
+namespace gcb {
+namespace kern {
+
+template <typename R>
+__device__ __forceinline__ void load_particle3(const ParticlePtrs3<R>& in, int64_t p,
+                                               double qm_default, Regs3<R>& r) {
+    r.x = in.b.x[p];
+    r.y = in.b.y[p];
+    r.z = in.z[p];
+    r.xp = in.b.xp[p];
+    r.yp = in.b.yp[p];
+    r.zp = in.zp[p];
+    r.ux = in.b.ux[p];
+    r.uy = in.b.uy[p];
+    r.uz = in.b.uz[p];
+    r.qm = in.b.qm ? in.b.qm[p] : qm_default;
+}
+
+template <typename R>
+__device__ __forceinline__ void store_particle3(const ParticlePtrs3<R>& in,
+                                                const ParticlePtrs3<R>& out, int64_t p,
+                                                const Regs3<R>& r, uint32_t flags) {
+    out.b.x[p] = r.x;
+    out.b.y[p] = r.y;
+    out.z[p] = r.z;
+    out.b.xp[p] = r.xp;
+    out.b.yp[p] = r.yp;
+    out.zp[p] = r.zp;
+    out.b.ux[p] = r.ux;
+    out.b.uy[p] = r.uy;
+    out.b.uz[p] = r.uz;
+    out.b.status[p] = (uint8_t)(in.b.status[p] | flags);
+    if (out.b.x != in.b.x) {   // out-of-place step after a sort: carry the rest along
+        if (in.b.qm) out.b.qm[p] = r.qm;
+        if (in.b.id) out.b.id[p] = in.b.id[p];
+    }
+}
+
+template <typename R, bool kYee, class Acc>
+__device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Regs3<R>& r,
+                                                    const PushConst3& pc, const Consts3<R>& K,
+                                                    double& res) {
+    uint32_t fl = 0;
+    res = 0.0;
+    Sample3<R> s;
+    if (gca) {
+        gather3<R, true, kYee>(acc, pc, K, r.x, r.y, r.z, s);
+        fl = gca_step3<R, kYee>(acc, s, r, pc, K, res);
+    } else {
+        gather3<R, false, kYee>(acc, pc, K, r.x, r.y, r.z, s);
+        boris_step3(s, r, pc, K);
+    }
+    return fl | finite_flag3(r);
+}
+
+template <typename R, typename T, bool kYee>
+__global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
+                                                       ParticlePtrs3<R> out, int64_t n, int ns,
+                                                       const T* __restrict__ F, PushConst3 pc,
+                                                       uint8_t* trace, bool replay,
+                                                       DevStats* stats) {
+    const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    unsigned cnt_g = 0, cnt_b = 0;
+    double maxres = 0.0;
+    if (p < n) {
+        const Consts3<R> K = make_consts3<R>(pc);
+        GlobalAcc3<T> acc{F, pc.b.nx, pc.b.ny, pc.nz};
+        Regs3<R> r;
+        load_particle3(in, p, pc.b.qm, r);
+        const int64_t ti = in.b.id ? (int64_t)in.b.id[p] : p;
+        uint32_t fl = 0;
+        for (int s = 0; s < ns; ++s) {
+            uint8_t* tr = trace ? trace + (size_t)s * n : nullptr;
+            bool gca;
+            if (replay) {
+                gca = tr[ti] == 0;
+            } else {
+                Sample3<R> smp;
+                gather3<R, false, kYee>(acc, pc, K, r.x, r.y, r.z, smp);
+                gca = switch_gca(smp.E, smp.B, r.ux, r.uy, r.uz, r.qm, pc.b, K);
+            }
+            double res;
+            fl |= coupled_update3<R, kYee>(acc, gca, r, pc, K, res);
+            if (tr && !replay) tr[ti] = gca ? 0 : 1;
+            if (gca) {
+                ++cnt_g;
+                maxres = nan_max(maxres, res);
+            } else {
+                ++cnt_b;
+            }
+        }
+        store_particle3(in, out, p, r, fl);
+    }
+    if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
+}
+
+template <typename R, typename T, bool kYee, int kMinWaves>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
+k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const int32_t* __restrict__ tile_start,
+              TileGeom3 g, int chunk, const T* __restrict__ F, PushConst3 pc, uint8_t* trace,
+              bool replay, DevStats* stats) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int wave_g[kWG / 64];
+    __shared__ int wave_b[kWG / 64];
+
+    const int ntiles = g.ntx * g.nty * g.ntz;
+    // consecutive tiles on the same XCD (workgroup b runs on XCD b % 8)
+    const int tile = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
+    if (tile >= ntiles) return;
+    const int W = g.window;
+    const int WWW = W * W * W;
+    T* lds = reinterpret_cast<T*>(smem);
+    uint16_t* queue = reinterpret_cast<uint16_t*>(
+        smem + (((size_t)WWW * 6 * sizeof(T) + 15) & ~(size_t)15));
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tx = tile % g.ntx;
+    const int tyz = tile / g.ntx;
+    const int ty = tyz % g.nty;
+    const int tz = tyz / g.nty;
+    const int oi = tx * g.tile - g.halo;
+    const int oj = ty * g.tile - g.halo;
+    const int ol = tz * g.tile - g.halo;
+
+    // stage the window: one (j, l) row (W records of 6 values, contiguous in
+    // HBM) per wave iteration, written to the six component planes
+    for (int row = wave; row < W * W; row += kWG / 64) {
+        const int ll = row / W;
+        const int rr = row - ll * W;
+        const int gj = wrap_index(oj + rr, pc.b.ny);
+        const int gl = wrap_index(ol + ll, pc.nz);
+        const T* grow = F + ((size_t)gl * pc.b.ny + gj) * pc.b.nx * 6;
+        for (int e = lane; e < W * 6; e += 64) {
+            const int c = e / 6;
+            const int k = e - c * 6;
+            const int gi = wrap_index(oi + c, pc.b.nx);
+            lds[((k * W + ll) * W + rr) * W + c] = grow[gi * 6 + k];
+        }
+    }
+    __syncthreads();
+
+    const Consts3<R> K = make_consts3<R>(pc);
+    TileAcc3<T> acc{lds, GlobalAcc3<T>{F, pc.b.nx, pc.b.ny, pc.nz}, oi, oj, ol, W, false};
+    const int64_t p0 = tile_start[tile];
+    const int64_t p1 = tile_start[tile + 1];
+    unsigned cnt_g = 0, cnt_b = 0, cnt_h = 0;
+    double maxres = 0.0;
+
+    for (int64_t base = p0; base < p1; base += kQueueMax) {
+        const int m = (int)((p1 - base) < kQueueMax ? (p1 - base) : kQueueMax);
+        // pass 1: switch decision, stable split into the two queues
+        const int nG = split_queues(m, queue, wave_g, wave_b, [&](int t) {
+            const int64_t p = base + t;
+            if (replay) return trace[in.b.id ? (int64_t)in.b.id[p] : p] == 0;
+            const double qm = in.b.qm ? in.b.qm[p] : pc.b.qm;
+            Sample3<R> s;
+            gather3<R, false, kYee>(acc, pc, K, in.b.x[p], in.b.y[p], in.z[p], s);
+            return switch_gca(s.E, s.B, in.b.ux[p], in.b.uy[p], in.b.uz[p], qm, pc.b, K);
+        });
+        // pass 2: guiding-center queue, then Boris queue
+        for (int q = threadIdx.x; q < m; q += kWG) {
+            const int64_t p = base + queue[q];
+            const bool gca = q < nG;
+            Regs3<R> r;
+            load_particle3(in, p, pc.b.qm, r);
+            acc.miss = false;
+            double res;
+            uint32_t fl = coupled_update3<R, kYee>(acc, gca, r, pc, K, res);
+            if (acc.miss) {
+                fl |= ST_HALO;
+                ++cnt_h;
+            }
+            store_particle3(in, out, p, r, fl);
+            if (trace && !replay) trace[in.b.id ? (int64_t)in.b.id[p] : p] = gca ? 0 : 1;
+            if (gca) {
+                ++cnt_g;
+                maxres = nan_max(maxres, res);
+            } else {
+                ++cnt_b;
+            }
+        }
+        __syncthreads();
+    }
+    if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
+}
+
+template <typename R, typename T, int kMinWaves>
+hipError_t launch_push3(const Push3Launch& L, const ParticlePtrs3<R>& in,
+                        const ParticlePtrs3<R>& out, const PushConst3& pc, hipStream_t stream) {
+    if (L.n == 0) return hipSuccess;
+    const T* F = static_cast<const T*>(L.fields);
+    if (L.kind == PushKind::Global) {
+        const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
+        const int ns = L.steps > 0 ? L.steps : 1;
+        if (L.yee)
+            hipLaunchKernelGGL((k_push3_global<R, T, true>), dim3(blocks), dim3(kWG), 0, stream,
+                               in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
+        else
+            hipLaunchKernelGGL((k_push3_global<R, T, false>), dim3(blocks), dim3(kWG), 0,
+                               stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
+        return hipGetLastError();
+    }
+    const int ntiles = L.geom.ntx * L.geom.nty * L.geom.ntz;
+    const int chunk = (ntiles + 7) / 8;
+    const size_t lds = tiled3_lds_bytes(L.geom.window, sizeof(T));
+    if (L.yee) {
+        auto kfn = k_push3_tiled<R, T, true, kMinWaves>;
+        hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
+                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay, L.stats);
+    } else {
+        auto kfn = k_push3_tiled<R, T, false, kMinWaves>;
+        hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
+                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay, L.stats);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kern
+}  // namespace gcb

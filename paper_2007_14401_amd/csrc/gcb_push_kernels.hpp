@@ -82,6 +82,51 @@ __device__ __forceinline__ void store_particle(const ParticlePtrs<R>& in,
     }
 }
 
+// Stable split of the m particles of one pass of a tile into two queues of
+// slots in LDS: those for which decide(t) holds (guiding center) from the
+// front in order, the others (Boris) from the back.  Every thread of the
+// workgroup calls it; returns the length of the guiding-center queue.
+template <class Decide>
+__device__ __forceinline__ int split_queues(int m, uint16_t* queue, int* wave_g, int* wave_b,
+                                            Decide&& decide) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int nG = 0, nB = 0;
+    for (int t0 = 0; t0 < m; t0 += kWG) {
+        const int t = t0 + (int)threadIdx.x;
+        const bool valid = t < m;
+        const bool gca = valid && decide(t);
+        const unsigned long long bg = __ballot(valid && gca);
+        const unsigned long long bb = __ballot(valid && !gca);
+        if (lane == 0) {
+            wave_g[wave] = __popcll(bg);
+            wave_b[wave] = __popcll(bb);
+        }
+        __syncthreads();
+        int offg = nG, offb = nB, totg = 0, totb = 0;
+#pragma unroll
+        for (int w = 0; w < kWG / 64; ++w) {
+            if (w < wave) {
+                offg += wave_g[w];
+                offb += wave_b[w];
+            }
+            totg += wave_g[w];
+            totb += wave_b[w];
+        }
+        if (valid) {
+            if (gca)
+                queue[offg + __popcll(bg & lt)] = (uint16_t)t;
+            else
+                queue[m - 1 - (offb + __popcll(bb & lt))] = (uint16_t)t;
+        }
+        nG += totg;
+        nB += totb;
+        __syncthreads();
+    }
+    return nG;
+}
+
 // one coupled step for a particle already in registers
 template <typename R, bool kYee, class Acc>
 __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Regs<R>& r,
@@ -190,55 +235,19 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict_
     const int64_t p1 = tile_start[tile + 1];
     unsigned cnt_g = 0, cnt_b = 0, cnt_h = 0;
     double maxres = 0.0;
-    const unsigned long long lt = (1ull << lane) - 1ull;
 
     for (int64_t base = p0; base < p1; base += kQueueMax) {
         const int m = (int)((p1 - base) < kQueueMax ? (p1 - base) : kQueueMax);
         // pass 1: switch decision, stable split into the two queues
-        int nG = 0, nB = 0;
-        for (int t0 = 0; t0 < m; t0 += kWG) {
-            const int t = t0 + (int)threadIdx.x;
-            const bool valid = t < m;
-            bool gca = false;
-            if (valid) {
-                const int64_t p = base + t;
-                if (replay) {
-                    gca = trace[in.id ? (int64_t)in.id[p] : p] == 0;
-                } else {
-                    const double x = in.x[p], y = in.y[p];
-                    const double qm = in.qm ? in.qm[p] : pc.qm;
-                    Sample<R> s;
-                    gather<R, false, kYee>(acc, pc, K, x, y, s);
-                    gca = switch_gca(s.E, s.B, in.ux[p], in.uy[p], in.uz[p], qm, pc, K);
-                }
-            }
-            const unsigned long long bg = __ballot(valid && gca);
-            const unsigned long long bb = __ballot(valid && !gca);
-            if (lane == 0) {
-                wave_g[wave] = __popcll(bg);
-                wave_b[wave] = __popcll(bb);
-            }
-            __syncthreads();
-            int offg = nG, offb = nB, totg = 0, totb = 0;
-#pragma unroll
-            for (int w = 0; w < kWG / 64; ++w) {
-                if (w < wave) {
-                    offg += wave_g[w];
-                    offb += wave_b[w];
-                }
-                totg += wave_g[w];
-                totb += wave_b[w];
-            }
-            if (valid) {
-                if (gca)
-                    queue[offg + __popcll(bg & lt)] = (uint16_t)t;
-                else
-                    queue[m - 1 - (offb + __popcll(bb & lt))] = (uint16_t)t;
-            }
-            nG += totg;
-            nB += totb;
-            __syncthreads();
-        }
+        const int nG = split_queues(m, queue, wave_g, wave_b, [&](int t) {
+            const int64_t p = base + t;
+            if (replay) return trace[in.id ? (int64_t)in.id[p] : p] == 0;
+            const double x = in.x[p], y = in.y[p];
+            const double qm = in.qm ? in.qm[p] : pc.qm;
+            Sample<R> s;
+            gather<R, false, kYee>(acc, pc, K, x, y, s);
+            return switch_gca(s.E, s.B, in.ux[p], in.uy[p], in.uz[p], qm, pc, K);
+        });
         // pass 2: guiding-center queue, then Boris queue
         for (int q = threadIdx.x; q < m; q += kWG) {
             const int64_t p = base + queue[q];

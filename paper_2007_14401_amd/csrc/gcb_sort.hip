@@ -12,6 +12,7 @@
 //   k_permute     gather every state array through idx
 //   k_gr_tile_keys, k_gr_permute: the same for the curved-spacetime state
 //                 ((r, theta) tiles of the grid cells)
+//   k_tile_keys3, k_permute3: the same for the 3D state (cubic tiles)
 #include <hip/hip_runtime.h>
 
 #include "gcb_internal.h"
@@ -41,6 +42,29 @@ __global__ __launch_bounds__(kSortWG) void k_tile_keys(const double* __restrict_
     ty = ty < g.nty ? ty : g.nty - 1;
     const uint32_t key = (uint32_t)(ty * g.ntx + tx);
     keys[p] = key;
+    idx[p] = (uint32_t)p;
+}
+
+// clamped tile coordinate of one position component (non-finite -> 0)
+__device__ __forceinline__ int tile_coord(double v, double inv_d, int tile, int nt) {
+    const double gc = floor(v * inv_d);
+    const int t = (gc >= 0.0 && gc < 2.0e9) ? (int)gc / tile : 0;
+    return t < nt ? t : nt - 1;
+}
+
+__global__ __launch_bounds__(kSortWG) void k_tile_keys3(const double* __restrict__ x,
+                                                        const double* __restrict__ y,
+                                                        const double* __restrict__ z,
+                                                        int64_t n, double inv_dx,
+                                                        double inv_dy, double inv_dz,
+                                                        TileGeom3 g, uint32_t* keys,
+                                                        uint32_t* idx) {
+    const int64_t p = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
+    if (p >= n) return;
+    const int tx = tile_coord(x[p], inv_dx, g.tile, g.ntx);
+    const int ty = tile_coord(y[p], inv_dy, g.tile, g.nty);
+    const int tz = tile_coord(z[p], inv_dz, g.tile, g.ntz);
+    keys[p] = (uint32_t)((tz * g.nty + ty) * g.ntx + tx);
     idx[p] = (uint32_t)p;
 }
 
@@ -247,12 +271,8 @@ __global__ __launch_bounds__(kSortWG) void k_radix_scatter(
 }
 
 template <typename U>
-__global__ __launch_bounds__(kSortWG) void k_permute(ParticlePtrs<U> src, ParticlePtrs<U> dst,
-                                                     const uint32_t* __restrict__ perm,
-                                                     int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
-    if (i >= n) return;
-    const int64_t s = perm[i];
+__device__ __forceinline__ void permute_one(const ParticlePtrs<U>& src,
+                                            const ParticlePtrs<U>& dst, int64_t i, int64_t s) {
     dst.x[i] = src.x[s];
     dst.y[i] = src.y[s];
     dst.xp[i] = src.xp[s];
@@ -263,6 +283,28 @@ __global__ __launch_bounds__(kSortWG) void k_permute(ParticlePtrs<U> src, Partic
     dst.status[i] = src.status[s];
     if (src.qm) dst.qm[i] = src.qm[s];
     if (src.id) dst.id[i] = src.id[s];
+}
+
+template <typename U>
+__global__ __launch_bounds__(kSortWG) void k_permute(ParticlePtrs<U> src, ParticlePtrs<U> dst,
+                                                     const uint32_t* __restrict__ perm,
+                                                     int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
+    if (i >= n) return;
+    permute_one(src, dst, i, (int64_t)perm[i]);
+}
+
+template <typename U>
+__global__ __launch_bounds__(kSortWG) void k_permute3(ParticlePtrs3<U> src,
+                                                      ParticlePtrs3<U> dst,
+                                                      const uint32_t* __restrict__ perm,
+                                                      int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
+    if (i >= n) return;
+    const int64_t s = perm[i];
+    permute_one(src.b, dst.b, i, s);
+    dst.z[i] = src.z[s];
+    dst.zp[i] = src.zp[s];
 }
 
 hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* sums,
@@ -376,6 +418,43 @@ hipError_t launch_permute(const ParticlePtrs<U>& src, const ParticlePtrs<U>& dst
                        n);
     return hipGetLastError();
 }
+
+hipError_t launch_cell_sort3(const double* x, const double* y, const double* z, int64_t n,
+                             double inv_dx, double inv_dy, double inv_dz, const TileGeom3& g,
+                             const SortBuffers& b, hipStream_t stream) {
+    const int ntiles = g.ntx * g.nty * g.ntz;
+    if (n > 0) {
+        const unsigned blocks = (unsigned)((n + kSortWG - 1) / kSortWG);
+        hipLaunchKernelGGL(k_tile_keys3, dim3(blocks), dim3(kSortWG), 0, stream, x, y, z, n,
+                           inv_dx, inv_dy, inv_dz, g, b.keys, b.idx);
+    }
+    int nbits = 0;
+    while ((1 << nbits) < ntiles) ++nbits;
+    uint32_t* kin = b.keys;
+    hipError_t e = radix_sort(n, nbits, b, stream, &kin);
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)((n + 1 + kSortWG - 1) / kSortWG);
+    hipLaunchKernelGGL(k_tile_bounds, dim3(blocks), dim3(kSortWG), 0, stream, kin, n, ntiles,
+                       b.tile_start);
+    return hipGetLastError();
+}
+
+template <typename U>
+hipError_t launch_permute3(const ParticlePtrs3<U>& src, const ParticlePtrs3<U>& dst,
+                           const uint32_t* perm, int64_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n + kSortWG - 1) / kSortWG);
+    hipLaunchKernelGGL(k_permute3<U>, dim3(blocks), dim3(kSortWG), 0, stream, src, dst, perm,
+                       n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_permute3<double>(const ParticlePtrs3<double>&,
+                                            const ParticlePtrs3<double>&, const uint32_t*,
+                                            int64_t, hipStream_t);
+template hipError_t launch_permute3<float>(const ParticlePtrs3<float>&,
+                                           const ParticlePtrs3<float>&, const uint32_t*,
+                                           int64_t, hipStream_t);
 
 template hipError_t launch_permute<double>(const ParticlePtrs<double>&,
                                            const ParticlePtrs<double>&, const uint32_t*,

@@ -35,6 +35,8 @@ GCB_TIMER_PUSH, GCB_TIMER_SORT, GCB_TIMER_BACKWARD, GCB_TIMER_OTHER = 0, 1, 2, 3
 GCB_NTIMERS = 4
 
 YEE_STAGGER = ((0.5, 0.0), (0.0, 0.5), (0.0, 0.0), (0.0, 0.5), (0.5, 0.0), (0.5, 0.5))
+YEE3_STAGGER = ((0.5, 0.0, 0.0), (0.0, 0.5, 0.0), (0.0, 0.0, 0.5),
+                (0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0))
 
 
 class GcbError(RuntimeError):
@@ -81,6 +83,18 @@ class gcb_gr_particles(C.Structure):
                 ("qm", C.c_void_p), ("id", C.c_void_p), ("status", C.c_void_p)]
 
 
+class gcb_grid3_desc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("dtype", C.c_int32), ("d", C.c_double * 3),
+                ("stagger", (C.c_double * 3) * 6)]
+
+
+class gcb_particles3(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("xp", C.c_void_p), ("yp", C.c_void_p), ("zp", C.c_void_p),
+                ("ux", C.c_void_p), ("uy", C.c_void_p), ("uz", C.c_void_p),
+                ("qm", C.c_void_p), ("id", C.c_void_p), ("status", C.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -104,6 +118,10 @@ def _load():
                                          C.POINTER(P * 3), C.c_int32, P]),
         "gcb_push_gr": (C.c_int, [P, C.POINTER(gcb_gr_particles), C.POINTER(gcb_params),
                                   C.c_int32, P, C.POINTER(gcb_stats), P]),
+        "gcb_load_fields_3d": (C.c_int, [P, C.POINTER(gcb_grid3_desc), C.POINTER(P * 3),
+                                         C.POINTER(P * 3), C.c_int32, P]),
+        "gcb_push_3d": (C.c_int, [P, C.POINTER(gcb_particles3), C.POINTER(gcb_params),
+                                  C.c_int32, P, C.POINTER(gcb_stats), P]),
         "gcb_set_timing": (C.c_int, [P, C.c_int32]),
         "gcb_get_timing": (C.c_int, [P, C.POINTER(C.c_double * GCB_NTIMERS),
                                      C.POINTER(C.c_int64 * GCB_NTIMERS)]),
@@ -118,7 +136,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("gcb_create", "gcb_destroy", "gcb_last_error", "gcb_load_fields", "gcb_push",
             "gcb_push_backward", "gcb_kinetic_energy", "gcb_set_timing", "gcb_get_timing",
-            "gcb_load_fields_gr", "gcb_push_gr")
+            "gcb_load_fields_gr", "gcb_push_gr", "gcb_load_fields_3d", "gcb_push_3d")
 
 
 def lib():
@@ -287,6 +305,58 @@ def gcb_push_gr(ctx, parts: gcb_gr_particles, prm: gcb_params, n_steps: int, s_t
                 want_stats: bool = False, stream=None):
     st = gcb_stats() if want_stats else None
     rc = _lib.gcb_push_gr(ctx, C.byref(parts), C.byref(prm), int(n_steps), _ptr(s_trace),
+                          C.byref(st) if st is not None else None, _stream_ptr(stream))
+    _check(rc, ctx)
+    if st is None:
+        return None
+    return {k: getattr(st, k) for k, _ in gcb_stats._fields_}
+
+
+def grid3_desc(nx, ny, nz, dx=1.0, dy=1.0, dz=1.0, stagger=YEE3_STAGGER,
+               dtype=GCB_F64) -> gcb_grid3_desc:
+    d = gcb_grid3_desc()
+    d.n[0], d.n[1], d.n[2] = int(nx), int(ny), int(nz)
+    d.d[0], d.d[1], d.d[2] = float(dx), float(dy), float(dz)
+    d.dtype = int(dtype)
+    for k in range(6):
+        for a in range(3):
+            d.stagger[k][a] = float(stagger[k][a])
+    return d
+
+
+def gcb_load_fields_3d(ctx, desc: gcb_grid3_desc, E, B, src=None, stream=None) -> None:
+    """E, B: sequences of three (nz, ny, nx) float64 arrays (numpy host or torch device)."""
+    if src is None:
+        src = GCB_HOST if isinstance(E[0], np.ndarray) else GCB_DEVICE
+    for a in list(E) + list(B):
+        if isinstance(a, np.ndarray):
+            assert a.dtype == np.float64 and a.flags.c_contiguous
+        else:
+            import torch
+            assert a.dtype == torch.float64 and a.is_contiguous()
+    Ea = (C.c_void_p * 3)(*[_ptr(a) for a in E])
+    Ba = (C.c_void_p * 3)(*[_ptr(a) for a in B])
+    sp = None if src == GCB_HOST and stream is None else _stream_ptr(stream)
+    _check(_lib.gcb_load_fields_3d(ctx, C.byref(desc), C.byref(Ea), C.byref(Ba), int(src), sp),
+           ctx)
+
+
+def particles3(t: dict) -> gcb_particles3:
+    """Build the struct from a dict of tensors x, y, z, xp, yp, zp, ux, uy, uz,
+    status and optional qm, id."""
+    p = gcb_particles3()
+    p.n = int(t["x"].shape[0])
+    for k in ("x", "y", "z", "xp", "yp", "zp", "ux", "uy", "uz", "status"):
+        setattr(p, k, _ptr(t[k]))
+    p.qm = _ptr(t.get("qm"))
+    p.id = _ptr(t.get("id"))
+    return p
+
+
+def gcb_push_3d(ctx, parts: gcb_particles3, prm: gcb_params, n_steps: int, s_trace=None,
+                want_stats: bool = False, stream=None):
+    st = gcb_stats() if want_stats else None
+    rc = _lib.gcb_push_3d(ctx, C.byref(parts), C.byref(prm), int(n_steps), _ptr(s_trace),
                           C.byref(st) if st is not None else None, _stream_ptr(stream))
     _check(rc, ctx)
     if st is None:

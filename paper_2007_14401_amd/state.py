@@ -7,14 +7,16 @@ import torch
 from . import gcb
 
 _KEYS = ("x", "y", "xp", "yp", "ux", "uy", "uz")
+_KEYS3 = ("x", "y", "z", "xp", "yp", "zp", "ux", "uy", "uz")
 
 
 def to_device(ens, device="cuda", form=gcb.GCB_FORM_F64, per_particle_qm=True,
               with_id=True) -> dict:
-    """numpy ensemble (attributes x, y, xp, yp, ux, uy, uz, qm, id) -> dict of tensors."""
+    """numpy ensemble (attributes x, y, xp, yp, ux, uy, uz, qm, id, and z, zp
+    for a 3D ensemble) -> dict of tensors."""
     udt = torch.float64 if form == gcb.GCB_FORM_F64 else torch.float32
     t = {}
-    for k in _KEYS:
+    for k in (_KEYS3 if hasattr(ens, "z") else _KEYS):
         dt = udt if k in ("ux", "uy", "uz") else torch.float64
         t[k] = torch.as_tensor(np.ascontiguousarray(getattr(ens, k)), dtype=dt).to(device)
     n = t["x"].shape[0]

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "gcb.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gcb_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(gcb_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
@@ -44,6 +44,8 @@ def test_null_arguments_rejected_without_device():
     assert lib.gcb_set_timing(None, 1) == gcb.GCB_EINVAL
     assert lib.gcb_load_fields_gr(None, None, None, None, 0, None) == gcb.GCB_EINVAL
     assert lib.gcb_push_gr(None, None, None, 1, None, None, None) == gcb.GCB_EINVAL
+    assert lib.gcb_load_fields_3d(None, None, None, None, 0, None) == gcb.GCB_EINVAL
+    assert lib.gcb_push_3d(None, None, None, 1, None, None, None) == gcb.GCB_EINVAL
     lib.gcb_destroy(None)
 
 
@@ -66,3 +68,5 @@ def test_params_struct_layout_matches_header():
     assert C.sizeof(gcb.gcb_stats) == 5 * 8
     assert C.sizeof(gcb.gcb_gr_desc) == 4 + 4 + 3 * 8 + 8
     assert C.sizeof(gcb.gcb_gr_particles) == 8 + 9 * 8
+    assert C.sizeof(gcb.gcb_grid3_desc) == 3 * 4 + 4 + 3 * 8 + 18 * 8
+    assert C.sizeof(gcb.gcb_particles3) == 8 + 12 * 8

@@ -1,0 +1,351 @@
+"""Parity of the 3D HIP path (trilinear gather, 3D Yee lattice) with the 3D
+CPU oracle (needs an MI355X).
+
+Bar, as for the 2D path: the binary64 kernels evaluate the oracle's
+operations in its order with correctly rounded +, -, *, /, sqrt and no
+contraction, so results agree to the last bit; asserted to 1e-12 relative
+(floors: one cell for positions, c for u), with identical switch decisions at
+every step and identical status bits (the informational LDS-window bit
+excluded).  The mixed form is held to the one-step bounds of the 2D mixed
+form.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_util import log
+from workloads import make_config3
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+GLOBAL, TILED, AUTO = 1, 2, 0
+
+
+def oracle_params3(cfg, **kw):
+    d = dict(dt=cfg.dt, c=cfg.c, f_rho=cfg.f_rho, f_E=cfg.f_E,
+             curvature=bool(cfg.curvature), n_iter=cfg.n_iter, Lx=cfg.Lx, Ly=cfg.Ly,
+             Lz=cfg.Lz, dl=cfg.dl)
+    d.update(kw)
+    return O.Params3(**d)
+
+
+def run_oracle3(cfg, F, ens, steps, trace=False, **kw):
+    prov = O.GridFields3(F, cfg.dx, cfg.dy, cfg.dz, cfg.stagger)
+    return O.push3(prov, O.State3.from_numpy(ens), oracle_params3(cfg, **kw), steps,
+                   trace=trace)
+
+
+class GpuRun3:
+    def __init__(self, cfg, F, dtype=None):
+        from paper_2007_14401_amd import gcb
+        self.gcb, self.cfg = gcb, cfg
+        self.ctx = gcb.gcb_create(0)
+        dtype = gcb.GCB_F64 if dtype is None else dtype
+        desc = gcb.grid3_desc(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dz, cfg.stagger,
+                              dtype)
+        gcb.gcb_load_fields_3d(self.ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
+
+    def params(self, **kw):
+        c = self.cfg
+        d = dict(dt=c.dt, c=c.c, qm=c.qm, f_rho=c.f_rho, f_E=c.f_E, curvature=c.curvature,
+                 n_iter=c.n_iter)
+        d.update(kw)
+        return self.gcb.params(**d)
+
+    def push(self, t, steps, trace=False, stats=False, **kw):
+        n = t["x"].shape[0]
+        tr = torch.zeros((steps, n), dtype=torch.uint8, device=t["x"].device) if trace else None
+        st = self.gcb.gcb_push_3d(self.ctx, self.gcb.particles3(t), self.params(**kw), steps,
+                                  s_trace=tr, want_stats=stats)
+        torch.cuda.synchronize()
+        return tr, st
+
+    def close(self):
+        self.gcb.gcb_destroy(self.ctx)
+
+
+def _state(ens, **kw):
+    from paper_2007_14401_amd import state
+    return state.to_device(ens, "cuda:0", **kw)
+
+
+def rel_errors3(got, ref, cfg):
+    out = {}
+    for k, floor, L in (("x", cfg.dx, cfg.Lx), ("y", cfg.dy, cfg.Ly), ("z", cfg.dz, cfg.Lz),
+                        ("xp", cfg.dx, cfg.Lx), ("yp", cfg.dy, cfg.Ly), ("zp", cfg.dz, cfg.Lz),
+                        ("ux", cfg.c, None), ("uy", cfg.c, None), ("uz", cfg.c, None)):
+        a = np.asarray(got[k], dtype=np.float64)
+        b = getattr(ref, k).numpy()
+        d = np.abs(a - b)
+        if L is not None:
+            d = np.minimum(d, np.abs(L - d))
+        with np.errstate(invalid="ignore"):
+            r = d / np.maximum(np.abs(b), floor)
+        r = np.where(np.isnan(a) & np.isnan(b), 0.0, r)
+        out[k] = float(np.max(r)) if r.size else 0.0
+    return out
+
+
+def _check(got, ref, cfg, what, tr_gpu=None, tr_ref=None):
+    errs = rel_errors3(got, ref, cfg)
+    log(f"{what}: max rel err {max(errs.values()):.2e}")
+    for k, v in errs.items():
+        assert v <= TOL, (what, k, v)
+    st_gpu = got["status"] & ~np.uint8(32)
+    st_ref = ref.status.numpy()
+    assert np.array_equal(st_gpu, st_ref), (what, "status bits differ",
+                                            np.count_nonzero(st_gpu != st_ref))
+    if tr_gpu is not None:
+        mism = np.count_nonzero(tr_gpu.cpu().numpy() != tr_ref.numpy())
+        assert mism == 0, (what, "switch decisions differ", mism)
+
+
+@pytest.fixture(scope="module")
+def h32():
+    cfg = make_config3("harris3d32")
+    F = cfg.fields()
+    run = GpuRun3(cfg, F)
+    yield cfg, F, run
+    run.close()
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile",
+                         [(GLOBAL, 0, 0), (TILED, 1, 6), (TILED, 2, 4), (AUTO, 2, 8)])
+def test_one_step_3d(h32, kernel, sort_every, tile):
+    """Tiles of 6 and 8 leave ragged last tiles on the 32-cell axes."""
+    from paper_2007_14401_amd import state
+    cfg, F, run = h32
+    ens = cfg.particles(n=4096 + 37)
+    log(f"3d one step kernel={kernel} sort_every={sort_every} tile={tile}")
+    t = _state(ens)
+    tr, _ = run.push(t, 1, trace=True, kernel=kernel, sort_every=sort_every, tile=tile)
+    ref, rtr, _ = run_oracle3(cfg, F, ens, 1, trace=True)
+    _check(state.unsort(t), ref, cfg, "3d one step", tr, rtr)
+    assert 0 < int(rtr.sum()) < rtr.numel()
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(GLOBAL, 0, 0), (GLOBAL, 5, 6),
+                                                    (TILED, 2, 6), (TILED, 1, 8)])
+def test_multistep_3d(h32, kernel, sort_every, tile):
+    from paper_2007_14401_amd import state
+    cfg, F, run = h32
+    ens = cfg.particles(n=3000)
+    steps = cfg.steps
+    log(f"3d multistep kernel={kernel} sort_every={sort_every} tile={tile}")
+    t = _state(ens)
+    tr, st = run.push(t, steps, trace=True, stats=True, kernel=kernel,
+                      sort_every=sort_every, tile=tile)
+    ref, rtr, rres = run_oracle3(cfg, F, ens, steps, trace=True)
+    _check(state.unsort(t), ref, cfg, "3d multistep", tr, rtr)
+    assert st["gca_steps"] == int((rtr == 0).sum())
+    assert st["boris_steps"] == int((rtr == 1).sum())
+    assert st["max_fp_residual"] == float(rres.max())
+
+
+VARIANTS = [
+    dict(curvature=0),
+    dict(n_iter=1),
+    dict(f_rho=0.0),                          # every particle Boris
+    dict(f_rho=math.inf, f_E=math.inf),       # every particle guiding center (E > B too)
+]
+
+
+@pytest.mark.parametrize("var", VARIANTS, ids=[str(v) for v in VARIANTS])
+@pytest.mark.parametrize("kernel", [GLOBAL, TILED])
+def test_variants_3d(h32, var, kernel):
+    from paper_2007_14401_amd import state
+    cfg, F, run = h32
+    cfg2 = cfg.with_(**var)
+    ens = cfg.particles(n=1500, seed_offset=5)
+    log(f"3d variant {var} kernel={kernel}")
+    t = _state(ens)
+    tr, _ = run.push(t, 8, trace=True, kernel=kernel, sort_every=2 if kernel == TILED else 0,
+                     tile=6, **var)
+    ref, rtr, _ = run_oracle3(cfg2, F, ens, 8, trace=True)
+    _check(state.unsort(t), ref, cfg2, f"3d variant {var}", tr, rtr)
+
+
+@pytest.mark.parametrize("geom", ["collocated", "cells", "box"])
+def test_grid_geometry_3d(geom):
+    """Runtime lattice offsets (collocated), unequal cell sizes (the switch
+    then uses dl = (dx dy dz)^(1/3) = 0.5), and unequal axis lengths."""
+    from paper_2007_14401_amd import state
+    base = make_config3("harris3d32")
+    if geom == "collocated":
+        cfg = base.with_(stagger=((0.0, 0.0, 0.0),) * 6)
+    elif geom == "cells":
+        cfg = base.with_(dx=0.25, dy=0.5, dz=1.0, delta=2.0, c=0.2)
+    else:
+        cfg = base.with_(nx=40, ny=24, nz=16)
+    F = cfg.fields()
+    run = GpuRun3(cfg, F)
+    try:
+        ens = cfg.particles(n=2000, seed_offset=9)
+        for kernel in (GLOBAL, TILED):
+            log(f"3d geometry {geom} kernel={kernel}")
+            t = _state(ens)
+            tr, _ = run.push(t, 6, trace=True, kernel=kernel,
+                             sort_every=2 if kernel == TILED else 0, tile=6)
+            ref, rtr, _ = run_oracle3(cfg, F, ens, 6, trace=True)
+            _check(state.unsort(t), ref, cfg, f"3d geometry {geom}", tr, rtr)
+    finally:
+        run.close()
+
+
+def test_edge_sizes_3d(h32):
+    """n = 0 and n = 1 through both kernels."""
+    from paper_2007_14401_amd import state
+    cfg, F, run = h32
+    for n in (0, 1):
+        ens = cfg.particles(n=1)
+        if n == 0:
+            ens = ens.subset(slice(0, 0))
+        for kernel, se in ((GLOBAL, 0), (TILED, 1)):
+            t = _state(ens)
+            run.push(t, 3, kernel=kernel, sort_every=se, tile=6)
+            if n:
+                ref, _, _ = run_oracle3(cfg, F, ens, 3)
+                _check(state.unsort(t), ref, cfg, f"3d n={n}")
+
+
+def test_deterministic_3d(h32):
+    cfg, F, run = h32
+    ens = cfg.particles(n=5000, seed_offset=2)
+    outs = []
+    for _ in range(2):
+        t = _state(ens)
+        run.push(t, 10, kernel=TILED, sort_every=2, tile=6)
+        outs.append({k: v.cpu().numpy().copy() for k, v in t.items() if v is not None})
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k].view(np.uint8), outs[1][k].view(np.uint8)), k
+
+
+@pytest.mark.parametrize("tile", [6, 8])
+def test_cell_sort_order_3d(h32, tile):
+    """A stable sort by cubic tile, x fastest (bit-exact index work)."""
+    cfg, F, run = h32
+    ens = cfg.particles(n=4096 + 37, seed_offset=11)
+    t = _state(ens)
+    run.push(t, 1, kernel=TILED, sort_every=1, tile=tile)
+    c = [np.floor(getattr(ens, k) / d).astype(np.int64) // tile
+         for k, d in (("x", cfg.dx), ("y", cfg.dy), ("z", cfg.dz))]
+    ntx, nty = -(-cfg.nx // tile), -(-cfg.ny // tile)
+    key = (c[2] * nty + c[1]) * ntx + c[0]
+    assert np.array_equal(t["id"].cpu().numpy(), np.argsort(key, kind="stable"))
+
+
+@pytest.mark.parametrize("kernel,sort_every", [(GLOBAL, 0), (TILED, 3)])
+def test_replay_3d(h32, kernel, sort_every):
+    cfg, F, run = h32
+    ens = cfg.particles(n=2500, seed_offset=8)
+    t1 = _state(ens)
+    tr, _ = run.push(t1, 10, trace=True, kernel=kernel, sort_every=sort_every, tile=6)
+    tr_copy = tr.clone()
+    t2 = _state(ens)
+    run.gcb.gcb_push_3d(run.ctx, run.gcb.particles3(t2),
+                        run.params(kernel=kernel, sort_every=sort_every, tile=6, replay=1), 10,
+                        s_trace=tr)
+    torch.cuda.synchronize()
+    assert torch.equal(tr, tr_copy)
+    for k in ("x", "y", "z", "xp", "yp", "zp", "ux", "uy", "uz", "status", "id"):
+        assert torch.equal(t1[k], t2[k]), k
+
+
+def test_argument_validation_3d(h32):
+    from paper_2007_14401_amd import gcb
+    cfg, F, run = h32
+    t = _state(cfg.particles(n=64))
+    p = gcb.particles3(t)
+    p.z = None
+    with pytest.raises(gcb.GcbError) as e:
+        gcb.gcb_push_3d(run.ctx, p, run.params(), 1)
+    assert e.value.code == gcb.GCB_EINVAL
+    with pytest.raises(gcb.GcbError) as e:
+        gcb.gcb_push_3d(run.ctx, gcb.particles3(t), run.params(kernel=TILED, sort_every=0), 1)
+    assert e.value.code == gcb.GCB_EUNSUPPORTED
+    # a tile whose window does not fit in LDS: refused for the tiled kernel,
+    # served by the global kernel under AUTO
+    with pytest.raises(gcb.GcbError) as e:
+        gcb.gcb_push_3d(run.ctx, gcb.particles3(t), run.params(kernel=TILED, sort_every=2,
+                                                               tile=16), 1)
+    assert e.value.code == gcb.GCB_EUNSUPPORTED
+    gcb.gcb_push_3d(run.ctx, gcb.particles3(t), run.params(kernel=AUTO, sort_every=2, tile=16), 1)
+    with pytest.raises(gcb.GcbError):
+        gcb.gcb_push_3d(run.ctx, gcb.particles3(t), run.params(form=gcb.GCB_FORM_MIXED), 1)
+    bad = gcb.grid3_desc(1, 8, 8)
+    with pytest.raises(gcb.GcbError) as e:
+        gcb.gcb_load_fields_3d(run.ctx, bad, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
+    assert e.value.code == gcb.GCB_EINVAL
+    ctx = gcb.gcb_create(0)
+    try:
+        with pytest.raises(gcb.GcbError) as e:
+            gcb.gcb_push_3d(ctx, gcb.particles3(t), run.params(), 1)
+        assert e.value.code == gcb.GCB_ENOFIELDS
+    finally:
+        gcb.gcb_destroy(ctx)
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(GLOBAL, 0, 0), (TILED, 2, 6)])
+def test_mixed_one_step_3d(kernel, sort_every, tile):
+    """Mixed form against the binary64 oracle, one step: the bounds of the 2D
+    mixed form (median u error <= 1e-5, 99th percentile <= 1e-3, positions
+    <= 1e-4 cells, switch mismatches <= 0.2 %)."""
+    from paper_2007_14401_amd import gcb, state
+    cfg = make_config3("harris3d32")
+    F = cfg.fields()
+    ens = cfg.particles(n=8192)
+    run = GpuRun3(cfg, F, dtype=gcb.GCB_F32)
+    try:
+        t = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED)
+        tr, _ = run.push(t, 1, trace=True, form=gcb.GCB_FORM_MIXED, kernel=kernel,
+                         sort_every=sort_every, tile=tile)
+    finally:
+        run.close()
+    got = state.unsort(t)
+    ref, rtr, _ = run_oracle3(cfg, F, ens, 1, trace=True)
+    u_g = np.stack([got[k].astype(np.float64) for k in ("ux", "uy", "uz")])
+    u_r = np.stack([getattr(ref, k).numpy() for k in ("ux", "uy", "uz")])
+    du = np.max(np.abs(u_g - u_r), axis=0) / np.maximum(np.max(np.abs(u_r), axis=0), cfg.c)
+    dx = np.max(np.stack([np.minimum(np.abs(got[k] - getattr(ref, k).numpy()),
+                                     L - np.abs(got[k] - getattr(ref, k).numpy()))
+                          for k, L in (("x", cfg.Lx), ("y", cfg.Ly), ("z", cfg.Lz))]), axis=0)
+    mism = float((tr.cpu().numpy() != rtr.numpy()).mean())
+    log(f"3d mixed one step kernel={kernel}: u median {np.median(du):.2e} p99 "
+        f"{np.quantile(du, 0.99):.2e} max {du.max():.2e}; x max {dx.max():.2e}; "
+        f"S mismatch {mism:.2e}")
+    assert np.median(du) <= 1e-5
+    assert np.quantile(du, 0.99) <= 1e-3
+    assert dx.max() <= 1e-4
+    assert mism <= 2e-3
+
+
+def test_full_size_sampled_3d():
+    """harris3d128 at full size (1e7 particles, 100 steps) in the benchmark's
+    launch configuration (tiled, sort every 2 steps, tile 6); 2000 sampled
+    particles recomputed by the oracle."""
+    from paper_2007_14401_amd import state
+    cfg = make_config3("harris3d128")
+    log("3d full size: generating inputs")
+    F = cfg.fields()
+    ens = cfg.particles()
+    run = GpuRun3(cfg, F)
+    try:
+        log("3d full size: gpu push")
+        t = _state(ens)
+        _, st = run.push(t, cfg.steps, stats=True, kernel=TILED, sort_every=2, tile=6)
+        log(f"3d full size stats {st}")
+        ids = t["id"].cpu().numpy()
+        sample = np.sort(np.random.default_rng(78).choice(ens.n, 2000, replace=False))
+        pos = np.empty(ens.n, dtype=np.int64)
+        pos[ids] = np.arange(ens.n)
+        h = {k: (v.cpu().numpy()[pos[sample]] if v is not None else None) for k, v in t.items()}
+        del t
+        log("3d full size: oracle on the sample")
+        ref, _, _ = run_oracle3(cfg, F, ens.subset(sample), cfg.steps)
+        _check(h, ref, cfg, "3d full size sampled")
+    finally:
+        run.close()
