@@ -38,6 +38,9 @@ FLOPS_GCA = 2216.0
 # switch part included.
 FLOPS_GR_ORBIT = 1611.0
 FLOPS_GR_GCA = 2218.0
+# The same count for one step of the 3D scheme (trilinear gather, K = 4).
+FLOPS_BORIS_3D = 528.0
+FLOPS_GCA_3D = 4025.0
 
 # Hardware-counter record of the binary64 push kernel (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, calibrated against a plain device copy); it is used only
@@ -180,6 +183,12 @@ def main():
     ap.add_argument("--gr-steps", type=int, default=40)
     ap.add_argument("--gr-warmup", type=int, default=4)
     ap.add_argument("--gr-sort-every", type=int, default=16)
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--d3-steps", type=int, default=40)
+    ap.add_argument("--d3-warmup", type=int, default=4)
+    ap.add_argument("--d3-sort-every", type=int, default=2)
+    ap.add_argument("--d3-tile", type=int, default=6)
+    ap.add_argument("--d3-kernel", type=int, default=0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -348,6 +357,62 @@ def main():
             gcb.gcb_destroy(ctx)
             torch.cuda.empty_cache()
 
+    def time_3d(steps: int, warmup: int, mixed: bool = False):
+        """3D push: 128^3 periodic double Harris sheet with oblique tearing,
+        1e7 particles (the workload's own size), binary64 or the mixed form."""
+        from workloads import make_config3
+        c3 = make_config3("harris3d128")
+        log(f"[bench] 3d: generating {c3.name}, n={c3.n}")
+        F3 = c3.fields()
+        e3 = c3.particles()
+        form = gcb.GCB_FORM_MIXED if mixed else gcb.GCB_FORM_F64
+        ctx = gcb.gcb_create(0)
+        try:
+            desc = gcb.grid3_desc(c3.nx, c3.ny, c3.nz, c3.dx, c3.dy, c3.dz, c3.stagger,
+                                  gcb.GCB_F32 if mixed else gcb.GCB_F64)
+            gcb.gcb_load_fields_3d(ctx, desc, [F3[0], F3[1], F3[2]], [F3[3], F3[4], F3[5]])
+            del F3
+            t = state.to_device(e3, dev, form=form, per_particle_qm=False)
+            parts = gcb.particles3(t)
+            prm = gcb.params(dt=c3.dt, c=c3.c, qm=c3.qm, f_rho=c3.f_rho, f_E=c3.f_E,
+                             curvature=c3.curvature, n_iter=c3.n_iter, form=form,
+                             sort_every=a.d3_sort_every, kernel=a.d3_kernel, tile=a.d3_tile)
+            st = gcb.gcb_push_3d(ctx, parts, prm, warmup, want_stats=True)
+            frac = st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])
+            halo = st["halo_misses"] / max(1, st["gca_steps"] + st["boris_steps"])
+            gcb.gcb_set_timing(ctx, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gcb.gcb_push_3d(ctx, parts, prm, steps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ms, cnt = gcb.gcb_get_timing(ctx)
+            gcb.gcb_set_timing(ctx, False)
+            kms = ms[gcb.GCB_TIMER_PUSH] / steps
+            sort_ms = ms[gcb.GCB_TIMER_SORT] / max(1, cnt[gcb.GCB_TIMER_SORT])
+            fl = FLOPS_GCA_3D * frac + FLOPS_BORIS_3D * (1.0 - frac)
+            tf = fl * e3.n / (kms * 1e-3) / 1e12
+            log(f"[bench] 3d: {steps} steps in {t1 - t0:.3f} s; kernel ms {ms}")
+            del t
+            return {"value": e3.n * steps / (t1 - t0), "unit": "particle-steps/s",
+                    "workload": f"{c3.name}: {c3.nx}x{c3.ny}x{c3.nz} periodic double Harris "
+                                f"sheet (guide 0.1 B0, oblique tearing, inflow E, reconnection "
+                                f"Ez along the X lines), 3D Yee lattice, trilinear gather, "
+                                f"{e3.n} electrons MJ theta=1 + Gamma^-2 power law to 1e4, "
+                                + ("binary32 bulk, binary64 positions" if mixed
+                                   else "binary64"),
+                    "steps": steps, "ms_per_step": (t1 - t0) * 1e3 / steps,
+                    "kernel_ms_per_step": kms, "gca_fraction": frac,
+                    "halo_miss_fraction": halo,
+                    "sort_every": a.d3_sort_every, "tile": a.d3_tile,
+                    "sort_ms_per_sort": sort_ms,
+                    "algorithmic_flops_per_particle_step": fl,
+                    "alu_achieved_TFLOPs": tf, "alu_frac": tf / FP64_VECTOR_PEAK_TF,
+                    "kernel": ["auto", "k_push3_global", "k_push3_tiled"][a.d3_kernel]}
+        finally:
+            gcb.gcb_destroy(ctx)
+            torch.cuda.empty_cache()
+
     r64 = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup)
     wall, push_ms, sort_ms, gca_frac = r64["wall"], r64["push_ms"], r64["sort_ms"], r64["gca_frac"]
     bytes_step = push_bytes_per_step(n, cfg.nx, cfg.ny, 0)
@@ -377,6 +442,13 @@ def main():
             forms["gr_mixed"] = time_gr(a.gr_steps, a.gr_warmup, mixed=True)
             forms["gr_mixed"]["speedup_vs_gr_f64"] = (forms["gr_mixed"]["value"]
                                                       / forms["gr"]["value"])
+
+    if not a.no_3d:
+        forms["d3"] = time_3d(a.d3_steps, a.d3_warmup)
+        if not a.no_mixed:
+            forms["d3_mixed"] = time_3d(a.d3_steps, a.d3_warmup, mixed=True)
+            forms["d3_mixed"]["speedup_vs_d3_f64"] = (forms["d3_mixed"]["value"]
+                                                      / forms["d3"]["value"])
 
     if not a.no_adjoint:
         forms["fwd_adjoint"] = time_fwd_adjoint(a.adjoint_steps, 32)

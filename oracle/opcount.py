@@ -82,6 +82,37 @@ def count(cfg_name="harris4096", n=4096, **over):
     return (c.flops + calls["n"]) / n, c.by, calls["n"] / n
 
 
+def count3(cfg_name="harris3d128", n=4096, **over):
+    """The same count for one step of the 3D oracle."""
+    import oracle.pusher as pusher
+    import oracle.pusher3d as pusher3d
+    from workloads import make_config3
+    from .fields3d import GridFields3
+    cfg = make_config3(cfg_name)
+    F = cfg.fields()
+    ens = cfg.particles(n=n)
+    p = pusher3d.Params3(dt=cfg.dt, c=cfg.c, f_rho=cfg.f_rho, f_E=cfg.f_E, curvature=True,
+                         n_iter=cfg.n_iter, Lx=cfg.Lx, Ly=cfg.Ly, Lz=cfg.Lz, dl=cfg.dl)
+    for k, v in over.items():
+        setattr(p, k, v)
+    prov = GridFields3(F, cfg.dx, cfg.dy, cfg.dz, cfg.stagger)
+    st = pusher3d.State3.from_numpy(ens)
+    import oracle.ieee as ieee
+    orig = ieee.sqrt
+    calls = {"n": 0}
+
+    def counting_sqrt(x):
+        calls["n"] += x.numel()
+        return orig(x)
+    pusher.sqrt = pusher3d.sqrt = counting_sqrt
+    try:
+        with _Count() as c:
+            pusher3d.step3(prov, st, p)
+    finally:
+        pusher.sqrt = pusher3d.sqrt = orig
+    return (c.flops + calls["n"]) / n
+
+
 def count_gr(cfg_name="grbh512", n=4096):
     """Per-branch operations of one curved-spacetime step: the switch part
     (metric, gather and switch at x^n) plus one branch, per particle."""
@@ -131,6 +162,10 @@ def main():
     print(f"Guiding-center branch:  {g:8.1f} flops/particle-step ({gs:.1f} sqrt), K=4, curvature")
     g3, _, _ = count(f_rho=math.inf, f_E=math.inf, n_iter=3)
     print(f"Guiding-center, K=3:    {g3:8.1f}")
+    b3 = count3(f_rho=0.0)
+    g3d = count3(f_rho=math.inf, f_E=math.inf)
+    print(f"3D Boris branch:        {b3:8.1f} flops/particle-step")
+    print(f"3D guiding-center:      {g3d:8.1f} flops/particle-step, K=4, curvature")
     gr_counts = count_gr()
     sw = gr_counts["switch"][0]
     for k in ("full orbit", "guiding center"):
