@@ -349,3 +349,59 @@ def test_full_size_sampled_3d():
         _check(h, ref, cfg, "3d full size sampled")
     finally:
         run.close()
+
+
+def test_mixed_report_3d_1e7():
+    """Mixed form on the full 3D workload (128^3, 1e7 particles, 100 steps,
+    the benchmark's launch configuration): 2000 sampled particles against the
+    binary64 oracle; errors and switch mismatches recorded, with the loose
+    multi-step bounds of the 2D report."""
+    import json
+    import os
+    from paper_2007_14401_amd import gcb, state
+    cfg = make_config3("harris3d128")
+    log("3d mixed report: generating inputs")
+    F = cfg.fields()
+    ens = cfg.particles()
+    run = GpuRun3(cfg, F, dtype=gcb.GCB_F32)
+    try:
+        t = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED)
+        tr, st = run.push(t, cfg.steps, trace=True, stats=True, form=gcb.GCB_FORM_MIXED,
+                          kernel=TILED, sort_every=2, tile=6)
+    finally:
+        run.close()
+    ids = t["id"].cpu().numpy()
+    sample = np.sort(np.random.default_rng(124).choice(ens.n, 2000, replace=False))
+    pos = np.empty(ens.n, dtype=np.int64)
+    pos[ids] = np.arange(ens.n)
+    sel = torch.as_tensor(pos[sample], device=t["x"].device)
+    got = {k: (v[sel].cpu().numpy() if v is not None else None) for k, v in t.items()}
+    trs = tr[:, torch.as_tensor(sample, device=tr.device)].cpu().numpy()
+    del t, tr
+    torch.cuda.empty_cache()
+    log("3d mixed report: oracle on the sample")
+    ref, rtr, _ = run_oracle3(cfg, F, ens.subset(sample), cfg.steps, trace=True)
+    u_g = np.stack([got[k].astype(np.float64) for k in ("ux", "uy", "uz")])
+    u_r = np.stack([getattr(ref, k).numpy() for k in ("ux", "uy", "uz")])
+    du = np.max(np.abs(u_g - u_r), axis=0) / np.maximum(np.max(np.abs(u_r), axis=0), cfg.c)
+    dx = np.max(np.stack([np.minimum(np.abs(got[k] - getattr(ref, k).numpy()),
+                                     L - np.abs(got[k] - getattr(ref, k).numpy()))
+                          for k, L in (("x", cfg.Lx), ("y", cfg.Ly), ("z", cfg.Lz))]), axis=0)
+    mism = trs != rtr.numpy()
+    ever = mism.any(axis=0)
+    rep = {"workload": cfg.name, "particles": ens.n, "steps": cfg.steps, "sample": 2000,
+           "u_rel_err": {"median": float(np.median(du)), "p99": float(np.quantile(du, 0.99)),
+                         "max": float(du.max())},
+           "x_abs_err_cells": {"median": float(np.median(dx)),
+                               "p99": float(np.quantile(dx, 0.99)), "max": float(dx.max())},
+           "switch_mismatch_fraction_particle_steps": float(mism.mean()),
+           "particles_with_any_switch_mismatch": float(ever.mean()),
+           "u_rel_err_median_no_mismatch": float(np.median(du[~ever])) if (~ever).any() else None,
+           "gca_fraction": st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])}
+    log("3d mixed report " + json.dumps(rep))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    os.makedirs(os.path.join(root, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(root, "gpurun_out", "d3_mixed_report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    assert rep["u_rel_err"]["median"] <= 1e-3
+    assert rep["switch_mismatch_fraction_particle_steps"] <= 1e-2
