@@ -18,6 +18,9 @@ Layout of the oracle:
               scheme (Sec. 3.1) and the multi-step driver.
   loss.py     mean kinetic energy and its gradient by reverse-mode autograd of
               the oracle itself (the oracle gradient of the adjoint checks).
+  frame.py    the exact guiding-center frame of Sec. 2.2 (exact v_E, kappa,
+              B', E', Psi, eta, xi, b*), used by the zero-curvature scheme
+              when Params.exact_frame is set.
   fields3d.py the 3D gather: trilinear interpolation with a linear shape
               function and its gradient on a staggered periodic 3D grid, plus
               closed-form 3D providers used by the pins.
@@ -41,6 +44,7 @@ from .pusher import (Params, State, ST_NONFINITE, ST_KAPPA, ST_QUAD, ST_BZERO,
 from .loss import kinetic_energy, push_gradients
 from .fields3d import (GridFields3, UniformFields3, LinearFields3, CircularFieldsXZ,
                        FieldSample3, YEE3, COLLOCATED3)
+from .frame import exact_frame, local_exact
 from .pusher3d import Params3, State3, local3, boris_step3, gca_step3, step3, push3
 
 __all__ = [
@@ -51,5 +55,5 @@ __all__ = [
     "min_image", "parallel_update", "kinetic_energy", "push_gradients",
     "GridFields3", "UniformFields3", "LinearFields3", "CircularFieldsXZ", "FieldSample3",
     "YEE3", "COLLOCATED3", "Params3", "State3", "local3", "boris_step3", "gca_step3",
-    "step3", "push3",
+    "step3", "push3", "exact_frame", "local_exact",
 ]

@@ -32,6 +32,9 @@ design notes of the repository):
     iterations R^{k+1} = R^k - H(R^k) from R^0 = R^n; the last increment
     |R^K - R^{K-1}| is the reported iteration error.
   * Periodic box; stored positions are wrapped into [0, L).
+  * Params.exact_frame (zero-curvature scheme only): b*, the exact v_E and
+    kappa and E_par = E'/kappa of the frame of Sec. 2.2 (frame.py) in place of
+    b, c E x B/B^2 and E.b; everything else unchanged.
 """
 from __future__ import annotations
 
@@ -67,6 +70,7 @@ class Params:
     Lx: float = 0.0
     Ly: float = 0.0
     dl: float = 1.0   # effective cell size sqrt(dx*dy)
+    exact_frame: bool = False   # b*, exact v_E (frame.py); zero-curvature scheme only
 
     @property
     def c2(self) -> float:
@@ -131,7 +135,12 @@ def local(prov, X, Y, p: Params):
     Returns a namespace with B, inv_B, b=(bx,by,bz), vE, kappa, Epar,
     bgb = (b.grad)b, vgb = (v_E.grad)b, A = v_E.(b.grad)b,
     C = v_E.(v_E.grad)b, the raw E and B vectors and status flags.
+    With p.exact_frame, the quantities of the exact frame (frame.py).
     """
+    if p.exact_frame:
+        from .frame import local_exact
+        assert not p.curvature, "the exact frame is used with the zero-curvature scheme"
+        return local_exact(prov, X, Y, p)
     s = prov(X, Y)
     Ex, Ey, Ez = s.E
     Bx, By, Bz = s.B
