@@ -183,6 +183,7 @@ def main():
     ap.add_argument("--gr-steps", type=int, default=40)
     ap.add_argument("--gr-warmup", type=int, default=4)
     ap.add_argument("--gr-sort-every", type=int, default=16)
+    ap.add_argument("--no-frame", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--d3-steps", type=int, default=40)
     ap.add_argument("--d3-warmup", type=int, default=4)
@@ -220,18 +221,21 @@ def main():
 
     dev = torch.device("cuda:0")
 
-    def time_form(form: int, fields_dtype: int, steps: int, warmup: int):
-        """Time `steps` pushes of the whole population in one form."""
+    def time_form(form: int, fields_dtype: int, steps: int, warmup: int, **extra):
+        """Time `steps` pushes of the whole population in one form (extra:
+        overrides of the push parameters)."""
         ctx = gcb.gcb_create(0)
         try:
             desc = gcb.grid_desc(cfg.nx, cfg.ny, cfg.dx, cfg.dy, cfg.stagger, fields_dtype)
             gcb.gcb_load_fields(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
             t = state.to_device(ens, dev, form=form, per_particle_qm=False)
             parts = gcb.particles(t)
+            kw = dict(curvature=cfg.curvature)
+            kw.update(extra)
             prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
-                             curvature=cfg.curvature, n_iter=cfg.n_iter, form=form,
-                             sort_every=a.sort_every, kernel=a.kernel, tile=a.tile)
-            log(f"[bench] form {form}: warmup {warmup} steps")
+                             n_iter=cfg.n_iter, form=form, sort_every=a.sort_every,
+                             kernel=a.kernel, tile=a.tile, **kw)
+            log(f"[bench] form {form} {extra}: warmup {warmup} steps")
             st = gcb.gcb_push(ctx, parts, prm, warmup, want_stats=True)
             log(f"[bench] warmup stats {st}")
             gcb.gcb_set_timing(ctx, True)
@@ -442,6 +446,20 @@ def main():
             forms["gr_mixed"] = time_gr(a.gr_steps, a.gr_warmup, mixed=True)
             forms["gr_mixed"]["speedup_vs_gr_f64"] = (forms["gr_mixed"]["value"]
                                                       / forms["gr"]["value"])
+
+    if not a.no_frame:
+        # the exact guiding-center frame against the reduced one, both with the
+        # zero-curvature scheme (the only one the exact frame serves)
+        fr = {}
+        for name, frame in (("reduced", gcb.GCB_FRAME_REDUCED), ("exact", gcb.GCB_FRAME_EXACT)):
+            r = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup, curvature=0,
+                          frame=frame)
+            fr[name] = {"value": n * a.steps / r["wall"], "kernel_ms": r["push_ms"],
+                        "gca_fraction": r["gca_frac"]}
+        forms["frame_no_curvature"] = {
+            "workload": f"{cfg.name}, binary64, curvature terms off (Sec. 2.2.1)",
+            "unit": "particle-steps/s", "reduced": fr["reduced"], "exact": fr["exact"],
+            "exact_over_reduced": fr["exact"]["value"] / fr["reduced"]["value"]}
 
     if not a.no_3d:
         forms["d3"] = time_3d(a.d3_steps, a.d3_warmup)

@@ -58,6 +58,12 @@ extern "C" {
                               selected quantities; state u is float; needs
                               fields loaded with dtype GCB_F32 */
 
+/* guiding-center frame (gcb_params.frame) */
+#define GCB_FRAME_REDUCED 0   /* the paper's schemes: b = B/B, v_E = c E x B/B^2, E_par = E.b */
+#define GCB_FRAME_EXACT   1   /* the exact frame of Sec. 2.2: b*, the exact v_E and kappa,
+                                 E_par = E'/kappa; with curvature = 0, GCB_FORM_F64 and
+                                 gcb_push only */
+
 /* where field arrays live (gcb_load_fields.src) */
 #define GCB_HOST   0
 #define GCB_DEVICE 1
@@ -137,6 +143,15 @@ typedef struct {
                             earlier gcb_push over the same particles) instead of
                             evaluating the switch; the push is then the map that
                             gcb_push_backward differentiates, with S held fixed */
+    int32_t frame;       /* GCB_FRAME_REDUCED (0) or GCB_FRAME_EXACT.  The exact frame
+                            (Sec. 2.2): w_E = c E x B/(E^2 + B^2), s = sqrt(1 - 4 w_E^2/c^2),
+                            v_E = 2 w_E/(1 + s), kappa = (1 - v_E^2/c^2)^(-1/2),
+                            B' = sqrt((B^2 - E^2 + (E^2 + B^2) s)/2), E' = E.B/B',
+                            b* = eta (Psi E_perp + B) with Psi = 2 E' B^2/(B'(E^2+B^2)(1+s)),
+                            eta = 1/(B sqrt(Psi^2 E_perp^2/B^2 + 1)); the zero-curvature
+                            scheme (Sec. 2.2.1) and the conversions of Sec. 3.1 then use
+                            b*, this v_E and kappa, and du_par/dt = (q/m) E'/kappa.  Other
+                            calls and combinations return GCB_EUNSUPPORTED. */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.

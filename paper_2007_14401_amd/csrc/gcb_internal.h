@@ -33,6 +33,7 @@ struct PushLaunch {
     bool replay;           // read the decisions from `trace` instead of writing them
     DevStats* stats;       // nullable
     int steps = 1;         // global kernel: steps per launch (trace: steps*n bytes)
+    bool exact = false;    // guiding-center branch in the exact frame (binary64 only)
 };
 
 // binary64 form (fields double, u double)

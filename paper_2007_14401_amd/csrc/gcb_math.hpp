@@ -267,6 +267,84 @@ GCB_HD uint32_t local_from_sample(const Sample<R>& s, const Consts<R>& K, Local<
     return flags;
 }
 
+// The exact frame of Sec. 2.2: the frame moving with v_E in which E and B
+// are parallel.  With s = sqrt(1 - 4 w_E^2/c^2), w_E = c E x B/(E^2 + B^2):
+// v_E = 2 w_E/(1 + s) (the paper's w_E (1 - s)/(2 w_E^2/c^2) without its
+// 0/0), B' = sqrt((B^2 - E^2 + (E^2 + B^2) s)/2), E' = E.B/B',
+// Psi = 2 E' B^2/(B' (E^2 + B^2)(1 + s)) (equal to E'(B^2 - B'^2)/(B' E_perp^2)),
+// eta = 1/(B sqrt(Psi^2 E_perp^2/B^2 + 1)), b* = eta (Psi E_perp + B).
+// Fills L with b = b*, the exact v_E and kappa, and E_par = E'/kappa (the
+// parallel force in the moving frame, its clock slowed by kappa); the lab B
+// stays in L.B.  The curvature terms are not formed: this frame serves the
+// zero-curvature scheme (Sec. 2.2.1).
+template <typename R>
+GCB_HD uint32_t local_fields_exact(const R E[3], const R Bv[3], const Consts<R>& K,
+                                   Local<R>& L) {
+    uint32_t flags = 0;
+    const R Ex = E[0], Ey = E[1], Ez = E[2];
+    const R Bx = Bv[0], By = Bv[1], Bz = Bv[2];
+    const R E2 = (Ex * Ex + Ey * Ey) + Ez * Ez;
+    const R B2 = (Bx * Bx + By * By) + Bz * Bz;
+    const R EB = (Ex * Bx + Ey * By) + Ez * Bz;
+    const R S = E2 + B2;
+    const R B = sqrt(B2);
+    const bool bzero = (B == (R)0);
+    const R inv_B = bzero ? (R)0 : (R)1 / B;
+    if (bzero) flags |= ST_BZERO;
+    L.B = B;
+    L.inv_B = inv_B;
+    const R f = (S == (R)0) ? (R)0 : K.c / S;
+    const R wx = f * (Ey * Bz - Ez * By);
+    const R wy = f * (Ez * Bx - Ex * Bz);
+    const R wz = f * (Ex * By - Ey * Bx);
+    const R w2 = (wx * wx + wy * wy) + wz * wz;
+    const R s_arg = (R)1 - ((R)4 * w2) * K.inv_c2;
+    const R s = sqrt(s_arg > (R)0 ? s_arg : (R)0);
+    const R g = (R)2 / ((R)1 + s);
+    const R vEx = g * wx, vEy = g * wy, vEz = g * wz;
+    L.vE[0] = vEx; L.vE[1] = vEy; L.vE[2] = vEz;
+    const R vE2 = (vEx * vEx + vEy * vEy) + vEz * vEz;
+    R om = (R)1 - vE2 * K.inv_c2;
+    if (om < (R)kKappaFloor) {
+        om = (R)kKappaFloor;
+        flags |= ST_KAPPA;
+    }
+    const R kappa = (R)1 / sqrt(om);
+    L.kappa = kappa;
+    const R Bp2 = (R)0.5 * ((B2 - E2) + S * s);
+    const R Bp = sqrt(Bp2 > (R)0 ? Bp2 : (R)0);
+    const bool bpzero = (Bp == (R)0);
+    const R Ep = bpzero ? (R)0 : EB / Bp;
+    const R a = bzero ? (R)0 : EB / B2;
+    const R epx = Ex - a * Bx, epy = Ey - a * By, epz = Ez - a * Bz;
+    const R Eperp2 = (epx * epx + epy * epy) + epz * epz;
+    const R Psi = bpzero ? (R)0 : (((R)2 * Ep) * B2) / ((Bp * S) * ((R)1 + s));
+    const R q = bzero ? (R)0 : ((Psi * Psi) * Eperp2) / B2;
+    const R eta = bzero ? (R)0 : (R)1 / (B * sqrt(q + (R)1));
+    const R xi = eta * Psi;
+    L.b[0] = xi * epx + eta * Bx;
+    L.b[1] = xi * epy + eta * By;
+    L.b[2] = xi * epz + eta * Bz;
+    L.Epar = Ep / kappa;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        L.bgb[i] = (R)0;
+        L.vgb[i] = (R)0;
+    }
+    L.A = (R)0;
+    L.C = (R)0;
+    return flags;
+}
+
+// the local quantities of the guiding-center step in the chosen frame
+template <bool kExact, typename R>
+GCB_HD uint32_t local_in_frame(const Sample<R>& s, const Consts<R>& K, Local<R>& L) {
+    if constexpr (kExact)
+        return local_fields_exact(s.E, s.B, K, L);
+    else
+        return local_from_sample(s, K, L);
+}
+
 // Gamma(R, u_par) = kappa sqrt(1 + (u_par^2 + 2 mu B kappa/m)/c^2)  (eq. lfacgca2)
 template <typename R>
 GCB_HD R gamma_gca(const Local<R>& L, R upar, R mu, const Consts<R>& K) {
@@ -476,12 +554,13 @@ GCB_HD double nan_max(double a, double b) {
 
 // One guiding-center step.  sn is the gather (with gradients) at x^n.
 // Returns status flags; res receives |R^K - R^{K-1}|_inf.
-template <typename R, bool kYee, class Acc>
+// kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only).
+template <typename R, bool kYee, bool kExact = false, class Acc>
 GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
                                              const PushConst& pc, const Consts<R>& K,
                                              double& res) {
     uint32_t flags = 0;
-    const bool curv = pc.curvature != 0;
+    const bool curv = !kExact && pc.curvature != 0;
     const double x = r.x, y = r.y;
     const R ux = r.ux, uy = r.uy, uz = r.uz;
     const R qm = (R)r.qm;
@@ -495,7 +574,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
         Sample<R> sh;
         gather<R, true, kYee>(acc, pc, K, Rhx, Rhy, sh);
         Local<R> Lh;
-        flags |= local_from_sample(sh, K, Lh);
+        flags |= local_in_frame<kExact>(sh, K, Lh);
         upar = (ux * Lh.b[0] + uy * Lh.b[1]) + uz * Lh.b[2];
         const R gf = gamma_full(ux, uy, uz, K);
         R vc[3] = {(R)0, (R)0, (R)0};
@@ -516,7 +595,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     R upn, Fnx, Fny;
     {
         Local<R> Ln;
-        flags |= local_from_sample(sn, K, Ln);
+        flags |= local_in_frame<kExact>(sn, K, Ln);
         upn = parallel_update(Ln, upar, mu, qm, curv, K, flags);
         drift_terms(Ln, upn, mu, inv_qm, curv, K, Fnx, Fny);
     }
@@ -534,7 +613,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
             Sample<R> sk;
             gather<R, true, kYee>(acc, pc, K, Rx, Ry, sk);
             Local<R> Lk;
-            flags |= local_from_sample(sk, K, Lk);
+            flags |= local_in_frame<kExact>(sk, K, Lk);
             drift_terms(Lk, upn, mu, inv_qm, curv, K, Fkx, Fky);
         }
         const double Rx_new = x + (double)(K.h * (Fnx + Fkx));
@@ -553,7 +632,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
         Sample<R> sm;
         gather<R, true, kYee>(acc, pc, K, Rmx, Rmy, sm);
         Local<R> Lm;
-        flags |= local_from_sample(sm, K, Lm);
+        flags |= local_in_frame<kExact>(sm, K, Lm);
         const R gr = gamma_gca(Lm, upn, mu, K);
         R vc[3] = {(R)0, (R)0, (R)0};
         if (curv) v_curv(Lm, upn, gr, inv_qm, K, vc);

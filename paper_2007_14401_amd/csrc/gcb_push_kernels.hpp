@@ -127,8 +127,9 @@ __device__ __forceinline__ int split_queues(int m, uint16_t* queue, int* wave_g,
     return nG;
 }
 
-// one coupled step for a particle already in registers
-template <typename R, bool kYee, class Acc>
+// one coupled step for a particle already in registers (kExact: the
+// guiding-center branch in the exact frame of Sec. 2.2)
+template <typename R, bool kYee, bool kExact, class Acc>
 __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Regs<R>& r,
                                                    const PushConst& pc, const Consts<R>& K,
                                                    double& res) {
@@ -137,7 +138,7 @@ __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Reg
     if (gca) {
         Sample<R> s;
         gather<R, true, kYee>(acc, pc, K, r.x, r.y, s);
-        fl = gca_step<R, kYee>(acc, s, r, pc, K, res);
+        fl = gca_step<R, kYee, kExact>(acc, s, r, pc, K, res);
     } else {
         Sample<R> s;
         gather<R, false, kYee>(acc, pc, K, r.x, r.y, s);
@@ -148,7 +149,7 @@ __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Reg
 
 // ns steps of one particle per lane (the particle stays in registers between
 // them); trace (per step n bytes) is indexed by id when ids are present
-template <typename R, typename T, bool kYee>
+template <typename R, typename T, bool kYee, bool kExact>
 __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, ParticlePtrs<R> out,
                                                       int64_t n, int ns, const T* __restrict__ F,
                                                       PushConst pc, uint8_t* trace,
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
                 gca = switch_gca(smp.E, smp.B, r.ux, r.uy, r.uz, r.qm, pc, K);
             }
             double res;
-            fl |= coupled_update<R, kYee>(acc, gca, r, pc, K, res);
+            fl |= coupled_update<R, kYee, kExact>(acc, gca, r, pc, K, res);
             if (tr && !replay) tr[ti] = gca ? 0 : 1;
             if (gca) {
                 ++cnt_g;
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
     if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
-template <typename R, typename T, bool kYee, int kMinWaves>
+template <typename R, typename T, bool kYee, int kMinWaves, bool kExact>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict__ tile_start,
              TileGeom g, int chunk, const T* __restrict__ F, PushConst pc, uint8_t* trace,
@@ -256,7 +257,7 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict_
             load_particle(in, p, pc.qm, r);
             acc.miss = false;
             double res;
-            uint32_t fl = coupled_update<R, kYee>(acc, gca, r, pc, K, res);
+            uint32_t fl = coupled_update<R, kYee, kExact>(acc, gca, r, pc, K, res);
             if (acc.miss) {
                 fl |= ST_HALO;
                 ++cnt_h;
@@ -275,19 +276,19 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict_
     if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
 }
 
-template <typename R, typename T, int kMinWaves>
-hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
-                       const ParticlePtrs<R>& out, const PushConst& pc, hipStream_t stream) {
-    if (L.n == 0) return hipSuccess;
+template <typename R, typename T, int kMinWaves, bool kExact>
+hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
+                             const ParticlePtrs<R>& out, const PushConst& pc,
+                             hipStream_t stream) {
     const T* F = static_cast<const T*>(L.fields);
     if (L.kind == PushKind::Global) {
         const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
         const int ns = L.steps > 0 ? L.steps : 1;
         if (L.yee)
-            hipLaunchKernelGGL((k_push_global<R, T, true>), dim3(blocks), dim3(kWG), 0, stream,
-                               in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
+            hipLaunchKernelGGL((k_push_global<R, T, true, kExact>), dim3(blocks), dim3(kWG), 0,
+                               stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
         else
-            hipLaunchKernelGGL((k_push_global<R, T, false>), dim3(blocks), dim3(kWG), 0,
+            hipLaunchKernelGGL((k_push_global<R, T, false, kExact>), dim3(blocks), dim3(kWG), 0,
                                stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
         return hipGetLastError();
     }
@@ -295,14 +296,14 @@ hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
     const int chunk = (ntiles + 7) / 8;
     const size_t lds = tiled_lds_bytes(L.geom.window, sizeof(T));
     if (L.yee) {
-        auto kfn = k_push_tiled<R, T, true, kMinWaves>;
+        auto kfn = k_push_tiled<R, T, true, kMinWaves, kExact>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay,
                            L.stats);
     } else {
-        auto kfn = k_push_tiled<R, T, false, kMinWaves>;
+        auto kfn = k_push_tiled<R, T, false, kMinWaves, kExact>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
@@ -310,6 +311,20 @@ hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
                            L.stats);
     }
     return hipGetLastError();
+}
+
+// the exact frame exists for the binary64 form only (the host rejects the
+// other combination)
+template <typename R, typename T, int kMinWaves>
+hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
+                       const ParticlePtrs<R>& out, const PushConst& pc, hipStream_t stream) {
+    if (L.n == 0) return hipSuccess;
+    if constexpr (!kMixed<R>) {
+        if (L.exact) return launch_push_frame<R, T, kMinWaves, true>(L, in, out, pc, stream);
+    } else {
+        if (L.exact) return hipErrorInvalidValue;
+    }
+    return launch_push_frame<R, T, kMinWaves, false>(L, in, out, pc, stream);
 }
 
 }  // namespace kern
