@@ -32,6 +32,12 @@ namespace {
 
 constexpr int kWG = 128;
 
+// Minimum waves per SIMD the step VJP kernels are compiled for (register
+// budget; 1 leaves it to the compiler).
+#ifndef GCB_ADJ_MIN_WAVES
+#define GCB_ADJ_MIN_WAVES 1
+#endif
+
 // Recorded gather points of one step, structure of arrays over particles:
 // X[s*n + p], Y[s*n + p] and bar[(s*12 + c)*n + p] for slot s of particle p,
 // c = E_x..E_z, B_x..B_z, dB/dx (3), dB/dy (3).
@@ -60,12 +66,10 @@ struct RecordSink {
 // One regime per launch: lanes whose particle took the other branch at this
 // step return at once, so no wavefront executes both reverse branches.
 template <bool kYee, bool kBoris>
-__global__ __launch_bounds__(kWG) void k_adjoint_step(const double* __restrict__ st,
-                                                      const double* __restrict__ qm_arr,
-                                                      const uint8_t* __restrict__ S,
-                                                      double* lam, int64_t n,
-                                                      const double* __restrict__ F,
-                                                      PushConst pc, RecordSink rec) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(GCB_ADJ_MIN_WAVES))) void
+k_adjoint_step(const double* __restrict__ st, const double* __restrict__ qm_arr,
+               const uint8_t* __restrict__ S, double* lam, int64_t n,
+               const double* __restrict__ F, PushConst pc, RecordSink rec) {
     const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (p >= n || (S[p] != 0) != kBoris) return;
     double s[7], l[7];
