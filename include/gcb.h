@@ -61,8 +61,8 @@ extern "C" {
 /* guiding-center frame (gcb_params.frame) */
 #define GCB_FRAME_REDUCED 0   /* the paper's schemes: b = B/B, v_E = c E x B/B^2, E_par = E.b */
 #define GCB_FRAME_EXACT   1   /* the exact frame of Sec. 2.2: b*, the exact v_E and kappa,
-                                 E_par = E'/kappa; with curvature = 0, GCB_FORM_F64 and
-                                 gcb_push only */
+                                 E_par = E'/kappa; with curvature = 0, GCB_FORM_F64,
+                                 gcb_push and gcb_push_3d only */
 
 /* where field arrays live (gcb_load_fields.src) */
 #define GCB_HOST   0

@@ -94,10 +94,11 @@ def exact_frame(E, B, p):
                            flags=flags.to(torch.uint8), E=(Ex, Ey, Ez), Bv=(Bx, By, Bz))
 
 
-def local_exact(prov, X, Y, p):
+def local_exact(prov, X, Y, p, Z=None):
     """The local namespace of the guiding-center step (see `pusher.local`)
-    with b = b*, the exact v_E and kappa, and E_par = E'/kappa."""
-    s = prov(X, Y)
+    with b = b*, the exact v_E and kappa, and E_par = E'/kappa; Z for a 3D
+    provider."""
+    s = prov(X, Y) if Z is None else prov(X, Y, Z)
     fr = exact_frame(s.E, s.B, p)
     z = torch.zeros_like(X)
     return SimpleNamespace(E=fr.E, Bv=fr.Bv, B=fr.B, inv_B=fr.inv_B, b=fr.bstar, vE=fr.vE,

@@ -75,7 +75,12 @@ class State3:
 
 def local3(prov, X, Y, Z, p: Params3):
     """b, v_E, kappa, E_par and the curvature terms at points (X, Y, Z); the
-    same namespace as the 2D oracle's `local`."""
+    same namespace as the 2D oracle's `local` (with p.exact_frame, the exact
+    frame of frame.py)."""
+    if p.exact_frame:
+        from .frame import local_exact
+        assert not p.curvature, "the exact frame is used with the zero-curvature scheme"
+        return local_exact(prov, X, Y, p, Z)
     s = prov(X, Y, Z)
     Ex, Ey, Ez = s.E
     Bx, By, Bz = s.B

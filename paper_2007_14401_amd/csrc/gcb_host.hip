@@ -171,10 +171,12 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
     return GCB_OK;
 }
 
-// the exact frame is served by gcb_push with curvature = 0 and binary64 only
+// the exact frame is served by gcb_push and gcb_push_3d (curvature = 0,
+// binary64) only
 int reject_exact_frame(gcb_ctx* ctx, const gcb_params* prm) {
     if (prm->frame != GCB_FRAME_REDUCED)
-        return fail(ctx, GCB_EUNSUPPORTED, "the exact frame is served by gcb_push only");
+        return fail(ctx, GCB_EUNSUPPORTED,
+                    "the exact frame is served by gcb_push and gcb_push_3d only");
     return GCB_OK;
 }
 
@@ -565,6 +567,7 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
         L.replay = prm->replay != 0;
         L.stats = dstats;
         L.steps = ns;
+        L.exact = prm->frame == GCB_FRAME_EXACT;
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))
@@ -876,8 +879,10 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     if (prm->form != GCB_FORM_F64 && prm->form != GCB_FORM_MIXED)
         return fail(ctx, GCB_EINVAL, "unknown form %d", prm->form);
     if (prm->replay) return fail(ctx, GCB_EUNSUPPORTED, "replay is not supported here");
-    if (prm->frame != GCB_FRAME_REDUCED)
-        return fail(ctx, GCB_EUNSUPPORTED, "the exact frame is served by gcb_push only");
+    {
+        const int rc = reject_exact_frame(ctx, prm);
+        if (rc) return rc;
+    }
     if (p->n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");
     if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
     if (p->n > 0 && (!p->r || !p->th || !p->ph || !p->ur || !p->uth || !p->uph || !p->status))
@@ -1018,7 +1023,9 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t 
     if (((uintptr_t)p->z | (uintptr_t)p->zp) & 7)
         return fail(ctx, GCB_EINVAL, "double arrays must be 8-byte aligned");
     if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
-    if ((rc = reject_exact_frame(ctx, prm))) return rc;
+    if (prm->frame == GCB_FRAME_EXACT && (prm->curvature != 0 || prm->form != GCB_FORM_F64))
+        return fail(ctx, GCB_EUNSUPPORTED,
+                    "the exact frame needs curvature = 0 and GCB_FORM_F64");
     if (!ctx->have_f3) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields_3d was not called");
     if (prm->form == GCB_FORM_F64 && ctx->dtype3 != GCB_F64)
         return fail(ctx, GCB_EINVAL, "GCB_FORM_F64 needs fields loaded as GCB_F64");

@@ -71,6 +71,7 @@ struct Push3Launch {
     bool replay;
     DevStats* stats;       // nullable
     int steps = 1;         // global kernel: steps per launch
+    bool exact = false;    // guiding-center branch in the exact frame (binary64 only)
 };
 
 hipError_t launch_push3_f64(const Push3Launch& L, const ParticlePtrs3<double>& in,

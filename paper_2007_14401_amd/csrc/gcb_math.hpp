@@ -336,9 +336,10 @@ GCB_HD uint32_t local_fields_exact(const R E[3], const R Bv[3], const Consts<R>&
     return flags;
 }
 
-// the local quantities of the guiding-center step in the chosen frame
-template <bool kExact, typename R>
-GCB_HD uint32_t local_in_frame(const Sample<R>& s, const Consts<R>& K, Local<R>& L) {
+// the local quantities of the guiding-center step in the chosen frame (any
+// sample type with E and B; the reduced frame's gradients come from it)
+template <bool kExact, typename R, class S>
+GCB_HD uint32_t local_in_frame(const S& s, const Consts<R>& K, Local<R>& L) {
     if constexpr (kExact)
         return local_fields_exact(s.E, s.B, K, L);
     else

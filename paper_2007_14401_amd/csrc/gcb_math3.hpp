@@ -212,11 +212,12 @@ GCB_HD void boris_step3(const Sample3<R>& s, Regs3<R>& r, const PushConst3& pc,
 // One guiding-center step (Sec. 2.2.1 / 2.2.2 inside the coupled step of
 // Sec. 3.1).  sn is the gather (with gradients) at x^n.  Returns status
 // flags; res receives |R^K - R^{K-1}|_inf over the three components.
-template <typename R, bool kYee, class Acc>
+// kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only).
+template <typename R, bool kYee, bool kExact = false, class Acc>
 GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
                           const PushConst3& pc, const Consts3<R>& K, double& res) {
     uint32_t flags = 0;
-    const bool curv = pc.b.curvature != 0;
+    const bool curv = !kExact && pc.b.curvature != 0;
     const double x[3] = {r.x, r.y, r.z};
     const double xprev[3] = {r.xp, r.yp, r.zp};
     const double box[3] = {pc.b.Lx, pc.b.Ly, pc.Lz};
@@ -233,7 +234,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
         Sample3<R> sh;
         gather3<R, true, kYee>(acc, pc, K, Rh[0], Rh[1], Rh[2], sh);
         Local<R> Lh;
-        flags |= local_from_sample(sh, K, Lh);
+        flags |= local_in_frame<kExact, R>(sh, K, Lh);
         upar = (ux * Lh.b[0] + uy * Lh.b[1]) + uz * Lh.b[2];
         const R gf = gamma_full(ux, uy, uz, K);
         R vc[3] = {(R)0, (R)0, (R)0};
@@ -254,7 +255,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
     R upn, Fn[3];
     {
         Local<R> Ln;
-        flags |= local_from_sample(sn, K, Ln);
+        flags |= local_in_frame<kExact, R>(sn, K, Ln);
         upn = parallel_update(Ln, upar, mu, qm, curv, K, flags);
         drift_terms3(Ln, upn, mu, inv_qm, curv, K, Fn);
     }
@@ -272,7 +273,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
             Sample3<R> sk;
             gather3<R, true, kYee>(acc, pc, K, Rp[0], Rp[1], Rp[2], sk);
             Local<R> Lk;
-            flags |= local_from_sample(sk, K, Lk);
+            flags |= local_in_frame<kExact, R>(sk, K, Lk);
             drift_terms3(Lk, upn, mu, inv_qm, curv, K, Fk);
         }
         double d[3];
@@ -295,7 +296,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
         Sample3<R> sm;
         gather3<R, true, kYee>(acc, pc, K, Rm[0], Rm[1], Rm[2], sm);
         Local<R> Lm;
-        flags |= local_from_sample(sm, K, Lm);
+        flags |= local_in_frame<kExact, R>(sm, K, Lm);
         const R gr = gamma_gca(Lm, upn, mu, K);
         R vc[3] = {(R)0, (R)0, (R)0};
         if (curv) v_curv(Lm, upn, gr, inv_qm, K, vc);

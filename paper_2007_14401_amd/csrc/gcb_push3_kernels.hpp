@@ -55,7 +55,7 @@ __device__ __forceinline__ void store_particle3(const ParticlePtrs3<R>& in,
     }
 }
 
-template <typename R, bool kYee, class Acc>
+template <typename R, bool kYee, bool kExact, class Acc>
 __device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Regs3<R>& r,
                                                     const PushConst3& pc, const Consts3<R>& K,
                                                     double& res) {
@@ -64,7 +64,7 @@ __device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Re
     Sample3<R> s;
     if (gca) {
         gather3<R, true, kYee>(acc, pc, K, r.x, r.y, r.z, s);
-        fl = gca_step3<R, kYee>(acc, s, r, pc, K, res);
+        fl = gca_step3<R, kYee, kExact>(acc, s, r, pc, K, res);
     } else {
         gather3<R, false, kYee>(acc, pc, K, r.x, r.y, r.z, s);
         boris_step3(s, r, pc, K);
@@ -72,7 +72,7 @@ __device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Re
     return fl | finite_flag3(r);
 }
 
-template <typename R, typename T, bool kYee>
+template <typename R, typename T, bool kYee, bool kExact>
 __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
                                                        ParticlePtrs3<R> out, int64_t n, int ns,
                                                        const T* __restrict__ F, PushConst3 pc,
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
                 gca = switch_gca(smp.E, smp.B, r.ux, r.uy, r.uz, r.qm, pc.b, K);
             }
             double res;
-            fl |= coupled_update3<R, kYee>(acc, gca, r, pc, K, res);
+            fl |= coupled_update3<R, kYee, kExact>(acc, gca, r, pc, K, res);
             if (tr && !replay) tr[ti] = gca ? 0 : 1;
             if (gca) {
                 ++cnt_g;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
     if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
-template <typename R, typename T, bool kYee, int kMinWaves>
+template <typename R, typename T, bool kYee, int kMinWaves, bool kExact>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const int32_t* __restrict__ tile_start,
               TileGeom3 g, int chunk, const T* __restrict__ F, PushConst3 pc, uint8_t* trace,
@@ -185,7 +185,7 @@ k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const int32_t* __restri
             load_particle3(in, p, pc.b.qm, r);
             acc.miss = false;
             double res;
-            uint32_t fl = coupled_update3<R, kYee>(acc, gca, r, pc, K, res);
+            uint32_t fl = coupled_update3<R, kYee, kExact>(acc, gca, r, pc, K, res);
             if (acc.miss) {
                 fl |= ST_HALO;
                 ++cnt_h;
@@ -204,39 +204,53 @@ k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const int32_t* __restri
     if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
 }
 
-template <typename R, typename T, int kMinWaves>
-hipError_t launch_push3(const Push3Launch& L, const ParticlePtrs3<R>& in,
-                        const ParticlePtrs3<R>& out, const PushConst3& pc, hipStream_t stream) {
-    if (L.n == 0) return hipSuccess;
+template <typename R, typename T, int kMinWaves, bool kExact>
+hipError_t launch_push3_frame(const Push3Launch& L, const ParticlePtrs3<R>& in,
+                              const ParticlePtrs3<R>& out, const PushConst3& pc,
+                              hipStream_t stream) {
     const T* F = static_cast<const T*>(L.fields);
     if (L.kind == PushKind::Global) {
         const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
         const int ns = L.steps > 0 ? L.steps : 1;
         if (L.yee)
-            hipLaunchKernelGGL((k_push3_global<R, T, true>), dim3(blocks), dim3(kWG), 0, stream,
-                               in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
-        else
-            hipLaunchKernelGGL((k_push3_global<R, T, false>), dim3(blocks), dim3(kWG), 0,
+            hipLaunchKernelGGL((k_push3_global<R, T, true, kExact>), dim3(blocks), dim3(kWG), 0,
                                stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
+        else
+            hipLaunchKernelGGL((k_push3_global<R, T, false, kExact>), dim3(blocks), dim3(kWG),
+                               0, stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
         return hipGetLastError();
     }
     const int ntiles = L.geom.ntx * L.geom.nty * L.geom.ntz;
     const int chunk = (ntiles + 7) / 8;
     const size_t lds = tiled3_lds_bytes(L.geom.window, sizeof(T));
     if (L.yee) {
-        auto kfn = k_push3_tiled<R, T, true, kMinWaves>;
+        auto kfn = k_push3_tiled<R, T, true, kMinWaves, kExact>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay, L.stats);
     } else {
-        auto kfn = k_push3_tiled<R, T, false, kMinWaves>;
+        auto kfn = k_push3_tiled<R, T, false, kMinWaves, kExact>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay, L.stats);
     }
     return hipGetLastError();
+}
+
+// the exact frame exists for the binary64 form only (the host rejects the
+// other combination)
+template <typename R, typename T, int kMinWaves>
+hipError_t launch_push3(const Push3Launch& L, const ParticlePtrs3<R>& in,
+                        const ParticlePtrs3<R>& out, const PushConst3& pc, hipStream_t stream) {
+    if (L.n == 0) return hipSuccess;
+    if constexpr (!kMixed<R>) {
+        if (L.exact) return launch_push3_frame<R, T, kMinWaves, true>(L, in, out, pc, stream);
+    } else {
+        if (L.exact) return hipErrorInvalidValue;
+    }
+    return launch_push3_frame<R, T, kMinWaves, false>(L, in, out, pc, stream);
 }
 
 }  // namespace kern

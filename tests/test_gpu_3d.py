@@ -405,3 +405,24 @@ def test_mixed_report_3d_1e7():
         json.dump(rep, f, indent=1)
     assert rep["u_rel_err"]["median"] <= 1e-3
     assert rep["switch_mismatch_fraction_particle_steps"] <= 1e-2
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile,steps", [(GLOBAL, 0, 0, 1), (TILED, 2, 6, 12)])
+def test_exact_frame_3d(kernel, sort_every, tile, steps):
+    """The exact guiding-center frame (Sec. 2.2) with the zero-curvature
+    scheme in 3D, on a sheet with a strong reconnection field (E.B != 0)."""
+    from paper_2007_14401_amd import gcb, state
+    cfg = make_config3("harris3d32", E_rec=0.5, guide=0.3, curvature=0)
+    F = cfg.fields()
+    run = GpuRun3(cfg, F)
+    try:
+        ens = cfg.particles(n=3000, seed_offset=4)
+        log(f"3d exact frame kernel={kernel} steps={steps}")
+        t = _state(ens)
+        tr, st = run.push(t, steps, trace=True, stats=True, kernel=kernel,
+                          sort_every=sort_every, tile=tile, frame=gcb.GCB_FRAME_EXACT)
+        ref, rtr, _ = run_oracle3(cfg, F, ens, steps, trace=True, exact_frame=True)
+        _check(state.unsort(t), ref, cfg, "3d exact frame", tr, rtr)
+        assert st["gca_steps"] > 0
+    finally:
+        run.close()

@@ -303,10 +303,12 @@ def test_rotated_circular_problem_matches_2d_oracle():
         assert torch.allclose(a, b, rtol=1e-12, atol=1e-13)
 
 
-def test_z_independent_grid_reduces_to_2d_oracle():
+@pytest.mark.parametrize("exact", [False, True])
+def test_z_independent_grid_reduces_to_2d_oracle(exact):
     """2D Harris fields copied onto every z plane of a 3D Yee grid (whose (x, y)
     offsets are the 2D Yee offsets): the 3D step reproduces the pinned 2D
-    oracle's x, y and u, with the same switch decisions."""
+    oracle's x, y and u, with the same switch decisions (also in the exact
+    frame with the zero-curvature scheme)."""
     from workloads import make_config
     cfg = make_config("harris64")
     F2 = cfg.fields()
@@ -317,8 +319,9 @@ def test_z_independent_grid_reduces_to_2d_oracle():
     z = rng.uniform(0.0, nz, ens.n)
     gam = np.sqrt(1 + (ens.ux ** 2 + ens.uy ** 2 + ens.uz ** 2) / cfg.c ** 2)
     zp = np.mod(z - ens.uz / gam, nz)
-    p2 = O.Params(c=cfg.c, Lx=cfg.Lx, Ly=cfg.Ly, dl=1.0)
-    p3 = params3(c=cfg.c, Lx=cfg.Lx, Ly=cfg.Ly, Lz=float(nz))
+    fkw = dict(exact_frame=True, curvature=False) if exact else {}
+    p2 = O.Params(c=cfg.c, Lx=cfg.Lx, Ly=cfg.Ly, dl=1.0, **fkw)
+    p3 = params3(c=cfg.c, Lx=cfg.Lx, Ly=cfg.Ly, Lz=float(nz), **fkw)
     st2 = O.State.from_numpy(ens)
     st3 = O.State3(st2.x, st2.y, torch.as_tensor(z), st2.xp, st2.yp, torch.as_tensor(zp),
                    st2.ux, st2.uy, st2.uz, st2.qm, st2.status.clone())
