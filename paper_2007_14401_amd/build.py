@@ -58,7 +58,10 @@ def build(verbose: bool = True) -> str:
         futs = {ex.submit(_compile, s, f): s for s, f in UNITS.items()}
         objs = [f.result() for f in futs]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]
+    # every symbol must resolve at link time (a missing definition would
+    # otherwise surface only when the library is loaded)
+    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-Wl,--no-undefined", *objs,
+           "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -248,6 +248,29 @@ int scratch_state(gcb_ctx* ctx, const ParticlePtrs<U>& like, int64_t n, Particle
     return GCB_OK;
 }
 
+// copy every array of a state (same shape) from a to b
+template <typename U>
+hipError_t copy_state(const ParticlePtrs<U>& a, const ParticlePtrs<U>& b, int64_t n,
+                      hipStream_t stream) {
+    const size_t nd = (size_t)n * sizeof(double), nu = (size_t)n * sizeof(U);
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && src) e = hipMemcpyAsync(dst, src, bytes, k, stream);
+    };
+    cp(b.x, a.x, nd);
+    cp(b.y, a.y, nd);
+    cp(b.xp, a.xp, nd);
+    cp(b.yp, a.yp, nd);
+    cp(b.ux, a.ux, nu);
+    cp(b.uy, a.uy, nu);
+    cp(b.uz, a.uz, nu);
+    cp(b.status, a.status, (size_t)n);
+    cp(b.qm, a.qm, nd);
+    cp(b.id, a.id, (size_t)n * sizeof(int32_t));
+    return e;
+}
+
 // the physics constants of a launch (geometry left to the caller)
 PushConst physics_const(const gcb_params* prm) {
     PushConst pc{};
@@ -454,9 +477,14 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         if ((rc = prepare_sort(ctx, n, g.ntx * g.nty, sb))) return rc;
         if ((rc = scratch_state<U>(ctx, user, n, scr))) return rc;
     }
-    // the global kernel keeps a particle in registers for up to
-    // kGlobalStepsPerLaunch steps (not past the next sort)
+    // On a sort step the push reads the state through the sort's permutation
+    // and writes it in tile order into the other of two buffers (the caller's
+    // arrays and a library copy); the other steps work in place.  A state
+    // that ends in the library copy is copied back.  The global kernel keeps a
+    // particle in registers for up to kGlobalStepsPerLaunch steps (not past
+    // the next sort).
     constexpr int32_t kGlobalStepsPerLaunch = 16;
+    ParticlePtrs<U> cur = user, other = scr;
     for (int32_t step = 0; step < n_steps;) {
         int32_t ns = 1;
         if (kind == PushKind::Global) {
@@ -464,15 +492,17 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
             if (prm->sort_every > 0)
                 ns = std::min(ns, prm->sort_every - step % prm->sort_every);
         }
-        ParticlePtrs<U> src = user;
+        ParticlePtrs<U> dst = cur;
+        const uint32_t* perm = nullptr;
         if (prm->sort_every > 0 && n > 0 && step % prm->sort_every == 0) {
             Timer t(ctx, stream, GCB_TIMER_SORT);
-            GCB_HIP(launch_cell_sort(user.x, user.y, n, pc.inv_dx, pc.inv_dy, g, sb, stream));
-            GCB_HIP(launch_permute<U>(user, scr, sb.idx, n, stream));
+            GCB_HIP(launch_cell_sort(cur.x, cur.y, n, pc.inv_dx, pc.inv_dy, g, sb, stream));
             t.done();
-            src = scr;
+            perm = sb.idx;
+            dst = other;
         }
         PushLaunch L;
+        L.perm = perm;
         L.kind = kind;
         L.yee = ctx->yee;
         L.fields = ctx->fields.ptr;
@@ -487,13 +517,19 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))
-            e = launch_push_f64(L, src, user, pc, stream);
+            e = launch_push_f64(L, cur, dst, pc, stream);
         else
-            e = launch_push_mixed(L, src, user, pc, stream);
+            e = launch_push_mixed(L, cur, dst, pc, stream);
         if (e != hipSuccess)
             return fail(ctx, GCB_EHIP, "push kernel launch failed: %s", hipGetErrorString(e));
         t.done();
+        if (perm) std::swap(cur, other);
         step += ns;
+    }
+    if (cur.x != user.x) {
+        Timer t(ctx, stream, GCB_TIMER_OTHER);
+        GCB_HIP(copy_state<U>(cur, user, n, stream));
+        t.done();
     }
     return GCB_OK;
 }
@@ -537,9 +573,9 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
         scr.z = zz[0];
         scr.zp = zz[1];
     }
-    // the global kernel keeps a particle in registers for up to
-    // kGlobalStepsPerLaunch steps (not past the next sort)
+    // sort steps move the state into the other buffer, as in 2D
     constexpr int32_t kGlobalStepsPerLaunch = 16;
+    ParticlePtrs3<U> cur = user, other = scr;
     for (int32_t step = 0; step < n_steps;) {
         int32_t ns = 1;
         if (kind == PushKind::Global) {
@@ -547,16 +583,18 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
             if (prm->sort_every > 0)
                 ns = std::min(ns, prm->sort_every - step % prm->sort_every);
         }
-        ParticlePtrs3<U> src = user;
+        ParticlePtrs3<U> dst = cur;
+        const uint32_t* perm = nullptr;
         if (prm->sort_every > 0 && n > 0 && step % prm->sort_every == 0) {
             Timer t(ctx, stream, GCB_TIMER_SORT);
-            GCB_HIP(launch_cell_sort3(user.b.x, user.b.y, user.z, n, pc.b.inv_dx, pc.b.inv_dy,
+            GCB_HIP(launch_cell_sort3(cur.b.x, cur.b.y, cur.z, n, pc.b.inv_dx, pc.b.inv_dy,
                                       pc.inv_dz, g, sb, stream));
-            GCB_HIP(launch_permute3<U>(user, scr, sb.idx, n, stream));
             t.done();
-            src = scr;
+            perm = sb.idx;
+            dst = other;
         }
         Push3Launch L;
+        L.perm = perm;
         L.kind = kind;
         L.yee = ctx->yee3;
         L.fields = ctx->fields3.ptr;
@@ -571,13 +609,26 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))
-            e = launch_push3_f64(L, src, user, pc, stream);
+            e = launch_push3_f64(L, cur, dst, pc, stream);
         else
-            e = launch_push3_mixed(L, src, user, pc, stream);
+            e = launch_push3_mixed(L, cur, dst, pc, stream);
         if (e != hipSuccess)
             return fail(ctx, GCB_EHIP, "push kernel launch failed: %s", hipGetErrorString(e));
         t.done();
+        if (perm) std::swap(cur, other);
         step += ns;
+    }
+    if (cur.b.x != user.b.x) {
+        Timer t(ctx, stream, GCB_TIMER_OTHER);
+        hipError_t e = copy_state<U>(cur.b, user.b, n, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(user.z, cur.z, (size_t)n * sizeof(double),
+                               hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(user.zp, cur.zp, (size_t)n * sizeof(double),
+                               hipMemcpyDeviceToDevice, stream);
+        if (e != hipSuccess) return fail(ctx, GCB_EHIP, "state copy: %s", hipGetErrorString(e));
+        t.done();
     }
     return GCB_OK;
 }

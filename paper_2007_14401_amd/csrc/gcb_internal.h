@@ -27,6 +27,7 @@ struct PushLaunch {
     bool yee;              // compile-time Yee offsets
     const void* fields;    // node-interleaved device fields (double or float)
     int64_t n;
+    const uint32_t* perm = nullptr;   // read slot perm[p] of the input (sort steps)
     const int32_t* tile_start;   // tiled: ntiles + 1 offsets
     TileGeom geom;
     uint8_t* trace;        // nullable: trace row of this step
@@ -65,6 +66,7 @@ struct Push3Launch {
     bool yee;              // compile-time 3D Yee offsets
     const void* fields;    // node-interleaved device fields (double or float)
     int64_t n;
+    const uint32_t* perm = nullptr;   // read slot perm[p] of the input (sort steps)
     const int32_t* tile_start;   // tiled: ntiles + 1 offsets
     TileGeom3 geom;
     uint8_t* trace;        // nullable: trace row of the launch's first step
@@ -106,19 +108,11 @@ hipError_t launch_cell_sort(const double* x, const double* y, int64_t n, double 
                             double inv_dy, const TileGeom& g, const SortBuffers& b,
                             hipStream_t stream);
 
-// Gather every array of the state through the permutation.
-template <typename U>
-hipError_t launch_permute(const ParticlePtrs<U>& src, const ParticlePtrs<U>& dst,
-                          const uint32_t* perm, int64_t n, hipStream_t stream);
-
 // The same for the 3D state: keys are the cubic tiles of (x, y, z), row-major
 // (x fastest).
 hipError_t launch_cell_sort3(const double* x, const double* y, const double* z, int64_t n,
                              double inv_dx, double inv_dy, double inv_dz, const TileGeom3& g,
                              const SortBuffers& b, hipStream_t stream);
-template <typename U>
-hipError_t launch_permute3(const ParticlePtrs3<U>& src, const ParticlePtrs3<U>& dst,
-                           const uint32_t* perm, int64_t n, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // fields

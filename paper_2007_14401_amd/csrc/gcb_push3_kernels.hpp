@@ -1,6 +1,9 @@
 // 3D push kernels, templated like the 2D ones on the bulk type R and the
 // field storage type T.
 //
+// As in 2D, both read slot perm[p] of `in` (p when perm is null) and write
+// slot p of `out`.
+//
 // k_push3_global: one lane per particle, up to `ns` steps per launch with the
 //   particle in registers, gathers through the caches.
 // k_push3_tiled: one workgroup per cubic tile of cell-sorted particles; the
@@ -38,7 +41,8 @@ __device__ __forceinline__ void load_particle3(const ParticlePtrs3<R>& in, int64
 template <typename R>
 __device__ __forceinline__ void store_particle3(const ParticlePtrs3<R>& in,
                                                 const ParticlePtrs3<R>& out, int64_t p,
-                                                const Regs3<R>& r, uint32_t flags) {
+                                                int64_t src, const Regs3<R>& r,
+                                                uint32_t flags) {
     out.b.x[p] = r.x;
     out.b.y[p] = r.y;
     out.z[p] = r.z;
@@ -48,10 +52,10 @@ __device__ __forceinline__ void store_particle3(const ParticlePtrs3<R>& in,
     out.b.ux[p] = r.ux;
     out.b.uy[p] = r.uy;
     out.b.uz[p] = r.uz;
-    out.b.status[p] = (uint8_t)(in.b.status[p] | flags);
+    out.b.status[p] = (uint8_t)(in.b.status[src] | flags);
     if (out.b.x != in.b.x) {   // out-of-place step after a sort: carry the rest along
         if (in.b.qm) out.b.qm[p] = r.qm;
-        if (in.b.id) out.b.id[p] = in.b.id[p];
+        if (in.b.id) out.b.id[p] = in.b.id[src];
     }
 }
 
@@ -74,7 +78,9 @@ __device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Re
 
 template <typename R, typename T, bool kYee, bool kExact>
 __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
-                                                       ParticlePtrs3<R> out, int64_t n, int ns,
+                                                       ParticlePtrs3<R> out,
+                                                       const uint32_t* __restrict__ perm,
+                                                       int64_t n, int ns,
                                                        const T* __restrict__ F, PushConst3 pc,
                                                        uint8_t* trace, bool replay,
                                                        DevStats* stats) {
@@ -84,9 +90,10 @@ __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
     if (p < n) {
         const Consts3<R> K = make_consts3<R>(pc);
         GlobalAcc3<T> acc{F, pc.b.nx, pc.b.ny, pc.nz};
+        const int64_t src = perm ? (int64_t)perm[p] : p;
         Regs3<R> r;
-        load_particle3(in, p, pc.b.qm, r);
-        const int64_t ti = in.b.id ? (int64_t)in.b.id[p] : p;
+        load_particle3(in, src, pc.b.qm, r);
+        const int64_t ti = in.b.id ? (int64_t)in.b.id[src] : p;
         uint32_t fl = 0;
         for (int s = 0; s < ns; ++s) {
             uint8_t* tr = trace ? trace + (size_t)s * n : nullptr;
@@ -108,16 +115,17 @@ __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
                 ++cnt_b;
             }
         }
-        store_particle3(in, out, p, r, fl);
+        store_particle3(in, out, p, src, r, fl);
     }
     if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
 template <typename R, typename T, bool kYee, int kMinWaves, bool kExact>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
-k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const int32_t* __restrict__ tile_start,
-              TileGeom3 g, int chunk, const T* __restrict__ F, PushConst3 pc, uint8_t* trace,
-              bool replay, DevStats* stats) {
+k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const uint32_t* __restrict__ perm,
+              const int32_t* __restrict__ tile_start, TileGeom3 g, int chunk,
+              const T* __restrict__ F, PushConst3 pc, uint8_t* trace, bool replay,
+              DevStats* stats) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int wave_g[kWG / 64];
     __shared__ int wave_b[kWG / 64];
@@ -171,18 +179,20 @@ k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const int32_t* __restri
         // pass 1: switch decision, stable split into the two queues
         const int nG = split_queues(m, queue, wave_g, wave_b, [&](int t) {
             const int64_t p = base + t;
-            if (replay) return trace[in.b.id ? (int64_t)in.b.id[p] : p] == 0;
-            const double qm = in.b.qm ? in.b.qm[p] : pc.b.qm;
+            const int64_t src = perm ? (int64_t)perm[p] : p;
+            if (replay) return trace[in.b.id ? (int64_t)in.b.id[src] : p] == 0;
+            const double qm = in.b.qm ? in.b.qm[src] : pc.b.qm;
             Sample3<R> s;
-            gather3<R, false, kYee>(acc, pc, K, in.b.x[p], in.b.y[p], in.z[p], s);
-            return switch_gca(s.E, s.B, in.b.ux[p], in.b.uy[p], in.b.uz[p], qm, pc.b, K);
+            gather3<R, false, kYee>(acc, pc, K, in.b.x[src], in.b.y[src], in.z[src], s);
+            return switch_gca(s.E, s.B, in.b.ux[src], in.b.uy[src], in.b.uz[src], qm, pc.b, K);
         });
         // pass 2: guiding-center queue, then Boris queue
         for (int q = threadIdx.x; q < m; q += kWG) {
             const int64_t p = base + queue[q];
+            const int64_t src = perm ? (int64_t)perm[p] : p;
             const bool gca = q < nG;
             Regs3<R> r;
-            load_particle3(in, p, pc.b.qm, r);
+            load_particle3(in, src, pc.b.qm, r);
             acc.miss = false;
             double res;
             uint32_t fl = coupled_update3<R, kYee, kExact>(acc, gca, r, pc, K, res);
@@ -190,8 +200,8 @@ k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const int32_t* __restri
                 fl |= ST_HALO;
                 ++cnt_h;
             }
-            store_particle3(in, out, p, r, fl);
-            if (trace && !replay) trace[in.b.id ? (int64_t)in.b.id[p] : p] = gca ? 0 : 1;
+            store_particle3(in, out, p, src, r, fl);
+            if (trace && !replay) trace[in.b.id ? (int64_t)in.b.id[src] : p] = gca ? 0 : 1;
             if (gca) {
                 ++cnt_g;
                 maxres = nan_max(maxres, res);
@@ -214,10 +224,12 @@ hipError_t launch_push3_frame(const Push3Launch& L, const ParticlePtrs3<R>& in,
         const int ns = L.steps > 0 ? L.steps : 1;
         if (L.yee)
             hipLaunchKernelGGL((k_push3_global<R, T, true, kExact>), dim3(blocks), dim3(kWG), 0,
-                               stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
+                               stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
+                               L.stats);
         else
             hipLaunchKernelGGL((k_push3_global<R, T, false, kExact>), dim3(blocks), dim3(kWG),
-                               0, stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
+                               0, stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
+                               L.stats);
         return hipGetLastError();
     }
     const int ntiles = L.geom.ntx * L.geom.nty * L.geom.ntz;
@@ -227,13 +239,13 @@ hipError_t launch_push3_frame(const Push3Launch& L, const ParticlePtrs3<R>& in,
         auto kfn = k_push3_tiled<R, T, true, kMinWaves, kExact>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
+        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay, L.stats);
     } else {
         auto kfn = k_push3_tiled<R, T, false, kMinWaves, kExact>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
+        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay, L.stats);
     }
     return hipGetLastError();

@@ -1,6 +1,11 @@
 // Push kernels, templated on the bulk arithmetic type R (double: binary64
 // form; float: mixed form) and the field storage type T.
 //
+// Both kernels read particle slot perm[p] of `in` (slot p when perm is null)
+// and write slot p of `out`: on the step of a cell sort, perm is the sort's
+// permutation and the push moves the state into tile order on the way (no
+// separate permutation pass; `in` and `out` are then different buffers).
+//
 // k_push_global: one lane per particle, any particle order, gathers through
 //   the cache hierarchy from the node-interleaved field array.
 // k_push_tiled: one workgroup per tile of cell-sorted particles.  The tile's
@@ -67,7 +72,8 @@ __device__ __forceinline__ void load_particle(const ParticlePtrs<R>& in, int64_t
 template <typename R>
 __device__ __forceinline__ void store_particle(const ParticlePtrs<R>& in,
                                                const ParticlePtrs<R>& out, int64_t p,
-                                               const Regs<R>& r, uint32_t flags) {
+                                               int64_t src, const Regs<R>& r,
+                                               uint32_t flags) {
     out.x[p] = r.x;
     out.y[p] = r.y;
     out.xp[p] = r.xp;
@@ -75,10 +81,10 @@ __device__ __forceinline__ void store_particle(const ParticlePtrs<R>& in,
     out.ux[p] = r.ux;
     out.uy[p] = r.uy;
     out.uz[p] = r.uz;
-    out.status[p] = (uint8_t)(in.status[p] | flags);
+    out.status[p] = (uint8_t)(in.status[src] | flags);
     if (out.x != in.x) {   // out-of-place step after a sort: carry the rest along
         if (in.qm) out.qm[p] = r.qm;
-        if (in.id) out.id[p] = in.id[p];
+        if (in.id) out.id[p] = in.id[src];
     }
 }
 
@@ -151,6 +157,7 @@ __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Reg
 // them); trace (per step n bytes) is indexed by id when ids are present
 template <typename R, typename T, bool kYee, bool kExact>
 __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, ParticlePtrs<R> out,
+                                                      const uint32_t* __restrict__ perm,
                                                       int64_t n, int ns, const T* __restrict__ F,
                                                       PushConst pc, uint8_t* trace,
                                                       bool replay, DevStats* stats) {
@@ -161,9 +168,10 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
     if (active) {
         const Consts<R> K = make_consts<R>(pc);
         GlobalAcc<T> acc{F, pc.nx, pc.ny};
+        const int64_t src = perm ? (int64_t)perm[p] : p;
         Regs<R> r;
-        load_particle(in, p, pc.qm, r);
-        const int64_t ti = in.id ? (int64_t)in.id[p] : p;
+        load_particle(in, src, pc.qm, r);
+        const int64_t ti = in.id ? (int64_t)in.id[src] : p;
         uint32_t fl = 0;
         for (int s = 0; s < ns; ++s) {
             uint8_t* tr = trace ? trace + (size_t)s * n : nullptr;
@@ -185,16 +193,17 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
                 ++cnt_b;
             }
         }
-        store_particle(in, out, p, r, fl);
+        store_particle(in, out, p, src, r, fl);
     }
     if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
 template <typename R, typename T, bool kYee, int kMinWaves, bool kExact>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
-k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict__ tile_start,
-             TileGeom g, int chunk, const T* __restrict__ F, PushConst pc, uint8_t* trace,
-             bool replay, DevStats* stats) {
+k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict__ perm,
+             const int32_t* __restrict__ tile_start, TileGeom g, int chunk,
+             const T* __restrict__ F, PushConst pc, uint8_t* trace, bool replay,
+             DevStats* stats) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int wave_g[kWG / 64];
     __shared__ int wave_b[kWG / 64];
@@ -242,19 +251,21 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict_
         // pass 1: switch decision, stable split into the two queues
         const int nG = split_queues(m, queue, wave_g, wave_b, [&](int t) {
             const int64_t p = base + t;
-            if (replay) return trace[in.id ? (int64_t)in.id[p] : p] == 0;
-            const double x = in.x[p], y = in.y[p];
-            const double qm = in.qm ? in.qm[p] : pc.qm;
+            const int64_t src = perm ? (int64_t)perm[p] : p;
+            if (replay) return trace[in.id ? (int64_t)in.id[src] : p] == 0;
+            const double x = in.x[src], y = in.y[src];
+            const double qm = in.qm ? in.qm[src] : pc.qm;
             Sample<R> s;
             gather<R, false, kYee>(acc, pc, K, x, y, s);
-            return switch_gca(s.E, s.B, in.ux[p], in.uy[p], in.uz[p], qm, pc, K);
+            return switch_gca(s.E, s.B, in.ux[src], in.uy[src], in.uz[src], qm, pc, K);
         });
         // pass 2: guiding-center queue, then Boris queue
         for (int q = threadIdx.x; q < m; q += kWG) {
             const int64_t p = base + queue[q];
+            const int64_t src = perm ? (int64_t)perm[p] : p;
             const bool gca = q < nG;
             Regs<R> r;
-            load_particle(in, p, pc.qm, r);
+            load_particle(in, src, pc.qm, r);
             acc.miss = false;
             double res;
             uint32_t fl = coupled_update<R, kYee, kExact>(acc, gca, r, pc, K, res);
@@ -262,8 +273,8 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const int32_t* __restrict_
                 fl |= ST_HALO;
                 ++cnt_h;
             }
-            store_particle(in, out, p, r, fl);
-            if (trace && !replay) trace[in.id ? (int64_t)in.id[p] : p] = gca ? 0 : 1;
+            store_particle(in, out, p, src, r, fl);
+            if (trace && !replay) trace[in.id ? (int64_t)in.id[src] : p] = gca ? 0 : 1;
             if (gca) {
                 ++cnt_g;
                 maxres = nan_max(maxres, res);
@@ -286,10 +297,12 @@ hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
         const int ns = L.steps > 0 ? L.steps : 1;
         if (L.yee)
             hipLaunchKernelGGL((k_push_global<R, T, true, kExact>), dim3(blocks), dim3(kWG), 0,
-                               stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
+                               stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
+                               L.stats);
         else
             hipLaunchKernelGGL((k_push_global<R, T, false, kExact>), dim3(blocks), dim3(kWG), 0,
-                               stream, in, out, L.n, ns, F, pc, L.trace, L.replay, L.stats);
+                               stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
+                               L.stats);
         return hipGetLastError();
     }
     const int ntiles = L.geom.ntx * L.geom.nty;
@@ -299,14 +312,14 @@ hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
         auto kfn = k_push_tiled<R, T, true, kMinWaves, kExact>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
+        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay,
                            L.stats);
     } else {
         auto kfn = k_push_tiled<R, T, false, kMinWaves, kExact>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out,
+        hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay,
                            L.stats);
     }

@@ -9,10 +9,12 @@
 //     scan             exclusive scan of the histogram (3 kernels)
 //     k_radix_scatter  wave-level multisplit ranks -> stable scatter
 //   k_tile_bounds tile_start from the boundaries of the sorted keys
-//   k_permute     gather every state array through idx
+// The push kernel of the sort's step then reads the state through idx (the
+// permutation) and writes it in tile order, so there is no permutation pass.
 //   k_gr_tile_keys, k_gr_permute: the same for the curved-spacetime state
-//                 ((r, theta) tiles of the grid cells)
-//   k_tile_keys3, k_permute3: the same for the 3D state (cubic tiles)
+//                 ((r, theta) tiles of the grid cells), which is permuted in
+//                 a pass of its own
+//   k_tile_keys3: the keys of the 3D state (cubic tiles)
 #include <hip/hip_runtime.h>
 
 #include "gcb_internal.h"
@@ -270,43 +272,6 @@ __global__ __launch_bounds__(kSortWG) void k_radix_scatter(
     }
 }
 
-template <typename U>
-__device__ __forceinline__ void permute_one(const ParticlePtrs<U>& src,
-                                            const ParticlePtrs<U>& dst, int64_t i, int64_t s) {
-    dst.x[i] = src.x[s];
-    dst.y[i] = src.y[s];
-    dst.xp[i] = src.xp[s];
-    dst.yp[i] = src.yp[s];
-    dst.ux[i] = src.ux[s];
-    dst.uy[i] = src.uy[s];
-    dst.uz[i] = src.uz[s];
-    dst.status[i] = src.status[s];
-    if (src.qm) dst.qm[i] = src.qm[s];
-    if (src.id) dst.id[i] = src.id[s];
-}
-
-template <typename U>
-__global__ __launch_bounds__(kSortWG) void k_permute(ParticlePtrs<U> src, ParticlePtrs<U> dst,
-                                                     const uint32_t* __restrict__ perm,
-                                                     int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
-    if (i >= n) return;
-    permute_one(src, dst, i, (int64_t)perm[i]);
-}
-
-template <typename U>
-__global__ __launch_bounds__(kSortWG) void k_permute3(ParticlePtrs3<U> src,
-                                                      ParticlePtrs3<U> dst,
-                                                      const uint32_t* __restrict__ perm,
-                                                      int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
-    if (i >= n) return;
-    const int64_t s = perm[i];
-    permute_one(src.b, dst.b, i, s);
-    dst.z[i] = src.z[s];
-    dst.zp[i] = src.zp[s];
-}
-
 hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* sums,
                           hipStream_t stream) {
     const int nb = (int)((n + kScanItems - 1) / kScanItems);
@@ -409,16 +374,6 @@ hipError_t launch_gr_permute(const GrPtrs& src, const GrPtrs& dst, size_t u_byte
     return hipGetLastError();
 }
 
-template <typename U>
-hipError_t launch_permute(const ParticlePtrs<U>& src, const ParticlePtrs<U>& dst,
-                          const uint32_t* perm, int64_t n, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((n + kSortWG - 1) / kSortWG);
-    hipLaunchKernelGGL(k_permute<U>, dim3(blocks), dim3(kSortWG), 0, stream, src, dst, perm,
-                       n);
-    return hipGetLastError();
-}
-
 hipError_t launch_cell_sort3(const double* x, const double* y, const double* z, int64_t n,
                              double inv_dx, double inv_dy, double inv_dz, const TileGeom3& g,
                              const SortBuffers& b, hipStream_t stream) {
@@ -438,29 +393,5 @@ hipError_t launch_cell_sort3(const double* x, const double* y, const double* z, 
                        b.tile_start);
     return hipGetLastError();
 }
-
-template <typename U>
-hipError_t launch_permute3(const ParticlePtrs3<U>& src, const ParticlePtrs3<U>& dst,
-                           const uint32_t* perm, int64_t n, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((n + kSortWG - 1) / kSortWG);
-    hipLaunchKernelGGL(k_permute3<U>, dim3(blocks), dim3(kSortWG), 0, stream, src, dst, perm,
-                       n);
-    return hipGetLastError();
-}
-
-template hipError_t launch_permute3<double>(const ParticlePtrs3<double>&,
-                                            const ParticlePtrs3<double>&, const uint32_t*,
-                                            int64_t, hipStream_t);
-template hipError_t launch_permute3<float>(const ParticlePtrs3<float>&,
-                                           const ParticlePtrs3<float>&, const uint32_t*,
-                                           int64_t, hipStream_t);
-
-template hipError_t launch_permute<double>(const ParticlePtrs<double>&,
-                                           const ParticlePtrs<double>&, const uint32_t*,
-                                           int64_t, hipStream_t);
-template hipError_t launch_permute<float>(const ParticlePtrs<float>&,
-                                          const ParticlePtrs<float>&, const uint32_t*,
-                                          int64_t, hipStream_t);
 
 }  // namespace gcb
