@@ -314,3 +314,42 @@ def test_replayed_switch_decisions_reproduce_the_run(h64, kernel, sort_every):
     assert torch.equal(tr, tr_copy)            # replay reads, does not write
     for k in ("x", "y", "xp", "yp", "ux", "uy", "uz", "status", "id"):
         assert torch.equal(t1[k], t2[k]), k
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_split_calls_equal_one_call(h64, kernel):
+    """13 steps as 7 + 6 steps in two calls equal 13 steps in one call, bit for
+    bit: with a sort every 3 steps the first call ends after an odd number of
+    sorts (its state comes back from the library's buffer) and the second
+    call sorts on a different schedule; every particle is independent of the
+    others, so the results do not depend on the order."""
+    from paper_2007_14401_amd import state
+    cfg, F, run = h64
+    ens = cfg.particles(n=3001, seed_offset=12)
+    a = _state(ens)
+    run.push(a, 13, kernel=kernel, sort_every=3, tile=16)
+    b = _state(ens)
+    run.push(b, 7, kernel=kernel, sort_every=3, tile=16)
+    run.push(b, 6, kernel=kernel, sort_every=3, tile=16)
+    ha, hb = state.unsort(a), state.unsort(b)
+    for k in ("x", "y", "xp", "yp", "ux", "uy", "uz", "status", "qm"):
+        assert np.array_equal(ha[k], hb[k]), k
+
+
+def test_non_default_stream(h64):
+    """Work enqueued on a caller's stream gives the null stream's result."""
+    from paper_2007_14401_amd import gcb, state
+    cfg, F, run = h64
+    ens = cfg.particles(n=2048, seed_offset=13)
+    a = _state(ens)
+    run.push(a, 8, kernel=2, sort_every=2, tile=16)
+    b = _state(ens)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                     curvature=cfg.curvature, n_iter=cfg.n_iter, kernel=2, sort_every=2,
+                     tile=16)
+    gcb.gcb_push(run.ctx, gcb.particles(b), prm, 8, stream=s)
+    s.synchronize()
+    for k in ("x", "y", "ux", "uy", "uz", "status", "id"):
+        assert torch.equal(a[k], b[k]), k
