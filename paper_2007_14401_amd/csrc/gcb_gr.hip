@@ -26,11 +26,11 @@ hipError_t launch_gr_cell_lengths(const gr::GrConst& g, double dr, double dth, d
     return hipGetLastError();
 }
 
-hipError_t launch_gr_push_f64(const GrPtrs& in, const GrPtrs& out, int64_t n, int n_steps,
-                              const double* F, const double* dl, const gr::GrConst& g,
-                              uint8_t* trace, int trace_step0, DevStats* stats,
-                              hipStream_t stream) {
-    return grk::launch<double, double>(in, out, n, n_steps, F, dl, g, trace, trace_step0, stats,
+hipError_t launch_gr_push_f64(const GrPtrs& in, const GrPtrs& out, const uint32_t* perm,
+                              int64_t n, int n_steps, const double* F, const double* dl,
+                              const gr::GrConst& g, uint8_t* trace, int trace_step0,
+                              DevStats* stats, hipStream_t stream) {
+    return grk::launch<double, double>(in, out, perm, n, n_steps, F, dl, g, trace, trace_step0, stats,
                                        stream);
 }
 

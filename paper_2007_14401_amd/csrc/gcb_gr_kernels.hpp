@@ -25,24 +25,26 @@ __device__ __forceinline__ double wave_max_nan(double v) {
     return v;
 }
 
-// ns steps of particle slot k: read from `in`, written to `out` (the same
-// arrays, or a sorted copy and the caller's arrays, which then also receive
-// q/m and the id)
+// ns steps of the particle in slot perm[k] of `in` (slot k when perm is
+// null), written to slot k of `out`: the same arrays, or, on the launch after
+// a sort, the other buffer, which then also receives q/m and the id
 template <typename R, typename T>
 __global__ __launch_bounds__(kGrWG) __attribute__((amdgpu_waves_per_eu(2))) void
-k_gr_push(GrPtrs in, GrPtrs out, int64_t n, int s0, int ns, const T* __restrict__ F,
-          const double* __restrict__ dl, gr::GrConst g, uint8_t* trace, DevStats* stats) {
+k_gr_push(GrPtrs in, GrPtrs out, const uint32_t* __restrict__ perm, int64_t n, int s0, int ns,
+          const T* __restrict__ F, const double* __restrict__ dl, gr::GrConst g,
+          uint8_t* trace, DevStats* stats) {
     const int64_t k = (int64_t)blockIdx.x * kGrWG + threadIdx.x;
     const bool active = k < n;
     unsigned cnt_g = 0, cnt_b = 0;
     double maxres = 0.0;
     if (active) {
-        double x[3] = {in.r[k], in.th[k], in.ph[k]};
-        R u[3] = {static_cast<const R*>(in.ur)[k], static_cast<const R*>(in.uth)[k],
-                  static_cast<const R*>(in.uph)[k]};
-        const double qm = in.qm ? in.qm[k] : g.qm;
-        const int32_t pid = in.id ? in.id[k] : (int32_t)k;
-        uint8_t st = in.status[k];
+        const int64_t src = perm ? (int64_t)perm[k] : k;
+        double x[3] = {in.r[src], in.th[src], in.ph[src]};
+        R u[3] = {static_cast<const R*>(in.ur)[src], static_cast<const R*>(in.uth)[src],
+                  static_cast<const R*>(in.uph)[src]};
+        const double qm = in.qm ? in.qm[src] : g.qm;
+        const int32_t pid = in.id ? in.id[src] : (int32_t)k;
+        uint8_t st = in.status[src];
         for (int s = 0; s < ns; ++s) {
             double res;
             const int S = gr::coupled_step(F, dl, g, x, u, qm, st, res);
@@ -82,16 +84,16 @@ k_gr_push(GrPtrs in, GrPtrs out, int64_t n, int s0, int ns, const T* __restrict_
 
 
 template <typename R, typename T>
-hipError_t launch(const GrPtrs& in, const GrPtrs& out, int64_t n, int n_steps, const T* F,
-                  const double* dl, const gr::GrConst& g, uint8_t* trace, int trace_step0,
-                  DevStats* stats, hipStream_t stream) {
+hipError_t launch(const GrPtrs& in, const GrPtrs& out, const uint32_t* perm, int64_t n,
+                  int n_steps, const T* F, const double* dl, const gr::GrConst& g,
+                  uint8_t* trace, int trace_step0, DevStats* stats, hipStream_t stream) {
     if (n == 0 || n_steps == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n + kGrWG - 1) / kGrWG);
     for (int s0 = 0; s0 < n_steps; s0 += kGrStepsPerLaunch) {
         const int ns = n_steps - s0 < kGrStepsPerLaunch ? n_steps - s0 : kGrStepsPerLaunch;
         hipLaunchKernelGGL((k_gr_push<R, T>), dim3(blocks), dim3(kGrWG), 0, stream,
-                           s0 == 0 ? in : out, out, n, trace_step0 + s0, ns, F, dl, g, trace,
-                           stats);
+                           s0 == 0 ? in : out, out, s0 == 0 ? perm : nullptr, n,
+                           trace_step0 + s0, ns, F, dl, g, trace, stats);
     }
     return hipGetLastError();
 }

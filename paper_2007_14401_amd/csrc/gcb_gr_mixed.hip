@@ -8,11 +8,11 @@
 
 namespace gcb {
 
-hipError_t launch_gr_push_mixed(const GrPtrs& in, const GrPtrs& out, int64_t n, int n_steps,
-                                const float* F, const double* dl, const gr::GrConst& g,
-                                uint8_t* trace, int trace_step0, DevStats* stats,
-                                hipStream_t stream) {
-    return grk::launch<float, float>(in, out, n, n_steps, F, dl, g, trace, trace_step0, stats,
+hipError_t launch_gr_push_mixed(const GrPtrs& in, const GrPtrs& out, const uint32_t* perm,
+                                int64_t n, int n_steps, const float* F, const double* dl,
+                                const gr::GrConst& g, uint8_t* trace, int trace_step0,
+                                DevStats* stats, hipStream_t stream) {
+    return grk::launch<float, float>(in, out, perm, n, n_steps, F, dl, g, trace, trace_step0, stats,
                                      stream);
 }
 

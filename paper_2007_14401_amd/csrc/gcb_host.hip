@@ -965,19 +965,22 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     g.n_iter = prm->n_iter;
     GrPtrs ptrs{p->r, p->th, p->ph, p->ur, p->uth, p->uph, p->qm, p->id, p->status};
     const double* dl = static_cast<const double*>(ctx->gr_dl.ptr);
-    auto push = [&](const GrPtrs& in, const GrPtrs& out, int ns, int step0) {
+    auto push = [&](const GrPtrs& in, const GrPtrs& out, const uint32_t* perm, int ns,
+                    int step0) {
         if (prm->form == GCB_FORM_F64)
-            return launch_gr_push_f64(in, out, p->n, ns,
+            return launch_gr_push_f64(in, out, perm, p->n, ns,
                                       static_cast<const double*>(ctx->gr_fields.ptr), dl, g,
                                       s_trace, step0, dstats, stream);
-        return launch_gr_push_mixed(in, out, p->n, ns,
+        return launch_gr_push_mixed(in, out, perm, p->n, ns,
                                     static_cast<const float*>(ctx->gr_fields.ptr), dl, g, s_trace,
                                     step0, dstats, stream);
     };
     if (prm->sort_every > 0 && p->n > 0 && n_steps > 0) {
-        // every sort_every steps: sort by (r, theta) tiles of kGrTile^2 cells
-        // into a scratch copy, then push from the copy back into the caller's
-        // arrays (which end up in tile order, `id` and `qm` carried along)
+        // every sort_every steps: sort by (r, theta) tiles of kGrTile^2 cells;
+        // the push reads through the permutation and writes in tile order
+        // into the other of two buffers (the caller's arrays and a library
+        // copy, `id` and `qm` carried along); a state that ends in the copy
+        // is copied back
         constexpr int kGrTile = 16;
         const int64_t n = p->n;
         const size_t ub = prm->form == GCB_FORM_F64 ? sizeof(double) : sizeof(float);
@@ -999,21 +1002,39 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
         sc.uph = c + 2 * n * ub;
         sc.id = p->id ? reinterpret_cast<int32_t*>(c + 3 * n * ub) : nullptr;
         sc.status = reinterpret_cast<uint8_t*>(c + 3 * n * ub + n * sizeof(int32_t));
+        GrPtrs cur = ptrs, other = sc;
         for (int32_t s0 = 0; s0 < n_steps; s0 += prm->sort_every) {
             const int ns = std::min<int32_t>(prm->sort_every, n_steps - s0);
             {
                 Timer t(ctx, stream, GCB_TIMER_SORT);
-                GCB_HIP(launch_gr_cell_sort(p->r, p->th, n, g, kGrTile, sb, stream));
-                GCB_HIP(launch_gr_permute(ptrs, sc, ub, sb.idx, n, stream));
+                GCB_HIP(launch_gr_cell_sort(cur.r, cur.th, n, g, kGrTile, sb, stream));
                 t.done();
             }
             Timer t(ctx, stream, GCB_TIMER_PUSH);
-            GCB_HIP(push(sc, ptrs, ns, s0));
+            GCB_HIP(push(cur, other, sb.idx, ns, s0));
+            t.done();
+            std::swap(cur, other);
+        }
+        if (cur.r != ptrs.r) {
+            Timer t(ctx, stream, GCB_TIMER_OTHER);
+            const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+            const size_t nd = (size_t)n * sizeof(double);
+            GCB_HIP(hipMemcpyAsync(ptrs.r, cur.r, nd, k, stream));
+            GCB_HIP(hipMemcpyAsync(ptrs.th, cur.th, nd, k, stream));
+            GCB_HIP(hipMemcpyAsync(ptrs.ph, cur.ph, nd, k, stream));
+            GCB_HIP(hipMemcpyAsync(ptrs.ur, cur.ur, n * ub, k, stream));
+            GCB_HIP(hipMemcpyAsync(ptrs.uth, cur.uth, n * ub, k, stream));
+            GCB_HIP(hipMemcpyAsync(ptrs.uph, cur.uph, n * ub, k, stream));
+            GCB_HIP(hipMemcpyAsync(ptrs.status, cur.status, (size_t)n, k, stream));
+            if (p->qm)
+                GCB_HIP(hipMemcpyAsync(const_cast<double*>(ptrs.qm), cur.qm, nd, k, stream));
+            if (p->id)
+                GCB_HIP(hipMemcpyAsync(ptrs.id, cur.id, (size_t)n * sizeof(int32_t), k, stream));
             t.done();
         }
     } else {
         Timer t(ctx, stream, GCB_TIMER_PUSH);
-        GCB_HIP(push(ptrs, ptrs, n_steps, 0));
+        GCB_HIP(push(ptrs, ptrs, nullptr, n_steps, 0));
         t.done();
     }
     return stats_end(ctx, p->status, p->n, stats, stream);

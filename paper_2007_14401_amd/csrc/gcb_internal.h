@@ -181,20 +181,19 @@ struct GrPtrs {
 hipError_t launch_gr_cell_sort(const double* r, const double* th, int64_t n,
                                const gr::GrConst& g, int tile, const SortBuffers& b,
                                hipStream_t stream);
-hipError_t launch_gr_permute(const GrPtrs& src, const GrPtrs& dst, size_t u_bytes,
-                             const uint32_t* perm, int64_t n, hipStream_t stream);
 
 hipError_t launch_gr_cell_lengths(const gr::GrConst& g, double dr, double dth, double* dl,
                                   hipStream_t stream);
-// n_steps steps; the first launch reads `in` and writes `out`, later ones
-// work in place on `out`; trace[step*n + (id ? id : slot)]
-hipError_t launch_gr_push_f64(const GrPtrs& in, const GrPtrs& out, int64_t n, int n_steps,
-                              const double* F, const double* dl, const gr::GrConst& g,
-                              uint8_t* trace, int trace_step0, DevStats* stats,
-                              hipStream_t stream);
-hipError_t launch_gr_push_mixed(const GrPtrs& in, const GrPtrs& out, int64_t n, int n_steps,
-                                const float* F, const double* dl, const gr::GrConst& g,
-                                uint8_t* trace, int trace_step0, DevStats* stats,
-                                hipStream_t stream);
+// n_steps steps; the first launch reads slot perm[k] of `in` (k when perm is
+// null) and writes slot k of `out`, later ones work in place on `out`;
+// trace[step*n + (id ? id : slot)]
+hipError_t launch_gr_push_f64(const GrPtrs& in, const GrPtrs& out, const uint32_t* perm,
+                              int64_t n, int n_steps, const double* F, const double* dl,
+                              const gr::GrConst& g, uint8_t* trace, int trace_step0,
+                              DevStats* stats, hipStream_t stream);
+hipError_t launch_gr_push_mixed(const GrPtrs& in, const GrPtrs& out, const uint32_t* perm,
+                                int64_t n, int n_steps, const float* F, const double* dl,
+                                const gr::GrConst& g, uint8_t* trace, int trace_step0,
+                                DevStats* stats, hipStream_t stream);
 
 }  // namespace gcb

@@ -10,11 +10,11 @@
 //     k_radix_scatter  wave-level multisplit ranks -> stable scatter
 //   k_tile_bounds tile_start from the boundaries of the sorted keys
 // The push kernel of the sort's step then reads the state through idx (the
-// permutation) and writes it in tile order, so there is no permutation pass.
-//   k_gr_tile_keys, k_gr_permute: the same for the curved-spacetime state
-//                 ((r, theta) tiles of the grid cells), which is permuted in
-//                 a pass of its own
-//   k_tile_keys3: the keys of the 3D state (cubic tiles)
+// permutation) and writes it in tile order, so there is no permutation pass
+// (the same for the curved-spacetime and 3D states).
+//   k_gr_tile_keys: the keys of the curved-spacetime state ((r, theta) tiles
+//                 of the grid cells)
+//   k_tile_keys3:   the keys of the 3D state (cubic tiles)
 #include <hip/hip_runtime.h>
 
 #include "gcb_internal.h"
@@ -95,24 +95,6 @@ __global__ __launch_bounds__(kSortWG) void k_gr_tile_keys(const double* __restri
     gr::grid_cell(g, r[p], th[p], i, j, wx, wy);
     keys[p] = (uint32_t)((j / tile) * ntx + i / tile);
     idx[p] = (uint32_t)p;
-}
-
-template <typename U>
-__global__ __launch_bounds__(kSortWG) void k_gr_permute(GrPtrs src, GrPtrs dst,
-                                                        const uint32_t* __restrict__ perm,
-                                                        int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * kSortWG + threadIdx.x;
-    if (i >= n) return;
-    const int64_t s = perm[i];
-    dst.r[i] = src.r[s];
-    dst.th[i] = src.th[s];
-    dst.ph[i] = src.ph[s];
-    static_cast<U*>(dst.ur)[i] = static_cast<const U*>(src.ur)[s];
-    static_cast<U*>(dst.uth)[i] = static_cast<const U*>(src.uth)[s];
-    static_cast<U*>(dst.uph)[i] = static_cast<const U*>(src.uph)[s];
-    if (src.qm) const_cast<double*>(dst.qm)[i] = src.qm[s];
-    if (src.id) dst.id[i] = src.id[s];
-    dst.status[i] = src.status[s];
 }
 
 __global__ __launch_bounds__(kSortWG) void k_radix_hist(const uint32_t* __restrict__ keys,
@@ -359,19 +341,6 @@ hipError_t launch_gr_cell_sort(const double* r, const double* th, int64_t n,
     while ((1 << nbits) < ntx * nty) ++nbits;
     uint32_t* kin = b.keys;
     return radix_sort(n, nbits, b, stream, &kin);
-}
-
-hipError_t launch_gr_permute(const GrPtrs& src, const GrPtrs& dst, size_t u_bytes,
-                             const uint32_t* perm, int64_t n, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((n + kSortWG - 1) / kSortWG);
-    if (u_bytes == sizeof(double))
-        hipLaunchKernelGGL(k_gr_permute<double>, dim3(blocks), dim3(kSortWG), 0, stream, src,
-                           dst, perm, n);
-    else
-        hipLaunchKernelGGL(k_gr_permute<float>, dim3(blocks), dim3(kSortWG), 0, stream, src,
-                           dst, perm, n);
-    return hipGetLastError();
 }
 
 hipError_t launch_cell_sort3(const double* x, const double* y, const double* z, int64_t n,
