@@ -179,6 +179,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=100)
+    ap.add_argument("--adjoint-c4-steps", type=int, default=512)
     ap.add_argument("--no-gr", action="store_true")
     ap.add_argument("--gr-steps", type=int, default=40)
     ap.add_argument("--gr-warmup", type=int, default=4)
@@ -259,10 +260,13 @@ def main():
             gcb.gcb_destroy(ctx)
             torch.cuda.empty_cache()
 
-    def time_fwd_adjoint(steps: int, checkpoint: int):
+    def time_fwd_adjoint(steps: int, checkpoint: int, wcfg=None, F=F, ens=ens):
         """Forward + reverse pass of the differentiable push (loss: mean final
-        kinetic energy; gradients to the E/B grids and the initial state)."""
+        kinetic energy; gradients to the E/B grids and the initial state), on
+        the benchmark workload or on `wcfg` with its fields F and particles ens."""
         from paper_2007_14401_amd import autograd as A
+        cfg_ = cfg if wcfg is None else wcfg
+        n_ = ens.n
         pctx = A.PushContext(0)
         try:
             Ft = torch.as_tensor(F, dtype=torch.float64, device=dev)
@@ -272,13 +276,13 @@ def main():
             names = ("x", "y", "xp", "yp", "ux", "uy", "uz")
             # initial positions cell-sorted (row-major cells), as the workload states;
             # the differentiable push itself does not re-sort
-            cell = (np.floor(ens.y / cfg.dy).astype(np.int64) * cfg.nx
-                    + np.floor(ens.x / cfg.dx).astype(np.int64))
+            cell = (np.floor(ens.y / cfg_.dy).astype(np.int64) * cfg_.nx
+                    + np.floor(ens.x / cfg_.dx).astype(np.int64))
             order = np.argsort(cell, kind="stable")
             st = {k: torch.as_tensor(getattr(ens, k)[order], dtype=torch.float64, device=dev)
                   .requires_grad_(True) for k in names}
-            prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
-                             curvature=cfg.curvature, n_iter=cfg.n_iter)
+            prm = gcb.params(dt=cfg_.dt, c=cfg_.c, qm=cfg_.qm, f_rho=cfg_.f_rho, f_E=cfg_.f_E,
+                             curvature=cfg_.curvature, n_iter=cfg_.n_iter)
             # warm-up: two steps forward and backward
             out = A.push(E, B, *[st[k] for k in names], None, pctx, prm, 2, checkpoint)
             A.kinetic_energy(out[4], out[5], out[6], pctx, prm).backward()
@@ -295,7 +299,8 @@ def main():
             ms, cnt = gcb.gcb_get_timing(pctx.ctx)
             gcb.gcb_set_timing(pctx.ctx, False)
             log(f"[bench] fwd+adjoint: {steps} steps in {t1 - t0:.3f} s; kernel ms {ms}")
-            return {"value": n * steps / (t1 - t0), "unit": "particle-steps/s",
+            return {"value": n_ * steps / (t1 - t0), "unit": "particle-steps/s",
+                    "workload": f"{cfg_.name}: {cfg_.nx}x{cfg_.ny}, {n_} particles",
                     "steps": steps, "checkpoint": checkpoint, "seconds": t1 - t0,
                     "forward_push_ms_per_step": ms[gcb.GCB_TIMER_PUSH] / max(1, steps),
                     "backward_ms_per_step": ms[gcb.GCB_TIMER_BACKWARD] / max(1, steps),
@@ -471,6 +476,13 @@ def main():
     if not a.no_adjoint:
         forms["fwd_adjoint"] = time_fwd_adjoint(a.adjoint_steps, 32)
         forms["fwd_adjoint"]["speed_vs_f64_forward"] = forms["fwd_adjoint"]["value"] / value
+        if a.adjoint_c4_steps > 0:
+            # the differentiation workload as stated: 1024^2 grid, 1e6
+            # particles, 512 steps, a checkpoint every 32 steps
+            c4 = make_config("harris1024")
+            log(f"[bench] differentiation workload {c4.name}: n={c4.n}")
+            forms["fwd_adjoint_c4"] = time_fwd_adjoint(a.adjoint_c4_steps, 32, wcfg=c4,
+                                                       F=c4.fields(), ens=c4.particles())
 
     copy_gbs = copy_bandwidth(dev)
     if a.copy_calib:
