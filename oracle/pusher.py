@@ -35,6 +35,15 @@ design notes of the repository):
   * Params.exact_frame (zero-curvature scheme only): b*, the exact v_E and
     kappa and E_par = E'/kappa of the frame of Sec. 2.2 (frame.py) in place of
     b, c E x B/B^2 and E.b; everything else unchanged.
+  * Params.gyration: how the gyration speed enters a guiding-center step.
+    GYR_MU (the paper's choice, eq. dmudt): mu is conserved, so wherever
+    u_perp_g^2 = 2 mu B kappa/m appears (eq. lfacgca2, k3 of the quadratic,
+    the reconstruction) it is evaluated with B and kappa of that point.
+    GYR_UPERP (the energy-conserving alternative the paper describes after
+    the SRGCA system): u_perp_g keeps the value of the decomposition over
+    the whole step.  GYR_ZERO (mu = 0, which the paper allows where
+    radiation has removed the gyration, Sec. 2.2 before Sec. 2.2.1): the
+    decomposition's gyration is discarded.
 """
 from __future__ import annotations
 
@@ -54,6 +63,11 @@ ST_QUAD = 4        # no admissible root of the parallel-update quadratic
 ST_BZERO = 8       # B = 0 at a guiding-center evaluation point
 ST_FPRES = 16      # fixed-point iteration error above tolerance
 
+# gyration handling of a guiding-center step (Params.gyration)
+GYR_MU = 0      # mu conserved (eq. dmudt)
+GYR_UPERP = 1   # u_perp_g constant over the step
+GYR_ZERO = 2    # mu = 0
+
 KAPPA_FLOOR = 1.0e-12   # lower clamp of 1 - v_E^2/c^2
 D_FLOOR = 1.0e-12       # |1 - (dt/2) v_E.(b.grad)b| below this: no division
 
@@ -71,6 +85,7 @@ class Params:
     Ly: float = 0.0
     dl: float = 1.0   # effective cell size sqrt(dx*dy)
     exact_frame: bool = False   # b*, exact v_E (frame.py); zero-curvature scheme only
+    gyration: int = GYR_MU      # GYR_MU, GYR_UPERP or GYR_ZERO
 
     @property
     def c2(self) -> float:
@@ -179,9 +194,31 @@ def local(prov, X, Y, p: Params):
                            flags=flags.to(torch.uint8))
 
 
-def gamma_gca(L, upar, mu, p: Params):
+def gyration(up2, Lh, p: Params):
+    """Gyration state of a guiding-center step from u_perp_g^2 at the
+    decomposition point: mu/m = u_perp_g^2/(2 B kappa), or u_perp_g^2 itself
+    when it is held constant (Params.gyration)."""
+    mu = ((0.5 * up2) * Lh.inv_B) / Lh.kappa
+    if p.gyration == GYR_ZERO:
+        mu = torch.zeros_like(mu)
+    return SimpleNamespace(mu=mu, up2=up2, fixed=p.gyration == GYR_UPERP)
+
+
+def conserved_mu(mu):
+    """The gyration state for a given mu/m, conserved over the step."""
+    return SimpleNamespace(mu=mu, up2=None, fixed=False)
+
+
+def uperp_sq(L, gy):
+    """u_perp_g^2 at a point: 2 mu B kappa/m, or the held value."""
+    if gy.fixed:
+        return gy.up2
+    return ((2.0 * gy.mu) * L.B) * L.kappa
+
+
+def gamma_gca(L, upar, gy, p: Params):
     """Gamma(R, u_par) = kappa sqrt(1 + (u_par^2 + 2 mu B kappa / m)/c^2) (eq. lfacgca2)."""
-    uperp2 = ((2.0 * mu) * L.B) * L.kappa
+    uperp2 = uperp_sq(L, gy)
     return L.kappa * sqrt(1.0 + (upar * upar + uperp2) * p.inv_c2)
 
 
@@ -259,7 +296,7 @@ def boris_step(s, st: State, p: Params):
 # guiding-center leapfrog (Sec. 2.2.1, 2.2.2) inside the coupled step (Sec. 3.1)
 
 
-def parallel_update(Ln, upar, mu, qm, p: Params):
+def parallel_update(Ln, upar, gy, qm, p: Params):
     """u_par^{n-1/2} -> u_par^{n+1/2} at R^n; returns (u_par_new, flags).
 
     Without curvature: u_par + (q dt/m) E_par.  With curvature: solve
@@ -271,13 +308,13 @@ def parallel_update(Ln, upar, mu, qm, p: Params):
         return upar + dtqm * Ln.Epar, torch.zeros_like(upar, dtype=torch.uint8)
     h = 0.5 * p.dt
     A, C = Ln.A, Ln.C
-    G0 = gamma_gca(Ln, upar, mu, p)
+    G0 = gamma_gca(Ln, upar, gy, p)
     upr = (upar * (1.0 + h * A) + dtqm * Ln.Epar) + (h * G0) * C
     D = 1.0 - h * A
     DD = D * D
     k1 = (h * h) * (C * C) - (p.c2 * DD) / (Ln.kappa * Ln.kappa)
     k2 = (upr * p.dt) * C
-    k3 = upr * upr + (p.c2 + ((2.0 * mu) * Ln.B) * Ln.kappa) * DD
+    k3 = upr * upr + (p.c2 + uperp_sq(Ln, gy)) * DD
     disc = k2 * k2 - (4.0 * k1) * k3
     dok = torch.abs(D) >= D_FLOOR
     ok = (k1 < 0.0) & (disc >= 0.0) & dok
@@ -293,7 +330,7 @@ def parallel_update(Ln, upar, mu, qm, p: Params):
     Ds = torch.where(dok, D, 1.0)
     unew = (upr + (h * gp) * C) / Ds
     # fallbacks: neglect the implicit Gamma term, or the curvature terms
-    gfb = gamma_gca(Ln, upr / Ds, mu, p)
+    gfb = gamma_gca(Ln, upr / Ds, gy, p)
     ufb = (upr + (h * gfb) * C) / Ds
     uexp = upar + dtqm * Ln.Epar
     out = torch.where(ok, unew, torch.where(dok, ufb, uexp))
@@ -301,9 +338,9 @@ def parallel_update(Ln, upar, mu, qm, p: Params):
     return out, flags
 
 
-def _drift_terms(L, upar_new, mu, inv_qm, p: Params):
+def _drift_terms(L, upar_new, gy, inv_qm, p: Params):
     """u_par b/Gamma + v_E + v_c at a point, x and y components."""
-    g = gamma_gca(L, upar_new, mu, p)
+    g = gamma_gca(L, upar_new, gy, p)
     a = upar_new / g
     if p.curvature:
         vc = v_curv(L, upar_new, g, inv_qm, p)
@@ -338,7 +375,7 @@ def gca_step(prov, st: State, p: Params):
     upy = (uy - upar * by) - (Lh.vE[1] + vc[1]) * gf
     upz = (uz - upar * bz) - (Lh.vE[2] + vc[2]) * gf
     up2 = (upx * upx + upy * upy) + upz * upz
-    mu = ((0.5 * up2) * Lh.inv_B) / Lh.kappa
+    gy = gyration(up2, Lh, p)
     nu = sqrt(up2)
     inv_nu = torch.where(nu > 0.0, 1.0 / torch.where(nu > 0.0, nu, 1.0), 0.0)
     bpx, bpy, bpz = upx * inv_nu, upy * inv_nu, upz * inv_nu
@@ -346,12 +383,12 @@ def gca_step(prov, st: State, p: Params):
     # 2.-3. fields at R^n = x^n and the parallel four-velocity update
     Ln = local(prov, x, y, p)
     flags |= Ln.flags
-    upn, qf = parallel_update(Ln, upar, mu, qm, p)
+    upn, qf = parallel_update(Ln, upar, gy, qm, p)
     flags |= qf
 
     # 4. R^{n+1} by fixed-point iteration R^{k+1} = R^k - H(R^k), R^0 = R^n
     h = 0.5 * p.dt
-    Fn = _drift_terms(Ln, upn, mu, inv_qm, p)
+    Fn = _drift_terms(Ln, upn, gy, inv_qm, p)
     Rx, Ry = x, y
     res = torch.zeros_like(x)
     for k in range(p.n_iter):
@@ -360,7 +397,7 @@ def gca_step(prov, st: State, p: Params):
         else:
             Lk = local(prov, Rx, Ry, p)
             flags |= Lk.flags
-            Fk = _drift_terms(Lk, upn, mu, inv_qm, p)
+            Fk = _drift_terms(Lk, upn, gy, inv_qm, p)
         Rx_new = x + h * (Fn[0] + Fk[0])
         Ry_new = y + h * (Fn[1] + Fk[1])
         res = torch.maximum(torch.abs(Rx_new - Rx), torch.abs(Ry_new - Ry))
@@ -372,13 +409,13 @@ def gca_step(prov, st: State, p: Params):
     Rmy = y + 0.5 * (Ry - y)
     Lm = local(prov, Rmx, Rmy, p)
     flags |= Lm.flags
-    gr = gamma_gca(Lm, upn, mu, p)
+    gr = gamma_gca(Lm, upn, gy, p)
     if p.curvature:
         vcm = v_curv(Lm, upn, gr, inv_qm, p)
     else:
         z = torch.zeros_like(x)
         vcm = (z, z, z)
-    um = sqrt(((2.0 * mu) * Lm.B) * Lm.kappa)
+    um = sqrt(uperp_sq(Lm, gy))
     bmx, bmy, bmz = Lm.b
     uxn = (upn * bmx + (Lm.vE[0] + vcm[0]) * gr) + um * bpx
     uyn = (upn * bmy + (Lm.vE[1] + vcm[1]) * gr) + um * bpy

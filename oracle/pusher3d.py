@@ -24,8 +24,8 @@ import torch
 
 from .ieee import sqrt
 from .pusher import (D_FLOOR, KAPPA_FLOOR, ST_BZERO, ST_FPRES, ST_KAPPA, ST_NONFINITE,
-                     Params, boris, gamma_gca, min_image, parallel_update, switch_gca,
-                     v_curv, wrap)
+                     Params, boris, gamma_gca, gyration, min_image, parallel_update, switch_gca,
+                     uperp_sq, v_curv, wrap)
 
 F64 = torch.float64
 
@@ -137,9 +137,9 @@ def boris_step3(s, st: State3, p: Params3):
 # guiding-center leapfrog (Sec. 2.2.1, 2.2.2) inside the coupled step (Sec. 3.1)
 
 
-def _drift_terms3(L, upar_new, mu, inv_qm, p: Params3):
+def _drift_terms3(L, upar_new, gy, inv_qm, p: Params3):
     """u_par b/Gamma + v_E + v_c at a point, all three components."""
-    g = gamma_gca(L, upar_new, mu, p)
+    g = gamma_gca(L, upar_new, gy, p)
     a = upar_new / g
     if p.curvature:
         vc = v_curv(L, upar_new, g, inv_qm, p)
@@ -173,7 +173,7 @@ def gca_step3(prov, st: State3, p: Params3):
     upy = (uy - upar * by) - (Lh.vE[1] + vc[1]) * gf
     upz = (uz - upar * bz) - (Lh.vE[2] + vc[2]) * gf
     up2 = (upx * upx + upy * upy) + upz * upz
-    mu = ((0.5 * up2) * Lh.inv_B) / Lh.kappa
+    gy = gyration(up2, Lh, p)
     nu = sqrt(up2)
     inv_nu = torch.where(nu > 0.0, 1.0 / torch.where(nu > 0.0, nu, 1.0), 0.0)
     bpx, bpy, bpz = upx * inv_nu, upy * inv_nu, upz * inv_nu
@@ -181,12 +181,12 @@ def gca_step3(prov, st: State3, p: Params3):
     # 2.-3. fields at R^n = x^n and the parallel four-velocity update
     Ln = local3(prov, *pos, p)
     flags |= Ln.flags
-    upn, qf = parallel_update(Ln, upar, mu, qm, p)
+    upn, qf = parallel_update(Ln, upar, gy, qm, p)
     flags |= qf
 
     # 4. R^{n+1} by fixed-point iteration R^{k+1} = R^k - H(R^k), R^0 = R^n
     h = 0.5 * p.dt
-    Fn = _drift_terms3(Ln, upn, mu, inv_qm, p)
+    Fn = _drift_terms3(Ln, upn, gy, inv_qm, p)
     R = pos
     res = torch.zeros_like(st.x)
     for k in range(p.n_iter):
@@ -195,7 +195,7 @@ def gca_step3(prov, st: State3, p: Params3):
         else:
             Lk = local3(prov, *R, p)
             flags |= Lk.flags
-            Fk = _drift_terms3(Lk, upn, mu, inv_qm, p)
+            Fk = _drift_terms3(Lk, upn, gy, inv_qm, p)
         Rn = tuple(c + h * (a + b) for c, a, b in zip(pos, Fn, Fk))
         d = [torch.abs(a - b) for a, b in zip(Rn, R)]
         res = torch.maximum(torch.maximum(d[0], d[1]), d[2])
@@ -206,13 +206,13 @@ def gca_step3(prov, st: State3, p: Params3):
     Rm = tuple(c + 0.5 * (r - c) for c, r in zip(pos, R))
     Lm = local3(prov, *Rm, p)
     flags |= Lm.flags
-    gr = gamma_gca(Lm, upn, mu, p)
+    gr = gamma_gca(Lm, upn, gy, p)
     if p.curvature:
         vcm = v_curv(Lm, upn, gr, inv_qm, p)
     else:
         zr = torch.zeros_like(st.x)
         vcm = (zr, zr, zr)
-    um = sqrt(((2.0 * mu) * Lm.B) * Lm.kappa)
+    um = sqrt(uperp_sq(Lm, gy))
     bmx, bmy, bmz = Lm.b
     uxn = (upn * bmx + (Lm.vE[0] + vcm[0]) * gr) + um * bpx
     uyn = (upn * bmy + (Lm.vE[1] + vcm[1]) * gr) + um * bpy

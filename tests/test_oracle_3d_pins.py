@@ -144,7 +144,7 @@ def test_curvature_in_xz_plane():
     assert torch.all(L.bgb[1].abs() < 1e-15)
     assert torch.allclose(L.bgb[2], -torch.sin(th) / r, atol=1e-14)
     upar = torch.full_like(r, 0.3)
-    gam = O.gamma_gca(L, upar, torch.zeros_like(r), p)
+    gam = O.gamma_gca(L, upar, O.conserved_mu(torch.zeros_like(r)), p)
     vc = O.v_curv(L, upar, gam, torch.full_like(r, 1 / qm), p)
     assert torch.allclose(vc[1], c * upar ** 2 / (qm * B0 * gam * r), rtol=1e-13)
     assert torch.all(vc[0].abs() < 1e-16) and torch.all(vc[2].abs() < 1e-16)

@@ -347,10 +347,10 @@ def test_parallel_update_satisfies_discrete_equation():
     upar = torch.as_tensor(rng.normal(0, 0.5, 16))
     mu = torch.as_tensor(rng.uniform(0, 0.05, 16))
     qm = torch.full((16,), -2.0, dtype=F64)
-    un, fl = O.parallel_update(L, upar, mu, qm, p)
+    un, fl = O.parallel_update(L, upar, O.conserved_mu(mu), qm, p)
     assert torch.all(fl == 0)
-    g0 = O.gamma_gca(L, upar, mu, p)
-    g1 = O.gamma_gca(L, un, mu, p)
+    g0 = O.gamma_gca(L, upar, O.conserved_mu(mu), p)
+    g1 = O.gamma_gca(L, un, O.conserved_mu(mu), p)
     lhs = (un - upar) / dt
     rhs = qm * L.Epar + 0.5 * (upar + un) * L.A + 0.5 * (g0 + g1) * L.C
     assert torch.allclose(lhs, rhs, rtol=1e-12, atol=1e-14)
@@ -369,7 +369,7 @@ def test_parallel_update_no_curvature_terms_closed_form():
     upar = torch.linspace(-1, 1, n, dtype=F64)
     mu = torch.full((n,), 0.01, dtype=F64)
     qm = torch.full((n,), -2.0, dtype=F64)
-    un, fl = O.parallel_update(L, upar, mu, qm, p)
+    un, fl = O.parallel_update(L, upar, O.conserved_mu(mu), qm, p)
     assert torch.all(fl == 0)
     assert torch.allclose(un, upar + qm * p.dt * L.Epar, rtol=0, atol=1e-15)
 
@@ -380,7 +380,7 @@ def test_parallel_update_fallback_flag():
     p = params()
     one = torch.ones(1, dtype=F64)
     L = SimpleNamespace(A=0 * one, C=10.0 * one, B=one, kappa=one, Epar=0 * one)
-    un, fl = O.parallel_update(L, 0.1 * one, 0 * one, -one, p)
+    un, fl = O.parallel_update(L, 0.1 * one, O.conserved_mu(0 * one), -one, p)
     assert int(fl[0]) == O.ST_QUAD and torch.isfinite(un).all()
 
 
@@ -401,7 +401,7 @@ def test_curvature_vector_circular_field():
     assert torch.all(L.bgb[2].abs() < 1e-15)
     upar = torch.full_like(r, 0.3)
     mu = torch.zeros_like(r)
-    gam = O.gamma_gca(L, upar, mu, p)
+    gam = O.gamma_gca(L, upar, O.conserved_mu(mu), p)
     qm = -5.0
     vc = O.v_curv(L, upar, gam, torch.full_like(r, 1 / qm), p)
     expect = c * upar ** 2 / (qm * 2.0 * gam * r)
@@ -468,10 +468,10 @@ def test_fixed_point_converges_to_trapezoidal_solution():
           zip((st.ux, st.uy, st.uz), Lh.b, Lh.vE, vc)]
     mu = 0.5 * (up[0] ** 2 + up[1] ** 2 + up[2] ** 2) * Lh.inv_B / Lh.kappa
     Ln = O.local(prov, st.x, st.y, p60)
-    un, _ = O.parallel_update(Ln, upar, mu, st.qm, p60)
+    un, _ = O.parallel_update(Ln, upar, O.conserved_mu(mu), st.qm, p60)
     L1 = O.local(prov, Rx, Ry, p60)
-    F0 = _drift_terms(Ln, un, mu, 1 / st.qm, p60)
-    F1 = _drift_terms(L1, un, mu, 1 / st.qm, p60)
+    F0 = _drift_terms(Ln, un, O.conserved_mu(mu), 1 / st.qm, p60)
+    F1 = _drift_terms(L1, un, O.conserved_mu(mu), 1 / st.qm, p60)
     Hx = Rx - st.x - 0.5 * p60.dt * (F0[0] + F1[0])
     Hy = Ry - st.y - 0.5 * p60.dt * (F0[1] + F1[1])
     assert torch.all(Hx[ok].abs() < 1e-12) and torch.all(Hy[ok].abs() < 1e-12)
