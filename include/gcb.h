@@ -64,6 +64,15 @@ extern "C" {
                                  E_par = E'/kappa; with curvature = 0, GCB_FORM_F64,
                                  gcb_push and gcb_push_3d only */
 
+/* gyration handling of a guiding-center step (gcb_params.gyration), Sec. 2.2 */
+#define GCB_GYRATION_MU    0   /* mu/m = u_perp_g^2/(2 B kappa) conserved (eq. dmudt): u_perp_g^2
+                                  = 2 mu B kappa/m at every point of the step (the paper's choice) */
+#define GCB_GYRATION_UPERP 1   /* u_perp_g held at its value at the decomposition over the step:
+                                  the alternative the paper describes, which conserves the energy
+                                  exactly when E = 0 and the curvature terms vanish */
+#define GCB_GYRATION_ZERO  2   /* mu = 0: the gyration found at the decomposition is discarded
+                                  (the paper allows it where radiation has removed it) */
+
 /* where field arrays live (gcb_load_fields.src) */
 #define GCB_HOST   0
 #define GCB_DEVICE 1
@@ -152,6 +161,9 @@ typedef struct {
                             scheme (Sec. 2.2.1) and the conversions of Sec. 3.1 then use
                             b*, this v_E and kappa, and du_par/dt = (q/m) E'/kappa.  Other
                             calls and combinations return GCB_EUNSUPPORTED. */
+    int32_t gyration;    /* GCB_GYRATION_* (0 = mu conserved).  Other values than
+                            GCB_GYRATION_MU: gcb_push and gcb_push_3d only (both forms,
+                            both frames); other calls return GCB_EUNSUPPORTED */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.

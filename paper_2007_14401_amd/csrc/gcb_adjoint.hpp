@@ -215,6 +215,10 @@ GCB_HD void local_vjp(const SampleD& s, const KD& K, const LocalBar& Lb, SampleB
 // ---------------------------------------------------------------------------
 // Gamma, curvature drift, drift terms
 
+// the gyration state of the differentiated step: mu conserved (the adjoint
+// serves the paper's eq. dmudt only)
+GCB_HD Gyr<double> conserved_mu(double mu) { return Gyr<double>{mu, 0.0, false}; }
+
 GCB_HD void gamma_vjp(const LocalD& L, double upar, double mu, const KD& K, double Gb,
                       LocalBar& Lb, double& uparb, double& mub) {
     const double uperp2 = ((2.0 * mu) * L.B) * L.kappa;
@@ -255,7 +259,7 @@ GCB_HD void vcurv_vjp(const LocalD& L, double upar, double gam, double inv_qm, c
 GCB_HD void drift_vjp(const LocalD& L, double upn, double mu, double inv_qm, bool curv,
                       const KD& K, const double Fb[2], LocalBar& Lb, double& upnb,
                       double& mub) {
-    const double g = gamma_gca(L, upn, mu, K);
+    const double g = gamma_gca(L, upn, conserved_mu(mu), K);
     const double a = upn / g;
     const double ab = Fb[0] * L.b[0] + Fb[1] * L.b[1];
     Lb.b[0] += a * Fb[0];
@@ -284,7 +288,7 @@ GCB_HD void parallel_vjp(const LocalD& Ln, double upar, double mu, double qm, bo
     }
     const double h = K.h;
     const double A = Ln.A, C = Ln.C;
-    const double G0 = gamma_gca(Ln, upar, mu, K);
+    const double G0 = gamma_gca(Ln, upar, conserved_mu(mu), K);
     const double upr = (upar * (1.0 + h * A) + dtqm * Ln.Epar) + (h * G0) * C;
     const double D = 1.0 - h * A;
     const double DD = D * D;
@@ -334,7 +338,7 @@ GCB_HD void parallel_vjp(const LocalD& Ln, double upar, double mu, double qm, bo
     } else {
         // fallback: Gamma taken at u'/D (no implicit term)
         const double v = upr / D;
-        const double gfb = gamma_gca(Ln, v, mu, K);
+        const double gfb = gamma_gca(Ln, v, conserved_mu(mu), K);
         const double upn = (upr + (h * gfb) * C) / D;
         uprb = upnb / D;
         const double gfbb = upnb * h * C / D;
@@ -488,8 +492,8 @@ GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const 
         LocalD L;
         local_at<kYee>(acc, pc, K, x, y, s, L);
         uint32_t fl = 0;
-        upn = parallel_update(L, upar, mu, qm, curv, K, fl);
-        drift_terms(L, upn, mu, inv_qm, curv, K, Fn[0], Fn[1]);
+        upn = parallel_update(L, upar, conserved_mu(mu), qm, curv, K, fl);
+        drift_terms(L, upn, conserved_mu(mu), inv_qm, curv, K, Fn[0], Fn[1]);
     }
     double Rk[kMaxAdjIter + 1][2];
     Rk[0][0] = x;
@@ -503,7 +507,7 @@ GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const 
             SampleD s;
             LocalD L;
             local_at<kYee>(acc, pc, K, Rk[k][0], Rk[k][1], s, L);
-            drift_terms(L, upn, mu, inv_qm, curv, K, F[0], F[1]);
+            drift_terms(L, upn, conserved_mu(mu), inv_qm, curv, K, F[0], F[1]);
         }
         Rk[k + 1][0] = x + h * (Fn[0] + F[0]);
         Rk[k + 1][1] = y + h * (Fn[1] + F[1]);
@@ -524,7 +528,7 @@ GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const 
         local_at<kYee>(acc, pc, K, Rmx, Rmy, s, L);
         LocalBar Lb;
         zero(Lb);
-        const double gr = gamma_gca(L, upn, mu, K);
+        const double gr = gamma_gca(L, upn, conserved_mu(mu), K);
         double vc[3] = {0.0, 0.0, 0.0};
         if (curv) v_curv(L, upn, gr, inv_qm, K, vc);
         const double um = sqrt(((2.0 * mu) * L.B) * L.kappa);

@@ -19,6 +19,14 @@ enum : uint32_t {
     ST_HALO = 32,
 };
 
+// Gyration handling of a guiding-center step (the values of
+// gcb_params.gyration): mu conserved, u_perp_g held, mu = 0.
+enum : int32_t {
+    GYR_MU = 0,
+    GYR_UPERP = 1,
+    GYR_ZERO = 2,
+};
+
 // 1 - v_E^2/c^2 is clamped to this floor where the drift reaches c.
 constexpr double kKappaFloor = 1.0e-12;
 // |1 - (dt/2) v_E.(b.grad)b| below this: no division in the parallel update.
@@ -37,6 +45,7 @@ struct PushConst {
     double stagger[6][2];
     int32_t nx, ny;
     int32_t curvature, n_iter;
+    int32_t gyration, pad_;  // GYR_*
 };
 
 // Device pointers of a structure-of-arrays particle state.

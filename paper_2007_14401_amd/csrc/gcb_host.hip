@@ -168,15 +168,21 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EINVAL, "replay must be 0 or 1");
     if (prm->frame != GCB_FRAME_REDUCED && prm->frame != GCB_FRAME_EXACT)
         return fail(ctx, GCB_EINVAL, "unknown frame %d", prm->frame);
+    if (prm->gyration < GCB_GYRATION_MU || prm->gyration > GCB_GYRATION_ZERO)
+        return fail(ctx, GCB_EINVAL, "unknown gyration %d", prm->gyration);
     return GCB_OK;
 }
 
-// the exact frame is served by gcb_push and gcb_push_3d (curvature = 0,
-// binary64) only
-int reject_exact_frame(gcb_ctx* ctx, const gcb_params* prm) {
+// the exact frame (curvature = 0, binary64) and the gyration options other
+// than a conserved mu are served by gcb_push and gcb_push_3d only
+int reject_push_options(gcb_ctx* ctx, const gcb_params* prm) {
     if (prm->frame != GCB_FRAME_REDUCED)
         return fail(ctx, GCB_EUNSUPPORTED,
                     "the exact frame is served by gcb_push and gcb_push_3d only");
+    if (prm->gyration != GCB_GYRATION_MU)
+        return fail(ctx, GCB_EUNSUPPORTED,
+                    "gyration options other than GCB_GYRATION_MU are served by gcb_push and "
+                    "gcb_push_3d only");
     return GCB_OK;
 }
 
@@ -284,6 +290,7 @@ PushConst physics_const(const gcb_params* prm) {
     pc.qm = prm->qm;
     pc.curvature = prm->curvature;
     pc.n_iter = prm->n_iter;
+    pc.gyration = prm->gyration;
     return pc;
 }
 
@@ -770,7 +777,7 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
         return fail(ctx, GCB_EUNSUPPORTED, "the adjoint needs GCB_FORM_F64 and binary64 fields");
     if (prm->n_iter > 8)
         return fail(ctx, GCB_EUNSUPPORTED, "the adjoint supports n_iter <= 8");
-    if ((rc = reject_exact_frame(ctx, prm))) return rc;
+    if ((rc = reject_push_options(ctx, prm))) return rc;
     GCB_HIP(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     const size_t nd = (size_t)n * sizeof(double);
@@ -931,7 +938,7 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
         return fail(ctx, GCB_EINVAL, "unknown form %d", prm->form);
     if (prm->replay) return fail(ctx, GCB_EUNSUPPORTED, "replay is not supported here");
     {
-        const int rc = reject_exact_frame(ctx, prm);
+        const int rc = reject_push_options(ctx, prm);
         if (rc) return rc;
     }
     if (p->n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");

@@ -346,10 +346,27 @@ GCB_HD uint32_t local_in_frame(const S& s, const Consts<R>& K, Local<R>& L) {
         return local_from_sample(s, K, L);
 }
 
+// Gyration state of a guiding-center step (Sec. 2.2): mu/m, conserved
+// (eq. dmudt), or, with `fixed`, u_perp_g^2 held at its decomposed value
+// over the step (the energy-conserving alternative of Sec. 2.2).  mu = 0 is
+// the state of a step that discards the gyration.
+template <typename R>
+struct Gyr {
+    R mu;
+    R up2;
+    bool fixed;
+};
+
+// u_perp_g^2 at a point: 2 mu B kappa/m, or the held value
+template <typename R>
+GCB_HD R uperp_sq(const Local<R>& L, const Gyr<R>& g) {
+    return g.fixed ? g.up2 : (((R)2 * g.mu) * L.B) * L.kappa;
+}
+
 // Gamma(R, u_par) = kappa sqrt(1 + (u_par^2 + 2 mu B kappa/m)/c^2)  (eq. lfacgca2)
 template <typename R>
-GCB_HD R gamma_gca(const Local<R>& L, R upar, R mu, const Consts<R>& K) {
-    const R uperp2 = (((R)2 * mu) * L.B) * L.kappa;
+GCB_HD R gamma_gca(const Local<R>& L, R upar, const Gyr<R>& gy, const Consts<R>& K) {
+    const R uperp2 = uperp_sq(L, gy);
     const R arg = (R)1 + (upar * upar + uperp2) * K.inv_c2;
     if constexpr (kMixed<R>) {
         if (arg > 1.0e6f) {   // ultra-relativistic: binary64
@@ -495,20 +512,20 @@ GCB_HD void boris_step(const Sample<R>& s, Regs<R>& r, const PushConst& pc,
 // of k1 G^2 + k2 G + k3 = 0 for G = Gamma(R^n, u_par^{n+1/2}), evaluated
 // without cancellation, then eq. dupardtcase2discsol.
 template <typename R>
-GCB_HD R parallel_update(const Local<R>& Ln, R upar, R mu, R qm,
+GCB_HD R parallel_update(const Local<R>& Ln, R upar, const Gyr<R>& gy, R qm,
                                              bool curvature, const Consts<R>& K,
                                              uint32_t& flags) {
     const R dtqm = qm * K.dt;
     if (!curvature) return upar + dtqm * Ln.Epar;
     const R h = K.h;
     const R A = Ln.A, C = Ln.C;
-    const R G0 = gamma_gca(Ln, upar, mu, K);
+    const R G0 = gamma_gca(Ln, upar, gy, K);
     const R upr = (upar * ((R)1 + h * A) + dtqm * Ln.Epar) + (h * G0) * C;
     const R D = (R)1 - h * A;
     const R DD = D * D;
     const R k1 = (h * h) * (C * C) - (K.c2 * DD) / (Ln.kappa * Ln.kappa);
     const R k2 = (upr * K.dt) * C;
-    const R k3 = upr * upr + (K.c2 + (((R)2 * mu) * Ln.B) * Ln.kappa) * DD;
+    const R k3 = upr * upr + (K.c2 + uperp_sq(Ln, gy)) * DD;
     const R disc = k2 * k2 - ((R)4 * k1) * k3;
     const bool dok = fabs(D) >= (R)kDFloor;
     bool ok = (k1 < (R)0) && (disc >= (R)0) && dok;
@@ -523,7 +540,7 @@ GCB_HD R parallel_update(const Local<R>& Ln, R upar, R mu, R qm,
     if (ok) return (upr + (h * gp) * C) / Ds;
     flags |= ST_QUAD;
     if (dok) {
-        const R gfb = gamma_gca(Ln, upr / Ds, mu, K);
+        const R gfb = gamma_gca(Ln, upr / Ds, gy, K);
         return (upr + (h * gfb) * C) / Ds;
     }
     return upar + dtqm * Ln.Epar;
@@ -531,10 +548,10 @@ GCB_HD R parallel_update(const Local<R>& Ln, R upar, R mu, R qm,
 
 // x, y components of u_par b / Gamma + v_E + v_c at a point.
 template <typename R>
-GCB_HD void drift_terms(const Local<R>& L, R upn, R mu, R inv_qm,
+GCB_HD void drift_terms(const Local<R>& L, R upn, const Gyr<R>& gy, R inv_qm,
                                             bool curvature, const Consts<R>& K, R& Fx,
                                             R& Fy) {
-    const R g = gamma_gca(L, upn, mu, K);
+    const R g = gamma_gca(L, upn, gy, K);
     const R a = upn / g;
     if (curvature) {
         R vc[3];
@@ -568,7 +585,8 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     const R inv_qm = (R)1 / qm;
 
     // 1. guiding-center variables at R^{n-1/2} = (x^n + x^{n-1})/2
-    R upar, mu, bpx, bpy, bpz;
+    R upar, bpx, bpy, bpz;
+    Gyr<R> gy;
     {
         const double Rhx = x - 0.5 * min_image(x - r.xp, pc.Lx);
         const double Rhy = y - 0.5 * min_image(y - r.yp, pc.Ly);
@@ -584,7 +602,9 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
         const R upy = (uy - upar * Lh.b[1]) - (Lh.vE[1] + vc[1]) * gf;
         const R upz = (uz - upar * Lh.b[2]) - (Lh.vE[2] + vc[2]) * gf;
         const R up2 = (upx * upx + upy * upy) + upz * upz;
-        mu = (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        gy.mu = pc.gyration == GYR_ZERO ? (R)0 : (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        gy.up2 = up2;
+        gy.fixed = pc.gyration == GYR_UPERP;
         const R nu = sqrt(up2);
         const R inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
         bpx = upx * inv_nu;
@@ -597,8 +617,8 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     {
         Local<R> Ln;
         flags |= local_in_frame<kExact>(sn, K, Ln);
-        upn = parallel_update(Ln, upar, mu, qm, curv, K, flags);
-        drift_terms(Ln, upn, mu, inv_qm, curv, K, Fnx, Fny);
+        upn = parallel_update(Ln, upar, gy, qm, curv, K, flags);
+        drift_terms(Ln, upn, gy, inv_qm, curv, K, Fnx, Fny);
     }
 
     // 4. R^{n+1}: K fixed-point iterations R^{k+1} = R^k - H(R^k), R^0 = R^n
@@ -615,7 +635,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
             gather<R, true, kYee>(acc, pc, K, Rx, Ry, sk);
             Local<R> Lk;
             flags |= local_in_frame<kExact>(sk, K, Lk);
-            drift_terms(Lk, upn, mu, inv_qm, curv, K, Fkx, Fky);
+            drift_terms(Lk, upn, gy, inv_qm, curv, K, Fkx, Fky);
         }
         const double Rx_new = x + (double)(K.h * (Fnx + Fkx));
         const double Ry_new = y + (double)(K.h * (Fny + Fky));
@@ -634,10 +654,10 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
         gather<R, true, kYee>(acc, pc, K, Rmx, Rmy, sm);
         Local<R> Lm;
         flags |= local_in_frame<kExact>(sm, K, Lm);
-        const R gr = gamma_gca(Lm, upn, mu, K);
+        const R gr = gamma_gca(Lm, upn, gy, K);
         R vc[3] = {(R)0, (R)0, (R)0};
         if (curv) v_curv(Lm, upn, gr, inv_qm, K, vc);
-        const R um = sqrt((((R)2 * mu) * Lm.B) * Lm.kappa);
+        const R um = sqrt(uperp_sq(Lm, gy));
         r.ux = (upn * Lm.b[0] + (Lm.vE[0] + vc[0]) * gr) + um * bpx;
         r.uy = (upn * Lm.b[1] + (Lm.vE[1] + vc[1]) * gr) + um * bpy;
         r.uz = (upn * Lm.b[2] + (Lm.vE[2] + vc[2]) * gr) + um * bpz;

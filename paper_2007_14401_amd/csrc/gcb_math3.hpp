@@ -175,9 +175,9 @@ GCB_HD uint32_t local_from_sample(const Sample3<R>& s, const Consts<R>& K, Local
 
 // u_par b / Gamma + v_E + v_c at a point, three components
 template <typename R>
-GCB_HD void drift_terms3(const Local<R>& L, R upn, R mu, R inv_qm, bool curvature,
+GCB_HD void drift_terms3(const Local<R>& L, R upn, const Gyr<R>& gy, R inv_qm, bool curvature,
                          const Consts<R>& K, R F[3]) {
-    const R g = gamma_gca(L, upn, mu, K);
+    const R g = gamma_gca(L, upn, gy, K);
     const R a = upn / g;
     if (curvature) {
         R vc[3];
@@ -226,7 +226,8 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
     const R inv_qm = (R)1 / qm;
 
     // 1. guiding-center variables at R^{n-1/2} = (x^n + x^{n-1})/2
-    R upar, mu, bp[3];
+    R upar, bp[3];
+    Gyr<R> gy;
     {
         double Rh[3];
 #pragma unroll
@@ -243,7 +244,9 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
         const R upy = (uy - upar * Lh.b[1]) - (Lh.vE[1] + vc[1]) * gf;
         const R upz = (uz - upar * Lh.b[2]) - (Lh.vE[2] + vc[2]) * gf;
         const R up2 = (upx * upx + upy * upy) + upz * upz;
-        mu = (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        gy.mu = pc.b.gyration == GYR_ZERO ? (R)0 : (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        gy.up2 = up2;
+        gy.fixed = pc.b.gyration == GYR_UPERP;
         const R nu = sqrt(up2);
         const R inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
         bp[0] = upx * inv_nu;
@@ -256,8 +259,8 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
     {
         Local<R> Ln;
         flags |= local_in_frame<kExact, R>(sn, K, Ln);
-        upn = parallel_update(Ln, upar, mu, qm, curv, K, flags);
-        drift_terms3(Ln, upn, mu, inv_qm, curv, K, Fn);
+        upn = parallel_update(Ln, upar, gy, qm, curv, K, flags);
+        drift_terms3(Ln, upn, gy, inv_qm, curv, K, Fn);
     }
 
     // 4. R^{n+1}: K fixed-point iterations R^{k+1} = R^k - H(R^k), R^0 = R^n
@@ -274,7 +277,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
             gather3<R, true, kYee>(acc, pc, K, Rp[0], Rp[1], Rp[2], sk);
             Local<R> Lk;
             flags |= local_in_frame<kExact, R>(sk, K, Lk);
-            drift_terms3(Lk, upn, mu, inv_qm, curv, K, Fk);
+            drift_terms3(Lk, upn, gy, inv_qm, curv, K, Fk);
         }
         double d[3];
 #pragma unroll
@@ -297,10 +300,10 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
         gather3<R, true, kYee>(acc, pc, K, Rm[0], Rm[1], Rm[2], sm);
         Local<R> Lm;
         flags |= local_in_frame<kExact, R>(sm, K, Lm);
-        const R gr = gamma_gca(Lm, upn, mu, K);
+        const R gr = gamma_gca(Lm, upn, gy, K);
         R vc[3] = {(R)0, (R)0, (R)0};
         if (curv) v_curv(Lm, upn, gr, inv_qm, K, vc);
-        const R um = sqrt((((R)2 * mu) * Lm.B) * Lm.kappa);
+        const R um = sqrt(uperp_sq(Lm, gy));
         r.ux = (upn * Lm.b[0] + (Lm.vE[0] + vc[0]) * gr) + um * bp[0];
         r.uy = (upn * Lm.b[1] + (Lm.vE[1] + vc[1]) * gr) + um * bp[1];
         r.uz = (upn * Lm.b[2] + (Lm.vE[2] + vc[2]) * gr) + um * bp[2];

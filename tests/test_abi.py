@@ -62,7 +62,7 @@ def test_create_without_gpu_fails_cleanly():
 def test_params_struct_layout_matches_header():
     """ctypes mirrors of the C structs have the sizes the header implies."""
     from paper_2007_14401_amd import gcb
-    assert C.sizeof(gcb.gcb_params) == 6 * 8 + 8 * 4
+    assert C.sizeof(gcb.gcb_params) == 6 * 8 + 9 * 4 + 4
     assert C.sizeof(gcb.gcb_particles) == 8 + 10 * 8
     assert C.sizeof(gcb.gcb_grid_desc) == 4 + 4 + 8 + 8 + 96 + 8
     assert C.sizeof(gcb.gcb_stats) == 5 * 8
@@ -70,3 +70,37 @@ def test_params_struct_layout_matches_header():
     assert C.sizeof(gcb.gcb_gr_particles) == 8 + 9 * 8
     assert C.sizeof(gcb.gcb_grid3_desc) == 3 * 4 + 4 + 3 * 8 + 18 * 8
     assert C.sizeof(gcb.gcb_particles3) == 8 + 12 * 8
+
+
+_STRUCTS = ("gcb_grid_desc", "gcb_params", "gcb_particles", "gcb_stats", "gcb_gr_desc",
+            "gcb_gr_particles", "gcb_grid3_desc", "gcb_particles3")
+
+
+def test_ctypes_mirrors_match_the_c_compiler(tmp_path):
+    """Every field of every public struct sits at the offset, and every
+    struct has the size, that a C compiler gives the header."""
+    import shutil
+    import subprocess
+    from paper_2007_14401_amd import gcb
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "gcb.h"', "int main(void) {"]
+    for name in _STRUCTS:
+        st = getattr(gcb, name)
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f in st._fields_:
+            lines.append(f'printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for name in _STRUCTS:
+        st = getattr(gcb, name)
+        assert got[(name, "size")] == C.sizeof(st), name
+        for f in st._fields_:
+            assert got[(name, f[0])] == getattr(st, f[0]).offset, (name, f[0])
