@@ -3,9 +3,11 @@
 // For a segment of n_steps steps starting from a caller-owned state, the
 // forward steps are recomputed (unsorted, one lane per particle, the same
 // arithmetic as gcb_push) while the start state of every step and its switch
-// decisions are kept; then, per step in reverse order, two kernels (one per
-// regime) map the cotangents of the step outputs to those of its inputs and
-// record every gather point with its cotangents.  After a batch of steps a
+// decisions are kept; the decisions give each step the list of its
+// guiding-center particles; then, per step in reverse order, two kernels (one
+// per regime; the guiding-center one with one lane per list entry) map the
+// cotangents of the step outputs to those of its inputs and record every
+// gather point with its cotangents.  After a batch of steps a
 // scatter kernel spreads the recorded cotangents over the nodes of a binary32
 // node-interleaved grid (global atomics), which is finally added to the
 // caller's dE/dB arrays.
@@ -22,6 +24,8 @@
 // a whole batch merge; atomic throughput is what bounds the scatter.
 // Compiled with -ffp-contract=off like the forward binary64 path.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "../../include/gcb.h"
 #include "gcb_adjoint.hpp"
@@ -63,15 +67,25 @@ struct RecordSink {
     }
 };
 
-// One regime per launch: lanes whose particle took the other branch at this
-// step return at once, so no wavefront executes both reverse branches.
+// One regime per launch.  Guiding-center branch: lane t takes entry t of the
+// step's list (k_gca_lists), so every lane of a wavefront has work and waves
+// past the list return at once.  Boris branch: one lane per particle, lanes
+// whose particle took the other branch return at once.
 template <bool kYee, bool kBoris>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(GCB_ADJ_MIN_WAVES))) void
 k_adjoint_step(const double* __restrict__ st, const double* __restrict__ qm_arr,
-               const uint8_t* __restrict__ S, double* lam, int64_t n,
+               const uint8_t* __restrict__ S, const uint32_t* __restrict__ list,
+               const unsigned* __restrict__ count, double* lam, int64_t n,
                const double* __restrict__ F, PushConst pc, RecordSink rec) {
-    const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (p >= n || (S[p] != 0) != kBoris) return;
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    int64_t p;
+    if (kBoris) {
+        if (t >= n || S[t] == 0) return;
+        p = t;
+    } else {
+        if (t >= (int64_t)*count) return;
+        p = list[t];
+    }
     double s[7], l[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
@@ -89,6 +103,55 @@ k_adjoint_step(const double* __restrict__ st, const double* __restrict__ qm_arr,
         adj::gca_step_vjp<kYee>(acc, rec, pc, K, s, qm, l);
 #pragma unroll
     for (int c = 0; c < 7; ++c) lam[c * n + p] = l[c];
+}
+
+// Guiding-center lists of every step of a segment: for step s (blockIdx.y),
+// the particles that took the guiding-center branch (S = 0) go to
+// list + s*n, count[s] of them (the caller zeroes count).  Each workgroup
+// claims its range with one atomic; inside a workgroup the entries are in
+// ascending particle order.  (The Boris branch is light and reads its state
+// faster in place, so it keeps one lane per particle.)
+constexpr int kListWG = 256;
+constexpr int kListItems = 16;   // consecutive particles per lane
+
+__global__ __launch_bounds__(kListWG) void k_gca_lists(const uint8_t* __restrict__ S,
+                                                       int64_t n, uint32_t* list,
+                                                       unsigned* count) {
+    const int64_t s = blockIdx.y;
+    const uint8_t* Ss = S + s * n;
+    uint32_t* out = list + s * n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t p0 = ((int64_t)blockIdx.x * kListWG + threadIdx.x) * kListItems;
+    unsigned mask = 0, ng = 0;
+#pragma unroll
+    for (int k = 0; k < kListItems; ++k) {
+        const int64_t p = p0 + k;
+        if (p < n && Ss[p] == 0) {
+            mask |= 1u << k;
+            ++ng;
+        }
+    }
+    // inclusive wave scan of the per-lane counts
+    unsigned sg = ng;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned u = __shfl_up(sg, off, 64);
+        if (lane >= off) sg += u;
+    }
+    __shared__ unsigned wg[kListWG / 64], base;
+    if (lane == 63) wg[wave] = sg;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tg = 0;
+        for (int w = 0; w < kListWG / 64; ++w) tg += wg[w];
+        base = tg ? atomicAdd(&count[s], tg) : 0u;
+    }
+    __syncthreads();
+    unsigned o = base + sg - ng;
+    for (int w = 0; w < wave; ++w) o += wg[w];
+#pragma unroll
+    for (int k = 0; k < kListItems; ++k)
+        if (mask & (1u << k)) out[o++] = (uint32_t)(p0 + k);
 }
 
 constexpr int kScatterWG = 256;
@@ -211,14 +274,28 @@ hipError_t launch_adjoint_step(const AdjointLaunch& L, double* lam, const PushCo
     const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
     if (L.yee) {
         hipLaunchKernelGGL((k_adjoint_step<true, false>), dim3(blocks), dim3(kWG), 0, stream,
-                           L.state, L.qm, L.strace, lam, L.n, L.fields, pc, rec);
+                           L.state, L.qm, L.strace, L.list, L.count, lam, L.n, L.fields, pc, rec);
         hipLaunchKernelGGL((k_adjoint_step<true, true>), dim3(blocks), dim3(kWG), 0, stream,
-                           L.state, L.qm, L.strace, lam, L.n, L.fields, pc, rec);
+                           L.state, L.qm, L.strace, L.list, L.count, lam, L.n, L.fields, pc, rec);
     } else {
         hipLaunchKernelGGL((k_adjoint_step<false, false>), dim3(blocks), dim3(kWG), 0, stream,
-                           L.state, L.qm, L.strace, lam, L.n, L.fields, pc, rec);
+                           L.state, L.qm, L.strace, L.list, L.count, lam, L.n, L.fields, pc, rec);
         hipLaunchKernelGGL((k_adjoint_step<false, true>), dim3(blocks), dim3(kWG), 0, stream,
-                           L.state, L.qm, L.strace, lam, L.n, L.fields, pc, rec);
+                           L.state, L.qm, L.strace, L.list, L.count, lam, L.n, L.fields, pc, rec);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gca_lists(const uint8_t* trace, int64_t n, int n_steps, uint32_t* lists,
+                            unsigned* counts, hipStream_t stream) {
+    if (n == 0 || n_steps == 0) return hipSuccess;
+    const int64_t per_block = (int64_t)kListWG * kListItems;
+    constexpr int kMaxGridY = 65535;
+    for (int s0 = 0; s0 < n_steps; s0 += kMaxGridY) {
+        const int ns = std::min(kMaxGridY, n_steps - s0);
+        const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)ns);
+        hipLaunchKernelGGL(k_gca_lists, grid, dim3(kListWG), 0, stream, trace + (size_t)s0 * n,
+                           n, lists + (size_t)s0 * n, counts + s0);
     }
     return hipGetLastError();
 }

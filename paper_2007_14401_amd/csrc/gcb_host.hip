@@ -59,7 +59,7 @@ struct gcb_ctx {
     DevBuf pscratch;     // sorted copy of the particle state
     DevBuf stats;        // DevStats + flagged counter
     DevBuf ke_partial;
-    DevBuf adj_states, adj_lam, adj_grad, adj_trace, adj_work, adj_samples;
+    DevBuf adj_states, adj_lam, adj_grad, adj_trace, adj_work, adj_samples, adj_lists;
     // timing
     bool timing = false;
     std::vector<TimedLaunch> launches;
@@ -677,7 +677,8 @@ void gcb_destroy(gcb_ctx* ctx) {
                       &ctx->sort_idx2,  &ctx->sort_hist,  &ctx->sort_scan,
                       &ctx->tile_start, &ctx->pscratch,   &ctx->stats,     &ctx->ke_partial,
                       &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace,
-                      &ctx->adj_work,   &ctx->adj_samples, &ctx->gr_fields, &ctx->gr_dl,
+                      &ctx->adj_work,   &ctx->adj_samples, &ctx->adj_lists, &ctx->gr_fields,
+                      &ctx->gr_dl,
                       &ctx->gr_pscratch, &ctx->fields3};
     for (DevBuf* b : bufs) release(*b);
     delete ctx;
@@ -784,6 +785,10 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
     const size_t nodes = (size_t)ctx->nx * ctx->ny;
     if ((rc = ensure(ctx, ctx->adj_states, (size_t)n_steps * 7 * nd))) return rc;
     if ((rc = ensure(ctx, ctx->adj_trace, (size_t)n_steps * n))) return rc;
+    // guiding-center lists of every step (uint32 per particle and step) and
+    // their lengths
+    if ((rc = ensure(ctx, ctx->adj_lists, (size_t)n_steps * (n + 1) * sizeof(uint32_t))))
+        return rc;
     if ((rc = ensure(ctx, ctx->adj_lam, 7 * nd))) return rc;
     if ((rc = ensure(ctx, ctx->adj_work, 7 * nd + (size_t)n))) return rc;
     if ((rc = ensure(ctx, ctx->adj_grad, nodes * 6 * sizeof(float)))) return rc;
@@ -840,6 +845,14 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
         L.stats = nullptr;
         GCB_HIP(launch_push_f64(L, w, w, pc, stream));
     }
+    // per-step guiding-center lists, so that their reverse kernel runs full
+    // wavefronts
+    uint32_t* lists = static_cast<uint32_t*>(ctx->adj_lists.ptr);
+    unsigned* counts = reinterpret_cast<unsigned*>(lists + (size_t)n_steps * n);
+    if (n > 0 && n_steps > 0) {
+        GCB_HIP(hipMemsetAsync(counts, 0, (size_t)n_steps * sizeof(unsigned), stream));
+        GCB_HIP(launch_gca_lists(trace, n, n_steps, lists, counts, stream));
+    }
     // reverse sweep
     for (int c = 0; c < 7 && n > 0; ++c)
         GCB_HIP(hipMemcpyAsync(lam + c * (size_t)n, lam_end[c], nd, hipMemcpyDeviceToDevice,
@@ -860,6 +873,8 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
         for (int32_t s = s_hi - 1; s >= s_lo; --s) {
             A.state = states + (size_t)s * 7 * n;
             A.strace = trace + (size_t)s * n;
+            A.list = lists + (size_t)s * n;
+            A.count = counts + s;
             A.batch_slot = s - s_lo;
             GCB_HIP(launch_adjoint_step(A, lam, pc, stream));
         }

@@ -142,6 +142,8 @@ struct AdjointLaunch {
     const double* state;    // the step's saved start state: 7 arrays of n (x,y,xp,yp,ux,uy,uz)
     const double* qm;       // nullable
     const uint8_t* strace;  // per-particle S of this step (1 = Boris)
+    const uint32_t* list;   // this step's guiding-center list (launch_gca_lists)
+    const unsigned* count;  // its length
     float* grad_fields;     // node-interleaved float gradient accumulators
     void* records;          // adjoint_record_bytes(n, n_iter, batch) of scratch
     int batch;              // steps whose gather points the records hold
@@ -157,6 +159,12 @@ size_t adjoint_record_bytes(int64_t n, int n_iter, int steps);
 // batch slot L.batch_slot of the records.
 hipError_t launch_adjoint_step(const AdjointLaunch& L, double* lam /*7*n in/out*/,
                                const PushConst& pc, hipStream_t stream);
+
+// Guiding-center lists of n_steps steps from their switch traces (trace:
+// n_steps*n, 0 = guiding center): for step s, lists[s*n + t] for
+// t < counts[s].  counts (n_steps) must be zero on entry.
+hipError_t launch_gca_lists(const uint8_t* trace, int64_t n, int n_steps, uint32_t* lists,
+                            unsigned* counts, hipStream_t stream);
 
 // Node cotangents of the first nb batch slots into L.grad_fields; strace_first
 // is the switch trace of the step in slot 0 (the later slots follow at
