@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle as O
-from workloads import make_config
+from workloads import make_config, make_config3
 
 F64 = torch.float64
 
@@ -84,6 +84,68 @@ def test_oracle_gradient_matches_central_differences(curvature):
         a = float(g["dF"][k, j, i])
         assert abs(a - v) <= 1e-6 * abs(v) + 1e-10, (k, j, i, a, v)
         checked += 1
+    assert checked >= 20
+
+
+def test_oracle_gradient3_matches_central_differences():
+    """The 3D push (harris3d32, curvature on): autograd of the oracle against
+    central differences of its forward on initial positions, four-velocities
+    and grid nodes of all six components, both regimes present."""
+    cfg = make_config3("harris3d32")
+    F = cfg.fields()
+    ens = cfg.particles(n=24, seed_offset=5)
+    st0 = O.State3.from_numpy(ens)
+    p = O.Params3(dt=cfg.dt, c=cfg.c, f_rho=cfg.f_rho, f_E=cfg.f_E, curvature=True,
+                  n_iter=cfg.n_iter, Lx=cfg.Lx, Ly=cfg.Ly, Lz=cfg.Lz, dl=cfg.dl)
+    steps = 5
+    g = O.push_gradients3(F, cfg.dx, cfg.dy, cfg.dz, cfg.stagger, st0, p, steps)
+    tr0 = g["trace"]
+    assert 0 < int(tr0.sum()) < tr0.numel()
+
+    def loss(Fp, s):
+        prov = O.GridFields3(torch.as_tensor(Fp), cfg.dx, cfg.dy, cfg.dz, cfg.stagger)
+        out, tr, _ = O.push3(prov, s, p, steps, trace=True)
+        return float(O.kinetic_energy(out.ux, out.uy, out.uz, p.c)), tr
+
+    def fd(perturb, h):
+        (lp, tp), (lm, tm) = loss(*perturb(+h)), loss(*perturb(-h))
+        if not (torch.equal(tp, tr0) and torch.equal(tm, tr0)):
+            return None
+        return (lp - lm) / (2 * h)
+
+    rng = np.random.default_rng(13)
+    checked = 0
+    for name in ("ux", "uy", "uz", "x", "y", "z"):
+        for i in rng.choice(st0.x.shape[0], 3, replace=False):
+            base = float(getattr(st0, name)[i])
+
+            def perturb(d, name=name, i=i):
+                s = st0.clone()
+                getattr(s, name)[i] += d
+                return F, s
+            v = fd(perturb, 1e-6 * max(1.0, abs(base)))
+            if v is None:
+                continue
+            a = float(g["d" + name][i])
+            assert abs(a - v) <= 1e-6 * max(abs(v), 1e-4 * abs(g["loss"])) + 1e-10, (name, i, a, v)
+            checked += 1
+    dF = g["dF"].abs().flatten()
+    for comp in range(6):
+        sub = g["dF"][comp].abs().flatten()
+        cand = torch.nonzero(sub > 1e-3 * dF.max()).flatten().numpy()
+        for flat in rng.choice(cand, min(2, len(cand)), replace=False):
+            l, j, i = np.unravel_index(flat, F.shape[1:])
+
+            def perturb(d, comp=comp, l=l, j=j, i=i):
+                Fp = F.copy()
+                Fp[comp, l, j, i] += d
+                return Fp, st0.clone()
+            v = fd(perturb, 1e-6)
+            if v is None:
+                continue
+            a = float(g["dF"][comp, l, j, i])
+            assert abs(a - v) <= 1e-6 * abs(v) + 1e-10, (comp, l, j, i, a, v)
+            checked += 1
     assert checked >= 20
 
 
