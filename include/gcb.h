@@ -339,6 +339,22 @@ typedef struct {
 int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm,
                 int32_t n_steps, uint8_t* s_trace, gcb_stats* stats, void* stream);
 
+/* Reverse-mode derivative of n_steps 3D pushes started from `start` (not
+   modified), every switch decision held at its forward value: gcb_push_backward
+   for the 3D state.  lam_end[9]: device arrays of length n with
+   dL/d(x, y, z, xp, yp, zp, ux, uy, uz) at the end of the segment (double);
+   lam_start[9]: output, the same at the segment start (double, overwritten).
+   dE[3], dB[3]: device float arrays of nx*ny*nz elements, element
+   [(l*ny + j)*nx + i] of component k, ACCUMULATED (+=) with dL/dF at every
+   node.  Only GCB_FORM_F64 with 3D fields loaded as GCB_F64, the reduced
+   frame, mu conserved and n_iter <= 8 (else GCB_EUNSUPPORTED).  The forward
+   steps are recomputed internally (unsorted); needs n_steps * n * 76 bytes
+   of context scratch plus the gather-point records of up to 8 steps. */
+int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_params* prm,
+                         int32_t n_steps, const double* const lam_end[9],
+                         double* const lam_start[9], float* const dE[3], float* const dB[3],
+                         void* stream);
+
 /* Kernel timing with HIP events recorded around every launch on the launch
    stream.  gcb_set_timing(ctx, 1) clears and enables; gcb_get_timing
    synchronises on the recorded events and returns, for each kernel class,

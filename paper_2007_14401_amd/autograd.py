@@ -1,4 +1,4 @@
-"""torch.autograd wrappers of the push and of the kinetic-energy loss.
+"""torch.autograd wrappers of the push (2D and 3D) and of the kinetic-energy loss.
 
 GcbPush runs n_steps binary64 pushes through libgcb in segments of
 `checkpoint` steps, keeping only each segment's start state; its backward
@@ -7,6 +7,9 @@ recomputes the segment's forward steps and applies the hand-written adjoint
 with the switch decisions held at their forward values.  Gradients reach the
 E and B grids (accumulated in binary32 on the device, returned as float64)
 and the initial state (x, y, xp, yp, u).
+
+GcbPush3 / push3 do the same for the 3D push with gcb_push_backward_3d
+(state x, y, z, xp, yp, zp, u; fields of shape (3, nz, ny, nx)).
 
 KineticEnergy is the mean (Gamma - 1) c^2 of a state, computed by the
 library's reduction kernel; its backward uses dL/du = u/(n Gamma).
@@ -104,6 +107,79 @@ def push(E, B, x, y, xp, yp, ux, uy, uz, qm, pctx, prm, n_steps, checkpoint=32):
         prm.kernel = gcb.GCB_KERNEL_AUTO
     return GcbPush.apply(E, B, x, y, xp, yp, ux, uy, uz, qm, pctx, prm, int(n_steps),
                          int(checkpoint))
+
+
+_NAMES3 = ("x", "y", "z", "xp", "yp", "zp", "ux", "uy", "uz")
+
+
+class PushContext3(PushContext):
+    """A libgcb context with binary64 3D fields taken from device tensors, on
+    a lattice of cell sizes d = (dx, dy, dz) and component offsets `stagger`."""
+
+    def __init__(self, device: int = 0, d=(1.0, 1.0, 1.0), stagger=gcb.YEE3_STAGGER):
+        super().__init__(device)
+        self.d, self.stagger = tuple(d), stagger
+
+    def load(self, E: torch.Tensor, B: torch.Tensor):
+        nz, ny, nx = (int(v) for v in E.shape[1:])
+        desc = gcb.grid3_desc(nx, ny, nz, *self.d, self.stagger, gcb.GCB_F64)
+        Ec = [E[i].detach().contiguous() for i in range(3)]
+        Bc = [B[i].detach().contiguous() for i in range(3)]
+        gcb.gcb_load_fields_3d(self.ctx, desc, Ec, Bc, src=gcb.GCB_DEVICE)
+        torch.cuda.current_stream().synchronize()
+        self.shape = (nz, ny, nx)
+
+
+class GcbPush3(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, E, B, x, y, z, xp, yp, zp, ux, uy, uz, qm, pctx: PushContext3, prm,
+                n_steps: int, checkpoint: int):
+        pctx.load(E, B)
+        n = x.shape[0]
+        st = {k: v.detach().clone() for k, v in zip(_NAMES3, (x, y, z, xp, yp, zp, ux, uy, uz))}
+        st["status"] = torch.zeros(n, dtype=torch.uint8, device=x.device)
+        qmd = qm.detach() if qm is not None else None
+        segs = []
+        done = 0
+        while done < n_steps:
+            k = min(checkpoint, n_steps - done)
+            segs.append(({kk: v.clone() for kk, v in st.items() if kk != "status"}, k))
+            d = dict(st, qm=qmd, id=None)
+            gcb.gcb_push_3d(pctx.ctx, gcb.particles3(d), prm, k)
+            done += k
+        ctx.pctx, ctx.prm, ctx.segs, ctx.qm = pctx, prm, segs, qmd
+        ctx.shape = tuple(E.shape)
+        return tuple(st[k] for k in _NAMES3)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        pctx, prm = ctx.pctx, ctx.prm
+        ref = ctx.segs[0][0]["x"] if ctx.segs else None
+        dev = ref.device if ref is not None else torch.device("cuda")
+        n = ref.shape[0] if ref is not None else 0
+        lam = [g.contiguous() if g is not None else torch.zeros(n, dtype=torch.float64, device=dev)
+               for g in grads]
+        dE = torch.zeros(ctx.shape, dtype=torch.float32, device=dev)
+        dB = torch.zeros(ctx.shape, dtype=torch.float32, device=dev)
+        for start, k in reversed(ctx.segs):
+            st = dict(start, qm=ctx.qm, id=None)
+            st["status"] = torch.zeros(n, dtype=torch.uint8, device=dev)
+            out = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(9)]
+            gcb.gcb_push_backward_3d(pctx.ctx, gcb.particles3(st), prm, k, lam, out,
+                                     [dE[0], dE[1], dE[2]], [dB[0], dB[1], dB[2]])
+            lam = out
+        return (dE.double(), dB.double(), *lam, None, None, None, None, None)
+
+
+def push3(E, B, x, y, z, xp, yp, zp, ux, uy, uz, qm, pctx, prm, n_steps, checkpoint=32):
+    """Differentiable 3D push; returns the final (x, y, z, xp, yp, zp, ux, uy, uz)
+    in input order (no cell sort)."""
+    prm = gcb.gcb_params.from_buffer_copy(prm)
+    prm.sort_every = 0
+    if prm.kernel == gcb.GCB_KERNEL_TILED:
+        prm.kernel = gcb.GCB_KERNEL_AUTO
+    return GcbPush3.apply(E, B, x, y, z, xp, yp, zp, ux, uy, uz, qm, pctx, prm, int(n_steps),
+                          int(checkpoint))
 
 
 class KineticEnergy(torch.autograd.Function):

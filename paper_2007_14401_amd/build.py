@@ -28,6 +28,7 @@ UNITS = {
     "gcb_host.hip": ["-ffp-contract=off"],
     "gcb_push_f64.hip": ["-ffp-contract=off"],
     "gcb_adjoint.hip": ["-ffp-contract=off"],
+    "gcb_adjoint3.hip": ["-ffp-contract=off"],
     "gcb_push_mixed.hip": [],
     "gcb_sort.hip": ["-ffp-contract=off"],
     "gcb_util.hip": ["-ffp-contract=off"],

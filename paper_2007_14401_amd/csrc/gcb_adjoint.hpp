@@ -125,10 +125,15 @@ GCB_HD void gather_vjp(const Acc& acc, Sink& sink, const PushConst& pc, bool yee
 // ---------------------------------------------------------------------------
 // local quantities
 
-GCB_HD void local_vjp(const SampleD& s, const KD& K, const LocalBar& Lb, SampleBar& sb) {
-    const double E[3] = {s.E[0], s.E[1], s.E[2]};
-    const double Bv[3] = {s.B[0], s.B[1], s.B[2]};
-    const double G[2][3] = {{s.dBx[0], s.dBx[1], s.dBx[2]}, {s.dBy[0], s.dBy[1], s.dBy[2]}};
+// Cotangents of E, B and of the ND B-gradient directions G[j][i] = d_j B_i
+// (ND = 2 in the plane, 3 in space) from those of the local quantities.
+template <int ND>
+GCB_HD void local_vjp_nd(const double E[3], const double Bv[3], const double G[ND][3],
+                         const KD& K, const LocalBar& Lb, double Eb[3], double Bb[3],
+                         double Gb[ND][3]) {
+    for (int i = 0; i < 3; ++i) Eb[i] = Bb[i] = 0.0;
+    for (int j = 0; j < ND; ++j)
+        for (int i = 0; i < 3; ++i) Gb[j][i] = 0.0;
     const double B = sqrt((Bv[0] * Bv[0] + Bv[1] * Bv[1]) + Bv[2] * Bv[2]);
     if (B == 0.0) return;   // b, v_E and the curvature terms are held at 0 there
     const double inv_B = 1.0 / B;
@@ -141,14 +146,18 @@ GCB_HD void local_vjp(const SampleD& s, const KD& K, const LocalBar& Lb, SampleB
     const double om = 1.0 - vE2 * K.inv_c2;
     const bool clamped = om < kKappaFloor;
     const double kappa = 1.0 / sqrt(clamped ? kKappaFloor : om);
-    double dn[2], db[2][3], bgb[3], vgb[3];
-    for (int j = 0; j < 2; ++j) {
+    double dn[ND], db[ND][3], bgb[3], vgb[3];
+    for (int j = 0; j < ND; ++j) {
         dn[j] = (b[0] * G[j][0] + b[1] * G[j][1]) + b[2] * G[j][2];
         for (int i = 0; i < 3; ++i) db[j][i] = (G[j][i] - b[i] * dn[j]) * inv_B;
     }
     for (int i = 0; i < 3; ++i) {
-        bgb[i] = b[0] * db[0][i] + b[1] * db[1][i];
-        vgb[i] = vE[0] * db[0][i] + vE[1] * db[1][i];
+        bgb[i] = 0.0;
+        vgb[i] = 0.0;
+        for (int j = 0; j < ND; ++j) {
+            bgb[i] += b[j] * db[j][i];
+            vgb[i] += vE[j] * db[j][i];
+        }
     }
 
     double vEb[3], bb[3], bgbb[3], vgbb[3];
@@ -160,30 +169,28 @@ GCB_HD void local_vjp(const SampleD& s, const KD& K, const LocalBar& Lb, SampleB
     }
     double invBb = Lb.inv_B;
     double Bmb = Lb.B;
-    double dbb[2][3];
-    for (int i = 0; i < 3; ++i) {
-        vEb[0] += vgbb[i] * db[0][i];
-        vEb[1] += vgbb[i] * db[1][i];
-        bb[0] += bgbb[i] * db[0][i];
-        bb[1] += bgbb[i] * db[1][i];
-        dbb[0][i] = vgbb[i] * vE[0] + bgbb[i] * b[0];
-        dbb[1][i] = vgbb[i] * vE[1] + bgbb[i] * b[1];
-    }
-    double dnb[2] = {0.0, 0.0};
-    double Gb[2][3];
-    for (int j = 0; j < 2; ++j)
+    double dbb[ND][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < ND; ++j) {
+            vEb[j] += vgbb[i] * db[j][i];
+            bb[j] += bgbb[i] * db[j][i];
+            dbb[j][i] = vgbb[i] * vE[j] + bgbb[i] * b[j];
+        }
+    double dnb[ND];
+    for (int j = 0; j < ND; ++j) {
+        dnb[j] = 0.0;
         for (int i = 0; i < 3; ++i) {
             Gb[j][i] = dbb[j][i] * inv_B;
             bb[i] -= dbb[j][i] * dn[j] * inv_B;
             dnb[j] -= dbb[j][i] * b[i] * inv_B;
             invBb += dbb[j][i] * (G[j][i] - b[i] * dn[j]);
         }
-    for (int j = 0; j < 2; ++j)
+    }
+    for (int j = 0; j < ND; ++j)
         for (int i = 0; i < 3; ++i) {
             bb[i] += dnb[j] * G[j][i];
             Gb[j][i] += dnb[j] * b[i];
         }
-    double Eb[3];
     for (int i = 0; i < 3; ++i) {
         Eb[i] = Lb.Epar * b[i];
         bb[i] += Lb.Epar * E[i];
@@ -195,7 +202,6 @@ GCB_HD void local_vjp(const SampleD& s, const KD& K, const LocalBar& Lb, SampleB
     }
     const double scb = (vEb[0] * ExB[0] + vEb[1] * ExB[1]) + vEb[2] * ExB[2];
     const double ExBb[3] = {vEb[0] * sc, vEb[1] * sc, vEb[2] * sc};
-    double Bb[3] = {0.0, 0.0, 0.0};
     cross_vjp(E, Bv, ExBb, Eb, Bb);
     invBb += scb * 2.0 * K.c * inv_B;
     for (int i = 0; i < 3; ++i) {
@@ -203,8 +209,14 @@ GCB_HD void local_vjp(const SampleD& s, const KD& K, const LocalBar& Lb, SampleB
         invBb += bb[i] * Bv[i];
     }
     Bmb += -invBb * inv_B * inv_B;
+    for (int i = 0; i < 3; ++i) Bb[i] += Bmb * b[i];
+}
+
+GCB_HD void local_vjp(const SampleD& s, const KD& K, const LocalBar& Lb, SampleBar& sb) {
+    const double G[2][3] = {{s.dBx[0], s.dBx[1], s.dBx[2]}, {s.dBy[0], s.dBy[1], s.dBy[2]}};
+    double Eb[3], Bb[3], Gb[2][3];
+    local_vjp_nd<2>(s.E, s.B, G, K, Lb, Eb, Bb, Gb);
     for (int i = 0; i < 3; ++i) {
-        Bb[i] += Bmb * b[i];
         sb.E[i] += Eb[i];
         sb.B[i] += Bb[i];
         sb.dBx[i] += Gb[0][i];

@@ -1,0 +1,242 @@
+// Reverse-mode derivative of the binary64 3D push: the kernels of
+// gcb_push_backward_3d.  The organisation is the 2D one (gcb_adjoint.hip):
+// the host recomputes the segment's forward steps keeping every step's start
+// state and switch decisions, lists each step's guiding-center particles,
+// then per step in reverse order runs one kernel per regime that maps the
+// cotangents of the step outputs to those of its inputs and records every
+// gather point with its cotangents; after a batch of steps a scatter kernel
+// spreads the recorded cotangents over a binary32 node-interleaved grid.
+// The scatter keeps, per particle and component, the 2x2x2 node stencil of
+// the current cell in registers and writes it (one atomic per non-zero
+// node) when a gather point falls in another cell and at the end: the
+// points of one guiding-center step mostly share a cell.
+// Compiled with -ffp-contract=off like the forward binary64 path.
+#include <hip/hip_runtime.h>
+
+#include "../../include/gcb.h"
+#include "gcb_adjoint3.hpp"
+#include "gcb_internal.h"
+
+namespace gcb {
+namespace {
+
+constexpr int kWG = 128;
+constexpr int kBar3 = 15;   // cotangents per gather point: E, B, dB/dx, dB/dy, dB/dz
+
+// Recorded gather points of one step, structure of arrays over particles:
+// X[s*n + p], Y, Z likewise and bar[(s*15 + c)*n + p] for slot s of particle
+// p, c = E_x..E_z, B_x..B_z, dB/dx (3), dB/dy (3), dB/dz (3).
+struct RecordSink3 {
+    double* X;
+    double* Y;
+    double* Z;
+    float* bar;
+    int64_t n, p;
+    int slot;
+    __device__ void sample(double x, double y, double z, const adj3::SampleBar3& sb) {
+        const int64_t o = (int64_t)slot * n + p;
+        X[o] = x;
+        Y[o] = y;
+        Z[o] = z;
+        float* b = bar + (int64_t)slot * kBar3 * n + p;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            b[c * n] = (float)sb.E[c];
+            b[(3 + c) * n] = (float)sb.B[c];
+            b[(6 + c) * n] = (float)sb.dB[0][c];
+            b[(9 + c) * n] = (float)sb.dB[1][c];
+            b[(12 + c) * n] = (float)sb.dB[2][c];
+        }
+        ++slot;
+    }
+};
+
+// One regime per launch, as in 2D: the guiding-center branch over the
+// step's list (lane t takes entry t), the Boris branch one lane per particle.
+template <bool kYee, bool kBoris>
+__global__ __launch_bounds__(kWG) void k_adjoint3_step(
+    const double* __restrict__ st, const double* __restrict__ qm_arr,
+    const uint8_t* __restrict__ S, const uint32_t* __restrict__ list,
+    const unsigned* __restrict__ count, double* lam, int64_t n, const double* __restrict__ F,
+    PushConst3 pc, RecordSink3 rec) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    int64_t p;
+    if (kBoris) {
+        if (t >= n || S[t] == 0) return;
+        p = t;
+    } else {
+        if (t >= (int64_t)*count) return;
+        p = list[t];
+    }
+    double s[9], l[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        s[c] = st[c * n + p];
+        l[c] = lam[c * n + p];
+    }
+    const double qm = qm_arr ? qm_arr[p] : pc.b.qm;
+    const GlobalAcc3<double> acc{F, pc.b.nx, pc.b.ny, pc.nz};
+    rec.p = p;
+    rec.slot = 0;
+    const Consts3<double> K = make_consts3<double>(pc);
+    if (kBoris)
+        adj3::boris_step_vjp3<kYee>(acc, rec, pc, K, s, qm, l);
+    else
+        adj3::gca_step_vjp3<kYee>(acc, rec, pc, K, s, qm, l);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) lam[c * n + p] = l[c];
+}
+
+constexpr int kScatterWG = 256;
+constexpr int kNoOrigin = -0x40000000;   // stencil not placed yet
+
+// Node cotangents of the gather points recorded over a batch of nb steps
+// (per step one Boris point or `slots` guiding-center points per particle;
+// step b of the batch at records (b*slots + q)).
+template <bool kYee>
+__global__ __launch_bounds__(kScatterWG) void k_scatter3_batch(
+    const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
+    const float* __restrict__ bar, const uint8_t* __restrict__ S, int64_t n, int nb, int slots,
+    PushConst3 pc, float* grad) {
+    const int64_t p = (int64_t)blockIdx.x * kScatterWG + threadIdx.x;
+    if (p >= n) return;
+    const double id[3] = {pc.b.inv_dx, pc.b.inv_dy, pc.inv_dz};
+    const int nn[3] = {pc.b.nx, pc.b.ny, pc.nz};
+    float w[6][8];
+    int org[6][3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        org[k][0] = org[k][1] = org[k][2] = kNoOrigin;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[k][e] = 0.0f;
+    }
+    auto flush = [&](int k) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (w[k][e] != 0.0f) {
+                const int i = wrap_index(org[k][0] + (e & 1), nn[0]);
+                const int j = wrap_index(org[k][1] + ((e >> 1) & 1), nn[1]);
+                const int l = wrap_index(org[k][2] + (e >> 2), nn[2]);
+                atomicAdd(&grad[(((size_t)l * nn[1] + j) * nn[0] + i) * 6 + k], w[k][e]);
+                w[k][e] = 0.0f;
+            }
+        }
+    };
+    for (int b = nb - 1; b >= 0; --b) {
+        const int ns = S[(int64_t)b * n + p] ? 1 : slots;
+        for (int q = 0; q < ns; ++q) {
+            const int64_t r = (int64_t)b * slots + q;
+            const double g[3] = {X[r * n + p] * id[0], Y[r * n + p] * id[1],
+                                 Z[r * n + p] * id[2]};
+            const float* bq = bar + r * kBar3 * n + p;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const double vb = (double)bq[k * n];
+                double gb[3] = {0.0, 0.0, 0.0};
+                if (k >= 3) {
+                    gb[0] = (double)bq[(3 + k) * n];
+                    gb[1] = (double)bq[(6 + k) * n];
+                    gb[2] = (double)bq[(9 + k) * n];
+                }
+                if (vb == 0.0 && gb[0] == 0.0 && gb[1] == 0.0 && gb[2] == 0.0) continue;
+                int c[3];
+                double W0[3], W1[3], s[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double off = kYee ? (((kYee3Set[k] >> a) & 1) ? 0.5 : 0.0)
+                                            : (a < 2 ? pc.b.stagger[k][a] : pc.sz[k]);
+                    const double xi = g[a] - off;
+                    const double f = floor(xi);
+                    c[a] = (int)f;
+                    W1[a] = xi - f;
+                    W0[a] = 1.0 - W1[a];
+                    s[a] = id[a];
+                }
+                if (c[0] != org[k][0] || c[1] != org[k][1] || c[2] != org[k][2]) {
+                    flush(k);
+                    org[k][0] = c[0];
+                    org[k][1] = c[1];
+                    org[k][2] = c[2];
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const double wx = (e & 1) ? W1[0] : W0[0];
+                    const double wy = ((e >> 1) & 1) ? W1[1] : W0[1];
+                    const double wz = (e >> 2) ? W1[2] : W0[2];
+                    const double sx = (e & 1) ? s[0] : -s[0];
+                    const double sy = ((e >> 1) & 1) ? s[1] : -s[1];
+                    const double sz = (e >> 2) ? s[2] : -s[2];
+                    w[k][e] += (float)(vb * (wx * wy * wz) + gb[0] * (sx * wy * wz) +
+                                       gb[1] * (wx * sy * wz) + gb[2] * (wx * wy * sz));
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) flush(k);
+}
+
+struct RecordArrays3 {
+    double* X;
+    double* Y;
+    double* Z;
+    float* bar;
+};
+
+RecordArrays3 record_arrays3(void* records, int64_t n, int slots, int batch) {
+    RecordArrays3 r;
+    const size_t m = (size_t)batch * slots * n;
+    r.X = static_cast<double*>(records);
+    r.Y = r.X + m;
+    r.Z = r.Y + m;
+    r.bar = reinterpret_cast<float*>(r.Z + m);
+    return r;
+}
+
+}  // namespace
+
+size_t adjoint3_record_bytes(int64_t n, int n_iter, int steps) {
+    return (size_t)steps * adjoint_slots(n_iter) * (size_t)n *
+           (3 * sizeof(double) + kBar3 * sizeof(float));
+}
+
+hipError_t launch_adjoint3_step(const Adjoint3Launch& L, double* lam, const PushConst3& pc,
+                                hipStream_t stream) {
+    if (L.n == 0) return hipSuccess;
+    const int slots = adjoint_slots(pc.b.n_iter);
+    const RecordArrays3 ra = record_arrays3(L.records, L.n, slots, L.batch);
+    const size_t off = (size_t)L.batch_slot * slots * L.n;
+    const RecordSink3 rec{ra.X + off, ra.Y + off, ra.Z + off, ra.bar + kBar3 * off, L.n, 0, 0};
+    const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
+    if (L.yee) {
+        hipLaunchKernelGGL((k_adjoint3_step<true, false>), dim3(blocks), dim3(kWG), 0, stream,
+                           L.state, L.qm, L.strace, L.list, L.count, lam, L.n, L.fields, pc, rec);
+        hipLaunchKernelGGL((k_adjoint3_step<true, true>), dim3(blocks), dim3(kWG), 0, stream,
+                           L.state, L.qm, L.strace, L.list, L.count, lam, L.n, L.fields, pc, rec);
+    } else {
+        hipLaunchKernelGGL((k_adjoint3_step<false, false>), dim3(blocks), dim3(kWG), 0, stream,
+                           L.state, L.qm, L.strace, L.list, L.count, lam, L.n, L.fields, pc, rec);
+        hipLaunchKernelGGL((k_adjoint3_step<false, true>), dim3(blocks), dim3(kWG), 0, stream,
+                           L.state, L.qm, L.strace, L.list, L.count, lam, L.n, L.fields, pc, rec);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint3_scatter(const Adjoint3Launch& L, const uint8_t* strace_first, int nb,
+                                   const PushConst3& pc, hipStream_t stream) {
+    if (L.n == 0 || nb <= 0) return hipSuccess;
+    const int slots = adjoint_slots(pc.b.n_iter);
+    const RecordArrays3 ra = record_arrays3(L.records, L.n, slots, L.batch);
+    const unsigned blocks = (unsigned)((L.n + kScatterWG - 1) / kScatterWG);
+    if (L.yee)
+        hipLaunchKernelGGL((k_scatter3_batch<true>), dim3(blocks), dim3(kScatterWG), 0, stream,
+                           ra.X, ra.Y, ra.Z, ra.bar, strace_first, L.n, nb, slots, pc,
+                           L.grad_fields);
+    else
+        hipLaunchKernelGGL((k_scatter3_batch<false>), dim3(blocks), dim3(kScatterWG), 0, stream,
+                           ra.X, ra.Y, ra.Z, ra.bar, strace_first, L.n, nb, slots, pc,
+                           L.grad_fields);
+    return hipGetLastError();
+}
+
+}  // namespace gcb

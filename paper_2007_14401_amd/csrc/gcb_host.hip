@@ -1141,6 +1141,149 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t 
     return stats_end(ctx, p->status, p->n, stats, stream);
 }
 
+int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_params* prm,
+                         int32_t n_steps, const double* const lam_end[9],
+                         double* const lam_start[9], float* const dE[3], float* const dB[3],
+                         void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    if (!start) return fail(ctx, GCB_EINVAL, "particles is NULL");
+    int rc;
+    if ((rc = validate_params(ctx, prm))) return rc;
+    gcb_particles view{start->n,  start->x,  start->y,  start->xp, start->yp, start->ux,
+                       start->uy, start->uz, start->qm, start->id, start->status};
+    if ((rc = validate_particles(ctx, &view, prm))) return rc;
+    if (start->n > 0 && (!start->z || !start->zp))
+        return fail(ctx, GCB_EINVAL, "particle arrays z, zp must be non-NULL");
+    if (((uintptr_t)start->z | (uintptr_t)start->zp) & 7)
+        return fail(ctx, GCB_EINVAL, "double arrays must be 8-byte aligned");
+    if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
+    if (!lam_end || !lam_start || !dE || !dB)
+        return fail(ctx, GCB_EINVAL, "lam_end, lam_start, dE and dB must be non-NULL");
+    const int64_t n = start->n;
+    for (int c = 0; c < 9; ++c)
+        if (n > 0 && (!lam_end[c] || !lam_start[c]))
+            return fail(ctx, GCB_EINVAL, "adjoint array %d is NULL", c);
+    for (int c = 0; c < 3; ++c)
+        if (!dE[c] || !dB[c]) return fail(ctx, GCB_EINVAL, "dE/dB component %d is NULL", c);
+    if (!ctx->have_f3) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields_3d was not called");
+    if (prm->form != GCB_FORM_F64 || ctx->dtype3 != GCB_F64)
+        return fail(ctx, GCB_EUNSUPPORTED, "the adjoint needs GCB_FORM_F64 and binary64 fields");
+    if (prm->n_iter > 8)
+        return fail(ctx, GCB_EUNSUPPORTED, "the adjoint supports n_iter <= 8");
+    if ((rc = reject_push_options(ctx, prm))) return rc;
+    GCB_HIP(hipSetDevice(ctx->device));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    constexpr int kS = 9;   // state arrays: x, y, z, xp, yp, zp, ux, uy, uz
+    const size_t nd = (size_t)n * sizeof(double);
+    const size_t nodes = (size_t)ctx->n3[0] * ctx->n3[1] * ctx->n3[2];
+    if ((rc = ensure(ctx, ctx->adj_states, (size_t)n_steps * kS * nd))) return rc;
+    if ((rc = ensure(ctx, ctx->adj_trace, (size_t)n_steps * n))) return rc;
+    if ((rc = ensure(ctx, ctx->adj_lists, (size_t)n_steps * (n + 1) * sizeof(uint32_t))))
+        return rc;
+    if ((rc = ensure(ctx, ctx->adj_lam, kS * nd))) return rc;
+    if ((rc = ensure(ctx, ctx->adj_work, kS * nd + (size_t)n))) return rc;
+    if ((rc = ensure(ctx, ctx->adj_grad, nodes * 6 * sizeof(float)))) return rc;
+    constexpr int kMaxBatch = 8;
+    constexpr size_t kRecordBudget = 32ull << 30;
+    const size_t per_step = adjoint3_record_bytes(n, prm->n_iter, 1);
+    int batch = per_step > 0 ? (int)std::min<size_t>(kMaxBatch, kRecordBudget / per_step) : 1;
+    batch = std::max(1, std::min(batch, std::max(1, (int)n_steps)));
+    if ((rc = ensure(ctx, ctx->adj_samples, adjoint3_record_bytes(n, prm->n_iter, batch))))
+        return rc;
+    double* work = static_cast<double*>(ctx->adj_work.ptr);
+    uint8_t* wstatus = reinterpret_cast<uint8_t*>(work + kS * (size_t)n);
+    double* states = static_cast<double*>(ctx->adj_states.ptr);
+    uint8_t* trace = static_cast<uint8_t*>(ctx->adj_trace.ptr);
+    double* lam = static_cast<double*>(ctx->adj_lam.ptr);
+    float* grad = static_cast<float*>(ctx->adj_grad.ptr);
+    const double* src[kS] = {start->x,  start->y,  start->z,
+                             start->xp, start->yp, start->zp,
+                             static_cast<const double*>(start->ux),
+                             static_cast<const double*>(start->uy),
+                             static_cast<const double*>(start->uz)};
+    Timer t(ctx, stream, GCB_TIMER_BACKWARD);
+    if (n > 0) {
+        for (int c = 0; c < kS; ++c)
+            GCB_HIP(hipMemcpyAsync(work + c * (size_t)n, src[c], nd, hipMemcpyDeviceToDevice,
+                                   stream));
+        GCB_HIP(hipMemsetAsync(wstatus, 0, (size_t)n, stream));
+    }
+    ParticlePtrs3<double> w;
+    w.b.x = work;
+    w.b.y = work + n;
+    w.z = work + 2 * n;
+    w.b.xp = work + 3 * n;
+    w.b.yp = work + 4 * n;
+    w.zp = work + 5 * n;
+    w.b.ux = work + 6 * n;
+    w.b.uy = work + 7 * n;
+    w.b.uz = work + 8 * n;
+    w.b.qm = start->qm;
+    w.b.id = nullptr;
+    w.b.status = wstatus;
+    const PushConst3 pc = make_const3(ctx, prm);
+    // forward recomputation, keeping each step's start state and decisions
+    for (int32_t s = 0; s < n_steps && n > 0; ++s) {
+        GCB_HIP(hipMemcpyAsync(states + (size_t)s * kS * n, work, kS * nd,
+                               hipMemcpyDeviceToDevice, stream));
+        Push3Launch L;
+        L.kind = PushKind::Global;
+        L.yee = ctx->yee3;
+        L.fields = ctx->fields3.ptr;
+        L.n = n;
+        L.tile_start = nullptr;
+        L.geom = TileGeom3{};
+        L.trace = trace + (size_t)s * n;
+        L.replay = false;
+        L.stats = nullptr;
+        L.steps = 1;
+        GCB_HIP(launch_push3_f64(L, w, w, pc, stream));
+    }
+    uint32_t* lists = static_cast<uint32_t*>(ctx->adj_lists.ptr);
+    unsigned* counts = reinterpret_cast<unsigned*>(lists + (size_t)n_steps * n);
+    if (n > 0 && n_steps > 0) {
+        GCB_HIP(hipMemsetAsync(counts, 0, (size_t)n_steps * sizeof(unsigned), stream));
+        GCB_HIP(launch_gca_lists(trace, n, n_steps, lists, counts, stream));
+    }
+    // reverse sweep
+    for (int c = 0; c < kS && n > 0; ++c)
+        GCB_HIP(hipMemcpyAsync(lam + c * (size_t)n, lam_end[c], nd, hipMemcpyDeviceToDevice,
+                               stream));
+    GCB_HIP(hipMemsetAsync(grad, 0, nodes * 6 * sizeof(float), stream));
+    for (int32_t s_hi = n_steps; s_hi > 0 && n > 0; s_hi -= batch) {
+        const int32_t s_lo = std::max<int32_t>(0, s_hi - batch);
+        Adjoint3Launch A;
+        A.yee = ctx->yee3;
+        A.fields = static_cast<const double*>(ctx->fields3.ptr);
+        A.n = n;
+        A.qm = start->qm;
+        A.grad_fields = grad;
+        A.records = ctx->adj_samples.ptr;
+        A.batch = batch;
+        for (int32_t s = s_hi - 1; s >= s_lo; --s) {
+            A.state = states + (size_t)s * kS * n;
+            A.strace = trace + (size_t)s * n;
+            A.list = lists + (size_t)s * n;
+            A.count = counts + s;
+            A.batch_slot = s - s_lo;
+            GCB_HIP(launch_adjoint3_step(A, lam, pc, stream));
+        }
+        GCB_HIP(launch_adjoint3_scatter(A, trace + (size_t)s_lo * n, s_hi - s_lo, pc, stream));
+    }
+    for (int c = 0; c < kS && n > 0; ++c)
+        GCB_HIP(hipMemcpyAsync(lam_start[c], lam + c * (size_t)n, nd, hipMemcpyDeviceToDevice,
+                               stream));
+    if (n_steps == 0 && n > 0)
+        for (int c = 0; c < kS; ++c)
+            GCB_HIP(hipMemcpyAsync(lam_start[c], lam_end[c], nd, hipMemcpyDeviceToDevice,
+                                   stream));
+    // the 3D node-interleaved layout is the 2D one with nx columns and ny*nz rows
+    float* const outs[6] = {dE[0], dE[1], dE[2], dB[0], dB[1], dB[2]};
+    GCB_HIP(launch_deinterleave_add(grad, ctx->n3[0], ctx->n3[1] * ctx->n3[2], outs, stream));
+    t.done();
+    return GCB_OK;
+}
+
 int gcb_kinetic_energy(gcb_ctx* ctx, const gcb_particles* p, const gcb_params* prm,
                        double* out, double* const lam_u[3], void* stream_) {
     if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");

@@ -175,6 +175,29 @@ hipError_t launch_adjoint_scatter(const AdjointLaunch& L, const uint8_t* strace_
 hipError_t launch_deinterleave_add(const float* grad_fields, int nx, int ny,
                                    float* const out[6], hipStream_t stream);
 
+// 3D adjoint (gcb_adjoint3.hip): the 2D organisation with 9-array states
+// (x, y, z, xp, yp, zp, ux, uy, uz) and 3D gather points.
+struct Adjoint3Launch {
+    bool yee;               // 3D Yee offsets
+    const double* fields;   // node-interleaved binary64 3D fields
+    int64_t n;
+    const double* state;    // the step's saved start state: 9 arrays of n
+    const double* qm;       // nullable
+    const uint8_t* strace;  // per-particle S of this step (1 = Boris)
+    const uint32_t* list;   // this step's guiding-center list
+    const unsigned* count;  // its length
+    float* grad_fields;     // node-interleaved float gradient accumulators
+    void* records;          // adjoint3_record_bytes(n, n_iter, batch) of scratch
+    int batch;
+    int batch_slot;
+};
+
+size_t adjoint3_record_bytes(int64_t n, int n_iter, int steps);
+hipError_t launch_adjoint3_step(const Adjoint3Launch& L, double* lam /*9*n in/out*/,
+                                const PushConst3& pc, hipStream_t stream);
+hipError_t launch_adjoint3_scatter(const Adjoint3Launch& L, const uint8_t* strace_first, int nb,
+                                   const PushConst3& pc, hipStream_t stream);
+
 // curved-spacetime push (gcb_gr.hip)
 struct GrPtrs {
     double *r, *th, *ph;

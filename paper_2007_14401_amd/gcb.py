@@ -124,6 +124,9 @@ def _load():
                                          C.POINTER(P * 3), C.c_int32, P]),
         "gcb_push_3d": (C.c_int, [P, C.POINTER(gcb_particles3), C.POINTER(gcb_params),
                                   C.c_int32, P, C.POINTER(gcb_stats), P]),
+        "gcb_push_backward_3d": (C.c_int, [P, C.POINTER(gcb_particles3), C.POINTER(gcb_params),
+                                           C.c_int32, C.POINTER(P * 9), C.POINTER(P * 9),
+                                           C.POINTER(P * 3), C.POINTER(P * 3), P]),
         "gcb_set_timing": (C.c_int, [P, C.c_int32]),
         "gcb_get_timing": (C.c_int, [P, C.POINTER(C.c_double * GCB_NTIMERS),
                                      C.POINTER(C.c_int64 * GCB_NTIMERS)]),
@@ -138,7 +141,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("gcb_create", "gcb_destroy", "gcb_last_error", "gcb_load_fields", "gcb_push",
             "gcb_push_backward", "gcb_kinetic_energy", "gcb_set_timing", "gcb_get_timing",
-            "gcb_load_fields_gr", "gcb_push_gr", "gcb_load_fields_3d", "gcb_push_3d")
+            "gcb_load_fields_gr", "gcb_push_gr", "gcb_load_fields_3d", "gcb_push_3d",
+            "gcb_push_backward_3d")
 
 
 def lib():
@@ -365,6 +369,19 @@ def gcb_push_3d(ctx, parts: gcb_particles3, prm: gcb_params, n_steps: int, s_tra
     if st is None:
         return None
     return {k: getattr(st, k) for k, _ in gcb_stats._fields_}
+
+
+def gcb_push_backward_3d(ctx, start: gcb_particles3, prm: gcb_params, n_steps: int, lam_end,
+                         lam_start, dE, dB, stream=None) -> None:
+    """lam_end, lam_start: nine device arrays (x, y, z, xp, yp, zp, ux, uy, uz);
+    dE, dB: three device float arrays of nz*ny*nx elements each (accumulated)."""
+    le = (C.c_void_p * 9)(*[_ptr(a) for a in lam_end])
+    ls = (C.c_void_p * 9)(*[_ptr(a) for a in lam_start])
+    de = (C.c_void_p * 3)(*[_ptr(a) for a in dE])
+    db = (C.c_void_p * 3)(*[_ptr(a) for a in dB])
+    _check(_lib.gcb_push_backward_3d(ctx, C.byref(start), C.byref(prm), int(n_steps),
+                                     C.byref(le), C.byref(ls), C.byref(de), C.byref(db),
+                                     _stream_ptr(stream)), ctx)
 
 
 def gcb_set_timing(ctx, enabled: bool) -> None:

@@ -46,6 +46,8 @@ def test_null_arguments_rejected_without_device():
     assert lib.gcb_push_gr(None, None, None, 1, None, None, None) == gcb.GCB_EINVAL
     assert lib.gcb_load_fields_3d(None, None, None, None, 0, None) == gcb.GCB_EINVAL
     assert lib.gcb_push_3d(None, None, None, 1, None, None, None) == gcb.GCB_EINVAL
+    assert lib.gcb_push_backward_3d(None, None, None, 1, None, None, None, None,
+                                    None) == gcb.GCB_EINVAL
     lib.gcb_destroy(None)
 
 
