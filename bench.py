@@ -180,6 +180,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--adjoint-c4-steps", type=int, default=512)
+    ap.add_argument("--adjoint3-steps", type=int, default=32)
     ap.add_argument("--no-gr", action="store_true")
     ap.add_argument("--gr-steps", type=int, default=40)
     ap.add_argument("--gr-warmup", type=int, default=4)
@@ -305,6 +306,58 @@ def main():
                     "forward_push_ms_per_step": ms[gcb.GCB_TIMER_PUSH] / max(1, steps),
                     "backward_ms_per_step": ms[gcb.GCB_TIMER_BACKWARD] / max(1, steps),
                     "kernel": "k_push_global + k_adjoint_step (unsorted, binary64)",
+                    "loss": float(L)}
+        finally:
+            pctx.close()
+            torch.cuda.empty_cache()
+
+    def time_fwd_adjoint3(steps: int, checkpoint: int):
+        """Forward + reverse pass of the differentiable 3D push on the 3D
+        workload (harris3d128, 1e7 particles; loss: mean final kinetic
+        energy), initial positions cell-sorted (row-major cells)."""
+        from paper_2007_14401_amd import autograd as A
+        from workloads import make_config3
+        c3 = make_config3("harris3d128")
+        log(f"[bench] 3d fwd+adjoint: generating {c3.name}, n={c3.n}")
+        F3 = c3.fields()
+        e3 = c3.particles()
+        pctx = A.PushContext3(0, (c3.dx, c3.dy, c3.dz), c3.stagger)
+        try:
+            Ft = torch.as_tensor(F3, dtype=torch.float64, device=dev)
+            del F3
+            E = Ft[:3].contiguous().requires_grad_(True)
+            B = Ft[3:].contiguous().requires_grad_(True)
+            del Ft
+            names = ("x", "y", "z", "xp", "yp", "zp", "ux", "uy", "uz")
+            cell = ((np.floor(e3.z / c3.dz).astype(np.int64) * c3.ny
+                     + np.floor(e3.y / c3.dy).astype(np.int64)) * c3.nx
+                    + np.floor(e3.x / c3.dx).astype(np.int64))
+            order = np.argsort(cell, kind="stable")
+            st = {k: torch.as_tensor(getattr(e3, k)[order], dtype=torch.float64, device=dev)
+                  .requires_grad_(True) for k in names}
+            prm = gcb.params(dt=c3.dt, c=c3.c, qm=c3.qm, f_rho=c3.f_rho, f_E=c3.f_E,
+                             curvature=c3.curvature, n_iter=c3.n_iter)
+            out = A.push3(E, B, *[st[k] for k in names], None, pctx, prm, 2, checkpoint)
+            A.kinetic_energy(out[6], out[7], out[8], pctx, prm).backward()
+            for v in list(st.values()) + [E, B]:
+                v.grad = None
+            gcb.gcb_set_timing(pctx.ctx, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = A.push3(E, B, *[st[k] for k in names], None, pctx, prm, steps, checkpoint)
+            L = A.kinetic_energy(out[6], out[7], out[8], pctx, prm)
+            L.backward()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ms, cnt = gcb.gcb_get_timing(pctx.ctx)
+            gcb.gcb_set_timing(pctx.ctx, False)
+            log(f"[bench] 3d fwd+adjoint: {steps} steps in {t1 - t0:.3f} s; kernel ms {ms}")
+            return {"value": e3.n * steps / (t1 - t0), "unit": "particle-steps/s",
+                    "workload": f"{c3.name}: {c3.nx}x{c3.ny}x{c3.nz}, {e3.n} particles",
+                    "steps": steps, "checkpoint": checkpoint, "seconds": t1 - t0,
+                    "forward_push_ms_per_step": ms[gcb.GCB_TIMER_PUSH] / max(1, steps),
+                    "backward_ms_per_step": ms[gcb.GCB_TIMER_BACKWARD] / max(1, steps),
+                    "kernel": "k_push3_global + k_adjoint3_step (unsorted, binary64)",
                     "loss": float(L)}
         finally:
             pctx.close()
@@ -483,6 +536,8 @@ def main():
             log(f"[bench] differentiation workload {c4.name}: n={c4.n}")
             forms["fwd_adjoint_c4"] = time_fwd_adjoint(a.adjoint_c4_steps, 32, wcfg=c4,
                                                        F=c4.fields(), ens=c4.particles())
+        if a.adjoint3_steps > 0 and not a.no_3d:
+            forms["fwd_adjoint_3d"] = time_fwd_adjoint3(a.adjoint3_steps, 32)
 
     copy_gbs = copy_bandwidth(dev)
     if a.copy_calib:

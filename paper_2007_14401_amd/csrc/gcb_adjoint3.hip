@@ -6,10 +6,10 @@
 // cotangents of the step outputs to those of its inputs and records every
 // gather point with its cotangents; after a batch of steps a scatter kernel
 // spreads the recorded cotangents over a binary32 node-interleaved grid.
-// The scatter keeps, per particle and component, the 2x2x2 node stencil of
-// the current cell in registers and writes it (one atomic per non-zero
-// node) when a gather point falls in another cell and at the end: the
-// points of one guiding-center step mostly share a cell.
+// The scatter sums, per particle and component, the points of a batch in a
+// 4x4x4 node window of its own in LDS and writes a window (one atomic per
+// non-zero node) only when a point leaves it and at the end: a particle
+// moves at most c dt per step, so most windows are written once per batch.
 // Compiled with -ffp-contract=off like the forward binary64 path.
 #include <hip/hip_runtime.h>
 
@@ -87,50 +87,54 @@ __global__ __launch_bounds__(kWG) void k_adjoint3_step(
     for (int c = 0; c < 9; ++c) lam[c * n + p] = l[c];
 }
 
-constexpr int kScatterWG = 256;
-constexpr int kNoOrigin = -0x40000000;   // stencil not placed yet
+constexpr int kScatterWG = 128;
+constexpr int kWin = 4;                        // nodes per axis of a window
+constexpr int kWin3 = kWin * kWin * kWin;
+constexpr int kNoOrigin = -0x40000000;         // window not placed yet
 
 // Node cotangents of the gather points recorded over a batch of nb steps
 // (per step one Boris point or `slots` guiding-center points per particle;
-// step b of the batch at records (b*slots + q)).
+// step b of the batch at records (b*slots + q)).  One component at a time,
+// each lane sums its particle's points in a 4x4x4 node window of its own in
+// LDS (entry e of lane t at e*kScatterWG + t); the window covers the 3x3x3
+// cells around the cell it was placed on, and moves (after writing its
+// non-zero nodes with one atomic each) when a point's cell leaves them.
 template <bool kYee>
 __global__ __launch_bounds__(kScatterWG) void k_scatter3_batch(
     const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
     const float* __restrict__ bar, const uint8_t* __restrict__ S, int64_t n, int nb, int slots,
     PushConst3 pc, float* grad) {
+    __shared__ float win[kWin3 * kScatterWG];
     const int64_t p = (int64_t)blockIdx.x * kScatterWG + threadIdx.x;
-    if (p >= n) return;
+    if (p >= n) return;   // no barrier below: every lane uses only its own entries
+    float* mine = win + threadIdx.x;
     const double id[3] = {pc.b.inv_dx, pc.b.inv_dy, pc.inv_dz};
     const int nn[3] = {pc.b.nx, pc.b.ny, pc.nz};
-    float w[6][8];
-    int org[6][3];
-#pragma unroll
+    for (int e = 0; e < kWin3; ++e) mine[e * kScatterWG] = 0.0f;
     for (int k = 0; k < 6; ++k) {
-        org[k][0] = org[k][1] = org[k][2] = kNoOrigin;
+        double off[3];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) w[k][e] = 0.0f;
-    }
-    auto flush = [&](int k) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            if (w[k][e] != 0.0f) {
-                const int i = wrap_index(org[k][0] + (e & 1), nn[0]);
-                const int j = wrap_index(org[k][1] + ((e >> 1) & 1), nn[1]);
-                const int l = wrap_index(org[k][2] + (e >> 2), nn[2]);
-                atomicAdd(&grad[(((size_t)l * nn[1] + j) * nn[0] + i) * 6 + k], w[k][e]);
-                w[k][e] = 0.0f;
+        for (int a = 0; a < 3; ++a)
+            off[a] = kYee ? (((kYee3Set[k] >> a) & 1) ? 0.5 : 0.0)
+                          : (a < 2 ? pc.b.stagger[k][a] : pc.sz[k]);
+        int org[3] = {kNoOrigin, kNoOrigin, kNoOrigin};
+        auto flush = [&]() {
+            for (int e = 0; e < kWin3; ++e) {
+                const float v = mine[e * kScatterWG];
+                if (v != 0.0f) {
+                    const int i = wrap_index(org[0] + (e % kWin), nn[0]);
+                    const int j = wrap_index(org[1] + (e / kWin) % kWin, nn[1]);
+                    const int l = wrap_index(org[2] + e / (kWin * kWin), nn[2]);
+                    atomicAdd(&grad[(((size_t)l * nn[1] + j) * nn[0] + i) * 6 + k], v);
+                    mine[e * kScatterWG] = 0.0f;
+                }
             }
-        }
-    };
-    for (int b = nb - 1; b >= 0; --b) {
-        const int ns = S[(int64_t)b * n + p] ? 1 : slots;
-        for (int q = 0; q < ns; ++q) {
-            const int64_t r = (int64_t)b * slots + q;
-            const double g[3] = {X[r * n + p] * id[0], Y[r * n + p] * id[1],
-                                 Z[r * n + p] * id[2]};
-            const float* bq = bar + r * kBar3 * n + p;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
+        };
+        for (int b = nb - 1; b >= 0; --b) {
+            const int ns = S[(int64_t)b * n + p] ? 1 : slots;
+            for (int q = 0; q < ns; ++q) {
+                const int64_t r = (int64_t)b * slots + q;
+                const float* bq = bar + r * kBar3 * n + p;
                 const double vb = (double)bq[k * n];
                 double gb[3] = {0.0, 0.0, 0.0};
                 if (k >= 3) {
@@ -139,41 +143,47 @@ __global__ __launch_bounds__(kScatterWG) void k_scatter3_batch(
                     gb[2] = (double)bq[(9 + k) * n];
                 }
                 if (vb == 0.0 && gb[0] == 0.0 && gb[1] == 0.0 && gb[2] == 0.0) continue;
+                const double g[3] = {X[r * n + p] * id[0], Y[r * n + p] * id[1],
+                                     Z[r * n + p] * id[2]};
                 int c[3];
-                double W0[3], W1[3], s[3];
+                double W1[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const double off = kYee ? (((kYee3Set[k] >> a) & 1) ? 0.5 : 0.0)
-                                            : (a < 2 ? pc.b.stagger[k][a] : pc.sz[k]);
-                    const double xi = g[a] - off;
+                    const double xi = g[a] - off[a];
                     const double f = floor(xi);
                     c[a] = (int)f;
                     W1[a] = xi - f;
-                    W0[a] = 1.0 - W1[a];
-                    s[a] = id[a];
                 }
-                if (c[0] != org[k][0] || c[1] != org[k][1] || c[2] != org[k][2]) {
-                    flush(k);
-                    org[k][0] = c[0];
-                    org[k][1] = c[1];
-                    org[k][2] = c[2];
+                // offsets in unsigned arithmetic: any cell index is allowed
+                unsigned d[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) d[a] = (unsigned)c[a] - (unsigned)org[a];
+                if (d[0] > 2u || d[1] > 2u || d[2] > 2u) {
+                    flush();
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        org[a] = (int)((unsigned)c[a] - 1u);
+                        d[a] = 1u;
+                    }
                 }
+                const int e0 = (int)d[0] + kWin * ((int)d[1] + kWin * (int)d[2]);
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const double wx = (e & 1) ? W1[0] : W0[0];
-                    const double wy = ((e >> 1) & 1) ? W1[1] : W0[1];
-                    const double wz = (e >> 2) ? W1[2] : W0[2];
-                    const double sx = (e & 1) ? s[0] : -s[0];
-                    const double sy = ((e >> 1) & 1) ? s[1] : -s[1];
-                    const double sz = (e >> 2) ? s[2] : -s[2];
-                    w[k][e] += (float)(vb * (wx * wy * wz) + gb[0] * (sx * wy * wz) +
-                                       gb[1] * (wx * sy * wz) + gb[2] * (wx * wy * sz));
+                    const int ox = e & 1, oy = (e >> 1) & 1, oz = e >> 2;
+                    const double wx = ox ? W1[0] : 1.0 - W1[0];
+                    const double wy = oy ? W1[1] : 1.0 - W1[1];
+                    const double wz = oz ? W1[2] : 1.0 - W1[2];
+                    const double sx = ox ? id[0] : -id[0];
+                    const double sy = oy ? id[1] : -id[1];
+                    const double sz = oz ? id[2] : -id[2];
+                    const float v = (float)(vb * (wx * wy * wz) + gb[0] * (sx * wy * wz) +
+                                            gb[1] * (wx * sy * wz) + gb[2] * (wx * wy * sz));
+                    mine[(e0 + ox + kWin * (oy + kWin * oz)) * kScatterWG] += v;
                 }
             }
         }
+        flush();
     }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) flush(k);
 }
 
 struct RecordArrays3 {
