@@ -114,5 +114,11 @@ def test_adjoint3_argument_checks():
         torch.cuda.synchronize()
         assert torch.equal(out[6], lam[6])
         assert all(float(gr.abs().max()) == 0.0 for gr in grid)
+        # no particles: nothing to do, grids untouched
+        t0 = {k: v[:0] for k, v in t.items()}
+        gcb.gcb_push_backward_3d(ctx, gcb.particles3(t0), gcb.params(), 3,
+                                 [v[:0] for v in lam], [v[:0] for v in out], grid[:3], grid[3:])
+        torch.cuda.synchronize()
+        assert all(float(gr.abs().max()) == 0.0 for gr in grid)
     finally:
         gcb.gcb_destroy(ctx)
