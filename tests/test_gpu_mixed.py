@@ -86,9 +86,9 @@ def test_mixed_deterministic():
         assert np.array_equal(outs[0][k].view(np.uint8), outs[1][k].view(np.uint8)), k
 
 
-def _report(n_total, steps, sample_n=2000):
+def _report(n_total, steps, sample_n=2000, name="harris4096"):
     from paper_2007_14401_amd import state
-    cfg = make_config("harris4096")
+    cfg = make_config(name)
     log(f"mixed report: generating {n_total} particles")
     F = cfg.fields()
     ens = cfg.particles(n=n_total)
@@ -112,7 +112,7 @@ def _report(n_total, steps, sample_n=2000):
     first = np.argmax(trs != rtr.numpy(), axis=0)
     ever = (trs != rtr.numpy()).any(axis=0)
     rep = {
-        "particles": n_total, "steps": steps, "sample": sample_n,
+        "workload": name, "particles": n_total, "steps": steps, "sample": sample_n,
         "u_rel_err": {"median": float(np.median(du)), "p99": float(np.quantile(du, 0.99)),
                       "max": float(du.max())},
         "x_abs_err_cells": {"median": float(np.median(dx)), "p99": float(np.quantile(dx, 0.99)),
@@ -124,7 +124,8 @@ def _report(n_total, steps, sample_n=2000):
     }
     log("mixed report " + json.dumps(rep))
     os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", f"mixed_report_{n_total}.json"), "w") as f:
+    with open(os.path.join(ROOT, "gpurun_out", f"mixed_report_{name}_{n_total}.json"),
+              "w") as f:
         json.dump(rep, f, indent=1)
     return rep
 
@@ -132,6 +133,15 @@ def _report(n_total, steps, sample_n=2000):
 def test_mixed_precision_report_1e7():
     """Full-size workload (4096^2, 1e7 particles, 100 steps), mixed form."""
     rep = _report(10_000_000, 100)
+    assert rep["u_rel_err"]["median"] <= 1e-3
+    assert rep["switch_mismatch_fraction_particle_steps"] <= 1e-2
+
+
+def test_mixed_precision_report_harris256():
+    """The small workload (256^2, 1e4 electrons, Maxwell-Juttner theta = 0.1,
+    Omega_c dt from 0.1 to 1e3) over its 1000 steps, mixed form, 2000
+    particles sampled against the oracle."""
+    rep = _report(10_000, 1000, name="harris256")
     assert rep["u_rel_err"]["median"] <= 1e-3
     assert rep["switch_mismatch_fraction_particle_steps"] <= 1e-2
 
