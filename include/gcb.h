@@ -208,7 +208,9 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm,
    device float arrays of nx*ny elements, element [j*nx+i] of component k,
    ACCUMULATED (+=) with dL/dF at every node.  Only GCB_FORM_F64 with
    fields loaded as GCB_F64.  The forward steps are recomputed internally
-   (unsorted); needs n_steps * n * 56 bytes of context scratch. */
+   (unsorted); needs n_steps * n * 61 bytes of context scratch plus the
+   gather-point records of up to 32 steps (64 bytes per gather point, at most
+   128 GiB and half the device memory free at the call). */
 int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start,
                       const gcb_params* prm, int32_t n_steps,
                       const double* const lam_end[7], double* const lam_start[7],
@@ -348,8 +350,9 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm,
    [(l*ny + j)*nx + i] of component k, ACCUMULATED (+=) with dL/dF at every
    node.  Only GCB_FORM_F64 with 3D fields loaded as GCB_F64, the reduced
    frame, mu conserved and n_iter <= 8 (else GCB_EUNSUPPORTED).  The forward
-   steps are recomputed internally (unsorted); needs n_steps * n * 76 bytes
-   of context scratch plus the gather-point records of up to 8 steps. */
+   steps are recomputed internally (unsorted); needs n_steps * n * 77 bytes
+   of context scratch plus the gather-point records of up to 8 steps (84 bytes
+   per gather point, at most 32 GiB and half the device memory free). */
 int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_params* prm,
                          int32_t n_steps, const double* const lam_end[9],
                          double* const lam_start[9], float* const dE[3], float* const dB[3],
