@@ -302,7 +302,7 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm,
    along x, y and z; (b.grad)b and (v_E.grad)b then include the z
    derivatives, and the guiding-center position R has three components.
    The cell size of the switch is dl = (dx dy dz)^(1/3) (Sec. 3, effective
-   cell size).  The adjoint (gcb_push_backward) is two-dimensional only. */
+   cell size).  Its adjoint is gcb_push_backward_3d. */
 typedef struct {
     int32_t n[3];            /* nx, ny, nz: nodes per axis, each in [2, 2^24] */
     int32_t dtype;           /* GCB_F64 or GCB_F32: precision of the device copy */

@@ -8,7 +8,8 @@ theta_j = j pi/nth, all six components at the nodes), in geometrized units:
     an equatorial current sheet of angular half-width w;
   * the toroidal field of field lines rotating at Omega_F = Omega_H/2
     (Omega_H = a/(2 r_+) for the horizon r_+ = 1 + sqrt(1 - a^2)), taken from
-    the flat-space rotating monopole: B^phi = -Omega_F B^r;
+    the flat-space rotating monopole: B^phi = -Omega_F B^r (Omega_F times
+    `rotation`, 1 by default, for weakly rotating variants);
   * the matching rotational electric field of the same flat-space solution,
     D^theta = -Omega_F sin(theta) B^r (so D.B = 0 away from the sheet),
     plus a reconnection field in the sheet, D^r = E_rec B0 / r^2 * sech^2
@@ -34,13 +35,14 @@ GR_COMPONENTS = ("D^r", "D^th", "D^ph", "B^r", "B^th", "B^ph")
 
 
 def magnetosphere_fields(nr: int, nth: int, r_min: float, r_max: float, a: float,
-                         B0: float, width: float, E_rec: float) -> np.ndarray:
+                         B0: float, width: float, E_rec: float,
+                         rotation: float = 1.0) -> np.ndarray:
     """F[k, j, i] = component k at (r_i, theta_j), shape (6, nth+1, nr+1)."""
     r = r_min + (r_max - r_min) * np.arange(nr + 1) / nr
     th = np.pi * np.arange(nth + 1) / nth
     TH, R = np.meshgrid(th, r, indexing="ij")
     r_plus = 1.0 + np.sqrt(1.0 - a * a)
-    omega_f = 0.5 * a / (2.0 * r_plus)
+    omega_f = rotation * 0.5 * a / (2.0 * r_plus)
     ct = np.cos(TH)
     sheet = np.tanh(ct / width)
     Br = B0 * sheet / (R * R)
@@ -114,10 +116,11 @@ class GRConfig:
     r_lo: float = 2.5
     r_hi: float = 30.0
     cos_max: float = 0.9
+    rotation: float = 1.0
 
     def fields(self) -> np.ndarray:
         return magnetosphere_fields(self.nr, self.nth, self.r_min, self.r_max, self.a,
-                                    self.B0, self.width, self.E_rec)
+                                    self.B0, self.width, self.E_rec, self.rotation)
 
     def particles(self, n: int | None = None, seed_offset: int = 0) -> GREnsemble:
         return magnetosphere_particles(self.n if n is None else n, self.seed + seed_offset,
