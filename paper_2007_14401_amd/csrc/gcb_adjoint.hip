@@ -67,6 +67,39 @@ struct RecordSink {
     }
 };
 
+// The guiding-center VJP keeps the field samples of R^{n-1/2}, R^n and the
+// first iterates of its forward recomputation in LDS (one column per lane)
+// and takes them again in the reverse sweep instead of a second gather.
+constexpr int kKeepSlots = 5;
+constexpr int kSampleVals = 12;   // E, B, dB/dx, dB/dy
+
+struct LdsSamples {
+    double* base;   // entry (slot*12 + c)*kWG + lane
+    __device__ void put(int slot, const adj::SampleD& s) const {
+        if (slot >= kKeepSlots) return;
+        double* b = base + slot * kSampleVals * kWG;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            b[c * kWG] = s.E[c];
+            b[(3 + c) * kWG] = s.B[c];
+            b[(6 + c) * kWG] = s.dBx[c];
+            b[(9 + c) * kWG] = s.dBy[c];
+        }
+    }
+    __device__ bool get(int slot, adj::SampleD& s) const {
+        if (slot >= kKeepSlots) return false;
+        const double* b = base + slot * kSampleVals * kWG;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            s.E[c] = b[c * kWG];
+            s.B[c] = b[(3 + c) * kWG];
+            s.dBx[c] = b[(6 + c) * kWG];
+            s.dBy[c] = b[(9 + c) * kWG];
+        }
+        return true;
+    }
+};
+
 // One regime per launch.  Guiding-center branch: lane t takes entry t of the
 // step's list (k_gca_lists), so every lane of a wavefront has work and waves
 // past the list return at once.  Boris branch: one lane per particle, lanes
@@ -97,10 +130,12 @@ k_adjoint_step(const double* __restrict__ st, const double* __restrict__ qm_arr,
     rec.p = p;
     rec.slot = 0;
     const Consts<double> K = make_consts<double>(pc);
-    if (kBoris)
+    if constexpr (kBoris) {
         adj::boris_step_vjp<kYee>(acc, rec, pc, K, s, qm, l);
-    else
-        adj::gca_step_vjp<kYee>(acc, rec, pc, K, s, qm, l);
+    } else {
+        __shared__ double kept[kKeepSlots * kSampleVals * kWG];
+        adj::gca_step_vjp<kYee>(acc, rec, pc, K, s, qm, l, LdsSamples{kept + threadIdx.x});
+    }
 #pragma unroll
     for (int c = 0; c < 7; ++c) lam[c * n + p] = l[c];
 }

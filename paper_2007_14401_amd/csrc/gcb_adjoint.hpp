@@ -461,6 +461,25 @@ GCB_HD void local_bar_to_position(const Acc& acc, Sink& sink, const PushConst& p
 
 constexpr int kMaxAdjIter = 8;   // fixed-point iterations the adjoint supports
 
+// Field samples of the forward recomputation that the reverse sweep takes
+// again instead of gathering them a second time: slot 0 is R^{n-1/2}, slot 1
+// R^n, slot 1 + k the iterate R^k; `put` may drop a slot, and `get` then
+// says so.  NoSamples keeps none.
+struct NoSamples {
+    GCB_HD void put(int, const SampleD&) {}
+    GCB_HD bool get(int, SampleD&) const { return false; }
+};
+
+// local quantities at a point, from a kept sample when there is one
+template <bool kYee, class Acc, class Keep>
+GCB_HD void local_again(const Acc& acc, const Keep& keep, int slot, const PushConst& pc,
+                        const KD& K, double X, double Y, SampleD& s, LocalD& L) {
+    if (keep.get(slot, s))
+        local_from_sample(s, K, L);
+    else
+        local_at<kYee>(acc, pc, K, X, Y, s, L);
+}
+
 // Number of gather points whose cotangents gca_step_vjp hands to its sink:
 // R^{n+1/2}, the iterates R^1..R^{K-1}, R^n and R^{n-1/2}.
 GCB_HD int gca_vjp_samples(int n_iter) {
@@ -468,9 +487,9 @@ GCB_HD int gca_vjp_samples(int n_iter) {
     return (Kit > 1 ? Kit - 1 : 0) + 3;
 }
 
-template <bool kYee, class Acc, class Sink>
+template <bool kYee, class Acc, class Sink, class Keep = NoSamples>
 GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const KD& K,
-                         const double st[7], double qm, double lam[7]) {
+                         const double st[7], double qm, double lam[7], Keep keep = Keep()) {
     const bool curv = pc.curvature != 0;
     const double x = st[0], y = st[1];
     const double ux = st[4], uy = st[5], uz = st[6];
@@ -486,6 +505,7 @@ GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const 
         SampleD s;
         LocalD L;
         local_at<kYee>(acc, pc, K, Rhx, Rhy, s, L);
+        keep.put(0, s);
         upar = (ux * L.b[0] + uy * L.b[1]) + uz * L.b[2];
         gf = gamma_full(ux, uy, uz, K);
         if (curv) v_curv(L, upar, gf, inv_qm, K, vch);
@@ -503,6 +523,7 @@ GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const 
         SampleD s;
         LocalD L;
         local_at<kYee>(acc, pc, K, x, y, s, L);
+        keep.put(1, s);
         uint32_t fl = 0;
         upn = parallel_update(L, upar, conserved_mu(mu), qm, curv, K, fl);
         drift_terms(L, upn, conserved_mu(mu), inv_qm, curv, K, Fn[0], Fn[1]);
@@ -519,6 +540,7 @@ GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const 
             SampleD s;
             LocalD L;
             local_at<kYee>(acc, pc, K, Rk[k][0], Rk[k][1], s, L);
+            keep.put(1 + k, s);
             drift_terms(L, upn, conserved_mu(mu), inv_qm, curv, K, F[0], F[1]);
         }
         Rk[k + 1][0] = x + h * (Fn[0] + F[0]);
@@ -586,7 +608,7 @@ GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const 
         } else {
             SampleD s;
             LocalD L;
-            local_at<kYee>(acc, pc, K, Rk[k][0], Rk[k][1], s, L);
+            local_again<kYee>(acc, keep, 1 + k, pc, K, Rk[k][0], Rk[k][1], s, L);
             LocalBar Lb;
             zero(Lb);
             drift_vjp(L, upn, mu, inv_qm, curv, K, Fkb, Lb, upnb, mub);
@@ -603,7 +625,7 @@ GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const 
     {
         SampleD s;
         LocalD L;
-        local_at<kYee>(acc, pc, K, x, y, s, L);
+        local_again<kYee>(acc, keep, 1, pc, K, x, y, s, L);
         LocalBar Lb;
         zero(Lb);
         drift_vjp(L, upn, mu, inv_qm, curv, K, Fnb, Lb, upnb, mub);
@@ -616,7 +638,7 @@ GCB_HD void gca_step_vjp(const Acc& acc, Sink& sink, const PushConst& pc, const 
     {
         SampleD s;
         LocalD L;
-        local_at<kYee>(acc, pc, K, Rhx, Rhy, s, L);
+        local_again<kYee>(acc, keep, 0, pc, K, Rhx, Rhy, s, L);
         LocalBar Lb;
         zero(Lb);
         double upb[3] = {0.0, 0.0, 0.0};
