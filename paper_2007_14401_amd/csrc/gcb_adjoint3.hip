@@ -51,6 +51,41 @@ struct RecordSink3 {
     }
 };
 
+// The guiding-center VJP keeps the field samples of R^{n-1/2}, R^n and the
+// first iterates of its forward recomputation in LDS (one column per lane),
+// as in 2D.
+constexpr int kKeepSlots3 = 4;
+constexpr int kSampleVals3 = 15;   // E, B, dB/dx, dB/dy, dB/dz
+
+struct LdsSamples3 {
+    double* base;   // entry (slot*15 + c)*kWG + lane
+    __device__ void put(int slot, const Sample3<double>& s) const {
+        if (slot >= kKeepSlots3) return;
+        double* b = base + slot * kSampleVals3 * kWG;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            b[c * kWG] = s.E[c];
+            b[(3 + c) * kWG] = s.B[c];
+            b[(6 + c) * kWG] = s.dBx[c];
+            b[(9 + c) * kWG] = s.dBy[c];
+            b[(12 + c) * kWG] = s.dBz[c];
+        }
+    }
+    __device__ bool get(int slot, Sample3<double>& s) const {
+        if (slot >= kKeepSlots3) return false;
+        const double* b = base + slot * kSampleVals3 * kWG;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            s.E[c] = b[c * kWG];
+            s.B[c] = b[(3 + c) * kWG];
+            s.dBx[c] = b[(6 + c) * kWG];
+            s.dBy[c] = b[(9 + c) * kWG];
+            s.dBz[c] = b[(12 + c) * kWG];
+        }
+        return true;
+    }
+};
+
 // One regime per launch, as in 2D: the guiding-center branch over the
 // step's list (lane t takes entry t), the Boris branch one lane per particle.
 template <bool kYee, bool kBoris>
@@ -79,10 +114,12 @@ __global__ __launch_bounds__(kWG) void k_adjoint3_step(
     rec.p = p;
     rec.slot = 0;
     const Consts3<double> K = make_consts3<double>(pc);
-    if (kBoris)
+    if constexpr (kBoris) {
         adj3::boris_step_vjp3<kYee>(acc, rec, pc, K, s, qm, l);
-    else
-        adj3::gca_step_vjp3<kYee>(acc, rec, pc, K, s, qm, l);
+    } else {
+        __shared__ double kept[kKeepSlots3 * kSampleVals3 * kWG];
+        adj3::gca_step_vjp3<kYee>(acc, rec, pc, K, s, qm, l, LdsSamples3{kept + threadIdx.x});
+    }
 #pragma unroll
     for (int c = 0; c < 9; ++c) lam[c * n + p] = l[c];
 }

@@ -175,6 +175,23 @@ GCB_HD void local_at3(const GlobalAcc3<double>& acc, const PushConst3& pc, const
     local_from_sample(s, K, L);
 }
 
+// Field samples of the forward recomputation taken again in the reverse sweep
+// (slots as in 2D: 0 = R^{n-1/2}, 1 = R^n, 1 + k = R^k); NoSamples3 keeps none.
+struct NoSamples3 {
+    GCB_HD void put(int, const Sample3D&) {}
+    GCB_HD bool get(int, Sample3D&) const { return false; }
+};
+
+template <bool kYee, class Keep>
+GCB_HD void local_again3(const GlobalAcc3<double>& acc, const Keep& keep, int slot,
+                         const PushConst3& pc, const K3& K, const double X[3], Sample3D& s,
+                         LocalD& L) {
+    if (keep.get(slot, s))
+        local_from_sample(s, K, L);
+    else
+        local_at3<kYee>(acc, pc, K, X, s, L);
+}
+
 template <bool kYee, class Sink>
 GCB_HD void local_bar_to_position3(const GlobalAcc3<double>& acc, Sink& sink,
                                    const PushConst3& pc, const K3& K, const Sample3D& s,
@@ -250,9 +267,10 @@ GCB_HD void boris_step_vjp3(const GlobalAcc3<double>& acc, Sink& sink, const Pus
 // Gather points gca_step_vjp3 hands to its sink: as in 2D.
 GCB_HD int gca_vjp_samples3(int n_iter) { return adj::gca_vjp_samples(n_iter); }
 
-template <bool kYee, class Sink>
+template <bool kYee, class Sink, class Keep = NoSamples3>
 GCB_HD void gca_step_vjp3(const GlobalAcc3<double>& acc, Sink& sink, const PushConst3& pc,
-                          const K3& K, const double st[9], double qm, double lam[9]) {
+                          const K3& K, const double st[9], double qm, double lam[9],
+                          Keep keep = Keep()) {
     const bool curv = pc.b.curvature != 0;
     const double x[3] = {st[0], st[1], st[2]};
     const double box[3] = {pc.b.Lx, pc.b.Ly, pc.Lz};
@@ -269,6 +287,7 @@ GCB_HD void gca_step_vjp3(const GlobalAcc3<double>& acc, Sink& sink, const PushC
         Sample3D s;
         LocalD L;
         local_at3<kYee>(acc, pc, K, Rh, s, L);
+        keep.put(0, s);
         upar = (ux * L.b[0] + uy * L.b[1]) + uz * L.b[2];
         gf = gamma_full(ux, uy, uz, K);
         if (curv) v_curv(L, upar, gf, inv_qm, K, vch);
@@ -286,6 +305,7 @@ GCB_HD void gca_step_vjp3(const GlobalAcc3<double>& acc, Sink& sink, const PushC
         Sample3D s;
         LocalD L;
         local_at3<kYee>(acc, pc, K, x, s, L);
+        keep.put(1, s);
         uint32_t fl = 0;
         upn = parallel_update(L, upar, conserved_mu(mu), qm, curv, K, fl);
         drift_terms3(L, upn, conserved_mu(mu), inv_qm, curv, K, Fn);
@@ -300,6 +320,7 @@ GCB_HD void gca_step_vjp3(const GlobalAcc3<double>& acc, Sink& sink, const PushC
             Sample3D s;
             LocalD L;
             local_at3<kYee>(acc, pc, K, Rk[k], s, L);
+            keep.put(1 + k, s);
             drift_terms3(L, upn, conserved_mu(mu), inv_qm, curv, K, F);
         }
         for (int a = 0; a < 3; ++a) Rk[k + 1][a] = x[a] + h * (Fn[a] + F[a]);
@@ -368,7 +389,7 @@ GCB_HD void gca_step_vjp3(const GlobalAcc3<double>& acc, Sink& sink, const PushC
         } else {
             Sample3D s;
             LocalD L;
-            local_at3<kYee>(acc, pc, K, Rk[k], s, L);
+            local_again3<kYee>(acc, keep, 1 + k, pc, K, Rk[k], s, L);
             LocalBar Lb;
             zero(Lb);
             drift_vjp3(L, upn, mu, inv_qm, curv, K, Fkb, Lb, upnb, mub);
@@ -383,7 +404,7 @@ GCB_HD void gca_step_vjp3(const GlobalAcc3<double>& acc, Sink& sink, const PushC
     {
         Sample3D s;
         LocalD L;
-        local_at3<kYee>(acc, pc, K, x, s, L);
+        local_again3<kYee>(acc, keep, 1, pc, K, x, s, L);
         LocalBar Lb;
         zero(Lb);
         drift_vjp3(L, upn, mu, inv_qm, curv, K, Fnb, Lb, upnb, mub);
@@ -396,7 +417,7 @@ GCB_HD void gca_step_vjp3(const GlobalAcc3<double>& acc, Sink& sink, const PushC
     {
         Sample3D s;
         LocalD L;
-        local_at3<kYee>(acc, pc, K, Rh, s, L);
+        local_again3<kYee>(acc, keep, 0, pc, K, Rh, s, L);
         LocalBar Lb;
         zero(Lb);
         double upb[3] = {0.0, 0.0, 0.0};
