@@ -16,6 +16,19 @@ def log(msg: str) -> None:
     sys.stdout.flush()
 
 
+def save_report(name: str, obj) -> None:
+    """Write a test's measured report as JSON into the directory named by the
+    GCB_REPORT_DIR environment variable (nothing is written when it is unset)."""
+    import json
+    import os
+    d = os.environ.get("GCB_REPORT_DIR")
+    if not d:
+        return
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, name), "w") as f:
+        json.dump(obj, f, indent=1)
+
+
 def oracle_params(cfg, **kw):
     d = dict(dt=cfg.dt, c=cfg.c, f_rho=cfg.f_rho, f_E=cfg.f_E,
              curvature=bool(cfg.curvature), n_iter=cfg.n_iter, Lx=cfg.Lx, Ly=cfg.Ly,

@@ -16,7 +16,7 @@ import pytest
 import torch
 
 import oracle as O
-from gpu_util import log
+from gpu_util import log, save_report
 from workloads import make_config3
 
 pytestmark = pytest.mark.gpu
@@ -357,7 +357,6 @@ def test_mixed_report_3d_1e7():
     binary64 oracle; errors and switch mismatches recorded, with the loose
     multi-step bounds of the 2D report."""
     import json
-    import os
     from paper_2007_14401_amd import gcb, state
     cfg = make_config3("harris3d128")
     log("3d mixed report: generating inputs")
@@ -399,10 +398,7 @@ def test_mixed_report_3d_1e7():
            "u_rel_err_median_no_mismatch": float(np.median(du[~ever])) if (~ever).any() else None,
            "gca_fraction": st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])}
     log("3d mixed report " + json.dumps(rep))
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    os.makedirs(os.path.join(root, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(root, "gpurun_out", "d3_mixed_report.json"), "w") as f:
-        json.dump(rep, f, indent=1)
+    save_report("d3_mixed_report.json", rep)
     assert rep["u_rel_err"]["median"] <= 1e-3
     assert rep["switch_mismatch_fraction_particle_steps"] <= 1e-2
 

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import log
+from gpu_util import log, save_report
 from oracle import gr
 from workloads import make_gr_config
 
@@ -340,10 +340,9 @@ def test_gr_mixed_deterministic():
 
 def test_gr_mixed_precision_report():
     """grbh512 at full size (1e7 particles, 200 steps) in the precision form;
-    2000 sampled particles against the binary64 oracle.  Writes the report to
-    gpurun_out/gr_mixed_report.json."""
+    2000 sampled particles against the binary64 oracle; the report goes to
+    gr_mixed_report.json in $GCB_REPORT_DIR."""
     import json
-    import os
     cfg = make_gr_config("grbh512")
     F = cfg.fields()
     e = cfg.particles()
@@ -374,9 +373,6 @@ def test_gr_mixed_precision_report():
            "u_rel_err_median_no_mismatch": float(np.median(du[~ever])) if (~ever).any() else None,
            "gca_fraction": st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])}
     log("gr mixed report " + json.dumps(rep))
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    os.makedirs(os.path.join(root, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(root, "gpurun_out", "gr_mixed_report.json"), "w") as f:
-        json.dump(rep, f, indent=1)
+    save_report("gr_mixed_report.json", rep)
     assert rep["u_rel_err"]["median"] <= 1e-2
     assert rep["switch_mismatch_fraction_particle_steps"] <= 2e-2

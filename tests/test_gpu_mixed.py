@@ -13,18 +13,16 @@ Over many steps chaotic orbits amplify these differences; the multi-step
 report (full-size workload) is measured and recorded, with loose bounds.
 """
 import json
-import os
 
 import numpy as np
 import pytest
 import torch
 
-from gpu_util import GpuRun, log, run_oracle
+from gpu_util import GpuRun, log, run_oracle, save_report
 from workloads import make_config
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _errors(got, ref, cfg, idx=None):
@@ -124,10 +122,7 @@ def _report(n_total, steps, sample_n=2000, name="harris4096"):
         "gca_fraction": st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"]),
     }
     log("mixed report " + json.dumps(rep))
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", f"mixed_report_{name}_{n_total}.json"),
-              "w") as f:
-        json.dump(rep, f, indent=1)
+    save_report(f"mixed_report_{name}_{n_total}.json", rep)
     return rep
 
 

@@ -10,7 +10,7 @@ gyro-radii the coupled push follows the gyro-resolved reference while the
 Boris push with the large step does not, and the coupled push switches to
 the guiding-center equations for most of the run.  The paper's figures are
 not in its text, so the thresholds are this workload's, not the paper's
-numbers; the full report is written to gpurun_out/replay_report.json.
+numbers; the full report goes to replay_report.json in $GCB_REPORT_DIR.
 
 Curved spacetime, the ambient-region test of Sec. 4.2
 (paper_2007_14401_amd/replay_gr.py): electrons at rest at r = 5.5 r_g with
@@ -21,24 +21,17 @@ reference more and more as Omega_C0 grows, while the coupled push, on the
 guiding-center equations once the gyro-radius is below the cell, stays on it
 at every magnetization.
 """
-import json
-import os
 
 import pytest
 
-from gpu_util import log
+from gpu_util import log, save_report
 
 pytestmark = pytest.mark.gpu
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-
 
 def test_replay_coupled_tracks_reference():
     from paper_2007_14401_amd import replay
     reps = [replay.run(r, 1111, log=log) for r in (1e-2, 1e-3)]
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "replay_report.json"), "w") as f:
-        json.dump(reps, f, indent=1)
+    save_report("replay_report.json", reps)
     for rep in reps:
         c, b = rep["coupled_curvature"], rep["boris"]
         log(f"rho/d_e={rep['rho_over_de']:g}: coupled max dev {c['max_deviation_de']:.3e} "
@@ -51,9 +44,7 @@ def test_replay_coupled_tracks_reference():
 def test_replay_gr_ambient():
     from paper_2007_14401_amd import replay_gr
     rep = replay_gr.run((1e1, 1e2, 1e3), 20.0, rotation=0.1, log=log)
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "replay_gr_report.json"), "w") as f:
-        json.dump(rep, f, indent=1)
+    save_report("replay_gr_report.json", rep)
     c, b = rep["coupled"]["max_deviation_rg"], rep["boris"]["max_deviation_rg"]
     frac = rep["coupled"]["gca_fraction"]
     # the coupled push stays close to the reference at every magnetization
