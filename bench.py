@@ -197,8 +197,8 @@ def main():
     a = ap.parse_args()
 
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the pusher has no "
-              "cross-GPU work in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): the library pushes "
+              "particles on a single GPU", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

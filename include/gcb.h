@@ -46,7 +46,7 @@ extern "C" {
 #define GCB_ENOFIELDS    -2   /* gcb_push before gcb_load_fields */
 #define GCB_ENOMEM       -3   /* device allocation failed */
 #define GCB_EHIP         -4   /* a HIP runtime call failed (message has the HIP error) */
-#define GCB_EUNSUPPORTED -5   /* valid request this build cannot serve */
+#define GCB_EUNSUPPORTED -5   /* valid request the library does not serve */
 
 /* precision of the device copy of the fields (gcb_grid_desc.dtype) */
 #define GCB_F64 0
