@@ -90,8 +90,9 @@ def _report(n_total, steps, sample_n=2000, name="harris4096"):
     log(f"mixed report: generating {n_total} particles")
     F = cfg.fields()
     ens = cfg.particles(n=n_total)
-    # the benchmark's launch configuration (tiled, sort every 4 steps, 24-cell tiles)
-    t, tr, st = _run_mixed(cfg, F, ens, steps, True, kernel=2, sort_every=4, tile=24)
+    # the benchmark's launch configuration of the mixed form (tiled, sort every
+    # 4 steps, 32-cell tiles)
+    t, tr, st = _run_mixed(cfg, F, ens, steps, True, kernel=2, sort_every=4, tile=32)
     ids = t["id"].cpu().numpy()
     rng = np.random.default_rng(123)
     sample = np.sort(rng.choice(ens.n, sample_n, replace=False))
