@@ -187,6 +187,8 @@ typedef struct {
     int64_t flagged;         /* particles with any status bit other than GCB_ST_HALO at the end */
     int64_t halo_misses;     /* particle-steps with a gather outside the LDS window */
     double  max_fp_residual; /* max over guiding-center steps of |R^K - R^{K-1}|_inf */
+    int64_t status_counts[7];/* particles with status bit 2^k set at the end, k = 0..6
+                                (GCB_ST_NONFINITE ... GCB_ST_OUT) */
 } gcb_stats;
 
 /* Advance the particles by n_steps steps of the coupled scheme (Sec. 3.1):

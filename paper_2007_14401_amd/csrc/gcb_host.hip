@@ -415,7 +415,9 @@ int stats_end(gcb_ctx* ctx, const uint8_t* status, int64_t n, gcb_stats* stats,
               hipStream_t stream) {
     if (!stats) return GCB_OK;
     DevStats* dstats = static_cast<DevStats*>(ctx->stats.ptr);
-    // the flagged count goes to the first word after the slots
+    // the flagged count and the status-bit counts go to the eight words after
+    // the slots
+    static_assert(sizeof(DevStats) >= 8 * sizeof(unsigned long long), "status counters");
     unsigned long long* flagged = reinterpret_cast<unsigned long long*>(dstats + kStatSlots);
     GCB_HIP(launch_count_flagged(status, n, flagged, stream));
     std::vector<DevStats> host(kStatSlots + 1);
@@ -435,7 +437,10 @@ int stats_end(gcb_ctx* ctx, const uint8_t* status, int64_t n, gcb_stats* stats,
     double m;
     std::memcpy(&m, &mbits, sizeof(m));
     stats->max_fp_residual = m;
-    stats->flagged = (int64_t)host[kStatSlots].gca_steps;
+    unsigned long long extra[8];
+    std::memcpy(extra, &host[kStatSlots], sizeof(extra));
+    stats->flagged = (int64_t)extra[0];
+    for (int k = 0; k < 7; ++k) stats->status_counts[k] = (int64_t)extra[1 + k];
     return GCB_OK;
 }
 

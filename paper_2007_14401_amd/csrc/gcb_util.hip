@@ -82,12 +82,19 @@ __global__ __launch_bounds__(kWG) void k_ke_final(const double* partial, int64_t
     if (threadIdx.x == 0) out[0] = n > 0 ? s[0] / (double)n : 0.0;
 }
 
+// out[0] += particles with any status bit other than HALO; out[1 + k] +=
+// particles with bit 2^k set, k = 0..6
 __global__ __launch_bounds__(kWG) void k_count_flagged(const uint8_t* __restrict__ st,
                                                        int64_t n, unsigned long long* out) {
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    const bool f = i < n && (st[i] & ~(uint8_t)ST_HALO) != 0;
-    const unsigned long long b = __ballot(f);
+    const uint8_t v = i < n ? st[i] : (uint8_t)0;
+    const unsigned long long b = __ballot((v & ~(uint8_t)ST_HALO) != 0);
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const unsigned long long m = __ballot((v >> k) & 1);
+        if ((threadIdx.x & 63) == 0 && m) atomicAdd(out + 1 + k, (unsigned long long)__popcll(m));
+    }
 }
 
 }  // namespace

@@ -71,7 +71,7 @@ class gcb_particles(C.Structure):
 class gcb_stats(C.Structure):
     _fields_ = [("gca_steps", C.c_int64), ("boris_steps", C.c_int64),
                 ("flagged", C.c_int64), ("halo_misses", C.c_int64),
-                ("max_fp_residual", C.c_double)]
+                ("max_fp_residual", C.c_double), ("status_counts", C.c_int64 * 7)]
 
 
 class gcb_gr_desc(C.Structure):
@@ -156,6 +156,12 @@ def _ptr(a):
     if isinstance(a, np.ndarray):
         return a.ctypes.data
     return a.data_ptr()
+
+
+def _stats_dict(st) -> dict:
+    d = {k: getattr(st, k) for k, _ in gcb_stats._fields_}
+    d["status_counts"] = list(d["status_counts"])
+    return d
 
 
 def _check(rc: int, ctx=None):
@@ -252,7 +258,7 @@ def gcb_push(ctx, parts: gcb_particles, prm: gcb_params, n_steps: int, s_trace=N
     _check(rc, ctx)
     if st is None:
         return None
-    return {k: getattr(st, k) for k, _ in gcb_stats._fields_}
+    return _stats_dict(st)
 
 
 def gcb_push_backward(ctx, start: gcb_particles, prm: gcb_params, n_steps: int, lam_end,
@@ -316,7 +322,7 @@ def gcb_push_gr(ctx, parts: gcb_gr_particles, prm: gcb_params, n_steps: int, s_t
     _check(rc, ctx)
     if st is None:
         return None
-    return {k: getattr(st, k) for k, _ in gcb_stats._fields_}
+    return _stats_dict(st)
 
 
 def grid3_desc(nx, ny, nz, dx=1.0, dy=1.0, dz=1.0, stagger=YEE3_STAGGER,
@@ -368,7 +374,7 @@ def gcb_push_3d(ctx, parts: gcb_particles3, prm: gcb_params, n_steps: int, s_tra
     _check(rc, ctx)
     if st is None:
         return None
-    return {k: getattr(st, k) for k, _ in gcb_stats._fields_}
+    return _stats_dict(st)
 
 
 def gcb_push_backward_3d(ctx, start: gcb_particles3, prm: gcb_params, n_steps: int, lam_end,

@@ -133,6 +133,9 @@ def test_gr_multistep(g64):
     assert abs(st["max_fp_residual"] - float(res.max())) <= 1e-12 * max(1.0, float(res.max()))
     flagged = int(((ref.status.numpy() & ~np.uint8(32)) != 0).sum())
     assert st["flagged"] == flagged
+    bits = ref.status.numpy()
+    for k in (0, 1, 2, 3, 4, 6):
+        assert st["status_counts"][k] == int(((bits >> k) & 1).sum()), k
 
 
 @pytest.mark.parametrize("kw", [{"n_iter": 1}, {"n_iter": 3}, {"f_rho": 0.0},

@@ -80,6 +80,13 @@ def test_multistep(h64, kernel, sort_every, tile):
     assert st["gca_steps"] == int((rtr == 0).sum())
     assert st["boris_steps"] == int((rtr == 1).sum())
     assert st["max_fp_residual"] == float(rres.max())
+    # status histogram: particles per status bit (the halo bit is the GPU's own)
+    bits = ref.status.numpy()
+    for k in range(7):
+        if k == 5:
+            continue
+        assert st["status_counts"][k] == int(((bits >> k) & 1).sum()), k
+    assert st["flagged"] == int(((bits & ~np.uint8(32)) != 0).sum())
 
 
 VARIANTS = [
