@@ -44,6 +44,15 @@ design notes of the repository):
     the whole step.  GYR_ZERO (mu = 0, which the paper allows where
     radiation has removed the gyration, Sec. 2.2 before Sec. 2.2.1): the
     decomposition's gyration is discarded.
+  * Params.mirror (curvature scheme only): the mirror force and the grad-B
+    drift, which Sec. 2.2 names and leaves out of the reduced equations, with
+    the paper's mu: du_par/dt gains -(mu/(m kappa Gamma)) b.grad|B| and the
+    bracket of the curvature drift gains (mu/(m kappa Gamma)) grad|B|.
+    grad(B/kappa) is taken as grad|B|/kappa (the gradient of kappa, which
+    needs that of E, is left out; with E = 0 both are the textbook
+    relativistic terms).  The force is time-centred by one
+    predictor-corrector pass on 1/Gamma; the decomposition and the
+    reconstruction keep the paper's u_perp_d = Gamma (v_E + v_c).
 """
 from __future__ import annotations
 
@@ -86,6 +95,7 @@ class Params:
     dl: float = 1.0   # effective cell size sqrt(dx*dy)
     exact_frame: bool = False   # b*, exact v_E (frame.py); zero-curvature scheme only
     gyration: int = GYR_MU      # GYR_MU, GYR_UPERP or GYR_ZERO
+    mirror: bool = False        # mirror force and grad-B drift (curvature scheme only)
 
     @property
     def c2(self) -> float:
@@ -149,8 +159,9 @@ def local(prov, X, Y, p: Params):
 
     Returns a namespace with B, inv_B, b=(bx,by,bz), vE, kappa, Epar,
     bgb = (b.grad)b, vgb = (v_E.grad)b, A = v_E.(b.grad)b,
-    C = v_E.(v_E.grad)b, the raw E and B vectors and status flags.
-    With p.exact_frame, the quantities of the exact frame (frame.py).
+    C = v_E.(v_E.grad)b, gB = grad|B| (x, y), the raw E and B vectors and
+    status flags.  With p.exact_frame, the quantities of the exact frame
+    (frame.py).
     """
     if p.exact_frame:
         from .frame import local_exact
@@ -176,10 +187,11 @@ def local(prov, X, Y, p: Params):
     kappa = 1.0 / sqrt(om)
     Epar = (Ex * bx + Ey * by) + Ez * bz
     # d_j b_i = (d_j B_i - b_i d_j|B|)/B with d_j|B| = b . d_j B
-    db = []
+    db, gB = [], []
     for j in range(2):
         gx, gy, gz = s.dB[j]
         dBn = (bx * gx + by * gy) + bz * gz
+        gB.append(dBn)
         db.append(((gx - bx * dBn) * inv_B,
                    (gy - by * dBn) * inv_B,
                    (gz - bz * dBn) * inv_B))
@@ -190,7 +202,7 @@ def local(prov, X, Y, p: Params):
     flags = (torch.where(kflag, ST_KAPPA, 0) | torch.where(bzero, ST_BZERO, 0))
     return SimpleNamespace(E=(Ex, Ey, Ez), Bv=(Bx, By, Bz), B=B, inv_B=inv_B,
                            b=(bx, by, bz), vE=(vEx, vEy, vEz), kappa=kappa,
-                           Epar=Epar, bgb=bgb, vgb=vgb, A=A, C=C,
+                           Epar=Epar, bgb=bgb, vgb=vgb, A=A, C=C, gB=tuple(gB),
                            flags=flags.to(torch.uint8))
 
 
@@ -222,12 +234,22 @@ def gamma_gca(L, upar, gy, p: Params):
     return L.kappa * sqrt(1.0 + (upar * upar + uperp2) * p.inv_c2)
 
 
-def v_curv(L, upar, gam, inv_qm, p: Params):
+def v_curv(L, upar, gam, inv_qm, p: Params, gy=None):
     """Curvature drift (eq. curvdrift):
-    (m c kappa^2/(q B)) b x [ (u_par^2/Gamma)(b.grad)b + u_par (v_E.grad)b ]."""
+    (m c kappa^2/(q B)) b x [ (u_par^2/Gamma)(b.grad)b + u_par (v_E.grad)b ].
+
+    With a gyration state gy (the mirror option), the grad-B drift joins the
+    bracket as (mu/(m kappa Gamma)) grad|B|: with kappa = 1 this is
+    c u_perp^2/(2 (q/m) Gamma B^2) b x grad|B|, the relativistic grad-B
+    drift.  grad(B/kappa) is taken as grad|B|/kappa (the gradient of kappa,
+    which needs that of E, is left out)."""
     pre = ((p.c * L.kappa) * L.kappa) * (L.inv_B * inv_qm)
     a1 = (upar * upar) / gam
-    w = tuple(a1 * L.bgb[i] + upar * L.vgb[i] for i in range(3))
+    w = [a1 * L.bgb[i] + upar * L.vgb[i] for i in range(3)]
+    if gy is not None:
+        a3 = (gy.mu / L.kappa) / gam
+        for i in range(len(L.gB)):
+            w[i] = w[i] + a3 * L.gB[i]
     bx, by, bz = L.b
     return (pre * (by * w[2] - bz * w[1]),
             pre * (bz * w[0] - bx * w[2]),
@@ -296,12 +318,14 @@ def boris_step(s, st: State, p: Params):
 # guiding-center leapfrog (Sec. 2.2.1, 2.2.2) inside the coupled step (Sec. 3.1)
 
 
-def parallel_update(Ln, upar, gy, qm, p: Params):
+def parallel_update(Ln, upar, gy, qm, p: Params, shift=None):
     """u_par^{n-1/2} -> u_par^{n+1/2} at R^n; returns (u_par_new, flags).
 
     Without curvature: u_par + (q dt/m) E_par.  With curvature: solve
     eq. dupardtcase2disc via the quadratic for Gamma(R^n, u_par^{n+1/2})
-    and take its positive root, then eq. dupardtcase2discsol.
+    and take its positive root, then eq. dupardtcase2discsol.  `shift`
+    (the mirror option) is an explicit change of u_par over the step that is
+    subtracted from the known part of the update.
     """
     dtqm = qm * p.dt
     if not p.curvature:
@@ -310,6 +334,8 @@ def parallel_update(Ln, upar, gy, qm, p: Params):
     A, C = Ln.A, Ln.C
     G0 = gamma_gca(Ln, upar, gy, p)
     upr = (upar * (1.0 + h * A) + dtqm * Ln.Epar) + (h * G0) * C
+    if shift is not None:
+        upr = upr - shift
     D = 1.0 - h * A
     DD = D * D
     k1 = (h * h) * (C * C) - (p.c2 * DD) / (Ln.kappa * Ln.kappa)
@@ -333,9 +359,31 @@ def parallel_update(Ln, upar, gy, qm, p: Params):
     gfb = gamma_gca(Ln, upr / Ds, gy, p)
     ufb = (upr + (h * gfb) * C) / Ds
     uexp = upar + dtqm * Ln.Epar
+    if shift is not None:
+        uexp = uexp - shift
     out = torch.where(ok, unew, torch.where(dok, ufb, uexp))
     flags = torch.where(ok, 0, ST_QUAD).to(torch.uint8)
     return out, flags
+
+
+def mirror_parallel(Ln, upar, gy, qm, p: Params):
+    """Parallel update with the mirror force -(mu/(m kappa Gamma)) b.grad|B|
+    added to eq. dupardt (the mirror option; with kappa = 1 it is the
+    relativistic mirror force, which keeps u_par^2 + 2 mu B/m constant).
+    Gamma is centred by one predictor-corrector pass: the predictor takes
+    1/Gamma(R^n, u_par^{n-1/2}), the corrector the mean of that and
+    1/Gamma(R^n, u_par*) with u_par* the predictor's result.  Returns
+    (u_par_new, flags of both passes)."""
+    if len(Ln.gB) == 2:
+        M = Ln.b[0] * Ln.gB[0] + Ln.b[1] * Ln.gB[1]
+    else:
+        M = (Ln.b[0] * Ln.gB[0] + Ln.b[1] * Ln.gB[1]) + Ln.b[2] * Ln.gB[2]
+    ds = (p.dt * (gy.mu / Ln.kappa)) * M
+    G0 = gamma_gca(Ln, upar, gy, p)
+    u1, f1 = parallel_update(Ln, upar, gy, qm, p, ds / G0)
+    G1 = gamma_gca(Ln, u1, gy, p)
+    u2, f2 = parallel_update(Ln, upar, gy, qm, p, ds * (0.5 * (1.0 / G0 + 1.0 / G1)))
+    return u2, f1 | f2
 
 
 def _drift_terms(L, upar_new, gy, inv_qm, p: Params):
@@ -343,7 +391,7 @@ def _drift_terms(L, upar_new, gy, inv_qm, p: Params):
     g = gamma_gca(L, upar_new, gy, p)
     a = upar_new / g
     if p.curvature:
-        vc = v_curv(L, upar_new, g, inv_qm, p)
+        vc = v_curv(L, upar_new, g, inv_qm, p, gy if p.mirror else None)
         return ((a * L.b[0] + L.vE[0]) + vc[0], (a * L.b[1] + L.vE[1]) + vc[1])
     return (a * L.b[0] + L.vE[0], a * L.b[1] + L.vE[1])
 
@@ -356,6 +404,7 @@ def gca_step(prov, st: State, p: Params):
     x, y, qm = st.x, st.y, st.qm
     ux, uy, uz = st.ux, st.uy, st.uz
     inv_qm = 1.0 / qm
+    assert p.curvature or not p.mirror, "the mirror terms ride on the curvature scheme"
     flags = torch.zeros_like(x, dtype=torch.uint8)
 
     # 1. switch to guiding-center variables at R^{n-1/2} = (x^n + x^{n-1})/2
@@ -383,7 +432,10 @@ def gca_step(prov, st: State, p: Params):
     # 2.-3. fields at R^n = x^n and the parallel four-velocity update
     Ln = local(prov, x, y, p)
     flags |= Ln.flags
-    upn, qf = parallel_update(Ln, upar, gy, qm, p)
+    if p.mirror:
+        upn, qf = mirror_parallel(Ln, upar, gy, qm, p)
+    else:
+        upn, qf = parallel_update(Ln, upar, gy, qm, p)
     flags |= qf
 
     # 4. R^{n+1} by fixed-point iteration R^{k+1} = R^k - H(R^k), R^0 = R^n

@@ -24,8 +24,8 @@ import torch
 
 from .ieee import sqrt
 from .pusher import (D_FLOOR, KAPPA_FLOOR, ST_BZERO, ST_FPRES, ST_KAPPA, ST_NONFINITE,
-                     Params, boris, gamma_gca, gyration, min_image, parallel_update, switch_gca,
-                     uperp_sq, v_curv, wrap)
+                     Params, boris, gamma_gca, gyration, min_image, mirror_parallel,
+                     parallel_update, switch_gca, uperp_sq, v_curv, wrap)
 
 F64 = torch.float64
 
@@ -100,10 +100,11 @@ def local3(prov, X, Y, Z, p: Params3):
     kappa = 1.0 / sqrt(om)
     Epar = (Ex * bx + Ey * by) + Ez * bz
     # d_j b_i = (d_j B_i - b_i d_j|B|)/B with d_j|B| = b . d_j B, j = x, y, z
-    db = []
+    db, gB = [], []
     for j in range(3):
         gx, gy, gz = s.dB[j]
         dBn = (bx * gx + by * gy) + bz * gz
+        gB.append(dBn)
         db.append(((gx - bx * dBn) * inv_B,
                    (gy - by * dBn) * inv_B,
                    (gz - bz * dBn) * inv_B))
@@ -114,7 +115,7 @@ def local3(prov, X, Y, Z, p: Params3):
     flags = (torch.where(kflag, ST_KAPPA, 0) | torch.where(bzero, ST_BZERO, 0))
     return SimpleNamespace(E=(Ex, Ey, Ez), Bv=(Bx, By, Bz), B=B, inv_B=inv_B,
                            b=(bx, by, bz), vE=(vEx, vEy, vEz), kappa=kappa,
-                           Epar=Epar, bgb=bgb, vgb=vgb, A=A, C=C,
+                           Epar=Epar, bgb=bgb, vgb=vgb, A=A, C=C, gB=tuple(gB),
                            flags=flags.to(torch.uint8))
 
 
@@ -142,7 +143,7 @@ def _drift_terms3(L, upar_new, gy, inv_qm, p: Params3):
     g = gamma_gca(L, upar_new, gy, p)
     a = upar_new / g
     if p.curvature:
-        vc = v_curv(L, upar_new, g, inv_qm, p)
+        vc = v_curv(L, upar_new, g, inv_qm, p, gy if p.mirror else None)
         return tuple((a * L.b[i] + L.vE[i]) + vc[i] for i in range(3))
     return tuple(a * L.b[i] + L.vE[i] for i in range(3))
 
@@ -151,6 +152,7 @@ def gca_step3(prov, st: State3, p: Params3):
     """One guiding-center step. Returns (x, y, z, xp, yp, zp, ux, uy, uz, flags, residual)."""
     pos = (st.x, st.y, st.z)
     prev = (st.xp, st.yp, st.zp)
+    assert p.curvature or not p.mirror, "the mirror terms ride on the curvature scheme"
     box = (p.Lx, p.Ly, p.Lz)
     qm = st.qm
     ux, uy, uz = st.ux, st.uy, st.uz
@@ -181,7 +183,10 @@ def gca_step3(prov, st: State3, p: Params3):
     # 2.-3. fields at R^n = x^n and the parallel four-velocity update
     Ln = local3(prov, *pos, p)
     flags |= Ln.flags
-    upn, qf = parallel_update(Ln, upar, gy, qm, p)
+    if p.mirror:
+        upn, qf = mirror_parallel(Ln, upar, gy, qm, p)
+    else:
+        upn, qf = parallel_update(Ln, upar, gy, qm, p)
     flags |= qf
 
     # 4. R^{n+1} by fixed-point iteration R^{k+1} = R^k - H(R^k), R^0 = R^n
