@@ -164,6 +164,19 @@ typedef struct {
     int32_t gyration;    /* GCB_GYRATION_* (0 = mu conserved).  Other values than
                             GCB_GYRATION_MU: gcb_push and gcb_push_3d only (both forms,
                             both frames); other calls return GCB_EUNSUPPORTED */
+    int32_t mirror;      /* 1: add the mirror force and the grad-B drift that Sec. 2.2
+                            names and leaves out, with the step's mu (mu/m =
+                            u_perp_g^2/(2 B kappa) under GCB_GYRATION_MU):
+                            du_par/dt gains -(mu/(m kappa Gamma)) b.grad|B| and the
+                            bracket of the curvature drift (eq. curvdrift) gains
+                            (mu/(m kappa Gamma)) grad|B| -- grad(B/kappa) is taken as
+                            grad|B|/kappa, so with E = 0 these are the textbook
+                            relativistic terms.  The force is time-centred by one
+                            predictor-corrector pass on 1/Gamma (two solves of the
+                            parallel update); the conversions of Sec. 3.1 are
+                            unchanged.  Needs curvature = 1 (else GCB_EUNSUPPORTED);
+                            gcb_push and gcb_push_3d only, both forms; 0 (default):
+                            the paper's reduced equations */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.

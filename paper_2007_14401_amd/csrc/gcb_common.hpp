@@ -27,6 +27,15 @@ enum : int32_t {
     GYR_ZERO = 2,
 };
 
+// Variants of the guiding-center branch, one kernel instance each: the
+// paper's reduced frame, the exact frame of Sec. 2.2, and the reduced frame
+// with the mirror force and grad-B drift (gcb_params.frame and .mirror).
+enum : int {
+    kVarReduced = 0,
+    kVarExact = 1,
+    kVarMirror = 2,
+};
+
 // 1 - v_E^2/c^2 is clamped to this floor where the drift reaches c.
 constexpr double kKappaFloor = 1.0e-12;
 // |1 - (dt/2) v_E.(b.grad)b| below this: no division in the parallel update.

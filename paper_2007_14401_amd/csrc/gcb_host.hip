@@ -170,11 +170,16 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EINVAL, "unknown frame %d", prm->frame);
     if (prm->gyration < GCB_GYRATION_MU || prm->gyration > GCB_GYRATION_ZERO)
         return fail(ctx, GCB_EINVAL, "unknown gyration %d", prm->gyration);
+    if (prm->mirror != 0 && prm->mirror != 1)
+        return fail(ctx, GCB_EINVAL, "mirror must be 0 or 1");
+    if (prm->mirror && prm->curvature != 1)
+        return fail(ctx, GCB_EUNSUPPORTED, "the mirror terms need curvature = 1");
     return GCB_OK;
 }
 
-// the exact frame (curvature = 0, binary64) and the gyration options other
-// than a conserved mu are served by gcb_push and gcb_push_3d only
+// the exact frame (curvature = 0, binary64), the gyration options other
+// than a conserved mu and the mirror terms are served by gcb_push and
+// gcb_push_3d only
 int reject_push_options(gcb_ctx* ctx, const gcb_params* prm) {
     if (prm->frame != GCB_FRAME_REDUCED)
         return fail(ctx, GCB_EUNSUPPORTED,
@@ -183,6 +188,9 @@ int reject_push_options(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EUNSUPPORTED,
                     "gyration options other than GCB_GYRATION_MU are served by gcb_push and "
                     "gcb_push_3d only");
+    if (prm->mirror != 0)
+        return fail(ctx, GCB_EUNSUPPORTED,
+                    "the mirror terms are served by gcb_push and gcb_push_3d only");
     return GCB_OK;
 }
 
@@ -545,6 +553,7 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         L.stats = dstats;
         L.steps = ns;
         L.exact = prm->frame == GCB_FRAME_EXACT;
+        L.mirror = prm->mirror != 0;
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))
@@ -637,6 +646,7 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
         L.stats = dstats;
         L.steps = ns;
         L.exact = prm->frame == GCB_FRAME_EXACT;
+        L.mirror = prm->mirror != 0;
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))

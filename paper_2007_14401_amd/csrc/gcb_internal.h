@@ -35,6 +35,7 @@ struct PushLaunch {
     DevStats* stats;       // nullable
     int steps = 1;         // global kernel: steps per launch (trace: steps*n bytes)
     bool exact = false;    // guiding-center branch in the exact frame (binary64 only)
+    bool mirror = false;   // guiding-center branch with the mirror terms
 };
 
 // binary64 form (fields double, u double)
@@ -74,6 +75,7 @@ struct Push3Launch {
     DevStats* stats;       // nullable
     int steps = 1;         // global kernel: steps per launch
     bool exact = false;    // guiding-center branch in the exact frame (binary64 only)
+    bool mirror = false;   // guiding-center branch with the mirror terms
 };
 
 hipError_t launch_push3_f64(const Push3Launch& L, const ParticlePtrs3<double>& in,

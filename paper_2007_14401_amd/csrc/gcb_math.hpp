@@ -183,6 +183,7 @@ struct Local {
     R kappa, Epar;
     R bgb[3], vgb[3];
     R A, C;
+    R gB[3];   // grad|B| (the 2D step fills x, y)
 };
 
 // b, v_E, kappa and E_par from E and B at the point.
@@ -236,12 +237,13 @@ GCB_HD uint32_t local_fields(const R E[3], const R Bv[3], const Consts<R>& K, Lo
 }
 
 // d_j b_i = (d_j B_i - b_i (b . d_j B)) / B for one direction j, from the
-// gradient dB[i] = d_j B_i.
+// gradient dB[i] = d_j B_i; returns d_j|B| = b . d_j B.
 template <typename R>
-GCB_HD void db_along(const Local<R>& L, const R dB[3], R db[3]) {
+GCB_HD R db_along(const Local<R>& L, const R dB[3], R db[3]) {
     const R dn = (L.b[0] * dB[0] + L.b[1] * dB[1]) + L.b[2] * dB[2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) db[i] = (dB[i] - L.b[i] * dn) * L.inv_B;
+    return dn;
 }
 
 // A = v_E.(b.grad)b and C = v_E.(v_E.grad)b from L.bgb and L.vgb.
@@ -256,8 +258,9 @@ template <typename R>
 GCB_HD uint32_t local_from_sample(const Sample<R>& s, const Consts<R>& K, Local<R>& L) {
     const uint32_t flags = local_fields(s.E, s.B, K, L);
     R dbx[3], dby[3];
-    db_along(L, s.dBx, dbx);
-    db_along(L, s.dBy, dby);
+    L.gB[0] = db_along(L, s.dBx, dbx);
+    L.gB[1] = db_along(L, s.dBy, dby);
+    L.gB[2] = (R)0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         L.bgb[i] = L.b[0] * dbx[i] + L.b[1] * dby[i];
@@ -393,6 +396,26 @@ GCB_HD void v_curv(const Local<R>& L, R upar, R gam, R inv_qm,
     vc[2] = pre * (L.b[0] * w1 - L.b[1] * w0);
 }
 
+// Curvature drift with the grad-B drift in its bracket (the mirror option):
+// (m c kappa^2/(q B)) b x [ (u_par^2/Gamma)(b.grad)b + u_par (v_E.grad)b
+//                           + (mu/(m kappa Gamma)) grad|B| ]
+// with grad(B/kappa) taken as grad|B|/kappa; kND gradient components (2 or 3).
+template <int kND, typename R>
+GCB_HD void v_curv_mirror(const Local<R>& L, R upar, R gam, R inv_qm, R mu,
+                          const Consts<R>& K, R vc[3]) {
+    const R pre = ((K.c * L.kappa) * L.kappa) * (L.inv_B * inv_qm);
+    const R a1 = (upar * upar) / gam;
+    R w[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) w[i] = a1 * L.bgb[i] + upar * L.vgb[i];
+    const R a3 = (mu / L.kappa) / gam;
+#pragma unroll
+    for (int i = 0; i < kND; ++i) w[i] = w[i] + a3 * L.gB[i];
+    vc[0] = pre * (L.b[1] * w[2] - L.b[2] * w[1]);
+    vc[1] = pre * (L.b[2] * w[0] - L.b[0] * w[2]);
+    vc[2] = pre * (L.b[0] * w[1] - L.b[1] * w[0]);
+}
+
 // Lorentz factor of the full four-velocity
 template <typename R>
 GCB_HD R gamma_full(R ux, R uy, R uz, const Consts<R>& K) {
@@ -510,17 +533,21 @@ GCB_HD void boris_step(const Sample<R>& s, Regs<R>& r, const PushConst& pc,
 
 // u_par^{n-1/2} -> u_par^{n+1/2} at R^n.  With curvature: the positive root
 // of k1 G^2 + k2 G + k3 = 0 for G = Gamma(R^n, u_par^{n+1/2}), evaluated
-// without cancellation, then eq. dupardtcase2discsol.
+// without cancellation, then eq. dupardtcase2discsol.  With `shifted`, the
+// explicit change `shift` (the mirror force over the step) is subtracted
+// from the known part of the update.
 template <typename R>
 GCB_HD R parallel_update(const Local<R>& Ln, R upar, const Gyr<R>& gy, R qm,
                                              bool curvature, const Consts<R>& K,
-                                             uint32_t& flags) {
+                                             uint32_t& flags, bool shifted = false,
+                                             R shift = (R)0) {
     const R dtqm = qm * K.dt;
     if (!curvature) return upar + dtqm * Ln.Epar;
     const R h = K.h;
     const R A = Ln.A, C = Ln.C;
     const R G0 = gamma_gca(Ln, upar, gy, K);
-    const R upr = (upar * ((R)1 + h * A) + dtqm * Ln.Epar) + (h * G0) * C;
+    R upr = (upar * ((R)1 + h * A) + dtqm * Ln.Epar) + (h * G0) * C;
+    if (shifted) upr = upr - shift;
     const R D = (R)1 - h * A;
     const R DD = D * D;
     const R k1 = (h * h) * (C * C) - (K.c2 * DD) / (Ln.kappa * Ln.kappa);
@@ -543,19 +570,42 @@ GCB_HD R parallel_update(const Local<R>& Ln, R upar, const Gyr<R>& gy, R qm,
         const R gfb = gamma_gca(Ln, upr / Ds, gy, K);
         return (upr + (h * gfb) * C) / Ds;
     }
-    return upar + dtqm * Ln.Epar;
+    const R uexp = upar + dtqm * Ln.Epar;
+    return shifted ? uexp - shift : uexp;
 }
 
-// x, y components of u_par b / Gamma + v_E + v_c at a point.
+// The parallel update with the mirror force -(mu/(m kappa Gamma)) b.grad|B|
+// (the mirror option), Gamma centred by one predictor-corrector pass: the
+// predictor takes 1/Gamma(R^n, u_par^{n-1/2}), the corrector the mean of that
+// and 1/Gamma(R^n, u_par*) at the predictor's result u_par*.  Flags of both
+// passes are kept.  kND gradient components (2 or 3).
+template <int kND, typename R>
+GCB_HD R mirror_parallel(const Local<R>& Ln, R upar, const Gyr<R>& gy, R qm,
+                         const Consts<R>& K, uint32_t& flags) {
+    R M = Ln.b[0] * Ln.gB[0] + Ln.b[1] * Ln.gB[1];
+    if constexpr (kND == 3) M = M + Ln.b[2] * Ln.gB[2];
+    const R ds = (K.dt * (gy.mu / Ln.kappa)) * M;
+    const R G0 = gamma_gca(Ln, upar, gy, K);
+    const R u1 = parallel_update(Ln, upar, gy, qm, true, K, flags, true, ds / G0);
+    const R G1 = gamma_gca(Ln, u1, gy, K);
+    return parallel_update(Ln, upar, gy, qm, true, K, flags, true,
+                           ds * ((R)0.5 * ((R)1 / G0 + (R)1 / G1)));
+}
+
+// x, y components of u_par b / Gamma + v_E + v_c at a point (v_c with the
+// grad-B drift under the mirror option).
 template <typename R>
 GCB_HD void drift_terms(const Local<R>& L, R upn, const Gyr<R>& gy, R inv_qm,
                                             bool curvature, const Consts<R>& K, R& Fx,
-                                            R& Fy) {
+                                            R& Fy, bool mirror = false) {
     const R g = gamma_gca(L, upn, gy, K);
     const R a = upn / g;
     if (curvature) {
         R vc[3];
-        v_curv(L, upn, g, inv_qm, K, vc);
+        if (mirror)
+            v_curv_mirror<2>(L, upn, g, inv_qm, gy.mu, K, vc);
+        else
+            v_curv(L, upn, g, inv_qm, K, vc);
         Fx = (a * L.b[0] + L.vE[0]) + vc[0];
         Fy = (a * L.b[1] + L.vE[1]) + vc[1];
     } else {
@@ -572,13 +622,16 @@ GCB_HD double nan_max(double a, double b) {
 
 // One guiding-center step.  sn is the gather (with gradients) at x^n.
 // Returns status flags; res receives |R^K - R^{K-1}|_inf.
-// kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only).
-template <typename R, bool kYee, bool kExact = false, class Acc>
+// kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only);
+// kMirror: the mirror force and grad-B drift (curvature scheme only).
+template <typename R, bool kYee, bool kExact = false, bool kMirror = false, class Acc>
 GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
                                              const PushConst& pc, const Consts<R>& K,
                                              double& res) {
     uint32_t flags = 0;
     const bool curv = !kExact && pc.curvature != 0;
+    // the mirror terms ride on the curvature scheme (the host refuses others)
+    const bool mirror = kMirror && curv;
     const double x = r.x, y = r.y;
     const R ux = r.ux, uy = r.uy, uz = r.uz;
     const R qm = (R)r.qm;
@@ -617,8 +670,11 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     {
         Local<R> Ln;
         flags |= local_in_frame<kExact>(sn, K, Ln);
-        upn = parallel_update(Ln, upar, gy, qm, curv, K, flags);
-        drift_terms(Ln, upn, gy, inv_qm, curv, K, Fnx, Fny);
+        if (mirror)
+            upn = mirror_parallel<2>(Ln, upar, gy, qm, K, flags);
+        else
+            upn = parallel_update(Ln, upar, gy, qm, curv, K, flags);
+        drift_terms(Ln, upn, gy, inv_qm, curv, K, Fnx, Fny, mirror);
     }
 
     // 4. R^{n+1}: K fixed-point iterations R^{k+1} = R^k - H(R^k), R^0 = R^n
@@ -635,7 +691,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
             gather<R, true, kYee>(acc, pc, K, Rx, Ry, sk);
             Local<R> Lk;
             flags |= local_in_frame<kExact>(sk, K, Lk);
-            drift_terms(Lk, upn, gy, inv_qm, curv, K, Fkx, Fky);
+            drift_terms(Lk, upn, gy, inv_qm, curv, K, Fkx, Fky, mirror);
         }
         const double Rx_new = x + (double)(K.h * (Fnx + Fkx));
         const double Ry_new = y + (double)(K.h * (Fny + Fky));

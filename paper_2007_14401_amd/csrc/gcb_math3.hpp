@@ -161,9 +161,9 @@ template <typename R>
 GCB_HD uint32_t local_from_sample(const Sample3<R>& s, const Consts<R>& K, Local<R>& L) {
     const uint32_t flags = local_fields(s.E, s.B, K, L);
     R dbx[3], dby[3], dbz[3];
-    db_along(L, s.dBx, dbx);
-    db_along(L, s.dBy, dby);
-    db_along(L, s.dBz, dbz);
+    L.gB[0] = db_along(L, s.dBx, dbx);
+    L.gB[1] = db_along(L, s.dBy, dby);
+    L.gB[2] = db_along(L, s.dBz, dbz);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         L.bgb[i] = (L.b[0] * dbx[i] + L.b[1] * dby[i]) + L.b[2] * dbz[i];
@@ -173,15 +173,19 @@ GCB_HD uint32_t local_from_sample(const Sample3<R>& s, const Consts<R>& K, Local
     return flags;
 }
 
-// u_par b / Gamma + v_E + v_c at a point, three components
+// u_par b / Gamma + v_E + v_c at a point, three components (v_c with the
+// grad-B drift under the mirror option)
 template <typename R>
 GCB_HD void drift_terms3(const Local<R>& L, R upn, const Gyr<R>& gy, R inv_qm, bool curvature,
-                         const Consts<R>& K, R F[3]) {
+                         const Consts<R>& K, R F[3], bool mirror = false) {
     const R g = gamma_gca(L, upn, gy, K);
     const R a = upn / g;
     if (curvature) {
         R vc[3];
-        v_curv(L, upn, g, inv_qm, K, vc);
+        if (mirror)
+            v_curv_mirror<3>(L, upn, g, inv_qm, gy.mu, K, vc);
+        else
+            v_curv(L, upn, g, inv_qm, K, vc);
 #pragma unroll
         for (int i = 0; i < 3; ++i) F[i] = (a * L.b[i] + L.vE[i]) + vc[i];
     } else {
@@ -212,12 +216,15 @@ GCB_HD void boris_step3(const Sample3<R>& s, Regs3<R>& r, const PushConst3& pc,
 // One guiding-center step (Sec. 2.2.1 / 2.2.2 inside the coupled step of
 // Sec. 3.1).  sn is the gather (with gradients) at x^n.  Returns status
 // flags; res receives |R^K - R^{K-1}|_inf over the three components.
-// kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only).
-template <typename R, bool kYee, bool kExact = false, class Acc>
+// kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only);
+// kMirror: the mirror force and grad-B drift (curvature scheme only).
+template <typename R, bool kYee, bool kExact = false, bool kMirror = false, class Acc>
 GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
                           const PushConst3& pc, const Consts3<R>& K, double& res) {
     uint32_t flags = 0;
     const bool curv = !kExact && pc.b.curvature != 0;
+    // the mirror terms ride on the curvature scheme (the host refuses others)
+    const bool mirror = kMirror && curv;
     const double x[3] = {r.x, r.y, r.z};
     const double xprev[3] = {r.xp, r.yp, r.zp};
     const double box[3] = {pc.b.Lx, pc.b.Ly, pc.Lz};
@@ -259,8 +266,11 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
     {
         Local<R> Ln;
         flags |= local_in_frame<kExact, R>(sn, K, Ln);
-        upn = parallel_update(Ln, upar, gy, qm, curv, K, flags);
-        drift_terms3(Ln, upn, gy, inv_qm, curv, K, Fn);
+        if (mirror)
+            upn = mirror_parallel<3>(Ln, upar, gy, qm, K, flags);
+        else
+            upn = parallel_update(Ln, upar, gy, qm, curv, K, flags);
+        drift_terms3(Ln, upn, gy, inv_qm, curv, K, Fn, mirror);
     }
 
     // 4. R^{n+1}: K fixed-point iterations R^{k+1} = R^k - H(R^k), R^0 = R^n
@@ -277,7 +287,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
             gather3<R, true, kYee>(acc, pc, K, Rp[0], Rp[1], Rp[2], sk);
             Local<R> Lk;
             flags |= local_in_frame<kExact, R>(sk, K, Lk);
-            drift_terms3(Lk, upn, gy, inv_qm, curv, K, Fk);
+            drift_terms3(Lk, upn, gy, inv_qm, curv, K, Fk, mirror);
         }
         double d[3];
 #pragma unroll

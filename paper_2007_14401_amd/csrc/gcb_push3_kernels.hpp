@@ -59,7 +59,7 @@ __device__ __forceinline__ void store_particle3(const ParticlePtrs3<R>& in,
     }
 }
 
-template <typename R, bool kYee, bool kExact, class Acc>
+template <typename R, bool kYee, int kVar, class Acc>
 __device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Regs3<R>& r,
                                                     const PushConst3& pc, const Consts3<R>& K,
                                                     double& res) {
@@ -68,7 +68,7 @@ __device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Re
     Sample3<R> s;
     if (gca) {
         gather3<R, true, kYee>(acc, pc, K, r.x, r.y, r.z, s);
-        fl = gca_step3<R, kYee, kExact>(acc, s, r, pc, K, res);
+        fl = gca_step3<R, kYee, kVar == kVarExact, kVar == kVarMirror>(acc, s, r, pc, K, res);
     } else {
         gather3<R, false, kYee>(acc, pc, K, r.x, r.y, r.z, s);
         boris_step3(s, r, pc, K);
@@ -76,7 +76,7 @@ __device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Re
     return fl | finite_flag3(r);
 }
 
-template <typename R, typename T, bool kYee, bool kExact>
+template <typename R, typename T, bool kYee, int kVar>
 __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
                                                        ParticlePtrs3<R> out,
                                                        const uint32_t* __restrict__ perm,
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
                 gca = switch_gca(smp.E, smp.B, r.ux, r.uy, r.uz, r.qm, pc.b, K);
             }
             double res;
-            fl |= coupled_update3<R, kYee, kExact>(acc, gca, r, pc, K, res);
+            fl |= coupled_update3<R, kYee, kVar>(acc, gca, r, pc, K, res);
             if (tr && !replay) tr[ti] = gca ? 0 : 1;
             if (gca) {
                 ++cnt_g;
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
     if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
-template <typename R, typename T, bool kYee, int kMinWaves, bool kExact>
+template <typename R, typename T, bool kYee, int kMinWaves, int kVar>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const uint32_t* __restrict__ perm,
               const int32_t* __restrict__ tile_start, TileGeom3 g, int chunk,
@@ -195,7 +195,7 @@ k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const uint32_t* __restr
             load_particle3(in, src, pc.b.qm, r);
             acc.miss = false;
             double res;
-            uint32_t fl = coupled_update3<R, kYee, kExact>(acc, gca, r, pc, K, res);
+            uint32_t fl = coupled_update3<R, kYee, kVar>(acc, gca, r, pc, K, res);
             if (acc.miss) {
                 fl |= ST_HALO;
                 ++cnt_h;
@@ -214,7 +214,7 @@ k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const uint32_t* __restr
     if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
 }
 
-template <typename R, typename T, int kMinWaves, bool kExact>
+template <typename R, typename T, int kMinWaves, int kVar>
 hipError_t launch_push3_frame(const Push3Launch& L, const ParticlePtrs3<R>& in,
                               const ParticlePtrs3<R>& out, const PushConst3& pc,
                               hipStream_t stream) {
@@ -223,11 +223,11 @@ hipError_t launch_push3_frame(const Push3Launch& L, const ParticlePtrs3<R>& in,
         const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
         const int ns = L.steps > 0 ? L.steps : 1;
         if (L.yee)
-            hipLaunchKernelGGL((k_push3_global<R, T, true, kExact>), dim3(blocks), dim3(kWG), 0,
+            hipLaunchKernelGGL((k_push3_global<R, T, true, kVar>), dim3(blocks), dim3(kWG), 0,
                                stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
                                L.stats);
         else
-            hipLaunchKernelGGL((k_push3_global<R, T, false, kExact>), dim3(blocks), dim3(kWG),
+            hipLaunchKernelGGL((k_push3_global<R, T, false, kVar>), dim3(blocks), dim3(kWG),
                                0, stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
                                L.stats);
         return hipGetLastError();
@@ -236,13 +236,13 @@ hipError_t launch_push3_frame(const Push3Launch& L, const ParticlePtrs3<R>& in,
     const int chunk = (ntiles + 7) / 8;
     const size_t lds = tiled3_lds_bytes(L.geom.window, sizeof(T));
     if (L.yee) {
-        auto kfn = k_push3_tiled<R, T, true, kMinWaves, kExact>;
+        auto kfn = k_push3_tiled<R, T, true, kMinWaves, kVar>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay, L.stats);
     } else {
-        auto kfn = k_push3_tiled<R, T, false, kMinWaves, kExact>;
+        auto kfn = k_push3_tiled<R, T, false, kMinWaves, kVar>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
@@ -258,11 +258,12 @@ hipError_t launch_push3(const Push3Launch& L, const ParticlePtrs3<R>& in,
                         const ParticlePtrs3<R>& out, const PushConst3& pc, hipStream_t stream) {
     if (L.n == 0) return hipSuccess;
     if constexpr (!kMixed<R>) {
-        if (L.exact) return launch_push3_frame<R, T, kMinWaves, true>(L, in, out, pc, stream);
+        if (L.exact) return launch_push3_frame<R, T, kMinWaves, kVarExact>(L, in, out, pc, stream);
     } else {
         if (L.exact) return hipErrorInvalidValue;
     }
-    return launch_push3_frame<R, T, kMinWaves, false>(L, in, out, pc, stream);
+    if (L.mirror) return launch_push3_frame<R, T, kMinWaves, kVarMirror>(L, in, out, pc, stream);
+    return launch_push3_frame<R, T, kMinWaves, kVarReduced>(L, in, out, pc, stream);
 }
 
 }  // namespace kern

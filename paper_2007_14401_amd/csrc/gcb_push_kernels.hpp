@@ -133,9 +133,10 @@ __device__ __forceinline__ int split_queues(int m, uint16_t* queue, int* wave_g,
     return nG;
 }
 
-// one coupled step for a particle already in registers (kExact: the
-// guiding-center branch in the exact frame of Sec. 2.2)
-template <typename R, bool kYee, bool kExact, class Acc>
+// one coupled step for a particle already in registers (kVar: the
+// guiding-center branch in the paper's reduced frame, in the exact frame of
+// Sec. 2.2, or with the mirror terms)
+template <typename R, bool kYee, int kVar, class Acc>
 __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Regs<R>& r,
                                                    const PushConst& pc, const Consts<R>& K,
                                                    double& res) {
@@ -144,7 +145,7 @@ __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Reg
     if (gca) {
         Sample<R> s;
         gather<R, true, kYee>(acc, pc, K, r.x, r.y, s);
-        fl = gca_step<R, kYee, kExact>(acc, s, r, pc, K, res);
+        fl = gca_step<R, kYee, kVar == kVarExact, kVar == kVarMirror>(acc, s, r, pc, K, res);
     } else {
         Sample<R> s;
         gather<R, false, kYee>(acc, pc, K, r.x, r.y, s);
@@ -155,7 +156,7 @@ __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Reg
 
 // ns steps of one particle per lane (the particle stays in registers between
 // them); trace (per step n bytes) is indexed by id when ids are present
-template <typename R, typename T, bool kYee, bool kExact>
+template <typename R, typename T, bool kYee, int kVar>
 __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, ParticlePtrs<R> out,
                                                       const uint32_t* __restrict__ perm,
                                                       int64_t n, int ns, const T* __restrict__ F,
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
                 gca = switch_gca(smp.E, smp.B, r.ux, r.uy, r.uz, r.qm, pc, K);
             }
             double res;
-            fl |= coupled_update<R, kYee, kExact>(acc, gca, r, pc, K, res);
+            fl |= coupled_update<R, kYee, kVar>(acc, gca, r, pc, K, res);
             if (tr && !replay) tr[ti] = gca ? 0 : 1;
             if (gca) {
                 ++cnt_g;
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
     if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
-template <typename R, typename T, bool kYee, int kMinWaves, bool kExact>
+template <typename R, typename T, bool kYee, int kMinWaves, int kVar>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict__ perm,
              const int32_t* __restrict__ tile_start, TileGeom g, int chunk,
@@ -268,7 +269,7 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict
             load_particle(in, src, pc.qm, r);
             acc.miss = false;
             double res;
-            uint32_t fl = coupled_update<R, kYee, kExact>(acc, gca, r, pc, K, res);
+            uint32_t fl = coupled_update<R, kYee, kVar>(acc, gca, r, pc, K, res);
             if (acc.miss) {
                 fl |= ST_HALO;
                 ++cnt_h;
@@ -287,7 +288,7 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict
     if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
 }
 
-template <typename R, typename T, int kMinWaves, bool kExact>
+template <typename R, typename T, int kMinWaves, int kVar>
 hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
                              const ParticlePtrs<R>& out, const PushConst& pc,
                              hipStream_t stream) {
@@ -296,11 +297,11 @@ hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
         const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
         const int ns = L.steps > 0 ? L.steps : 1;
         if (L.yee)
-            hipLaunchKernelGGL((k_push_global<R, T, true, kExact>), dim3(blocks), dim3(kWG), 0,
+            hipLaunchKernelGGL((k_push_global<R, T, true, kVar>), dim3(blocks), dim3(kWG), 0,
                                stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
                                L.stats);
         else
-            hipLaunchKernelGGL((k_push_global<R, T, false, kExact>), dim3(blocks), dim3(kWG), 0,
+            hipLaunchKernelGGL((k_push_global<R, T, false, kVar>), dim3(blocks), dim3(kWG), 0,
                                stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
                                L.stats);
         return hipGetLastError();
@@ -309,14 +310,14 @@ hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
     const int chunk = (ntiles + 7) / 8;
     const size_t lds = tiled_lds_bytes(L.geom.window, sizeof(T));
     if (L.yee) {
-        auto kfn = k_push_tiled<R, T, true, kMinWaves, kExact>;
+        auto kfn = k_push_tiled<R, T, true, kMinWaves, kVar>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay,
                            L.stats);
     } else {
-        auto kfn = k_push_tiled<R, T, false, kMinWaves, kExact>;
+        auto kfn = k_push_tiled<R, T, false, kMinWaves, kVar>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
@@ -333,11 +334,12 @@ hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
                        const ParticlePtrs<R>& out, const PushConst& pc, hipStream_t stream) {
     if (L.n == 0) return hipSuccess;
     if constexpr (!kMixed<R>) {
-        if (L.exact) return launch_push_frame<R, T, kMinWaves, true>(L, in, out, pc, stream);
+        if (L.exact) return launch_push_frame<R, T, kMinWaves, kVarExact>(L, in, out, pc, stream);
     } else {
         if (L.exact) return hipErrorInvalidValue;
     }
-    return launch_push_frame<R, T, kMinWaves, false>(L, in, out, pc, stream);
+    if (L.mirror) return launch_push_frame<R, T, kMinWaves, kVarMirror>(L, in, out, pc, stream);
+    return launch_push_frame<R, T, kMinWaves, kVarReduced>(L, in, out, pc, stream);
 }
 
 }  // namespace kern

@@ -102,7 +102,8 @@ def test_adjoint3_argument_checks():
         desc = gcb.grid3_desc(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dz, cfg.stagger,
                               gcb.GCB_F64)
         gcb.gcb_load_fields_3d(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
-        for bad in (dict(gyration=1), dict(frame=1, curvature=0), dict(n_iter=9)):
+        for bad in (dict(gyration=1), dict(frame=1, curvature=0), dict(n_iter=9),
+                    dict(mirror=1)):
             with pytest.raises(gcb.GcbError) as e:
                 gcb.gcb_push_backward_3d(ctx, gcb.particles3(t), gcb.params(**bad), 1, lam,
                                          out, grid[:3], grid[3:])
