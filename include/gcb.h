@@ -93,6 +93,10 @@ extern "C" {
                                  and was served from global memory (same values)         */
 #define GCB_ST_OUT      64    /* curved-spacetime push: the particle left the (r, theta)
                                  domain and is no longer advanced                        */
+#define GCB_ST_MIRROR  128    /* (v_perp_g/c)^2 = u_perp_g^2/(Gamma^2 c^2) at a guiding-center
+                                 decomposition exceeded gcb_params.mirror_tol: the mirror
+                                 terms the reduced equations leave out may not be
+                                 negligible (the check Sec. 2.2 asks for)               */
 
 typedef struct gcb_ctx gcb_ctx;
 
@@ -177,6 +181,13 @@ typedef struct {
                             unchanged.  Needs curvature = 1 (else GCB_EUNSUPPORTED);
                             gcb_push and gcb_push_3d only, both forms; 0 (default):
                             the paper's reduced equations */
+    double  mirror_tol;  /* > 0: set GCB_ST_MIRROR where (v_perp_g/c)^2 exceeds this at a
+                            guiding-center decomposition (Gamma of the full u), the
+                            validity check of leaving out (or of the size of) the mirror
+                            terms, whose ratio to the curvature terms grows as
+                            v_perp_g^2 (Sec. 2.2); 0 (default): no check.  Finite and
+                            >= 0 (else GCB_EINVAL); gcb_push and gcb_push_3d only (other
+                            calls return GCB_EUNSUPPORTED for a value other than 0) */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.
@@ -200,8 +211,8 @@ typedef struct {
     int64_t flagged;         /* particles with any status bit other than GCB_ST_HALO at the end */
     int64_t halo_misses;     /* particle-steps with a gather outside the LDS window */
     double  max_fp_residual; /* max over guiding-center steps of |R^K - R^{K-1}|_inf */
-    int64_t status_counts[7];/* particles with status bit 2^k set at the end, k = 0..6
-                                (GCB_ST_NONFINITE ... GCB_ST_OUT) */
+    int64_t status_counts[8];/* particles with status bit 2^k set at the end, k = 0..7
+                                (GCB_ST_NONFINITE ... GCB_ST_MIRROR) */
 } gcb_stats;
 
 /* Advance the particles by n_steps steps of the coupled scheme (Sec. 3.1):

@@ -42,7 +42,7 @@ from .pusher import (Params, State, ST_NONFINITE, ST_KAPPA, ST_QUAD, ST_BZERO,
                      ST_FPRES, local, gamma_gca, v_curv, switch_gca, boris,
                      gca_step, step, push, wrap, min_image, parallel_update,
                      GYR_MU, GYR_UPERP, GYR_ZERO, gyration, conserved_mu, uperp_sq,
-                     mirror_parallel)
+                     mirror_parallel, mirror_check, ST_MIRROR)
 from .loss import kinetic_energy, push_gradients, push_gradients3
 from .fields3d import (GridFields3, UniformFields3, LinearFields3, CircularFieldsXZ,
                        FieldSample3, YEE3, COLLOCATED3)
@@ -59,5 +59,5 @@ __all__ = [
     "YEE3", "COLLOCATED3", "Params3", "State3", "local3", "boris_step3", "gca_step3",
     "step3", "push3", "exact_frame", "local_exact",
     "GYR_MU", "GYR_UPERP", "GYR_ZERO", "gyration", "conserved_mu", "uperp_sq",
-    "mirror_parallel",
+    "mirror_parallel", "mirror_check", "ST_MIRROR",
 ]

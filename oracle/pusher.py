@@ -53,6 +53,9 @@ design notes of the repository):
     relativistic terms).  The force is time-centred by one
     predictor-corrector pass on 1/Gamma; the decomposition and the
     reconstruction keep the paper's u_perp_d = Gamma (v_E + v_c).
+  * Params.mirror_tol (> 0): the check of the neglect of the mirror terms
+    that Sec. 2.2 asks for, as a status bit: ST_MIRROR where
+    (v_perp_g/c)^2 = u_perp_g^2/(Gamma^2 c^2) at a decomposition exceeds it.
 """
 from __future__ import annotations
 
@@ -71,6 +74,7 @@ ST_KAPPA = 2       # v_E >= c at a guiding-center evaluation (kappa clamped)
 ST_QUAD = 4        # no admissible root of the parallel-update quadratic
 ST_BZERO = 8       # B = 0 at a guiding-center evaluation point
 ST_FPRES = 16      # fixed-point iteration error above tolerance
+ST_MIRROR = 128    # (v_perp_g/c)^2 above Params.mirror_tol at a decomposition
 
 # gyration handling of a guiding-center step (Params.gyration)
 GYR_MU = 0      # mu conserved (eq. dmudt)
@@ -96,6 +100,7 @@ class Params:
     exact_frame: bool = False   # b*, exact v_E (frame.py); zero-curvature scheme only
     gyration: int = GYR_MU      # GYR_MU, GYR_UPERP or GYR_ZERO
     mirror: bool = False        # mirror force and grad-B drift (curvature scheme only)
+    mirror_tol: float = 0.0     # > 0: flag ST_MIRROR where (v_perp_g/c)^2 exceeds it
 
     @property
     def c2(self) -> float:
@@ -214,6 +219,16 @@ def gyration(up2, Lh, p: Params):
     if p.gyration == GYR_ZERO:
         mu = torch.zeros_like(mu)
     return SimpleNamespace(mu=mu, up2=up2, fixed=p.gyration == GYR_UPERP)
+
+
+def mirror_check(up2, gf, p: Params):
+    """ST_MIRROR where (v_perp_g/c)^2 = u_perp_g^2/(Gamma^2 c^2) exceeds
+    p.mirror_tol (> 0) at the decomposition, Gamma of the full u: the check
+    Sec. 2.2 asks for of the neglect of the mirror terms, whose size against
+    the curvature terms grows as v_perp_g^2."""
+    if not p.mirror_tol > 0.0:
+        return torch.zeros_like(up2, dtype=torch.uint8)
+    return torch.where(up2 * p.inv_c2 > p.mirror_tol * (gf * gf), ST_MIRROR, 0).to(torch.uint8)
 
 
 def conserved_mu(mu):
@@ -424,6 +439,7 @@ def gca_step(prov, st: State, p: Params):
     upy = (uy - upar * by) - (Lh.vE[1] + vc[1]) * gf
     upz = (uz - upar * bz) - (Lh.vE[2] + vc[2]) * gf
     up2 = (upx * upx + upy * upy) + upz * upz
+    flags |= mirror_check(up2, gf, p)
     gy = gyration(up2, Lh, p)
     nu = sqrt(up2)
     inv_nu = torch.where(nu > 0.0, 1.0 / torch.where(nu > 0.0, nu, 1.0), 0.0)

@@ -24,7 +24,7 @@ import torch
 
 from .ieee import sqrt
 from .pusher import (D_FLOOR, KAPPA_FLOOR, ST_BZERO, ST_FPRES, ST_KAPPA, ST_NONFINITE,
-                     Params, boris, gamma_gca, gyration, min_image, mirror_parallel,
+                     Params, boris, gamma_gca, gyration, min_image, mirror_check, mirror_parallel,
                      parallel_update, switch_gca, uperp_sq, v_curv, wrap)
 
 F64 = torch.float64
@@ -175,6 +175,7 @@ def gca_step3(prov, st: State3, p: Params3):
     upy = (uy - upar * by) - (Lh.vE[1] + vc[1]) * gf
     upz = (uz - upar * bz) - (Lh.vE[2] + vc[2]) * gf
     up2 = (upx * upx + upy * upy) + upz * upz
+    flags |= mirror_check(up2, gf, p)
     gy = gyration(up2, Lh, p)
     nu = sqrt(up2)
     inv_nu = torch.where(nu > 0.0, 1.0 / torch.where(nu > 0.0, nu, 1.0), 0.0)

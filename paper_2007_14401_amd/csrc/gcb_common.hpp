@@ -17,6 +17,7 @@ enum : uint32_t {
     ST_BZERO = 8,
     ST_FPRES = 16,
     ST_HALO = 32,
+    ST_MIRROR = 128,
 };
 
 // Gyration handling of a guiding-center step (the values of
@@ -55,6 +56,7 @@ struct PushConst {
     int32_t nx, ny;
     int32_t curvature, n_iter;
     int32_t gyration, pad_;  // GYR_*
+    double mirror_tol;       // > 0: ST_MIRROR where (v_perp_g/c)^2 exceeds it
 };
 
 // Device pointers of a structure-of-arrays particle state.

@@ -174,12 +174,14 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EINVAL, "mirror must be 0 or 1");
     if (prm->mirror && prm->curvature != 1)
         return fail(ctx, GCB_EUNSUPPORTED, "the mirror terms need curvature = 1");
+    if (!(std::isfinite(prm->mirror_tol) && prm->mirror_tol >= 0.0))
+        return fail(ctx, GCB_EINVAL, "mirror_tol must be finite and >= 0");
     return GCB_OK;
 }
 
 // the exact frame (curvature = 0, binary64), the gyration options other
-// than a conserved mu and the mirror terms are served by gcb_push and
-// gcb_push_3d only
+// than a conserved mu, the mirror terms and their check are served by gcb_push
+// and gcb_push_3d only
 int reject_push_options(gcb_ctx* ctx, const gcb_params* prm) {
     if (prm->frame != GCB_FRAME_REDUCED)
         return fail(ctx, GCB_EUNSUPPORTED,
@@ -188,9 +190,10 @@ int reject_push_options(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EUNSUPPORTED,
                     "gyration options other than GCB_GYRATION_MU are served by gcb_push and "
                     "gcb_push_3d only");
-    if (prm->mirror != 0)
+    if (prm->mirror != 0 || prm->mirror_tol != 0.0)
         return fail(ctx, GCB_EUNSUPPORTED,
-                    "the mirror terms are served by gcb_push and gcb_push_3d only");
+                    "the mirror terms and their check are served by gcb_push and gcb_push_3d "
+                    "only");
     return GCB_OK;
 }
 
@@ -299,6 +302,7 @@ PushConst physics_const(const gcb_params* prm) {
     pc.curvature = prm->curvature;
     pc.n_iter = prm->n_iter;
     pc.gyration = prm->gyration;
+    pc.mirror_tol = prm->mirror_tol;
     return pc;
 }
 
@@ -405,7 +409,8 @@ int prepare_sort(gcb_ctx* ctx, int64_t n, int ntiles, SortBuffers& sb) {
     return GCB_OK;
 }
 
-constexpr size_t kStatBytes = kStatSlots * sizeof(DevStats) + sizeof(DevStats);
+// the slots, then the flagged count and eight status-bit counts
+constexpr size_t kStatBytes = kStatSlots * sizeof(DevStats) + 9 * sizeof(unsigned long long);
 
 // zero the device accumulators of a push that reports statistics
 int stats_begin(gcb_ctx* ctx, const gcb_stats* stats, hipStream_t stream, DevStats** dstats) {
@@ -423,12 +428,11 @@ int stats_end(gcb_ctx* ctx, const uint8_t* status, int64_t n, gcb_stats* stats,
               hipStream_t stream) {
     if (!stats) return GCB_OK;
     DevStats* dstats = static_cast<DevStats*>(ctx->stats.ptr);
-    // the flagged count and the status-bit counts go to the eight words after
-    // the slots
-    static_assert(sizeof(DevStats) >= 8 * sizeof(unsigned long long), "status counters");
+    // the flagged count and the eight status-bit counts go to the nine words
+    // after the slots
     unsigned long long* flagged = reinterpret_cast<unsigned long long*>(dstats + kStatSlots);
     GCB_HIP(launch_count_flagged(status, n, flagged, stream));
-    std::vector<DevStats> host(kStatSlots + 1);
+    std::vector<DevStats> host(kStatSlots + 2);
     GCB_HIP(hipMemcpyAsync(host.data(), dstats, kStatBytes, hipMemcpyDeviceToHost, stream));
     GCB_HIP(hipStreamSynchronize(stream));
     unsigned long long g = 0, b = 0, h = 0, mbits = 0;
@@ -445,10 +449,10 @@ int stats_end(gcb_ctx* ctx, const uint8_t* status, int64_t n, gcb_stats* stats,
     double m;
     std::memcpy(&m, &mbits, sizeof(m));
     stats->max_fp_residual = m;
-    unsigned long long extra[8];
+    unsigned long long extra[9];
     std::memcpy(extra, &host[kStatSlots], sizeof(extra));
     stats->flagged = (int64_t)extra[0];
-    for (int k = 0; k < 7; ++k) stats->status_counts[k] = (int64_t)extra[1 + k];
+    for (int k = 0; k < 8; ++k) stats->status_counts[k] = (int64_t)extra[1 + k];
     return GCB_OK;
 }
 

@@ -614,6 +614,15 @@ GCB_HD void drift_terms(const Local<R>& L, R upn, const Gyr<R>& gy, R inv_qm,
     }
 }
 
+// The check of the neglect of the mirror terms (Sec. 2.2): ST_MIRROR where
+// (v_perp_g/c)^2 = u_perp_g^2/(Gamma^2 c^2) exceeds pc.mirror_tol (> 0) at
+// the decomposition, Gamma of the full four-velocity.
+template <typename R>
+GCB_HD uint32_t mirror_check(R up2, R gf, const PushConst& pc, const Consts<R>& K) {
+    if (!(pc.mirror_tol > 0.0)) return 0u;
+    return up2 * K.inv_c2 > (R)pc.mirror_tol * (gf * gf) ? (uint32_t)ST_MIRROR : 0u;
+}
+
 GCB_HD double nan_max(double a, double b) {
     if (a != a) return a;
     if (b != b) return b;
@@ -655,6 +664,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
         const R upy = (uy - upar * Lh.b[1]) - (Lh.vE[1] + vc[1]) * gf;
         const R upz = (uz - upar * Lh.b[2]) - (Lh.vE[2] + vc[2]) * gf;
         const R up2 = (upx * upx + upy * upy) + upz * upz;
+        flags |= mirror_check(up2, gf, pc, K);
         gy.mu = pc.gyration == GYR_ZERO ? (R)0 : (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
         gy.up2 = up2;
         gy.fixed = pc.gyration == GYR_UPERP;

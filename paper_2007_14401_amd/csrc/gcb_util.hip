@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kWG) void k_count_flagged(const uint8_t* __restrict
     const unsigned long long b = __ballot((v & ~(uint8_t)ST_HALO) != 0);
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < 8; ++k) {
         const unsigned long long m = __ballot((v >> k) & 1);
         if ((threadIdx.x & 63) == 0 && m) atomicAdd(out + 1 + k, (unsigned long long)__popcll(m));
     }

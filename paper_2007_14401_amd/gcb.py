@@ -33,6 +33,7 @@ GCB_FRAME_REDUCED, GCB_FRAME_EXACT = 0, 1
 GCB_GYRATION_MU, GCB_GYRATION_UPERP, GCB_GYRATION_ZERO = 0, 1, 2
 GCB_ST_NONFINITE, GCB_ST_KAPPA, GCB_ST_QUAD, GCB_ST_BZERO, GCB_ST_FPRES, GCB_ST_HALO = 1, 2, 4, 8, 16, 32
 GCB_ST_OUT = 64
+GCB_ST_MIRROR = 128
 GCB_TIMER_PUSH, GCB_TIMER_SORT, GCB_TIMER_BACKWARD, GCB_TIMER_OTHER = 0, 1, 2, 3
 GCB_NTIMERS = 4
 
@@ -59,7 +60,7 @@ class gcb_params(C.Structure):
                 ("curvature", C.c_int32), ("n_iter", C.c_int32), ("form", C.c_int32),
                 ("sort_every", C.c_int32), ("kernel", C.c_int32), ("tile", C.c_int32),
                 ("replay", C.c_int32), ("frame", C.c_int32), ("gyration", C.c_int32),
-                ("mirror", C.c_int32)]
+                ("mirror", C.c_int32), ("mirror_tol", C.c_double)]
 
 
 class gcb_particles(C.Structure):
@@ -72,7 +73,7 @@ class gcb_particles(C.Structure):
 class gcb_stats(C.Structure):
     _fields_ = [("gca_steps", C.c_int64), ("boris_steps", C.c_int64),
                 ("flagged", C.c_int64), ("halo_misses", C.c_int64),
-                ("max_fp_residual", C.c_double), ("status_counts", C.c_int64 * 7)]
+                ("max_fp_residual", C.c_double), ("status_counts", C.c_int64 * 8)]
 
 
 class gcb_gr_desc(C.Structure):
@@ -230,13 +231,13 @@ def gcb_load_fields(ctx, desc: gcb_grid_desc, E, B, src=None, stream=None) -> No
 def params(dt=1.0, c=0.45, qm=-1.0, f_rho=0.4, f_E=1.0, fp_tol=1e-7, curvature=1,
            n_iter=4, form=GCB_FORM_F64, sort_every=0, kernel=GCB_KERNEL_AUTO,
            tile=0, replay=0, frame=GCB_FRAME_REDUCED,
-           gyration=GCB_GYRATION_MU, mirror=0) -> gcb_params:
+           gyration=GCB_GYRATION_MU, mirror=0, mirror_tol=0.0) -> gcb_params:
     p = gcb_params()
     p.dt, p.c, p.qm, p.f_rho, p.f_E, p.fp_tol = dt, c, qm, f_rho, f_E, fp_tol
     p.curvature, p.n_iter, p.form = int(curvature), int(n_iter), int(form)
     p.sort_every, p.kernel, p.tile = int(sort_every), int(kernel), int(tile)
     p.replay, p.frame, p.gyration = int(replay), int(frame), int(gyration)
-    p.mirror = int(mirror)
+    p.mirror, p.mirror_tol = int(mirror), float(mirror_tol)
     return p
 
 

@@ -16,6 +16,7 @@ from workloads import make_config, make_config3
 pytestmark = pytest.mark.gpu
 
 UPERP = 1
+TOL_CHECK = 1e-3   # (v_perp_g/c)^2 threshold of the check of the neglect
 
 
 @pytest.fixture(scope="module")
@@ -31,18 +32,41 @@ def h64():
                                                           (1, 0, 0, 20), (2, 3, 24, 20)])
 def test_mirror_parity(h64, kernel, sort_every, tile, steps):
     """Harris sheet, mu conserved; tile 24 leaves a ragged last tile on the
-    64-cell grid."""
-    from paper_2007_14401_amd import state
+    64-cell grid.  The check of the neglect (mirror_tol) runs alongside: its
+    status bit is part of the bitwise status comparison and of the
+    histogram."""
+    from paper_2007_14401_amd import gcb, state
     cfg, F, run = h64
     ens = cfg.particles(n=4096 + 37, seed_offset=15)
     log(f"mirror kernel={kernel} sort_every={sort_every} tile={tile} steps={steps}")
     t = state.to_device(ens, "cuda:0")
     tr, st = run.push(t, steps, trace=True, stats=True, kernel=kernel, sort_every=sort_every,
-                      tile=tile, mirror=1)
-    ref, rtr, rres = run_oracle(cfg, F, ens, steps, trace=True, mirror=True)
+                      tile=tile, mirror=1, mirror_tol=TOL_CHECK)
+    ref, rtr, rres = run_oracle(cfg, F, ens, steps, trace=True, mirror=True,
+                                mirror_tol=TOL_CHECK)
     _check(state.unsort(t), ref, cfg, "mirror", tr, rtr)
     assert st["gca_steps"] == int((rtr == 0).sum()) > 0
     assert st["max_fp_residual"] == float(rres.max())
+    flagged = int(((ref.status.numpy() & gcb.GCB_ST_MIRROR) != 0).sum())
+    assert st["status_counts"][7] == flagged
+    log(f"  mirror check: {flagged} of {ens.n} particles above (v_perp_g/c)^2 = {TOL_CHECK}")
+    assert 0 < flagged < ens.n
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(1, 0, 0), (2, 2, 24)])
+def test_mirror_check_on_the_reduced_equations(h64, kernel, sort_every, tile):
+    """The check of the neglect on the paper's own equations (mirror = 0),
+    binary64, 10 steps: status bits bit for bit with the oracle."""
+    from paper_2007_14401_amd import gcb, state
+    cfg, F, run = h64
+    ens = cfg.particles(n=4096 + 11, seed_offset=20)
+    t = state.to_device(ens, "cuda:0")
+    tr, st = run.push(t, 10, trace=True, stats=True, kernel=kernel, sort_every=sort_every,
+                      tile=tile, mirror_tol=TOL_CHECK)
+    ref, rtr, _ = run_oracle(cfg, F, ens, 10, trace=True, mirror_tol=TOL_CHECK)
+    _check(state.unsort(t), ref, cfg, "mirror check", tr, rtr)
+    flagged = int(((ref.status.numpy() & gcb.GCB_ST_MIRROR) != 0).sum())
+    assert st["status_counts"][7] == flagged and 0 < flagged < ens.n
 
 
 def test_mirror_with_held_uperp(h64):
@@ -83,8 +107,9 @@ def test_mirror_parity_3d(kernel, sort_every, tile, steps):
         log(f"3d mirror kernel={kernel} steps={steps}")
         t = _state3(ens)
         tr, st = run.push(t, steps, trace=True, stats=True, kernel=kernel,
-                          sort_every=sort_every, tile=tile, mirror=1)
-        ref, rtr, _ = run_oracle3(cfg, F, ens, steps, trace=True, mirror=True)
+                          sort_every=sort_every, tile=tile, mirror=1, mirror_tol=TOL_CHECK)
+        ref, rtr, _ = run_oracle3(cfg, F, ens, steps, trace=True, mirror=True,
+                                  mirror_tol=TOL_CHECK)
         _check3(state.unsort(t), ref, cfg, "3d mirror", tr, rtr)
         assert st["gca_steps"] > 0
     finally:
@@ -132,6 +157,8 @@ def test_mirror_argument_checks(h64):
     cfg, F, run = h64
     t = state.to_device(cfg.particles(n=64), "cuda:0")
     for bad, code in ((dict(mirror=2), gcb.GCB_EINVAL), (dict(mirror=-1), gcb.GCB_EINVAL),
+                      (dict(mirror_tol=-1e-3), gcb.GCB_EINVAL),
+                      (dict(mirror_tol=float("nan")), gcb.GCB_EINVAL),
                       (dict(mirror=1, curvature=0), gcb.GCB_EUNSUPPORTED),
                       (dict(mirror=1, curvature=0, frame=gcb.GCB_FRAME_EXACT),
                        gcb.GCB_EUNSUPPORTED)):
@@ -143,10 +170,11 @@ def test_mirror_argument_checks(h64):
     lam0 = [torch.zeros(n, dtype=torch.float64, device="cuda:0") for _ in range(7)]
     grid = [torch.zeros((cfg.ny, cfg.nx), dtype=torch.float32, device="cuda:0")
             for _ in range(6)]
-    with pytest.raises(gcb.GcbError) as e:
-        gcb.gcb_push_backward(run.ctx, gcb.particles(t), gcb.params(mirror=1), 1, lam, lam0,
-                              grid[:3], grid[3:])
-    assert e.value.code == gcb.GCB_EUNSUPPORTED
+    for opt in (dict(mirror=1), dict(mirror_tol=1e-3)):
+        with pytest.raises(gcb.GcbError) as e:
+            gcb.gcb_push_backward(run.ctx, gcb.particles(t), gcb.params(**opt), 1, lam, lam0,
+                                  grid[:3], grid[3:])
+        assert e.value.code == gcb.GCB_EUNSUPPORTED, opt
     z = torch.zeros(n, dtype=torch.float64, device="cuda:0")
     g = {"r": z + 5.0, "th": z + 1.0, "ph": z.clone(), "ur": z.clone(), "uth": z.clone(),
          "uph": z.clone(), "status": torch.zeros(n, dtype=torch.uint8, device="cuda:0")}

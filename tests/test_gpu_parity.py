@@ -82,7 +82,7 @@ def test_multistep(h64, kernel, sort_every, tile):
     assert st["max_fp_residual"] == float(rres.max())
     # status histogram: particles per status bit (the halo bit is the GPU's own)
     bits = ref.status.numpy()
-    for k in range(7):
+    for k in range(8):
         if k == 5:
             continue
         assert st["status_counts"][k] == int(((bits >> k) & 1).sum()), k

@@ -241,3 +241,41 @@ def test_three_dimensions():
 def _ramp3():
     return O.LinearFields3([0, 0, 0], np.zeros((3, 3)), [0, 0, 1.0],
                            [[0, 0, 0], [0, 0, 0], [0, 0, GRAD]])
+
+
+def test_mirror_check_flags_fast_gyration():
+    """The check of the neglect (Params.mirror_tol, ST_MIRROR): in a uniform
+    B = z_hat (no drifts, so u_perp_g is the in-plane part of u exactly) a
+    guiding-center particle is flagged iff u_perp^2/(Gamma^2 c^2) > tol, with
+    Gamma of the full u; the flag is sticky; tol = 0 turns the check off and
+    full-orbit particles are never checked.  The cases sit at least 10 %
+    from the threshold."""
+    c, tol = 0.45, 0.04                     # v_perp_g > 0.2 c
+    prov = O.LinearFields([0, 0, 0], np.zeros((3, 2)), [0, 0, 1.0], np.zeros((3, 2)))
+    uperp = np.array([0.05, 0.08, 0.12, 0.3, 1.0, 0.3, 2.0])
+    upar = np.array([0.0, 0.02, 0.0, 0.5, 3.0, 2.5, 0.0])
+    ratio = uperp ** 2 / ((1.0 + (uperp ** 2 + upar ** 2) / c ** 2) * c ** 2)
+    want = ratio > tol
+    assert np.all(np.abs(ratio / tol - 1.0) > 0.1) and want.any() and not want.all()
+    n = len(uperp)
+    st = state(3.0, 4.0, list(uperp), [0.0] * n, list(upar), [-20.0] * n)
+    for k in range(3):
+        st, S, _ = O.step(prov, st, params(mirror=False, mirror_tol=tol, f_rho=1e9))
+        assert not bool(S.any())
+        got = (st.status.numpy() & O.ST_MIRROR) != 0
+        assert np.array_equal(got, want), (k, got, want, ratio)
+    st = state(3.0, 4.0, list(uperp), [0.0] * n, list(upar), [-20.0] * n)
+    st, _, _ = O.step(prov, st, params(mirror_tol=0.0, f_rho=1e9))
+    assert not np.any(st.status.numpy() & O.ST_MIRROR)
+    st = state(3.0, 4.0, list(uperp), [0.0] * n, list(upar), [-20.0] * n)
+    st, S, _ = O.step(prov, st, params(mirror_tol=tol, f_rho=0.0))
+    assert bool(S.all()) and not np.any(st.status.numpy() & O.ST_MIRROR)
+    # 3D: the same decision
+    p3 = O.Params3(dt=1.0, c=c, f_rho=1e9, f_E=1.0, curvature=True, n_iter=4, Lx=1.0e6,
+                   Ly=1.0e6, Lz=1.0e6, dl=1.0, mirror_tol=tol)
+    prov3 = O.LinearFields3([0, 0, 0], np.zeros((3, 3)), [0, 0, 1.0], np.zeros((3, 3)))
+    x = torch.full((n,), 3.0, dtype=F64)
+    s3 = O.State3(x, x + 1, x + 2, x.clone(), x + 1, x + 2, T(*uperp), torch.zeros(n, dtype=F64),
+                  T(*upar), torch.full((n,), -20.0, dtype=F64), torch.zeros(n, dtype=torch.uint8))
+    s3, S, _ = O.step3(prov3, s3, p3)
+    assert np.array_equal((s3.status.numpy() & O.ST_MIRROR) != 0, want)
