@@ -187,6 +187,7 @@ def main():
     ap.add_argument("--gr-warmup", type=int, default=4)
     ap.add_argument("--gr-sort-every", type=int, default=16)
     ap.add_argument("--no-frame", action="store_true")
+    ap.add_argument("--no-mirror", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--d3-steps", type=int, default=40)
     ap.add_argument("--d3-warmup", type=int, default=4)
@@ -522,6 +523,16 @@ def main():
             "workload": f"{cfg.name}, binary64, curvature terms off (Sec. 2.2.1)",
             "unit": "particle-steps/s", "reduced": fr["reduced"], "exact": fr["exact"],
             "exact_over_reduced": fr["exact"]["value"] / fr["reduced"]["value"]}
+
+    if not a.no_mirror:
+        # the mirror force and grad-B drift (their own kernel instance) on the
+        # benchmark workload, binary64, curvature scheme
+        r = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup, mirror=1)
+        forms["mirror"] = {
+            "workload": f"{cfg.name}, binary64, curvature scheme with the mirror terms",
+            "unit": "particle-steps/s", "value": n * a.steps / r["wall"],
+            "kernel_ms": r["push_ms"], "gca_fraction": r["gca_frac"],
+            "over_headline": n * a.steps / r["wall"] / value}
 
     if not a.no_3d:
         forms["d3"] = time_3d(a.d3_steps, a.d3_warmup)

@@ -21,11 +21,17 @@ Everything runs through libgcb:
     local Omega_C; a step that resolves the largest one is at least as fine);
     its positions are sampled every M steps;
   * Boris: f_rho = 0, step Delta t;
-  * coupled: f_rho = 0.4, f_E = 1 (Sec. 4.1), step Delta t, curvature on/off.
+  * coupled: f_rho = 0.4, f_E = 1 (Sec. 4.1), step Delta t, curvature on/off,
+    and with curvature plus the mirror terms the paper leaves out
+    (gcb_params.mirror); every coupled run checks the neglect of those terms
+    (gcb_params.mirror_tol = MIRROR_TOL: v_perp_g < 0.1 c at every
+    decomposition, the condition the paper reports holding throughout its
+    experiments).
 The report gives, per run, the largest distance to the reference trajectory
 over the particles and times (minimum image, in d_e), the same at the end,
 the relative error of the final Lorentz factor and, for the coupled runs,
-the fraction of guiding-center steps.
+the fraction of guiding-center steps and the number of particles the check
+flagged.
 
     python -m paper_2007_14401_amd.replay [--rho 1e-2 1e-3 1e-4] [--steps 1111]
 """
@@ -93,6 +99,9 @@ def _min_image(d, L):
     return d - L * np.floor(d / L + 0.5)
 
 
+MIRROR_TOL = 0.01   # (v_perp_g/c)^2: v_perp_g below 0.1 c
+
+
 def run(rho_over_de: float, steps: int = 1111, device: int = 0, log=print) -> dict:
     F, stagger = _fields()
     rho0 = rho_over_de * D_E                      # cells
@@ -118,19 +127,22 @@ def run(rho_over_de: float, steps: int = 1111, device: int = 0, log=print) -> di
                 xs.append(np.stack([t["x"].cpu().numpy(), t["y"].cpu().numpy()]))
             u = np.stack([t[k].cpu().numpy() for k in ("ux", "uy", "uz")])
             gam = np.sqrt(1.0 + (u * u).sum(axis=0) / (C * C))
-            return np.array(xs), gam, gca / (steps * n_sub * 5)
+            flagged = int(((t["status"].cpu().numpy() & gcb.GCB_ST_MIRROR) != 0).sum())
+            return np.array(xs), gam, gca / (steps * n_sub * 5), flagged
 
         log(f"replay rho/d_e={rho_over_de:g}: reference with M = {M} substeps per step")
-        ref_x, ref_g, _ = traj(DT / M, M, f_rho=0.0)
+        ref_x, ref_g, _, _ = traj(DT / M, M, f_rho=0.0)
+        chk = dict(mirror_tol=MIRROR_TOL)
         runs = {"boris": dict(f_rho=0.0),
-                "coupled_curvature": dict(f_rho=0.4, f_E=1.0, curvature=1),
-                "coupled_no_curvature": dict(f_rho=0.4, f_E=1.0, curvature=0)}
+                "coupled_curvature": dict(f_rho=0.4, f_E=1.0, curvature=1, **chk),
+                "coupled_no_curvature": dict(f_rho=0.4, f_E=1.0, curvature=0, **chk),
+                "coupled_mirror": dict(f_rho=0.4, f_E=1.0, curvature=1, mirror=1, **chk)}
         rep = {"rho_over_de": rho_over_de, "omega0_dt": omega0 * DT,
                "dt_over_dt_gyr0": omega0 * DT * 60.0 / (2.0 * math.pi),
                "reference_substeps": M, "steps": steps, "time_wp": steps * DT * C / D_E,
                "reference_final_gamma": ref_g.tolist()}
         for name, kw in runs.items():
-            xs, g, frac = traj(DT, 1, **kw)
+            xs, g, frac, flagged = traj(DT, 1, **kw)
             dx = _min_image(xs[:, 0] - ref_x[:, 0], NX)
             dy = _min_image(xs[:, 1] - ref_x[:, 1], NY)
             d = np.sqrt(dx * dx + dy * dy) / D_E
@@ -139,8 +151,11 @@ def run(rho_over_de: float, steps: int = 1111, device: int = 0, log=print) -> di
                          "median_deviation_de": float(np.median(d)),
                          "final_gamma_rel_err": (np.abs(g - ref_g) / ref_g).tolist(),
                          "gca_fraction": frac}
+            if name != "boris":
+                rep[name]["mirror_check_flagged"] = flagged
             log(f"  {name:22s} max deviation {d.max():.3e} d_e, final "
-                f"{np.round(d[-1], 4).tolist()}, GCA fraction {frac:.3f}")
+                f"{np.round(d[-1], 4).tolist()}, GCA fraction {frac:.3f}, "
+                f"mirror check flagged {flagged}")
         return rep
     finally:
         gcb.gcb_destroy(ctx)
