@@ -186,8 +186,9 @@ typedef struct {
                             validity check of leaving out (or of the size of) the mirror
                             terms, whose ratio to the curvature terms grows as
                             v_perp_g^2 (Sec. 2.2); 0 (default): no check.  Finite and
-                            >= 0 (else GCB_EINVAL); gcb_push and gcb_push_3d only (other
-                            calls return GCB_EUNSUPPORTED for a value other than 0) */
+                            >= 0 (else GCB_EINVAL); gcb_push, gcb_push_3d and gcb_push_gr
+                            (there with c = 1 and the metric's norm of u_perp_g); the
+                            adjoints return GCB_EUNSUPPORTED for a value other than 0 */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.

@@ -65,6 +65,7 @@ ST_KAPPA = 2
 ST_BZERO = 8
 ST_FPRES = 16
 GR_ST_OUT = 64      # left the (r, theta) domain; no longer advanced
+ST_MIRROR = 128     # (v_perp_g/c)^2 above GRParams.mirror_tol at a decomposition
 
 KAPPA_FLOOR = 1.0e-12
 TWO_PI = 2.0 * math.pi
@@ -413,6 +414,7 @@ class GRParams:
     f_E: float = 1.0
     n_iter: int = 4
     fp_tol: float = 1.0e-7
+    mirror_tol: float = 0.0   # > 0: ST_MIRROR where (v_perp_g/c)^2 exceeds it
 
 
 @dataclass
@@ -473,6 +475,10 @@ def grgca_step(metric, grid, x, u, qm, p: GRParams):
     upar = (L0.b_up[0] * u[0] + L0.b_up[1] * u[1]) + L0.b_up[2] * u[2]
     uperp = tuple((u[i] - upar * L0.b_dn[i]) - L0.vE[i] * Gf for i in range(3))
     up2 = norm2_cov(m0, uperp)
+    # the check of the neglect of the mirror terms (Sec. 2.2), c = 1:
+    # (v_perp_g/c)^2 = gamma^ij u_perp_g,i u_perp_g,j / Gamma^2 above mirror_tol
+    if p.mirror_tol > 0.0:
+        flags = flags | torch.where(up2 > p.mirror_tol * (Gf * Gf), ST_MIRROR, 0).to(torch.uint8)
     mu = ((0.5 * up2) / L0.B) / L0.kappa
     mu = torch.where(L0.B > 0.0, mu, 0.0)
     nu = sqrt(up2)

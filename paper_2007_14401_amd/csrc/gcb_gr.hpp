@@ -178,6 +178,7 @@ GCB_HD void kerr_schild(double a_, double r_, double th, Metric<R>& m) {
 
 struct GrConst {
     double a, dt, qm, f_rho, f_E, fp_tol;
+    double mirror_tol;   // > 0: ST_MIRROR where (v_perp_g/c)^2 exceeds it
     double r_min, r_max, inv_dr, inv_dth;
     int nr, nth, n_iter;
 };
@@ -489,6 +490,8 @@ GCB_HD int coupled_step(const T* __restrict__ F, const double* __restrict__ dl_t
         R uperp[3];
         for (int i = 0; i < 3; ++i) uperp[i] = (u[i] - upar * L0.b_dn[i]) - L0.vE[i] * Gf;
         const R up2 = norm2_cov(m0, uperp);
+        // the check of the neglect of the mirror terms (c = 1)
+        if (g.mirror_tol > 0.0 && up2 > (R)g.mirror_tol * (Gf * Gf)) fl |= ST_MIRROR;
         mu = (((R)0.5 * up2) / L0.B) / L0.kappa;
         if (!(L0.B > (R)0)) mu = (R)0;
         const R nu = sqrt(up2);

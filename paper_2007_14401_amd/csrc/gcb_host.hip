@@ -180,9 +180,9 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
 }
 
 // the exact frame (curvature = 0, binary64), the gyration options other
-// than a conserved mu, the mirror terms and their check are served by gcb_push
-// and gcb_push_3d only
-int reject_push_options(gcb_ctx* ctx, const gcb_params* prm) {
+// than a conserved mu and the mirror terms are served by gcb_push and
+// gcb_push_3d only, the check of the mirror terms (check_ok) by the pushes
+int reject_push_options(gcb_ctx* ctx, const gcb_params* prm, bool check_ok = false) {
     if (prm->frame != GCB_FRAME_REDUCED)
         return fail(ctx, GCB_EUNSUPPORTED,
                     "the exact frame is served by gcb_push and gcb_push_3d only");
@@ -190,10 +190,12 @@ int reject_push_options(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EUNSUPPORTED,
                     "gyration options other than GCB_GYRATION_MU are served by gcb_push and "
                     "gcb_push_3d only");
-    if (prm->mirror != 0 || prm->mirror_tol != 0.0)
+    if (prm->mirror != 0)
         return fail(ctx, GCB_EUNSUPPORTED,
-                    "the mirror terms and their check are served by gcb_push and gcb_push_3d "
-                    "only");
+                    "the mirror terms are served by gcb_push and gcb_push_3d only");
+    if (!check_ok && prm->mirror_tol != 0.0)
+        return fail(ctx, GCB_EUNSUPPORTED,
+                    "the check of the mirror terms is served by the pushes only");
     return GCB_OK;
 }
 
@@ -990,8 +992,10 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     if (prm->form != GCB_FORM_F64 && prm->form != GCB_FORM_MIXED)
         return fail(ctx, GCB_EINVAL, "unknown form %d", prm->form);
     if (prm->replay) return fail(ctx, GCB_EUNSUPPORTED, "replay is not supported here");
+    if (!(std::isfinite(prm->mirror_tol) && prm->mirror_tol >= 0.0))
+        return fail(ctx, GCB_EINVAL, "mirror_tol must be finite and >= 0");
     {
-        const int rc = reject_push_options(ctx, prm);
+        const int rc = reject_push_options(ctx, prm, true);
         if (rc) return rc;
     }
     if (p->n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");
@@ -1022,6 +1026,7 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     g.f_rho = prm->f_rho;
     g.f_E = prm->f_E;
     g.fp_tol = prm->fp_tol;
+    g.mirror_tol = prm->mirror_tol;
     g.n_iter = prm->n_iter;
     GrPtrs ptrs{p->r, p->th, p->ph, p->ur, p->uth, p->uph, p->qm, p->id, p->status};
     const double* dl = static_cast<const double*>(ctx->gr_dl.ptr);

@@ -35,7 +35,11 @@ large moment.
 The report gives, per particle, the largest distance to the reference
 trajectory (flat-space Cartesian mapping of (r, theta, phi), in r_g) over the
 times at which the reference particle is still inside the domain, the final
-distance, and for the coupled run the fraction of guiding-center steps.
+distance, and for the coupled run the fraction of guiding-center steps and,
+for each threshold of MIRROR_TOLS, whether the check of the neglect of the
+mirror terms (gcb_params.mirror_tol: (v_perp_g/c)^2 at every decomposition
+at most the threshold) flagged the particle; the check does not change the
+orbit, so the runs at the other thresholds only supply their flags.
 
     python -m paper_2007_14401_amd.replay_gr [--omega 1e1 1e2 1e3 1e4] [--t-end 20]
                                              [--rotation 0.1 1]
@@ -53,6 +57,7 @@ import torch
 from . import gcb
 
 R0, TH0 = 5.5, math.pi / 3.0
+MIRROR_TOLS = (0.01, 0.1, 0.3)   # (v_perp_g/c)^2: v_perp_g below 0.1, 0.32, 0.55 c
 DT = 2.0 * math.pi / 60.0
 
 
@@ -114,24 +119,32 @@ def run(omegas=(1e1, 1e2, 1e3, 1e4), t_end: float = 20.0, rotation: float = 0.1,
                 gca += (tr == 0).sum(dim=0).cpu().numpy()
                 pos.append(_cartesian(*(t[k].cpu().numpy() for k in ("r", "th", "ph"))))
                 inside.append((t["status"].cpu().numpy() & gcb.GCB_ST_OUT) == 0)
-            return np.array(pos), np.array(inside), gca / (steps * n_sub)
+            mirror = (t["status"].cpu().numpy() & gcb.GCB_ST_MIRROR) != 0
+            return np.array(pos), np.array(inside), gca / (steps * n_sub), mirror
 
         log(f"replay gr: rotation {rotation:g}, Omega_C0 r_g/c = {list(omegas)}, B0 = {B0:.4g}, "
             f"reference with M = {M} substeps per step of {DT:.4f} r_g/c, {steps} steps")
-        ref_x, ref_in, _ = traj(DT / M, M, f_rho=0.0)
+        ref_x, ref_in, _, _ = traj(DT / M, M, f_rho=0.0)
         rep = {"rotation": rotation, "omega_c0": list(omegas),
                "rho_c0_over_rg": [1.0 / w for w in omegas],
                "qm": qm.tolist(), "dt": DT, "steps": steps, "t_end": steps * DT,
                "reference_substeps": M,
                "reference_inside_at_end": ref_in[-1].tolist()}
-        for name, kw in (("boris", dict(f_rho=0.0)), ("coupled", dict(f_rho=1.0, f_E=1.0))):
-            xs, _, frac = traj(DT, 1, **kw)
+        for name, kw in (("boris", dict(f_rho=0.0)),
+                         ("coupled", dict(f_rho=1.0, f_E=1.0, mirror_tol=MIRROR_TOLS[0]))):
+            xs, _, frac, mirror = traj(DT, 1, **kw)
             d = np.sqrt(((xs - ref_x) ** 2).sum(axis=1))      # (steps+1, n)
             dmax = np.where(ref_in, d, 0.0).max(axis=0)
             rep[name] = {"max_deviation_rg": dmax.tolist(), "final_deviation_rg": d[-1].tolist(),
                          "gca_fraction": frac.tolist()}
             log(f"  {name:8s} max deviation {np.round(dmax, 5).tolist()} r_g, "
                 f"GCA fraction {np.round(frac, 3).tolist()}")
+            if name == "coupled":
+                flags = {str(MIRROR_TOLS[0]): mirror.tolist()}
+                for tol in MIRROR_TOLS[1:]:
+                    flags[str(tol)] = traj(DT, 1, **dict(kw, mirror_tol=tol))[3].tolist()
+                rep[name]["mirror_check_flagged"] = flags
+                log(f"  coupled  mirror check flagged, per threshold on (v_perp_g/c)^2: {flags}")
         return rep
     finally:
         gcb.gcb_destroy(ctx)

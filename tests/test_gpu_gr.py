@@ -134,8 +134,22 @@ def test_gr_multistep(g64):
     flagged = int(((ref.status.numpy() & ~np.uint8(32)) != 0).sum())
     assert st["flagged"] == flagged
     bits = ref.status.numpy()
-    for k in (0, 1, 2, 3, 4, 6):
+    for k in (0, 1, 2, 3, 4, 6, 7):
         assert st["status_counts"][k] == int(((bits >> k) & 1).sum()), k
+
+
+def test_gr_mirror_check(g64):
+    """The check of the neglect of the mirror terms in curved spacetime
+    (mirror_tol, GCB_ST_MIRROR at (v_perp_g/c)^2 above it): status bits bit for
+    bit with the oracle, and the histogram counts them."""
+    cfg, F, run = g64
+    e = cfg.particles(n=2000, seed_offset=9)
+    t = to_device(e)
+    tr, st = run.push(t, 10, stats=True, mirror_tol=0.01)
+    ref, S, _ = run_oracle(cfg, F, e, 10, mirror_tol=0.01)
+    compare(t, ref, tr, S, what="gr mirror check")
+    n_flag = int(((ref.status.numpy() & 128) != 0).sum())
+    assert st["status_counts"][7] == n_flag and 0 < n_flag < e.n, n_flag
 
 
 @pytest.mark.parametrize("kw", [{"n_iter": 1}, {"n_iter": 3}, {"f_rho": 0.0},

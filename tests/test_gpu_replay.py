@@ -62,3 +62,9 @@ def test_replay_gr_ambient():
     # the switch: the weakest magnetization starts on the full orbit, the
     # stronger ones on the guiding-center equations
     assert frac[0] < frac[1] and frac[1] > 0.3, frac
+    # the check of the neglect of the mirror terms at three thresholds: a
+    # particle flagged at a threshold is flagged at every smaller one
+    flags = rep["coupled"]["mirror_check_flagged"]
+    tols = sorted(flags, key=float)
+    for lo, hi in zip(tols, tols[1:]):
+        assert all(a or not b for a, b in zip(flags[lo], flags[hi])), flags
