@@ -29,7 +29,7 @@ __device__ __forceinline__ double wave_max_nan(double v) {
 // null), written to slot k of `out`: the same arrays, or, on the launch after
 // a sort, the other buffer, which then also receives q/m and the id
 template <typename R, typename T>
-__global__ __launch_bounds__(kGrWG) __attribute__((amdgpu_waves_per_eu(2))) void
+__global__ __launch_bounds__(kGrWG) __attribute__((amdgpu_waves_per_eu(3))) void
 k_gr_push(GrPtrs in, GrPtrs out, const uint32_t* __restrict__ perm, int64_t n, int s0, int ns,
           const T* __restrict__ F, const double* __restrict__ dl, gr::GrConst g,
           uint8_t* trace, DevStats* stats) {
