@@ -181,3 +181,35 @@ def test_mirror_argument_checks(h64):
     with pytest.raises(gcb.GcbError) as e:
         gcb.gcb_push_gr(run.ctx, gcb.gr_particles(g), gcb.params(mirror=1), 1)
     assert e.value.code == gcb.GCB_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(1, 0, 0), (2, 1, 6)])
+def test_mirror_mixed_one_step_3d(kernel, sort_every, tile):
+    """The 3D mixed form with the option against the binary64 oracle with it,
+    one step: the bounds of the mixed form's one-step test."""
+    from paper_2007_14401_amd import gcb, state
+    cfg = make_config3("harris3d32")
+    F = cfg.fields()
+    ens = cfg.particles(n=8192, seed_offset=21)
+    run = GpuRun3(cfg, F, dtype=gcb.GCB_F32)
+    try:
+        t = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED)
+        tr, _ = run.push(t, 1, trace=True, form=gcb.GCB_FORM_MIXED, kernel=kernel,
+                         sort_every=sort_every, tile=tile, mirror=1)
+    finally:
+        run.close()
+    got = state.unsort(t)
+    ref, rtr, _ = run_oracle3(cfg, F, ens, 1, trace=True, mirror=True)
+    u_g = np.stack([got[k].astype(np.float64) for k in ("ux", "uy", "uz")])
+    u_r = np.stack([getattr(ref, k).numpy() for k in ("ux", "uy", "uz")])
+    du = np.max(np.abs(u_g - u_r), axis=0) / np.maximum(np.max(np.abs(u_r), axis=0), cfg.c)
+    dx = np.max(np.stack([np.minimum(np.abs(got[k] - getattr(ref, k).numpy()),
+                                     L - np.abs(got[k] - getattr(ref, k).numpy()))
+                          for k, L in (("x", cfg.Lx), ("y", cfg.Ly), ("z", cfg.Lz))]), axis=0)
+    mism = float((tr.cpu().numpy() != rtr.numpy()).mean())
+    log(f"3d mixed mirror kernel={kernel}: u median {np.median(du):.2e} "
+        f"p99 {np.quantile(du, 0.99):.2e}; x max {dx.max():.2e}; S mismatch {mism:.2e}")
+    assert np.median(du) <= 1e-5
+    assert np.quantile(du, 0.99) <= 1e-3
+    assert dx.max() <= 1e-4
+    assert mism <= 2e-3
