@@ -279,3 +279,37 @@ def test_mirror_check_flags_fast_gyration():
                   T(*upar), torch.full((n,), -20.0, dtype=F64), torch.zeros(n, dtype=torch.uint8))
     s3, S, _ = O.step3(prov3, s3, p3)
     assert np.array_equal((s3.status.numpy() & O.ST_MIRROR) != 0, want)
+
+
+def test_check_does_not_change_the_orbit():
+    """The check only sets a status bit: with and without mirror_tol the
+    states agree bit for bit (flat space with E != 0, and curved spacetime on
+    the small magnetosphere), and a particle flagged at a threshold is flagged
+    at every smaller one."""
+    prov = _general_fields()
+    runs = {}
+    for tol in (0.0, 1e-3, 1e-2):
+        st = _random_state(n=200, seed=7)
+        for _ in range(6):
+            st, _, _ = O.step(prov, st, params(mirror_tol=tol))
+        runs[tol] = st
+    for k in ("x", "y", "xp", "yp", "ux", "uy", "uz"):
+        assert torch.equal(getattr(runs[0.0], k), getattr(runs[1e-2], k)), k
+    f3, f2 = ((runs[t].status.numpy() & O.ST_MIRROR) != 0 for t in (1e-3, 1e-2))
+    assert not np.any(f2 & ~f3) and f3.any() and not (runs[0.0].status.numpy() & O.ST_MIRROR).any()
+
+    from oracle import gr
+    from workloads.gr import make_gr_config
+    cfg = make_gr_config("grbh64")
+    F = cfg.fields()
+    e = cfg.particles(n=400, seed_offset=3)
+    out = {}
+    for tol in (0.0, 0.01, 0.1):
+        p = gr.GRParams(dt=cfg.dt, f_rho=cfg.f_rho, f_E=cfg.f_E, n_iter=cfg.n_iter, mirror_tol=tol)
+        out[tol], _, _ = gr.push(gr.KerrSchild(cfg.a), gr.GRGrid(F, cfg.r_min, cfg.r_max),
+                                 gr.GRState.from_numpy(e), p, 5)
+    for k in ("r", "th", "ph", "ur", "uth", "uph"):
+        assert torch.equal(getattr(out[0.0], k), getattr(out[0.1], k)), k
+    g1, g2 = ((out[t].status.numpy() & gr.ST_MIRROR) != 0 for t in (0.01, 0.1))
+    assert not np.any(g2 & ~g1) and g1.any()
+    assert not (out[0.0].status.numpy() & gr.ST_MIRROR).any()
