@@ -30,6 +30,33 @@ YEE = ((0.5, 0.0), (0.0, 0.5), (0.0, 0.0), (0.0, 0.5), (0.5, 0.0), (0.5, 0.5))
 COLLOCATED = ((0.0, 0.0),) * 6
 
 
+# Lattice coordinates (position / cell size) of magnitude FAR or more have no
+# field: the gather returns NaN there.  Periodicity defines the field at any
+# finite point, but no step of the method moves a particle that far from the
+# box unless an iteration diverged (e.g. with the drift speed clamped where
+# it reaches c), and node indices of such points do not fit a 32-bit integer.
+FAR = float(2 ** 30)
+
+
+def far_points(*lattice_coords):
+    """True where any lattice coordinate is NaN or of magnitude >= FAR."""
+    ok = None
+    for g in lattice_coords:
+        o = torch.abs(g) < FAR
+        ok = o if ok is None else ok & o
+    return ~ok
+
+
+def nan_where(far, sample):
+    """The sample with every value replaced by NaN where `far`."""
+    if not bool(far.any()):
+        return sample
+    f = lambda v: torch.where(far, float("nan"), v)
+    return type(sample)(*(tuple(f(v) for v in part) if not isinstance(part[0], tuple)
+                          else tuple(tuple(f(v) for v in row) for row in part)
+                          for part in sample))
+
+
 class FieldSample(NamedTuple):
     E: tuple   # (Ex, Ey, Ez)
     B: tuple   # (Bx, By, Bz)
@@ -88,11 +115,16 @@ class GridFields:
         return val, ddx, ddy
 
     def __call__(self, X, Y) -> FieldSample:
+        # a point 2^30 cells or more from the origin (or not a number): a
+        # fixed-point iteration that ran away; its fields are NaN
+        far = far_points(X * self.inv_dx, Y * self.inv_dy)
+        X = torch.where(far, 0.0, X)
+        Y = torch.where(far, 0.0, Y)
         E = tuple(self.component(k, X, Y, False)[0] for k in range(3))
         Bs = [self.component(k, X, Y, True) for k in range(3, 6)]
         B = tuple(b[0] for b in Bs)
         dB = (tuple(b[1] for b in Bs), tuple(b[2] for b in Bs))
-        return FieldSample(E, B, dB)
+        return nan_where(far, FieldSample(E, B, dB))
 
 
 def _full(X, v):

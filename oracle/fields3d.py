@@ -23,6 +23,7 @@ from typing import NamedTuple
 import numpy as np
 import torch
 
+from .fields import far_points, nan_where
 from .ieee import sqrt
 
 F64 = torch.float64
@@ -98,11 +99,17 @@ class GridFields3:
         return val, ddx, ddy, ddz
 
     def __call__(self, X, Y, Z) -> FieldSample3:
+        # a point 2^30 cells or more from the origin (or not a number) has NaN
+        # fields, as in 2D
+        far = far_points(X * self.inv_dx, Y * self.inv_dy, Z * self.inv_dz)
+        X = torch.where(far, 0.0, X)
+        Y = torch.where(far, 0.0, Y)
+        Z = torch.where(far, 0.0, Z)
         E = tuple(self.component(k, X, Y, Z, False)[0] for k in range(3))
         Bs = [self.component(k, X, Y, Z, True) for k in range(3, 6)]
         B = tuple(b[0] for b in Bs)
         dB = tuple(tuple(b[j + 1] for b in Bs) for j in range(3))
-        return FieldSample3(E, B, dB)
+        return nan_where(far, FieldSample3(E, B, dB))
 
 
 def _full(X, v):

@@ -94,6 +94,34 @@ def test_interp_partition_of_unity_and_periodicity():
         assert torch.allclose(u, v, rtol=0, atol=1e-12)
 
 
+def test_interp_far_points_are_nan():
+    """Reading of the design notes for a runaway iteration: lattice
+    coordinates of magnitude 2^30 or more (or NaN) give an all-NaN sample;
+    just inside the bound periodicity still holds exactly (a shift by a
+    whole number of periods leaves the dyadic weights and the node values
+    unchanged), in 2D and in 3D."""
+    nx, ny, nz = 16, 12, 8
+    rng = np.random.default_rng(7)
+    g2 = O.GridFields(rng.normal(size=(6, ny, nx)), 1.0, 1.0, YEE)
+    g3 = O.GridFields3(rng.normal(size=(6, nz, ny, nx)), 1.0, 1.0, 1.0, O.YEE3)
+    lim = float(2 ** 30)
+    X = T(3.25, lim, -lim, float("nan"), 3.25 + 48.0 * 2 ** 24, 5.5)
+    Y = T(2.5, 1.0, 1.0, 1.0, 2.5, -lim)
+    s = g2(X, Y)
+    far = torch.tensor([False, True, True, True, False, True])
+    for v in s.E + s.B + s.dB[0] + s.dB[1]:
+        assert torch.equal(torch.isnan(v), far)
+    for a, b in zip(s.E + s.B, s.E + s.B):
+        assert a[0] == b[4]
+    Z = T(1.75, 1.0, 1.0, 1.0, 1.75 + 8.0 * 2 ** 26, 1.0)
+    s3 = g3(X, Y, Z)
+    for v in s3.E + s3.B:
+        assert torch.equal(torch.isnan(v), far)
+        assert v[0] == v[4]
+    s3 = g3(T(1.0), T(1.0), T(-lim))
+    assert torch.isnan(s3.B[0]).all()
+
+
 def test_interp_at_nodes_returns_node_values():
     """At a component's own node the gather returns that node's value (Yee offsets)."""
     rng = np.random.default_rng(3)
