@@ -231,6 +231,8 @@ __global__ __launch_bounds__(kScatterWG) void k_scatter_batch(
             const int64_t r = (int64_t)b * slots + q;
             const double gx = X[r * n + p] * idx;
             const double gy = Y[r * n + p] * idy;
+            // a runaway point's sample is a constant NaN: no node cotangent
+            if (!(fabs(gx) < kFarLattice && fabs(gy) < kFarLattice)) continue;
             const float* bq = bar + r * 12 * n + p;
 #pragma unroll
             for (int k = 0; k < 6; ++k) {

@@ -72,6 +72,8 @@ GCB_HD void scatter_sample(Add& add, const PushConst& pc, bool yee, double X, do
     const double gx = X * pc.inv_dx;
     const double gy = Y * pc.inv_dy;
     const double idx = pc.inv_dx, idy = pc.inv_dy;
+    // a runaway point's sample is a constant NaN: no node cotangent
+    if (!(fabs(gx) < kFarLattice && fabs(gy) < kFarLattice)) return;
     for (int k = 0; k < 6; ++k) {
         const double sx = yee ? kYeeStagger[k][0] : pc.stagger[k][0];
         const double sy = yee ? kYeeStagger[k][1] : pc.stagger[k][1];
@@ -102,6 +104,8 @@ GCB_HD void gather_vjp(const Acc& acc, Sink& sink, const PushConst& pc, bool yee
     const double gx = X * pc.inv_dx;
     const double gy = Y * pc.inv_dy;
     const double idx = pc.inv_dx, idy = pc.inv_dy;
+    // a runaway point's sample is a constant NaN: it does not depend on (X, Y)
+    if (!(fabs(gx) < kFarLattice && fabs(gy) < kFarLattice)) return;
     for (int k = 0; k < 6; ++k) {
         const double sx = yee ? kYeeStagger[k][0] : pc.stagger[k][0];
         const double sy = yee ? kYeeStagger[k][1] : pc.stagger[k][1];

@@ -182,6 +182,10 @@ __global__ __launch_bounds__(kScatterWG) void k_scatter3_batch(
                 if (vb == 0.0 && gb[0] == 0.0 && gb[1] == 0.0 && gb[2] == 0.0) continue;
                 const double g[3] = {X[r * n + p] * id[0], Y[r * n + p] * id[1],
                                      Z[r * n + p] * id[2]};
+                // a runaway point's sample is a constant NaN: no node cotangent
+                if (!(fabs(g[0]) < kFarLattice && fabs(g[1]) < kFarLattice &&
+                      fabs(g[2]) < kFarLattice))
+                    continue;
                 int c[3];
                 double W1[3];
 #pragma unroll

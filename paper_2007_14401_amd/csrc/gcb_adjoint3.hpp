@@ -49,6 +49,13 @@ GCB_HD double offset3(const PushConst3& pc, bool yee, int k, int a) {
     return a < 2 ? pc.b.stagger[k][a] : pc.sz[k];
 }
 
+// a runaway point (lattice coordinate NaN or of magnitude kFarLattice or
+// more): its sample is a constant NaN, with no node or position cotangent
+GCB_HD bool far3(const PushConst3& pc, double X, double Y, double Z) {
+    return !(fabs(X * pc.b.inv_dx) < kFarLattice && fabs(Y * pc.b.inv_dy) < kFarLattice &&
+             fabs(Z * pc.inv_dz) < kFarLattice);
+}
+
 // cell and weights of component k's stencil at (X, Y, Z)
 GCB_HD void stencil3(const PushConst3& pc, bool yee, int k, double X, double Y, double Z,
                      int c[3], double w[3]) {
@@ -73,6 +80,7 @@ template <class Add>
 GCB_HD void scatter_sample3(Add& add, const PushConst3& pc, bool yee, double X, double Y,
                             double Z, const SampleBar3& sb) {
     const double id[3] = {pc.b.inv_dx, pc.b.inv_dy, pc.inv_dz};
+    if (far3(pc, X, Y, Z)) return;
     for (int k = 0; k < 6; ++k) {
         double vb, gb[3];
         comp_bar(sb, k, vb, gb);
@@ -101,6 +109,7 @@ GCB_HD void gather_vjp3(const GlobalAcc3<double>& acc, Sink& sink, const PushCon
                         bool yee, double X, double Y, double Z, const SampleBar3& sb,
                         double P[3]) {
     sink.sample(X, Y, Z, sb);
+    if (far3(pc, X, Y, Z)) return;
     const double id[3] = {pc.b.inv_dx, pc.b.inv_dy, pc.inv_dz};
     for (int k = 0; k < 6; ++k) {
         double vb, gb[3];

@@ -42,6 +42,10 @@ constexpr double kKappaFloor = 1.0e-12;
 // |1 - (dt/2) v_E.(b.grad)b| below this: no division in the parallel update.
 constexpr double kDFloor = 1.0e-12;
 
+// Lattice coordinates (position / cell size) of magnitude this or more, or
+// NaN, have no field: a gather there returns NaN (a runaway iteration).
+constexpr double kFarLattice = 1073741824.0;   // 2^30
+
 // 2D Yee lattice offsets (cells) of Ex, Ey, Ez, Bx, By, Bz.
 constexpr double kYeeStagger[6][2] = {
     {0.5, 0.0}, {0.0, 0.5}, {0.0, 0.0}, {0.0, 0.5}, {0.5, 0.0}, {0.5, 0.5}};

@@ -141,14 +141,10 @@ GCB_HD void yee_fetch(const TileAcc<T>& acc, int ia, int ib, int ja,
         interp_yee<R, kGrad>(GlobalLoad<T>{g}, wx, wy, K, s);
 }
 
-// All six components at (X, Y); B gradients when kGrad.  kYee: the 2D Yee
-// offsets (the values of the runtime table when it holds them).  Lattice
-// coordinates and weights are formed in binary64 from the binary64 position.
+// the gather at lattice coordinates (gx, gy) = (X/dx, Y/dy)
 template <typename R, bool kGrad, bool kYee, class Acc>
-GCB_HD void gather(const Acc& acc, const PushConst& pc,
-                                       const Consts<R>& K, double X, double Y, Sample<R>& s) {
-    const double gx = X * pc.inv_dx;
-    const double gy = Y * pc.inv_dy;
+GCB_HD void gather_at(const Acc& acc, const PushConst& pc, const Consts<R>& K, double gx,
+                      double gy, Sample<R>& s) {
     if constexpr (kYee) {
         // lattice coordinate minus the offset: offset 0 leaves it unchanged
         const double xb = gx - 0.5;
@@ -168,6 +164,36 @@ GCB_HD void gather(const Acc& acc, const PushConst& pc,
         for (int k = 0; k < 3; ++k)
             interp_comp<R, kGrad>(acc, k + 3, gx, gy, pc.stagger[k + 3][0],
                                   pc.stagger[k + 3][1], K, s.B[k], s.dBx[k], s.dBy[k]);
+    }
+}
+
+// All six components at (X, Y); B gradients when kGrad.  kYee: the 2D Yee
+// offsets (the values of the runtime table when it holds them).  Lattice
+// coordinates and weights are formed in binary64 from the binary64 position.
+// A point whose lattice coordinates are NaN or of magnitude kFarLattice or
+// more (a fixed-point iteration that ran away) has an all-NaN sample: it is
+// gathered at the origin instead, so that every node index stays a small
+// integer, and the values are replaced afterwards.
+template <typename R, bool kGrad, bool kYee, class Acc>
+GCB_HD void gather(const Acc& acc, const PushConst& pc,
+                                       const Consts<R>& K, double X, double Y, Sample<R>& s) {
+    double gx = X * pc.inv_dx;
+    double gy = Y * pc.inv_dy;
+    const bool far = !(fabs(gx) < kFarLattice && fabs(gy) < kFarLattice);
+    if (__builtin_expect(far, 0)) {
+        gx = 0.0;
+        gy = 0.0;
+    }
+    gather_at<R, kGrad, kYee>(acc, pc, K, gx, gy, s);
+    if (__builtin_expect(far, 0)) {
+        const R q = (R)__builtin_nan("");
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            s.E[i] = q;
+            s.B[i] = q;
+            s.dBx[i] = q;
+            s.dBy[i] = q;
+        }
     }
 }
 
@@ -616,11 +642,33 @@ GCB_HD void drift_terms(const Local<R>& L, R upn, const Gyr<R>& gy, R inv_qm,
 
 // The check of the neglect of the mirror terms (Sec. 2.2): ST_MIRROR where
 // (v_perp_g/c)^2 = u_perp_g^2/(Gamma^2 c^2) exceeds pc.mirror_tol (> 0) at
-// the decomposition, Gamma of the full four-velocity.
+// the decomposition, Gamma of the full four-velocity.  up2 and gf come from
+// the decomposition of u (ux, uy, uz) with the local quantities Lh and the
+// curvature drift vc there.  In the mixed form a comparison within 1e-4 of
+// the threshold is taken again in binary64 (the decomposition redone in
+// binary64 from the same binary32 inputs), as the switch test is.
 template <typename R>
-GCB_HD uint32_t mirror_check(R up2, R gf, const PushConst& pc, const Consts<R>& K) {
+GCB_HD uint32_t mirror_check(R ux, R uy, R uz, const Local<R>& Lh, const R vc[3], R up2, R gf,
+                             const PushConst& pc, const Consts<R>& K) {
     if (!(pc.mirror_tol > 0.0)) return 0u;
-    return up2 * K.inv_c2 > (R)pc.mirror_tol * (gf * gf) ? (uint32_t)ST_MIRROR : 0u;
+    const R lhs = up2 * K.inv_c2;
+    const R rhs = (R)pc.mirror_tol * (gf * gf);
+    if constexpr (kMixed<R>) {
+        if (fabs(lhs - rhs) <= 1.0e-4f * rhs) {
+            const double u[3] = {ux, uy, uz};
+            const double b[3] = {Lh.b[0], Lh.b[1], Lh.b[2]};
+            const double g = sqrt(1.0 + ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]) * pc.inv_c2);
+            const double upar = (u[0] * b[0] + u[1] * b[1]) + u[2] * b[2];
+            double q = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double w = (u[i] - upar * b[i]) - ((double)Lh.vE[i] + (double)vc[i]) * g;
+                q = q + w * w;
+            }
+            return q * pc.inv_c2 > pc.mirror_tol * (g * g) ? (uint32_t)ST_MIRROR : 0u;
+        }
+    }
+    return lhs > rhs ? (uint32_t)ST_MIRROR : 0u;
 }
 
 GCB_HD double nan_max(double a, double b) {
@@ -664,7 +712,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
         const R upy = (uy - upar * Lh.b[1]) - (Lh.vE[1] + vc[1]) * gf;
         const R upz = (uz - upar * Lh.b[2]) - (Lh.vE[2] + vc[2]) * gf;
         const R up2 = (upx * upx + upy * upy) + upz * upz;
-        flags |= mirror_check(up2, gf, pc, K);
+        flags |= mirror_check(ux, uy, uz, Lh, vc, up2, gf, pc, K);
         gy.mu = pc.gyration == GYR_ZERO ? (R)0 : (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
         gy.up2 = up2;
         gy.fixed = pc.gyration == GYR_UPERP;

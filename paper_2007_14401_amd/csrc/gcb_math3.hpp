@@ -116,12 +116,10 @@ GCB_HD void yee3_fetch(const TileAcc3<T>& acc, const int fl[3][2], const R wx[2]
     }
 }
 
-// All six components at (X, Y, Z); B gradients when kGrad.  kYee: the 3D Yee
-// offsets.  Lattice coordinates and weights in binary64 from the positions.
+// the gather at lattice coordinates g = (X/dx, Y/dy, Z/dz)
 template <typename R, bool kGrad, bool kYee, class Acc>
-GCB_HD void gather3(const Acc& acc, const PushConst3& pc, const Consts3<R>& K, double X,
-                    double Y, double Z, Sample3<R>& s) {
-    const double g[3] = {X * pc.b.inv_dx, Y * pc.b.inv_dy, Z * pc.inv_dz};
+GCB_HD void gather3_at(const Acc& acc, const PushConst3& pc, const Consts3<R>& K,
+                       const double g[3], Sample3<R>& s) {
     if constexpr (kYee) {
         // lattice coordinate minus the offset: offset 0 leaves it unchanged
         int fl[3][2];
@@ -149,6 +147,31 @@ GCB_HD void gather3(const Acc& acc, const PushConst3& pc, const Consts3<R>& K, d
             trilerp(f, (R)(xi - fi), (R)(eta - fj), (R)(zeta - fk), K, kGrad && k >= 3, val,
                     ddx, ddy, ddz);
             store_comp<R, kGrad>(k, val, ddx, ddy, ddz, s);
+        }
+    }
+}
+
+// All six components at (X, Y, Z); B gradients when kGrad.  kYee: the 3D Yee
+// offsets.  Lattice coordinates and weights in binary64 from the positions.
+template <typename R, bool kGrad, bool kYee, class Acc>
+GCB_HD void gather3(const Acc& acc, const PushConst3& pc, const Consts3<R>& K, double X,
+                    double Y, double Z, Sample3<R>& s) {
+    double g[3] = {X * pc.b.inv_dx, Y * pc.b.inv_dy, Z * pc.inv_dz};
+    // a runaway point (lattice coordinate NaN or of magnitude kFarLattice or
+    // more) is gathered at the origin and its sample replaced by NaN
+    const bool far = !(fabs(g[0]) < kFarLattice && fabs(g[1]) < kFarLattice &&
+                       fabs(g[2]) < kFarLattice);
+    if (__builtin_expect(far, 0)) g[0] = g[1] = g[2] = 0.0;
+    gather3_at<R, kGrad, kYee>(acc, pc, K, g, s);
+    if (__builtin_expect(far, 0)) {
+        const R q = (R)__builtin_nan("");
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            s.E[i] = q;
+            s.B[i] = q;
+            s.dBx[i] = q;
+            s.dBy[i] = q;
+            s.dBz[i] = q;
         }
     }
 }
@@ -251,7 +274,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
         const R upy = (uy - upar * Lh.b[1]) - (Lh.vE[1] + vc[1]) * gf;
         const R upz = (uz - upar * Lh.b[2]) - (Lh.vE[2] + vc[2]) * gf;
         const R up2 = (upx * upx + upy * upy) + upz * upz;
-        flags |= mirror_check(up2, gf, pc.b, K);
+        flags |= mirror_check(ux, uy, uz, Lh, vc, up2, gf, pc.b, K);
         gy.mu = pc.b.gyration == GYR_ZERO ? (R)0 : (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
         gy.up2 = up2;
         gy.fixed = pc.b.gyration == GYR_UPERP;

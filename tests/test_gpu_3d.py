@@ -85,7 +85,7 @@ def rel_errors3(got, ref, cfg):
             d = np.minimum(d, np.abs(L - d))
         with np.errstate(invalid="ignore"):
             r = d / np.maximum(np.abs(b), floor)
-        r = np.where(np.isnan(a) & np.isnan(b), 0.0, r)
+        r = np.where((a == b) | (np.isnan(a) & np.isnan(b)), 0.0, r)
         out[k] = float(np.max(r)) if r.size else 0.0
     return out
 

@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 UPERP = 1
 TOL_CHECK = 1e-3   # (v_perp_g/c)^2 threshold of the check of the neglect
+ST_MIRROR = 128
 
 
 @pytest.fixture(scope="module")
@@ -116,6 +117,28 @@ def test_mirror_parity_3d(kernel, sort_every, tile, steps):
         run.close()
 
 
+def _split_tol(run):
+    """A mirror_tol that the oracle's one step flags for between 5 % and 95 %
+    of the particles (run(tol) returns the oracle's state)."""
+    for tol in (1e-4, 1e-3, 1e-2, 0.03, 0.1, 0.3):
+        frac = float(((run(tol).status.numpy() & ST_MIRROR) != 0).mean())
+        if 0.05 < frac < 0.95:
+            log(f"mirror_tol {tol}: oracle flags {frac:.3f}")
+            return tol
+    raise AssertionError("no threshold splits the particles")
+
+
+def _check_mirror_bits(got, ref, tol):
+    """ST_MIRROR of the mixed form against the binary64 oracle: near the
+    threshold the mixed form repeats the comparison in binary64, so the bits
+    agree but for particles whose binary32 inputs moved them across it."""
+    a = (got["status"] & ST_MIRROR) != 0
+    b = (ref.status.numpy() & ST_MIRROR) != 0
+    mism = float((a != b).mean())
+    log(f"  ST_MIRROR at tol {tol}: {int(b.sum())} flagged by the oracle, mismatch {mism:.2e}")
+    assert mism <= 1e-3
+
+
 def test_mirror_mixed_one_step():
     """Mixed form against the binary64 oracle with the option, one step,
     both kernels: the bounds of the mixed form's one-step test."""
@@ -125,13 +148,15 @@ def test_mirror_mixed_one_step():
     ens = cfg.particles(n=8192, seed_offset=19)
     run = GpuRun(cfg, F, dtype=gcb.GCB_F32)
     try:
-        ref, rtr, _ = run_oracle(cfg, F, ens, 1, trace=True, mirror=True)
+        tol = _split_tol(lambda m: run_oracle(cfg, F, ens, 1, mirror=True, mirror_tol=m)[0])
+        ref, rtr, _ = run_oracle(cfg, F, ens, 1, trace=True, mirror=True, mirror_tol=tol)
         for kernel, se, tile in ((1, 0, 0), (2, 1, 16)):
             log(f"mixed mirror kernel={kernel}")
             t = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED)
             tr, _ = run.push(t, 1, trace=True, form=gcb.GCB_FORM_MIXED, kernel=kernel,
-                             sort_every=se, tile=tile, mirror=1)
+                             sort_every=se, tile=tile, mirror=1, mirror_tol=tol)
             got = state.unsort(t)
+            _check_mirror_bits(got, ref, tol)
             u_g = np.stack([got[k].astype(np.float64) for k in ("ux", "uy", "uz")])
             u_r = np.stack([getattr(ref, k).numpy() for k in ("ux", "uy", "uz")])
             du = np.max(np.abs(u_g - u_r), axis=0) / np.maximum(np.max(np.abs(u_r), axis=0),
@@ -192,14 +217,16 @@ def test_mirror_mixed_one_step_3d(kernel, sort_every, tile):
     F = cfg.fields()
     ens = cfg.particles(n=8192, seed_offset=21)
     run = GpuRun3(cfg, F, dtype=gcb.GCB_F32)
+    tol = _split_tol(lambda m: run_oracle3(cfg, F, ens, 1, mirror=True, mirror_tol=m)[0])
     try:
         t = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED)
         tr, _ = run.push(t, 1, trace=True, form=gcb.GCB_FORM_MIXED, kernel=kernel,
-                         sort_every=sort_every, tile=tile, mirror=1)
+                         sort_every=sort_every, tile=tile, mirror=1, mirror_tol=tol)
     finally:
         run.close()
     got = state.unsort(t)
-    ref, rtr, _ = run_oracle3(cfg, F, ens, 1, trace=True, mirror=True)
+    ref, rtr, _ = run_oracle3(cfg, F, ens, 1, trace=True, mirror=True, mirror_tol=tol)
+    _check_mirror_bits(got, ref, tol)
     u_g = np.stack([got[k].astype(np.float64) for k in ("ux", "uy", "uz")])
     u_r = np.stack([getattr(ref, k).numpy() for k in ("ux", "uy", "uz")])
     du = np.max(np.abs(u_g - u_r), axis=0) / np.maximum(np.max(np.abs(u_r), axis=0), cfg.c)
