@@ -14,6 +14,11 @@ GcbPush3 / push3 do the same for the 3D push with gcb_push_backward_3d
 KineticEnergy is the mean (Gamma - 1) c^2 of a state, computed by the
 library's reduction kernel; its backward uses dL/du = u/(n Gamma).
 
+A context holds one set of fields at a time.  Each forward records the
+context's load generation and keeps E and B; a backward that finds other
+fields loaded (a second forward on the same context ran in between, e.g. one
+of a finite-difference pair) loads its own again before recomputing.
+
 Argument marshalling and segment bookkeeping only: every step of the push and
 of its derivative runs in the library's kernels.  Sorting is not used here
 (the adjoint recomputes steps unsorted, with identical arithmetic).
@@ -32,6 +37,7 @@ class PushContext:
 
     def __init__(self, device: int = 0):
         self.ctx = gcb.gcb_create(device)
+        self.generation = 0   # incremented by every load
 
     def load(self, E: torch.Tensor, B: torch.Tensor, dx=1.0, dy=1.0,
              stagger=gcb.YEE_STAGGER):
@@ -42,11 +48,21 @@ class PushContext:
         gcb.gcb_load_fields(self.ctx, desc, Ec, Bc, src=gcb.GCB_DEVICE)
         torch.cuda.current_stream().synchronize()
         self.shape = (ny, nx)
+        self.generation += 1
 
     def close(self):
         if self.ctx is not None:
             gcb.gcb_destroy(self.ctx)
             self.ctx = None
+
+
+def _reload_if_replaced(ctx, pctx):
+    """Load the fields of this graph's forward again if another load has
+    replaced them on the shared context since."""
+    if pctx.generation != ctx.generation:
+        E, B = ctx.saved_tensors
+        pctx.load(E, B)
+        ctx.generation = pctx.generation
 
 
 def _parts(st: dict, qm):
@@ -74,11 +90,14 @@ class GcbPush(torch.autograd.Function):
             done += k
         ctx.pctx, ctx.prm, ctx.segs, ctx.qm = pctx, prm, segs, qmd
         ctx.shape = tuple(E.shape)
+        ctx.generation = pctx.generation
+        ctx.save_for_backward(E.detach(), B.detach())
         return tuple(st[k] for k in _NAMES)
 
     @staticmethod
     def backward(ctx, *grads):
         pctx, prm = ctx.pctx, ctx.prm
+        _reload_if_replaced(ctx, pctx)
         ref = ctx.segs[0][0]["x"] if ctx.segs else None
         dev = ref.device if ref is not None else torch.device("cuda")
         n = ref.shape[0] if ref is not None else 0
@@ -128,6 +147,7 @@ class PushContext3(PushContext):
         gcb.gcb_load_fields_3d(self.ctx, desc, Ec, Bc, src=gcb.GCB_DEVICE)
         torch.cuda.current_stream().synchronize()
         self.shape = (nz, ny, nx)
+        self.generation += 1
 
 
 class GcbPush3(torch.autograd.Function):
@@ -149,11 +169,14 @@ class GcbPush3(torch.autograd.Function):
             done += k
         ctx.pctx, ctx.prm, ctx.segs, ctx.qm = pctx, prm, segs, qmd
         ctx.shape = tuple(E.shape)
+        ctx.generation = pctx.generation
+        ctx.save_for_backward(E.detach(), B.detach())
         return tuple(st[k] for k in _NAMES3)
 
     @staticmethod
     def backward(ctx, *grads):
         pctx, prm = ctx.pctx, ctx.prm
+        _reload_if_replaced(ctx, pctx)
         ref = ctx.segs[0][0]["x"] if ctx.segs else None
         dev = ref.device if ref is not None else torch.device("cuda")
         n = ref.shape[0] if ref is not None else 0

@@ -111,6 +111,14 @@ int ensure(gcb_ctx* ctx, DevBuf& b, size_t bytes) {
     return GCB_OK;
 }
 
+// Scratch of a call, from the context buffer `b` (grown with hipMalloc).
+int take(gcb_ctx* ctx, DevBuf& b, size_t bytes, void** out) {
+    const int rc = ensure(ctx, b, bytes);
+    if (rc) return rc;
+    *out = b.ptr;
+    return GCB_OK;
+}
+
 void release(DevBuf& b) {
     if (b.ptr) (void)hipFree(b.ptr);
     b.ptr = nullptr;
@@ -245,9 +253,10 @@ int scratch_state(gcb_ctx* ctx, const ParticlePtrs<U>& like, int64_t n, Particle
     auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
     size_t bytes = (4 + n_extra) * up(nd) + 3 * up(nu) + up(n) + (like.qm ? up(nd) : 0) +
                    (like.id ? up((size_t)n * 4) : 0);
-    int rc = ensure(ctx, ctx->pscratch, bytes);
+    void* base;
+    int rc = take(ctx, ctx->pscratch, bytes, &base);
     if (rc) return rc;
-    char* b = static_cast<char*>(ctx->pscratch.ptr);
+    char* b = static_cast<char*>(base);
     auto take = [&](size_t s) {
         char* r = b;
         b += up(s);
@@ -362,17 +371,28 @@ size_t record_budget(size_t fixed) {
     return std::min(fixed, free_b / 2);
 }
 
+// Halo of the LDS window in nodes: the drift bound c dt per step over the
+// steps between sorts, plus one node for the stencil.  Formed in binary64;
+// 0 when it exceeds kMaxHalo (no window that large fits in LDS, and the int
+// arithmetic of the window origin stays far from overflow).  A window of 0
+// marks the tiled kernel as unavailable.
+constexpr double kMaxHalo = 256.0;
+int window_halo(const gcb_params* prm, double inv_min_cell) {
+    const int se = prm->sort_every > 0 ? prm->sort_every : 1;
+    const double h = std::ceil(((double)se * prm->c) * prm->dt * inv_min_cell) + 1.0;
+    return (h <= kMaxHalo) ? (int)h : 0;
+}
+
 TileGeom3 make_geom3(const gcb_ctx* ctx, const gcb_params* prm) {
     TileGeom3 g;
     g.tile = prm->tile ? prm->tile : 6;
     const double inv_min =
         std::max(1.0 / ctx->d3[0], std::max(1.0 / ctx->d3[1], 1.0 / ctx->d3[2]));
-    const int se = prm->sort_every > 0 ? prm->sort_every : 1;
-    g.halo = (int)std::ceil(se * prm->c * prm->dt * inv_min) + 1;
+    g.halo = window_halo(prm, inv_min);
     g.ntx = (ctx->n3[0] + g.tile - 1) / g.tile;
     g.nty = (ctx->n3[1] + g.tile - 1) / g.tile;
     g.ntz = (ctx->n3[2] + g.tile - 1) / g.tile;
-    g.window = g.tile + 2 * g.halo;
+    g.window = g.halo > 0 ? g.tile + 2 * g.halo : 0;
     return g;
 }
 
@@ -380,11 +400,10 @@ TileGeom make_geom(const gcb_ctx* ctx, const gcb_params* prm) {
     TileGeom g;
     g.tile = prm->tile ? prm->tile : 24;
     const double inv_min = std::max(1.0 / ctx->dx, 1.0 / ctx->dy);
-    const int se = prm->sort_every > 0 ? prm->sort_every : 1;
-    g.halo = (int)std::ceil(se * prm->c * prm->dt * inv_min) + 1;
+    g.halo = window_halo(prm, inv_min);
     g.ntx = (ctx->nx + g.tile - 1) / g.tile;
     g.nty = (ctx->ny + g.tile - 1) / g.tile;
-    g.window = g.tile + 2 * g.halo;
+    g.window = g.halo > 0 ? g.tile + 2 * g.halo : 0;
     return g;
 }
 
@@ -392,50 +411,61 @@ constexpr size_t kMaxLds = 160 * 1024;
 
 int prepare_sort(gcb_ctx* ctx, int64_t n, int ntiles, SortBuffers& sb) {
     int rc;
-    if ((rc = ensure(ctx, ctx->sort_keys, (size_t)n * 4))) return rc;
-    if ((rc = ensure(ctx, ctx->sort_idx, (size_t)n * 4))) return rc;
-    if ((rc = ensure(ctx, ctx->sort_keys2, (size_t)n * 4))) return rc;
-    if ((rc = ensure(ctx, ctx->sort_idx2, (size_t)n * 4))) return rc;
+    void *k, *i, *k2, *i2, *h, *sc, *ts;
+    if ((rc = take(ctx, ctx->sort_keys, (size_t)n * 4, &k))) return rc;
+    if ((rc = take(ctx, ctx->sort_idx, (size_t)n * 4, &i))) return rc;
+    if ((rc = take(ctx, ctx->sort_keys2, (size_t)n * 4, &k2))) return rc;
+    if ((rc = take(ctx, ctx->sort_idx2, (size_t)n * 4, &i2))) return rc;
     const int64_t nh = sort_hist_elems(n);
-    if ((rc = ensure(ctx, ctx->sort_hist, (size_t)nh * 4))) return rc;
+    if ((rc = take(ctx, ctx->sort_hist, (size_t)nh * 4, &h))) return rc;
     const int64_t ns = std::max(sort_scan_tmp_elems(nh), sort_scan_tmp_elems(ntiles + 1));
-    if ((rc = ensure(ctx, ctx->sort_scan, (size_t)ns * 4))) return rc;
-    if ((rc = ensure(ctx, ctx->tile_start, (size_t)(ntiles + 1) * 4))) return rc;
-    sb.keys = static_cast<uint32_t*>(ctx->sort_keys.ptr);
-    sb.idx = static_cast<uint32_t*>(ctx->sort_idx.ptr);
-    sb.keys2 = static_cast<uint32_t*>(ctx->sort_keys2.ptr);
-    sb.idx2 = static_cast<uint32_t*>(ctx->sort_idx2.ptr);
-    sb.hist = static_cast<uint32_t*>(ctx->sort_hist.ptr);
-    sb.scan_tmp = static_cast<uint32_t*>(ctx->sort_scan.ptr);
-    sb.tile_start = static_cast<int32_t*>(ctx->tile_start.ptr);
+    if ((rc = take(ctx, ctx->sort_scan, (size_t)ns * 4, &sc))) return rc;
+    if ((rc = take(ctx, ctx->tile_start, (size_t)(ntiles + 1) * 4, &ts))) return rc;
+    sb.keys = static_cast<uint32_t*>(k);
+    sb.idx = static_cast<uint32_t*>(i);
+    sb.keys2 = static_cast<uint32_t*>(k2);
+    sb.idx2 = static_cast<uint32_t*>(i2);
+    sb.hist = static_cast<uint32_t*>(h);
+    sb.scan_tmp = static_cast<uint32_t*>(sc);
+    sb.tile_start = static_cast<int32_t*>(ts);
     return GCB_OK;
 }
 
 // the slots, then the flagged count and eight status-bit counts
 constexpr size_t kStatBytes = kStatSlots * sizeof(DevStats) + 9 * sizeof(unsigned long long);
 
-// zero the device accumulators of a push that reports statistics
-int stats_begin(gcb_ctx* ctx, const gcb_stats* stats, hipStream_t stream, DevStats** dstats) {
+// the device accumulators of a push that reports statistics (not cleared)
+int stats_take(gcb_ctx* ctx, const gcb_stats* stats, DevStats** dstats) {
     *dstats = nullptr;
     if (!stats) return GCB_OK;
-    int rc;
-    if ((rc = ensure(ctx, ctx->stats, kStatBytes))) return rc;
-    *dstats = static_cast<DevStats*>(ctx->stats.ptr);
-    GCB_HIP(hipMemsetAsync(*dstats, 0, kStatBytes, stream));
+    void* p;
+    const int rc = take(ctx, ctx->stats, kStatBytes, &p);
+    if (rc) return rc;
+    *dstats = static_cast<DevStats*>(p);
     return GCB_OK;
 }
 
+// clear them (a kernel on the stream)
+int stats_zero(gcb_ctx* ctx, DevStats* dstats, hipStream_t stream) {
+    if (dstats) GCB_HIP(launch_zero_words(dstats, (int64_t)(kStatBytes / 8), stream));
+    return GCB_OK;
+}
+
+int stats_begin(gcb_ctx* ctx, const gcb_stats* stats, hipStream_t stream, DevStats** dstats) {
+    const int rc = stats_take(ctx, stats, dstats);
+    return rc ? rc : stats_zero(ctx, *dstats, stream);
+}
+
 // count the flagged particles, copy the accumulators back and sum the slots
-int stats_end(gcb_ctx* ctx, const uint8_t* status, int64_t n, gcb_stats* stats,
-              hipStream_t stream) {
+int stats_end(gcb_ctx* ctx, DevStats* dstats, const uint8_t* status, int64_t n,
+              gcb_stats* stats, hipStream_t stream) {
     if (!stats) return GCB_OK;
-    DevStats* dstats = static_cast<DevStats*>(ctx->stats.ptr);
     // the flagged count and the eight status-bit counts go to the nine words
     // after the slots
     unsigned long long* flagged = reinterpret_cast<unsigned long long*>(dstats + kStatSlots);
     GCB_HIP(launch_count_flagged(status, n, flagged, stream));
-    std::vector<DevStats> host(kStatSlots + 2);
-    GCB_HIP(hipMemcpyAsync(host.data(), dstats, kStatBytes, hipMemcpyDeviceToHost, stream));
+    DevStats host[kStatSlots + 2];   // 33 kB on the host stack: no allocation
+    GCB_HIP(hipMemcpyAsync(host, dstats, kStatBytes, hipMemcpyDeviceToHost, stream));
     GCB_HIP(hipStreamSynchronize(stream));
     unsigned long long g = 0, b = 0, h = 0, mbits = 0;
     for (int s = 0; s < kStatSlots; ++s) {
@@ -511,7 +541,8 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     const PushConst pc = make_const(ctx, prm);
     const TileGeom g = make_geom(ctx, prm);
     const size_t esz = prm->form == GCB_FORM_F64 ? sizeof(double) : sizeof(float);
-    const bool tiled_ok = prm->sort_every > 0 && tiled_lds_bytes(g.window, esz) <= kMaxLds;
+    const bool tiled_ok =
+        prm->sort_every > 0 && g.window > 0 && tiled_lds_bytes(g.window, esz) <= kMaxLds;
     PushKind kind;
     int rc;
     if ((rc = choose_kind(ctx, prm, tiled_ok, g.window, &kind))) return rc;
@@ -522,6 +553,8 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         if ((rc = prepare_sort(ctx, n, g.ntx * g.nty, sb))) return rc;
         if ((rc = scratch_state<U>(ctx, user, n, scr))) return rc;
     }
+    // all scratch is in place: the first device work of the call
+    if ((rc = stats_zero(ctx, dstats, stream))) return rc;
     // On a sort step the push reads the state through the sort's permutation
     // and writes it in tile order into the other of two buffers (the caller's
     // arrays and a library copy); the other steps work in place.  A state
@@ -605,7 +638,8 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
     const PushConst3 pc = make_const3(ctx, prm);
     const TileGeom3 g = make_geom3(ctx, prm);
     const size_t esz = prm->form == GCB_FORM_F64 ? sizeof(double) : sizeof(float);
-    const bool tiled_ok = prm->sort_every > 0 && tiled3_lds_bytes(g.window, esz) <= kMaxLds;
+    const bool tiled_ok =
+        prm->sort_every > 0 && g.window > 0 && tiled3_lds_bytes(g.window, esz) <= kMaxLds;
     PushKind kind;
     int rc;
     if ((rc = choose_kind(ctx, prm, tiled_ok, g.window, &kind))) return rc;
@@ -787,13 +821,13 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     GCB_HIP(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DevStats* dstats;
-    if ((rc = stats_begin(ctx, stats, stream, &dstats))) return rc;
+    if ((rc = stats_take(ctx, stats, &dstats))) return rc;
     if (prm->form == GCB_FORM_F64)
         rc = run_push<double>(ctx, p, prm, n_steps, s_trace, dstats, stream);
     else
         rc = run_push<float>(ctx, p, prm, n_steps, s_trace, dstats, stream);
     if (rc) return rc;
-    return stats_end(ctx, p->status, p->n, stats, stream);
+    return stats_end(ctx, dstats, p->status, p->n, stats, stream);
 }
 
 int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params* prm,
@@ -1102,7 +1136,7 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
         GCB_HIP(push(ptrs, ptrs, nullptr, n_steps, 0));
         t.done();
     }
-    return stats_end(ctx, p->status, p->n, stats, stream);
+    return stats_end(ctx, dstats, p->status, p->n, stats, stream);
 }
 
 int gcb_load_fields_3d(gcb_ctx* ctx, const gcb_grid3_desc* d, const double* const E[3],
@@ -1181,7 +1215,7 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t 
     else
         rc = run_push3<float>(ctx, p, prm, n_steps, s_trace, dstats, stream);
     if (rc) return rc;
-    return stats_end(ctx, p->status, p->n, stats, stream);
+    return stats_end(ctx, dstats, p->status, p->n, stats, stream);
 }
 
 int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_params* prm,

@@ -134,6 +134,9 @@ int64_t kinetic_partial_elems(int64_t n);
 hipError_t launch_count_flagged(const uint8_t* status, int64_t n,
                                 unsigned long long* out, hipStream_t stream);
 
+// zero `words` 8-byte words at p (8-byte aligned) with a kernel
+hipError_t launch_zero_words(void* p, int64_t words, hipStream_t stream);
+
 // ---------------------------------------------------------------------------
 // adjoint
 

@@ -97,7 +97,22 @@ __global__ __launch_bounds__(kWG) void k_count_flagged(const uint8_t* __restrict
     }
 }
 
+// zero n 8-byte words (a kernel, not a memset node, so that the clear is an
+// ordinary kernel of the stream wherever the caller records it)
+__global__ __launch_bounds__(kWG) void k_zero_words(unsigned long long* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 }  // namespace
+
+hipError_t launch_zero_words(void* p, int64_t words, hipStream_t stream) {
+    if (words <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((words + kWG - 1) / kWG);
+    hipLaunchKernelGGL(k_zero_words, dim3(blocks), dim3(kWG), 0, stream,
+                       static_cast<unsigned long long*>(p), words);
+    return hipGetLastError();
+}
 
 hipError_t launch_interleave_fields(const double* const comps[6], int nx, int ny, void* dst,
                                     bool to_float, hipStream_t stream) {

@@ -101,6 +101,42 @@ def test_checkpoint_segments_do_not_change_gradients():
     assert np.max(np.abs(f1 - f2)) <= 1e-6 * np.max(np.abs(f1))
 
 
+def test_backward_after_second_forward_on_shared_context():
+    """Two forwards on one PushContext (the second with perturbed fields, as
+    in a finite-difference pair), then the backward of the first: its
+    gradients equal those of a run on a context of its own, bit for bit."""
+    from paper_2007_14401_amd import autograd as A, gcb
+    cfg = make_config("harris64")
+    F = cfg.fields()
+    ens = cfg.particles(n=300, seed_offset=6)
+    steps = 10
+    _, g_ref, f_ref = _grad_gpu(cfg, F, ens, steps, 4)
+    pctx = A.PushContext(0)
+    try:
+        prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                         curvature=cfg.curvature, n_iter=cfg.n_iter)
+        qm = torch.as_tensor(ens.qm, dtype=torch.float64, device=DEV)
+
+        def forward(scale):
+            E, B = _fields(F)
+            E = (E * scale).requires_grad_(True)
+            B = (B * scale).requires_grad_(True)
+            st = {k: v.requires_grad_(True) for k, v in _tensors(ens).items()}
+            out = A.push(E, B, *[st[k] for k in NAMES], qm, pctx, prm, steps, 4)
+            return E, B, st, A.kinetic_energy(out[4], out[5], out[6], pctx, prm)
+
+        E1, B1, st1, L1 = forward(1.0)
+        forward(1.001)          # replaces the fields held by the context
+        L1.backward()
+        torch.cuda.synchronize()
+        for k in NAMES:
+            assert np.array_equal(st1[k].grad.cpu().numpy(), g_ref[k]), k
+        gF = torch.cat([E1.grad, B1.grad]).cpu().numpy()
+        assert np.max(np.abs(gF - f_ref)) <= 1e-6 * np.max(np.abs(f_ref))
+    finally:
+        pctx.close()
+
+
 def _c4_fd(steps, n_nodes, n_u, node_h, min_nodes, min_u):
     """Central differences of the push with replayed switch decisions against
     the adjoint on the differentiation workload (1024^2 grid, 1e6 particles)."""
