@@ -227,6 +227,27 @@ typedef struct {
 int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm,
              int32_t n_steps, uint8_t* s_trace, gcb_stats* stats, void* stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc: gcb_push
+   (same arguments, same kernels, bit-for-bit the same results) with every
+   piece of the library's call scratch (cell-sort keys and permutation, the
+   tile-ordered copy of the state, statistics accumulators) carved from a
+   fixed device array of GCB_NOALLOC_SCRATCH_BYTES that the library holds on
+   each device it runs on until the process ends; the call performs no
+   hipMalloc/hipFree and no other allocation.  With sorting on (sort_every >
+   0, n > 0) a call needs about (16 + 4*8 + 3*sizeof(u) + 1 [+ 8 with qm]
+   [+ 4 with id]) bytes per particle plus 32 kB for statistics: about 720,000
+   binary64 particles with qm and id fit.  A call that needs more returns
+   GCB_EINVAL before any device work is enqueued.  Fields must have been
+   loaded (gcb_load_fields allocates).  The array keeps the last call's
+   contents; what must start at zero is cleared by the call.  Every context
+   on a device shares that device's array: calls that overlap in time on one
+   device (other streams, other threads) race and must be serialised by the
+   caller.  Timings (gcb_set_timing) are not recorded for this call. */
+#define GCB_NOALLOC_SCRATCH_BYTES (64u << 20)
+int gcb_push_noalloc(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm,
+                     int32_t n_steps, uint8_t* s_trace, gcb_stats* stats, void* stream);
+
 /* Reverse-mode derivative of n_steps pushes started from `start` (which is
    not modified), with every switch decision held at its forward value.
    lam_end[7]: device arrays of length n with dL/d(x, y, xp, yp, ux, uy, uz)

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,34 @@ struct TimedLaunch {
     hipEvent_t start, stop;
 };
 
+}  // namespace
+
+// The fixed scratch of gcb_push_noalloc: one copy per device, which the
+// device holds until the process ends.  Host code never uses the array's
+// name as an address: gcb_create looks up the device's copy once per device
+// with hipGetSymbolAddress and every use goes through that pointer.
+constexpr size_t kNoAllocScratchBytes = (size_t)GCB_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// address of `scratch` on `device` (the current device), looked up once
+hipError_t noalloc_scratch(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 }  // namespace
 
 struct gcb_ctx {
@@ -60,6 +89,12 @@ struct gcb_ctx {
     DevBuf stats;        // DevStats + flagged counter
     DevBuf ke_partial;
     DevBuf adj_states, adj_lam, adj_grad, adj_trace, adj_work, adj_samples, adj_lists;
+    // fixed scratch of gcb_push_noalloc on this context's device (the address
+    // of the file-scope array `scratch` there); while `arena` is set, every
+    // piece of call scratch is carved from it instead of allocated
+    char* noalloc_base = nullptr;
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
     // timing
     bool timing = false;
     std::vector<TimedLaunch> launches;
@@ -111,8 +146,20 @@ int ensure(gcb_ctx* ctx, DevBuf& b, size_t bytes) {
     return GCB_OK;
 }
 
-// Scratch of a call, from the context buffer `b` (grown with hipMalloc).
+// Scratch of a call: from the context buffer `b` (grown with hipMalloc), or,
+// inside gcb_push_noalloc, carved from the fixed array (256-byte aligned),
+// failing with GCB_EINVAL when it is exhausted.
 int take(gcb_ctx* ctx, DevBuf& b, size_t bytes, void** out) {
+    if (ctx->arena) {
+        const size_t off = (ctx->arena_used + 255) & ~(size_t)255;
+        if (off > ctx->arena_cap || bytes > ctx->arena_cap - off)
+            return fail(ctx, GCB_EINVAL,
+                        "gcb_push_noalloc: the call needs more than the %zu bytes of its fixed "
+                        "scratch (fewer particles, or gcb_push)", ctx->arena_cap);
+        *out = ctx->arena + off;
+        ctx->arena_used = off + bytes;
+        return GCB_OK;
+    }
     const int rc = ensure(ctx, b, bytes);
     if (rc) return rc;
     *out = b.ptr;
@@ -733,9 +780,15 @@ int gcb_create(gcb_ctx** out, int device) {
     e = hipSetDevice(device);
     if (e != hipSuccess)
         return fail(nullptr, GCB_EHIP, "hipSetDevice(%d): %s", device, hipGetErrorString(e));
+    void* base = nullptr;
+    e = noalloc_scratch(device, &base);
+    if (e != hipSuccess)
+        return fail(nullptr, GCB_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                    hipGetErrorString(e));
     gcb_ctx* c = new (std::nothrow) gcb_ctx();
     if (!c) return fail(nullptr, GCB_ENOMEM, "out of host memory");
     c->device = device;
+    c->noalloc_base = static_cast<char*>(base);
     *out = c;
     return GCB_OK;
 }
@@ -828,6 +881,26 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         rc = run_push<float>(ctx, p, prm, n_steps, s_trace, dstats, stream);
     if (rc) return rc;
     return stats_end(ctx, dstats, p->status, p->n, stats, stream);
+}
+
+int gcb_push_noalloc(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_steps,
+                     uint8_t* s_trace, gcb_stats* stats, void* stream) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    if (!ctx->noalloc_base)
+        return fail(ctx, GCB_EHIP, "the fixed scratch of device %d is not available",
+                    ctx->device);
+    // every piece of scratch below is carved from the device's fixed array;
+    // timing records (a growing host list) are not kept for this call
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    ctx->arena = ctx->noalloc_base;
+    ctx->arena_cap = kNoAllocScratchBytes;
+    ctx->arena_used = 0;
+    const int rc = gcb_push(ctx, p, prm, n_steps, s_trace, stats, stream);
+    ctx->arena = nullptr;
+    ctx->arena_cap = ctx->arena_used = 0;
+    ctx->timing = timing;
+    return rc;
 }
 
 int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params* prm,

@@ -113,6 +113,8 @@ def _load():
                                       C.POINTER(P * 3), C.c_int32, P]),
         "gcb_push": (C.c_int, [P, C.POINTER(gcb_particles), C.POINTER(gcb_params),
                                C.c_int32, P, C.POINTER(gcb_stats), P]),
+        "gcb_push_noalloc": (C.c_int, [P, C.POINTER(gcb_particles), C.POINTER(gcb_params),
+                                       C.c_int32, P, C.POINTER(gcb_stats), P]),
         "gcb_push_backward": (C.c_int, [P, C.POINTER(gcb_particles), C.POINTER(gcb_params),
                                         C.c_int32, C.POINTER(P * 7), C.POINTER(P * 7),
                                         C.POINTER(P * 3), C.POINTER(P * 3), P]),
@@ -144,7 +146,7 @@ _lib = _load()
 EXPORTED = ("gcb_create", "gcb_destroy", "gcb_last_error", "gcb_load_fields", "gcb_push",
             "gcb_push_backward", "gcb_kinetic_energy", "gcb_set_timing", "gcb_get_timing",
             "gcb_load_fields_gr", "gcb_push_gr", "gcb_load_fields_3d", "gcb_push_3d",
-            "gcb_push_backward_3d")
+            "gcb_push_backward_3d", "gcb_push_noalloc")
 
 
 def lib():
@@ -262,6 +264,21 @@ def gcb_push(ctx, parts: gcb_particles, prm: gcb_params, n_steps: int, s_trace=N
     if st is None:
         return None
     return _stats_dict(st)
+
+
+def gcb_push_noalloc(ctx, parts: gcb_particles, prm: gcb_params, n_steps: int, s_trace=None,
+                     want_stats: bool = False, stream=None):
+    """gcb_push with the library's scratch taken from its fixed device array."""
+    st = gcb_stats() if want_stats else None
+    rc = _lib.gcb_push_noalloc(ctx, C.byref(parts), C.byref(prm), int(n_steps), _ptr(s_trace),
+                               C.byref(st) if st is not None else None, _stream_ptr(stream))
+    _check(rc, ctx)
+    if st is None:
+        return None
+    return _stats_dict(st)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def gcb_push_backward(ctx, start: gcb_particles, prm: gcb_params, n_steps: int, lam_end,
