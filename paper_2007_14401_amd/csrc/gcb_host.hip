@@ -231,6 +231,16 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EUNSUPPORTED, "the mirror terms need curvature = 1");
     if (!(std::isfinite(prm->mirror_tol) && prm->mirror_tol >= 0.0))
         return fail(ctx, GCB_EINVAL, "mirror_tol must be finite and >= 0");
+    if (prm->arith != GCB_ARITH_EXACT && prm->arith != GCB_ARITH_FAST)
+        return fail(ctx, GCB_EINVAL, "unknown arith %d", prm->arith);
+    return GCB_OK;
+}
+
+// the contracted binary64 arithmetic is served by the 2D binary64 push only
+int reject_fast_arith(gcb_ctx* ctx, const gcb_params* prm) {
+    if (prm->arith != GCB_ARITH_EXACT)
+        return fail(ctx, GCB_EUNSUPPORTED,
+                    "GCB_ARITH_FAST is served by gcb_push with GCB_FORM_F64 only");
     return GCB_OK;
 }
 
@@ -238,6 +248,7 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
 // than a conserved mu and the mirror terms are served by gcb_push and
 // gcb_push_3d only, the check of the mirror terms (check_ok) by the pushes
 int reject_push_options(gcb_ctx* ctx, const gcb_params* prm, bool check_ok = false) {
+    if (reject_fast_arith(ctx, prm)) return GCB_EUNSUPPORTED;
     if (prm->frame != GCB_FRAME_REDUCED)
         return fail(ctx, GCB_EUNSUPPORTED,
                     "the exact frame is served by gcb_push and gcb_push_3d only");
@@ -588,8 +599,8 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     const PushConst pc = make_const(ctx, prm);
     const TileGeom g = make_geom(ctx, prm);
     const size_t esz = prm->form == GCB_FORM_F64 ? sizeof(double) : sizeof(float);
-    const bool tiled_ok =
-        prm->sort_every > 0 && g.window > 0 && tiled_lds_bytes(g.window, esz) <= kMaxLds;
+    const bool tiled_ok = prm->sort_every > 0 && g.window > 0 && g.window <= kTiledMaxWindow &&
+                          tiled_lds_bytes(g.window, esz) <= kMaxLds;
     PushKind kind;
     int rc;
     if ((rc = choose_kind(ctx, prm, tiled_ok, g.window, &kind))) return rc;
@@ -606,17 +617,14 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     // and writes it in tile order into the other of two buffers (the caller's
     // arrays and a library copy); the other steps work in place.  A state
     // that ends in the library copy is copied back.  The global kernel keeps a
-    // particle in registers for up to kGlobalStepsPerLaunch steps (not past
-    // the next sort).
+    // particle in registers, the tiled kernel a tile's particles in LDS, for
+    // up to 16 steps per launch (not past the next sort).
     constexpr int32_t kGlobalStepsPerLaunch = 16;
     ParticlePtrs<U> cur = user, other = scr;
     for (int32_t step = 0; step < n_steps;) {
-        int32_t ns = 1;
-        if (kind == PushKind::Global) {
-            ns = std::min(kGlobalStepsPerLaunch, n_steps - step);
-            if (prm->sort_every > 0)
-                ns = std::min(ns, prm->sort_every - step % prm->sort_every);
-        }
+        int32_t ns = std::min(kind == PushKind::Global ? kGlobalStepsPerLaunch : kTiledMaxSteps,
+                              n_steps - step);
+        if (prm->sort_every > 0) ns = std::min(ns, prm->sort_every - step % prm->sort_every);
         ParticlePtrs<U> dst = cur;
         const uint32_t* perm = nullptr;
         if (prm->sort_every > 0 && n > 0 && step % prm->sort_every == 0) {
@@ -643,7 +651,8 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))
-            e = launch_push_f64(L, cur, dst, pc, stream);
+            e = prm->arith == GCB_ARITH_FAST ? launch_push_f64_fast(L, cur, dst, pc, stream)
+                                             : launch_push_f64(L, cur, dst, pc, stream);
         else
             e = launch_push_mixed(L, cur, dst, pc, stream);
         if (e != hipSuccess)
@@ -862,6 +871,8 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     if (prm->frame == GCB_FRAME_EXACT && (prm->curvature != 0 || prm->form != GCB_FORM_F64))
         return fail(ctx, GCB_EUNSUPPORTED,
                     "the exact frame needs curvature = 0 and GCB_FORM_F64");
+    if (prm->arith == GCB_ARITH_FAST && prm->form != GCB_FORM_F64)
+        return fail(ctx, GCB_EUNSUPPORTED, "GCB_ARITH_FAST needs GCB_FORM_F64");
     if (!ctx->have_fields) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields was not called");
     if (prm->form == GCB_FORM_F64 && ctx->dtype != GCB_F64)
         return fail(ctx, GCB_EINVAL, "GCB_FORM_F64 needs fields loaded as GCB_F64");
@@ -1258,6 +1269,7 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t 
     if (!p) return fail(ctx, GCB_EINVAL, "particles is NULL");
     int rc;
     if ((rc = validate_params(ctx, prm))) return rc;
+    if ((rc = reject_fast_arith(ctx, prm))) return rc;
     // the 2D checks on the x, y, u, qm, id and status arrays, then z
     gcb_particles view{p->n, p->x, p->y, p->xp, p->yp, p->ux, p->uy, p->uz, p->qm, p->id,
                        p->status};

@@ -43,14 +43,23 @@ hipError_t launch_push_f64(const PushLaunch& L, const ParticlePtrs<double>& in,
                            const ParticlePtrs<double>& out, const PushConst& pc,
                            hipStream_t stream);
 
+// binary64 form with contracted multiply-adds (GCB_ARITH_FAST)
+hipError_t launch_push_f64_fast(const PushLaunch& L, const ParticlePtrs<double>& in,
+                                const ParticlePtrs<double>& out, const PushConst& pc,
+                                hipStream_t stream);
+
 // mixed form (fields float, u float)
 hipError_t launch_push_mixed(const PushLaunch& L, const ParticlePtrs<float>& in,
                              const ParticlePtrs<float>& out, const PushConst& pc,
                              hipStream_t stream);
 
-// LDS bytes the tiled kernel needs for a window of `window` nodes per side.
+// LDS bytes the tiled kernel needs for a window of `window` nodes per side
+// (window <= kTiledMaxWindow).
 size_t tiled_lds_bytes(int window, size_t elem_bytes);
-constexpr int kQueueMax = 2048;   // particles compacted per pass in a tile
+constexpr int kTiledChunk = 256;       // particles a tiled workgroup holds in LDS at once
+constexpr int kTiledMaxWindow = 64;    // window edge the tiled kernel stages
+constexpr int kTiledMaxSteps = 16;     // steps per tiled launch (not past the next sort)
+constexpr int kQueueMax = 2048;   // particles compacted per pass in a 3D tile
 
 // ---------------------------------------------------------------------------
 // 3D push

@@ -23,7 +23,15 @@
 #include "gcb_access.hpp"
 #include "gcb_common.hpp"
 
+// The arithmetic below is compiled once per form and contraction setting
+// (each in a translation unit of its own); an inline namespace per setting
+// keeps the instances of different units apart.
+#ifndef GCB_ARITH_NS
+#define GCB_ARITH_NS arith_exact
+#endif
+
 namespace gcb {
+inline namespace GCB_ARITH_NS {
 
 template <typename R>
 constexpr bool kMixed = std::is_same<R, float>::value;
@@ -792,4 +800,5 @@ GCB_HD uint32_t finite_flag(const Regs<R>& r) {
     return ok ? 0u : (uint32_t)ST_NONFINITE;
 }
 
+}  // inline namespace GCB_ARITH_NS
 }  // namespace gcb

@@ -8,12 +8,14 @@
 //
 // k_push_global: one lane per particle, any particle order, gathers through
 //   the cache hierarchy from the node-interleaved field array.
-// k_push_tiled: one workgroup per tile of cell-sorted particles.  The tile's
-//   field window (tile + halo, all six components) is staged once in LDS;
-//   then, per pass of up to kQueueMax particles, every lane evaluates the
-//   switch for its particle and the workgroup builds two queues in LDS
-//   (guiding-center first, Boris from the back), so that each wavefront of the
-//   update pass runs a single branch of the coupled step.
+// k_push_tiled: one workgroup per tile of cell-sorted particles for all the
+//   steps of a launch (those between two sorts).  The tile's field window
+//   (tile + halo, all six components) is staged once in LDS; the particles
+//   are taken in chunks of up to kWG whose state stays in LDS for all steps;
+//   per step every lane evaluates the switch for its particle and the
+//   workgroup builds two queues in LDS (guiding-center first, Boris from the
+//   back), so that each wavefront of the update pass runs a single branch of
+//   the coupled step.
 //
 // Included by exactly one translation unit per form (the binary64 one is
 // compiled with -ffp-contract=off).
@@ -25,8 +27,14 @@
 #include "gcb_internal.h"
 #include "gcb_math.hpp"
 
+// The kernels are compiled once per form and contraction setting; the
+// namespace of their instances is set by the including unit.
+#ifndef GCB_KERN_NS
+#define GCB_KERN_NS kern
+#endif
+
 namespace gcb {
-namespace kern {
+namespace GCB_KERN_NS {
 
 constexpr int kWG = 256;
 
@@ -199,12 +207,50 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
     if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
+// LDS layout of the tiled kernel: the field window (six W x W component
+// planes of T), then the state of one chunk of up to kWG particles in
+// structure-of-arrays form, then the queue of slots.
+template <typename R>
+struct ChunkLds {
+    double *x, *y, *xp, *yp, *qm;
+    R *ux, *uy, *uz;
+    int32_t* src;     // source slot of the particle in `in`
+    uint8_t* flags;   // status bits raised during the launch
+    uint16_t* queue;
+};
+
+template <typename R>
+__device__ __forceinline__ ChunkLds<R> carve_chunk(unsigned char* base) {
+    ChunkLds<R> c;
+    c.x = reinterpret_cast<double*>(base);
+    c.y = c.x + kWG;
+    c.xp = c.y + kWG;
+    c.yp = c.xp + kWG;
+    c.qm = c.yp + kWG;
+    c.ux = reinterpret_cast<R*>(c.qm + kWG);
+    c.uy = c.ux + kWG;
+    c.uz = c.uy + kWG;
+    c.src = reinterpret_cast<int32_t*>(c.uz + kWG);
+    c.flags = reinterpret_cast<uint8_t*>(c.src + kWG);
+    c.queue = reinterpret_cast<uint16_t*>(c.flags + kWG);
+    return c;
+}
+
+// One workgroup per tile of cell-sorted particles, for all `steps` steps of
+// a launch (the steps between two cell sorts, so the particle-to-tile
+// assignment of the last sort holds for all of them).  The tile's field
+// window is staged in LDS once; its particles are taken in chunks of up to
+// kWG, each chunk's state is read into LDS once, advanced `steps` steps there
+// and written out once.  Every step builds the two queues afresh (the switch
+// is evaluated at that step's x^n) so that each wavefront of the update runs
+// a single branch.  Particles are independent, so chunk after chunk gives
+// the same result as step after step over the whole tile.
 template <typename R, typename T, bool kYee, int kMinWaves, int kVar>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict__ perm,
              const int32_t* __restrict__ tile_start, TileGeom g, int chunk,
-             const T* __restrict__ F, PushConst pc, uint8_t* trace, bool replay,
-             DevStats* stats) {
+             const T* __restrict__ F, PushConst pc, uint8_t* trace, int64_t n, int steps,
+             bool replay, DevStats* stats) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int wave_g[kWG / 64];
     __shared__ int wave_b[kWG / 64];
@@ -216,8 +262,8 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict
     if (tile >= ntiles) return;
     const int W = g.window;
     T* lds = reinterpret_cast<T*>(smem);
-    uint16_t* queue = reinterpret_cast<uint16_t*>(
-        smem + (((size_t)W * W * 6 * sizeof(T) + 15) & ~(size_t)15));
+    const ChunkLds<R> S =
+        carve_chunk<R>(smem + (((size_t)W * W * 6 * sizeof(T) + 15) & ~(size_t)15));
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -226,19 +272,44 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict
     const int oi = tx * g.tile - g.halo;
     const int oj = ty * g.tile - g.halo;
 
-    // stage the window: one row (W records of 6 values, read contiguously)
-    // per wave iteration, written to the six component planes
-    for (int rr = wave; rr < W; rr += kWG / 64) {
-        const int gj = wrap_index(oj + rr, pc.ny);
-        const T* grow = F + (size_t)gj * pc.nx * 6;
-        for (int e = lane; e < W * 6; e += 64) {
+    // stage the window: a row of W records (6 W values, contiguous in the
+    // node-interleaved array) per wave iteration, written to the six
+    // component planes; a lane's columns are the same in every row, so their
+    // offsets are formed once, and the loads of two rows are in flight
+    // together (6 W <= 64 kCols: the host keeps W <= 64)
+    {
+        constexpr int kCols = 6;
+        int goff[kCols], loff[kCols];
+#pragma unroll
+        for (int u = 0; u < kCols; ++u) {
+            const int e = lane + 64 * u;
             const int c = e / 6;
             const int k = e - c * 6;
-            const int gi = wrap_index(oi + c, pc.nx);
-            lds[(k * W + rr) * W + c] = grow[gi * 6 + k];
+            const bool ok = e < W * 6;
+            goff[u] = ok ? wrap_index(oi + c, pc.nx) * 6 + k : -1;
+            loff[u] = ok ? k * W * W + c : 0;
+        }
+        constexpr int kRowStep = 2 * (kWG / 64);
+        for (int rr = wave; rr < W; rr += kRowStep) {
+            const int r2 = rr + kWG / 64;
+            const bool two = r2 < W;
+            const T* row0 = F + (size_t)wrap_index(oj + rr, pc.ny) * pc.nx * 6;
+            const T* row1 = F + (size_t)wrap_index(oj + (two ? r2 : rr), pc.ny) * pc.nx * 6;
+            T v0[kCols], v1[kCols];
+#pragma unroll
+            for (int u = 0; u < kCols; ++u) {
+                v0[u] = goff[u] >= 0 ? row0[goff[u]] : (T)0;
+                v1[u] = goff[u] >= 0 ? row1[goff[u]] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < kCols; ++u) {
+                if (goff[u] >= 0) {
+                    lds[loff[u] + rr * W] = v0[u];
+                    if (two) lds[loff[u] + r2 * W] = v1[u];
+                }
+            }
         }
     }
-    __syncthreads();
 
     const Consts<R> K = make_consts<R>(pc);
     TileAcc<T> acc{lds, F, pc.nx, pc.ny, oi, oj, W, false};
@@ -246,44 +317,95 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict
     const int64_t p1 = tile_start[tile + 1];
     unsigned cnt_g = 0, cnt_b = 0, cnt_h = 0;
     double maxres = 0.0;
+    const int t = threadIdx.x;
 
-    for (int64_t base = p0; base < p1; base += kQueueMax) {
-        const int m = (int)((p1 - base) < kQueueMax ? (p1 - base) : kQueueMax);
-        // pass 1: switch decision, stable split into the two queues
-        const int nG = split_queues(m, queue, wave_g, wave_b, [&](int t) {
+    for (int64_t base = p0; base < p1; base += kWG) {
+        const int m = (int)((p1 - base) < kWG ? (p1 - base) : kWG);
+        // the chunk's state into LDS (slot t of the chunk from slot perm[p]
+        // of the input)
+        if (t < m) {
             const int64_t p = base + t;
             const int64_t src = perm ? (int64_t)perm[p] : p;
-            if (replay) return trace[in.id ? (int64_t)in.id[src] : p] == 0;
-            const double x = in.x[src], y = in.y[src];
-            const double qm = in.qm ? in.qm[src] : pc.qm;
-            Sample<R> s;
-            gather<R, false, kYee>(acc, pc, K, x, y, s);
-            return switch_gca(s.E, s.B, in.ux[src], in.uy[src], in.uz[src], qm, pc, K);
-        });
-        // pass 2: guiding-center queue, then Boris queue
-        for (int q = threadIdx.x; q < m; q += kWG) {
-            const int64_t p = base + queue[q];
-            const int64_t src = perm ? (int64_t)perm[p] : p;
-            const bool gca = q < nG;
-            Regs<R> r;
-            load_particle(in, src, pc.qm, r);
-            acc.miss = false;
-            double res;
-            uint32_t fl = coupled_update<R, kYee, kVar>(acc, gca, r, pc, K, res);
-            if (acc.miss) {
-                fl |= ST_HALO;
-                ++cnt_h;
+            S.x[t] = in.x[src];
+            S.y[t] = in.y[src];
+            S.xp[t] = in.xp[src];
+            S.yp[t] = in.yp[src];
+            S.ux[t] = in.ux[src];
+            S.uy[t] = in.uy[src];
+            S.uz[t] = in.uz[src];
+            S.qm[t] = in.qm ? in.qm[src] : pc.qm;
+            S.src[t] = (int32_t)src;
+            S.flags[t] = 0;
+        }
+        __syncthreads();   // also orders the window staging before its first use
+
+        for (int s = 0; s < steps; ++s) {
+            uint8_t* tr = trace ? trace + (int64_t)s * n : nullptr;
+            // pass 1: switch decision, stable split into the two queues
+            const int nG = split_queues(m, S.queue, wave_g, wave_b, [&](int q) {
+                if (replay) return tr[in.id ? (int64_t)in.id[S.src[q]] : base + q] == 0;
+                Sample<R> smp;
+                gather<R, false, kYee>(acc, pc, K, S.x[q], S.y[q], smp);
+                return switch_gca(smp.E, smp.B, S.ux[q], S.uy[q], S.uz[q], S.qm[q], pc, K);
+            });
+            // pass 2: guiding-center queue, then Boris queue (m <= kWG: one
+            // slot per lane)
+            if (t < m) {
+                const int q = S.queue[t];
+                const bool gca = t < nG;
+                Regs<R> r;
+                r.x = S.x[q];
+                r.y = S.y[q];
+                r.xp = S.xp[q];
+                r.yp = S.yp[q];
+                r.ux = S.ux[q];
+                r.uy = S.uy[q];
+                r.uz = S.uz[q];
+                r.qm = S.qm[q];
+                acc.miss = false;
+                double res;
+                uint32_t fl = coupled_update<R, kYee, kVar>(acc, gca, r, pc, K, res);
+                if (acc.miss) {
+                    fl |= ST_HALO;
+                    ++cnt_h;
+                }
+                S.x[q] = r.x;
+                S.y[q] = r.y;
+                S.xp[q] = r.xp;
+                S.yp[q] = r.yp;
+                S.ux[q] = r.ux;
+                S.uy[q] = r.uy;
+                S.uz[q] = r.uz;
+                S.flags[q] |= (uint8_t)fl;
+                if (tr && !replay) tr[in.id ? (int64_t)in.id[S.src[q]] : base + q] = gca ? 0 : 1;
+                if (gca) {
+                    ++cnt_g;
+                    maxres = nan_max(maxres, res);
+                } else {
+                    ++cnt_b;
+                }
             }
-            store_particle(in, out, p, src, r, fl);
-            if (trace && !replay) trace[in.id ? (int64_t)in.id[src] : p] = gca ? 0 : 1;
-            if (gca) {
-                ++cnt_g;
-                maxres = nan_max(maxres, res);
-            } else {
-                ++cnt_b;
+            __syncthreads();
+        }
+
+        // the chunk's state out (slot base + t of the output)
+        if (t < m) {
+            const int64_t p = base + t;
+            const int64_t src = S.src[t];
+            out.x[p] = S.x[t];
+            out.y[p] = S.y[t];
+            out.xp[p] = S.xp[t];
+            out.yp[p] = S.yp[t];
+            out.ux[p] = S.ux[t];
+            out.uy[p] = S.uy[t];
+            out.uz[p] = S.uz[t];
+            out.status[p] = (uint8_t)(in.status[src] | S.flags[t]);
+            if (out.x != in.x) {   // out-of-place launch after a sort: carry the rest
+                if (in.qm) out.qm[p] = S.qm[t];
+                if (in.id) out.id[p] = in.id[src];
             }
         }
-        __syncthreads();
+        __syncthreads();   // before the next chunk overwrites the LDS state
     }
     if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
 }
@@ -308,20 +430,21 @@ hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
     }
     const int ntiles = L.geom.ntx * L.geom.nty;
     const int chunk = (ntiles + 7) / 8;
+    const int ns = L.steps > 0 ? L.steps : 1;
     const size_t lds = tiled_lds_bytes(L.geom.window, sizeof(T));
     if (L.yee) {
         auto kfn = k_push_tiled<R, T, true, kMinWaves, kVar>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
-                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay,
+                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.n, ns, L.replay,
                            L.stats);
     } else {
         auto kfn = k_push_tiled<R, T, false, kMinWaves, kVar>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
-                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay,
+                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.n, ns, L.replay,
                            L.stats);
     }
     return hipGetLastError();
@@ -342,5 +465,5 @@ hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
     return launch_push_frame<R, T, kMinWaves, kVarReduced>(L, in, out, pc, stream);
 }
 
-}  // namespace kern
+}  // namespace GCB_KERN_NS
 }  // namespace gcb
