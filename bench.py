@@ -101,6 +101,32 @@ def measured_traffic(workload: str, n: int, sort_every: int, tile: int):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
+def counter_limiter(workload: str, n: int, sort_every: int, tile: int):
+    """What the committed counter record of the binary64 push says limits it
+    (VALU busy share, waves per SIMD, traffic over algorithmic bytes), or
+    None when the record is for another launch or the kernel changed."""
+    rec = counter_record()
+    if not rec or "limiter" not in rec:
+        return None
+    if (rec.get("sources_sha256") != kernel_sources_sha256() or rec.get("workload") != workload
+            or rec.get("n") != n or rec.get("sort_every") != sort_every
+            or rec.get("tile") != tile):
+        return None
+    return rec["limiter"]
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(cfg, F, ens, budget_s: float = 20.0):
     """The CPU oracle (torch float64) on a bounded sample of the same workload:
     a random subset of the particles, pushed for up to the workload's step
@@ -138,6 +164,7 @@ def cpu_baseline(cfg, F, ens, budget_s: float = 20.0):
     finally:
         torch.set_num_threads(threads)
     return {"value": v, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count(),
             "sample": f"{n} random particles of the workload x {steps} steps "
                       f"({el:.1f} s, torch CPU float64, {threads} threads)",
             "single_thread": {"value": v1, "sample": f"{n1} particles x {steps1} steps "
@@ -172,11 +199,17 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--kernel", type=int, default=0)
     ap.add_argument("--sort-every", type=int, default=4)
-    ap.add_argument("--tile", type=int, default=24)
+    ap.add_argument("--tile", type=int, default=20)
+    ap.add_argument("--arith", choices=("fast", "exact"), default="fast",
+                    help="binary64 arithmetic of the headline push: contracted "
+                         "multiply-adds (fast, the production build) or the parity build")
     ap.add_argument("--mixed-tile", type=int, default=32)
     ap.add_argument("--f-rho", type=float, default=None)
     ap.add_argument("--f-E", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the Boris-only (f_rho = 0) and guiding-center-only "
+                         "(f_rho = f_E = inf) runs of the headline push")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=100)
@@ -234,12 +267,13 @@ def main():
             gcb.gcb_load_fields(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
             t = state.to_device(ens, dev, form=form, per_particle_qm=False)
             parts = gcb.particles(t)
-            kw = dict(curvature=cfg.curvature)
+            kw = dict(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                      n_iter=cfg.n_iter, form=form, sort_every=a.sort_every, kernel=a.kernel,
+                      curvature=cfg.curvature, tile=a.tile)
+            if form == gcb.GCB_FORM_F64:
+                kw["arith"] = ARITH
             kw.update(extra)
-            kw.setdefault("tile", a.tile)
-            prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
-                             n_iter=cfg.n_iter, form=form, sort_every=a.sort_every,
-                             kernel=a.kernel, **kw)
+            prm = gcb.params(**kw)
             log(f"[bench] form {form} {extra}: warmup {warmup} steps")
             st = gcb.gcb_push(ctx, parts, prm, warmup, want_stats=True)
             log(f"[bench] warmup stats {st}")
@@ -256,8 +290,9 @@ def main():
             st = gcb.gcb_push(ctx, parts, prm, 1, want_stats=True)
             torch.cuda.synchronize()
             del t
-            return {"wall": t1 - t0,
-                    "push_ms": ms[gcb.GCB_TIMER_PUSH] / max(1, cnt[gcb.GCB_TIMER_PUSH]),
+            # push time per step (a tiled launch runs the steps between two sorts)
+            return {"wall": t1 - t0, "launches": cnt[gcb.GCB_TIMER_PUSH],
+                    "push_ms": ms[gcb.GCB_TIMER_PUSH] / steps,
                     "sort_ms": ms[gcb.GCB_TIMER_SORT] / max(1, cnt[gcb.GCB_TIMER_SORT]),
                     "gca_frac": st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])}
         finally:
@@ -478,6 +513,7 @@ def main():
             gcb.gcb_destroy(ctx)
             torch.cuda.empty_cache()
 
+    ARITH = gcb.GCB_ARITH_FAST if a.arith == "fast" else gcb.GCB_ARITH_EXACT
     r64 = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup)
     wall, push_ms, sort_ms, gca_frac = r64["wall"], r64["push_ms"], r64["sort_ms"], r64["gca_frac"]
     bytes_step = push_bytes_per_step(n, cfg.nx, cfg.ny, 0)
@@ -487,7 +523,47 @@ def main():
     alu_tf = flops * n / (push_ms * 1e-3) / 1e12
     traffic = measured_traffic(cfg.name, n, a.sort_every, a.tile)
 
+    def roof(flops_pp: float, kms: float, nbytes: float) -> dict:
+        """Both roofs of a push launch: algorithmic flops and bytes per launch
+        over its HIP-event duration, and which roof the arithmetic intensity
+        puts it under (the ridge of the binary64 vector peak and the HBM
+        peak: 78.6 TFLOP/s / 8 TB/s = 9.8 flop/B)."""
+        tf = flops_pp * n / (kms * 1e-3) / 1e12
+        gbs = nbytes / (kms * 1e-3) / 1e9
+        ai = flops_pp * n / nbytes
+        ridge = FP64_VECTOR_PEAK_TF * 1e12 / (HBM_PEAK_GBS * 1e9)
+        return {"kernel_ms": kms, "algorithmic_flops_per_particle_step": flops_pp,
+                "algorithmic_bytes_per_launch": nbytes,
+                "arithmetic_intensity_flop_per_byte": ai,
+                "bound_by_intensity": "hbm" if ai < ridge else "alu",
+                "alu_achieved_TFLOPs": tf, "alu_frac": tf / FP64_VECTOR_PEAK_TF,
+                "hbm_achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+
+    hroof = roof(flops, push_ms, bytes_step)
+    hbm_bound = hroof["bound_by_intensity"] == "hbm"
     forms = {}
+    if a.arith == "fast":
+        # the same push in the parity build (no contraction), for comparison
+        rx = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup,
+                       arith=gcb.GCB_ARITH_EXACT)
+        forms["f64_exact_arith"] = {
+            "workload": f"{cfg.name}, binary64 without contraction (bit for bit with the "
+                        f"oracle)", "value": n * a.steps / rx["wall"],
+            "unit": "particle-steps/s", "kernel_ms": rx["push_ms"],
+            "headline_over_this": value / (n * a.steps / rx["wall"])}
+    if not a.no_legs:
+        # the two branches of the coupled step on their own (the same
+        # particles and kernel): every particle Boris, every particle guiding
+        # center
+        for leg, kw in (("boris_only", dict(f_rho=0.0)),
+                        ("gca_only", dict(f_rho=math.inf, f_E=math.inf))):
+            r = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup, **kw)
+            fl = FLOPS_GCA * r["gca_frac"] + FLOPS_BORIS * (1.0 - r["gca_frac"])
+            forms[leg] = {"workload": f"{cfg.name}, binary64, " + ", ".join(
+                              f"{k}={v}" for k, v in kw.items()),
+                          "value": n * a.steps / r["wall"], "unit": "particle-steps/s",
+                          "gca_fraction": r["gca_frac"],
+                          **roof(fl, r["push_ms"], bytes_step)}
     if not a.no_mixed:
         # the binary32 window is half the size: the mixed form's best tile is larger
         rm = time_form(gcb.GCB_FORM_MIXED, gcb.GCB_F32, a.steps, a.warmup, tile=a.mixed_tile)
@@ -579,26 +655,39 @@ def main():
         "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny} periodic double Harris sheet "
                                f"(guide 0.1 B0, tearing, inflow E, reconnection Ez at X points),"
                                f" {n} electrons MJ theta=1 + Gamma^-2 power law to 1e4, "
-                               f"binary64 plain path, curvature on, K={cfg.n_iter}",
+                               f"binary64 plain path ({a.arith} arithmetic), curvature on, K={cfg.n_iter}",
                    "particles": n, "grid": [cfg.nx, cfg.ny], "form": "f64",
+                   "arith": a.arith,
                    "kernel": ["auto", "global", "tiled"][a.kernel],
                    "sort_every": a.sort_every, "tile": a.tile,
                    "gca_fraction": round(gca_frac, 4)},
-        # the push issues far more binary64 vector instructions per byte than the
-        # HBM can feed: it is bound by the vector ALU, so that is the roofline;
-        # the HBM figures of the same launch sit beside it
-        "roofline": {"bound": "alu", "achieved": alu_tf, "peak": FP64_VECTOR_PEAK_TF,
-                     "unit": "TFLOP/s", "frac": alu_tf / FP64_VECTOR_PEAK_TF,
+        # The roof is the one the push's arithmetic intensity (algorithmic flops
+        # per algorithmic byte) puts it under: below the ridge point of the
+        # binary64 vector peak and the HBM peak it is HBM.  Both fractions are
+        # given; the forward target is 60 % of the HBM peak.
+        "roofline": {"bound": "hbm" if hbm_bound else "alu",
+                     "achieved": achieved if hbm_bound else alu_tf,
+                     "peak": HBM_PEAK_GBS if hbm_bound else FP64_VECTOR_PEAK_TF,
+                     "unit": "GB/s" if hbm_bound else "TFLOP/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if hbm_bound
+                             else (alu_tf / FP64_VECTOR_PEAK_TF),
                      "traffic": traffic,
                      "kernel": "k_push_tiled" if a.kernel != 1 else "k_push_global",
                      "kernel_ms": push_ms,
                      "algorithmic_flops_per_particle_step": flops,
                      "algorithmic_flops_per_launch": flops * n,
+                     "arithmetic_intensity_flop_per_byte": hroof[
+                         "arithmetic_intensity_flop_per_byte"],
+                     "alu_achieved_TFLOPs": alu_tf, "alu_peak_TFLOPs": FP64_VECTOR_PEAK_TF,
+                     "alu_frac": alu_tf / FP64_VECTOR_PEAK_TF,
                      "hbm_achieved_GBs": achieved, "hbm_peak_GBs": HBM_PEAK_GBS,
                      "hbm_copy_measured_GBs": copy_gbs,
                      "hbm_frac": achieved / HBM_PEAK_GBS,
+                     "hbm_target_frac": 0.6,
+                     "hbm_frac_of_target": achieved / HBM_PEAK_GBS / 0.6,
                      "algorithmic_bytes_per_launch": bytes_step,
-                     "traffic_over_algorithmic": (traffic / bytes_step) if traffic else None},
+                     "traffic_over_algorithmic": (traffic / bytes_step) if traffic else None,
+                     "limiter": counter_limiter(cfg.name, n, a.sort_every, a.tile)},
         "sort_ms_per_sort": sort_ms,
         "forms": forms,
     }

@@ -58,6 +58,19 @@ extern "C" {
                               selected quantities; state u is float; needs
                               fields loaded with dtype GCB_F32 */
 
+/* binary64 arithmetic (gcb_params.arith) */
+#define GCB_ARITH_EXACT 0   /* every operation of the step separately rounded, in the
+                               order of the CPU definition the library is tested
+                               against (no fused multiply-add): results agree with it
+                               bit for bit (the parity build of the kernels) */
+#define GCB_ARITH_FAST  1   /* the same operations with multiply-adds fused where the
+                               compiler forms them (the production build): each fused
+                               operation rounds once instead of twice, so a step
+                               differs from GCB_ARITH_EXACT by a few units in the last
+                               place (relative 1e-12 asserted per step, switch decisions
+                               identical); over many steps the difference grows as the
+                               orbit's own sensitivity to its initial state does */
+
 /* guiding-center frame (gcb_params.frame) */
 #define GCB_FRAME_REDUCED 0   /* the paper's schemes: b = B/B, v_E = c E x B/B^2, E_par = E.b */
 #define GCB_FRAME_EXACT   1   /* the exact frame of Sec. 2.2: b*, the exact v_E and kappa,
@@ -189,6 +202,10 @@ typedef struct {
                             >= 0 (else GCB_EINVAL); gcb_push, gcb_push_3d and gcb_push_gr
                             (there with c = 1 and the metric's norm of u_perp_g); the
                             adjoints return GCB_EUNSUPPORTED for a value other than 0 */
+    int32_t arith;       /* GCB_ARITH_EXACT (0, default) or GCB_ARITH_FAST: how the
+                            binary64 form evaluates the step (see below).
+                            GCB_ARITH_FAST: gcb_push and gcb_push_noalloc with
+                            GCB_FORM_F64 only (else GCB_EUNSUPPORTED) */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.

@@ -3,8 +3,10 @@
 Each translation unit is compiled separately (in parallel) and linked into
 paper_2007_14401_amd/libgcb.so.  The binary64 push and adjoint units are
 compiled with -ffp-contract=off so that their arithmetic is evaluated exactly
-as written (no fused multiply-add); the mixed-precision units may contract and
-use the hardware's binary32 reciprocal and square root.
+as written (no fused multiply-add: the parity build, GCB_ARITH_EXACT); the
+contracted binary64 push (GCB_ARITH_FAST, the production build) is the same
+source compiled with -ffp-contract=fast; the mixed-precision units may
+contract and use the hardware's binary32 reciprocal and square root.
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ FAST_F32 = ["-fno-hip-fp32-correctly-rounded-divide-sqrt"]
 UNITS = {
     "gcb_host.hip": ["-ffp-contract=off"],
     "gcb_push_f64.hip": ["-ffp-contract=off"],
+    "gcb_push_f64_fast.hip": ["-ffp-contract=fast"],
     "gcb_adjoint.hip": ["-ffp-contract=off"],
     "gcb_adjoint3.hip": ["-ffp-contract=off"],
     "gcb_push_mixed.hip": FAST_F32,

@@ -31,6 +31,7 @@ GCB_HOST, GCB_DEVICE = 0, 1
 GCB_KERNEL_AUTO, GCB_KERNEL_GLOBAL, GCB_KERNEL_TILED = 0, 1, 2
 GCB_FRAME_REDUCED, GCB_FRAME_EXACT = 0, 1
 GCB_GYRATION_MU, GCB_GYRATION_UPERP, GCB_GYRATION_ZERO = 0, 1, 2
+GCB_ARITH_EXACT, GCB_ARITH_FAST = 0, 1
 GCB_ST_NONFINITE, GCB_ST_KAPPA, GCB_ST_QUAD, GCB_ST_BZERO, GCB_ST_FPRES, GCB_ST_HALO = 1, 2, 4, 8, 16, 32
 GCB_ST_OUT = 64
 GCB_ST_MIRROR = 128
@@ -60,7 +61,7 @@ class gcb_params(C.Structure):
                 ("curvature", C.c_int32), ("n_iter", C.c_int32), ("form", C.c_int32),
                 ("sort_every", C.c_int32), ("kernel", C.c_int32), ("tile", C.c_int32),
                 ("replay", C.c_int32), ("frame", C.c_int32), ("gyration", C.c_int32),
-                ("mirror", C.c_int32), ("mirror_tol", C.c_double)]
+                ("mirror", C.c_int32), ("mirror_tol", C.c_double), ("arith", C.c_int32)]
 
 
 class gcb_particles(C.Structure):
@@ -233,13 +234,15 @@ def gcb_load_fields(ctx, desc: gcb_grid_desc, E, B, src=None, stream=None) -> No
 def params(dt=1.0, c=0.45, qm=-1.0, f_rho=0.4, f_E=1.0, fp_tol=1e-7, curvature=1,
            n_iter=4, form=GCB_FORM_F64, sort_every=0, kernel=GCB_KERNEL_AUTO,
            tile=0, replay=0, frame=GCB_FRAME_REDUCED,
-           gyration=GCB_GYRATION_MU, mirror=0, mirror_tol=0.0) -> gcb_params:
+           gyration=GCB_GYRATION_MU, mirror=0, mirror_tol=0.0,
+           arith=GCB_ARITH_EXACT) -> gcb_params:
     p = gcb_params()
     p.dt, p.c, p.qm, p.f_rho, p.f_E, p.fp_tol = dt, c, qm, f_rho, f_E, fp_tol
     p.curvature, p.n_iter, p.form = int(curvature), int(n_iter), int(form)
     p.sort_every, p.kernel, p.tile = int(sort_every), int(kernel), int(tile)
     p.replay, p.frame, p.gyration = int(replay), int(frame), int(gyration)
     p.mirror, p.mirror_tol = int(mirror), float(mirror_tol)
+    p.arith = int(arith)
     return p
 
 

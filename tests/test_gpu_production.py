@@ -1,0 +1,213 @@
+"""The production arithmetic of the binary64 push (GCB_ARITH_FAST: the same
+kernels compiled with contracted multiply-adds) against the oracle (needs an
+MI355X), by the chaos-aware protocol:
+
+  * one step from identical states: 1e-12 relative (floors: one cell for
+    positions, c for u) and identical switch decisions for every particle;
+  * many steps: a contracted step differs from the exact one by a few units
+    in the last place at every step (each fused multiply-add rounds once
+    instead of twice), and an orbit amplifies such differences by its own
+    sensitivity.  That sensitivity is measured on the oracle itself: the
+    oracle run again with every particle's position and four-velocity moved
+    by up to four units in the last place after every step (a random whole
+    number in [-4, 4] per value, three independent runs).  Per particle the
+    GPU error must stay within max(1e-12, 10 x the largest oracle deviation);
+    particles whose oracle deviation exceeds 1e-12 are the sensitive ones
+    (reported), and every other particle must also keep every switch decision
+    of the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_util import GpuRun, log, oracle_params
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+FAST = 1
+
+
+def _state(ens, **kw):
+    from paper_2007_14401_amd import state
+    return state.to_device(ens, "cuda:0", **kw)
+
+
+def particle_errors(got, ref, cfg):
+    """Per-particle max relative error over x, y (minimum image), xp, yp, u."""
+    err = None
+    for k, floor in (("x", cfg.dx), ("y", cfg.dy), ("xp", cfg.dx), ("yp", cfg.dy),
+                     ("ux", cfg.c), ("uy", cfg.c), ("uz", cfg.c)):
+        a = np.asarray(got[k], dtype=np.float64)
+        b = getattr(ref, k).numpy() if hasattr(ref, k) else np.asarray(ref[k])
+        d = np.abs(a - b)
+        if k in ("x", "xp", "y", "yp"):
+            L = cfg.Lx if k in ("x", "xp") else cfg.Ly
+            d = np.minimum(d, np.abs(L - d))
+        with np.errstate(invalid="ignore"):
+            r = d / np.maximum(np.abs(b), floor)
+        r = np.where((a == b) | (np.isnan(a) & np.isnan(b)), 0.0, r)
+        r = np.where(np.isnan(r), np.inf, r)
+        err = r if err is None else np.maximum(err, r)
+    return err
+
+
+ULPS = 4
+
+
+def _nudge(t: torch.Tensor, rng) -> torch.Tensor:
+    """Every element moved by a random whole number of units in the last
+    place in [-ULPS, ULPS]."""
+    a = t.numpy().copy()
+    k = rng.integers(-ULPS, ULPS + 1, a.shape)
+    for j in range(ULPS):
+        a = np.where(k > j, np.nextafter(a, np.inf), a)
+        a = np.where(k < -j, np.nextafter(a, -np.inf), a)
+    return torch.as_tensor(a)
+
+
+def oracle_runs(cfg, F, ens, steps, seeds=(1, 2, 3)):
+    """The oracle from the given start, and the same with x, y and u nudged by
+    up to ULPS units in the last place after every step (one run per seed)."""
+    p = oracle_params(cfg)
+    prov = O.GridFields(F, cfg.dx, cfg.dy, cfg.stagger)
+    ref, tr, _ = O.push(prov, O.State.from_numpy(ens), p, steps, trace=True)
+    noisy = []
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        st = O.State.from_numpy(ens)
+        for _ in range(steps):
+            st, _, _ = O.step(prov, st, p)
+            for k in ("x", "y", "ux", "uy", "uz"):
+                setattr(st, k, _nudge(getattr(st, k), rng))
+        noisy.append(st)
+    return ref, tr, noisy
+
+
+def chaos_aware_check(got, tr_gpu, ref, tr_ref, noisy, cfg, what):
+    err = particle_errors(got, ref, cfg)
+    sens = np.max(np.stack([particle_errors({k: getattr(s, k).numpy() for k in
+                                             ("x", "y", "xp", "yp", "ux", "uy", "uz")},
+                                            ref, cfg) for s in noisy]), axis=0)
+    bound = np.maximum(TOL, 10.0 * sens)
+    sensitive = sens > TOL
+    bad = err > bound
+    log(f"{what}: {int(sensitive.sum())} of {err.size} particles sensitive beyond 1e-12 "
+        f"(oracle deviation median {np.median(sens):.1e}, max {sens.max():.1e}); GPU error "
+        f"median {np.median(err):.1e}, max {err.max():.1e}; over the bound: {int(bad.sum())}")
+    assert not bad.any(), (what, np.flatnonzero(bad)[:10], err[bad][:10], sens[bad][:10])
+    if tr_gpu is not None:
+        calm = ~sensitive
+        mism = np.count_nonzero(tr_gpu[:, calm] != tr_ref.numpy()[:, calm])
+        assert mism == 0, (what, "switch decisions of insensitive particles differ", mism)
+    return err, sens
+
+
+@pytest.fixture(scope="module")
+def h64():
+    cfg = make_config("harris64")
+    F = cfg.fields()
+    run = GpuRun(cfg, F)
+    yield cfg, F, run
+    run.close()
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(1, 0, 0), (2, 1, 16), (2, 4, 20)])
+def test_fast_one_step(h64, kernel, sort_every, tile):
+    from paper_2007_14401_amd import state
+    cfg, F, run = h64
+    ens = cfg.particles(n=4096 + 37)
+    t = _state(ens)
+    tr, st = run.push(t, 1, trace=True, stats=True, kernel=kernel, sort_every=sort_every,
+                      tile=tile, arith=FAST)
+    ref, rtr, _ = O.push(O.GridFields(F, cfg.dx, cfg.dy, cfg.stagger),
+                         O.State.from_numpy(ens), oracle_params(cfg), 1, trace=True)
+    got = state.unsort(t)
+    err = particle_errors(got, ref, cfg)
+    log(f"fast one step kernel={kernel}: rel err median {np.median(err):.2e}, p99 "
+        f"{np.quantile(err, 0.99):.2e}, max {err.max():.2e}; bit-identical "
+        f"{np.mean(err == 0):.3f}")
+    assert err.max() <= TOL
+    assert np.array_equal(tr.cpu().numpy(), rtr.numpy())
+    assert np.array_equal(got["status"] & ~np.uint8(32), ref.status.numpy())
+    assert st["gca_steps"] == int((rtr == 0).sum())
+    # the contraction is in effect: some results differ from the exact ones
+    t2 = _state(ens)
+    run.push(t2, 1, kernel=kernel, sort_every=sort_every, tile=tile)
+    assert not torch.equal(t2["ux"], t["ux"]) or not torch.equal(t2["x"], t["x"])
+
+
+def test_fast_multistep_chaos_aware(h64):
+    from paper_2007_14401_amd import state
+    cfg, F, run = h64
+    ens = cfg.particles(n=1500, seed_offset=3)
+    steps = 50
+    t = _state(ens)
+    tr, _ = run.push(t, steps, trace=True, kernel=2, sort_every=4, tile=20, arith=FAST)
+    ref, rtr, noisy = oracle_runs(cfg, F, ens, steps)
+    chaos_aware_check(state.unsort(t), tr.cpu().numpy(), ref, rtr, noisy, cfg,
+                      "harris64 50 steps")
+
+
+def test_fast_c1_full_run_chaos_aware():
+    """harris256: 1000 steps, Omega_c0 dt in [0.1, 1e3]; 1500 of the 1e4
+    particles checked (particles are independent)."""
+    from paper_2007_14401_amd import state
+    cfg = make_config("harris256")
+    F = cfg.fields()
+    ens = cfg.particles()
+    run = GpuRun(cfg, F)
+    try:
+        t = _state(ens)
+        tr, _ = run.push(t, cfg.steps, trace=True, kernel=2, sort_every=4, tile=32, arith=FAST)
+    finally:
+        run.close()
+    got = state.unsort(t)
+    rng = np.random.default_rng(17)
+    sample = np.sort(rng.choice(ens.n, 1500, replace=False))
+    log("c1 fast: oracle runs on the sample")
+    ref, rtr, noisy = oracle_runs(cfg, F, ens.subset(sample), cfg.steps)
+    sub = {k: (v[sample] if v is not None else None) for k, v in got.items()}
+    chaos_aware_check(sub, tr.cpu().numpy()[:, sample], ref, rtr, noisy, cfg,
+                      "harris256 1000 steps")
+
+
+def test_fast_c2_full_size_sampled():
+    """harris4096 at full size (1e7 particles, 100 steps) in the benchmark's
+    launch configuration; 2000 sampled particles checked."""
+    from paper_2007_14401_amd import state
+    cfg = make_config("harris4096")
+    F = cfg.fields()
+    ens = cfg.particles()
+    run = GpuRun(cfg, F)
+    try:
+        t = _state(ens)
+        run.push(t, cfg.steps, kernel=2, sort_every=4, tile=20, arith=FAST)
+        ids = t["id"].cpu().numpy()
+        rng = np.random.default_rng(78)
+        sample = np.sort(rng.choice(ens.n, 2000, replace=False))
+        pos = np.empty(ens.n, dtype=np.int64)
+        pos[ids] = np.arange(ens.n)
+        h = {k: (v.cpu().numpy()[pos[sample]] if v is not None else None) for k, v in t.items()}
+        del t
+    finally:
+        run.close()
+    log("c2 fast: oracle runs on the sample")
+    ref, _, noisy = oracle_runs(cfg, F, ens.subset(sample), cfg.steps)
+    chaos_aware_check(h, None, ref, None, noisy, cfg, "harris4096 100 steps sampled")
+
+
+def test_fast_refused_elsewhere(h64):
+    from paper_2007_14401_amd import gcb
+    cfg, F, run = h64
+    t = _state(cfg.particles(n=64))
+    with pytest.raises(gcb.GcbError) as e:
+        gcb.gcb_push(run.ctx, gcb.particles(t), gcb.params(arith=2), 1)
+    assert e.value.code == gcb.GCB_EINVAL
+    with pytest.raises(gcb.GcbError) as e:
+        gcb.gcb_push(run.ctx, gcb.particles(t), gcb.params(arith=FAST, form=gcb.GCB_FORM_MIXED), 1)
+    assert e.value.code in (gcb.GCB_EUNSUPPORTED, gcb.GCB_EINVAL)
