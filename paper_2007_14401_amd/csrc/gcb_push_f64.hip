@@ -12,10 +12,8 @@ namespace gcb {
 size_t tiled_lds_bytes(int window, size_t elem_bytes) {
     size_t f = (size_t)window * window * 6 * elem_bytes;
     f = (f + 15) & ~(size_t)15;
-    // chunk state: x, y, xp, yp, q/m (binary64), u (elem_bytes each), source
-    // slot, status bits; then the queue
-    const size_t chunk = (size_t)kTiledChunk * (5 * 8 + 3 * elem_bytes + 4 + 1);
-    return f + chunk + (size_t)kTiledChunk * sizeof(uint16_t);
+    // then the queue of a chunk
+    return f + (size_t)kTiledChunk * sizeof(uint16_t);
 }
 
 hipError_t launch_push_f64(const PushLaunch& L, const ParticlePtrs<double>& in,

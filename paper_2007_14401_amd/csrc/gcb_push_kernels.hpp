@@ -11,11 +11,10 @@
 // k_push_tiled: one workgroup per tile of cell-sorted particles for all the
 //   steps of a launch (those between two sorts).  The tile's field window
 //   (tile + halo, all six components) is staged once in LDS; the particles
-//   are taken in chunks of up to kWG whose state stays in LDS for all steps;
-//   per step every lane evaluates the switch for its particle and the
-//   workgroup builds two queues in LDS (guiding-center first, Boris from the
-//   back), so that each wavefront of the update pass runs a single branch of
-//   the coupled step.
+//   are split into two queues by the branch of their first step (so that a
+//   wavefront starts on one branch of the coupled step) and each lane keeps
+//   its particle in registers for all steps, re-evaluating the switch at
+//   every step.
 //
 // Included by exactly one translation unit per form (the binary64 one is
 // compiled with -ffp-contract=off).
@@ -207,44 +206,18 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
     if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
-// LDS layout of the tiled kernel: the field window (six W x W component
-// planes of T), then the state of one chunk of up to kWG particles in
-// structure-of-arrays form, then the queue of slots.
-template <typename R>
-struct ChunkLds {
-    double *x, *y, *xp, *yp, *qm;
-    R *ux, *uy, *uz;
-    int32_t* src;     // source slot of the particle in `in`
-    uint8_t* flags;   // status bits raised during the launch
-    uint16_t* queue;
-};
-
-template <typename R>
-__device__ __forceinline__ ChunkLds<R> carve_chunk(unsigned char* base) {
-    ChunkLds<R> c;
-    c.x = reinterpret_cast<double*>(base);
-    c.y = c.x + kWG;
-    c.xp = c.y + kWG;
-    c.yp = c.xp + kWG;
-    c.qm = c.yp + kWG;
-    c.ux = reinterpret_cast<R*>(c.qm + kWG);
-    c.uy = c.ux + kWG;
-    c.uz = c.uy + kWG;
-    c.src = reinterpret_cast<int32_t*>(c.uz + kWG);
-    c.flags = reinterpret_cast<uint8_t*>(c.src + kWG);
-    c.queue = reinterpret_cast<uint16_t*>(c.flags + kWG);
-    return c;
-}
-
 // One workgroup per tile of cell-sorted particles, for all `steps` steps of
 // a launch (the steps between two cell sorts, so the particle-to-tile
 // assignment of the last sort holds for all of them).  The tile's field
-// window is staged in LDS once; its particles are taken in chunks of up to
-// kWG, each chunk's state is read into LDS once, advanced `steps` steps there
-// and written out once.  Every step builds the two queues afresh (the switch
-// is evaluated at that step's x^n) so that each wavefront of the update runs
-// a single branch.  Particles are independent, so chunk after chunk gives
-// the same result as step after step over the whole tile.
+// window (six W x W component planes) is staged in LDS once.  Its particles
+// are taken in chunks of up to kWG: the switch is evaluated for each at the
+// launch's first step and the chunk is split into two queues (guiding center
+// first, Boris from the back), so that a wavefront starts with particles of
+// one branch; each lane then keeps its particle in registers for every step
+// of the launch, evaluating the switch itself at every step (Sec. 4.1) from
+// the gather at x^n that the update uses.  Particles seldom change branch
+// between two sorts, so the wavefronts mostly stay on one branch; one that
+// holds both takes both, with the same results.
 template <typename R, typename T, bool kYee, int kMinWaves, int kVar>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict__ perm,
@@ -262,8 +235,8 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict
     if (tile >= ntiles) return;
     const int W = g.window;
     T* lds = reinterpret_cast<T*>(smem);
-    const ChunkLds<R> S =
-        carve_chunk<R>(smem + (((size_t)W * W * 6 * sizeof(T) + 15) & ~(size_t)15));
+    uint16_t* queue = reinterpret_cast<uint16_t*>(
+        smem + (((size_t)W * W * 6 * sizeof(T) + 15) & ~(size_t)15));
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -310,6 +283,7 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict
             }
         }
     }
+    __syncthreads();
 
     const Consts<R> K = make_consts<R>(pc);
     TileAcc<T> acc{lds, F, pc.nx, pc.ny, oi, oj, W, false};
@@ -321,63 +295,55 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict
 
     for (int64_t base = p0; base < p1; base += kWG) {
         const int m = (int)((p1 - base) < kWG ? (p1 - base) : kWG);
-        // the chunk's state into LDS (slot t of the chunk from slot perm[p]
-        // of the input)
-        if (t < m) {
-            const int64_t p = base + t;
+        // the branch of the launch's first step per particle, split into
+        // the two queues
+        const int nG = split_queues(m, queue, wave_g, wave_b, [&](int q) {
+            const int64_t p = base + q;
             const int64_t src = perm ? (int64_t)perm[p] : p;
-            S.x[t] = in.x[src];
-            S.y[t] = in.y[src];
-            S.xp[t] = in.xp[src];
-            S.yp[t] = in.yp[src];
-            S.ux[t] = in.ux[src];
-            S.uy[t] = in.uy[src];
-            S.uz[t] = in.uz[src];
-            S.qm[t] = in.qm ? in.qm[src] : pc.qm;
-            S.src[t] = (int32_t)src;
-            S.flags[t] = 0;
-        }
-        __syncthreads();   // also orders the window staging before its first use
-
-        for (int s = 0; s < steps; ++s) {
-            uint8_t* tr = trace ? trace + (int64_t)s * n : nullptr;
-            // pass 1: switch decision, stable split into the two queues
-            const int nG = split_queues(m, S.queue, wave_g, wave_b, [&](int q) {
-                if (replay) return tr[in.id ? (int64_t)in.id[S.src[q]] : base + q] == 0;
+            if (replay) return trace[in.id ? (int64_t)in.id[src] : p] == 0;
+            Sample<R> smp;
+            gather<R, false, kYee>(acc, pc, K, in.x[src], in.y[src], smp);
+            const double qm = in.qm ? in.qm[src] : pc.qm;
+            return switch_gca(smp.E, smp.B, in.ux[src], in.uy[src], in.uz[src], qm, pc, K);
+        });
+        if (t < m) {
+            const int64_t p = base + queue[t];
+            const int64_t src = perm ? (int64_t)perm[p] : p;
+            const int64_t tid = in.id ? (int64_t)in.id[src] : p;   // trace column
+            Regs<R> r;
+            load_particle(in, src, pc.qm, r);
+            uint32_t fl = 0;
+            bool gca = t < nG;
+            for (int s = 0; s < steps; ++s) {
+                uint8_t* tr = trace ? trace + (int64_t)s * n : nullptr;
+                // the gather at x^n serves the switch and the update; the
+                // gradients are formed for the branch of the previous step
+                const bool prev = gca;
                 Sample<R> smp;
-                gather<R, false, kYee>(acc, pc, K, S.x[q], S.y[q], smp);
-                return switch_gca(smp.E, smp.B, S.ux[q], S.uy[q], S.uz[q], S.qm[q], pc, K);
-            });
-            // pass 2: guiding-center queue, then Boris queue (m <= kWG: one
-            // slot per lane)
-            if (t < m) {
-                const int q = S.queue[t];
-                const bool gca = t < nG;
-                Regs<R> r;
-                r.x = S.x[q];
-                r.y = S.y[q];
-                r.xp = S.xp[q];
-                r.yp = S.yp[q];
-                r.ux = S.ux[q];
-                r.uy = S.uy[q];
-                r.uz = S.uz[q];
-                r.qm = S.qm[q];
                 acc.miss = false;
-                double res;
-                uint32_t fl = coupled_update<R, kYee, kVar>(acc, gca, r, pc, K, res);
+                if (prev)
+                    gather<R, true, kYee>(acc, pc, K, r.x, r.y, smp);
+                else
+                    gather<R, false, kYee>(acc, pc, K, r.x, r.y, smp);
+                if (s > 0) {
+                    if (replay)
+                        gca = tr[tid] == 0;
+                    else
+                        gca = switch_gca(smp.E, smp.B, r.ux, r.uy, r.uz, r.qm, pc, K);
+                    if (gca && !prev) gather<R, true, kYee>(acc, pc, K, r.x, r.y, smp);
+                }
+                double res = 0.0;
+                if (gca)
+                    fl |= gca_step<R, kYee, kVar == kVarExact, kVar == kVarMirror>(acc, smp, r,
+                                                                                  pc, K, res);
+                else
+                    boris_step(smp, r, pc, K);
+                fl |= finite_flag(r);
                 if (acc.miss) {
                     fl |= ST_HALO;
                     ++cnt_h;
                 }
-                S.x[q] = r.x;
-                S.y[q] = r.y;
-                S.xp[q] = r.xp;
-                S.yp[q] = r.yp;
-                S.ux[q] = r.ux;
-                S.uy[q] = r.uy;
-                S.uz[q] = r.uz;
-                S.flags[q] |= (uint8_t)fl;
-                if (tr && !replay) tr[in.id ? (int64_t)in.id[S.src[q]] : base + q] = gca ? 0 : 1;
+                if (tr && !replay) tr[tid] = gca ? 0 : 1;
                 if (gca) {
                     ++cnt_g;
                     maxres = nan_max(maxres, res);
@@ -385,27 +351,9 @@ k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict
                     ++cnt_b;
                 }
             }
-            __syncthreads();
+            store_particle(in, out, p, src, r, fl);
         }
-
-        // the chunk's state out (slot base + t of the output)
-        if (t < m) {
-            const int64_t p = base + t;
-            const int64_t src = S.src[t];
-            out.x[p] = S.x[t];
-            out.y[p] = S.y[t];
-            out.xp[p] = S.xp[t];
-            out.yp[p] = S.yp[t];
-            out.ux[p] = S.ux[t];
-            out.uy[p] = S.uy[t];
-            out.uz[p] = S.uz[t];
-            out.status[p] = (uint8_t)(in.status[src] | S.flags[t]);
-            if (out.x != in.x) {   // out-of-place launch after a sort: carry the rest
-                if (in.qm) out.qm[p] = S.qm[t];
-                if (in.id) out.id[p] = in.id[src];
-            }
-        }
-        __syncthreads();   // before the next chunk overwrites the LDS state
+        __syncthreads();   // the queue is rebuilt for the next chunk
     }
     if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
 }
