@@ -56,6 +56,7 @@ struct PushConst {
     double f_rho, f_E, inv_dl, fp_tol;
     double inv_dx, inv_dy, Lx, Ly;
     double qm;               // used when the per-particle array is absent
+    double inv_Lx, inv_Ly;   // 1/Lx, 1/Ly (the production binary64 form)
     double stagger[6][2];
     int32_t nx, ny;
     int32_t curvature, n_iter;

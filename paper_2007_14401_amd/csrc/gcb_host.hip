@@ -382,6 +382,8 @@ PushConst make_const(const gcb_ctx* ctx, const gcb_params* prm) {
     pc.inv_dy = 1.0 / ctx->dy;
     pc.Lx = ctx->nx * ctx->dx;
     pc.Ly = ctx->ny * ctx->dy;
+    pc.inv_Lx = 1.0 / pc.Lx;
+    pc.inv_Ly = 1.0 / pc.Ly;
     std::memcpy(pc.stagger, ctx->stagger, sizeof(pc.stagger));
     pc.nx = ctx->nx;
     pc.ny = ctx->ny;

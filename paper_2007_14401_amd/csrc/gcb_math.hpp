@@ -36,6 +36,52 @@ inline namespace GCB_ARITH_NS {
 template <typename R>
 constexpr bool kMixed = std::is_same<R, float>::value;
 
+// The production form of the binary64 arithmetic (GCB_ARITH_FAST; its unit
+// defines GCB_FAST_ARITH): besides contracted multiply-adds, a square root
+// that only serves as a divisor becomes a reciprocal square root (B and 1/B
+// from 1/sqrt(B^2), kappa and 1/kappa from 1/sqrt(1 - v_E^2/c^2), 1/Gamma
+// from 1/sqrt(1 + u^2/c^2)) and divisions by per-launch constants become
+// multiplications.  Each such value differs from the correctly rounded one
+// by a few units in the last place.
+#ifndef GCB_FAST_ARITH
+#define GCB_FAST_ARITH 0
+#endif
+template <typename R>
+constexpr bool kFastD = (GCB_FAST_ARITH != 0) && std::is_same<R, double>::value;
+
+// 1/sqrt(x) for finite x > 0 in binary64: the hardware estimate refined by
+// two Newton-Raphson steps y <- y + y (1 - x y^2)/2 (each roughly doubles
+// the number of correct bits; the result is within a few units in the last
+// place).
+GCB_HD double rsqrt_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+#else
+    double y = 1.0 / sqrt(x);
+#endif
+    double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+    return y;
+}
+
+// A Lorentz factor and, in the production form, its reciprocal.
+template <typename R>
+struct Gam {
+    R g, inv;
+};
+
+// num / Gamma: a division, or in the production form a multiplication by
+// the reciprocal
+template <typename R>
+GCB_HD R over(R num, const Gam<R>& G) {
+    if constexpr (kFastD<R>)
+        return num * G.inv;
+    else
+        return num / G.g;
+}
+
 // Constants of a launch in the bulk type.
 template <typename R>
 struct Consts {
@@ -215,6 +261,7 @@ struct Local {
     R B, inv_B;
     R b[3], vE[3];
     R kappa, Epar;
+    R inv_kappa;   // production form only: sqrt(1 - v_E^2/c^2)
     R bgb[3], vgb[3];
     R A, C;
     R gB[3];   // grad|B| (the 2D step fills x, y)
@@ -227,9 +274,18 @@ GCB_HD uint32_t local_fields(const R E[3], const R Bv[3], const Consts<R>& K, Lo
     const R Ex = E[0], Ey = E[1], Ez = E[2];
     const R Bx = Bv[0], By = Bv[1], Bz = Bv[2];
     const R B2 = (Bx * Bx + By * By) + Bz * Bz;
-    const R B = sqrt(B2);
-    const bool bzero = (B == (R)0);
-    const R inv_B = bzero ? (R)0 : (R)1 / B;
+    R B, inv_B;
+    bool bzero;
+    if constexpr (kFastD<R>) {
+        // B^2 = 0 gives B = 1/B = 0, NaN stays NaN, as in the exact form
+        bzero = B2 == (R)0;
+        inv_B = B2 > (R)0 ? rsqrt_nr(B2) : (bzero ? (R)0 : B2);
+        B = B2 * inv_B;
+    } else {
+        B = sqrt(B2);
+        bzero = (B == (R)0);
+        inv_B = bzero ? (R)0 : (R)1 / B;
+    }
     if (bzero) flags |= ST_BZERO;
     L.B = B;
     L.inv_B = inv_B;
@@ -264,7 +320,13 @@ GCB_HD uint32_t local_fields(const R E[3], const R Bv[3], const Consts<R>& K, Lo
             om = (R)kKappaFloor;
             flags |= ST_KAPPA;
         }
-        L.kappa = (R)1 / sqrt(om);
+        if constexpr (kFastD<R>) {
+            const R k = rsqrt_nr(om);
+            L.kappa = k;
+            L.inv_kappa = om * k;
+        } else {
+            L.kappa = (R)1 / sqrt(om);
+        }
     }
     L.Epar = (Ex * bx + Ey * by) + Ez * bz;
     return flags;
@@ -348,6 +410,7 @@ GCB_HD uint32_t local_fields_exact(const R E[3], const R Bv[3], const Consts<R>&
     }
     const R kappa = (R)1 / sqrt(om);
     L.kappa = kappa;
+    if constexpr (kFastD<R>) L.inv_kappa = (R)1 / kappa;
     const R Bp2 = (R)0.5 * ((B2 - E2) + S * s);
     const R Bp = sqrt(Bp2 > (R)0 ? Bp2 : (R)0);
     const bool bpzero = (Bp == (R)0);
@@ -415,6 +478,19 @@ GCB_HD R gamma_gca(const Local<R>& L, R upar, const Gyr<R>& gy, const Consts<R>&
     return L.kappa * sqrt(arg);
 }
 
+// Gamma(R, u_par) (eq. lfacgca2) and, in the production form, 1/Gamma from
+// one reciprocal square root
+template <typename R>
+GCB_HD Gam<R> gamma_gca2(const Local<R>& L, R upar, const Gyr<R>& gy, const Consts<R>& K) {
+    if constexpr (kFastD<R>) {
+        const R arg = (R)1 + (upar * upar + uperp_sq(L, gy)) * K.inv_c2;
+        const R s = rsqrt_nr(arg);
+        return {L.kappa * (arg * s), s * L.inv_kappa};
+    } else {
+        return {gamma_gca(L, upar, gy, K), (R)0};
+    }
+}
+
 // Curvature drift (eq. curvdrift):
 // (m c kappa^2 / (q B)) b x [ (u_par^2/Gamma)(b.grad)b + u_par (v_E.grad)b ]
 template <typename R>
@@ -428,6 +504,25 @@ GCB_HD void v_curv(const Local<R>& L, R upar, R gam, R inv_qm,
     vc[0] = pre * (L.b[1] * w2 - L.b[2] * w1);
     vc[1] = pre * (L.b[2] * w0 - L.b[0] * w2);
     vc[2] = pre * (L.b[0] * w1 - L.b[1] * w0);
+}
+
+// The curvature drift with Gamma and its reciprocal: the same arithmetic, the
+// division by Gamma a multiplication in the production form.
+template <typename R>
+GCB_HD void v_curv_g(const Local<R>& L, R upar, const Gam<R>& G, R inv_qm,
+                     const Consts<R>& K, R vc[3]) {
+    if constexpr (kFastD<R>) {
+        const R pre = ((K.c * L.kappa) * L.kappa) * (L.inv_B * inv_qm);
+        const R a1 = (upar * upar) * G.inv;
+        const R w0 = a1 * L.bgb[0] + upar * L.vgb[0];
+        const R w1 = a1 * L.bgb[1] + upar * L.vgb[1];
+        const R w2 = a1 * L.bgb[2] + upar * L.vgb[2];
+        vc[0] = pre * (L.b[1] * w2 - L.b[2] * w1);
+        vc[1] = pre * (L.b[2] * w0 - L.b[0] * w2);
+        vc[2] = pre * (L.b[0] * w1 - L.b[1] * w0);
+    } else {
+        v_curv(L, upar, G.g, inv_qm, K, vc);
+    }
 }
 
 // Curvature drift with the grad-B drift in its bracket (the mirror option):
@@ -462,6 +557,19 @@ GCB_HD R gamma_full(R ux, R uy, R uz, const Consts<R>& K) {
         }
     }
     return sqrt(arg);
+}
+
+// the Lorentz factor of the full four-velocity and, in the production form,
+// its reciprocal
+template <typename R>
+GCB_HD Gam<R> gamma_full2(R ux, R uy, R uz, const Consts<R>& K) {
+    if constexpr (kFastD<R>) {
+        const R arg = (R)1 + ((ux * ux + uy * uy) + uz * uz) * K.inv_c2;
+        const R s = rsqrt_nr(arg);
+        return {arg * s, s};
+    } else {
+        return {gamma_full(ux, uy, uz, K), (R)0};
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -522,6 +630,28 @@ GCB_HD double min_image(double d, double L) {
     return d - L * floor(d / L + 0.5);
 }
 
+// the same with 1/L given: the division becomes a multiplication in the
+// production form
+template <typename R>
+GCB_HD double wrap_i(double x, double L, double inv_L) {
+    if constexpr (kFastD<R>) {
+        double w = x - L * floor(x * inv_L);
+        if (w < 0.0) w = w + L;
+        if (w >= L) w = w - L;
+        return w;
+    } else {
+        return wrap(x, L);
+    }
+}
+
+template <typename R>
+GCB_HD double min_image_i(double d, double L, double inv_L) {
+    if constexpr (kFastD<R>)
+        return d - L * floor(d * inv_L + 0.5);
+    else
+        return min_image(d, L);
+}
+
 // ---------------------------------------------------------------------------
 // Relativistic Boris push (Sec. 2.1), fields at x^n
 
@@ -552,14 +682,19 @@ template <typename R>
 GCB_HD void boris_step(const Sample<R>& s, Regs<R>& r, const PushConst& pc,
                                            const Consts<R>& K) {
     boris(s.E, s.B, r.ux, r.uy, r.uz, (R)r.qm, K);
-    const R gn = gamma_full(r.ux, r.uy, r.uz, K);
-    const R inv_g = (R)1 / gn;
+    R inv_g;
+    if constexpr (kFastD<R>) {
+        inv_g = gamma_full2(r.ux, r.uy, r.uz, K).inv;
+    } else {
+        const R gn = gamma_full(r.ux, r.uy, r.uz, K);
+        inv_g = (R)1 / gn;
+    }
     const double xn = r.x + pc.dt * (double)(r.ux * inv_g);
     const double yn = r.y + pc.dt * (double)(r.uy * inv_g);
     r.xp = r.x;
     r.yp = r.y;
-    r.x = wrap(xn, pc.Lx);
-    r.y = wrap(yn, pc.Ly);
+    r.x = wrap_i<R>(xn, pc.Lx, pc.inv_Lx);
+    r.y = wrap_i<R>(yn, pc.Ly, pc.inv_Ly);
 }
 
 // ---------------------------------------------------------------------------
@@ -579,12 +714,16 @@ GCB_HD R parallel_update(const Local<R>& Ln, R upar, const Gyr<R>& gy, R qm,
     if (!curvature) return upar + dtqm * Ln.Epar;
     const R h = K.h;
     const R A = Ln.A, C = Ln.C;
-    const R G0 = gamma_gca(Ln, upar, gy, K);
+    const R G0 = gamma_gca2(Ln, upar, gy, K).g;
     R upr = (upar * ((R)1 + h * A) + dtqm * Ln.Epar) + (h * G0) * C;
     if (shifted) upr = upr - shift;
     const R D = (R)1 - h * A;
     const R DD = D * D;
-    const R k1 = (h * h) * (C * C) - (K.c2 * DD) / (Ln.kappa * Ln.kappa);
+    R k1;
+    if constexpr (kFastD<R>)
+        k1 = (h * h) * (C * C) - (K.c2 * DD) * (Ln.inv_kappa * Ln.inv_kappa);
+    else
+        k1 = (h * h) * (C * C) - (K.c2 * DD) / (Ln.kappa * Ln.kappa);
     const R k2 = (upr * K.dt) * C;
     const R k3 = upr * upr + (K.c2 + uperp_sq(Ln, gy)) * DD;
     const R disc = k2 * k2 - ((R)4 * k1) * k3;
@@ -632,14 +771,14 @@ template <typename R>
 GCB_HD void drift_terms(const Local<R>& L, R upn, const Gyr<R>& gy, R inv_qm,
                                             bool curvature, const Consts<R>& K, R& Fx,
                                             R& Fy, bool mirror = false) {
-    const R g = gamma_gca(L, upn, gy, K);
-    const R a = upn / g;
+    const Gam<R> G = gamma_gca2(L, upn, gy, K);
+    const R a = over(upn, G);
     if (curvature) {
         R vc[3];
         if (mirror)
-            v_curv_mirror<2>(L, upn, g, inv_qm, gy.mu, K, vc);
+            v_curv_mirror<2>(L, upn, G.g, inv_qm, gy.mu, K, vc);
         else
-            v_curv(L, upn, g, inv_qm, K, vc);
+            v_curv_g(L, upn, G, inv_qm, K, vc);
         Fx = (a * L.b[0] + L.vE[0]) + vc[0];
         Fy = (a * L.b[1] + L.vE[1]) + vc[1];
     } else {
@@ -706,26 +845,37 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     R upar, bpx, bpy, bpz;
     Gyr<R> gy;
     {
-        const double Rhx = x - 0.5 * min_image(x - r.xp, pc.Lx);
-        const double Rhy = y - 0.5 * min_image(y - r.yp, pc.Ly);
+        const double Rhx = x - 0.5 * min_image_i<R>(x - r.xp, pc.Lx, pc.inv_Lx);
+        const double Rhy = y - 0.5 * min_image_i<R>(y - r.yp, pc.Ly, pc.inv_Ly);
         Sample<R> sh;
         gather<R, true, kYee>(acc, pc, K, Rhx, Rhy, sh);
         Local<R> Lh;
         flags |= local_in_frame<kExact>(sh, K, Lh);
         upar = (ux * Lh.b[0] + uy * Lh.b[1]) + uz * Lh.b[2];
-        const R gf = gamma_full(ux, uy, uz, K);
+        const Gam<R> G = gamma_full2(ux, uy, uz, K);
+        const R gf = G.g;
         R vc[3] = {(R)0, (R)0, (R)0};
-        if (curv) v_curv(Lh, upar, gf, inv_qm, K, vc);
+        if (curv) v_curv_g(Lh, upar, G, inv_qm, K, vc);
         const R upx = (ux - upar * Lh.b[0]) - (Lh.vE[0] + vc[0]) * gf;
         const R upy = (uy - upar * Lh.b[1]) - (Lh.vE[1] + vc[1]) * gf;
         const R upz = (uz - upar * Lh.b[2]) - (Lh.vE[2] + vc[2]) * gf;
         const R up2 = (upx * upx + upy * upy) + upz * upz;
         flags |= mirror_check(ux, uy, uz, Lh, vc, up2, gf, pc, K);
-        gy.mu = pc.gyration == GYR_ZERO ? (R)0 : (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        R mu;
+        if constexpr (kFastD<R>)
+            mu = (((R)0.5 * up2) * Lh.inv_B) * Lh.inv_kappa;
+        else
+            mu = (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        gy.mu = pc.gyration == GYR_ZERO ? (R)0 : mu;
         gy.up2 = up2;
         gy.fixed = pc.gyration == GYR_UPERP;
-        const R nu = sqrt(up2);
-        const R inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
+        R inv_nu;
+        if constexpr (kFastD<R>) {
+            inv_nu = up2 > (R)0 ? rsqrt_nr(up2) : (R)0;
+        } else {
+            const R nu = sqrt(up2);
+            inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
+        }
         bpx = upx * inv_nu;
         bpy = upy * inv_nu;
         bpz = upz * inv_nu;
@@ -776,9 +926,10 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
         gather<R, true, kYee>(acc, pc, K, Rmx, Rmy, sm);
         Local<R> Lm;
         flags |= local_in_frame<kExact>(sm, K, Lm);
-        const R gr = gamma_gca(Lm, upn, gy, K);
+        const Gam<R> G = gamma_gca2(Lm, upn, gy, K);
+        const R gr = G.g;
         R vc[3] = {(R)0, (R)0, (R)0};
-        if (curv) v_curv(Lm, upn, gr, inv_qm, K, vc);
+        if (curv) v_curv_g(Lm, upn, G, inv_qm, K, vc);
         const R um = sqrt(uperp_sq(Lm, gy));
         r.ux = (upn * Lm.b[0] + (Lm.vE[0] + vc[0]) * gr) + um * bpx;
         r.uy = (upn * Lm.b[1] + (Lm.vE[1] + vc[1]) * gr) + um * bpy;
@@ -788,8 +939,8 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     // 6. store
     r.xp = x;
     r.yp = y;
-    r.x = wrap(Rx, pc.Lx);
-    r.y = wrap(Ry, pc.Ly);
+    r.x = wrap_i<R>(Rx, pc.Lx, pc.inv_Lx);
+    r.y = wrap_i<R>(Ry, pc.Ly, pc.inv_Ly);
     return flags;
 }
 

@@ -220,13 +220,23 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
 // holds both takes both, with the same results.
 template <typename R, typename T, bool kYee, int kMinWaves, int kVar>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
-k_push_tiled(ParticlePtrs<R> in, ParticlePtrs<R> out, const uint32_t* __restrict__ perm,
+k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __restrict__ perm,
              const int32_t* __restrict__ tile_start, TileGeom g, int chunk,
              const T* __restrict__ F, PushConst pc, uint8_t* trace, int64_t n, int steps,
              bool replay, DevStats* stats) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int wave_g[kWG / 64];
     __shared__ int wave_b[kWG / 64];
+    // The state arrays are used only before and after the steps of a chunk:
+    // their twenty pointers are kept in LDS and read where they are used, so
+    // that they do not occupy scalar registers through the steps.
+    __shared__ ParticlePtrs<R> io[2];
+    if (threadIdx.x == 0) {
+        io[0] = in_arg;
+        io[1] = out_arg;
+    }
+    const ParticlePtrs<R>& in = io[0];
+    const ParticlePtrs<R>& out = io[1];
 
     const int ntiles = g.ntx * g.nty;
     // consecutive tiles on the same XCD: workgroups are dealt to the 8 XCDs
