@@ -4,13 +4,17 @@ positions and selected quantities) against the binary64 CPU oracle.
 Stated tolerance (one step, from the arithmetic): inputs are rounded to
 binary32 (relative 6e-8) and a guiding-center step chains about 30 dependent
 rounding stages plus the conditioning of kappa near E -> B, so per-step
-relative errors of u of order 1e-6 are expected; positions stay binary64 and
-move by at most about c dt per step, so their one-step error is below 1e-6
-cells.  Asserted: median relative u error <= 1e-5, 99th percentile <= 1e-3,
-max position error <= 1e-4 cells, switch mismatches <= 0.2 % of particles.
+relative errors of u of order 1e-7..1e-6 are expected; positions stay
+binary64 and move by at most about c dt per step.  Measured one step
+(harris64): u median 6e-8, 99th percentile 2.3e-7, no switch mismatch.
+Asserted at about ten times that: median <= 1e-6, 99th percentile <= 3e-6,
+position error <= 1e-6 cells, switch mismatches <= 1 in 8192.
 
-Over many steps chaotic orbits amplify these differences; the multi-step
-report (full-size workload) is measured and recorded, with loose bounds.
+Over many steps the orbits' own sensitivity amplifies these differences;
+the multi-step reports compare at least 1e5 particles sampled from the
+full-size runs (all 1e4 of the small workload) with the oracle, and their
+bounds are about ten times the measured medians, 99th percentiles and
+switch-mismatch rates (the measured figures are in the design notes).
 """
 import json
 
@@ -22,6 +26,15 @@ from gpu_util import GpuRun, log, run_oracle, save_report
 from workloads import make_config
 
 pytestmark = pytest.mark.gpu
+
+# multi-step report bounds, about ten times the measured values (u relative
+# error median and 99th percentile, position error median in cells, switch
+# mismatches per particle-step).  Measured, harris4096 100 steps, 1e5
+# particles sampled: 1e7 particles 2.3e-6 / 3.1e-5 / 1.1e-5 / 0 in 1e7,
+# 1e8 particles 2.3e-6 / 3.1e-5 / 1.1e-5 / 2e-7; harris256 1000 steps, all
+# 1e4 particles: 9.8e-6 / 5.3e-4 / 4.8e-4 / 1.4e-6.
+MED_FULL, P99_FULL, XMED_FULL, MISM_FULL = 3e-5, 3e-4, 1e-4, 2e-6
+MED_256, P99_256, XMED_256, MISM_256 = 1e-4, 5e-3, 5e-3, 1.5e-5
 
 
 
@@ -66,10 +79,10 @@ def test_mixed_one_step(kernel, sort_every, tile):
     log(f"mixed one step kernel={kernel}: u median {np.median(du):.2e} p99 "
         f"{np.quantile(du, 0.99):.2e} max {du.max():.2e}; x max {dx.max():.2e}; "
         f"S mismatch {mism:.2e}")
-    assert np.median(du) <= 1e-5
-    assert np.quantile(du, 0.99) <= 1e-3
-    assert dx.max() <= 1e-4
-    assert mism <= 2e-3
+    assert np.median(du) <= 1e-6
+    assert np.quantile(du, 0.99) <= 3e-6
+    assert dx.max() <= 1e-6
+    assert mism <= 1.0 / 8192
 
 
 def test_mixed_deterministic():
@@ -84,7 +97,7 @@ def test_mixed_deterministic():
         assert np.array_equal(outs[0][k].view(np.uint8), outs[1][k].view(np.uint8)), k
 
 
-def _report(n_total, steps, sample_n=2000, name="harris4096"):
+def _report(n_total, steps, sample_n=100_000, name="harris4096"):
     from paper_2007_14401_amd import state
     cfg = make_config(name)
     log(f"mixed report: generating {n_total} particles")
@@ -95,6 +108,7 @@ def _report(n_total, steps, sample_n=2000, name="harris4096"):
     t, tr, st = _run_mixed(cfg, F, ens, steps, True, kernel=2, sort_every=4, tile=32)
     ids = t["id"].cpu().numpy()
     rng = np.random.default_rng(123)
+    sample_n = min(sample_n, ens.n)
     sample = np.sort(rng.choice(ens.n, sample_n, replace=False))
     pos = np.empty(ens.n, dtype=np.int64)
     pos[ids] = np.arange(ens.n)
@@ -127,25 +141,27 @@ def _report(n_total, steps, sample_n=2000, name="harris4096"):
     return rep
 
 
+def _bounds(rep, med, p99, x_med, mism):
+    assert rep["u_rel_err"]["median"] <= med
+    assert rep["u_rel_err"]["p99"] <= p99
+    assert rep["x_abs_err_cells"]["median"] <= x_med
+    assert rep["switch_mismatch_fraction_particle_steps"] <= mism
+
+
 def test_mixed_precision_report_1e7():
-    """Full-size workload (4096^2, 1e7 particles, 100 steps), mixed form."""
-    rep = _report(10_000_000, 100)
-    assert rep["u_rel_err"]["median"] <= 1e-3
-    assert rep["switch_mismatch_fraction_particle_steps"] <= 1e-2
+    """Full-size workload (4096^2, 1e7 particles, 100 steps), mixed form,
+    1e5 particles sampled against the oracle."""
+    _bounds(_report(10_000_000, 100), MED_FULL, P99_FULL, XMED_FULL, MISM_FULL)
 
 
 def test_mixed_precision_report_harris256():
     """The small workload (256^2, 1e4 electrons, Maxwell-Juttner theta = 0.1,
-    Omega_c dt from 0.1 to 1e3) over its 1000 steps, mixed form, 2000
-    particles sampled against the oracle."""
-    rep = _report(10_000, 1000, name="harris256")
-    assert rep["u_rel_err"]["median"] <= 1e-3
-    assert rep["switch_mismatch_fraction_particle_steps"] <= 1e-2
+    Omega_c dt from 0.1 to 1e3) over its 1000 steps, mixed form, every
+    particle against the oracle."""
+    _bounds(_report(10_000, 1000, name="harris256"), MED_256, P99_256, XMED_256, MISM_256)
 
 
 def test_mixed_precision_report_1e8():
     """The same fields and steps with 1e8 particles (about 6 particles per
-    cell), mixed form, sampled against the oracle."""
-    rep = _report(100_000_000, 100)
-    assert rep["u_rel_err"]["median"] <= 1e-3
-    assert rep["switch_mismatch_fraction_particle_steps"] <= 1e-2
+    cell), mixed form, 1e5 particles sampled against the oracle."""
+    _bounds(_report(100_000_000, 100), MED_FULL, P99_FULL, XMED_FULL, MISM_FULL)
