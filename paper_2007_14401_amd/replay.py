@@ -102,13 +102,26 @@ def _min_image(d, L):
 MIRROR_TOL = 0.01   # (v_perp_g/c)^2: v_perp_g below 0.1 c
 
 
-def run(rho_over_de: float, steps: int = 1111, device: int = 0, log=print) -> dict:
+def setup(rho_over_de: float):
+    """Inputs at one magnetization: the fields, their lattice offsets, q/m of
+    the positrons and the reference's substeps per step."""
     F, stagger = _fields()
     rho0 = rho_over_de * D_E                      # cells
     omega0 = C / rho0                             # non-relativistic gyro-frequency, per step
     qm = omega0 * C / 1.0                         # positrons, B0 = 1
     bmax = float(np.sqrt((F[3] ** 2 + F[4] ** 2 + F[5] ** 2).max()))
     M = int(math.ceil(60.0 * (qm * bmax / C) * DT / (2.0 * math.pi)))
+    return F, stagger, qm, M
+
+
+def start(F, stagger, qm, dt):
+    """The 5 positrons of the test (see _start)."""
+    return _start(F, stagger, qm, dt)
+
+
+def run(rho_over_de: float, steps: int = 1111, device: int = 0, log=print) -> dict:
+    F, stagger, qm, M = setup(rho_over_de)
+    omega0 = qm / C
     dev = f"cuda:{device}"
     ctx = gcb.gcb_create(device)
     try:

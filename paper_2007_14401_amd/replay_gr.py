@@ -1,6 +1,23 @@
-"""Synthetic replay of the paper's curved-spacetime ambient-region test
-(Sec. 4.2) on the GPU path.
+"""Synthetic replays of the paper's curved-spacetime tests (Sec. 4.2) on the
+GPU path: the near-sheet test (`run_sheet`) and the ambient-region test
+(`run`).
 
+Near the current sheet (`run_sheet`).  The paper starts 5 electrons about
+r_g from the equatorial current sheet with u = Gamma v_E of the local fields
+and rho_C0/r_g = 1e-2, 1e-3, 1e-4 (Omega_C0/(c/r_g) = 1e2 ... 1e4), and
+integrates to t ~ 20 r_g/c with the same three integrators as below
+(f_rho = f_E = 1 for the coupled push).  In its snapshot the particles
+drift into the sheet and are accelerated there.  The stand-in is the
+split-monopole magnetosphere of `workloads.gr` without rotation and with a
+toroidal electric field (`inflow`, 0.1 by default) whose drift carries the
+particles toward the sheet at about 0.1 c and which exceeds B inside it.
+The electrons start at r = 3 ... 7 r_g, one r_g above the equatorial plane
+(cos(theta) = 1/r), phi = 0, with the covariant four-velocity of the local
+drift, u_i = Gamma v_E,i, v_E,i = sqrt(gamma) eps_ijk D^j B^k/B^2 and
+Gamma = (1 - v_E^2)^(-1/2) in the Kerr-Schild spatial metric; q/m is set per
+particle from the field magnitude at its start, q/m = -Omega_C0/|B|.
+
+The ambient region (`run`).
 The paper starts 4 electrons at rest in the ambient region of its black-hole
 magnetosphere (away from the twisted field lines near the hole), with
 initial gyro-radii rho_C0/r_g = 1e-1, 1e-2, 1e-3, 1e-4, i.e.
@@ -43,6 +60,8 @@ orbit, so the runs at the other thresholds only supply their flags.
 
     python -m paper_2007_14401_amd.replay_gr [--omega 1e1 1e2 1e3 1e4] [--t-end 20]
                                              [--rotation 0.1 1]
+    python -m paper_2007_14401_amd.replay_gr --test sheet [--rho 1e-2 1e-3 1e-4]
+                                             [--inflow 0.1]
 """
 from __future__ import annotations
 
@@ -57,6 +76,7 @@ import torch
 from . import gcb
 
 R0, TH0 = 5.5, math.pi / 3.0
+SHEET_R = (3.0, 4.0, 5.0, 6.0, 7.0)   # start radii of the near-sheet test
 MIRROR_TOLS = (0.01, 0.1, 0.3)   # (v_perp_g/c)^2: v_perp_g below 0.1, 0.32, 0.55 c
 DT = 2.0 * math.pi / 60.0
 
@@ -79,6 +99,151 @@ def _field_magnitude(F, cfg, r, th):
 
 def _cartesian(r, th, ph):
     return np.stack([r * np.sin(th) * np.cos(ph), r * np.sin(th) * np.sin(ph), r * np.cos(th)])
+
+
+def _ks_metric(a, r, th):
+    """Spatial metric of spherical Kerr-Schild coordinates (M = 1): gamma_ij,
+    gamma^ij (3 x 3 x n) and sqrt(gamma)."""
+    s, c = np.sin(th), np.cos(th)
+    rho2 = r * r + a * a * c * c
+    z = 2.0 * r / rho2
+    n = np.shape(r)
+    g = np.zeros((3, 3) + n)
+    g[0, 0] = 1.0 + z
+    g[0, 2] = g[2, 0] = -a * (1.0 + z) * s * s
+    g[1, 1] = rho2
+    g[2, 2] = s * s * (rho2 + a * a * (1.0 + z) * s * s)
+    gi = np.zeros((3, 3) + n)
+    gi[0, 0] = 1.0 / (1.0 + z) + a * a * s * s / rho2
+    gi[0, 2] = gi[2, 0] = a / rho2
+    gi[1, 1] = 1.0 / rho2
+    gi[2, 2] = 1.0 / (rho2 * s * s)
+    return g, gi, np.sqrt(1.0 + z) * rho2 * s
+
+
+def _sample(F, cfg, r, th):
+    """D^i and B^i at (r, theta), bilinear on the (r, theta) nodes."""
+    fr = (r - cfg.r_min) / (cfg.r_max - cfg.r_min) * cfg.nr
+    ft = th / math.pi * cfg.nth
+    i = np.floor(fr).astype(np.int64)
+    j = np.floor(ft).astype(np.int64)
+    wr, wt = fr - i, ft - j
+    v = [(1 - wt) * ((1 - wr) * F[k][j, i] + wr * F[k][j, i + 1])
+         + wt * ((1 - wr) * F[k][j + 1, i] + wr * F[k][j + 1, i + 1]) for k in range(6)]
+    return np.array(v[:3]), np.array(v[3:])
+
+
+def _drift_start(F, cfg, r, th):
+    """Covariant u_i = Gamma v_E,i of the local drift at (r, theta) and the
+    field magnitude |B| there (metric norm)."""
+    g, gi, sg = _ks_metric(cfg.a, r, th)
+    D, B = _sample(F, cfg, r, th)
+    B2 = np.einsum("ij...,i...,j...->...", g, B, B)
+    cr = np.array([D[1] * B[2] - D[2] * B[1], D[2] * B[0] - D[0] * B[2],
+                   D[0] * B[1] - D[1] * B[0]])
+    vE = sg * cr / B2
+    v2 = np.einsum("ij...,i...,j...->...", gi, vE, vE)
+    gam = 1.0 / np.sqrt(1.0 - v2)
+    return gam * vE, np.sqrt(B2)
+
+
+def _lorentz(cfg, r, th, u):
+    _, gi, _ = _ks_metric(cfg.a, r, th)
+    return np.sqrt(1.0 + np.einsum("ij...,i...,j...->...", gi, u, u))
+
+
+def sheet_setup(rho_over_rg: float, inflow: float = 0.1):
+    """Inputs of the near-sheet test at one magnetization: the workload, its
+    fields, the start (r, theta, u), per-particle q/m, the reference's
+    substeps per step and the number of steps to t = 20 r_g/c."""
+    from workloads.gr import make_gr_config
+    cfg = make_gr_config("grbh512", rotation=0.0, inflow=inflow)
+    F = cfg.fields()
+    r0 = np.array(SHEET_R)
+    th0 = np.arccos(1.0 / r0)
+    u0, Bmag = _drift_start(F, cfg, r0, th0)
+    qm = -(1.0 / rho_over_rg) / Bmag
+    r_nodes = cfg.r_min + (cfg.r_max - cfg.r_min) * np.arange(cfg.nr + 1) / cfg.nr
+    th_nodes = np.pi * np.arange(cfg.nth + 1) / cfg.nth
+    TH, R = np.meshgrid(th_nodes, r_nodes, indexing="ij")
+    bmax = float(np.sqrt(F[3] ** 2 + (R * F[4]) ** 2 + (R * np.sin(TH) * F[5]) ** 2).max())
+    M = int(math.ceil(60.0 * float(np.abs(qm).max()) * bmax * DT / (2.0 * math.pi)))
+    return cfg, F, r0, th0, u0, qm, M, int(round(20.0 / DT))
+
+
+def run_sheet(rhos=(1e-2, 1e-3, 1e-4), inflow: float = 0.1, device: int = 0,
+              log=print) -> list:
+    """The near-sheet test: per magnetization, the largest distance of the
+    large-step Boris and coupled runs from the gyro-resolved reference (while
+    the reference particle is inside the grid), the coupled run's fraction of
+    guiding-center steps, the step of its first switch per particle, and the
+    largest Lorentz factor each run reaches."""
+    dev = f"cuda:{device}"
+    reps = []
+    for rho in rhos:
+        cfg, F, r0, th0, u0, qm, M, steps = sheet_setup(rho, inflow)
+        n = r0.size
+        ctx = gcb.gcb_create(device)
+        try:
+            desc = gcb.gr_desc(cfg.nr, cfg.nth, cfg.r_min, cfg.r_max, cfg.a)
+            gcb.gcb_load_fields_gr(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
+
+            def traj(dt, n_sub, **kw):
+                z = torch.zeros(n, dtype=torch.float64, device=dev)
+                t = {"r": torch.as_tensor(r0, device=dev), "th": torch.as_tensor(th0, device=dev),
+                     "ph": z.clone(), "ur": torch.as_tensor(u0[0], device=dev),
+                     "uth": torch.as_tensor(u0[1], device=dev),
+                     "uph": torch.as_tensor(u0[2], device=dev),
+                     "qm": torch.as_tensor(qm, device=dev),
+                     "id": torch.arange(n, dtype=torch.int32, device=dev),
+                     "status": torch.zeros(n, dtype=torch.uint8, device=dev)}
+                prm = gcb.params(dt=dt, c=1.0, qm=float(qm[0]), n_iter=cfg.n_iter, **kw)
+                tr = torch.zeros((n_sub, n), dtype=torch.uint8, device=dev)
+                pos = [_cartesian(r0, th0, np.zeros(n))]
+                inside = [np.ones(n, dtype=bool)]
+                gca = np.zeros(n)
+                last = []
+                gmax = _lorentz(cfg, r0, th0, u0)
+                for s in range(steps):
+                    gcb.gcb_push_gr(ctx, gcb.gr_particles(t), prm, n_sub, s_trace=tr)
+                    S = tr.cpu().numpy()
+                    gca += (S == 0).sum(axis=0)
+                    last.append(S[-1])
+                    h = {k: t[k].cpu().numpy() for k in ("r", "th", "ph", "ur", "uth", "uph")}
+                    pos.append(_cartesian(h["r"], h["th"], h["ph"]))
+                    ins = (t["status"].cpu().numpy() & gcb.GCB_ST_OUT) == 0
+                    inside.append(ins)
+                    g = _lorentz(cfg, h["r"], h["th"], np.array([h["ur"], h["uth"], h["uph"]]))
+                    gmax = np.where(ins, np.maximum(gmax, g), gmax)
+                # the first step whose branch differs from that of the first step
+                S = np.array(last)
+                ch = S != S[0:1]
+                first = np.where(ch.any(axis=0), ch.argmax(axis=0), -1)
+                return np.array(pos), np.array(inside), gca / (steps * n_sub), first, gmax
+
+            log(f"replay gr sheet: rho/r_g = {rho:g}, reference with M = {M} substeps, "
+                f"{steps} steps of {DT:.4f} r_g/c")
+            ref_x, ref_in, _, _, ref_g = traj(DT / M, M, f_rho=0.0)
+            rep = {"rho_c0_over_rg": rho, "omega_c0": 1.0 / rho, "inflow": inflow,
+                   "start_r": r0.tolist(), "start_theta": th0.tolist(), "qm": qm.tolist(),
+                   "dt": DT, "steps": steps, "reference_substeps": M,
+                   "reference_inside_at_end": ref_in[-1].tolist(),
+                   "reference_max_gamma": ref_g.tolist()}
+            for name, kw in (("boris", dict(f_rho=0.0)),
+                             ("coupled", dict(f_rho=1.0, f_E=1.0))):
+                xs, _, frac, first, gmax = traj(DT, 1, **kw)
+                d = np.sqrt(((xs - ref_x) ** 2).sum(axis=1))
+                dmax = np.where(ref_in, d, 0.0).max(axis=0)
+                rep[name] = {"max_deviation_rg": dmax.tolist(),
+                             "gca_fraction": frac.tolist(), "max_gamma": gmax.tolist()}
+                if name == "coupled":
+                    rep[name]["first_switch_step"] = first.tolist()
+                log(f"  {name:8s} max deviation {np.round(dmax, 4).tolist()} r_g, GCA fraction "
+                    f"{np.round(frac, 3).tolist()}, max Gamma {np.round(gmax, 1).tolist()}")
+            reps.append(rep)
+        finally:
+            gcb.gcb_destroy(ctx)
+    return reps
 
 
 def run(omegas=(1e1, 1e2, 1e3, 1e4), t_end: float = 20.0, rotation: float = 0.1,
@@ -152,13 +317,19 @@ def run(omegas=(1e1, 1e2, 1e3, 1e4), t_end: float = 20.0, rotation: float = 0.1,
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
+    ap.add_argument("--test", choices=("sheet", "ambient"), default="ambient")
+    ap.add_argument("--rho", type=float, nargs="+", default=[1e-2, 1e-3, 1e-4])
+    ap.add_argument("--inflow", type=float, default=0.1)
     ap.add_argument("--omega", type=float, nargs="+", default=[1e1, 1e2, 1e3, 1e4])
     ap.add_argument("--t-end", type=float, default=20.0)
     ap.add_argument("--rotation", type=float, nargs="+", default=[0.1, 1.0])
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    rep = [run(a.omega, a.t_end, rot, log=lambda s: print(s, file=sys.stderr, flush=True))
-           for rot in a.rotation]
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    if a.test == "sheet":
+        rep = run_sheet(a.rho, a.inflow, log=log)
+    else:
+        rep = [run(a.omega, a.t_end, rot, log=log) for rot in a.rotation]
     text = json.dumps(rep, indent=1)
     if a.out:
         with open(a.out, "w") as f:

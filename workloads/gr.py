@@ -13,7 +13,11 @@ theta_j = j pi/nth, all six components at the nodes), in geometrized units:
   * the matching rotational electric field of the same flat-space solution,
     D^theta = -Omega_F sin(theta) B^r (so D.B = 0 away from the sheet),
     plus a reconnection field in the sheet, D^r = E_rec B0 / r^2 * sech^2
-    (cos(theta)/w), which gives particles there a parallel electric field.
+    (cos(theta)/w), which gives particles there a parallel electric field;
+  * optionally (`inflow` > 0) a toroidal electric field D^phi = inflow B0/r^3,
+    whose drift D x B carries field lines of both hemispheres toward the
+    sheet at a speed of about inflow sin(theta) c, and which exceeds B inside
+    the sheet (the stand-in of the near-sheet test of Sec. 4.2).
 These are closed-form samples; none of the pusher's arithmetic is used.
 
 Particles: positions uniform in r and in cos(theta) over a band away from the
@@ -36,7 +40,7 @@ GR_COMPONENTS = ("D^r", "D^th", "D^ph", "B^r", "B^th", "B^ph")
 
 def magnetosphere_fields(nr: int, nth: int, r_min: float, r_max: float, a: float,
                          B0: float, width: float, E_rec: float,
-                         rotation: float = 1.0) -> np.ndarray:
+                         rotation: float = 1.0, inflow: float = 0.0) -> np.ndarray:
     """F[k, j, i] = component k at (r_i, theta_j), shape (6, nth+1, nr+1)."""
     r = r_min + (r_max - r_min) * np.arange(nr + 1) / nr
     th = np.pi * np.arange(nth + 1) / nth
@@ -49,6 +53,7 @@ def magnetosphere_fields(nr: int, nth: int, r_min: float, r_max: float, a: float
     F = np.zeros((6, nth + 1, nr + 1))
     F[0] = E_rec * B0 / (R * R) / np.cosh(ct / width) ** 2
     F[1] = -omega_f * np.sin(TH) * Br
+    F[2] = inflow * B0 / (R * R * R)
     F[3] = Br
     F[5] = -omega_f * Br
     return F
@@ -117,10 +122,12 @@ class GRConfig:
     r_hi: float = 30.0
     cos_max: float = 0.9
     rotation: float = 1.0
+    inflow: float = 0.0
 
     def fields(self) -> np.ndarray:
         return magnetosphere_fields(self.nr, self.nth, self.r_min, self.r_max, self.a,
-                                    self.B0, self.width, self.E_rec, self.rotation)
+                                    self.B0, self.width, self.E_rec, self.rotation,
+                                    self.inflow)
 
     def particles(self, n: int | None = None, seed_offset: int = 0) -> GREnsemble:
         return magnetosphere_particles(self.n if n is None else n, self.seed + seed_offset,
