@@ -401,10 +401,12 @@ def main():
             pctx.close()
             torch.cuda.empty_cache()
 
-    def time_gr(steps: int, warmup: int, mixed: bool = False):
+    def time_gr(steps: int, warmup: int, mixed: bool = False, arith=None):
         """Curved-spacetime push: Kerr a = 0.9, 512 x 512 (r, theta) grid,
-        1e7 particles (the workload's own size), binary64 or the precision
-        form."""
+        1e7 particles (the workload's own size), binary64 (the headline's
+        arithmetic unless `arith` says otherwise) or the precision form."""
+        if arith is None:
+            arith = gcb.GCB_ARITH_EXACT if mixed else ARITH
         from workloads import make_gr_config
         gcfg = make_gr_config("grbh512")
         log(f"[bench] curved spacetime: generating {gcfg.name}, n={gcfg.n}")
@@ -424,7 +426,8 @@ def main():
             parts = gcb.gr_particles(t)
             prm = gcb.params(dt=gcfg.dt, c=1.0, qm=gcfg.qm, f_rho=gcfg.f_rho, f_E=gcfg.f_E,
                              n_iter=gcfg.n_iter, sort_every=a.gr_sort_every,
-                             form=gcb.GCB_FORM_MIXED if mixed else gcb.GCB_FORM_F64)
+                             form=gcb.GCB_FORM_MIXED if mixed else gcb.GCB_FORM_F64,
+                             arith=arith)
             st = gcb.gcb_push_gr(ctx, parts, prm, warmup, want_stats=True)
             frac = st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])
             gcb.gcb_set_timing(ctx, True)
@@ -445,13 +448,16 @@ def main():
                                 f"{gcfg.nr}x{gcfg.nth} (r, theta) grid r in "
                                 f"[{gcfg.r_min}, {gcfg.r_max}], split monopole with an "
                                 f"equatorial current sheet, {ge.n} particles, "
-                                + ("binary32 bulk, binary64 positions" if mixed else "binary64"),
+                                + ("binary32 bulk, binary64 positions" if mixed else
+                                   "binary64, " + ("production" if arith == gcb.GCB_ARITH_FAST
+                                                   else "exact") + " arithmetic"),
                     "steps": steps, "ms_per_step": (t1 - t0) * 1e3 / steps,
                     "kernel_ms_per_step": kms, "gca_fraction": frac,
                     "sort_every": a.gr_sort_every, "sort_ms_per_sort": sort_ms,
                     "algorithmic_flops_per_particle_step": fl,
                     "alu_achieved_TFLOPs": tf, "alu_frac": tf / FP64_VECTOR_PEAK_TF,
-                    "kernel": "k_gr_push (one lane per particle, 8 steps per launch), "
+                    "kernel": "k_gr_push (regime queues per workgroup, one lane per "
+                              "particle for the 8 steps of a launch, blocks in XCD order), "
                               "(r, theta) tile sort every sort_every steps"}
         finally:
             gcb.gcb_destroy(ctx)
@@ -581,6 +587,9 @@ def main():
 
     if not a.no_gr:
         forms["gr"] = time_gr(a.gr_steps, a.gr_warmup)
+        if a.arith == "fast":
+            forms["gr_exact_arith"] = time_gr(a.gr_steps, a.gr_warmup,
+                                              arith=gcb.GCB_ARITH_EXACT)
         if not a.no_mixed:
             forms["gr_mixed"] = time_gr(a.gr_steps, a.gr_warmup, mixed=True)
             forms["gr_mixed"]["speedup_vs_gr_f64"] = (forms["gr_mixed"]["value"]

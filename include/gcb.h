@@ -63,9 +63,11 @@ extern "C" {
                                order of the CPU definition the library is tested
                                against (no fused multiply-add): results agree with it
                                bit for bit (the parity build of the kernels) */
-#define GCB_ARITH_FAST  1   /* the same operations with multiply-adds fused where the
-                               compiler forms them (the production build): each fused
-                               operation rounds once instead of twice, so a step
+#define GCB_ARITH_FAST  1   /* the production build: multiply-adds fused where the
+                               compiler forms them (one rounding instead of two), and
+                               a square root that only serves as a divisor taken as a
+                               refined hardware reciprocal square root, quotients by a
+                               shared value as products with its reciprocal; a step
                                differs from GCB_ARITH_EXACT by a few units in the last
                                place (relative 1e-12 asserted per step, switch decisions
                                identical); over many steps the difference grows as the
@@ -204,8 +206,9 @@ typedef struct {
                             adjoints return GCB_EUNSUPPORTED for a value other than 0 */
     int32_t arith;       /* GCB_ARITH_EXACT (0, default) or GCB_ARITH_FAST: how the
                             binary64 form evaluates the step (see below).
-                            GCB_ARITH_FAST: gcb_push and gcb_push_noalloc with
-                            GCB_FORM_F64 only (else GCB_EUNSUPPORTED) */
+                            GCB_ARITH_FAST: gcb_push, gcb_push_noalloc and
+                            gcb_push_gr with GCB_FORM_F64 only (else
+                            GCB_EUNSUPPORTED) */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.
@@ -342,9 +345,10 @@ typedef struct {
    push) or the guiding-center step of Sec. 2.4 (half parallel push,
    implicit-midpoint update of (R, u_par) by n_iter iterations, half push,
    u rebuilt at R^{n+1} with the gyration direction of the step start).
-   Reads dt, qm, f_rho, f_E, fp_tol, n_iter, form and sort_every of params
-   (c is 1 here; replay must be 0; the other fields are ignored).  GCB_FORM_F64 needs
-   fields loaded as GCB_F64; GCB_FORM_MIXED (binary32 fields, metric,
+   Reads dt, qm, f_rho, f_E, fp_tol, mirror_tol, n_iter, form, arith and
+   sort_every of params (c is 1 here; replay must be 0; frame, gyration and
+   mirror must keep their defaults).  GCB_FORM_F64 needs fields loaded as
+   GCB_F64 and takes either arith; GCB_FORM_MIXED (binary32 fields, metric,
    four-velocity and bulk arithmetic, binary64 positions, and binary64 for
    Gamma when |u|^2 > 1e6, for 1 - v_E^2 when v_E^2 > 0.81 and for a switch
    ratio within a relative 1e-4 of its threshold) needs GCB_F32 fields.

@@ -41,6 +41,7 @@ UNITS = {
     "gcb_sort.hip": ["-ffp-contract=off"],
     "gcb_util.hip": ["-ffp-contract=off"],
     "gcb_gr.hip": ["-ffp-contract=off"],
+    "gcb_gr_fast.hip": ["-ffp-contract=fast"],
     "gcb_gr_mixed.hip": FAST_F32,
     "gcb_push3_f64.hip": ["-ffp-contract=off"],
     "gcb_push3_mixed.hip": FAST_F32,

@@ -46,6 +46,39 @@ constexpr double kDFloor = 1.0e-12;
 // NaN, have no field: a gather there returns NaN (a runaway iteration).
 constexpr double kFarLattice = 1073741824.0;   // 2^30
 
+// 1/sqrt(x) for finite x > 0 in binary64: the hardware estimate refined by
+// two Newton-Raphson steps y <- y + y (1 - x y^2)/2 (each roughly doubles
+// the number of correct bits; the result is within a few units in the last
+// place).
+GCB_HD double rsqrt_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+#else
+    double y = 1.0 / sqrt(x);
+#endif
+    double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+    return y;
+}
+
+// 1/x for finite normal x in binary64: the hardware estimate refined by two
+// Newton-Raphson steps y <- y + y (1 - x y); within a few units in the last
+// place.
+GCB_HD double rcp_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(x);
+#else
+    double y = 1.0 / x;
+#endif
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    return y;
+}
+
 // 2D Yee lattice offsets (cells) of Ex, Ey, Ez, Bx, By, Bz.
 constexpr double kYeeStagger[6][2] = {
     {0.5, 0.0}, {0.0, 0.5}, {0.0, 0.0}, {0.0, 0.5}, {0.5, 0.0}, {0.5, 0.5}};

@@ -61,6 +61,19 @@ constexpr double kPio2Lo = 6.07710050650619224932e-11;
 template <typename R>
 constexpr bool kF32 = std::is_same<R, float>::value;
 
+// The production form of the binary64 arithmetic (GCB_ARITH_FAST; its unit
+// defines GCB_FAST_ARITH): besides contracted multiply-adds, the metric's
+// quotients share the reciprocals of rho^2 and 1 + z, and a square root that
+// only serves as a divisor (the lapse, the triad's diagonal, Gamma in the
+// geodesic terms, B and kappa in the decomposition) becomes a reciprocal
+// square root.  Each such value differs from the correctly rounded one by a
+// few units in the last place.
+#ifndef GCB_FAST_ARITH
+#define GCB_FAST_ARITH 0
+#endif
+template <typename R>
+constexpr bool kGrFast = (GCB_FAST_ARITH != 0) && std::is_same<R, double>::value;
+
 // binary64: the full polynomial; binary32: the reduction in binary64 and
 // the polynomials to degree 11/12, which reach binary32 precision
 template <typename R>
@@ -138,6 +151,46 @@ GCB_HD void kerr_schild(double a_, double r_, double th, Metric<R>& m) {
     const R s2 = sn * sn;
     const R c2 = cs * cs;
     const R rho2 = r * r + a2 * c2;
+    if constexpr (kGrFast<R>) {
+        const R ir2 = rcp_nr(rho2);
+        const R z = ((R)2 * r) * ir2;
+        const R opz = (R)1 + z;
+        const R al = rsqrt_nr(opz);
+        const R iopz = al * al;
+        m.alpha = al;
+        m.beta_r = z * iopz;
+        m.gu_rr = iopz + (a2 * s2) * ir2;
+        m.gu_rph = a * ir2;
+        m.gu_thth = ir2;
+        // 1/(rho^2 sin^2), infinite on the axis
+        const R rs2 = rho2 * s2;
+        m.gu_phph = rs2 == (R)0 ? (R)__builtin_inf() : rcp_nr(rs2);
+        m.gd_rr = opz;
+        m.gd_rph = -(a * opz) * s2;
+        m.gd_thth = rho2;
+        m.gd_phph = s2 * (rho2 + (a2 * opz) * s2);
+        m.sqrtg = ((opz * al) * rho2) * sn;
+        if (kDerivs) {
+            const R sc = sn * cs;
+            const R drho2[2] = {(R)2 * r, (R)-2 * (a2 * sc)};
+            const R ir4 = ir2 * ir2;
+            const R dz[2] = {((R)2 * (a2 * c2 - r * r)) * ir4, ((R)4 * (r * (a2 * sc))) * ir4};
+            const R iopz2 = iopz * iopz;
+            const R gp2 = m.gu_phph * m.gu_phph;
+            for (int i = 0; i < 2; ++i) {
+                m.dalpha[i] = (R)-0.5 * (al * iopz) * dz[i];
+                m.dbeta_r[i] = dz[i] * iopz2;
+                m.dgu_rph[i] = -(a * drho2[i]) * ir4;
+                m.dgu_thth[i] = -drho2[i] * ir4;
+            }
+            m.dgu_rr[0] = -(dz[0] * iopz2) - (a2 * s2) * drho2[0] * ir4;
+            m.dgu_rr[1] = (-(dz[1] * iopz2) + (a2 * ((R)2 * sc)) * ir2) -
+                          (a2 * s2) * drho2[1] * ir4;
+            m.dgu_phph[0] = -(drho2[0] * s2) * gp2;
+            m.dgu_phph[1] = -(drho2[1] * s2 + rho2 * ((R)2 * sc)) * gp2;
+        }
+        return;
+    }
     const R z = ((R)2 * r) / rho2;
     const R opz = (R)1 + z;
     const R sq = sqrt(opz);
@@ -285,6 +338,24 @@ GCB_HD R gamma_of(const Metric<R>& m, const R u[3]) {
 
 GCB_HD double max_nan(double a, double b) { return (a > b || a != a) ? a : b; }
 
+// A Lorentz factor and, in the production form, its reciprocal (the
+// geodesic terms divide by it).
+template <typename R>
+struct Lorentz {
+    R g, inv;
+};
+
+template <typename R>
+GCB_HD Lorentz<R> lorentz_of(const Metric<R>& m, const R u[3]) {
+    if constexpr (kGrFast<R>) {
+        const R s = (R)1 + norm2_cov(m, u);
+        const R inv = rsqrt_nr(s);
+        return {s * inv, inv};
+    } else {
+        return {gamma_of(m, u), (R)0};
+    }
+}
+
 // ---------------------------------------------------------------------------
 // local-frame half push: Lorentz force over dt/2 (Boris with step alpha dt/2)
 
@@ -292,22 +363,45 @@ template <typename R>
 GCB_HD void half_push(const Metric<R>& m, const GrSample<R>& f, R u[3], double qm_,
                       double dt_) {
     const R qm = (R)qm_, dt = (R)dt_;
-    const R L11 = sqrt(m.gd_rr);
-    const R L22 = sqrt(m.gd_thth);
-    const R L31 = m.gd_rph / L11;
-    const R L33 = sqrt(m.gd_phph - L31 * L31);
-    const R u1 = u[0] / L11;
-    const R u2 = u[1] / L22;
-    const R u3 = (u[2] - L31 * u1) / L33;
+    R L11, L22, L31, L33, u1, u2, u3;
+    if constexpr (kGrFast<R>) {
+        const R i11 = rsqrt_nr(m.gd_rr);
+        const R i22 = rsqrt_nr(m.gd_thth);
+        L11 = m.gd_rr * i11;
+        L22 = m.gd_thth * i22;
+        L31 = m.gd_rph * i11;
+        const R q33 = m.gd_phph - L31 * L31;
+        const R i33 = rsqrt_nr(q33);
+        L33 = q33 * i33;
+        u1 = u[0] * i11;
+        u2 = u[1] * i22;
+        u3 = (u[2] - L31 * u1) * i33;
+    } else {
+        L11 = sqrt(m.gd_rr);
+        L22 = sqrt(m.gd_thth);
+        L31 = m.gd_rph / L11;
+        L33 = sqrt(m.gd_phph - L31 * L31);
+        u1 = u[0] / L11;
+        u2 = u[1] / L22;
+        u3 = (u[2] - L31 * u1) / L33;
+    }
     const R D1 = L11 * f.D[0] + L31 * f.D[2], D2 = L22 * f.D[1], D3 = L33 * f.D[2];
     const R B1 = L11 * f.B[0] + L31 * f.B[2], B2 = L22 * f.B[1], B3 = L33 * f.B[2];
     const R hq = (qm * (m.alpha * ((R)0.5 * dt))) * (R)0.5;
     const R umx = u1 + hq * D1, umy = u2 + hq * D2, umz = u3 + hq * D3;
-    const R gm = sqrt((R)1 + ((umx * umx + umy * umy) + umz * umz));
-    const R fq = hq / gm;
+    const R gm2 = (R)1 + ((umx * umx + umy * umy) + umz * umz);
+    R fq;
+    if constexpr (kGrFast<R>)
+        fq = hq * rsqrt_nr(gm2);
+    else
+        fq = hq / sqrt(gm2);
     const R tx = fq * B1, ty = fq * B2, tz = fq * B3;
     const R t2 = (tx * tx + ty * ty) + tz * tz;
-    const R g = (R)2 / ((R)1 + t2);
+    R g;
+    if constexpr (kGrFast<R>)
+        g = (R)2 * rcp_nr((R)1 + t2);
+    else
+        g = (R)2 / ((R)1 + t2);
     const R sx = g * tx, sy = g * ty, sz = g * tz;
     const R upx = umx + (umy * tz - umz * ty);
     const R upy = umy + (umz * tx - umx * tz);
@@ -325,23 +419,31 @@ GCB_HD void half_push(const Metric<R>& m, const GrSample<R>& f, R u[3], double q
 // G_i = -Gamma d_i alpha + u_j d_i beta^j - alpha u_j u_k d_i gamma^jk/(2 Gamma)
 // for i = r, theta (G_phi = 0)
 template <typename R>
-GCB_HD void geo_V(const Metric<R>& m, const R u[3], R Gam, R V[3]) {
+GCB_HD void geo_V(const Metric<R>& m, const R u[3], const Lorentz<R>& Gam, R V[3]) {
     R up[3];
     raise(m, u, up);
-    const R ag = m.alpha / Gam;
+    R ag;
+    if constexpr (kGrFast<R>)
+        ag = m.alpha * Gam.inv;
+    else
+        ag = m.alpha / Gam.g;
     V[0] = ag * up[0] - m.beta_r;
     V[1] = ag * up[1];
     V[2] = ag * up[2];
 }
 
 template <typename R>
-GCB_HD void geo_G(const Metric<R>& m, const R u[3], R Gam, R G[2]) {
+GCB_HD void geo_G(const Metric<R>& m, const R u[3], const Lorentz<R>& Gam, R G[2]) {
     const R ur = u[0], ut = u[1], up = u[2];
-    const R h = m.alpha / ((R)2 * Gam);
+    R h;
+    if constexpr (kGrFast<R>)
+        h = ((R)0.5 * m.alpha) * Gam.inv;
+    else
+        h = m.alpha / ((R)2 * Gam.g);
     for (int i = 0; i < 2; ++i) {
         const R q = ((ur * ur) * m.dgu_rr[i] + ((R)2 * (ur * up)) * m.dgu_rph[i]) +
                     ((ut * ut) * m.dgu_thth[i] + (up * up) * m.dgu_phph[i]);
-        G[i] = (-(Gam * m.dalpha[i]) + ur * m.dbeta_r[i]) - h * q;
+        G[i] = (-(Gam.g * m.dalpha[i]) + ur * m.dbeta_r[i]) - h * q;
     }
 }
 
@@ -350,6 +452,7 @@ template <typename R>
 struct GcLocal {
     R B, kappa, Dpar;
     R b_up[3], b_dn[3], vE[3];
+    R inv_B, inv_kappa;   // the production form's reciprocals
 };
 
 // (a, r, th) locate the point for the binary64 recomputation of 1 - v_E^2
@@ -361,11 +464,21 @@ GCB_HD uint32_t gc_local(const Metric<R>& m, const GrSample<R>& f, GcLocal<R>& L
     R Bl[3];
     lower(m, f.B, Bl);
     const R B2 = (f.B[0] * Bl[0] + f.B[1] * Bl[1]) + f.B[2] * Bl[2];
-    const R Bm = sqrt(B2);
-    const bool bzero = Bm == (R)0;
-    const R inv_B = bzero ? (R)0 : (R)1 / Bm;
+    R Bm, inv_B;
+    bool bzero;
+    if constexpr (kGrFast<R>) {
+        // 1/B from 1/sqrt(B^2); a negative or NaN B^2 gives NaN as sqrt does
+        bzero = B2 == (R)0;
+        inv_B = B2 > (R)0 ? rsqrt_nr(B2) : (bzero ? (R)0 : sqrt(B2));
+        Bm = bzero ? (R)0 : B2 * inv_B;
+    } else {
+        Bm = sqrt(B2);
+        bzero = Bm == (R)0;
+        inv_B = bzero ? (R)0 : (R)1 / Bm;
+    }
     if (bzero) flags |= ST_BZERO;
     L.B = Bm;
+    L.inv_B = inv_B;
     for (int i = 0; i < 3; ++i) {
         L.b_up[i] = f.B[i] * inv_B;
         L.b_dn[i] = Bl[i] * inv_B;
@@ -398,7 +511,12 @@ GCB_HD uint32_t gc_local(const Metric<R>& m, const GrSample<R>& f, GcLocal<R>& L
             om = (R)kKappaFloor;
             flags |= ST_KAPPA;
         }
-        L.kappa = (R)1 / sqrt(om);
+        if constexpr (kGrFast<R>) {
+            L.kappa = rsqrt_nr(om);
+            L.inv_kappa = om * L.kappa;
+        } else {
+            L.kappa = (R)1 / sqrt(om);
+        }
     }
     L.Dpar = (f.D[0] * L.b_dn[0] + f.D[1] * L.b_dn[1]) + f.D[2] * L.b_dn[2];
     return flags;
@@ -408,6 +526,18 @@ GCB_HD uint32_t gc_local(const Metric<R>& m, const GrSample<R>& f, GcLocal<R>& L
 template <typename R>
 GCB_HD R gamma_gc(const GcLocal<R>& L, R upar, R mu) {
     return L.kappa * sqrt(((R)1 + upar * upar) + (((R)2 * mu) * L.B) * L.kappa);
+}
+
+// the same with, in the production form, its reciprocal
+template <typename R>
+GCB_HD Lorentz<R> lorentz_gc(const GcLocal<R>& L, R upar, R mu) {
+    if constexpr (kGrFast<R>) {
+        const R s = ((R)1 + upar * upar) + (((R)2 * mu) * L.B) * L.kappa;
+        const R rs = rsqrt_nr(s);
+        return {L.kappa * (s * rs), L.inv_kappa * rs};
+    } else {
+        return {gamma_gc(L, upar, mu), (R)0};
+    }
 }
 
 template <typename R>
@@ -440,6 +570,51 @@ GCB_HD double wrap_phi(double ph) {
     return w;
 }
 
+// The switch (Sec. 4.1) at x^n from the metric and the fields there.
+template <typename R>
+GCB_HD bool switch_with(const Metric<R>& m0, const GrSample<R>& f0,
+                        const double* __restrict__ dl_table, const GrConst& g,
+                        const double x[3], const R u[3], double qm) {
+    int ci, cj;
+    double wx, wy;
+    grid_cell(g, x[0], x[1], ci, cj, wx, wy);
+    const double dl = dl_table[(size_t)cj * g.nr + ci];
+    return switch_gca(m0, f0, u, qm, dl, g, x[0], x[1]);
+}
+
+// The same with the metric and the fields at x^n evaluated here (the start
+// of a step, kept for the step's decomposition or half push).
+template <typename R, typename T>
+GCB_HD bool switch_at(const T* __restrict__ F, const double* __restrict__ dl_table,
+                      const GrConst& g, const double x[3], const R u[3], double qm,
+                      Metric<R>& m0, GrSample<R>& f0) {
+    kerr_schild<false>(g.a, x[0], x[1], m0);
+    grid_sample(F, g, x[0], x[1], f0);
+    return switch_with(m0, f0, dl_table, g, x, u, qm);
+}
+
+// The metric and the fields at a particle's position as the end of one step
+// evaluated them, for the start of the next: the same point, so the same
+// values, evaluated once.
+template <typename R>
+struct StepStart {
+    Metric<R> m;   // without the derivatives
+    GrSample<R> f;
+    bool valid;
+};
+
+// The branch the next step of a particle takes: true for the guiding
+// center; a particle outside the domain is not advanced and counts as not.
+template <typename R, typename T>
+GCB_HD bool starts_gca(const T* __restrict__ F, const double* __restrict__ dl_table,
+                       const GrConst& g, const double x[3], const R u[3], double qm,
+                       uint8_t status) {
+    if ((status & kStOut) || !inside(g, x[0], x[1])) return false;
+    Metric<R> m0;
+    GrSample<R> f0;
+    return switch_at(F, dl_table, g, x, u, qm, m0, f0);
+}
+
 // One coupled step (Sec. 3.2) of one particle.  Returns S: 0 guiding
 // center, 1 full orbit, 2 not advanced (outside the domain).
 //
@@ -457,10 +632,13 @@ GCB_HD double wrap_phi(double ph) {
 // geodesic force G, metric and fields at x^{n+1} -- so they are evaluated in
 // one pass: a wavefront whose lanes took different branches runs the shared
 // metric evaluations once, and only the branch-specific parts diverge.
+//
+// `start` carries the metric and the fields at x^{n+1} into the next step of
+// the same particle (start.valid false: evaluated here).
 template <typename R, typename T>
 GCB_HD int coupled_step(const T* __restrict__ F, const double* __restrict__ dl_table,
                         const GrConst& g, double x[3], R u[3], double qm, uint8_t& status,
-                        double& res) {
+                        double& res, StepStart<R>& start) {
     res = 0.0;
     if ((status & kStOut) || !inside(g, x[0], x[1])) {
         if (!inside(g, x[0], x[1])) status |= kStOut;
@@ -468,14 +646,15 @@ GCB_HD int coupled_step(const T* __restrict__ F, const double* __restrict__ dl_t
     }
     const R dt = (R)g.dt;
     Metric<R> m0;
-    kerr_schild<false>(g.a, x[0], x[1], m0);
     GrSample<R> f0;
-    grid_sample(F, g, x[0], x[1], f0);
-    int ci, cj;
-    double wx, wy;
-    grid_cell(g, x[0], x[1], ci, cj, wx, wy);
-    const double dl = dl_table[(size_t)cj * g.nr + ci];
-    const bool gca = switch_gca(m0, f0, u, qm, dl, g, x[0], x[1]);
+    bool gca;
+    if (start.valid) {
+        m0 = start.m;
+        f0 = start.f;
+        gca = switch_with(m0, f0, dl_table, g, x, u, qm);
+    } else {
+        gca = switch_at(F, dl_table, g, x, u, qm, m0, f0);
+    }
 
     uint32_t fl = 0;
     // guiding-center state: mu, gyration direction, u_par after the half push
@@ -492,10 +671,16 @@ GCB_HD int coupled_step(const T* __restrict__ F, const double* __restrict__ dl_t
         const R up2 = norm2_cov(m0, uperp);
         // the check of the neglect of the mirror terms (c = 1)
         if (g.mirror_tol > 0.0 && up2 > (R)g.mirror_tol * (Gf * Gf)) fl |= ST_MIRROR;
-        mu = (((R)0.5 * up2) / L0.B) / L0.kappa;
+        R inv_nu;
+        if constexpr (kGrFast<R>) {
+            mu = (((R)0.5 * up2) * L0.inv_B) * L0.inv_kappa;
+            inv_nu = up2 > (R)0 ? rsqrt_nr(up2) : (R)0;
+        } else {
+            mu = (((R)0.5 * up2) / L0.B) / L0.kappa;
+            const R nu = sqrt(up2);
+            inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
+        }
         if (!(L0.B > (R)0)) mu = (R)0;
-        const R nu = sqrt(up2);
-        const R inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
         for (int i = 0; i < 3; ++i) bperp[i] = uperp[i] * inv_nu;
         p1 = upar + ((R)qm * (m0.alpha * ((R)0.5 * dt))) * L0.Dpar;
         pk = p1;
@@ -510,7 +695,8 @@ GCB_HD int coupled_step(const T* __restrict__ F, const double* __restrict__ dl_t
         for (int i = 0; i < 3; ++i) Xb[i] = 0.5 * (Xk[i] + x[i]);
         Metric<R> mb;
         kerr_schild<true>(g.a, Xb[0], Xb[1], mb);
-        R V[3], ub[3], Gam;
+        R V[3], ub[3];
+        Lorentz<R> Gam;
         R bup0 = (R)0, bup1 = (R)0;
         if (gca) {
             const R pb = (R)0.5 * (pk + p1);
@@ -518,20 +704,27 @@ GCB_HD int coupled_step(const T* __restrict__ F, const double* __restrict__ dl_t
             grid_sample(F, g, Xb[0], Xb[1], fb);
             GcLocal<R> Lb;
             fl |= gc_local(mb, fb, Lb, g.a, Xb[0], Xb[1]);
-            Gam = gamma_gc(Lb, pb, mu);
+            Gam = lorentz_gc(Lb, pb, mu);
             R vu[3];
             raise(mb, Lb.vE, vu);
-            V[0] = mb.alpha * (pb * (Lb.b_up[0] / Gam) + vu[0]) - mb.beta_r;
-            V[1] = mb.alpha * (pb * (Lb.b_up[1] / Gam) + vu[1]);
-            V[2] = mb.alpha * (pb * (Lb.b_up[2] / Gam) + vu[2]);
+            R bG[3];
+            for (int i = 0; i < 3; ++i) {
+                if constexpr (kGrFast<R>)
+                    bG[i] = Lb.b_up[i] * Gam.inv;
+                else
+                    bG[i] = Lb.b_up[i] / Gam.g;
+            }
+            V[0] = mb.alpha * (pb * bG[0] + vu[0]) - mb.beta_r;
+            V[1] = mb.alpha * (pb * bG[1] + vu[1]);
+            V[2] = mb.alpha * (pb * bG[2] + vu[2]);
             const R upg = sqrt((((R)2 * mu) * Lb.kappa) * Lb.B);
             for (int i = 0; i < 3; ++i)
-                ub[i] = (pb * Lb.b_dn[i] + Lb.vE[i] * Gam) + upg * bperp[i];
+                ub[i] = (pb * Lb.b_dn[i] + Lb.vE[i] * Gam.g) + upg * bperp[i];
             bup0 = Lb.b_up[0];
             bup1 = Lb.b_up[1];
         } else {
             for (int i = 0; i < 3; ++i) ub[i] = (R)0.5 * (uk[i] + u1[i]);
-            Gam = gamma_of(mb, ub);
+            Gam = lorentz_of(mb, ub);
             geo_V(mb, ub, Gam, V);
         }
         R G[2];
@@ -578,6 +771,9 @@ GCB_HD int coupled_step(const T* __restrict__ F, const double* __restrict__ dl_t
     x[2] = wrap_phi(Xk[2]);
     for (int i = 0; i < 3; ++i) u[i] = un[i];
     status = (uint8_t)(status | fl);
+    start.m = m1;
+    start.f = f1;
+    start.valid = true;
     return gca ? 0 : 1;
 }
 

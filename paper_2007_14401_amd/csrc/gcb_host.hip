@@ -236,19 +236,23 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
     return GCB_OK;
 }
 
-// the contracted binary64 arithmetic is served by the 2D binary64 push only
+// the production binary64 arithmetic is served by the 2D and the
+// curved-spacetime binary64 pushes only
 int reject_fast_arith(gcb_ctx* ctx, const gcb_params* prm) {
     if (prm->arith != GCB_ARITH_EXACT)
         return fail(ctx, GCB_EUNSUPPORTED,
-                    "GCB_ARITH_FAST is served by gcb_push with GCB_FORM_F64 only");
+                    "GCB_ARITH_FAST is served by gcb_push and gcb_push_gr with GCB_FORM_F64 "
+                    "only");
     return GCB_OK;
 }
 
 // the exact frame (curvature = 0, binary64), the gyration options other
 // than a conserved mu and the mirror terms are served by gcb_push and
-// gcb_push_3d only, the check of the mirror terms (check_ok) by the pushes
-int reject_push_options(gcb_ctx* ctx, const gcb_params* prm, bool check_ok = false) {
-    if (reject_fast_arith(ctx, prm)) return GCB_EUNSUPPORTED;
+// gcb_push_3d only, the check of the mirror terms (check_ok) by the pushes,
+// the production arithmetic (fast_ok) as reject_fast_arith says
+int reject_push_options(gcb_ctx* ctx, const gcb_params* prm, bool check_ok = false,
+                        bool fast_ok = false) {
+    if (!fast_ok && reject_fast_arith(ctx, prm)) return GCB_EUNSUPPORTED;
     if (prm->frame != GCB_FRAME_REDUCED)
         return fail(ctx, GCB_EUNSUPPORTED,
                     "the exact frame is served by gcb_push and gcb_push_3d only");
@@ -1114,8 +1118,12 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     if (prm->replay) return fail(ctx, GCB_EUNSUPPORTED, "replay is not supported here");
     if (!(std::isfinite(prm->mirror_tol) && prm->mirror_tol >= 0.0))
         return fail(ctx, GCB_EINVAL, "mirror_tol must be finite and >= 0");
+    if (prm->arith != GCB_ARITH_EXACT && prm->arith != GCB_ARITH_FAST)
+        return fail(ctx, GCB_EINVAL, "unknown arith %d", prm->arith);
+    if (prm->arith == GCB_ARITH_FAST && prm->form != GCB_FORM_F64)
+        return fail(ctx, GCB_EUNSUPPORTED, "GCB_ARITH_FAST needs GCB_FORM_F64");
     {
-        const int rc = reject_push_options(ctx, prm, true);
+        const int rc = reject_push_options(ctx, prm, true, true);
         if (rc) return rc;
     }
     if (p->n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");
@@ -1152,6 +1160,10 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
     const double* dl = static_cast<const double*>(ctx->gr_dl.ptr);
     auto push = [&](const GrPtrs& in, const GrPtrs& out, const uint32_t* perm, int ns,
                     int step0) {
+        if (prm->form == GCB_FORM_F64 && prm->arith == GCB_ARITH_FAST)
+            return launch_gr_push_fast(in, out, perm, p->n, ns,
+                                       static_cast<const double*>(ctx->gr_fields.ptr), dl, g,
+                                       s_trace, step0, dstats, stream);
         if (prm->form == GCB_FORM_F64)
             return launch_gr_push_f64(in, out, perm, p->n, ns,
                                       static_cast<const double*>(ctx->gr_fields.ptr), dl, g,

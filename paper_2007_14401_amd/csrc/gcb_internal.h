@@ -240,5 +240,9 @@ hipError_t launch_gr_push_mixed(const GrPtrs& in, const GrPtrs& out, const uint3
                                 int64_t n, int n_steps, const float* F, const double* dl,
                                 const gr::GrConst& g, uint8_t* trace, int trace_step0,
                                 DevStats* stats, hipStream_t stream);
+hipError_t launch_gr_push_fast(const GrPtrs& in, const GrPtrs& out, const uint32_t* perm,
+                               int64_t n, int n_steps, const double* F, const double* dl,
+                               const gr::GrConst& g, uint8_t* trace, int trace_step0,
+                               DevStats* stats, hipStream_t stream);
 
 }  // namespace gcb

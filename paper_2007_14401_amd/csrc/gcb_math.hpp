@@ -49,23 +49,6 @@ constexpr bool kMixed = std::is_same<R, float>::value;
 template <typename R>
 constexpr bool kFastD = (GCB_FAST_ARITH != 0) && std::is_same<R, double>::value;
 
-// 1/sqrt(x) for finite x > 0 in binary64: the hardware estimate refined by
-// two Newton-Raphson steps y <- y + y (1 - x y^2)/2 (each roughly doubles
-// the number of correct bits; the result is within a few units in the last
-// place).
-GCB_HD double rsqrt_nr(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    double y = __builtin_amdgcn_rsq(x);
-#else
-    double y = 1.0 / sqrt(x);
-#endif
-    double e = fma(-(x * y), y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-(x * y), y, 1.0);
-    y = fma(0.5 * y, e, y);
-    return y;
-}
-
 // A Lorentz factor and, in the production form, its reciprocal.
 template <typename R>
 struct Gam {

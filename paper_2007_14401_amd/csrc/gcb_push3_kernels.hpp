@@ -177,7 +177,7 @@ k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const uint32_t* __restr
     for (int64_t base = p0; base < p1; base += kQueueMax) {
         const int m = (int)((p1 - base) < kQueueMax ? (p1 - base) : kQueueMax);
         // pass 1: switch decision, stable split into the two queues
-        const int nG = split_queues(m, queue, wave_g, wave_b, [&](int t) {
+        const int nG = split_queues<kWG>(m, queue, wave_g, wave_b, [&](int t) {
             const int64_t p = base + t;
             const int64_t src = perm ? (int64_t)perm[p] : p;
             if (replay) return trace[in.b.id ? (int64_t)in.b.id[src] : p] == 0;

@@ -25,6 +25,7 @@
 #include "gcb_access.hpp"
 #include "gcb_internal.h"
 #include "gcb_math.hpp"
+#include "gcb_queues.hpp"
 
 // The kernels are compiled once per form and contraction setting; the
 // namespace of their instances is set by the including unit.
@@ -93,51 +94,6 @@ __device__ __forceinline__ void store_particle(const ParticlePtrs<R>& in,
         if (in.qm) out.qm[p] = r.qm;
         if (in.id) out.id[p] = in.id[src];
     }
-}
-
-// Stable split of the m particles of one pass of a tile into two queues of
-// slots in LDS: those for which decide(t) holds (guiding center) from the
-// front in order, the others (Boris) from the back.  Every thread of the
-// workgroup calls it; returns the length of the guiding-center queue.
-template <class Decide>
-__device__ __forceinline__ int split_queues(int m, uint16_t* queue, int* wave_g, int* wave_b,
-                                            Decide&& decide) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    int nG = 0, nB = 0;
-    for (int t0 = 0; t0 < m; t0 += kWG) {
-        const int t = t0 + (int)threadIdx.x;
-        const bool valid = t < m;
-        const bool gca = valid && decide(t);
-        const unsigned long long bg = __ballot(valid && gca);
-        const unsigned long long bb = __ballot(valid && !gca);
-        if (lane == 0) {
-            wave_g[wave] = __popcll(bg);
-            wave_b[wave] = __popcll(bb);
-        }
-        __syncthreads();
-        int offg = nG, offb = nB, totg = 0, totb = 0;
-#pragma unroll
-        for (int w = 0; w < kWG / 64; ++w) {
-            if (w < wave) {
-                offg += wave_g[w];
-                offb += wave_b[w];
-            }
-            totg += wave_g[w];
-            totb += wave_b[w];
-        }
-        if (valid) {
-            if (gca)
-                queue[offg + __popcll(bg & lt)] = (uint16_t)t;
-            else
-                queue[m - 1 - (offb + __popcll(bb & lt))] = (uint16_t)t;
-        }
-        nG += totg;
-        nB += totb;
-        __syncthreads();
-    }
-    return nG;
 }
 
 // one coupled step for a particle already in registers (kVar: the
@@ -307,7 +263,7 @@ k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __
         const int m = (int)((p1 - base) < kWG ? (p1 - base) : kWG);
         // the branch of the launch's first step per particle, split into
         // the two queues
-        const int nG = split_queues(m, queue, wave_g, wave_b, [&](int q) {
+        const int nG = split_queues<kWG>(m, queue, wave_g, wave_b, [&](int q) {
             const int64_t p = base + q;
             const int64_t src = perm ? (int64_t)perm[p] : p;
             if (replay) return trace[in.id ? (int64_t)in.id[src] : p] == 0;
