@@ -47,9 +47,10 @@ FLOPS_GCA_3D = 4025.0
 # while the kernel sources still hash to the value it was taken with.
 COUNTER_RECORD = os.path.join(ROOT, "profiles", "k_push_tiled_harris4096.md")
 KERNEL_SOURCES = tuple(os.path.join("paper_2007_14401_amd", "csrc", f) for f in (
-    "gcb_common.hpp", "gcb_access.hpp", "gcb_math.hpp", "gcb_push_kernels.hpp",
-    "gcb_push_f64.hip", "gcb_push_mixed.hip", "gcb_sort.hip", "gcb_host.hip",
-    "gcb_internal.h")) + (os.path.join("paper_2007_14401_amd", "build.py"),)
+    "gcb_common.hpp", "gcb_access.hpp", "gcb_math.hpp", "gcb_queues.hpp",
+    "gcb_push_kernels.hpp", "gcb_push_f64.hip", "gcb_push_f64_fast.hip", "gcb_push_mixed.hip",
+    "gcb_sort.hip", "gcb_host.hip", "gcb_internal.h")) + (
+    os.path.join("paper_2007_14401_amd", "build.py"),)
 
 
 def log(*a):
@@ -89,8 +90,9 @@ def counter_record(path: str = COUNTER_RECORD):
 
 
 def measured_traffic(workload: str, n: int, sort_every: int, tile: int):
-    """HBM bytes per launch of the binary64 push from the counter record, or
-    None when there is none for this launch or the kernel changed since."""
+    """HBM bytes per launch of the binary64 push (a launch runs the steps
+    between two sorts) from the counter record, or None when there is none for
+    this launch or the kernel changed since."""
     rec = counter_record()
     if not rec:
         return None
@@ -522,7 +524,13 @@ def main():
     ARITH = gcb.GCB_ARITH_FAST if a.arith == "fast" else gcb.GCB_ARITH_EXACT
     r64 = time_form(gcb.GCB_FORM_F64, gcb.GCB_F64, a.steps, a.warmup)
     wall, push_ms, sort_ms, gca_frac = r64["wall"], r64["push_ms"], r64["sort_ms"], r64["gca_frac"]
+    # a launch runs the steps between two sorts: the roofline is taken per
+    # launch (algorithmic bytes and flops of its particle-steps over its
+    # average HIP-event duration), which is the same ratio as per step
+    steps_per_launch = a.steps / max(1, r64["launches"])
+    launch_ms = push_ms * steps_per_launch
     bytes_step = push_bytes_per_step(n, cfg.nx, cfg.ny, 0)
+    bytes_launch = bytes_step * steps_per_launch
     achieved = bytes_step / (push_ms * 1e-3) / 1e9
     value = n * a.steps / wall
     flops = FLOPS_GCA * gca_frac + FLOPS_BORIS * (1.0 - gca_frac)
@@ -681,10 +689,15 @@ def main():
                      "frac": (achieved / HBM_PEAK_GBS) if hbm_bound
                              else (alu_tf / FP64_VECTOR_PEAK_TF),
                      "traffic": traffic,
-                     "kernel": "k_push_tiled" if a.kernel != 1 else "k_push_global",
-                     "kernel_ms": push_ms,
+                     "kernel": ("kern_fast::" if a.arith == "fast" else "kern::")
+                               + ("k_push_tiled<double, double, true, 3, 0>" if a.kernel != 1
+                                  else "k_push_global<double, double, true, 0>"),
+                     "kernel_ms": launch_ms,
+                     "kernel_ms_per_step": push_ms,
+                     "steps_per_launch": steps_per_launch,
                      "algorithmic_flops_per_particle_step": flops,
-                     "algorithmic_flops_per_launch": flops * n,
+                     "algorithmic_bytes_per_particle_step": bytes_step / n,
+                     "algorithmic_flops_per_launch": flops * n * steps_per_launch,
                      "arithmetic_intensity_flop_per_byte": hroof[
                          "arithmetic_intensity_flop_per_byte"],
                      "alu_achieved_TFLOPs": alu_tf, "alu_peak_TFLOPs": FP64_VECTOR_PEAK_TF,
@@ -694,8 +707,8 @@ def main():
                      "hbm_frac": achieved / HBM_PEAK_GBS,
                      "hbm_target_frac": 0.6,
                      "hbm_frac_of_target": achieved / HBM_PEAK_GBS / 0.6,
-                     "algorithmic_bytes_per_launch": bytes_step,
-                     "traffic_over_algorithmic": (traffic / bytes_step) if traffic else None,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "traffic_over_algorithmic": (traffic / bytes_launch) if traffic else None,
                      "limiter": counter_limiter(cfg.name, n, a.sort_every, a.tile)},
         "sort_ms_per_sort": sort_ms,
         "forms": forms,
