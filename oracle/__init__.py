@@ -27,6 +27,8 @@ Layout of the oracle:
   pusher3d.py the coupled step in three dimensions (trilinear gather,
               gradients along z, three-component guiding-center position);
               reuses the dimension-free functions of pusher.py.
+  trig.py     sin and cos by a fixed reduction and polynomial (the curved-
+              spacetime metric and the gyro-phase option).
   gr.py       the general-relativistic coupled scheme (Sec. 2.3, 2.4, 3.2) in
               Kerr-Schild coordinates: metric functions and derivatives, the
               (r, theta) grid gather, the local-frame half pushes, the
@@ -41,7 +43,8 @@ from .fields import (GridFields, UniformFields, LinearFields, CircularFields,
 from .pusher import (Params, State, ST_NONFINITE, ST_KAPPA, ST_QUAD, ST_BZERO,
                      ST_FPRES, local, gamma_gca, v_curv, switch_gca, boris,
                      gca_step, step, push, wrap, min_image, parallel_update,
-                     GYR_MU, GYR_UPERP, GYR_ZERO, gyration, conserved_mu, uperp_sq,
+                     GYR_MU, GYR_UPERP, GYR_ZERO, GYR_PHASE, gyration, conserved_mu, uperp_sq,
+                     rotate_about, phase_advance,
                      mirror_parallel, mirror_check, ST_MIRROR)
 from .loss import kinetic_energy, push_gradients, push_gradients3
 from .fields3d import (GridFields3, UniformFields3, LinearFields3, CircularFieldsXZ,
@@ -58,6 +61,7 @@ __all__ = [
     "GridFields3", "UniformFields3", "LinearFields3", "CircularFieldsXZ", "FieldSample3",
     "YEE3", "COLLOCATED3", "Params3", "State3", "local3", "boris_step3", "gca_step3",
     "step3", "push3", "exact_frame", "local_exact",
-    "GYR_MU", "GYR_UPERP", "GYR_ZERO", "gyration", "conserved_mu", "uperp_sq",
+    "GYR_MU", "GYR_UPERP", "GYR_ZERO", "GYR_PHASE", "gyration", "conserved_mu", "uperp_sq",
+    "rotate_about", "phase_advance",
     "mirror_parallel", "mirror_check", "ST_MIRROR",
 ]

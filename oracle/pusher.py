@@ -43,7 +43,14 @@ design notes of the repository):
     the SRGCA system): u_perp_g keeps the value of the decomposition over
     the whole step.  GYR_ZERO (mu = 0, which the paper allows where
     radiation has removed the gyration, Sec. 2.2 before Sec. 2.2.1): the
-    decomposition's gyration is discarded.
+    decomposition's gyration is discarded.  GYR_PHASE (mu conserved, and the
+    gyration phase evolved by the extra equation Sec. 3.1 allows in place of
+    holding the gyration direction): over the step the gyration direction is
+    turned about b at R^n by the angle -(q/m) B dt/(c kappa Gamma), the
+    gyration frequency of a particle whose guiding center drifts with v_E
+    (in the drift frame q B'/(m c gamma') with B' = B/kappa, and the lab time
+    runs kappa times faster; Gamma = kappa gamma' is eq. lfacgca2), with
+    Gamma at R^n and the mean of u_par before and after the parallel update.
   * Params.mirror (curvature scheme only): the mirror force and the grad-B
     drift, which Sec. 2.2 names and leaves out of the reduced equations, with
     the paper's mu: du_par/dt gains -(mu/(m kappa Gamma)) b.grad|B| and the
@@ -65,6 +72,7 @@ from types import SimpleNamespace
 import torch
 
 from .ieee import sqrt
+from .trig import sincos
 
 F64 = torch.float64
 
@@ -80,6 +88,7 @@ ST_MIRROR = 128    # (v_perp_g/c)^2 above Params.mirror_tol at a decomposition
 GYR_MU = 0      # mu conserved (eq. dmudt)
 GYR_UPERP = 1   # u_perp_g constant over the step
 GYR_ZERO = 2    # mu = 0
+GYR_PHASE = 3   # mu conserved, the gyration phase advanced over the step
 
 KAPPA_FLOOR = 1.0e-12   # lower clamp of 1 - v_E^2/c^2
 D_FLOOR = 1.0e-12       # |1 - (dt/2) v_E.(b.grad)b| below this: no division
@@ -98,7 +107,7 @@ class Params:
     Ly: float = 0.0
     dl: float = 1.0   # effective cell size sqrt(dx*dy)
     exact_frame: bool = False   # b*, exact v_E (frame.py); zero-curvature scheme only
-    gyration: int = GYR_MU      # GYR_MU, GYR_UPERP or GYR_ZERO
+    gyration: int = GYR_MU      # GYR_MU, GYR_UPERP, GYR_ZERO or GYR_PHASE
     mirror: bool = False        # mirror force and grad-B drift (curvature scheme only)
     mirror_tol: float = 0.0     # > 0: flag ST_MIRROR where (v_perp_g/c)^2 exceeds it
 
@@ -219,6 +228,29 @@ def gyration(up2, Lh, p: Params):
     if p.gyration == GYR_ZERO:
         mu = torch.zeros_like(mu)
     return SimpleNamespace(mu=mu, up2=up2, fixed=p.gyration == GYR_UPERP)
+
+
+def rotate_about(b, d, ang):
+    """d turned by the angle ang (right-handed) about the unit vector b:
+    d cos + (b x d) sin + b (b.d)(1 - cos) (Rodrigues' rotation formula)."""
+    sn, cs = sincos(ang)
+    bd = (b[0] * d[0] + b[1] * d[1]) + b[2] * d[2]
+    cx = b[1] * d[2] - b[2] * d[1]
+    cy = b[2] * d[0] - b[0] * d[2]
+    cz = b[0] * d[1] - b[1] * d[0]
+    w = bd * (1.0 - cs)
+    return ((d[0] * cs + cx * sn) + b[0] * w,
+            (d[1] * cs + cy * sn) + b[1] * w,
+            (d[2] * cs + cz * sn) + b[2] * w)
+
+
+def phase_advance(Ln, upar, upn, gy, qm, bp, p: Params):
+    """The gyration direction bp after one step of the gyro-phase option:
+    turned about b at R^n by -(q/m) B dt/(c kappa Gamma), Gamma from eq.
+    lfacgca2 at R^n with the mean of u_par^{n-1/2} and u_par^{n+1/2}."""
+    gn = gamma_gca(Ln, 0.5 * (upar + upn), gy, p)
+    ang = -((qm * Ln.B) * p.dt) / ((p.c * Ln.kappa) * gn)
+    return rotate_about(Ln.b, bp, ang)
 
 
 def mirror_check(up2, gf, p: Params):
@@ -453,6 +485,8 @@ def gca_step(prov, st: State, p: Params):
     else:
         upn, qf = parallel_update(Ln, upar, gy, qm, p)
     flags |= qf
+    if p.gyration == GYR_PHASE:
+        bpx, bpy, bpz = phase_advance(Ln, upar, upn, gy, qm, (bpx, bpy, bpz), p)
 
     # 4. R^{n+1} by fixed-point iteration R^{k+1} = R^k - H(R^k), R^0 = R^n
     h = 0.5 * p.dt

@@ -23,9 +23,10 @@ from types import SimpleNamespace
 import torch
 
 from .ieee import sqrt
-from .pusher import (D_FLOOR, KAPPA_FLOOR, ST_BZERO, ST_FPRES, ST_KAPPA, ST_NONFINITE,
-                     Params, boris, gamma_gca, gyration, min_image, mirror_check, mirror_parallel,
-                     parallel_update, switch_gca, uperp_sq, v_curv, wrap)
+from .pusher import (D_FLOOR, GYR_PHASE, KAPPA_FLOOR, ST_BZERO, ST_FPRES, ST_KAPPA,
+                     ST_NONFINITE, Params, boris, gamma_gca, gyration, min_image, mirror_check,
+                     mirror_parallel, parallel_update, phase_advance, switch_gca, uperp_sq,
+                     v_curv, wrap)
 
 F64 = torch.float64
 
@@ -189,6 +190,8 @@ def gca_step3(prov, st: State3, p: Params3):
     else:
         upn, qf = parallel_update(Ln, upar, gy, qm, p)
     flags |= qf
+    if p.gyration == GYR_PHASE:
+        bpx, bpy, bpz = phase_advance(Ln, upar, upn, gy, qm, (bpx, bpy, bpz), p)
 
     # 4. R^{n+1} by fixed-point iteration R^{k+1} = R^k - H(R^k), R^0 = R^n
     h = 0.5 * p.dt
