@@ -87,6 +87,13 @@ extern "C" {
                                   exactly when E = 0 and the curvature terms vanish */
 #define GCB_GYRATION_ZERO  2   /* mu = 0: the gyration found at the decomposition is discarded
                                   (the paper allows it where radiation has removed it) */
+#define GCB_GYRATION_PHASE 3   /* mu conserved as GCB_GYRATION_MU, and the gyration phase
+                                  evolved (the extra equation Sec. 3.1 allows) instead of the
+                                  gyration direction being held: over the step the direction is
+                                  turned about b at R^n by -(q/m) B dt/(c kappa Gamma), Gamma of
+                                  eq. lfacgca2 at R^n with the mean of u_par before and after the
+                                  parallel update (the gyration frequency of a particle whose
+                                  guiding center drifts with v_E); reduced frame, mirror = 0 */
 
 /* where field arrays live (gcb_load_fields.src) */
 #define GCB_HOST   0
@@ -181,8 +188,9 @@ typedef struct {
                             b*, this v_E and kappa, and du_par/dt = (q/m) E'/kappa.  Other
                             calls and combinations return GCB_EUNSUPPORTED. */
     int32_t gyration;    /* GCB_GYRATION_* (0 = mu conserved).  Other values than
-                            GCB_GYRATION_MU: gcb_push and gcb_push_3d only (both forms,
-                            both frames); other calls return GCB_EUNSUPPORTED */
+                            GCB_GYRATION_MU: gcb_push and gcb_push_3d only (both forms;
+                            both frames, except GCB_GYRATION_PHASE: reduced frame and no
+                            mirror terms); other calls return GCB_EUNSUPPORTED */
     int32_t mirror;      /* 1: add the mirror force and the grad-B drift that Sec. 2.2
                             names and leaves out, with the step's mu (mu/m =
                             u_perp_g^2/(2 B kappa) under GCB_GYRATION_MU):

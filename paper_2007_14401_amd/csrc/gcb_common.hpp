@@ -21,20 +21,24 @@ enum : uint32_t {
 };
 
 // Gyration handling of a guiding-center step (the values of
-// gcb_params.gyration): mu conserved, u_perp_g held, mu = 0.
+// gcb_params.gyration): mu conserved, u_perp_g held, mu = 0, mu conserved
+// with the gyration phase advanced over the step.
 enum : int32_t {
     GYR_MU = 0,
     GYR_UPERP = 1,
     GYR_ZERO = 2,
+    GYR_PHASE = 3,
 };
 
 // Variants of the guiding-center branch, one kernel instance each: the
-// paper's reduced frame, the exact frame of Sec. 2.2, and the reduced frame
-// with the mirror force and grad-B drift (gcb_params.frame and .mirror).
+// paper's reduced frame, the exact frame of Sec. 2.2, the reduced frame
+// with the mirror force and grad-B drift (gcb_params.frame and .mirror), and
+// the reduced frame with the gyration phase advanced (GYR_PHASE).
 enum : int {
     kVarReduced = 0,
     kVarExact = 1,
     kVarMirror = 2,
+    kVarPhase = 3,
 };
 
 // 1 - v_E^2/c^2 is clamped to this floor where the drift reaches c.

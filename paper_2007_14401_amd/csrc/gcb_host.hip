@@ -223,8 +223,11 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EINVAL, "replay must be 0 or 1");
     if (prm->frame != GCB_FRAME_REDUCED && prm->frame != GCB_FRAME_EXACT)
         return fail(ctx, GCB_EINVAL, "unknown frame %d", prm->frame);
-    if (prm->gyration < GCB_GYRATION_MU || prm->gyration > GCB_GYRATION_ZERO)
+    if (prm->gyration < GCB_GYRATION_MU || prm->gyration > GCB_GYRATION_PHASE)
         return fail(ctx, GCB_EINVAL, "unknown gyration %d", prm->gyration);
+    if (prm->gyration == GCB_GYRATION_PHASE && (prm->frame != GCB_FRAME_REDUCED || prm->mirror))
+        return fail(ctx, GCB_EUNSUPPORTED,
+                    "GCB_GYRATION_PHASE goes with the reduced frame and without the mirror terms");
     if (prm->mirror != 0 && prm->mirror != 1)
         return fail(ctx, GCB_EINVAL, "mirror must be 0 or 1");
     if (prm->mirror && prm->curvature != 1)
@@ -654,6 +657,7 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         L.steps = ns;
         L.exact = prm->frame == GCB_FRAME_EXACT;
         L.mirror = prm->mirror != 0;
+        L.phase = prm->gyration == GCB_GYRATION_PHASE;
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))
@@ -749,6 +753,7 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
         L.steps = ns;
         L.exact = prm->frame == GCB_FRAME_EXACT;
         L.mirror = prm->mirror != 0;
+        L.phase = prm->gyration == GCB_GYRATION_PHASE;
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))

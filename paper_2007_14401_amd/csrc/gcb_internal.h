@@ -36,6 +36,7 @@ struct PushLaunch {
     int steps = 1;         // global kernel: steps per launch (trace: steps*n bytes)
     bool exact = false;    // guiding-center branch in the exact frame (binary64 only)
     bool mirror = false;   // guiding-center branch with the mirror terms
+    bool phase = false;    // guiding-center branch with the gyration phase advanced
 };
 
 // binary64 form (fields double, u double)
@@ -85,6 +86,7 @@ struct Push3Launch {
     int steps = 1;         // global kernel: steps per launch
     bool exact = false;    // guiding-center branch in the exact frame (binary64 only)
     bool mirror = false;   // guiding-center branch with the mirror terms
+    bool phase = false;    // guiding-center branch with the gyration phase advanced
 };
 
 hipError_t launch_push3_f64(const Push3Launch& L, const ParticlePtrs3<double>& in,

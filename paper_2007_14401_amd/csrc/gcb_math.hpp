@@ -22,6 +22,7 @@
 
 #include "gcb_access.hpp"
 #include "gcb_common.hpp"
+#include "gcb_trig.hpp"
 
 // The arithmetic below is compiled once per form and contraction setting
 // (each in a translation unit of its own); an inline namespace per setting
@@ -801,6 +802,32 @@ GCB_HD uint32_t mirror_check(R ux, R uy, R uz, const Local<R>& Lh, const R vc[3]
     return lhs > rhs ? (uint32_t)ST_MIRROR : 0u;
 }
 
+// The gyro-phase option (GYR_PHASE, kernel instances of their own): the
+// gyration direction d turned about b at R^n by -(q/m) B dt/(c kappa Gamma),
+// Gamma of eq. lfacgca2 at R^n with the mean of u_par before and after the
+// parallel update -- the gyration frequency of a particle whose guiding
+// center drifts with v_E -- by Rodrigues' formula
+// d cos + (b x d) sin + b (b.d)(1 - cos).
+template <typename R>
+GCB_HD void phase_advance(const Local<R>& Ln, R upar, R upn, const Gyr<R>& gy, R qm,
+                          const Consts<R>& K, R d[3]) {
+    const R gn = gamma_gca(Ln, (R)0.5 * (upar + upn), gy, K);
+    const R ang = -((qm * Ln.B) * K.dt) / ((K.c * Ln.kappa) * gn);
+    R sn, cs;
+    sincos_poly<R>((double)ang, sn, cs);
+    const R bd = (Ln.b[0] * d[0] + Ln.b[1] * d[1]) + Ln.b[2] * d[2];
+    const R cx = Ln.b[1] * d[2] - Ln.b[2] * d[1];
+    const R cy = Ln.b[2] * d[0] - Ln.b[0] * d[2];
+    const R cz = Ln.b[0] * d[1] - Ln.b[1] * d[0];
+    const R w = bd * ((R)1 - cs);
+    const R d0 = (d[0] * cs + cx * sn) + Ln.b[0] * w;
+    const R d1 = (d[1] * cs + cy * sn) + Ln.b[1] * w;
+    const R d2 = (d[2] * cs + cz * sn) + Ln.b[2] * w;
+    d[0] = d0;
+    d[1] = d1;
+    d[2] = d2;
+}
+
 GCB_HD double nan_max(double a, double b) {
     if (a != a) return a;
     if (b != b) return b;
@@ -810,8 +837,10 @@ GCB_HD double nan_max(double a, double b) {
 // One guiding-center step.  sn is the gather (with gradients) at x^n.
 // Returns status flags; res receives |R^K - R^{K-1}|_inf.
 // kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only);
-// kMirror: the mirror force and grad-B drift (curvature scheme only).
-template <typename R, bool kYee, bool kExact = false, bool kMirror = false, class Acc>
+// kMirror: the mirror force and grad-B drift (curvature scheme only);
+// kPhase: the gyration phase advanced over the step (GYR_PHASE).
+template <typename R, bool kYee, bool kExact = false, bool kMirror = false, bool kPhase = false,
+          class Acc>
 GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
                                              const PushConst& pc, const Consts<R>& K,
                                              double& res) {
@@ -874,6 +903,13 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
         else
             upn = parallel_update(Ln, upar, gy, qm, curv, K, flags);
         drift_terms(Ln, upn, gy, inv_qm, curv, K, Fnx, Fny, mirror);
+        if constexpr (kPhase) {
+            R d[3] = {bpx, bpy, bpz};
+            phase_advance(Ln, upar, upn, gy, qm, K, d);
+            bpx = d[0];
+            bpy = d[1];
+            bpz = d[2];
+        }
     }
 
     // 4. R^{n+1}: K fixed-point iterations R^{k+1} = R^k - H(R^k), R^0 = R^n
@@ -901,7 +937,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     if (res > pc.fp_tol) flags |= ST_FPRES;
 
     // 5. particle variables at R^{n+1/2} = (R^n + R^{n+1})/2, gyration
-    //    direction held fixed
+    //    direction held fixed (or advanced, kPhase)
     {
         const double Rmx = x + 0.5 * (Rx - x);
         const double Rmy = y + 0.5 * (Ry - y);

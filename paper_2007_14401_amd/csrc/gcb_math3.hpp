@@ -241,7 +241,8 @@ GCB_HD void boris_step3(const Sample3<R>& s, Regs3<R>& r, const PushConst3& pc,
 // flags; res receives |R^K - R^{K-1}|_inf over the three components.
 // kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only);
 // kMirror: the mirror force and grad-B drift (curvature scheme only).
-template <typename R, bool kYee, bool kExact = false, bool kMirror = false, class Acc>
+template <typename R, bool kYee, bool kExact = false, bool kMirror = false, bool kPhase = false,
+          class Acc>
 GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
                           const PushConst3& pc, const Consts3<R>& K, double& res) {
     uint32_t flags = 0;
@@ -295,6 +296,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
         else
             upn = parallel_update(Ln, upar, gy, qm, curv, K, flags);
         drift_terms3(Ln, upn, gy, inv_qm, curv, K, Fn, mirror);
+        if constexpr (kPhase) phase_advance(Ln, upar, upn, gy, qm, K, bp);
     }
 
     // 4. R^{n+1}: K fixed-point iterations R^{k+1} = R^k - H(R^k), R^0 = R^n
@@ -325,7 +327,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
     if (res > pc.b.fp_tol) flags |= ST_FPRES;
 
     // 5. particle variables at R^{n+1/2} = (R^n + R^{n+1})/2, gyration
-    //    direction held fixed
+    //    direction held fixed (or advanced, kPhase)
     {
         double Rm[3];
 #pragma unroll

@@ -68,7 +68,8 @@ __device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Re
     Sample3<R> s;
     if (gca) {
         gather3<R, true, kYee>(acc, pc, K, r.x, r.y, r.z, s);
-        fl = gca_step3<R, kYee, kVar == kVarExact, kVar == kVarMirror>(acc, s, r, pc, K, res);
+        fl = gca_step3<R, kYee, kVar == kVarExact, kVar == kVarMirror, kVar == kVarPhase>(
+            acc, s, r, pc, K, res);
     } else {
         gather3<R, false, kYee>(acc, pc, K, r.x, r.y, r.z, s);
         boris_step3(s, r, pc, K);
@@ -263,6 +264,7 @@ hipError_t launch_push3(const Push3Launch& L, const ParticlePtrs3<R>& in,
         if (L.exact) return hipErrorInvalidValue;
     }
     if (L.mirror) return launch_push3_frame<R, T, kMinWaves, kVarMirror>(L, in, out, pc, stream);
+    if (L.phase) return launch_push3_frame<R, T, kMinWaves, kVarPhase>(L, in, out, pc, stream);
     return launch_push3_frame<R, T, kMinWaves, kVarReduced>(L, in, out, pc, stream);
 }
 

@@ -108,7 +108,8 @@ __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Reg
     if (gca) {
         Sample<R> s;
         gather<R, true, kYee>(acc, pc, K, r.x, r.y, s);
-        fl = gca_step<R, kYee, kVar == kVarExact, kVar == kVarMirror>(acc, s, r, pc, K, res);
+        fl = gca_step<R, kYee, kVar == kVarExact, kVar == kVarMirror, kVar == kVarPhase>(
+            acc, s, r, pc, K, res);
     } else {
         Sample<R> s;
         gather<R, false, kYee>(acc, pc, K, r.x, r.y, s);
@@ -300,8 +301,8 @@ k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __
                 }
                 double res = 0.0;
                 if (gca)
-                    fl |= gca_step<R, kYee, kVar == kVarExact, kVar == kVarMirror>(acc, smp, r,
-                                                                                  pc, K, res);
+                    fl |= gca_step<R, kYee, kVar == kVarExact, kVar == kVarMirror,
+                                   kVar == kVarPhase>(acc, smp, r, pc, K, res);
                 else
                     boris_step(smp, r, pc, K);
                 fl |= finite_flag(r);
@@ -376,6 +377,7 @@ hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
         if (L.exact) return hipErrorInvalidValue;
     }
     if (L.mirror) return launch_push_frame<R, T, kMinWaves, kVarMirror>(L, in, out, pc, stream);
+    if (L.phase) return launch_push_frame<R, T, kMinWaves, kVarPhase>(L, in, out, pc, stream);
     return launch_push_frame<R, T, kMinWaves, kVarReduced>(L, in, out, pc, stream);
 }
 

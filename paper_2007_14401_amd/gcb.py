@@ -30,7 +30,7 @@ GCB_FORM_F64, GCB_FORM_MIXED = 0, 1
 GCB_HOST, GCB_DEVICE = 0, 1
 GCB_KERNEL_AUTO, GCB_KERNEL_GLOBAL, GCB_KERNEL_TILED = 0, 1, 2
 GCB_FRAME_REDUCED, GCB_FRAME_EXACT = 0, 1
-GCB_GYRATION_MU, GCB_GYRATION_UPERP, GCB_GYRATION_ZERO = 0, 1, 2
+GCB_GYRATION_MU, GCB_GYRATION_UPERP, GCB_GYRATION_ZERO, GCB_GYRATION_PHASE = 0, 1, 2, 3
 GCB_ARITH_EXACT, GCB_ARITH_FAST = 0, 1
 GCB_ST_NONFINITE, GCB_ST_KAPPA, GCB_ST_QUAD, GCB_ST_BZERO, GCB_ST_FPRES, GCB_ST_HALO = 1, 2, 4, 8, 16, 32
 GCB_ST_OUT = 64

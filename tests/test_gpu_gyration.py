@@ -1,6 +1,7 @@
 """Parity of the gyration options of the guiding-center step (Sec. 2.2:
-u_perp_g held over the step, or mu = 0, instead of a conserved mu) with the
-oracle (needs an MI355X).  Bar: the binary64 path of the parity tests,
+u_perp_g held over the step, or mu = 0, instead of a conserved mu; and the
+gyration phase advanced over the step, the extra equation Sec. 3.1 allows)
+with the oracle (needs an MI355X).  Bar: the binary64 path of the parity tests,
 1e-12 relative with identical switch decisions and status bits (bit for bit
 expected); the mixed form to the bounds of its one-step test."""
 import numpy as np
@@ -14,7 +15,7 @@ from workloads import make_config, make_config3
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-UPERP, ZERO = 1, 2
+UPERP, ZERO, PHASE = 1, 2, 3
 
 
 def _check(got, ref, cfg, what, tr_gpu, tr_ref):
@@ -35,7 +36,7 @@ def h64():
     run.close()
 
 
-@pytest.mark.parametrize("gyr", [UPERP, ZERO])
+@pytest.mark.parametrize("gyr", [UPERP, ZERO, PHASE])
 @pytest.mark.parametrize("kernel,sort_every,tile,steps", [(1, 0, 0, 1), (2, 1, 16, 1),
                                                           (1, 0, 0, 20), (2, 3, 24, 20)])
 def test_gyration_parity(h64, gyr, kernel, sort_every, tile, steps):
@@ -75,15 +76,15 @@ def test_gyration_options_differ(h64):
     cfg, F, run = h64
     ens = cfg.particles(n=2000, seed_offset=7)
     out = []
-    for gyr in (0, UPERP, ZERO):
+    for gyr in (0, UPERP, ZERO, PHASE):
         t = state.to_device(ens, "cuda:0")
         run.push(t, 10, kernel=1, gyration=gyr)
         out.append(state.unsort(t))
-    for a, b in ((0, 1), (0, 2), (1, 2)):
+    for a, b in ((0, 1), (0, 2), (1, 2), (0, 3)):
         assert np.abs(out[a]["ux"] - out[b]["ux"]).max() > 1e-9, (a, b)
 
 
-@pytest.mark.parametrize("gyr", [UPERP, ZERO])
+@pytest.mark.parametrize("gyr", [UPERP, ZERO, PHASE])
 @pytest.mark.parametrize("kernel,sort_every,tile,steps", [(1, 0, 0, 1), (2, 2, 6, 12)])
 def test_gyration_parity_3d(gyr, kernel, sort_every, tile, steps):
     cfg = make_config3("harris3d32")
@@ -103,7 +104,7 @@ def test_gyration_parity_3d(gyr, kernel, sort_every, tile, steps):
         run.close()
 
 
-@pytest.mark.parametrize("gyr", [UPERP, ZERO])
+@pytest.mark.parametrize("gyr", [UPERP, ZERO, PHASE])
 def test_gyration_mixed_one_step(gyr):
     """Mixed form against the binary64 oracle with the same option, one
     step, both kernels: the bounds of the mixed form's one-step test."""
@@ -144,8 +145,13 @@ def test_gyration_argument_checks(h64):
     cfg, F, run = h64
     t = state.to_device(cfg.particles(n=64), "cuda:0")
     with pytest.raises(gcb.GcbError) as e:
-        gcb.gcb_push(run.ctx, gcb.particles(t), gcb.params(gyration=3), 1)
+        gcb.gcb_push(run.ctx, gcb.particles(t), gcb.params(gyration=4), 1)
     assert e.value.code == gcb.GCB_EINVAL
+    # the phase option goes with the reduced frame and without the mirror terms
+    for kw in (dict(curvature=0, frame=gcb.GCB_FRAME_EXACT), dict(mirror=1)):
+        with pytest.raises(gcb.GcbError) as e:
+            gcb.gcb_push(run.ctx, gcb.particles(t), gcb.params(gyration=PHASE, **kw), 1)
+        assert e.value.code == gcb.GCB_EUNSUPPORTED, kw
     with pytest.raises(gcb.GcbError) as e:
         gcb.gcb_push(run.ctx, gcb.particles(t), gcb.params(gyration=-1), 1)
     assert e.value.code == gcb.GCB_EINVAL
@@ -158,3 +164,17 @@ def test_gyration_argument_checks(h64):
         gcb.gcb_push_backward(run.ctx, gcb.particles(t), gcb.params(gyration=UPERP), 1, lam,
                               lam0, grid[:3], grid[3:])
     assert e.value.code == gcb.GCB_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(1, 0, 0), (2, 1, 16)])
+def test_gyration_phase_production_one_step(h64, kernel, sort_every, tile):
+    """The phase option in the production binary64 build (GCB_ARITH_FAST):
+    one step within 1e-12 of the oracle, identical switch decisions."""
+    from paper_2007_14401_amd import state
+    cfg, F, run = h64
+    ens = cfg.particles(n=4096 + 37, seed_offset=10)
+    t = state.to_device(ens, "cuda:0")
+    tr, _ = run.push(t, 1, trace=True, kernel=kernel, sort_every=sort_every, tile=tile,
+                     gyration=PHASE, arith=1)
+    ref, rtr, _ = run_oracle(cfg, F, ens, 1, trace=True, gyration=PHASE)
+    _check(state.unsort(t), ref, cfg, "gyration phase, production build", tr, rtr)
