@@ -3,7 +3,9 @@
 A provider is called with particle positions (X, Y) and returns a
 `FieldSample`: E and B (three components each) and the in-plane gradient of
 each B component, dB[j][i] = d B_i / d x_j for j in (x, y).  The problem is
-2D3V, so d/dz is identically zero.
+2D3V, so d/dz is identically zero.  `e_gradient(X, Y)` gives the E
+gradients in the same layout (only the exact guiding-center frame with
+curvature needs them).
 
 `GridFields` is the grid gather of the paper: a field value at a particle is
 the sum over the surrounding nodes of node value times a linear shape
@@ -126,6 +128,16 @@ class GridFields:
         dB = (tuple(b[1] for b in Bs), tuple(b[2] for b in Bs))
         return nan_where(far, FieldSample(E, B, dB))
 
+    def e_gradient(self, X, Y):
+        """dE[j][i] = d E_i / d x_j (j = x, y) by differentiating W on each E
+        component's own lattice, as for B; NaN where the sample is."""
+        far = far_points(X * self.inv_dx, Y * self.inv_dy)
+        X = torch.where(far, 0.0, X)
+        Y = torch.where(far, 0.0, Y)
+        Es = [self.component(k, X, Y, True) for k in range(3)]
+        nan = lambda v: torch.where(far, float("nan"), v)
+        return (tuple(nan(e[1]) for e in Es), tuple(nan(e[2]) for e in Es))
+
 
 def _full(X, v):
     return torch.full_like(X, float(v))
@@ -144,6 +156,10 @@ class UniformFields:
                            tuple(_full(X, v) for v in self.B),
                            ((z, z, z), (z, z, z)))
 
+    def e_gradient(self, X, Y):
+        z = torch.zeros_like(X)
+        return ((z, z, z), (z, z, z))
+
 
 class LinearFields:
     """E(x) = E0 + GE @ (x, y), B(x) = B0 + GB @ (x, y) with 3x2 gradient matrices."""
@@ -160,6 +176,10 @@ class LinearFields:
         dB = (tuple(_full(X, self.GB[i, 0]) for i in range(3)),
               tuple(_full(X, self.GB[i, 1]) for i in range(3)))
         return FieldSample(E, B, dB)
+
+    def e_gradient(self, X, Y):
+        return (tuple(_full(X, self.GE[i, 0]) for i in range(3)),
+                tuple(_full(X, self.GE[i, 1]) for i in range(3)))
 
     def sample_grid(self, nx, ny, dx=1.0, dy=1.0, stagger=YEE):
         """The same fields sampled on each component's staggered nodes."""
@@ -202,3 +222,7 @@ class CircularFields:
         dBy_dy = -self.B0 * dx * dy / r3
         return FieldSample((z, z, z), (Bx, By, Bz),
                            ((dBx_dx, dBy_dx, z), (dBx_dy, dBy_dy, z)))
+
+    def e_gradient(self, X, Y):
+        z = torch.zeros_like(X)
+        return ((z, z, z), (z, z, z))

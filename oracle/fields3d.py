@@ -111,6 +111,17 @@ class GridFields3:
         dB = tuple(tuple(b[j + 1] for b in Bs) for j in range(3))
         return nan_where(far, FieldSample3(E, B, dB))
 
+    def e_gradient(self, X, Y, Z):
+        """dE[j][i] = d E_i / d x_j (j = x, y, z), differentiating W on each E
+        component's own lattice; NaN where the sample is."""
+        far = far_points(X * self.inv_dx, Y * self.inv_dy, Z * self.inv_dz)
+        X = torch.where(far, 0.0, X)
+        Y = torch.where(far, 0.0, Y)
+        Z = torch.where(far, 0.0, Z)
+        Es = [self.component(k, X, Y, Z, True) for k in range(3)]
+        nan = lambda v: torch.where(far, float("nan"), v)
+        return tuple(tuple(nan(e[j + 1]) for e in Es) for j in range(3))
+
 
 def _full(X, v):
     return torch.full_like(X, float(v))
@@ -129,6 +140,10 @@ class UniformFields3:
                             tuple(_full(X, v) for v in self.B),
                             ((z, z, z), (z, z, z), (z, z, z)))
 
+    def e_gradient(self, X, Y, Z):
+        z = torch.zeros_like(X)
+        return ((z, z, z), (z, z, z), (z, z, z))
+
 
 class LinearFields3:
     """E(x) = E0 + GE @ (x, y, z), B(x) = B0 + GB @ (x, y, z) with 3x3 gradients."""
@@ -146,6 +161,9 @@ class LinearFields3:
                   for i in range(3))
         dB = tuple(tuple(_full(X, self.GB[i, j]) for i in range(3)) for j in range(3))
         return FieldSample3(E, B, dB)
+
+    def e_gradient(self, X, Y, Z):
+        return tuple(tuple(_full(X, self.GE[i, j]) for i in range(3)) for j in range(3))
 
     def sample_grid(self, nx, ny, nz, dx=1.0, dy=1.0, dz=1.0, stagger=YEE3):
         """The same fields sampled on each component's staggered nodes, (6, nz, ny, nx)."""
@@ -190,3 +208,7 @@ class CircularFieldsXZ:
         dBz_dz = self.B0 * ex * ez / r3
         return FieldSample3((z, z, z), (Bx, By, Bz),
                             ((dBx_dx, z, dBz_dx), (z, z, z), (dBx_dz, z, dBz_dz)))
+
+    def e_gradient(self, X, Y, Z):
+        z = torch.zeros_like(X)
+        return ((z, z, z), (z, z, z), (z, z, z))

@@ -23,9 +23,18 @@ Readings used here (each listed with its reason in the design notes):
     the moving frame's clock runs slow by kappa, so du_par/dt = (q/m) E'/kappa
     (equal to (q/m)(E + v_E x B/c).b*; it reduces to (q/m) E.b when E.B = 0).
   * The local namespace keeps the lab-frame B in mu = m u_perp_g^2/(2 B kappa)
-    and eq. lfacgca2, with the exact kappa; the curvature terms are not
-    formed (the exact frame is offered with the zero-curvature scheme of
-    Sec. 2.2.1, whose equations hold b, v_E and E_par only).
+    and eq. lfacgca2, with the exact kappa.
+  * With the curvature scheme (Sec. 2.2.2) b* stands for b in eq. curvdrift
+    and eq. dupardt, in the cross product and in both directional derivatives,
+    (b*.grad)b* and (v_E.grad)b*, with the exact v_E; the prefactor
+    m c kappa^2/(q B) keeps the lab B, as mu does.  b* is a function of the
+    local E and B only, so its gradient is the chain rule
+    d_j b*_i = sum_c (d b*_i/d F_c) d_j F_c over the six components, with the
+    gather gradients d_j F_c (the E components differentiated through W on
+    their own lattices, as the B components are).  The partial derivatives
+    d b*_i/d F_c are taken by reverse-mode differentiation of `exact_frame`
+    (torch autograd, a library primitive).  Where B = 0, b* = 0 and its
+    gradient is 0.
   * B = 0: b* = 0, v_E = 0 and the B = 0 flag, as for the reduced frame;
     B' = 0 (E x B with E > B and E.B = 0): E' = 0 and Psi = 0.
 """
@@ -94,13 +103,53 @@ def exact_frame(E, B, p):
                            flags=flags.to(torch.uint8), E=(Ex, Ey, Ez), Bv=(Bx, By, Bz))
 
 
+def bstar_jacobian(E, B, p):
+    """J[i][c] = d b*_i / d F_c, F = (Ex, Ey, Ez, Bx, By, Bz), per particle:
+    reverse-mode differentiation of `exact_frame` (each particle's b* depends
+    on its own E and B only, so the gradient of the sum over particles is the
+    per-particle derivative).  Zero where B = 0."""
+    leaves = [v.detach().clone().requires_grad_(True) for v in (*E, *B)]
+    with torch.enable_grad():
+        fr = exact_frame(tuple(leaves[:3]), tuple(leaves[3:]), p)
+        J = []
+        for i in range(3):
+            g = torch.autograd.grad(fr.bstar[i].sum(), leaves, retain_graph=i < 2,
+                                    allow_unused=True)
+            J.append([torch.zeros_like(E[0]) if gi is None else gi.detach() for gi in g])
+    bzero = fr.B.detach() == 0.0
+    return [[torch.where(bzero, 0.0, v) for v in row] for row in J]
+
+
+def curvature_terms(fr, dF, p):
+    """(b*.grad)b*, (v_E.grad)b*, A = v_E.(b*.grad)b*, C = v_E.(v_E.grad)b*
+    from the frame `fr` and the field gradients dF[j][c] = d_j F_c
+    (j over the dimensions of the provider, c over the six components)."""
+    J = bstar_jacobian(fr.E, fr.Bv, p)
+    nd = len(dF)
+    # d_j b*_i = sum_c J[i][c] d_j F_c
+    db = [[sum(J[i][c] * dF[j][c] for c in range(6)) for i in range(3)] for j in range(nd)]
+    bs, vE = fr.bstar, fr.vE
+    bgb = tuple(sum(bs[j] * db[j][i] for j in range(nd)) for i in range(3))
+    vgb = tuple(sum(vE[j] * db[j][i] for j in range(nd)) for i in range(3))
+    A = (vE[0] * bgb[0] + vE[1] * bgb[1]) + vE[2] * bgb[2]
+    C = (vE[0] * vgb[0] + vE[1] * vgb[1]) + vE[2] * vgb[2]
+    return bgb, vgb, A, C
+
+
 def local_exact(prov, X, Y, p, Z=None):
     """The local namespace of the guiding-center step (see `pusher.local`)
-    with b = b*, the exact v_E and kappa, and E_par = E'/kappa; Z for a 3D
+    with b = b*, the exact v_E and kappa, and E_par = E'/kappa; with
+    p.curvature the curvature terms of b* (`curvature_terms`).  Z for a 3D
     provider."""
     s = prov(X, Y) if Z is None else prov(X, Y, Z)
     fr = exact_frame(s.E, s.B, p)
     z = torch.zeros_like(X)
+    if p.curvature:
+        dE = prov.e_gradient(X, Y) if Z is None else prov.e_gradient(X, Y, Z)
+        dF = [tuple(dE[j]) + tuple(s.dB[j]) for j in range(len(s.dB))]
+        bgb, vgb, A, C = curvature_terms(fr, dF, p)
+    else:
+        bgb, vgb, A, C = (z, z, z), (z, z, z), z, z
     return SimpleNamespace(E=fr.E, Bv=fr.Bv, B=fr.B, inv_B=fr.inv_B, b=fr.bstar, vE=fr.vE,
-                           kappa=fr.kappa, Epar=fr.Epar, bgb=(z, z, z), vgb=(z, z, z), A=z,
-                           C=z, flags=fr.flags)
+                           kappa=fr.kappa, Epar=fr.Epar, bgb=bgb, vgb=vgb, A=A, C=C,
+                           flags=fr.flags)

@@ -32,9 +32,10 @@ design notes of the repository):
     iterations R^{k+1} = R^k - H(R^k) from R^0 = R^n; the last increment
     |R^K - R^{K-1}| is the reported iteration error.
   * Periodic box; stored positions are wrapped into [0, L).
-  * Params.exact_frame (zero-curvature scheme only): b*, the exact v_E and
-    kappa and E_par = E'/kappa of the frame of Sec. 2.2 (frame.py) in place of
-    b, c E x B/B^2 and E.b; everything else unchanged.
+  * Params.exact_frame: b*, the exact v_E and kappa and E_par = E'/kappa of
+    the frame of Sec. 2.2 (frame.py) in place of b, c E x B/B^2 and E.b;
+    with the curvature scheme also (b*.grad)b* and (v_E.grad)b* from the
+    gradients of b* (frame.py); everything else unchanged.
   * Params.gyration: how the gyration speed enters a guiding-center step.
     GYR_MU (the paper's choice, eq. dmudt): mu is conserved, so wherever
     u_perp_g^2 = 2 mu B kappa/m appears (eq. lfacgca2, k3 of the quadratic,
@@ -106,7 +107,7 @@ class Params:
     Lx: float = 0.0
     Ly: float = 0.0
     dl: float = 1.0   # effective cell size sqrt(dx*dy)
-    exact_frame: bool = False   # b*, exact v_E (frame.py); zero-curvature scheme only
+    exact_frame: bool = False   # b*, exact v_E and their curvature terms (frame.py)
     gyration: int = GYR_MU      # GYR_MU, GYR_UPERP, GYR_ZERO or GYR_PHASE
     mirror: bool = False        # mirror force and grad-B drift (curvature scheme only)
     mirror_tol: float = 0.0     # > 0: flag ST_MIRROR where (v_perp_g/c)^2 exceeds it
@@ -179,7 +180,6 @@ def local(prov, X, Y, p: Params):
     """
     if p.exact_frame:
         from .frame import local_exact
-        assert not p.curvature, "the exact frame is used with the zero-curvature scheme"
         return local_exact(prov, X, Y, p)
     s = prov(X, Y)
     Ex, Ey, Ez = s.E
@@ -452,6 +452,7 @@ def gca_step(prov, st: State, p: Params):
     ux, uy, uz = st.ux, st.uy, st.uz
     inv_qm = 1.0 / qm
     assert p.curvature or not p.mirror, "the mirror terms ride on the curvature scheme"
+    assert not (p.exact_frame and p.mirror), "the mirror terms go with the reduced frame"
     flags = torch.zeros_like(x, dtype=torch.uint8)
 
     # 1. switch to guiding-center variables at R^{n-1/2} = (x^n + x^{n-1})/2

@@ -80,7 +80,6 @@ def local3(prov, X, Y, Z, p: Params3):
     frame of frame.py)."""
     if p.exact_frame:
         from .frame import local_exact
-        assert not p.curvature, "the exact frame is used with the zero-curvature scheme"
         return local_exact(prov, X, Y, p, Z)
     s = prov(X, Y, Z)
     Ex, Ey, Ez = s.E
@@ -154,6 +153,7 @@ def gca_step3(prov, st: State3, p: Params3):
     pos = (st.x, st.y, st.z)
     prev = (st.xp, st.yp, st.zp)
     assert p.curvature or not p.mirror, "the mirror terms ride on the curvature scheme"
+    assert not (p.exact_frame and p.mirror), "the mirror terms go with the reduced frame"
     box = (p.Lx, p.Ly, p.Lz)
     qm = st.qm
     ux, uy, uz = st.ux, st.uy, st.uz

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle as O
-from oracle.frame import exact_frame
+from oracle.frame import exact_frame, local_exact
 
 F64 = torch.float64
 
@@ -203,3 +203,140 @@ def test_exact_frame_equals_reduced_frame_when_fields_are_perpendicular():
     assert torch.equal(Sa, Sb) and 0 < int(Sa.sum()) < Sa.numel()
     for k in ("x", "y", "ux", "uy", "uz"):
         assert torch.allclose(getattr(a, k), getattr(b, k), rtol=1e-12, atol=1e-14), k
+
+
+# ---------------------------------------------------------------------------
+# the exact frame with the curvature scheme (Sec. 2.2 with Sec. 2.2.2): the
+# curvature terms are built from the gradient of b*, which depends on E too
+
+
+def _bstar_at(prov, p, *X):
+    s = prov(*X)
+    return exact_frame(s.E, s.B, p).bstar
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_exact_frame_curvature_terms_match_finite_differences(nd):
+    """(b*.grad)b*, (v_E.grad)b*, A and C of the oracle against central
+    differences of b* itself, evaluated from the fields at displaced points,
+    for fields linear in position with E.B != 0 (so b* differs from b and
+    depends on the gradients of both E and B)."""
+    rng = np.random.default_rng(47 + nd)
+    n = 64
+    E0 = np.array([0.06, -0.04, 0.09])[:, None] + 0.0 * rng.normal(size=(3, 1))
+    B0 = np.array([0.3, 0.5, 0.8])
+    GE = rng.normal(0.0, 0.004, (3, nd))
+    GB = rng.normal(0.0, 0.01, (3, nd))
+    if nd == 2:
+        prov = O.LinearFields(E0[:, 0], GE, B0, GB)
+        p = O.Params(c=0.45, curvature=True, exact_frame=True, Lx=1e6, Ly=1e6)
+    else:
+        prov = O.LinearFields3(E0[:, 0], GE, B0, GB)
+        p = O.Params3(c=0.45, curvature=True, exact_frame=True, Lx=1e6, Ly=1e6, Lz=1e6)
+    X = [torch.as_tensor(rng.uniform(0.0, 6.0, n)) for _ in range(nd)]
+    L = local_exact(prov, *X[:2], p, *X[2:])
+    h = 1e-5
+    db = []
+    for j in range(nd):
+        Xp = [x + (h if k == j else 0.0) for k, x in enumerate(X)]
+        Xm = [x - (h if k == j else 0.0) for k, x in enumerate(X)]
+        db.append([(a - b) / (2 * h) for a, b in
+                   zip(_bstar_at(prov, p, *Xp), _bstar_at(prov, p, *Xm))])
+    bgb = [sum(L.b[j] * db[j][i] for j in range(nd)) for i in range(3)]
+    vgb = [sum(L.vE[j] * db[j][i] for j in range(nd)) for i in range(3)]
+    scale = max(float(torch.stack(bgb).abs().max()), float(torch.stack(vgb).abs().max()))
+    assert scale > 1e-4   # the terms are not trivially small
+    for i in range(3):
+        assert float((L.bgb[i] - bgb[i]).abs().max()) < 1e-7 * scale
+        assert float((L.vgb[i] - vgb[i]).abs().max()) < 1e-7 * scale
+    A = (L.vE[0] * bgb[0] + L.vE[1] * bgb[1]) + L.vE[2] * bgb[2]
+    C = (L.vE[0] * vgb[0] + L.vE[1] * vgb[1]) + L.vE[2] * vgb[2]
+    assert float((L.A - A).abs().max()) < 1e-7 * scale
+    assert float((L.C - C).abs().max()) < 1e-7 * scale
+    # b* itself differs from b by much more than the tolerance
+    s = prov(*X)
+    Bm = torch.sqrt(sum(v * v for v in s.B))
+    assert float(max((bs - Bv / Bm).abs().max() for bs, Bv in zip(L.b, s.B))) > 1e-3
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_grid_e_gradient_is_the_derivative_of_the_gather(nd):
+    """The gather's E gradients (differentiated W on each E lattice) equal the
+    slope of the gathered E along each axis inside a cell, where the
+    interpolant is linear along the axis."""
+    rng = np.random.default_rng(53 + nd)
+    shape = (6,) + (8,) * nd
+    prov = (O.GridFields(rng.normal(size=shape)) if nd == 2
+            else O.GridFields3(rng.normal(size=shape)))
+    n = 100
+    # points at least 0.1 cell from every lattice line of every component
+    X = [torch.as_tensor(np.floor(rng.uniform(0, 8, n)) + rng.uniform(0.1, 0.4, n))
+         for _ in range(nd)]
+    dE = prov.e_gradient(*X)
+    h = 1e-6
+    for j in range(nd):
+        Xp = [x + (h if k == j else 0.0) for k, x in enumerate(X)]
+        Xm = [x - (h if k == j else 0.0) for k, x in enumerate(X)]
+        for i in range(3):
+            fd = (prov(*Xp).E[i] - prov(*Xm).E[i]) / (2 * h)
+            assert torch.allclose(dE[j][i], fd, rtol=1e-7, atol=1e-8)
+
+
+def test_exact_frame_curvature_equals_reduced_frame_for_ideal_fields():
+    """Ideal fields E = -v x B/c with uniform v (E.B = 0 up to rounding at every
+    point, E < B): b* = b and the exact v_E is c E x B/B^2, and the gradient of
+    b* reduces to that of b (its E-dependent part is proportional to the
+    gradient of E.B).  The curvature scheme in both frames then agrees to
+    rounding over a multi-step run, with identical switch decisions."""
+    rng = np.random.default_rng(59)
+    c = 0.45
+    v = np.array([0.02, -0.03, 0.01])
+    B0 = np.array([0.3, 0.2, 1.0])
+    GB = rng.normal(0.0, 0.02, (3, 2))
+    E0 = -np.cross(v, B0) / c
+    GE = np.stack([-np.cross(v, GB[:, j]) / c for j in range(2)], axis=1)
+    prov = O.LinearFields(E0, GE, B0, GB)
+    n = 200
+    # inside the box, away from its edges: no wrap over the run
+    x, y = rng.uniform(20, 40, n), rng.uniform(20, 40, n)
+    u = 0.2 * rng.normal(size=(3, n))
+    qm = -np.where(np.arange(n) % 3 == 0, 0.05, 20.0)
+    st0 = O.State(*(torch.as_tensor(w) for w in (x, y, x.copy(), y.copy(), *u, qm)),
+                  torch.zeros(n, dtype=torch.uint8))
+    kw = dict(c=c, curvature=True, Lx=1e6, Ly=1e6, dl=1.0)
+    Lr = O.local(prov, st0.x, st0.y, O.Params(**kw))
+    Le = O.local(prov, st0.x, st0.y, O.Params(exact_frame=True, **kw))
+    for k in ("b", "vE", "bgb", "vgb"):
+        for a, b in zip(getattr(Lr, k), getattr(Le, k)):
+            assert torch.allclose(a, b, rtol=1e-12, atol=1e-15), k
+    for k in ("kappa", "A", "C", "Epar"):
+        assert torch.allclose(getattr(Lr, k), getattr(Le, k), rtol=1e-12, atol=1e-15), k
+    assert float(torch.stack(Lr.bgb).abs().max()) > 1e-3
+    a, Sa, _ = O.push(prov, st0.clone(), O.Params(**kw), 10, trace=True)
+    b, Sb, _ = O.push(prov, st0.clone(), O.Params(exact_frame=True, **kw), 10, trace=True)
+    assert torch.equal(Sa, Sb) and 0 < int(Sa.sum()) < Sa.numel()
+    for k in ("x", "y", "ux", "uy", "uz"):
+        assert torch.allclose(getattr(a, k), getattr(b, k), rtol=1e-11, atol=1e-13), k
+
+
+def test_exact_frame_curvature_in_uniform_fields_is_the_zero_curvature_step():
+    """Uniform fields with E.B != 0: the gradient of b* vanishes, so the
+    curvature scheme in the exact frame takes exactly (bit for bit) the step
+    of the zero-curvature scheme: the quadratic's root reduces to the explicit
+    parallel update and the curvature drift to zero."""
+    rng = np.random.default_rng(61)
+    E = [0.05, -0.02, 0.07]
+    B = [0.2, 0.4, 0.8]
+    prov = O.UniformFields(E, B)
+    n = 100
+    x, y = rng.uniform(0, 20, n), rng.uniform(0, 20, n)
+    u = 0.2 * rng.normal(size=(3, n))
+    qm = -np.full(n, 20.0)
+    st0 = O.State(*(torch.as_tensor(w) for w in (x, y, x - 0.01, y + 0.02, *u, qm)),
+                  torch.zeros(n, dtype=torch.uint8))
+    kw = dict(c=0.45, exact_frame=True, Lx=1e6, Ly=1e6, dl=1.0)
+    a, Sa, _ = O.push(prov, st0.clone(), O.Params(curvature=False, **kw), 5, trace=True)
+    b, Sb, _ = O.push(prov, st0.clone(), O.Params(curvature=True, **kw), 5, trace=True)
+    assert not bool(Sa.any()) and torch.equal(Sa, Sb)
+    for k in ("x", "y", "xp", "yp", "ux", "uy", "uz"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
