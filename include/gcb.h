@@ -76,8 +76,8 @@ extern "C" {
 /* guiding-center frame (gcb_params.frame) */
 #define GCB_FRAME_REDUCED 0   /* the paper's schemes: b = B/B, v_E = c E x B/B^2, E_par = E.b */
 #define GCB_FRAME_EXACT   1   /* the exact frame of Sec. 2.2: b*, the exact v_E and kappa,
-                                 E_par = E'/kappa; with curvature = 0, GCB_FORM_F64,
-                                 gcb_push and gcb_push_3d only */
+                                 E_par = E'/kappa, and with curvature = 1 the curvature terms
+                                 of b*; GCB_FORM_F64, gcb_push and gcb_push_3d only */
 
 /* gyration handling of a guiding-center step (gcb_params.gyration), Sec. 2.2 */
 #define GCB_GYRATION_MU    0   /* mu/m = u_perp_g^2/(2 B kappa) conserved (eq. dmudt): u_perp_g^2
@@ -183,10 +183,15 @@ typedef struct {
                             v_E = 2 w_E/(1 + s), kappa = (1 - v_E^2/c^2)^(-1/2),
                             B' = sqrt((B^2 - E^2 + (E^2 + B^2) s)/2), E' = E.B/B',
                             b* = eta (Psi E_perp + B) with Psi = 2 E' B^2/(B'(E^2+B^2)(1+s)),
-                            eta = 1/(B sqrt(Psi^2 E_perp^2/B^2 + 1)); the zero-curvature
-                            scheme (Sec. 2.2.1) and the conversions of Sec. 3.1 then use
-                            b*, this v_E and kappa, and du_par/dt = (q/m) E'/kappa.  Other
-                            calls and combinations return GCB_EUNSUPPORTED. */
+                            eta = 1/(B sqrt(Psi^2 E_perp^2/B^2 + 1)); the scheme
+                            (Sec. 2.2.1 with curvature = 0, Sec. 2.2.2 with curvature = 1)
+                            and the conversions of Sec. 3.1 then use b*, this v_E and
+                            kappa, and du_par/dt = (q/m) E'/kappa; with curvature = 1,
+                            (b*.grad)b* and (v_E.grad)b* in eq. curvdrift and eq. dupardt,
+                            the gradient of b* by the chain rule through E and B (the
+                            gather then also forms the E gradients).  Binary64 (either
+                            arithmetic), gcb_push and gcb_push_3d, mirror = 0; other calls
+                            and combinations return GCB_EUNSUPPORTED. */
     int32_t gyration;    /* GCB_GYRATION_* (0 = mu conserved).  Other values than
                             GCB_GYRATION_MU: gcb_push and gcb_push_3d only (both forms;
                             both frames, except GCB_GYRATION_PHASE: reduced frame and no

@@ -31,15 +31,20 @@ enum : int32_t {
 };
 
 // Variants of the guiding-center branch, one kernel instance each: the
-// paper's reduced frame, the exact frame of Sec. 2.2, the reduced frame
-// with the mirror force and grad-B drift (gcb_params.frame and .mirror), and
-// the reduced frame with the gyration phase advanced (GYR_PHASE).
+// paper's reduced frame, the exact frame of Sec. 2.2 with the zero-curvature
+// scheme, the reduced frame with the mirror force and grad-B drift
+// (gcb_params.frame and .mirror), the reduced frame with the gyration phase
+// advanced (GYR_PHASE), and the exact frame with the curvature scheme.
 enum : int {
     kVarReduced = 0,
     kVarExact = 1,
     kVarMirror = 2,
     kVarPhase = 3,
+    kVarExactCurv = 4,
 };
+
+// the exact frame (either scheme)
+constexpr bool var_exact(int v) { return v == kVarExact || v == kVarExactCurv; }
 
 // 1 - v_E^2/c^2 is clamped to this floor where the drift reaches c.
 constexpr double kKappaFloor = 1.0e-12;

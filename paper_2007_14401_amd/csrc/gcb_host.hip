@@ -232,6 +232,8 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EINVAL, "mirror must be 0 or 1");
     if (prm->mirror && prm->curvature != 1)
         return fail(ctx, GCB_EUNSUPPORTED, "the mirror terms need curvature = 1");
+    if (prm->mirror && prm->frame != GCB_FRAME_REDUCED)
+        return fail(ctx, GCB_EUNSUPPORTED, "the mirror terms go with the reduced frame");
     if (!(std::isfinite(prm->mirror_tol) && prm->mirror_tol >= 0.0))
         return fail(ctx, GCB_EINVAL, "mirror_tol must be finite and >= 0");
     if (prm->arith != GCB_ARITH_EXACT && prm->arith != GCB_ARITH_FAST)
@@ -249,7 +251,7 @@ int reject_fast_arith(gcb_ctx* ctx, const gcb_params* prm) {
     return GCB_OK;
 }
 
-// the exact frame (curvature = 0, binary64), the gyration options other
+// the exact frame (binary64), the gyration options other
 // than a conserved mu and the mirror terms are served by gcb_push and
 // gcb_push_3d only, the check of the mirror terms (check_ok) by the pushes,
 // the production arithmetic (fast_ok) as reject_fast_arith says
@@ -879,9 +881,8 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     if ((rc = validate_params(ctx, prm))) return rc;
     if ((rc = validate_particles(ctx, p, prm))) return rc;
     if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
-    if (prm->frame == GCB_FRAME_EXACT && (prm->curvature != 0 || prm->form != GCB_FORM_F64))
-        return fail(ctx, GCB_EUNSUPPORTED,
-                    "the exact frame needs curvature = 0 and GCB_FORM_F64");
+    if (prm->frame == GCB_FRAME_EXACT && prm->form != GCB_FORM_F64)
+        return fail(ctx, GCB_EUNSUPPORTED, "the exact frame needs GCB_FORM_F64");
     if (prm->arith == GCB_ARITH_FAST && prm->form != GCB_FORM_F64)
         return fail(ctx, GCB_EUNSUPPORTED, "GCB_ARITH_FAST needs GCB_FORM_F64");
     if (!ctx->have_fields) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields was not called");
@@ -1298,9 +1299,8 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t 
     if (((uintptr_t)p->z | (uintptr_t)p->zp) & 7)
         return fail(ctx, GCB_EINVAL, "double arrays must be 8-byte aligned");
     if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
-    if (prm->frame == GCB_FRAME_EXACT && (prm->curvature != 0 || prm->form != GCB_FORM_F64))
-        return fail(ctx, GCB_EUNSUPPORTED,
-                    "the exact frame needs curvature = 0 and GCB_FORM_F64");
+    if (prm->frame == GCB_FRAME_EXACT && prm->form != GCB_FORM_F64)
+        return fail(ctx, GCB_EUNSUPPORTED, "the exact frame needs GCB_FORM_F64");
     if (!ctx->have_f3) return fail(ctx, GCB_ENOFIELDS, "gcb_load_fields_3d was not called");
     if (prm->form == GCB_FORM_F64 && ctx->dtype3 != GCB_F64)
         return fail(ctx, GCB_EINVAL, "GCB_FORM_F64 needs fields loaded as GCB_F64");

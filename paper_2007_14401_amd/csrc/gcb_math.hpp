@@ -102,8 +102,17 @@ struct Regs {
 
 template <typename R>
 struct Sample {
+    static constexpr bool kGradE = false;
     R E[3], B[3];
     R dBx[3], dBy[3];   // d B_i / dx, d B_i / dy
+};
+
+// A sample with the E gradients as well (the exact guiding-center frame with
+// curvature: b* depends on E): W differentiated on each E lattice too.
+template <typename R>
+struct SampleEG : Sample<R> {
+    static constexpr bool kGradE = true;
+    R dEx[3], dEy[3];   // d E_i / dx, d E_i / dy
 };
 
 // One component at grid coordinates (gx, gy) = (X/dx, Y/dy) with lattice
@@ -133,9 +142,9 @@ GCB_HD void interp_comp(const Acc& acc, int k, double gx, double gy,
 // The six components from four located 2x2 stencils (2D Yee lattice): the
 // same operations as interp_comp, with the floor/weight computations shared
 // by the components of one weight set.
-template <typename R, bool kGrad, class Loader>
+template <typename R, bool kGrad, class Loader, class S>
 GCB_HD void interp_yee(const Loader& ld, const R wx[2], const R wy[2],
-                                           const Consts<R>& K, Sample<R>& s) {
+                                           const Consts<R>& K, S& s) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const int set = kYeeSet[k];
@@ -148,6 +157,10 @@ GCB_HD void interp_yee(const Loader& ld, const R wx[2], const R wy[2],
         const R val = (((ax * ay) * f00 + (bx * ay) * f10) + (ax * by) * f01) + (bx * by) * f11;
         if (k < 3) {
             s.E[k] = val;
+            if constexpr (S::kGradE) {
+                s.dEx[k] = (ay * (f10 - f00) + by * (f11 - f01)) * K.inv_dx;
+                s.dEy[k] = (ax * (f01 - f00) + bx * (f11 - f10)) * K.inv_dy;
+            }
         } else {
             s.B[k - 3] = val;
             if (kGrad) {
@@ -158,19 +171,19 @@ GCB_HD void interp_yee(const Loader& ld, const R wx[2], const R wy[2],
     }
 }
 
-template <typename R, bool kGrad, typename T>
+template <typename R, bool kGrad, typename T, class S>
 GCB_HD void yee_fetch(const GlobalAcc<T>& acc, int ia, int ib, int ja,
                                           int jb, const R wx[2], const R wy[2],
-                                          const Consts<R>& K, Sample<R>& s) {
+                                          const Consts<R>& K, S& s) {
     typename GlobalAcc<T>::Loc g;
     acc.locate(ia, ib, ja, jb, g);
     interp_yee<R, kGrad>(GlobalLoad<T>{g}, wx, wy, K, s);
 }
 
-template <typename R, bool kGrad, typename T>
+template <typename R, bool kGrad, typename T, class S>
 GCB_HD void yee_fetch(const TileAcc<T>& acc, int ia, int ib, int ja,
                                           int jb, const R wx[2], const R wy[2],
-                                          const Consts<R>& K, Sample<R>& s) {
+                                          const Consts<R>& K, S& s) {
     int off[4];
     typename GlobalAcc<T>::Loc g;
     if (acc.locate(ia, ib, ja, jb, off, g))
@@ -180,9 +193,9 @@ GCB_HD void yee_fetch(const TileAcc<T>& acc, int ia, int ib, int ja,
 }
 
 // the gather at lattice coordinates (gx, gy) = (X/dx, Y/dy)
-template <typename R, bool kGrad, bool kYee, class Acc>
+template <typename R, bool kGrad, bool kYee, class Acc, class S>
 GCB_HD void gather_at(const Acc& acc, const PushConst& pc, const Consts<R>& K, double gx,
-                      double gy, Sample<R>& s) {
+                      double gy, S& s) {
     if constexpr (kYee) {
         // lattice coordinate minus the offset: offset 0 leaves it unchanged
         const double xb = gx - 0.5;
@@ -193,11 +206,17 @@ GCB_HD void gather_at(const Acc& acc, const PushConst& pc, const Consts<R>& K, d
         const R wy[2] = {(R)(gy - fya), (R)(yb - fyb)};
         yee_fetch<R, kGrad>(acc, (int)fxa, (int)fxb, (int)fya, (int)fyb, wx, wy, K, s);
     } else {
-        R d0, d1;
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            interp_comp<R, false>(acc, k, gx, gy, pc.stagger[k][0], pc.stagger[k][1], K,
-                                  s.E[k], d0, d1);
+        for (int k = 0; k < 3; ++k) {
+            if constexpr (S::kGradE) {
+                interp_comp<R, true>(acc, k, gx, gy, pc.stagger[k][0], pc.stagger[k][1], K,
+                                     s.E[k], s.dEx[k], s.dEy[k]);
+            } else {
+                R d0, d1;
+                interp_comp<R, false>(acc, k, gx, gy, pc.stagger[k][0], pc.stagger[k][1], K,
+                                      s.E[k], d0, d1);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k)
             interp_comp<R, kGrad>(acc, k + 3, gx, gy, pc.stagger[k + 3][0],
@@ -212,9 +231,9 @@ GCB_HD void gather_at(const Acc& acc, const PushConst& pc, const Consts<R>& K, d
 // more (a fixed-point iteration that ran away) has an all-NaN sample: it is
 // gathered at the origin instead, so that every node index stays a small
 // integer, and the values are replaced afterwards.
-template <typename R, bool kGrad, bool kYee, class Acc>
+template <typename R, bool kGrad, bool kYee, class Acc, class S>
 GCB_HD void gather(const Acc& acc, const PushConst& pc,
-                                       const Consts<R>& K, double X, double Y, Sample<R>& s) {
+                                       const Consts<R>& K, double X, double Y, S& s) {
     double gx = X * pc.inv_dx;
     double gy = Y * pc.inv_dy;
     const bool far = !(fabs(gx) < kFarLattice && fabs(gy) < kFarLattice);
@@ -231,6 +250,10 @@ GCB_HD void gather(const Acc& acc, const PushConst& pc,
             s.B[i] = q;
             s.dBx[i] = q;
             s.dBy[i] = q;
+            if constexpr (S::kGradE) {
+                s.dEx[i] = q;
+                s.dEy[i] = q;
+            }
         }
     }
 }
@@ -358,8 +381,9 @@ GCB_HD uint32_t local_from_sample(const Sample<R>& s, const Consts<R>& K, Local<
 // eta = 1/(B sqrt(Psi^2 E_perp^2/B^2 + 1)), b* = eta (Psi E_perp + B).
 // Fills L with b = b*, the exact v_E and kappa, and E_par = E'/kappa (the
 // parallel force in the moving frame, its clock slowed by kappa); the lab B
-// stays in L.B.  The curvature terms are not formed: this frame serves the
-// zero-curvature scheme (Sec. 2.2.1).
+// stays in L.B.  The curvature terms are left at zero here: the
+// zero-curvature scheme (Sec. 2.2.1) needs none, and local_exact_curv adds
+// them for the curvature scheme.
 template <typename R>
 GCB_HD uint32_t local_fields_exact(const R E[3], const R Bv[3], const Consts<R>& K,
                                    Local<R>& L) {
@@ -420,11 +444,147 @@ GCB_HD uint32_t local_fields_exact(const R E[3], const R Bv[3], const Consts<R>&
     return flags;
 }
 
+// A value with its derivatives along nd directions (forward-mode
+// differentiation): the gradient of b* is carried through the arithmetic of
+// the frame by the chain rule, one operation at a time.
+template <typename R, int nd>
+struct Dual {
+    R v;
+    R d[nd];
+};
+
+template <typename R, int nd>
+GCB_HD Dual<R, nd> dconst(R a) {
+    Dual<R, nd> r;
+    r.v = a;
+#pragma unroll
+    for (int j = 0; j < nd; ++j) r.d[j] = (R)0;
+    return r;
+}
+template <typename R, int nd>
+GCB_HD Dual<R, nd> operator+(const Dual<R, nd>& a, const Dual<R, nd>& b) {
+    Dual<R, nd> r;
+    r.v = a.v + b.v;
+#pragma unroll
+    for (int j = 0; j < nd; ++j) r.d[j] = a.d[j] + b.d[j];
+    return r;
+}
+template <typename R, int nd>
+GCB_HD Dual<R, nd> operator-(const Dual<R, nd>& a, const Dual<R, nd>& b) {
+    Dual<R, nd> r;
+    r.v = a.v - b.v;
+#pragma unroll
+    for (int j = 0; j < nd; ++j) r.d[j] = a.d[j] - b.d[j];
+    return r;
+}
+template <typename R, int nd>
+GCB_HD Dual<R, nd> operator*(const Dual<R, nd>& a, const Dual<R, nd>& b) {
+    Dual<R, nd> r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int j = 0; j < nd; ++j) r.d[j] = a.d[j] * b.v + a.v * b.d[j];
+    return r;
+}
+template <typename R, int nd>
+GCB_HD Dual<R, nd> operator*(R a, const Dual<R, nd>& b) {
+    Dual<R, nd> r;
+    r.v = a * b.v;
+#pragma unroll
+    for (int j = 0; j < nd; ++j) r.d[j] = a * b.d[j];
+    return r;
+}
+// (a/b)' = (a' - (a/b) b')/b
+template <typename R, int nd>
+GCB_HD Dual<R, nd> operator/(const Dual<R, nd>& a, const Dual<R, nd>& b) {
+    Dual<R, nd> r;
+    r.v = a.v / b.v;
+#pragma unroll
+    for (int j = 0; j < nd; ++j) r.d[j] = (a.d[j] - r.v * b.d[j]) / b.v;
+    return r;
+}
+// sqrt(a)' = a'/(2 sqrt(a)); a derivative of 0 where the root is 0 (the
+// frame takes the root of a clamped argument there)
+template <typename R, int nd>
+GCB_HD Dual<R, nd> dsqrt(const Dual<R, nd>& a) {
+    Dual<R, nd> r;
+    r.v = sqrt(a.v);
+    const R f = r.v > (R)0 ? (R)0.5 / r.v : (R)0;
+#pragma unroll
+    for (int j = 0; j < nd; ++j) r.d[j] = a.d[j] * f;
+    return r;
+}
+
+// b* of the exact frame (the operations of local_fields_exact, the same
+// selects) on values carrying their spatial derivatives: gives d_j b*_i.
+template <typename R, int nd>
+GCB_HD void bstar_dual(const Dual<R, nd> E[3], const Dual<R, nd> Bv[3], const Consts<R>& K,
+                       Dual<R, nd> b[3]) {
+    using D = Dual<R, nd>;
+    const D zero = dconst<R, nd>((R)0);
+    const D E2 = (E[0] * E[0] + E[1] * E[1]) + E[2] * E[2];
+    const D B2 = (Bv[0] * Bv[0] + Bv[1] * Bv[1]) + Bv[2] * Bv[2];
+    const D EB = (E[0] * Bv[0] + E[1] * Bv[1]) + E[2] * Bv[2];
+    const D S = E2 + B2;
+    const D B = dsqrt(B2);
+    const bool bzero = B.v == (R)0;
+    const D f = S.v == (R)0 ? zero : dconst<R, nd>(K.c) / S;
+    const D w[3] = {f * (E[1] * Bv[2] - E[2] * Bv[1]), f * (E[2] * Bv[0] - E[0] * Bv[2]),
+                    f * (E[0] * Bv[1] - E[1] * Bv[0])};
+    const D w2 = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
+    const D s_arg = dconst<R, nd>((R)1) - K.inv_c2 * ((R)4 * w2);
+    const D s = s_arg.v > (R)0 ? dsqrt(s_arg) : zero;
+    const D Bp2 = (R)0.5 * ((B2 - E2) + S * s);
+    const D Bp = Bp2.v > (R)0 ? dsqrt(Bp2) : zero;
+    const bool bpzero = Bp.v == (R)0;
+    const D Ep = bpzero ? zero : EB / Bp;
+    const D a = bzero ? zero : EB / B2;
+    const D ep[3] = {E[0] - a * Bv[0], E[1] - a * Bv[1], E[2] - a * Bv[2]};
+    const D Eperp2 = (ep[0] * ep[0] + ep[1] * ep[1]) + ep[2] * ep[2];
+    const D one = dconst<R, nd>((R)1);
+    const D Psi = bpzero ? zero : ((R)2 * Ep * B2) / ((Bp * S) * (one + s));
+    const D q = bzero ? zero : ((Psi * Psi) * Eperp2) / B2;
+    const D eta = bzero ? zero : one / (B * dsqrt(q + one));
+    const D xi = eta * Psi;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) b[i] = xi * ep[i] + eta * Bv[i];
+}
+
+// The exact frame with the curvature scheme (Sec. 2.2 with Sec. 2.2.2):
+// the values of local_fields_exact, and (b*.grad)b*, (v_E.grad)b*, A, C
+// from d_j b*, carried by forward-mode differentiation from the gather's E
+// and B gradients (2D: j = x, y).
+template <typename R>
+GCB_HD uint32_t local_exact_curv(const SampleEG<R>& s, const Consts<R>& K, Local<R>& L) {
+    const uint32_t flags = local_fields_exact(s.E, s.B, K, L);
+    Dual<R, 2> E[3], Bv[3], b[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        E[i].v = s.E[i];
+        E[i].d[0] = s.dEx[i];
+        E[i].d[1] = s.dEy[i];
+        Bv[i].v = s.B[i];
+        Bv[i].d[0] = s.dBx[i];
+        Bv[i].d[1] = s.dBy[i];
+    }
+    bstar_dual<R, 2>(E, Bv, K, b);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        L.bgb[i] = L.b[0] * b[i].d[0] + L.b[1] * b[i].d[1];
+        L.vgb[i] = L.vE[0] * b[i].d[0] + L.vE[1] * b[i].d[1];
+        L.gB[i] = (R)0;
+    }
+    curvature_scalars(L);
+    return flags;
+}
+
 // the local quantities of the guiding-center step in the chosen frame (any
-// sample type with E and B; the reduced frame's gradients come from it)
+// sample type with E and B; the reduced frame's gradients come from it, the
+// exact frame's curvature terms from a sample with the E gradients)
 template <bool kExact, typename R, class S>
 GCB_HD uint32_t local_in_frame(const S& s, const Consts<R>& K, Local<R>& L) {
-    if constexpr (kExact)
+    if constexpr (kExact && S::kGradE)
+        return local_exact_curv(s, K, L);
+    else if constexpr (kExact)
         return local_fields_exact(s.E, s.B, K, L);
     else
         return local_from_sample(s, K, L);
@@ -836,16 +996,20 @@ GCB_HD double nan_max(double a, double b) {
 
 // One guiding-center step.  sn is the gather (with gradients) at x^n.
 // Returns status flags; res receives |R^K - R^{K-1}|_inf.
-// kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only);
+// kExact: the exact frame of Sec. 2.2 (with kExCurv its curvature scheme);
 // kMirror: the mirror force and grad-B drift (curvature scheme only);
 // kPhase: the gyration phase advanced over the step (GYR_PHASE).
 template <typename R, bool kYee, bool kExact = false, bool kMirror = false, bool kPhase = false,
-          class Acc>
+          bool kExCurv = false, class Acc>
 GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
                                              const PushConst& pc, const Consts<R>& K,
                                              double& res) {
+    // kExCurv: the exact frame with the curvature scheme, whose gathers carry
+    // the E gradients
+    static_assert(!kExCurv || kExact, "kExCurv is a form of the exact frame");
+    using Smp = std::conditional_t<kExCurv, SampleEG<R>, Sample<R>>;
     uint32_t flags = 0;
-    const bool curv = !kExact && pc.curvature != 0;
+    const bool curv = kExCurv || (!kExact && pc.curvature != 0);
     // the mirror terms ride on the curvature scheme (the host refuses others)
     const bool mirror = kMirror && curv;
     const double x = r.x, y = r.y;
@@ -859,7 +1023,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     {
         const double Rhx = x - 0.5 * min_image_i<R>(x - r.xp, pc.Lx, pc.inv_Lx);
         const double Rhy = y - 0.5 * min_image_i<R>(y - r.yp, pc.Ly, pc.inv_Ly);
-        Sample<R> sh;
+        Smp sh;
         gather<R, true, kYee>(acc, pc, K, Rhx, Rhy, sh);
         Local<R> Lh;
         flags |= local_in_frame<kExact>(sh, K, Lh);
@@ -897,7 +1061,13 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     R upn, Fnx, Fny;
     {
         Local<R> Ln;
-        flags |= local_in_frame<kExact>(sn, K, Ln);
+        if constexpr (kExCurv) {
+            SampleEG<R> se;
+            gather<R, true, kYee>(acc, pc, K, x, y, se);
+            flags |= local_in_frame<kExact>(se, K, Ln);
+        } else {
+            flags |= local_in_frame<kExact>(sn, K, Ln);
+        }
         if (mirror)
             upn = mirror_parallel<2>(Ln, upar, gy, qm, K, flags);
         else
@@ -922,7 +1092,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
             Fkx = Fnx;
             Fky = Fny;
         } else {
-            Sample<R> sk;
+            Smp sk;
             gather<R, true, kYee>(acc, pc, K, Rx, Ry, sk);
             Local<R> Lk;
             flags |= local_in_frame<kExact>(sk, K, Lk);
@@ -941,7 +1111,7 @@ GCB_HD uint32_t gca_step(const Acc& acc, const Sample<R>& sn, Regs<R>& r,
     {
         const double Rmx = x + 0.5 * (Rx - x);
         const double Rmy = y + 0.5 * (Ry - y);
-        Sample<R> sm;
+        Smp sm;
         gather<R, true, kYee>(acc, pc, K, Rmx, Rmy, sm);
         Local<R> Lm;
         flags |= local_in_frame<kExact>(sm, K, Lm);

@@ -36,8 +36,16 @@ struct Regs3 {
 
 template <typename R>
 struct Sample3 {
+    static constexpr bool kGradE = false;
     R E[3], B[3];
     R dBx[3], dBy[3], dBz[3];   // d B_i / dx, dy, dz
+};
+
+// with the E gradients as well (the exact frame with curvature)
+template <typename R>
+struct SampleEG3 : Sample3<R> {
+    static constexpr bool kGradE = true;
+    R dEx[3], dEy[3], dEz[3];   // d E_i / dx, dy, dz
 };
 
 // ---------------------------------------------------------------------------
@@ -64,10 +72,15 @@ GCB_HD void trilerp(const R f[8], R wx, R wy, R wz, const Consts3<R>& K, bool gr
     }
 }
 
-template <typename R, bool kGrad>
-GCB_HD void store_comp(int k, R val, R ddx, R ddy, R ddz, Sample3<R>& s) {
+template <typename R, bool kGrad, class S>
+GCB_HD void store_comp(int k, R val, R ddx, R ddy, R ddz, S& s) {
     if (k < 3) {
         s.E[k] = val;
+        if constexpr (S::kGradE) {
+            s.dEx[k] = ddx;
+            s.dEy[k] = ddy;
+            s.dEz[k] = ddz;
+        }
     } else {
         s.B[k - 3] = val;
         if (kGrad) {
@@ -79,32 +92,32 @@ GCB_HD void store_comp(int k, R val, R ddx, R ddy, R ddz, Sample3<R>& s) {
 }
 
 // the six components from the located Yee stencils
-template <typename R, bool kGrad, class Loader>
+template <typename R, bool kGrad, class Loader, class S>
 GCB_HD void interp3_yee(const Loader& ld, const R wx[2], const R wy[2], const R wz[2],
-                        const Consts3<R>& K, Sample3<R>& s) {
+                        const Consts3<R>& K, S& s) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const int set = kYee3Set[k];
         R f[8];
         ld.template load8<R>(set, k, f);
         R val, ddx, ddy, ddz;
-        trilerp(f, wx[set & 1], wy[(set >> 1) & 1], wz[set >> 2], K, kGrad && k >= 3, val, ddx,
-                ddy, ddz);
+        trilerp(f, wx[set & 1], wy[(set >> 1) & 1], wz[set >> 2], K,
+                (kGrad && k >= 3) || S::kGradE, val, ddx, ddy, ddz);
         store_comp<R, kGrad>(k, val, ddx, ddy, ddz, s);
     }
 }
 
-template <typename R, bool kGrad, typename T>
+template <typename R, bool kGrad, typename T, class S>
 GCB_HD void yee3_fetch(const GlobalAcc3<T>& acc, const int fl[3][2], const R wx[2],
-                       const R wy[2], const R wz[2], const Consts3<R>& K, Sample3<R>& s) {
+                       const R wy[2], const R wz[2], const Consts3<R>& K, S& s) {
     typename GlobalAcc3<T>::Loc L;
     acc.locate(fl, L);
     interp3_yee<R, kGrad>(GlobalLoad3<T>{acc, L}, wx, wy, wz, K, s);
 }
 
-template <typename R, bool kGrad, typename T>
+template <typename R, bool kGrad, typename T, class S>
 GCB_HD void yee3_fetch(const TileAcc3<T>& acc, const int fl[3][2], const R wx[2],
-                       const R wy[2], const R wz[2], const Consts3<R>& K, Sample3<R>& s) {
+                       const R wy[2], const R wz[2], const Consts3<R>& K, S& s) {
     int off[8];
     typename GlobalAcc3<T>::Loc L;
     if (acc.locate(fl, off, L)) {
@@ -117,9 +130,9 @@ GCB_HD void yee3_fetch(const TileAcc3<T>& acc, const int fl[3][2], const R wx[2]
 }
 
 // the gather at lattice coordinates g = (X/dx, Y/dy, Z/dz)
-template <typename R, bool kGrad, bool kYee, class Acc>
+template <typename R, bool kGrad, bool kYee, class Acc, class S>
 GCB_HD void gather3_at(const Acc& acc, const PushConst3& pc, const Consts3<R>& K,
-                       const double g[3], Sample3<R>& s) {
+                       const double g[3], S& s) {
     if constexpr (kYee) {
         // lattice coordinate minus the offset: offset 0 leaves it unchanged
         int fl[3][2];
@@ -144,8 +157,8 @@ GCB_HD void gather3_at(const Acc& acc, const PushConst3& pc, const Consts3<R>& K
             R f[8];
             acc.template oct<R>(k, (int)fi, (int)fj, (int)fk, f);
             R val, ddx, ddy, ddz;
-            trilerp(f, (R)(xi - fi), (R)(eta - fj), (R)(zeta - fk), K, kGrad && k >= 3, val,
-                    ddx, ddy, ddz);
+            trilerp(f, (R)(xi - fi), (R)(eta - fj), (R)(zeta - fk), K,
+                    (kGrad && k >= 3) || S::kGradE, val, ddx, ddy, ddz);
             store_comp<R, kGrad>(k, val, ddx, ddy, ddz, s);
         }
     }
@@ -153,9 +166,9 @@ GCB_HD void gather3_at(const Acc& acc, const PushConst3& pc, const Consts3<R>& K
 
 // All six components at (X, Y, Z); B gradients when kGrad.  kYee: the 3D Yee
 // offsets.  Lattice coordinates and weights in binary64 from the positions.
-template <typename R, bool kGrad, bool kYee, class Acc>
+template <typename R, bool kGrad, bool kYee, class Acc, class S>
 GCB_HD void gather3(const Acc& acc, const PushConst3& pc, const Consts3<R>& K, double X,
-                    double Y, double Z, Sample3<R>& s) {
+                    double Y, double Z, S& s) {
     double g[3] = {X * pc.b.inv_dx, Y * pc.b.inv_dy, Z * pc.inv_dz};
     // a runaway point (lattice coordinate NaN or of magnitude kFarLattice or
     // more) is gathered at the origin and its sample replaced by NaN
@@ -172,6 +185,11 @@ GCB_HD void gather3(const Acc& acc, const PushConst3& pc, const Consts3<R>& K, d
             s.dBx[i] = q;
             s.dBy[i] = q;
             s.dBz[i] = q;
+            if constexpr (S::kGradE) {
+                s.dEx[i] = q;
+                s.dEy[i] = q;
+                s.dEz[i] = q;
+            }
         }
     }
 }
@@ -191,6 +209,34 @@ GCB_HD uint32_t local_from_sample(const Sample3<R>& s, const Consts<R>& K, Local
     for (int i = 0; i < 3; ++i) {
         L.bgb[i] = (L.b[0] * dbx[i] + L.b[1] * dby[i]) + L.b[2] * dbz[i];
         L.vgb[i] = (L.vE[0] * dbx[i] + L.vE[1] * dby[i]) + L.vE[2] * dbz[i];
+    }
+    curvature_scalars(L);
+    return flags;
+}
+
+// The exact frame with the curvature scheme in 3D: as the 2D
+// local_exact_curv, with d_j b* over j = x, y, z.
+template <typename R>
+GCB_HD uint32_t local_exact_curv(const SampleEG3<R>& s, const Consts<R>& K, Local<R>& L) {
+    const uint32_t flags = local_fields_exact(s.E, s.B, K, L);
+    Dual<R, 3> E[3], Bv[3], b[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        E[i].v = s.E[i];
+        E[i].d[0] = s.dEx[i];
+        E[i].d[1] = s.dEy[i];
+        E[i].d[2] = s.dEz[i];
+        Bv[i].v = s.B[i];
+        Bv[i].d[0] = s.dBx[i];
+        Bv[i].d[1] = s.dBy[i];
+        Bv[i].d[2] = s.dBz[i];
+    }
+    bstar_dual<R, 3>(E, Bv, K, b);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        L.bgb[i] = (L.b[0] * b[i].d[0] + L.b[1] * b[i].d[1]) + L.b[2] * b[i].d[2];
+        L.vgb[i] = (L.vE[0] * b[i].d[0] + L.vE[1] * b[i].d[1]) + L.vE[2] * b[i].d[2];
+        L.gB[i] = (R)0;
     }
     curvature_scalars(L);
     return flags;
@@ -239,14 +285,17 @@ GCB_HD void boris_step3(const Sample3<R>& s, Regs3<R>& r, const PushConst3& pc,
 // One guiding-center step (Sec. 2.2.1 / 2.2.2 inside the coupled step of
 // Sec. 3.1).  sn is the gather (with gradients) at x^n.  Returns status
 // flags; res receives |R^K - R^{K-1}|_inf over the three components.
-// kExact: the exact frame of Sec. 2.2 (zero-curvature scheme only);
+// kExact: the exact frame of Sec. 2.2 (with kExCurv its curvature scheme,
+// whose gathers carry the E gradients);
 // kMirror: the mirror force and grad-B drift (curvature scheme only).
 template <typename R, bool kYee, bool kExact = false, bool kMirror = false, bool kPhase = false,
-          class Acc>
+          bool kExCurv = false, class Acc>
 GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
                           const PushConst3& pc, const Consts3<R>& K, double& res) {
+    static_assert(!kExCurv || kExact, "kExCurv is a form of the exact frame");
+    using Smp = std::conditional_t<kExCurv, SampleEG3<R>, Sample3<R>>;
     uint32_t flags = 0;
-    const bool curv = !kExact && pc.b.curvature != 0;
+    const bool curv = kExCurv || (!kExact && pc.b.curvature != 0);
     // the mirror terms ride on the curvature scheme (the host refuses others)
     const bool mirror = kMirror && curv;
     const double x[3] = {r.x, r.y, r.z};
@@ -263,7 +312,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
         double Rh[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) Rh[a] = x[a] - 0.5 * min_image(x[a] - xprev[a], box[a]);
-        Sample3<R> sh;
+        Smp sh;
         gather3<R, true, kYee>(acc, pc, K, Rh[0], Rh[1], Rh[2], sh);
         Local<R> Lh;
         flags |= local_in_frame<kExact, R>(sh, K, Lh);
@@ -290,7 +339,13 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
     R upn, Fn[3];
     {
         Local<R> Ln;
-        flags |= local_in_frame<kExact, R>(sn, K, Ln);
+        if constexpr (kExCurv) {
+            SampleEG3<R> se;
+            gather3<R, true, kYee>(acc, pc, K, x[0], x[1], x[2], se);
+            flags |= local_in_frame<kExact, R>(se, K, Ln);
+        } else {
+            flags |= local_in_frame<kExact, R>(sn, K, Ln);
+        }
         if (mirror)
             upn = mirror_parallel<3>(Ln, upar, gy, qm, K, flags);
         else
@@ -309,7 +364,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
             Fk[1] = Fn[1];
             Fk[2] = Fn[2];
         } else {
-            Sample3<R> sk;
+            Smp sk;
             gather3<R, true, kYee>(acc, pc, K, Rp[0], Rp[1], Rp[2], sk);
             Local<R> Lk;
             flags |= local_in_frame<kExact, R>(sk, K, Lk);
@@ -332,7 +387,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
         double Rm[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) Rm[a] = x[a] + 0.5 * (Rp[a] - x[a]);
-        Sample3<R> sm;
+        Smp sm;
         gather3<R, true, kYee>(acc, pc, K, Rm[0], Rm[1], Rm[2], sm);
         Local<R> Lm;
         flags |= local_in_frame<kExact, R>(sm, K, Lm);

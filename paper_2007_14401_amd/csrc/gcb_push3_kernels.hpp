@@ -68,7 +68,8 @@ __device__ __forceinline__ uint32_t coupled_update3(const Acc& acc, bool gca, Re
     Sample3<R> s;
     if (gca) {
         gather3<R, true, kYee>(acc, pc, K, r.x, r.y, r.z, s);
-        fl = gca_step3<R, kYee, kVar == kVarExact, kVar == kVarMirror, kVar == kVarPhase>(
+        fl = gca_step3<R, kYee, var_exact(kVar), kVar == kVarMirror, kVar == kVarPhase,
+                       kVar == kVarExactCurv>(
             acc, s, r, pc, K, res);
     } else {
         gather3<R, false, kYee>(acc, pc, K, r.x, r.y, r.z, s);
@@ -259,6 +260,8 @@ hipError_t launch_push3(const Push3Launch& L, const ParticlePtrs3<R>& in,
                         const ParticlePtrs3<R>& out, const PushConst3& pc, hipStream_t stream) {
     if (L.n == 0) return hipSuccess;
     if constexpr (!kMixed<R>) {
+        if (L.exact && pc.b.curvature)
+            return launch_push3_frame<R, T, kMinWaves, kVarExactCurv>(L, in, out, pc, stream);
         if (L.exact) return launch_push3_frame<R, T, kMinWaves, kVarExact>(L, in, out, pc, stream);
     } else {
         if (L.exact) return hipErrorInvalidValue;

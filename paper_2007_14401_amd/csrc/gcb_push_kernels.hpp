@@ -108,8 +108,8 @@ __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Reg
     if (gca) {
         Sample<R> s;
         gather<R, true, kYee>(acc, pc, K, r.x, r.y, s);
-        fl = gca_step<R, kYee, kVar == kVarExact, kVar == kVarMirror, kVar == kVarPhase>(
-            acc, s, r, pc, K, res);
+        fl = gca_step<R, kYee, var_exact(kVar), kVar == kVarMirror, kVar == kVarPhase,
+                      kVar == kVarExactCurv>(acc, s, r, pc, K, res);
     } else {
         Sample<R> s;
         gather<R, false, kYee>(acc, pc, K, r.x, r.y, s);
@@ -301,8 +301,9 @@ k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __
                 }
                 double res = 0.0;
                 if (gca)
-                    fl |= gca_step<R, kYee, kVar == kVarExact, kVar == kVarMirror,
-                                   kVar == kVarPhase>(acc, smp, r, pc, K, res);
+                    fl |= gca_step<R, kYee, var_exact(kVar), kVar == kVarMirror,
+                                   kVar == kVarPhase, kVar == kVarExactCurv>(acc, smp, r, pc,
+                                                                             K, res);
                 else
                     boris_step(smp, r, pc, K);
                 fl |= finite_flag(r);
@@ -372,6 +373,8 @@ hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
                        const ParticlePtrs<R>& out, const PushConst& pc, hipStream_t stream) {
     if (L.n == 0) return hipSuccess;
     if constexpr (!kMixed<R>) {
+        if (L.exact && pc.curvature)
+            return launch_push_frame<R, T, kMinWaves, kVarExactCurv>(L, in, out, pc, stream);
         if (L.exact) return launch_push_frame<R, T, kMinWaves, kVarExact>(L, in, out, pc, stream);
     } else {
         if (L.exact) return hipErrorInvalidValue;

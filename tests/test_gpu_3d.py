@@ -422,3 +422,76 @@ def test_exact_frame_3d(kernel, sort_every, tile, steps):
         assert st["gca_steps"] > 0
     finally:
         run.close()
+
+
+def _particle_errors3(got, ref, cfg):
+    """Per-particle max relative error (floors one cell and c; minimum image)."""
+    err = None
+    for k, floor, L in (("x", cfg.dx, cfg.Lx), ("y", cfg.dy, cfg.Ly), ("z", cfg.dz, cfg.Lz),
+                        ("ux", cfg.c, None), ("uy", cfg.c, None), ("uz", cfg.c, None)):
+        a = np.asarray(got[k], dtype=np.float64)
+        b = getattr(ref, k).numpy()
+        d = np.abs(a - b)
+        if L is not None:
+            d = np.minimum(d, np.abs(L - d))
+        with np.errstate(invalid="ignore"):
+            r = d / np.maximum(np.abs(b), floor)
+        r = np.where((a == b) | (np.isnan(a) & np.isnan(b)), 0.0, r)
+        r = np.where(np.isnan(r), np.inf, r)
+        err = r if err is None else np.maximum(err, r)
+    return err
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(GLOBAL, 0, 0), (TILED, 2, 6)])
+def test_exact_frame_curvature_3d(kernel, sort_every, tile):
+    """The exact frame with the curvature scheme in 3D (gradient of b* along
+    x, y and z).  The kernel differentiates b* in forward mode, the oracle by
+    reverse-mode autograd: one step from identical states within 1e-12 with
+    identical switch decisions and status bits; 8 steps by the chaos-aware
+    protocol (each particle within 10x the deviation of the oracle nudged by
+    up to four units in the last place after every step, and the switch
+    decisions of every insensitive particle identical)."""
+    from paper_2007_14401_amd import gcb, state
+    from test_gpu_production import _nudge
+    cfg = make_config3("harris3d32", E_rec=0.5, guide=0.3, curvature=1)
+    F = cfg.fields()
+    run = GpuRun3(cfg, F)
+    try:
+        ens = cfg.particles(n=3000, seed_offset=6)
+        log(f"3d exact frame + curvature kernel={kernel}: one step")
+        t = _state(ens)
+        tr, st = run.push(t, 1, trace=True, stats=True, kernel=kernel, sort_every=sort_every,
+                          tile=tile, frame=gcb.GCB_FRAME_EXACT, curvature=1)
+        ref, rtr, _ = run_oracle3(cfg, F, ens, 1, trace=True, exact_frame=True, curvature=True)
+        _check(state.unsort(t), ref, cfg, "3d exact frame + curvature, one step", tr, rtr)
+        assert st["gca_steps"] > 0
+
+        steps = 8
+        log(f"3d exact frame + curvature kernel={kernel}: {steps} steps")
+        t = _state(ens)
+        tr, _ = run.push(t, steps, trace=True, kernel=kernel, sort_every=sort_every, tile=tile,
+                         frame=gcb.GCB_FRAME_EXACT, curvature=1)
+        ref, rtr, _ = run_oracle3(cfg, F, ens, steps, trace=True, exact_frame=True,
+                                  curvature=True)
+        prov = O.GridFields3(F, cfg.dx, cfg.dy, cfg.dz, cfg.stagger)
+        p = oracle_params3(cfg, exact_frame=True, curvature=True)
+        sens = None
+        for sd in (1, 2, 3):
+            rng = np.random.default_rng(sd)
+            s_ = O.State3.from_numpy(ens)
+            for _ in range(steps):
+                s_, _, _ = O.step3(prov, s_, p)
+                for k in ("x", "y", "z", "ux", "uy", "uz"):
+                    setattr(s_, k, _nudge(getattr(s_, k), rng))
+            e = _particle_errors3({k: getattr(s_, k).numpy() for k in
+                                   ("x", "y", "z", "ux", "uy", "uz")}, ref, cfg)
+            sens = e if sens is None else np.maximum(sens, e)
+        err = _particle_errors3(state.unsort(t), ref, cfg)
+        bound = np.maximum(TOL, 10.0 * sens)
+        calm = sens <= TOL
+        log(f"  {int((~calm).sum())} sensitive of {err.size}; GPU error median "
+            f"{np.median(err):.1e}, max {err.max():.1e}; over the bound {int((err > bound).sum())}")
+        assert not (err > bound).any()
+        assert np.count_nonzero(tr.cpu().numpy()[:, calm] != rtr.numpy()[:, calm]) == 0
+    finally:
+        run.close()

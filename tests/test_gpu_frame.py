@@ -1,11 +1,21 @@
 """Parity of the exact-frame option (Sec. 2.2: b*, exact v_E and kappa,
-du_par/dt = (q/m) E'/kappa; zero-curvature scheme) with the oracle (needs an
-MI355X).  Bar: the binary64 path of the parity tests, 1e-12 relative with
-identical switch decisions and status bits (bit-for-bit expected)."""
+du_par/dt = (q/m) E'/kappa) with the oracle (needs an MI355X).
+
+Zero-curvature scheme: the bar of the binary64 parity tests, 1e-12 relative
+with identical switch decisions and status bits (bit for bit expected).
+
+Curvature scheme (Sec. 2.2.2 with b* and its gradient): the kernel carries
+the gradient of b* by forward-mode differentiation, the oracle takes it by
+reverse-mode autograd, so the two agree to rounding, not bit for bit.  Bar:
+one step from identical states 1e-12 relative with identical switch
+decisions and status bits; many steps by the chaos-aware protocol of the
+production arithmetic (each particle within 10x the deviation of the oracle
+nudged by up to four units in the last place after every step)."""
 import numpy as np
 import pytest
 
 from gpu_util import GpuRun, log, rel_errors, run_oracle
+from test_gpu_production import chaos_aware_check, oracle_runs, particle_errors
 from workloads import make_config
 
 pytestmark = pytest.mark.gpu
@@ -71,7 +81,7 @@ def test_exact_frame_argument_checks(strong):
     t = state.to_device(cfg.particles(n=64), "cuda:0")
     with pytest.raises(gcb.GcbError) as e:
         gcb.gcb_push(run.ctx, gcb.particles(t), gcb.params(frame=gcb.GCB_FRAME_EXACT,
-                                                           curvature=1), 1)
+                                                           curvature=1, mirror=1), 1)
     assert e.value.code == gcb.GCB_EUNSUPPORTED
     with pytest.raises(gcb.GcbError) as e:
         gcb.gcb_push(run.ctx, gcb.particles(t), gcb.params(frame=7), 1)
@@ -82,3 +92,47 @@ def test_exact_frame_argument_checks(strong):
                                                             curvature=0,
                                                             form=gcb.GCB_FORM_MIXED), 1)
     assert e.value.code == gcb.GCB_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# the exact frame with the curvature scheme
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile,arith", [(1, 0, 0, 0), (2, 1, 16, 0),
+                                                          (1, 0, 0, 1), (2, 1, 16, 1)])
+def test_exact_frame_curvature_one_step(strong, kernel, sort_every, tile, arith):
+    from paper_2007_14401_amd import gcb, state
+    cfg, F, run = strong
+    ens = cfg.particles(n=4096 + 37)
+    log(f"exact frame + curvature one step kernel={kernel} arith={arith}")
+    t = state.to_device(ens, "cuda:0")
+    tr, st = run.push(t, 1, trace=True, stats=True, kernel=kernel, sort_every=sort_every,
+                      tile=tile, frame=gcb.GCB_FRAME_EXACT, curvature=1, arith=arith)
+    ref, rtr, _ = run_oracle(cfg, F, ens, 1, trace=True, exact_frame=True, curvature=True)
+    got = state.unsort(t)
+    err = particle_errors(got, ref, cfg)
+    log(f"  rel err median {np.median(err):.2e}, max {err.max():.2e}")
+    assert err.max() <= TOL
+    assert np.array_equal(tr.cpu().numpy(), rtr.numpy())
+    assert np.array_equal(got["status"] & ~np.uint8(32), ref.status.numpy())
+    assert st["gca_steps"] == int((rtr == 0).sum()) > 0
+    # the option changes the orbits against the zero-curvature exact frame
+    t0 = state.to_device(ens, "cuda:0")
+    run.push(t0, 1, kernel=kernel, sort_every=sort_every, tile=tile,
+             frame=gcb.GCB_FRAME_EXACT, curvature=0)
+    assert np.abs(state.unsort(t0)["ux"] - got["ux"]).max() > 1e-9
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(1, 0, 0), (2, 3, 16)])
+def test_exact_frame_curvature_multistep_chaos_aware(strong, kernel, sort_every, tile):
+    from paper_2007_14401_amd import gcb, state
+    cfg, F, run = strong
+    ens = cfg.particles(n=1500, seed_offset=5)
+    steps = 20
+    log(f"exact frame + curvature {steps} steps kernel={kernel}")
+    t = state.to_device(ens, "cuda:0")
+    tr, _ = run.push(t, steps, trace=True, kernel=kernel, sort_every=sort_every, tile=tile,
+                     frame=gcb.GCB_FRAME_EXACT, curvature=1)
+    ref, rtr, noisy = oracle_runs(cfg, F, ens, steps, exact_frame=True, curvature=True)
+    chaos_aware_check(state.unsort(t), tr.cpu().numpy(), ref, rtr, noisy, cfg,
+                      f"exact frame + curvature, {steps} steps")

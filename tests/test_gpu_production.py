@@ -70,10 +70,11 @@ def _nudge(t: torch.Tensor, rng) -> torch.Tensor:
     return torch.as_tensor(a)
 
 
-def oracle_runs(cfg, F, ens, steps, seeds=(1, 2, 3)):
+def oracle_runs(cfg, F, ens, steps, seeds=(1, 2, 3), **kw):
     """The oracle from the given start, and the same with x, y and u nudged by
-    up to ULPS units in the last place after every step (one run per seed)."""
-    p = oracle_params(cfg)
+    up to ULPS units in the last place after every step (one run per seed);
+    kw: oracle parameters besides those of the config."""
+    p = oracle_params(cfg, **kw)
     prov = O.GridFields(F, cfg.dx, cfg.dy, cfg.stagger)
     ref, tr, _ = O.push(prov, O.State.from_numpy(ens), p, steps, trace=True)
     noisy = []
