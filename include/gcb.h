@@ -222,6 +222,14 @@ typedef struct {
                             GCB_ARITH_FAST: gcb_push, gcb_push_noalloc and
                             gcb_push_gr with GCB_FORM_F64 only (else
                             GCB_EUNSUPPORTED) */
+    int32_t keep_order;  /* 1: with sort_every > 0 the particles are still cell-sorted
+                            (the tiled kernel works through each tile's particles) but
+                            every particle is written back to its own slot, so the
+                            arrays keep their order and a switch trace needs no ids
+                            (trace column = slot); the results are those of any other
+                            order.  0 (default): sorting permutes the arrays.  Values
+                            other than 0 and 1: GCB_EINVAL; gcb_push, gcb_push_noalloc
+                            and gcb_push_backward only (else GCB_EUNSUPPORTED) */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.

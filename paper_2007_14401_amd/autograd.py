@@ -20,8 +20,10 @@ fields loaded (a second forward on the same context ran in between, e.g. one
 of a finite-difference pair) loads its own again before recomputing.
 
 Argument marshalling and segment bookkeeping only: every step of the push and
-of its derivative runs in the library's kernels.  Sorting is not used here
-(the adjoint recomputes steps unsorted, with identical arithmetic).
+of its derivative runs in the library's kernels.  The 2D push sorts in place
+(gcb_params keep_order), so the arrays keep their order; the 3D push runs
+unsorted.  Forward and recomputation use the parity arithmetic, so they agree
+bit for bit whatever kernel runs them.
 """
 from __future__ import annotations
 
@@ -118,12 +120,13 @@ class GcbPush(torch.autograd.Function):
 def push(E, B, x, y, xp, yp, ux, uy, uz, qm, pctx, prm, n_steps, checkpoint=32):
     """Differentiable push; returns the final (x, y, xp, yp, ux, uy, uz).
 
-    The particles are not cell-sorted here (sort_every is forced to 0), so the
-    outputs stay in input order."""
+    The particles are cell-sorted every prm.sort_every steps (4 when it is 0)
+    in place (keep_order), so the tiled kernel does the work and the outputs
+    stay in input order; gcb_push_backward recomputes the same way."""
     prm = gcb.gcb_params.from_buffer_copy(prm)
-    prm.sort_every = 0
-    if prm.kernel == gcb.GCB_KERNEL_TILED:
-        prm.kernel = gcb.GCB_KERNEL_AUTO
+    if prm.sort_every <= 0:
+        prm.sort_every = 4
+    prm.keep_order = 1
     return GcbPush.apply(E, B, x, y, xp, yp, ux, uy, uz, qm, pctx, prm, int(n_steps),
                          int(checkpoint))
 
@@ -199,6 +202,7 @@ def push3(E, B, x, y, z, xp, yp, zp, ux, uy, uz, qm, pctx, prm, n_steps, checkpo
     in input order (no cell sort)."""
     prm = gcb.gcb_params.from_buffer_copy(prm)
     prm.sort_every = 0
+    prm.keep_order = 0
     if prm.kernel == gcb.GCB_KERNEL_TILED:
         prm.kernel = gcb.GCB_KERNEL_AUTO
     return GcbPush3.apply(E, B, x, y, z, xp, yp, zp, ux, uy, uz, qm, pctx, prm, int(n_steps),

@@ -119,6 +119,10 @@ struct ParticlePtrs {
     double* qm;      // may be null
     int32_t* id;     // may be null
     uint8_t* status;
+    // binary64 push, optional: the start state of every step of a launch,
+    // recorded for the adjoint (step s at rec + 7*n*s: arrays x, y, xp, yp,
+    // ux, uy, uz of n doubles, a particle at its trace column)
+    double* rec;
 };
 
 // 3D lattice: the constants of a 2D launch (physics, x and y geometry, the

@@ -238,6 +238,8 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
         return fail(ctx, GCB_EINVAL, "mirror_tol must be finite and >= 0");
     if (prm->arith != GCB_ARITH_EXACT && prm->arith != GCB_ARITH_FAST)
         return fail(ctx, GCB_EINVAL, "unknown arith %d", prm->arith);
+    if (prm->keep_order != 0 && prm->keep_order != 1)
+        return fail(ctx, GCB_EINVAL, "keep_order must be 0 or 1");
     return GCB_OK;
 }
 
@@ -297,7 +299,7 @@ int validate_particles(gcb_ctx* ctx, const gcb_particles* p, const gcb_params* p
 
 template <typename U>
 ParticlePtrs<U> ptrs_of(const gcb_particles* p) {
-    ParticlePtrs<U> r;
+    ParticlePtrs<U> r{};
     r.x = p->x;
     r.y = p->y;
     r.xp = p->xp;
@@ -603,9 +605,12 @@ int choose_kind(gcb_ctx* ctx, const gcb_params* prm, bool tiled_ok, int window,
     return GCB_OK;
 }
 
+// record (binary64, keep_order or no sorting): the start state of every
+// step, 7 arrays of n doubles per step (the adjoint's recomputation)
 template <typename U>
 int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_steps,
-             uint8_t* s_trace, DevStats* dstats, hipStream_t stream) {
+             uint8_t* s_trace, DevStats* dstats, hipStream_t stream,
+             double* record = nullptr) {
     const int64_t n = p->n;
     const PushConst pc = make_const(ctx, prm);
     const TileGeom g = make_geom(ctx, prm);
@@ -618,9 +623,13 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     ParticlePtrs<U> user = ptrs_of<U>(p);
     ParticlePtrs<U> scr{};
     SortBuffers sb{};
-    if (prm->sort_every > 0 && n > 0) {
+    // keep_order: the tiled kernel works through the tiles of each sort in
+    // place (the arrays keep their order); the global kernel needs no sort
+    const bool keep = prm->keep_order != 0;
+    const bool sorting = prm->sort_every > 0 && n > 0 && !(keep && kind == PushKind::Global);
+    if (sorting) {
         if ((rc = prepare_sort(ctx, n, g.ntx * g.nty, sb))) return rc;
-        if ((rc = scratch_state<U>(ctx, user, n, scr))) return rc;
+        if (!keep && (rc = scratch_state<U>(ctx, user, n, scr))) return rc;
     }
     // all scratch is in place: the first device work of the call
     if ((rc = stats_zero(ctx, dstats, stream))) return rc;
@@ -635,16 +644,20 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
     for (int32_t step = 0; step < n_steps;) {
         int32_t ns = std::min(kind == PushKind::Global ? kGlobalStepsPerLaunch : kTiledMaxSteps,
                               n_steps - step);
-        if (prm->sort_every > 0) ns = std::min(ns, prm->sort_every - step % prm->sort_every);
+        if (sorting) ns = std::min(ns, prm->sort_every - step % prm->sort_every);
         ParticlePtrs<U> dst = cur;
         const uint32_t* perm = nullptr;
-        if (prm->sort_every > 0 && n > 0 && step % prm->sort_every == 0) {
+        if (sorting && step % prm->sort_every == 0) {
             Timer t(ctx, stream, GCB_TIMER_SORT);
             GCB_HIP(launch_cell_sort(cur.x, cur.y, n, pc.inv_dx, pc.inv_dy, g, sb, stream));
             t.done();
             perm = sb.idx;
-            dst = other;
+            if (!keep) dst = other;
         }
+        // in place, the sort's permutation serves every launch until the next
+        if (sorting && keep) perm = sb.idx;
+        cur.rec = record ? record + (size_t)step * 7 * n : nullptr;
+        dst.rec = cur.rec;
         PushLaunch L;
         L.perm = perm;
         L.kind = kind;
@@ -670,7 +683,7 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         if (e != hipSuccess)
             return fail(ctx, GCB_EHIP, "push kernel launch failed: %s", hipGetErrorString(e));
         t.done();
-        if (perm) std::swap(cur, other);
+        if (perm && !keep) std::swap(cur, other);
         step += ns;
     }
     if (cur.x != user.x) {
@@ -683,7 +696,7 @@ int run_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
 
 template <typename U>
 ParticlePtrs3<U> ptrs3_of(const gcb_particles3* p) {
-    ParticlePtrs3<U> r;
+    ParticlePtrs3<U> r{};
     r.b.x = p->x;
     r.b.y = p->y;
     r.b.xp = p->xp;
@@ -890,7 +903,7 @@ int gcb_push(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm, int32_t n_st
         return fail(ctx, GCB_EINVAL, "GCB_FORM_F64 needs fields loaded as GCB_F64");
     if (prm->form == GCB_FORM_MIXED && ctx->dtype != GCB_F32)
         return fail(ctx, GCB_EINVAL, "GCB_FORM_MIXED needs fields loaded as GCB_F32");
-    if (s_trace && p->n > 0 && !p->id && prm->sort_every > 0)
+    if (s_trace && p->n > 0 && !p->id && prm->sort_every > 0 && !prm->keep_order)
         return fail(ctx, GCB_EINVAL, "a switch trace with sorting needs particle ids");
     if (prm->replay && !s_trace && p->n > 0 && n_steps > 0)
         return fail(ctx, GCB_EINVAL, "replay needs the switch trace s_trace");
@@ -987,7 +1000,7 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
                                    stream));
         GCB_HIP(hipMemsetAsync(wstatus, 0, (size_t)n, stream));
     }
-    ParticlePtrs<double> w;
+    ParticlePtrs<double> w{};
     w.x = work;
     w.y = work + n;
     w.xp = work + 2 * n;
@@ -999,21 +1012,22 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
     w.id = nullptr;
     w.status = wstatus;
     const PushConst pc = make_const(ctx, prm);
-    // forward recomputation, keeping each step's start state and decisions
-    for (int32_t s = 0; s < n_steps && n > 0; ++s) {
-        GCB_HIP(hipMemcpyAsync(states + (size_t)s * 7 * n, work, 7 * nd,
-                               hipMemcpyDeviceToDevice, stream));
-        PushLaunch L;
-        L.kind = PushKind::Global;
-        L.yee = ctx->yee;
-        L.fields = ctx->fields.ptr;
-        L.n = n;
-        L.tile_start = nullptr;
-        L.geom = TileGeom{};
-        L.trace = trace + (size_t)s * n;
-        L.replay = false;
-        L.stats = nullptr;
-        GCB_HIP(launch_push_f64(L, w, w, pc, stream));
+    // forward recomputation, keeping each step's start state and decisions:
+    // the push of the segment in place (keep_order; with sort_every > 0 the
+    // tiled kernel), which records the start state of every step inside its
+    // launches.  The parity arithmetic makes it the forward pass bit for bit,
+    // whichever kernel ran that.
+    if (n > 0 && n_steps > 0) {
+        gcb_params rp = *prm;
+        rp.keep_order = 1;
+        rp.replay = 0;
+        gcb_particles wp{n, w.x, w.y, w.xp, w.yp, w.ux, w.uy, w.uz, start->qm, nullptr,
+                         wstatus};
+        const bool timing = ctx->timing;   // timed as part of the backward pass
+        ctx->timing = false;
+        rc = run_push<double>(ctx, &wp, &rp, n_steps, trace, nullptr, stream, states);
+        ctx->timing = timing;
+        if (rc) return rc;
     }
     // per-step guiding-center lists, so that their reverse kernel runs full
     // wavefronts
@@ -1132,6 +1146,8 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
         const int rc = reject_push_options(ctx, prm, true, true);
         if (rc) return rc;
     }
+    if (prm->keep_order != 0)
+        return fail(ctx, GCB_EUNSUPPORTED, "keep_order is served by gcb_push only");
     if (p->n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");
     if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
     if (p->n > 0 && (!p->r || !p->th || !p->ph || !p->ur || !p->uth || !p->uph || !p->status))
@@ -1290,6 +1306,8 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t 
     int rc;
     if ((rc = validate_params(ctx, prm))) return rc;
     if ((rc = reject_fast_arith(ctx, prm))) return rc;
+    if (prm->keep_order != 0)
+        return fail(ctx, GCB_EUNSUPPORTED, "keep_order is served by gcb_push only");
     // the 2D checks on the x, y, u, qm, id and status arrays, then z
     gcb_particles view{p->n, p->x, p->y, p->xp, p->yp, p->ux, p->uy, p->uz, p->qm, p->id,
                        p->status};
@@ -1389,7 +1407,7 @@ int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_pa
                                    stream));
         GCB_HIP(hipMemsetAsync(wstatus, 0, (size_t)n, stream));
     }
-    ParticlePtrs3<double> w;
+    ParticlePtrs3<double> w{};
     w.b.x = work;
     w.b.y = work + n;
     w.z = work + 2 * n;

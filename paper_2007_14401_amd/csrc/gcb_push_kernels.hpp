@@ -5,6 +5,10 @@
 // and write slot p of `out`: on the step of a cell sort, perm is the sort's
 // permutation and the push moves the state into tile order on the way (no
 // separate permutation pass; `in` and `out` are then different buffers).
+// The tiled kernel given a permutation with `out` equal to `in` keeps the
+// order instead: it works through the tiles in the permutation's order and
+// writes each particle back to the slot it was read from (gcb_params
+// keep_order).
 //
 // k_push_global: one lane per particle, any particle order, gathers through
 //   the cache hierarchy from the node-interleaved field array.
@@ -77,6 +81,19 @@ __device__ __forceinline__ void load_particle(const ParticlePtrs<R>& in, int64_t
     r.qm = in.qm ? in.qm[p] : qm_default;
 }
 
+// the start state of a step for the adjoint: slot i of the step's records
+template <typename R>
+__device__ __forceinline__ void record_state(double* rec, int64_t n, int64_t i,
+                                             const Regs<R>& r) {
+    rec[i] = r.x;
+    rec[n + i] = r.y;
+    rec[2 * n + i] = r.xp;
+    rec[3 * n + i] = r.yp;
+    rec[4 * n + i] = (double)r.ux;
+    rec[5 * n + i] = (double)r.uy;
+    rec[6 * n + i] = (double)r.uz;
+}
+
 template <typename R>
 __device__ __forceinline__ void store_particle(const ParticlePtrs<R>& in,
                                                const ParticlePtrs<R>& out, int64_t p,
@@ -120,7 +137,7 @@ __device__ __forceinline__ uint32_t coupled_update(const Acc& acc, bool gca, Reg
 
 // ns steps of one particle per lane (the particle stays in registers between
 // them); trace (per step n bytes) is indexed by id when ids are present
-template <typename R, typename T, bool kYee, int kVar>
+template <typename R, typename T, bool kYee, int kVar, bool kRec = false>
 __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, ParticlePtrs<R> out,
                                                       const uint32_t* __restrict__ perm,
                                                       int64_t n, int ns, const T* __restrict__ F,
@@ -140,6 +157,7 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
         uint32_t fl = 0;
         for (int s = 0; s < ns; ++s) {
             uint8_t* tr = trace ? trace + (size_t)s * n : nullptr;
+            if constexpr (kRec) record_state(in.rec + (int64_t)s * 7 * n, n, ti, r);
             bool gca;
             if (replay) {
                 gca = tr[ti] == 0;
@@ -175,7 +193,7 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
 // the gather at x^n that the update uses.  Particles seldom change branch
 // between two sorts, so the wavefronts mostly stay on one branch; one that
 // holds both takes both, with the same results.
-template <typename R, typename T, bool kYee, int kMinWaves, int kVar>
+template <typename R, typename T, bool kYee, int kMinWaves, int kVar, bool kRec = false>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __restrict__ perm,
              const int32_t* __restrict__ tile_start, TileGeom g, int chunk,
@@ -276,13 +294,16 @@ k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __
         if (t < m) {
             const int64_t p = base + queue[t];
             const int64_t src = perm ? (int64_t)perm[p] : p;
-            const int64_t tid = in.id ? (int64_t)in.id[src] : p;   // trace column
+            const bool keep = perm && out.x == in.x;
+            const int64_t slot = keep ? src : p;   // where the particle is written
+            const int64_t tid = in.id ? (int64_t)in.id[src] : slot;   // trace column
             Regs<R> r;
             load_particle(in, src, pc.qm, r);
             uint32_t fl = 0;
             bool gca = t < nG;
             for (int s = 0; s < steps; ++s) {
                 uint8_t* tr = trace ? trace + (int64_t)s * n : nullptr;
+                if constexpr (kRec) record_state(in.rec + (int64_t)s * 7 * n, n, tid, r);
                 // the gather at x^n serves the switch and the update; the
                 // gradients are formed for the branch of the previous step
                 const bool prev = gca;
@@ -319,14 +340,14 @@ k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __
                     ++cnt_b;
                 }
             }
-            store_particle(in, out, p, src, r, fl);
+            store_particle(in, out, slot, src, r, fl);
         }
         __syncthreads();   // the queue is rebuilt for the next chunk
     }
     if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
 }
 
-template <typename R, typename T, int kMinWaves, int kVar>
+template <typename R, typename T, int kMinWaves, int kVar, bool kRec = false>
 hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
                              const ParticlePtrs<R>& out, const PushConst& pc,
                              hipStream_t stream) {
@@ -335,11 +356,12 @@ hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
         const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
         const int ns = L.steps > 0 ? L.steps : 1;
         if (L.yee)
-            hipLaunchKernelGGL((k_push_global<R, T, true, kVar>), dim3(blocks), dim3(kWG), 0,
+            hipLaunchKernelGGL((k_push_global<R, T, true, kVar, kRec>), dim3(blocks), dim3(kWG), 0,
                                stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
                                L.stats);
         else
-            hipLaunchKernelGGL((k_push_global<R, T, false, kVar>), dim3(blocks), dim3(kWG), 0,
+            hipLaunchKernelGGL((k_push_global<R, T, false, kVar, kRec>), dim3(blocks), dim3(kWG),
+                               0,
                                stream, in, out, L.perm, L.n, ns, F, pc, L.trace, L.replay,
                                L.stats);
         return hipGetLastError();
@@ -349,14 +371,14 @@ hipError_t launch_push_frame(const PushLaunch& L, const ParticlePtrs<R>& in,
     const int ns = L.steps > 0 ? L.steps : 1;
     const size_t lds = tiled_lds_bytes(L.geom.window, sizeof(T));
     if (L.yee) {
-        auto kfn = k_push_tiled<R, T, true, kMinWaves, kVar>;
+        auto kfn = k_push_tiled<R, T, true, kMinWaves, kVar, kRec>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.n, ns, L.replay,
                            L.stats);
     } else {
-        auto kfn = k_push_tiled<R, T, false, kMinWaves, kVar>;
+        auto kfn = k_push_tiled<R, T, false, kMinWaves, kVar, kRec>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
@@ -372,6 +394,17 @@ template <typename R, typename T, int kMinWaves>
 hipError_t launch_push(const PushLaunch& L, const ParticlePtrs<R>& in,
                        const ParticlePtrs<R>& out, const PushConst& pc, hipStream_t stream) {
     if (L.n == 0) return hipSuccess;
+    // start-state records (the adjoint's recomputation): instances of their
+    // own, in the binary64 parity arithmetic with the paper's reduced frame
+    // only (the adjoint's scope)
+    if (in.rec) {
+        if constexpr (!kMixed<R> && GCB_FAST_ARITH == 0) {
+            if (L.exact || L.mirror || L.phase) return hipErrorInvalidValue;
+            return launch_push_frame<R, T, kMinWaves, kVarReduced, true>(L, in, out, pc, stream);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if constexpr (!kMixed<R>) {
         if (L.exact && pc.curvature)
             return launch_push_frame<R, T, kMinWaves, kVarExactCurv>(L, in, out, pc, stream);

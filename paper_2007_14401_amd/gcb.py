@@ -61,7 +61,8 @@ class gcb_params(C.Structure):
                 ("curvature", C.c_int32), ("n_iter", C.c_int32), ("form", C.c_int32),
                 ("sort_every", C.c_int32), ("kernel", C.c_int32), ("tile", C.c_int32),
                 ("replay", C.c_int32), ("frame", C.c_int32), ("gyration", C.c_int32),
-                ("mirror", C.c_int32), ("mirror_tol", C.c_double), ("arith", C.c_int32)]
+                ("mirror", C.c_int32), ("mirror_tol", C.c_double), ("arith", C.c_int32),
+                ("keep_order", C.c_int32)]
 
 
 class gcb_particles(C.Structure):
@@ -235,14 +236,14 @@ def params(dt=1.0, c=0.45, qm=-1.0, f_rho=0.4, f_E=1.0, fp_tol=1e-7, curvature=1
            n_iter=4, form=GCB_FORM_F64, sort_every=0, kernel=GCB_KERNEL_AUTO,
            tile=0, replay=0, frame=GCB_FRAME_REDUCED,
            gyration=GCB_GYRATION_MU, mirror=0, mirror_tol=0.0,
-           arith=GCB_ARITH_EXACT) -> gcb_params:
+           arith=GCB_ARITH_EXACT, keep_order=0) -> gcb_params:
     p = gcb_params()
     p.dt, p.c, p.qm, p.f_rho, p.f_E, p.fp_tol = dt, c, qm, f_rho, f_E, fp_tol
     p.curvature, p.n_iter, p.form = int(curvature), int(n_iter), int(form)
     p.sort_every, p.kernel, p.tile = int(sort_every), int(kernel), int(tile)
     p.replay, p.frame, p.gyration = int(replay), int(frame), int(gyration)
     p.mirror, p.mirror_tol = int(mirror), float(mirror_tol)
-    p.arith = int(arith)
+    p.arith, p.keep_order = int(arith), int(keep_order)
     return p
 
 

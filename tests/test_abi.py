@@ -64,7 +64,7 @@ def test_create_without_gpu_fails_cleanly():
 def test_params_struct_layout_matches_header():
     """ctypes mirrors of the C structs have the sizes the header implies."""
     from paper_2007_14401_amd import gcb
-    assert C.sizeof(gcb.gcb_params) == 6 * 8 + 10 * 4 + 8 + 8   # arith + padding
+    assert C.sizeof(gcb.gcb_params) == 6 * 8 + 10 * 4 + 8 + 4 + 4   # arith, keep_order
     assert C.sizeof(gcb.gcb_particles) == 8 + 10 * 8
     assert C.sizeof(gcb.gcb_grid_desc) == 4 + 4 + 8 + 8 + 96 + 8
     assert C.sizeof(gcb.gcb_stats) == 5 * 8 + 8 * 8

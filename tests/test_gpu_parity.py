@@ -360,3 +360,23 @@ def test_non_default_stream(h64):
     s.synchronize()
     for k in ("x", "y", "ux", "uy", "uz", "status", "id"):
         assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile,steps", [(2, 4, 16, 12), (2, 3, 8, 7),
+                                                          (1, 4, 0, 6), (0, 1, 16, 3)])
+def test_keep_order(h64, kernel, sort_every, tile, steps):
+    """keep_order: the particles are cell-sorted and pushed tile by tile, but
+    every one is written back to its own slot, so the arrays keep their order
+    and the switch trace is in slot order without ids.  The state and the
+    trace equal the oracle's in input order, bit for bit."""
+    cfg, F, run = h64
+    ens = cfg.particles(n=4096 + 37, seed_offset=11)
+    log(f"keep_order kernel={kernel} sort_every={sort_every} tile={tile} steps={steps}")
+    t = _state(ens, with_id=False)
+    tr, st = run.push(t, steps, trace=True, stats=True, kernel=kernel, sort_every=sort_every,
+                      tile=tile, keep_order=1)
+    ref, rtr, rres = run_oracle(cfg, F, ens, steps, trace=True)
+    got = {k: v.cpu().numpy() for k, v in t.items() if v is not None}
+    _check(got, ref, cfg, "keep_order", tr, rtr)
+    assert st["gca_steps"] == int((rtr == 0).sum())
+    assert st["max_fp_residual"] == float(rres.max())
