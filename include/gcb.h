@@ -313,6 +313,18 @@ int gcb_kinetic_energy(gcb_ctx* ctx, const gcb_particles* p,
                        const gcb_params* prm, double* out,
                        double* const lam_u[3], void* stream);
 
+/* The library's binary64 sin and cos, the ones the curved-spacetime metric
+   takes of theta (Sec. 2.3) and the gyro-phase option of the phase advance
+   (Sec. 3.1): Cody-Waite reduction by pi/2 (two-part constant, exact
+   multiples for |x| < 1.6e6) and Taylor polynomials of degree 19 and 20 on
+   [-pi/4, pi/4], within two units in the last place of the correctly rounded
+   values away from their zeros, for |x| <= 1e5 at least.  x, s and c are
+   device arrays of n doubles on the context's device (s[i] = sin x[i],
+   c[i] = cos x[i]); caller-owned; enqueued on `stream`.  n < 0 or NULL
+   arrays with n > 0: GCB_EINVAL. */
+int gcb_sincos(gcb_ctx* ctx, const double* x, double* s, double* c, int64_t n,
+               void* stream);
+
 /* ---------------------------------------------------------------------------
    Curved spacetime (Sec. 2.3, 2.4, 3.2): the coupled scheme in Kerr
    spacetime (M = 1, spin a) in spherical Kerr-Schild coordinates, geometrized

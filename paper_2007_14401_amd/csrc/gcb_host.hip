@@ -1507,6 +1507,16 @@ int gcb_kinetic_energy(gcb_ctx* ctx, const gcb_particles* p, const gcb_params* p
     return GCB_OK;
 }
 
+int gcb_sincos(gcb_ctx* ctx, const double* x, double* s, double* c, int64_t n,
+               void* stream_) {
+    if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");
+    if (n > 0 && (!x || !s || !c)) return fail(ctx, GCB_EINVAL, "x, s and c must be non-NULL");
+    GCB_HIP(hipSetDevice(ctx->device));
+    GCB_HIP(launch_sincos(x, s, c, n, static_cast<hipStream_t>(stream_)));
+    return GCB_OK;
+}
+
 int gcb_set_timing(gcb_ctx* ctx, int32_t enabled) {
     if (!ctx) return fail(nullptr, GCB_EINVAL, "ctx is NULL");
     for (auto& l : ctx->launches) {

@@ -148,6 +148,10 @@ hipError_t launch_count_flagged(const uint8_t* status, int64_t n,
 // zero `words` 8-byte words at p (8-byte aligned) with a kernel
 hipError_t launch_zero_words(void* p, int64_t words, hipStream_t stream);
 
+// the library's binary64 sin and cos of n values (device arrays)
+hipError_t launch_sincos(const double* x, double* s, double* c, int64_t n,
+                         hipStream_t stream);
+
 // ---------------------------------------------------------------------------
 // adjoint
 

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gcb_internal.h"
+#include "gcb_trig.hpp"
 
 namespace gcb {
 namespace {
@@ -104,7 +105,28 @@ __global__ __launch_bounds__(kWG) void k_zero_words(unsigned long long* p, int64
     if (i < n) p[i] = 0ull;
 }
 
+// the library's sin and cos (the curved-spacetime metric's and the gyro-phase
+// option's), binary64, this unit compiled without contraction like those
+// instances of the parity arithmetic
+__global__ __launch_bounds__(kWG) void k_sincos(const double* __restrict__ x, double* s,
+                                                double* c, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= n) return;
+    double sn, cs;
+    sincos_poly<double>(x[i], sn, cs);
+    s[i] = sn;
+    c[i] = cs;
+}
+
 }  // namespace
+
+hipError_t launch_sincos(const double* x, double* s, double* c, int64_t n,
+                         hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n + kWG - 1) / kWG);
+    hipLaunchKernelGGL(k_sincos, dim3(blocks), dim3(kWG), 0, stream, x, s, c, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_zero_words(void* p, int64_t words, hipStream_t stream) {
     if (words <= 0) return hipSuccess;

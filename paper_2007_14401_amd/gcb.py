@@ -133,6 +133,7 @@ def _load():
         "gcb_push_backward_3d": (C.c_int, [P, C.POINTER(gcb_particles3), C.POINTER(gcb_params),
                                            C.c_int32, C.POINTER(P * 9), C.POINTER(P * 9),
                                            C.POINTER(P * 3), C.POINTER(P * 3), P]),
+        "gcb_sincos": (C.c_int, [P, P, P, P, C.c_int64, P]),
         "gcb_set_timing": (C.c_int, [P, C.c_int32]),
         "gcb_get_timing": (C.c_int, [P, C.POINTER(C.c_double * GCB_NTIMERS),
                                      C.POINTER(C.c_int64 * GCB_NTIMERS)]),
@@ -148,7 +149,7 @@ _lib = _load()
 EXPORTED = ("gcb_create", "gcb_destroy", "gcb_last_error", "gcb_load_fields", "gcb_push",
             "gcb_push_backward", "gcb_kinetic_energy", "gcb_set_timing", "gcb_get_timing",
             "gcb_load_fields_gr", "gcb_push_gr", "gcb_load_fields_3d", "gcb_push_3d",
-            "gcb_push_backward_3d", "gcb_push_noalloc")
+            "gcb_push_backward_3d", "gcb_push_noalloc", "gcb_sincos")
 
 
 def lib():
@@ -294,6 +295,12 @@ def gcb_push_backward(ctx, start: gcb_particles, prm: gcb_params, n_steps: int, 
     _check(_lib.gcb_push_backward(ctx, C.byref(start), C.byref(prm), int(n_steps),
                                   C.byref(le), C.byref(ls), C.byref(de), C.byref(db),
                                   _stream_ptr(stream)), ctx)
+
+
+def gcb_sincos(ctx, x, s, c, stream=None):
+    """s = sin x, c = cos x by the library's binary64 sin/cos (device tensors)."""
+    _check(_lib.gcb_sincos(ctx, _ptr(x), _ptr(s), _ptr(c), int(x.numel()),
+                           _stream_ptr(stream)), ctx)
 
 
 def gcb_kinetic_energy(ctx, parts: gcb_particles, prm: gcb_params, out, lam_u=None,

@@ -106,3 +106,9 @@ def test_ctypes_mirrors_match_the_c_compiler(tmp_path):
         assert got[(name, "size")] == C.sizeof(st), name
         for f in st._fields_:
             assert got[(name, f[0])] == getattr(st, f[0]).offset, (name, f[0])
+
+
+def test_sincos_rejects_bad_arguments_without_device():
+    from paper_2007_14401_amd import gcb
+    lib = gcb.lib()
+    assert lib.gcb_sincos(None, None, None, None, 4, None) == gcb.GCB_EINVAL
