@@ -230,8 +230,8 @@ def main():
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--d3-steps", type=int, default=40)
     ap.add_argument("--d3-warmup", type=int, default=4)
-    ap.add_argument("--d3-sort-every", type=int, default=2)
-    ap.add_argument("--d3-tile", type=int, default=6)
+    ap.add_argument("--d3-sort-every", type=int, default=4)
+    ap.add_argument("--d3-tile", type=int, default=4)
     ap.add_argument("--d3-kernel", type=int, default=0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -474,9 +474,10 @@ def main():
             gcb.gcb_destroy(ctx)
             torch.cuda.empty_cache()
 
-    def time_3d(steps: int, warmup: int, mixed: bool = False):
+    def time_3d(steps: int, warmup: int, mixed: bool = False, arith=None):
         """3D push: 128^3 periodic double Harris sheet with oblique tearing,
-        1e7 particles (the workload's own size), binary64 or the mixed form."""
+        1e7 particles (the workload's own size), binary64 (production
+        arithmetic unless `arith` says otherwise) or the mixed form."""
         from workloads import make_config3
         c3 = make_config3("harris3d128")
         log(f"[bench] 3d: generating {c3.name}, n={c3.n}")
@@ -493,7 +494,9 @@ def main():
             parts = gcb.particles3(t)
             prm = gcb.params(dt=c3.dt, c=c3.c, qm=c3.qm, f_rho=c3.f_rho, f_E=c3.f_E,
                              curvature=c3.curvature, n_iter=c3.n_iter, form=form,
-                             sort_every=a.d3_sort_every, kernel=a.d3_kernel, tile=a.d3_tile)
+                             sort_every=a.d3_sort_every, kernel=a.d3_kernel, tile=a.d3_tile,
+                             arith=(gcb.GCB_ARITH_EXACT if mixed else
+                                    (ARITH if arith is None else arith)))
             st = gcb.gcb_push_3d(ctx, parts, prm, warmup, want_stats=True)
             frac = st["gca_steps"] / max(1, st["gca_steps"] + st["boris_steps"])
             halo = st["halo_misses"] / max(1, st["gca_steps"] + st["boris_steps"])
@@ -649,6 +652,7 @@ def main():
 
     if not a.no_3d:
         forms["d3"] = time_3d(a.d3_steps, a.d3_warmup)
+        forms["d3_exact_arith"] = time_3d(a.d3_steps, a.d3_warmup, arith=gcb.GCB_ARITH_EXACT)
         if not a.no_mixed:
             forms["d3_mixed"] = time_3d(a.d3_steps, a.d3_warmup, mixed=True)
             forms["d3_mixed"]["speedup_vs_d3_f64"] = (forms["d3_mixed"]["value"]

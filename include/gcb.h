@@ -219,8 +219,8 @@ typedef struct {
                             adjoints return GCB_EUNSUPPORTED for a value other than 0 */
     int32_t arith;       /* GCB_ARITH_EXACT (0, default) or GCB_ARITH_FAST: how the
                             binary64 form evaluates the step (see below).
-                            GCB_ARITH_FAST: gcb_push, gcb_push_noalloc and
-                            gcb_push_gr with GCB_FORM_F64 only (else
+                            GCB_ARITH_FAST: gcb_push, gcb_push_noalloc, gcb_push_3d
+                            and gcb_push_gr with GCB_FORM_F64 only (else
                             GCB_EUNSUPPORTED) */
     int32_t keep_order;  /* 1: with sort_every > 0 the particles are still cell-sorted
                             (the tiled kernel works through each tile's particles) but

@@ -44,6 +44,7 @@ UNITS = {
     "gcb_gr_fast.hip": ["-ffp-contract=fast"],
     "gcb_gr_mixed.hip": FAST_F32,
     "gcb_push3_f64.hip": ["-ffp-contract=off"],
+    "gcb_push3_f64_fast.hip": ["-ffp-contract=fast"],
     "gcb_push3_mixed.hip": FAST_F32,
 }
 

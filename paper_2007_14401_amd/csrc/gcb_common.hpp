@@ -130,6 +130,7 @@ struct ParticlePtrs {
 struct PushConst3 {
     PushConst b;
     double inv_dz, Lz;
+    double inv_Lz;           // 1/Lz (the production binary64 form)
     double sz[6];            // z offsets of the lattices, in cells
     int32_t nz, pad_;
 };

@@ -243,13 +243,13 @@ int validate_params(gcb_ctx* ctx, const gcb_params* prm) {
     return GCB_OK;
 }
 
-// the production binary64 arithmetic is served by the 2D and the
-// curved-spacetime binary64 pushes only
+// the production binary64 arithmetic is served by the binary64 pushes
+// (2D, 3D, curved spacetime) only
 int reject_fast_arith(gcb_ctx* ctx, const gcb_params* prm) {
     if (prm->arith != GCB_ARITH_EXACT)
         return fail(ctx, GCB_EUNSUPPORTED,
-                    "GCB_ARITH_FAST is served by gcb_push and gcb_push_gr with GCB_FORM_F64 "
-                    "only");
+                    "GCB_ARITH_FAST is served by gcb_push, gcb_push_3d and gcb_push_gr with "
+                    "GCB_FORM_F64 only");
     return GCB_OK;
 }
 
@@ -412,6 +412,9 @@ PushConst3 make_const3(const gcb_ctx* ctx, const gcb_params* prm) {
     pc.b.Lx = ctx->n3[0] * ctx->d3[0];
     pc.b.Ly = ctx->n3[1] * ctx->d3[1];
     pc.Lz = ctx->n3[2] * ctx->d3[2];
+    pc.b.inv_Lx = 1.0 / pc.b.Lx;
+    pc.b.inv_Ly = 1.0 / pc.b.Ly;
+    pc.inv_Lz = 1.0 / pc.Lz;
     for (int k = 0; k < 6; ++k) {
         pc.b.stagger[k][0] = ctx->stagger3[k][0];
         pc.b.stagger[k][1] = ctx->stagger3[k][1];
@@ -738,12 +741,9 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
     constexpr int32_t kGlobalStepsPerLaunch = 16;
     ParticlePtrs3<U> cur = user, other = scr;
     for (int32_t step = 0; step < n_steps;) {
-        int32_t ns = 1;
-        if (kind == PushKind::Global) {
-            ns = std::min(kGlobalStepsPerLaunch, n_steps - step);
-            if (prm->sort_every > 0)
-                ns = std::min(ns, prm->sort_every - step % prm->sort_every);
-        }
+        int32_t ns = std::min(kind == PushKind::Global ? kGlobalStepsPerLaunch : kTiledMaxSteps,
+                              n_steps - step);
+        if (prm->sort_every > 0) ns = std::min(ns, prm->sort_every - step % prm->sort_every);
         ParticlePtrs3<U> dst = cur;
         const uint32_t* perm = nullptr;
         if (prm->sort_every > 0 && n > 0 && step % prm->sort_every == 0) {
@@ -772,7 +772,8 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
         Timer t(ctx, stream, GCB_TIMER_PUSH);
         hipError_t e;
         if constexpr (sizeof(U) == sizeof(double))
-            e = launch_push3_f64(L, cur, dst, pc, stream);
+            e = prm->arith == GCB_ARITH_FAST ? launch_push3_f64_fast(L, cur, dst, pc, stream)
+                                             : launch_push3_f64(L, cur, dst, pc, stream);
         else
             e = launch_push3_mixed(L, cur, dst, pc, stream);
         if (e != hipSuccess)
@@ -1305,7 +1306,8 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t 
     if (!p) return fail(ctx, GCB_EINVAL, "particles is NULL");
     int rc;
     if ((rc = validate_params(ctx, prm))) return rc;
-    if ((rc = reject_fast_arith(ctx, prm))) return rc;
+    if (prm->arith == GCB_ARITH_FAST && prm->form != GCB_FORM_F64)
+        return fail(ctx, GCB_EUNSUPPORTED, "GCB_ARITH_FAST needs GCB_FORM_F64");
     if (prm->keep_order != 0)
         return fail(ctx, GCB_EUNSUPPORTED, "keep_order is served by gcb_push only");
     // the 2D checks on the x, y, u, qm, id and status arrays, then z

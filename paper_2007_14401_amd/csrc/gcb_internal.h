@@ -83,7 +83,7 @@ struct Push3Launch {
     uint8_t* trace;        // nullable: trace row of the launch's first step
     bool replay;
     DevStats* stats;       // nullable
-    int steps = 1;         // global kernel: steps per launch
+    int steps = 1;         // steps per launch (trace: steps*n bytes)
     bool exact = false;    // guiding-center branch in the exact frame (binary64 only)
     bool mirror = false;   // guiding-center branch with the mirror terms
     bool phase = false;    // guiding-center branch with the gyration phase advanced
@@ -92,6 +92,10 @@ struct Push3Launch {
 hipError_t launch_push3_f64(const Push3Launch& L, const ParticlePtrs3<double>& in,
                             const ParticlePtrs3<double>& out, const PushConst3& pc,
                             hipStream_t stream);
+// the same with contracted multiply-adds (GCB_ARITH_FAST)
+hipError_t launch_push3_f64_fast(const Push3Launch& L, const ParticlePtrs3<double>& in,
+                                 const ParticlePtrs3<double>& out, const PushConst3& pc,
+                                 hipStream_t stream);
 hipError_t launch_push3_mixed(const Push3Launch& L, const ParticlePtrs3<float>& in,
                               const ParticlePtrs3<float>& out, const PushConst3& pc,
                               hipStream_t stream);

@@ -13,6 +13,8 @@
 #include "gcb_math.hpp"
 
 namespace gcb {
+// one instance per arithmetic (see gcb_math.hpp)
+inline namespace GCB_ARITH_NS {
 
 template <typename R>
 struct Consts3 : Consts<R> {
@@ -247,14 +249,14 @@ GCB_HD uint32_t local_exact_curv(const SampleEG3<R>& s, const Consts<R>& K, Loca
 template <typename R>
 GCB_HD void drift_terms3(const Local<R>& L, R upn, const Gyr<R>& gy, R inv_qm, bool curvature,
                          const Consts<R>& K, R F[3], bool mirror = false) {
-    const R g = gamma_gca(L, upn, gy, K);
-    const R a = upn / g;
+    const Gam<R> G = gamma_gca2(L, upn, gy, K);
+    const R a = over(upn, G);
     if (curvature) {
         R vc[3];
         if (mirror)
-            v_curv_mirror<3>(L, upn, g, inv_qm, gy.mu, K, vc);
+            v_curv_mirror<3>(L, upn, G.g, inv_qm, gy.mu, K, vc);
         else
-            v_curv(L, upn, g, inv_qm, K, vc);
+            v_curv_g(L, upn, G, inv_qm, K, vc);
 #pragma unroll
         for (int i = 0; i < 3; ++i) F[i] = (a * L.b[i] + L.vE[i]) + vc[i];
     } else {
@@ -269,17 +271,22 @@ template <typename R>
 GCB_HD void boris_step3(const Sample3<R>& s, Regs3<R>& r, const PushConst3& pc,
                         const Consts<R>& K) {
     boris(s.E, s.B, r.ux, r.uy, r.uz, (R)r.qm, K);
-    const R gn = gamma_full(r.ux, r.uy, r.uz, K);
-    const R inv_g = (R)1 / gn;
+    R inv_g;
+    if constexpr (kFastD<R>) {
+        inv_g = gamma_full2(r.ux, r.uy, r.uz, K).inv;
+    } else {
+        const R gn = gamma_full(r.ux, r.uy, r.uz, K);
+        inv_g = (R)1 / gn;
+    }
     const double xn = r.x + pc.b.dt * (double)(r.ux * inv_g);
     const double yn = r.y + pc.b.dt * (double)(r.uy * inv_g);
     const double zn = r.z + pc.b.dt * (double)(r.uz * inv_g);
     r.xp = r.x;
     r.yp = r.y;
     r.zp = r.z;
-    r.x = wrap(xn, pc.b.Lx);
-    r.y = wrap(yn, pc.b.Ly);
-    r.z = wrap(zn, pc.Lz);
+    r.x = wrap_i<R>(xn, pc.b.Lx, pc.b.inv_Lx);
+    r.y = wrap_i<R>(yn, pc.b.Ly, pc.b.inv_Ly);
+    r.z = wrap_i<R>(zn, pc.Lz, pc.inv_Lz);
 }
 
 // One guiding-center step (Sec. 2.2.1 / 2.2.2 inside the coupled step of
@@ -301,6 +308,7 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
     const double x[3] = {r.x, r.y, r.z};
     const double xprev[3] = {r.xp, r.yp, r.zp};
     const double box[3] = {pc.b.Lx, pc.b.Ly, pc.Lz};
+    const double inv_box[3] = {pc.b.inv_Lx, pc.b.inv_Ly, pc.inv_Lz};
     const R ux = r.ux, uy = r.uy, uz = r.uz;
     const R qm = (R)r.qm;
     const R inv_qm = (R)1 / qm;
@@ -311,25 +319,37 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
     {
         double Rh[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) Rh[a] = x[a] - 0.5 * min_image(x[a] - xprev[a], box[a]);
+        for (int a = 0; a < 3; ++a)
+            Rh[a] = x[a] - 0.5 * min_image_i<R>(x[a] - xprev[a], box[a], inv_box[a]);
         Smp sh;
         gather3<R, true, kYee>(acc, pc, K, Rh[0], Rh[1], Rh[2], sh);
         Local<R> Lh;
         flags |= local_in_frame<kExact, R>(sh, K, Lh);
         upar = (ux * Lh.b[0] + uy * Lh.b[1]) + uz * Lh.b[2];
-        const R gf = gamma_full(ux, uy, uz, K);
+        const Gam<R> G = gamma_full2(ux, uy, uz, K);
+        const R gf = G.g;
         R vc[3] = {(R)0, (R)0, (R)0};
-        if (curv) v_curv(Lh, upar, gf, inv_qm, K, vc);
+        if (curv) v_curv_g(Lh, upar, G, inv_qm, K, vc);
         const R upx = (ux - upar * Lh.b[0]) - (Lh.vE[0] + vc[0]) * gf;
         const R upy = (uy - upar * Lh.b[1]) - (Lh.vE[1] + vc[1]) * gf;
         const R upz = (uz - upar * Lh.b[2]) - (Lh.vE[2] + vc[2]) * gf;
         const R up2 = (upx * upx + upy * upy) + upz * upz;
         flags |= mirror_check(ux, uy, uz, Lh, vc, up2, gf, pc.b, K);
-        gy.mu = pc.b.gyration == GYR_ZERO ? (R)0 : (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        R mu;
+        if constexpr (kFastD<R>)
+            mu = (((R)0.5 * up2) * Lh.inv_B) * Lh.inv_kappa;
+        else
+            mu = (((R)0.5 * up2) * Lh.inv_B) / Lh.kappa;
+        gy.mu = pc.b.gyration == GYR_ZERO ? (R)0 : mu;
         gy.up2 = up2;
         gy.fixed = pc.b.gyration == GYR_UPERP;
-        const R nu = sqrt(up2);
-        const R inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
+        R inv_nu;
+        if constexpr (kFastD<R>) {
+            inv_nu = up2 > (R)0 ? rsqrt_nr(up2) : (R)0;
+        } else {
+            const R nu = sqrt(up2);
+            inv_nu = nu > (R)0 ? (R)1 / nu : (R)0;
+        }
         bp[0] = upx * inv_nu;
         bp[1] = upy * inv_nu;
         bp[2] = upz * inv_nu;
@@ -391,9 +411,10 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
         gather3<R, true, kYee>(acc, pc, K, Rm[0], Rm[1], Rm[2], sm);
         Local<R> Lm;
         flags |= local_in_frame<kExact, R>(sm, K, Lm);
-        const R gr = gamma_gca(Lm, upn, gy, K);
+        const Gam<R> G = gamma_gca2(Lm, upn, gy, K);
+        const R gr = G.g;
         R vc[3] = {(R)0, (R)0, (R)0};
-        if (curv) v_curv(Lm, upn, gr, inv_qm, K, vc);
+        if (curv) v_curv_g(Lm, upn, G, inv_qm, K, vc);
         const R um = sqrt(uperp_sq(Lm, gy));
         r.ux = (upn * Lm.b[0] + (Lm.vE[0] + vc[0]) * gr) + um * bp[0];
         r.uy = (upn * Lm.b[1] + (Lm.vE[1] + vc[1]) * gr) + um * bp[1];
@@ -404,9 +425,9 @@ GCB_HD uint32_t gca_step3(const Acc& acc, const Sample3<R>& sn, Regs3<R>& r,
     r.xp = x[0];
     r.yp = x[1];
     r.zp = x[2];
-    r.x = wrap(Rp[0], pc.b.Lx);
-    r.y = wrap(Rp[1], pc.b.Ly);
-    r.z = wrap(Rp[2], pc.Lz);
+    r.x = wrap_i<R>(Rp[0], pc.b.Lx, pc.b.inv_Lx);
+    r.y = wrap_i<R>(Rp[1], pc.b.Ly, pc.b.inv_Ly);
+    r.z = wrap_i<R>(Rp[2], pc.Lz, pc.inv_Lz);
     return flags;
 }
 
@@ -418,4 +439,5 @@ GCB_HD uint32_t finite_flag3(const Regs3<R>& r) {
     return ok ? 0u : (uint32_t)ST_NONFINITE;
 }
 
+}  // inline namespace GCB_ARITH_NS
 }  // namespace gcb

@@ -6,9 +6,11 @@
 //
 // k_push3_global: one lane per particle, up to `ns` steps per launch with the
 //   particle in registers, gathers through the caches.
-// k_push3_tiled: one workgroup per cubic tile of cell-sorted particles; the
-//   tile's field window (tile + halo per side, W^3 nodes of six components)
-//   is staged once in LDS, then the per-regime queues of the 2D kernel.
+// k_push3_tiled: one workgroup per cubic tile of cell-sorted particles for
+//   all the steps of a launch (those between two sorts); the tile's field
+//   window (tile + halo per side, W^3 nodes of six components) is staged once
+//   in LDS, then the per-regime queues and register-resident steps of the 2D
+//   kernel.
 //
 // Included by exactly one translation unit per form.
 #pragma once
@@ -21,7 +23,7 @@
 #include "gcb_push_kernels.hpp"
 
 namespace gcb {
-namespace kern {
+namespace GCB_KERN_NS {
 
 template <typename R>
 __device__ __forceinline__ void load_particle3(const ParticlePtrs3<R>& in, int64_t p,
@@ -122,15 +124,30 @@ __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
     if (stats) flush_stats(stats, cnt_g, cnt_b, 0, maxres);
 }
 
+// One workgroup per cubic tile of cell-sorted particles for all `steps`
+// steps of a launch (those between two sorts), as the 2D kernel: the tile's
+// window is staged in LDS once; each chunk of up to kQueueMax particles is
+// split into the two queues by the branch of its first step, and each lane
+// then keeps a particle in registers for every step of the launch,
+// re-evaluating the switch at every step from the gather the update uses.
 template <typename R, typename T, bool kYee, int kMinWaves, int kVar>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
-k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const uint32_t* __restrict__ perm,
-              const int32_t* __restrict__ tile_start, TileGeom3 g, int chunk,
-              const T* __restrict__ F, PushConst3 pc, uint8_t* trace, bool replay,
-              DevStats* stats) {
+k_push3_tiled(ParticlePtrs3<R> in_arg, ParticlePtrs3<R> out_arg,
+              const uint32_t* __restrict__ perm, const int32_t* __restrict__ tile_start,
+              TileGeom3 g, int chunk, const T* __restrict__ F, PushConst3 pc, uint8_t* trace,
+              int64_t n, int steps, bool replay, DevStats* stats) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int wave_g[kWG / 64];
     __shared__ int wave_b[kWG / 64];
+    // the state arrays' pointers are used only before and after the steps:
+    // kept in LDS, not in scalar registers through the steps
+    __shared__ ParticlePtrs3<R> io[2];
+    if (threadIdx.x == 0) {
+        io[0] = in_arg;
+        io[1] = out_arg;
+    }
+    const ParticlePtrs3<R>& in = io[0];
+    const ParticlePtrs3<R>& out = io[1];
 
     const int ntiles = g.ntx * g.nty * g.ntz;
     // consecutive tiles on the same XCD (workgroup b runs on XCD b % 8)
@@ -178,7 +195,7 @@ k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const uint32_t* __restr
 
     for (int64_t base = p0; base < p1; base += kQueueMax) {
         const int m = (int)((p1 - base) < kQueueMax ? (p1 - base) : kQueueMax);
-        // pass 1: switch decision, stable split into the two queues
+        // the branch of the launch's first step, stable split into the queues
         const int nG = split_queues<kWG>(m, queue, wave_g, wave_b, [&](int t) {
             const int64_t p = base + t;
             const int64_t src = perm ? (int64_t)perm[p] : p;
@@ -188,30 +205,55 @@ k_push3_tiled(ParticlePtrs3<R> in, ParticlePtrs3<R> out, const uint32_t* __restr
             gather3<R, false, kYee>(acc, pc, K, in.b.x[src], in.b.y[src], in.z[src], s);
             return switch_gca(s.E, s.B, in.b.ux[src], in.b.uy[src], in.b.uz[src], qm, pc.b, K);
         });
-        // pass 2: guiding-center queue, then Boris queue
         for (int q = threadIdx.x; q < m; q += kWG) {
             const int64_t p = base + queue[q];
             const int64_t src = perm ? (int64_t)perm[p] : p;
-            const bool gca = q < nG;
+            const int64_t tid = in.b.id ? (int64_t)in.b.id[src] : p;   // trace column
             Regs3<R> r;
             load_particle3(in, src, pc.b.qm, r);
-            acc.miss = false;
-            double res;
-            uint32_t fl = coupled_update3<R, kYee, kVar>(acc, gca, r, pc, K, res);
-            if (acc.miss) {
-                fl |= ST_HALO;
-                ++cnt_h;
+            uint32_t fl = 0;
+            bool gca = q < nG;
+            for (int st = 0; st < steps; ++st) {
+                uint8_t* tr = trace ? trace + (int64_t)st * n : nullptr;
+                // the gather at x^n serves the switch and the update; the
+                // gradients are formed for the branch of the previous step
+                const bool prev = gca;
+                Sample3<R> smp;
+                acc.miss = false;
+                if (prev)
+                    gather3<R, true, kYee>(acc, pc, K, r.x, r.y, r.z, smp);
+                else
+                    gather3<R, false, kYee>(acc, pc, K, r.x, r.y, r.z, smp);
+                if (st > 0) {
+                    if (replay)
+                        gca = tr[tid] == 0;
+                    else
+                        gca = switch_gca(smp.E, smp.B, r.ux, r.uy, r.uz, r.qm, pc.b, K);
+                    if (gca && !prev) gather3<R, true, kYee>(acc, pc, K, r.x, r.y, r.z, smp);
+                }
+                double res = 0.0;
+                if (gca)
+                    fl |= gca_step3<R, kYee, var_exact(kVar), kVar == kVarMirror,
+                                    kVar == kVarPhase, kVar == kVarExactCurv>(acc, smp, r, pc,
+                                                                              K, res);
+                else
+                    boris_step3(smp, r, pc, K);
+                fl |= finite_flag3(r);
+                if (acc.miss) {
+                    fl |= ST_HALO;
+                    ++cnt_h;
+                }
+                if (tr && !replay) tr[tid] = gca ? 0 : 1;
+                if (gca) {
+                    ++cnt_g;
+                    maxres = nan_max(maxres, res);
+                } else {
+                    ++cnt_b;
+                }
             }
             store_particle3(in, out, p, src, r, fl);
-            if (trace && !replay) trace[in.b.id ? (int64_t)in.b.id[src] : p] = gca ? 0 : 1;
-            if (gca) {
-                ++cnt_g;
-                maxres = nan_max(maxres, res);
-            } else {
-                ++cnt_b;
-            }
         }
-        __syncthreads();
+        __syncthreads();   // the queue is rebuilt for the next chunk
     }
     if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
 }
@@ -236,19 +278,22 @@ hipError_t launch_push3_frame(const Push3Launch& L, const ParticlePtrs3<R>& in,
     }
     const int ntiles = L.geom.ntx * L.geom.nty * L.geom.ntz;
     const int chunk = (ntiles + 7) / 8;
+    const int ns = L.steps > 0 ? L.steps : 1;
     const size_t lds = tiled3_lds_bytes(L.geom.window, sizeof(T));
     if (L.yee) {
         auto kfn = k_push3_tiled<R, T, true, kMinWaves, kVar>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
-                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay, L.stats);
+                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.n, ns, L.replay,
+                           L.stats);
     } else {
         auto kfn = k_push3_tiled<R, T, false, kMinWaves, kVar>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
-                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.replay, L.stats);
+                           L.tile_start, L.geom, chunk, F, pc, L.trace, L.n, ns, L.replay,
+                           L.stats);
     }
     return hipGetLastError();
 }
@@ -271,5 +316,5 @@ hipError_t launch_push3(const Push3Launch& L, const ParticlePtrs3<R>& in,
     return launch_push3_frame<R, T, kMinWaves, kVarReduced>(L, in, out, pc, stream);
 }
 
-}  // namespace kern
+}  // namespace GCB_KERN_NS
 }  // namespace gcb

@@ -495,3 +495,61 @@ def test_exact_frame_curvature_3d(kernel, sort_every, tile):
         assert np.count_nonzero(tr.cpu().numpy()[:, calm] != rtr.numpy()[:, calm]) == 0
     finally:
         run.close()
+
+
+def _chaos_aware3(cfg, F, ens, steps, got, tr_gpu, what, **kw):
+    """The chaos-aware protocol in 3D: each particle within 10x the largest
+    deviation of the oracle nudged by up to four units in the last place
+    after every step (three runs), and the switch decisions of every
+    particle whose nudged deviation stays within 1e-12 identical."""
+    from test_gpu_production import _nudge
+    ref, rtr, _ = run_oracle3(cfg, F, ens, steps, trace=True, **kw)
+    prov = O.GridFields3(F, cfg.dx, cfg.dy, cfg.dz, cfg.stagger)
+    p = oracle_params3(cfg, **kw)
+    sens = None
+    for sd in (1, 2, 3):
+        rng = np.random.default_rng(sd)
+        s_ = O.State3.from_numpy(ens)
+        for _ in range(steps):
+            s_, _, _ = O.step3(prov, s_, p)
+            for k in ("x", "y", "z", "ux", "uy", "uz"):
+                setattr(s_, k, _nudge(getattr(s_, k), rng))
+        e = _particle_errors3({k: getattr(s_, k).numpy() for k in
+                               ("x", "y", "z", "ux", "uy", "uz")}, ref, cfg)
+        sens = e if sens is None else np.maximum(sens, e)
+    err = _particle_errors3(got, ref, cfg)
+    bound = np.maximum(TOL, 10.0 * sens)
+    calm = sens <= TOL
+    log(f"{what}: {int((~calm).sum())} sensitive of {err.size}; GPU error median "
+        f"{np.median(err):.1e}, max {err.max():.1e}; over the bound {int((err > bound).sum())}")
+    assert not (err > bound).any(), what
+    assert np.count_nonzero(tr_gpu.cpu().numpy()[:, calm] != rtr.numpy()[:, calm]) == 0, what
+
+
+@pytest.mark.parametrize("kernel,sort_every,tile", [(GLOBAL, 0, 0), (TILED, 2, 6), (TILED, 4, 4)])
+def test_fast_arith_3d(kernel, sort_every, tile):
+    """The production arithmetic (GCB_ARITH_FAST) of the 3D push: one step
+    within 1e-12 of the oracle with identical switch decisions and status
+    bits; 12 steps by the chaos-aware protocol."""
+    from paper_2007_14401_amd import gcb, state
+    cfg = make_config3("harris3d32")
+    F = cfg.fields()
+    run = GpuRun3(cfg, F)
+    try:
+        ens = cfg.particles(n=3000, seed_offset=7)
+        log(f"3d fast arithmetic kernel={kernel} sort_every={sort_every}: one step")
+        t = _state(ens)
+        tr, st = run.push(t, 1, trace=True, stats=True, kernel=kernel, sort_every=sort_every,
+                          tile=tile, arith=gcb.GCB_ARITH_FAST)
+        ref, rtr, _ = run_oracle3(cfg, F, ens, 1, trace=True)
+        _check(state.unsort(t), ref, cfg, "3d fast arithmetic, one step", tr, rtr)
+        t2 = _state(ens)
+        run.push(t2, 1, kernel=kernel, sort_every=sort_every, tile=tile)
+        assert not torch.equal(t2["ux"], t["ux"]) or not torch.equal(t2["x"], t["x"])
+        steps = 12
+        t = _state(ens)
+        tr, _ = run.push(t, steps, trace=True, kernel=kernel, sort_every=sort_every, tile=tile,
+                         arith=gcb.GCB_ARITH_FAST)
+        _chaos_aware3(cfg, F, ens, steps, state.unsort(t), tr, f"3d fast arithmetic, {steps} steps")
+    finally:
+        run.close()
