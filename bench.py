@@ -714,8 +714,9 @@ def main():
                              else (alu_tf / FP64_VECTOR_PEAK_TF),
                      "traffic": traffic,
                      "kernel": ("kern_fast::" if a.arith == "fast" else "kern::")
-                               + ("k_push_tiled<double, double, true, 3, 0>" if a.kernel != 1
-                                  else "k_push_global<double, double, true, 0>"),
+                               + ("k_push_tiled<double, double, true, 3, 0, false>"
+                                  if a.kernel != 1
+                                  else "k_push_global<double, double, true, 0, false>"),
                      "kernel_ms": launch_ms,
                      "kernel_ms_per_step": push_ms,
                      "steps_per_launch": steps_per_launch,
