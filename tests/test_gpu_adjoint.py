@@ -311,3 +311,45 @@ def test_c4_finite_differences_grid_nodes():
     position (the bilinear gradient of B jumps across cell lines), so almost
     every difference quotient leaves the linear regime."""
     _c4_fd(32, 64, 0, 1e-7, 48, 0)
+
+
+def test_recomputation_kernels_agree():
+    """gcb_push_backward recomputes a segment with the in-place tiled push
+    (sort_every > 0) or the global kernel (sort_every = 0); both run the
+    parity arithmetic, so the state cotangents are equal bit for bit and the
+    binary32 field cotangents to their accumulation order."""
+    from paper_2007_14401_amd import gcb
+    cfg = make_config("harris64")
+    F = cfg.fields()
+    ens = cfg.particles(n=1000 + 13, seed_offset=41)
+    steps = 12
+    ctx = gcb.gcb_create(0)
+    try:
+        desc = gcb.grid_desc(cfg.nx, cfg.ny, cfg.dx, cfg.dy, cfg.stagger, gcb.GCB_F64)
+        gcb.gcb_load_fields(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
+        st = _tensors(ens)
+        st["status"] = torch.zeros(ens.n, dtype=torch.uint8, device=DEV)
+        st["qm"] = torch.as_tensor(ens.qm, dtype=torch.float64, device=DEV)
+        st["id"] = None
+        rng = np.random.default_rng(3)
+        lam_end = [torch.as_tensor(rng.normal(size=ens.n), device=DEV) for _ in range(7)]
+        out = {}
+        for se, tile in ((0, 0), (4, 16), (3, 8)):
+            lam = [torch.empty(ens.n, dtype=torch.float64, device=DEV) for _ in range(7)]
+            dE = torch.zeros((3, cfg.ny, cfg.nx), dtype=torch.float32, device=DEV)
+            dB = torch.zeros((3, cfg.ny, cfg.nx), dtype=torch.float32, device=DEV)
+            prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                             curvature=cfg.curvature, n_iter=cfg.n_iter, sort_every=se,
+                             tile=tile)
+            gcb.gcb_push_backward(ctx, gcb.particles(st), prm, steps, lam_end, lam,
+                                  [dE[0], dE[1], dE[2]], [dB[0], dB[1], dB[2]])
+            torch.cuda.synchronize()
+            out[se] = ([v.cpu().numpy() for v in lam], torch.cat([dE, dB]).cpu().numpy())
+        base_l, base_f = out[0]
+        for se in (4, 3):
+            l, f = out[se]
+            for a, b in zip(l, base_l):
+                assert np.array_equal(a, b), se
+            assert np.max(np.abs(f - base_f)) <= 1e-5 * np.max(np.abs(base_f)), se
+    finally:
+        gcb.gcb_destroy(ctx)

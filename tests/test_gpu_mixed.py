@@ -165,3 +165,26 @@ def test_mixed_precision_report_1e8():
     """The same fields and steps with 1e8 particles (about 6 particles per
     cell), mixed form, 1e5 particles sampled against the oracle."""
     _bounds(_report(100_000_000, 100), MED_FULL, P99_FULL, XMED_FULL, MISM_FULL)
+
+
+def test_mixed_keep_order_equals_sorted_push():
+    """keep_order in the precision form: the same results as the permuting
+    sort (particles are independent), in input order without ids."""
+    from paper_2007_14401_amd import gcb, state
+    cfg = make_config("harris64")
+    F = cfg.fields()
+    run = GpuRun(cfg, F, dtype=gcb.GCB_F32)
+    try:
+        ens = cfg.particles(n=4096 + 37, seed_offset=12)
+        a = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED)
+        tr_a, _ = run.push(a, 9, trace=True, kernel=2, sort_every=3, tile=16,
+                           form=gcb.GCB_FORM_MIXED)
+        b = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED, with_id=False)
+        tr_b, _ = run.push(b, 9, trace=True, kernel=2, sort_every=3, tile=16,
+                           form=gcb.GCB_FORM_MIXED, keep_order=1)
+        ua = state.unsort(a)
+        for k in ("x", "y", "xp", "yp", "ux", "uy", "uz", "status"):
+            assert np.array_equal(ua[k], b[k].cpu().numpy()), k
+        assert torch.equal(tr_a, tr_b)
+    finally:
+        run.close()
