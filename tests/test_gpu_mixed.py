@@ -104,8 +104,8 @@ def _report(n_total, steps, sample_n=100_000, name="harris4096"):
     F = cfg.fields()
     ens = cfg.particles(n=n_total)
     # the benchmark's launch configuration of the mixed form (tiled, sort every
-    # 4 steps, 32-cell tiles)
-    t, tr, st = _run_mixed(cfg, F, ens, steps, True, kernel=2, sort_every=4, tile=32)
+    # 10 steps, 28-cell tiles)
+    t, tr, st = _run_mixed(cfg, F, ens, steps, True, kernel=2, sort_every=10, tile=28)
     ids = t["id"].cpu().numpy()
     rng = np.random.default_rng(123)
     sample_n = min(sample_n, ens.n)

@@ -216,7 +216,7 @@ def test_c2_full_size_sampled():
         log("c2: gpu push")
         t = _state(ens)
         steps = cfg.steps
-        _, st = run.push(t, steps, stats=True, kernel=2, sort_every=4, tile=24)
+        _, st = run.push(t, steps, stats=True, kernel=2, sort_every=10, tile=20)
         log(f"c2 stats {st}")
         frac = st["gca_steps"] / (st["gca_steps"] + st["boris_steps"])
         log(f"c2 guiding-center fraction over the run {frac:.3f}")

@@ -187,7 +187,7 @@ def test_fast_c2_full_size_sampled():
     run = GpuRun(cfg, F)
     try:
         t = _state(ens)
-        run.push(t, cfg.steps, kernel=2, sort_every=4, tile=20, arith=FAST)
+        run.push(t, cfg.steps, kernel=2, sort_every=10, tile=20, arith=FAST)
         ids = t["id"].cpu().numpy()
         rng = np.random.default_rng(78)
         sample = np.sort(rng.choice(ens.n, 2000, replace=False))
