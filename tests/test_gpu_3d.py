@@ -553,3 +553,30 @@ def test_fast_arith_3d(kernel, sort_every, tile):
         _chaos_aware3(cfg, F, ens, steps, state.unsort(t), tr, f"3d fast arithmetic, {steps} steps")
     finally:
         run.close()
+
+
+@pytest.mark.parametrize("opt", [dict(frame=1, curvature=0), dict(frame=1, curvature=1),
+                                 dict(mirror=1), dict(gyration=3), dict(gyration=1)],
+                         ids=["exact", "exact_curv", "mirror", "phase", "uperp"])
+def test_fast_arith_3d_variants(opt):
+    """The production arithmetic of the 3D push in every guiding-center
+    variant: one step within 1e-12 of the oracle with identical switch
+    decisions and status bits."""
+    from paper_2007_14401_amd import gcb, state
+    cfg = make_config3("harris3d32", E_rec=0.5, guide=0.3)
+    F = cfg.fields()
+    run = GpuRun3(cfg, F)
+    try:
+        ens = cfg.particles(n=3000, seed_offset=8)
+        log(f"3d fast arithmetic {opt}: one step")
+        t = _state(ens)
+        tr, st = run.push(t, 1, trace=True, stats=True, kernel=TILED, sort_every=4, tile=4,
+                          arith=gcb.GCB_ARITH_FAST, **opt)
+        kw = dict(curvature=bool(opt.get("curvature", cfg.curvature)),
+                  exact_frame=opt.get("frame", 0) == 1, mirror=opt.get("mirror", 0) == 1,
+                  gyration=opt.get("gyration", 0))
+        ref, rtr, _ = run_oracle3(cfg, F, ens, 1, trace=True, **kw)
+        _check(state.unsort(t), ref, cfg, f"3d fast arithmetic {opt}", tr, rtr)
+        assert st["gca_steps"] > 0
+    finally:
+        run.close()
