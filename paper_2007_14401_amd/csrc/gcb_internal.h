@@ -57,7 +57,7 @@ hipError_t launch_push_mixed(const PushLaunch& L, const ParticlePtrs<float>& in,
 // LDS bytes the tiled kernel needs for a window of `window` nodes per side
 // (window <= kTiledMaxWindow).
 size_t tiled_lds_bytes(int window, size_t elem_bytes);
-constexpr int kTiledChunk = 256;       // particles a tiled workgroup holds in LDS at once
+constexpr int kTiledChunk = 512;       // particles a tiled workgroup queues in LDS at once
 constexpr int kTiledMaxWindow = 64;    // window edge the tiled kernel stages
 constexpr int kTiledMaxSteps = 16;     // steps per tiled launch (not past the next sort)
 constexpr int kQueueMax = 2048;   // particles compacted per pass in a 3D tile

@@ -185,14 +185,19 @@ __global__ __launch_bounds__(kWG) void k_push_global(ParticlePtrs<R> in, Particl
 // a launch (the steps between two cell sorts, so the particle-to-tile
 // assignment of the last sort holds for all of them).  The tile's field
 // window (six W x W component planes) is staged in LDS once.  Its particles
-// are taken in chunks of up to kWG: the switch is evaluated for each at the
-// launch's first step and the chunk is split into two queues (guiding center
-// first, Boris from the back), so that a wavefront starts with particles of
-// one branch; each lane then keeps its particle in registers for every step
-// of the launch, evaluating the switch itself at every step (Sec. 4.1) from
-// the gather at x^n that the update uses.  Particles seldom change branch
-// between two sorts, so the wavefronts mostly stay on one branch; one that
-// holds both takes both, with the same results.
+// are taken in chunks of up to kTiledChunk: the switch is evaluated for each
+// at the launch's first step and the chunk is split into two queues
+// (guiding center first, Boris from the back).  The queues are cut into
+// slices of 64, the guiding-center slices first; each wavefront takes the
+// next slice from a counter in LDS until none is left, so a wavefront starts
+// with particles of one branch, and one that finishes a short Boris slice
+// takes another instead of idling while the workgroup's other wavefronts
+// finish theirs (the workgroup's LDS is held until its last wavefront ends).
+// Each lane keeps its particle in registers for every step of the launch,
+// evaluating the switch itself at every step (Sec. 4.1) from the gather at
+// x^n that the update uses.  Particles seldom change branch between two
+// sorts, so the wavefronts mostly stay on one branch; one that holds both
+// takes both, with the same results.
 template <typename R, typename T, bool kYee, int kMinWaves, int kVar, bool kRec = false>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __restrict__ perm,
@@ -202,6 +207,7 @@ k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int wave_g[kWG / 64];
     __shared__ int wave_b[kWG / 64];
+    __shared__ int next_slice;
     // The state arrays are used only before and after the steps of a chunk:
     // their twenty pointers are kept in LDS and read where they are used, so
     // that they do not occupy scalar registers through the steps.
@@ -276,10 +282,12 @@ k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __
     const int64_t p1 = tile_start[tile + 1];
     unsigned cnt_g = 0, cnt_b = 0, cnt_h = 0;
     double maxres = 0.0;
-    const int t = threadIdx.x;
 
-    for (int64_t base = p0; base < p1; base += kWG) {
-        const int m = (int)((p1 - base) < kWG ? (p1 - base) : kWG);
+    for (int64_t base = p0; base < p1; base += kTiledChunk) {
+        const int m = (int)((p1 - base) < kTiledChunk ? (p1 - base) : kTiledChunk);
+        // (the barriers of the split order this reset before any slice is
+        // taken, and the barrier at the end of the previous chunk after it)
+        if (threadIdx.x == 0) next_slice = 0;
         // the branch of the launch's first step per particle, split into
         // the two queues
         const int nG = split_queues<kWG>(m, queue, wave_g, wave_b, [&](int q) {
@@ -291,8 +299,17 @@ k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __
             const double qm = in.qm ? in.qm[src] : pc.qm;
             return switch_gca(smp.E, smp.B, in.ux[src], in.uy[src], in.uz[src], qm, pc, K);
         });
-        if (t < m) {
-            const int64_t p = base + queue[t];
+        const int sG = (nG + 63) >> 6;                 // guiding-center slices
+        const int sAll = sG + ((m - nG + 63) >> 6);   // and the Boris ones
+        for (;;) {
+            int sl = 0;
+            if (lane == 0) sl = atomicAdd(&next_slice, 1);
+            sl = __builtin_amdgcn_readfirstlane(sl);
+            if (sl >= sAll) break;
+            const bool gslice = sl < sG;
+            const int q = gslice ? sl * 64 + lane : nG + (sl - sG) * 64 + lane;
+            if (q >= (gslice ? nG : m)) continue;   // the slice's unfilled lanes
+            const int64_t p = base + queue[q];
             const int64_t src = perm ? (int64_t)perm[p] : p;
             const bool keep = perm && out.x == in.x;
             const int64_t slot = keep ? src : p;   // where the particle is written
@@ -300,7 +317,7 @@ k_push_tiled(ParticlePtrs<R> in_arg, ParticlePtrs<R> out_arg, const uint32_t* __
             Regs<R> r;
             load_particle(in, src, pc.qm, r);
             uint32_t fl = 0;
-            bool gca = t < nG;
+            bool gca = gslice;
             for (int s = 0; s < steps; ++s) {
                 uint8_t* tr = trace ? trace + (int64_t)s * n : nullptr;
                 if constexpr (kRec) record_state(in.rec + (int64_t)s * 7 * n, n, tid, r);
