@@ -89,6 +89,7 @@ struct gcb_ctx {
     DevBuf stats;        // DevStats + flagged counter
     DevBuf ke_partial;
     DevBuf adj_states, adj_lam, adj_grad, adj_trace, adj_work, adj_samples, adj_lists;
+    DevBuf adj_order;    // tile order of a backward segment: q/m and the permutation
     // fixed scratch of gcb_push_noalloc on this context's device (the address
     // of the file-scope array `scratch` there); while `arena` is set, every
     // piece of call scratch is carved from it instead of allocated
@@ -434,6 +435,11 @@ PushConst3 make_const3(const gcb_ctx* ctx, const gcb_params* prm) {
 // 6 steps, 26.6 with 27), so 3D keeps short ones.
 constexpr int kAdjMaxBatch = 32;
 constexpr size_t kAdjRecordBudget = 128ull << 30;
+// Tile edge (cells) of the order a 2D backward segment runs its particles in.
+#ifndef GCB_ADJ_ORDER_TILE
+#define GCB_ADJ_ORDER_TILE 32
+#endif
+constexpr int kAdjOrderTile = GCB_ADJ_ORDER_TILE;
 constexpr int kAdj3MaxBatch = 8;
 constexpr size_t kAdj3RecordBudget = 32ull << 30;
 
@@ -840,7 +846,8 @@ void gcb_destroy(gcb_ctx* ctx) {
                       &ctx->sort_idx2,  &ctx->sort_hist,  &ctx->sort_scan,
                       &ctx->tile_start, &ctx->pscratch,   &ctx->stats,     &ctx->ke_partial,
                       &ctx->adj_states, &ctx->adj_lam,    &ctx->adj_grad,  &ctx->adj_trace,
-                      &ctx->adj_work,   &ctx->adj_samples, &ctx->adj_lists, &ctx->gr_fields,
+                      &ctx->adj_work,   &ctx->adj_samples, &ctx->adj_lists, &ctx->adj_order,
+                      &ctx->gr_fields,
                       &ctx->gr_dl,
                       &ctx->gr_pscratch, &ctx->fields3};
     for (DevBuf* b : bufs) release(*b);
@@ -984,6 +991,23 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
     batch = std::max(1, std::min(batch, std::max(1, (int)n_steps)));
     if ((rc = ensure(ctx, ctx->adj_samples, adjoint_record_bytes(n, prm->n_iter, batch))))
         return rc;
+    // The segment runs on its particles in the tile order of their start
+    // positions (kAdjOrderTile-cell tiles): the state, q/m and the adjoint
+    // are permuted on the way in and the adjoint back on the way out.  Each
+    // particle's arithmetic is its own, so the order changes no value; the
+    // reverse kernels' gathers of neighbouring lanes then share cache lines.
+    TileGeom og{};
+    og.tile = kAdjOrderTile;
+    og.ntx = (ctx->nx + og.tile - 1) / og.tile;
+    og.nty = (ctx->ny + og.tile - 1) / og.tile;
+    const bool ordered = n > 0 && n_steps > 0;
+    double* qms = nullptr;          // q/m in tile order
+    uint32_t* perm = nullptr;       // tile slot -> caller's slot
+    if (ordered) {
+        if ((rc = ensure(ctx, ctx->adj_order, nd + (size_t)n * 4))) return rc;
+        qms = static_cast<double*>(ctx->adj_order.ptr);
+        perm = reinterpret_cast<uint32_t*>(qms + n);
+    }
     double* work = static_cast<double*>(ctx->adj_work.ptr);
     uint8_t* wstatus = reinterpret_cast<uint8_t*>(work + 7 * (size_t)n);
     double* states = static_cast<double*>(ctx->adj_states.ptr);
@@ -995,12 +1019,27 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
                             static_cast<const double*>(start->uy),
                             static_cast<const double*>(start->uz)};
     Timer t(ctx, stream, GCB_TIMER_BACKWARD);
+    if (ordered) {
+        SortBuffers ssb{};
+        if ((rc = prepare_sort(ctx, n, og.ntx * og.nty, ssb))) return rc;
+        GCB_HIP(launch_cell_sort(start->x, start->y, n, 1.0 / ctx->dx, 1.0 / ctx->dy, og, ssb,
+                                 stream));
+        // the sort's buffers serve the recomputation's sorts too: keep the
+        // permutation
+        GCB_HIP(hipMemcpyAsync(perm, ssb.idx, (size_t)n * 4, hipMemcpyDeviceToDevice, stream));
+        if (start->qm) GCB_HIP(launch_permute_f64(start->qm, perm, n, qms, false, stream));
+    }
     if (n > 0) {
-        for (int c = 0; c < 7; ++c)
-            GCB_HIP(hipMemcpyAsync(work + c * (size_t)n, src[c], nd, hipMemcpyDeviceToDevice,
-                                   stream));
+        for (int c = 0; c < 7; ++c) {
+            if (perm)
+                GCB_HIP(launch_permute_f64(src[c], perm, n, work + c * (size_t)n, false, stream));
+            else
+                GCB_HIP(hipMemcpyAsync(work + c * (size_t)n, src[c], nd,
+                                       hipMemcpyDeviceToDevice, stream));
+        }
         GCB_HIP(hipMemsetAsync(wstatus, 0, (size_t)n, stream));
     }
+    double* wqm = (perm && start->qm) ? qms : start->qm;
     ParticlePtrs<double> w{};
     w.x = work;
     w.y = work + n;
@@ -1009,7 +1048,7 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
     w.ux = work + 4 * n;
     w.uy = work + 5 * n;
     w.uz = work + 6 * n;
-    w.qm = start->qm;
+    w.qm = wqm;
     w.id = nullptr;
     w.status = wstatus;
     const PushConst pc = make_const(ctx, prm);
@@ -1022,8 +1061,7 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
         gcb_params rp = *prm;
         rp.keep_order = 1;
         rp.replay = 0;
-        gcb_particles wp{n, w.x, w.y, w.xp, w.yp, w.ux, w.uy, w.uz, start->qm, nullptr,
-                         wstatus};
+        gcb_particles wp{n, w.x, w.y, w.xp, w.yp, w.ux, w.uy, w.uz, wqm, nullptr, wstatus};
         const bool timing = ctx->timing;   // timed as part of the backward pass
         ctx->timing = false;
         rc = run_push<double>(ctx, &wp, &rp, n_steps, trace, nullptr, stream, states);
@@ -1039,9 +1077,13 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
         GCB_HIP(launch_gca_lists(trace, n, n_steps, lists, counts, stream));
     }
     // reverse sweep
-    for (int c = 0; c < 7 && n > 0; ++c)
-        GCB_HIP(hipMemcpyAsync(lam + c * (size_t)n, lam_end[c], nd, hipMemcpyDeviceToDevice,
-                               stream));
+    for (int c = 0; c < 7 && n > 0; ++c) {
+        if (perm)
+            GCB_HIP(launch_permute_f64(lam_end[c], perm, n, lam + c * (size_t)n, false, stream));
+        else
+            GCB_HIP(hipMemcpyAsync(lam + c * (size_t)n, lam_end[c], nd, hipMemcpyDeviceToDevice,
+                                   stream));
+    }
     GCB_HIP(hipMemsetAsync(grad, 0, nodes * 6 * sizeof(float), stream));
     // steps in reverse order, in batches [s_lo, s_hi) of at most `batch` steps:
     // the vector-Jacobian products of the batch's steps, then one scatter
@@ -1051,7 +1093,7 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
         A.yee = ctx->yee;
         A.fields = static_cast<const double*>(ctx->fields.ptr);
         A.n = n;
-        A.qm = start->qm;
+        A.qm = wqm;
         A.grad_fields = grad;
         A.records = ctx->adj_samples.ptr;
         A.batch = batch;
@@ -1065,9 +1107,14 @@ int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start, const gcb_params
         }
         GCB_HIP(launch_adjoint_scatter(A, trace + (size_t)s_lo * n, s_hi - s_lo, pc, stream));
     }
-    for (int c = 0; c < 7 && n > 0; ++c)
-        GCB_HIP(hipMemcpyAsync(lam_start[c], lam + c * (size_t)n, nd, hipMemcpyDeviceToDevice,
-                               stream));
+    for (int c = 0; c < 7 && n > 0; ++c) {
+        if (perm)
+            GCB_HIP(launch_permute_f64(lam + c * (size_t)n, perm, n, lam_start[c], true,
+                                       stream));
+        else
+            GCB_HIP(hipMemcpyAsync(lam_start[c], lam + c * (size_t)n, nd,
+                                   hipMemcpyDeviceToDevice, stream));
+    }
     if (n_steps == 0 && n > 0)
         for (int c = 0; c < 7; ++c)
             GCB_HIP(hipMemcpyAsync(lam_start[c], lam_end[c], nd, hipMemcpyDeviceToDevice,

@@ -153,6 +153,10 @@ hipError_t launch_count_flagged(const uint8_t* status, int64_t n,
 hipError_t launch_zero_words(void* p, int64_t words, hipStream_t stream);
 
 // the library's binary64 sin and cos of n values (device arrays)
+// dst[s] = src[perm[s]] (inverse: dst[perm[s]] = src[s]) for n binary64 values
+hipError_t launch_permute_f64(const double* src, const uint32_t* perm, int64_t n, double* dst,
+                              bool inverse, hipStream_t stream);
+
 hipError_t launch_sincos(const double* x, double* s, double* c, int64_t n,
                          hipStream_t stream);
 

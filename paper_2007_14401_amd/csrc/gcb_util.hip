@@ -120,6 +120,33 @@ __global__ __launch_bounds__(kWG) void k_sincos(const double* __restrict__ x, do
 
 }  // namespace
 
+// dst[s] = src[perm[s]] for n binary64 values (perm: sorted slot -> source slot)
+__global__ __launch_bounds__(kWG) void k_gather_f64(const double* __restrict__ src,
+                                                    const uint32_t* __restrict__ perm,
+                                                    int64_t n, double* __restrict__ dst) {
+    const int64_t s = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (s < n) dst[s] = src[perm[s]];
+}
+
+// dst[perm[s]] = src[s], the inverse of k_gather_f64
+__global__ __launch_bounds__(kWG) void k_scatter_f64(const double* __restrict__ src,
+                                                     const uint32_t* __restrict__ perm,
+                                                     int64_t n, double* __restrict__ dst) {
+    const int64_t s = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (s < n) dst[perm[s]] = src[s];
+}
+
+hipError_t launch_permute_f64(const double* src, const uint32_t* perm, int64_t n, double* dst,
+                              bool inverse, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n + kWG - 1) / kWG);
+    if (inverse)
+        hipLaunchKernelGGL(k_scatter_f64, dim3(blocks), dim3(kWG), 0, stream, src, perm, n, dst);
+    else
+        hipLaunchKernelGGL(k_gather_f64, dim3(blocks), dim3(kWG), 0, stream, src, perm, n, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_sincos(const double* x, double* s, double* c, int64_t n,
                          hipStream_t stream) {
     if (n <= 0) return hipSuccess;
