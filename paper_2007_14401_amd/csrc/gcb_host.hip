@@ -440,6 +440,11 @@ constexpr size_t kAdjRecordBudget = 128ull << 30;
 #define GCB_ADJ_ORDER_TILE 32
 #endif
 constexpr int kAdjOrderTile = GCB_ADJ_ORDER_TILE;
+// The same for the 3D backward (cubic tiles).
+#ifndef GCB_ADJ3_ORDER_TILE
+#define GCB_ADJ3_ORDER_TILE 8
+#endif
+constexpr int kAdj3OrderTile = GCB_ADJ3_ORDER_TILE;
 constexpr int kAdj3MaxBatch = 8;
 constexpr size_t kAdj3RecordBudget = 32ull << 30;
 
@@ -1438,6 +1443,21 @@ int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_pa
     batch = std::max(1, std::min(batch, std::max(1, (int)n_steps)));
     if ((rc = ensure(ctx, ctx->adj_samples, adjoint3_record_bytes(n, prm->n_iter, batch))))
         return rc;
+    // the segment's particles in the tile order of their start positions, as
+    // in the 2D backward (cubic kAdj3OrderTile-cell tiles)
+    TileGeom3 og{};
+    og.tile = kAdj3OrderTile;
+    og.ntx = (ctx->n3[0] + og.tile - 1) / og.tile;
+    og.nty = (ctx->n3[1] + og.tile - 1) / og.tile;
+    og.ntz = (ctx->n3[2] + og.tile - 1) / og.tile;
+    const bool ordered = n > 0 && n_steps > 0;
+    double* qms = nullptr;          // q/m in tile order
+    uint32_t* perm = nullptr;       // tile slot -> caller's slot
+    if (ordered) {
+        if ((rc = ensure(ctx, ctx->adj_order, nd + (size_t)n * 4))) return rc;
+        qms = static_cast<double*>(ctx->adj_order.ptr);
+        perm = reinterpret_cast<uint32_t*>(qms + n);
+    }
     double* work = static_cast<double*>(ctx->adj_work.ptr);
     uint8_t* wstatus = reinterpret_cast<uint8_t*>(work + kS * (size_t)n);
     double* states = static_cast<double*>(ctx->adj_states.ptr);
@@ -1450,12 +1470,25 @@ int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_pa
                              static_cast<const double*>(start->uy),
                              static_cast<const double*>(start->uz)};
     Timer t(ctx, stream, GCB_TIMER_BACKWARD);
+    if (ordered) {
+        SortBuffers ssb{};
+        if ((rc = prepare_sort(ctx, n, og.ntx * og.nty * og.ntz, ssb))) return rc;
+        GCB_HIP(launch_cell_sort3(start->x, start->y, start->z, n, 1.0 / ctx->d3[0],
+                                  1.0 / ctx->d3[1], 1.0 / ctx->d3[2], og, ssb, stream));
+        GCB_HIP(hipMemcpyAsync(perm, ssb.idx, (size_t)n * 4, hipMemcpyDeviceToDevice, stream));
+        if (start->qm) GCB_HIP(launch_permute_f64(start->qm, perm, n, qms, false, stream));
+    }
     if (n > 0) {
-        for (int c = 0; c < kS; ++c)
-            GCB_HIP(hipMemcpyAsync(work + c * (size_t)n, src[c], nd, hipMemcpyDeviceToDevice,
-                                   stream));
+        for (int c = 0; c < kS; ++c) {
+            if (perm)
+                GCB_HIP(launch_permute_f64(src[c], perm, n, work + c * (size_t)n, false, stream));
+            else
+                GCB_HIP(hipMemcpyAsync(work + c * (size_t)n, src[c], nd,
+                                       hipMemcpyDeviceToDevice, stream));
+        }
         GCB_HIP(hipMemsetAsync(wstatus, 0, (size_t)n, stream));
     }
+    double* wqm = (perm && start->qm) ? qms : start->qm;
     ParticlePtrs3<double> w{};
     w.b.x = work;
     w.b.y = work + n;
@@ -1466,7 +1499,7 @@ int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_pa
     w.b.ux = work + 6 * n;
     w.b.uy = work + 7 * n;
     w.b.uz = work + 8 * n;
-    w.b.qm = start->qm;
+    w.b.qm = wqm;
     w.b.id = nullptr;
     w.b.status = wstatus;
     const PushConst3 pc = make_const3(ctx, prm);
@@ -1494,9 +1527,13 @@ int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_pa
         GCB_HIP(launch_gca_lists(trace, n, n_steps, lists, counts, stream));
     }
     // reverse sweep
-    for (int c = 0; c < kS && n > 0; ++c)
-        GCB_HIP(hipMemcpyAsync(lam + c * (size_t)n, lam_end[c], nd, hipMemcpyDeviceToDevice,
-                               stream));
+    for (int c = 0; c < kS && n > 0; ++c) {
+        if (perm)
+            GCB_HIP(launch_permute_f64(lam_end[c], perm, n, lam + c * (size_t)n, false, stream));
+        else
+            GCB_HIP(hipMemcpyAsync(lam + c * (size_t)n, lam_end[c], nd, hipMemcpyDeviceToDevice,
+                                   stream));
+    }
     GCB_HIP(hipMemsetAsync(grad, 0, nodes * 6 * sizeof(float), stream));
     for (int32_t s_hi = n_steps; s_hi > 0 && n > 0; s_hi -= batch) {
         const int32_t s_lo = std::max<int32_t>(0, s_hi - batch);
@@ -1504,7 +1541,7 @@ int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_pa
         A.yee = ctx->yee3;
         A.fields = static_cast<const double*>(ctx->fields3.ptr);
         A.n = n;
-        A.qm = start->qm;
+        A.qm = wqm;
         A.grad_fields = grad;
         A.records = ctx->adj_samples.ptr;
         A.batch = batch;
@@ -1518,9 +1555,14 @@ int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_pa
         }
         GCB_HIP(launch_adjoint3_scatter(A, trace + (size_t)s_lo * n, s_hi - s_lo, pc, stream));
     }
-    for (int c = 0; c < kS && n > 0; ++c)
-        GCB_HIP(hipMemcpyAsync(lam_start[c], lam + c * (size_t)n, nd, hipMemcpyDeviceToDevice,
-                               stream));
+    for (int c = 0; c < kS && n > 0; ++c) {
+        if (perm)
+            GCB_HIP(launch_permute_f64(lam + c * (size_t)n, perm, n, lam_start[c], true,
+                                       stream));
+        else
+            GCB_HIP(hipMemcpyAsync(lam_start[c], lam + c * (size_t)n, nd,
+                                   hipMemcpyDeviceToDevice, stream));
+    }
     if (n_steps == 0 && n > 0)
         for (int c = 0; c < kS; ++c)
             GCB_HIP(hipMemcpyAsync(lam_start[c], lam_end[c], nd, hipMemcpyDeviceToDevice,
