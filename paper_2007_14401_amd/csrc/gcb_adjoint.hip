@@ -70,7 +70,10 @@ struct RecordSink {
 // The guiding-center VJP keeps the field samples of R^{n-1/2}, R^n and the
 // first iterates of its forward recomputation in LDS (one column per lane)
 // and takes them again in the reverse sweep instead of a second gather.
-constexpr int kKeepSlots = 5;
+#ifndef GCB_ADJ_KEEP_SLOTS
+#define GCB_ADJ_KEEP_SLOTS 5
+#endif
+constexpr int kKeepSlots = GCB_ADJ_KEEP_SLOTS;
 constexpr int kSampleVals = 12;   // E, B, dB/dx, dB/dy
 
 struct LdsSamples {
