@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--mixed-tile", type=int, default=28)
     ap.add_argument("--mixed-sort-every", type=int, default=10,
                     help="cell-sort period of the mixed form (default: --sort-every)")
+    ap.add_argument("--mixed-1e8-steps", type=int, default=20,
+                    help="steps of the precision form at 1e8 particles (0: skip)")
     ap.add_argument("--f-rho", type=float, default=None)
     ap.add_argument("--f-E", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -264,14 +266,15 @@ def main():
 
     dev = torch.device("cuda:0")
 
-    def time_form(form: int, fields_dtype: int, steps: int, warmup: int, **extra):
-        """Time `steps` pushes of the whole population in one form (extra:
-        overrides of the push parameters)."""
+    def time_form(form: int, fields_dtype: int, steps: int, warmup: int, ens_=None, **extra):
+        """Time `steps` pushes of the whole population (ens_, else the
+        workload's) in one form (extra: overrides of the push parameters)."""
         ctx = gcb.gcb_create(0)
         try:
             desc = gcb.grid_desc(cfg.nx, cfg.ny, cfg.dx, cfg.dy, cfg.stagger, fields_dtype)
             gcb.gcb_load_fields(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
-            t = state.to_device(ens, dev, form=form, per_particle_qm=False)
+            t = state.to_device(ens if ens_ is None else ens_, dev, form=form,
+                                per_particle_qm=False)
             parts = gcb.particles(t)
             kw = dict(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
                       n_iter=cfg.n_iter, form=form, sort_every=a.sort_every, kernel=a.kernel,
@@ -550,8 +553,8 @@ def main():
     traffic = measured_traffic(cfg.name, n, a.sort_every, a.tile)
 
     def roof(flops_pp: float, kms: float, nbytes: float) -> dict:
-        """Both roofs of a push launch: algorithmic flops and bytes per launch
-        over its HIP-event duration, and which roof the arithmetic intensity
+        """Both roofs of a push: algorithmic flops and bytes per step over its
+        HIP-event time per step, and which roof the arithmetic intensity
         puts it under (the ridge of the binary64 vector peak and the HBM
         peak: 78.6 TFLOP/s / 8 TB/s = 9.8 flop/B)."""
         tf = flops_pp * n / (kms * 1e-3) / 1e12
@@ -559,7 +562,7 @@ def main():
         ai = flops_pp * n / nbytes
         ridge = FP64_VECTOR_PEAK_TF * 1e12 / (HBM_PEAK_GBS * 1e9)
         return {"kernel_ms": kms, "algorithmic_flops_per_particle_step": flops_pp,
-                "algorithmic_bytes_per_launch": nbytes,
+                "algorithmic_bytes_per_step": nbytes,
                 "arithmetic_intensity_flop_per_byte": ai,
                 "bound_by_intensity": "hbm" if ai < ridge else "alu",
                 "alu_achieved_TFLOPs": tf, "alu_frac": tf / FP64_VECTOR_PEAK_TF,
@@ -602,10 +605,29 @@ def main():
             "sort_ms_per_sort": rm["sort_ms"],
             "hbm_achieved_GBs": bm / (rm["push_ms"] * 1e-3) / 1e9,
             "hbm_frac": bm / (rm["push_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "algorithmic_bytes_per_launch": bm,
+            "algorithmic_bytes_per_step": bm,
             "speedup_vs_f64": (n * a.steps / rm["wall"]) / value,
             "tile": a.mixed_tile, "sort_every": mse,
             "dtype": "f32 bulk, f64 positions"}
+        if a.mixed_1e8_steps > 0 and a.config == "harris4096" and a.n is None:
+            # the precision form's second size: 1e8 particles on the same fields
+            n8 = 100_000_000
+            log(f"[bench] mixed form at {n8} particles: generating")
+            ens8 = cfg.particles(n=n8)
+            r8 = time_form(gcb.GCB_FORM_MIXED, gcb.GCB_F32, a.mixed_1e8_steps, 2, ens_=ens8,
+                           tile=a.mixed_tile, sort_every=mse)
+            del ens8
+            b8 = push_bytes_per_step(n8, cfg.nx, cfg.ny, 1)
+            forms["mixed_1e8"] = {
+                "workload": "harris4096 fields, 100000000 particles of the same mix",
+                "value": n8 * a.mixed_1e8_steps / r8["wall"], "unit": "particle-steps/s",
+                "steps": a.mixed_1e8_steps,
+                "ms_per_step": r8["wall"] * 1e3 / a.mixed_1e8_steps, "kernel_ms": r8["push_ms"],
+                "hbm_achieved_GBs": b8 / (r8["push_ms"] * 1e-3) / 1e9,
+                "hbm_frac": b8 / (r8["push_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "algorithmic_bytes_per_step": b8,
+                "tile": a.mixed_tile, "sort_every": mse,
+                "dtype": "f32 bulk, f64 positions"}
 
     if not a.no_gr:
         forms["gr"] = time_gr(a.gr_steps, a.gr_warmup)
