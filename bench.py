@@ -388,7 +388,8 @@ def main():
             st = {k: torch.as_tensor(getattr(e3, k)[order], dtype=torch.float64, device=dev)
                   .requires_grad_(True) for k in names}
             prm = gcb.params(dt=c3.dt, c=c3.c, qm=c3.qm, f_rho=c3.f_rho, f_E=c3.f_E,
-                             curvature=c3.curvature, n_iter=c3.n_iter)
+                             curvature=c3.curvature, n_iter=c3.n_iter,
+                             sort_every=a.d3_sort_every, tile=a.d3_tile)
             out = A.push3(E, B, *[st[k] for k in names], None, pctx, prm, 2, checkpoint)
             A.kinetic_energy(out[6], out[7], out[8], pctx, prm).backward()
             for v in list(st.values()) + [E, B]:
@@ -409,7 +410,9 @@ def main():
                     "steps": steps, "checkpoint": checkpoint, "seconds": t1 - t0,
                     "forward_push_ms_per_step": ms[gcb.GCB_TIMER_PUSH] / max(1, steps),
                     "backward_ms_per_step": ms[gcb.GCB_TIMER_BACKWARD] / max(1, steps),
-                    "kernel": "k_push3_global + k_adjoint3_step (unsorted, binary64)",
+                    "sort_every": a.d3_sort_every, "tile": a.d3_tile,
+                    "kernel": "k_push3_tiled in place (keep_order, parity binary64) + "
+                              "k_adjoint3_step + k_scatter3_batch",
                     "loss": float(L)}
         finally:
             pctx.close()

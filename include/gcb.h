@@ -228,8 +228,9 @@ typedef struct {
                             arrays keep their order and a switch trace needs no ids
                             (trace column = slot); the results are those of any other
                             order.  0 (default): sorting permutes the arrays.  Values
-                            other than 0 and 1: GCB_EINVAL; gcb_push, gcb_push_noalloc
-                            and gcb_push_backward only (else GCB_EUNSUPPORTED) */
+                            other than 0 and 1: GCB_EINVAL; gcb_push, gcb_push_noalloc,
+                            gcb_push_3d and the backward passes only (else
+                            GCB_EUNSUPPORTED) */
 } gcb_params;
 
 /* Particle state, structure of arrays, caller-owned device memory of length n.
@@ -296,10 +297,14 @@ int gcb_push_noalloc(gcb_ctx* ctx, gcb_particles* p, const gcb_params* prm,
    derivatives at the segment start (double, overwritten).  dE[3], dB[3]:
    device float arrays of nx*ny elements, element [j*nx+i] of component k,
    ACCUMULATED (+=) with dL/dF at every node.  Only GCB_FORM_F64 with
-   fields loaded as GCB_F64.  The forward steps are recomputed internally
-   (unsorted); needs n_steps * n * 61 bytes of context scratch plus the
-   gather-point records of up to 32 steps (64 bytes per gather point, at most
-   128 GiB and half the device memory free at the call). */
+   fields loaded as GCB_F64.  The call works on the particles in the tile
+   order of their start positions (permuted in and the adjoint permuted back;
+   no result depends on the order).  The forward steps are recomputed
+   internally: with params.sort_every > 0 by the tiled push in place
+   (keep_order), else by the cache-served kernel; needs n_steps * n * 61 +
+   n * 12 bytes of context scratch plus the gather-point records of up to 32
+   steps (64 bytes per gather point, at most 128 GiB and half the device
+   memory free at the call). */
 int gcb_push_backward(gcb_ctx* ctx, const gcb_particles* start,
                       const gcb_params* prm, int32_t n_steps,
                       const double* const lam_end[7], double* const lam_start[7],
@@ -451,10 +456,13 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm,
    dE[3], dB[3]: device float arrays of nx*ny*nz elements, element
    [(l*ny + j)*nx + i] of component k, ACCUMULATED (+=) with dL/dF at every
    node.  Only GCB_FORM_F64 with 3D fields loaded as GCB_F64, the reduced
-   frame, mu conserved and n_iter <= 8 (else GCB_EUNSUPPORTED).  The forward
-   steps are recomputed internally (unsorted); needs n_steps * n * 77 bytes
-   of context scratch plus the gather-point records of up to 8 steps (84 bytes
-   per gather point, at most 32 GiB and half the device memory free). */
+   frame, mu conserved and n_iter <= 8 (else GCB_EUNSUPPORTED).  As in 2D the
+   call works in the tile order of the start positions, and the forward steps
+   are recomputed internally: with params.sort_every > 0 and a tile window
+   that fits in LDS by the tiled push in place (keep_order), else by the
+   cache-served kernel; needs n_steps * n * 77 + n * 12 bytes of context
+   scratch plus the gather-point records of up to 8 steps (84 bytes per
+   gather point, at most 32 GiB and half the device memory free). */
 int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_params* prm,
                          int32_t n_steps, const double* const lam_end[9],
                          double* const lam_start[9], float* const dE[3], float* const dB[3],

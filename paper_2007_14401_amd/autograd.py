@@ -21,9 +21,9 @@ of a finite-difference pair) loads its own again before recomputing.
 
 Argument marshalling and segment bookkeeping only: every step of the push and
 of its derivative runs in the library's kernels.  The 2D push sorts in place
-(gcb_params keep_order), so the arrays keep their order; the 3D push runs
-unsorted.  Forward and recomputation use the parity arithmetic, so they agree
-bit for bit whatever kernel runs them.
+(gcb_params keep_order), so the arrays keep their order; so does the 3D push.
+Forward and recomputation use the parity arithmetic, so they agree bit for
+bit whatever kernel runs them.
 """
 from __future__ import annotations
 
@@ -199,12 +199,18 @@ class GcbPush3(torch.autograd.Function):
 
 def push3(E, B, x, y, z, xp, yp, zp, ux, uy, uz, qm, pctx, prm, n_steps, checkpoint=32):
     """Differentiable 3D push; returns the final (x, y, z, xp, yp, zp, ux, uy, uz)
-    in input order (no cell sort)."""
+    in input order.
+
+    As in 2D, the particles are cell-sorted in place (keep_order) every
+    prm.sort_every steps (4 when it is 0), in cubic tiles of prm.tile cells (4
+    when it is 0), so the tiled kernel does the work; gcb_push_backward_3d
+    recomputes the same way."""
     prm = gcb.gcb_params.from_buffer_copy(prm)
-    prm.sort_every = 0
-    prm.keep_order = 0
-    if prm.kernel == gcb.GCB_KERNEL_TILED:
-        prm.kernel = gcb.GCB_KERNEL_AUTO
+    if prm.sort_every <= 0:
+        prm.sort_every = 4
+    if prm.tile <= 0:
+        prm.tile = 4
+    prm.keep_order = 1
     return GcbPush3.apply(E, B, x, y, z, xp, yp, zp, ux, uy, uz, qm, pctx, prm, int(n_steps),
                           int(checkpoint))
 

@@ -726,9 +726,12 @@ ParticlePtrs3<U> ptrs3_of(const gcb_particles3* p) {
     return r;
 }
 
+// record (binary64, keep_order, tiled kernel): the start state of every
+// step, 9 arrays of n doubles per step (the adjoint's recomputation)
 template <typename U>
 int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_steps,
-              uint8_t* s_trace, DevStats* dstats, hipStream_t stream) {
+              uint8_t* s_trace, DevStats* dstats, hipStream_t stream,
+              double* record = nullptr) {
     const int64_t n = p->n;
     const PushConst3 pc = make_const3(ctx, prm);
     const TileGeom3 g = make_geom3(ctx, prm);
@@ -738,15 +741,23 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
     PushKind kind;
     int rc;
     if ((rc = choose_kind(ctx, prm, tiled_ok, g.window, &kind))) return rc;
+    if (record && kind != PushKind::Tiled)
+        return fail(ctx, GCB_EUNSUPPORTED, "start-state records need the tiled kernel");
     ParticlePtrs3<U> user = ptrs3_of<U>(p);
     ParticlePtrs3<U> scr{};
     SortBuffers sb{};
-    if (prm->sort_every > 0 && n > 0) {
+    // keep_order: the tiled kernel works through the tiles of each sort in
+    // place (the arrays keep their order); the global kernel needs no sort
+    const bool keep = prm->keep_order != 0;
+    const bool sorting = prm->sort_every > 0 && n > 0 && !(keep && kind == PushKind::Global);
+    if (sorting) {
         if ((rc = prepare_sort(ctx, n, g.ntx * g.nty * g.ntz, sb))) return rc;
-        double* zz[2];
-        if ((rc = scratch_state<U>(ctx, user.b, n, scr.b, 2, zz))) return rc;
-        scr.z = zz[0];
-        scr.zp = zz[1];
+        if (!keep) {
+            double* zz[2];
+            if ((rc = scratch_state<U>(ctx, user.b, n, scr.b, 2, zz))) return rc;
+            scr.z = zz[0];
+            scr.zp = zz[1];
+        }
     }
     // sort steps move the state into the other buffer, as in 2D
     constexpr int32_t kGlobalStepsPerLaunch = 16;
@@ -754,17 +765,21 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
     for (int32_t step = 0; step < n_steps;) {
         int32_t ns = std::min(kind == PushKind::Global ? kGlobalStepsPerLaunch : kTiledMaxSteps,
                               n_steps - step);
-        if (prm->sort_every > 0) ns = std::min(ns, prm->sort_every - step % prm->sort_every);
+        if (sorting) ns = std::min(ns, prm->sort_every - step % prm->sort_every);
         ParticlePtrs3<U> dst = cur;
         const uint32_t* perm = nullptr;
-        if (prm->sort_every > 0 && n > 0 && step % prm->sort_every == 0) {
+        if (sorting && step % prm->sort_every == 0) {
             Timer t(ctx, stream, GCB_TIMER_SORT);
             GCB_HIP(launch_cell_sort3(cur.b.x, cur.b.y, cur.z, n, pc.b.inv_dx, pc.b.inv_dy,
                                       pc.inv_dz, g, sb, stream));
             t.done();
             perm = sb.idx;
-            dst = other;
+            if (!keep) dst = other;
         }
+        // in place, the sort's permutation serves every launch until the next
+        if (sorting && keep) perm = sb.idx;
+        cur.b.rec = record ? record + (size_t)step * 9 * n : nullptr;
+        dst.b.rec = cur.b.rec;
         Push3Launch L;
         L.perm = perm;
         L.kind = kind;
@@ -790,7 +805,7 @@ int run_push3(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t n_
         if (e != hipSuccess)
             return fail(ctx, GCB_EHIP, "push kernel launch failed: %s", hipGetErrorString(e));
         t.done();
-        if (perm) std::swap(cur, other);
+        if (perm && !keep) std::swap(cur, other);
         step += ns;
     }
     if (cur.b.x != user.b.x) {
@@ -1200,7 +1215,8 @@ int gcb_push_gr(gcb_ctx* ctx, gcb_gr_particles* p, const gcb_params* prm, int32_
         if (rc) return rc;
     }
     if (prm->keep_order != 0)
-        return fail(ctx, GCB_EUNSUPPORTED, "keep_order is served by gcb_push only");
+        return fail(ctx, GCB_EUNSUPPORTED,
+                    "keep_order is served by gcb_push and gcb_push_3d only");
     if (p->n < 0) return fail(ctx, GCB_EINVAL, "n must be >= 0");
     if (n_steps < 0) return fail(ctx, GCB_EINVAL, "n_steps must be >= 0");
     if (p->n > 0 && (!p->r || !p->th || !p->ph || !p->ur || !p->uth || !p->uph || !p->status))
@@ -1360,8 +1376,6 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t 
     if ((rc = validate_params(ctx, prm))) return rc;
     if (prm->arith == GCB_ARITH_FAST && prm->form != GCB_FORM_F64)
         return fail(ctx, GCB_EUNSUPPORTED, "GCB_ARITH_FAST needs GCB_FORM_F64");
-    if (prm->keep_order != 0)
-        return fail(ctx, GCB_EUNSUPPORTED, "keep_order is served by gcb_push only");
     // the 2D checks on the x, y, u, qm, id and status arrays, then z
     gcb_particles view{p->n, p->x, p->y, p->xp, p->yp, p->ux, p->uy, p->uz, p->qm, p->id,
                        p->status};
@@ -1378,7 +1392,7 @@ int gcb_push_3d(gcb_ctx* ctx, gcb_particles3* p, const gcb_params* prm, int32_t 
         return fail(ctx, GCB_EINVAL, "GCB_FORM_F64 needs fields loaded as GCB_F64");
     if (prm->form == GCB_FORM_MIXED && ctx->dtype3 != GCB_F32)
         return fail(ctx, GCB_EINVAL, "GCB_FORM_MIXED needs fields loaded as GCB_F32");
-    if (s_trace && p->n > 0 && !p->id && prm->sort_every > 0)
+    if (s_trace && p->n > 0 && !p->id && prm->sort_every > 0 && !prm->keep_order)
         return fail(ctx, GCB_EINVAL, "a switch trace with sorting needs particle ids");
     if (prm->replay && !s_trace && p->n > 0 && n_steps > 0)
         return fail(ctx, GCB_EINVAL, "replay needs the switch trace s_trace");
@@ -1503,8 +1517,30 @@ int gcb_push_backward_3d(gcb_ctx* ctx, const gcb_particles3* start, const gcb_pa
     w.b.id = nullptr;
     w.b.status = wstatus;
     const PushConst3 pc = make_const3(ctx, prm);
-    // forward recomputation, keeping each step's start state and decisions
-    for (int32_t s = 0; s < n_steps && n > 0; ++s) {
+    // forward recomputation, keeping each step's start state and decisions:
+    // with sort_every > 0 and a window that fits, the tiled push in place
+    // (keep_order), which records the start state of every step inside its
+    // launches; otherwise one launch of the global kernel and one state copy
+    // per step.  The parity arithmetic makes either the forward pass bit for
+    // bit.
+    gcb_params rp = *prm;
+    rp.keep_order = 1;
+    rp.replay = 0;
+    const TileGeom3 rg = make_geom3(ctx, &rp);
+    const bool tiled_rec = n > 0 && n_steps > 0 && rp.sort_every > 0 &&
+                           rp.kernel != GCB_KERNEL_GLOBAL && rg.window > 0 &&
+                           tiled3_lds_bytes(rg.window, sizeof(double)) <= kMaxLds;
+    if (tiled_rec) {
+        rp.kernel = GCB_KERNEL_TILED;
+        gcb_particles3 wp{n,    w.b.x, w.b.y, w.z,  w.b.xp, w.b.yp, w.zp,
+                          w.b.ux, w.b.uy, w.b.uz, wqm,  nullptr, wstatus};
+        const bool timing = ctx->timing;   // timed as part of the backward pass
+        ctx->timing = false;
+        rc = run_push3<double>(ctx, &wp, &rp, n_steps, trace, nullptr, stream, states);
+        ctx->timing = timing;
+        if (rc) return rc;
+    }
+    for (int32_t s = 0; s < n_steps && n > 0 && !tiled_rec; ++s) {
         GCB_HIP(hipMemcpyAsync(states + (size_t)s * kS * n, work, kS * nd,
                                hipMemcpyDeviceToDevice, stream));
         Push3Launch L;

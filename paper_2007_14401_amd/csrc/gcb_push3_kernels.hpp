@@ -2,7 +2,9 @@
 // field storage type T.
 //
 // As in 2D, both read slot perm[p] of `in` (p when perm is null) and write
-// slot p of `out`.
+// slot p of `out`; the tiled kernel given a permutation with `out` equal to
+// `in` keeps the order (keep_order: it writes each particle back to its own
+// slot), and its recording instances write each step's start state.
 //
 // k_push3_global: one lane per particle, up to `ns` steps per launch with the
 //   particle in registers, gathers through the caches.
@@ -59,6 +61,22 @@ __device__ __forceinline__ void store_particle3(const ParticlePtrs3<R>& in,
         if (in.b.qm) out.b.qm[p] = r.qm;
         if (in.b.id) out.b.id[p] = in.b.id[src];
     }
+}
+
+// start state of a step into the records (x, y, z, xp, yp, zp, ux, uy, uz,
+// arrays of n; the adjoint's recomputation)
+template <typename R>
+__device__ __forceinline__ void record_state3(double* rec, int64_t n, int64_t i,
+                                              const Regs3<R>& r) {
+    rec[i] = r.x;
+    rec[n + i] = r.y;
+    rec[2 * n + i] = r.z;
+    rec[3 * n + i] = r.xp;
+    rec[4 * n + i] = r.yp;
+    rec[5 * n + i] = r.zp;
+    rec[6 * n + i] = (double)r.ux;
+    rec[7 * n + i] = (double)r.uy;
+    rec[8 * n + i] = (double)r.uz;
 }
 
 template <typename R, bool kYee, int kVar, class Acc>
@@ -130,7 +148,7 @@ __global__ __launch_bounds__(kWG) void k_push3_global(ParticlePtrs3<R> in,
 // split into the two queues by the branch of its first step, and each lane
 // then keeps a particle in registers for every step of the launch,
 // re-evaluating the switch at every step from the gather the update uses.
-template <typename R, typename T, bool kYee, int kMinWaves, int kVar>
+template <typename R, typename T, bool kYee, int kMinWaves, int kVar, bool kRec = false>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void
 k_push3_tiled(ParticlePtrs3<R> in_arg, ParticlePtrs3<R> out_arg,
               const uint32_t* __restrict__ perm, const int32_t* __restrict__ tile_start,
@@ -208,13 +226,16 @@ k_push3_tiled(ParticlePtrs3<R> in_arg, ParticlePtrs3<R> out_arg,
         for (int q = threadIdx.x; q < m; q += kWG) {
             const int64_t p = base + queue[q];
             const int64_t src = perm ? (int64_t)perm[p] : p;
-            const int64_t tid = in.b.id ? (int64_t)in.b.id[src] : p;   // trace column
+            const bool keep = perm && out.b.x == in.b.x;
+            const int64_t slot = keep ? src : p;   // where the particle is written
+            const int64_t tid = in.b.id ? (int64_t)in.b.id[src] : slot;   // trace column
             Regs3<R> r;
             load_particle3(in, src, pc.b.qm, r);
             uint32_t fl = 0;
             bool gca = q < nG;
             for (int st = 0; st < steps; ++st) {
                 uint8_t* tr = trace ? trace + (int64_t)st * n : nullptr;
+                if constexpr (kRec) record_state3(in.b.rec + (int64_t)st * 9 * n, n, tid, r);
                 // the gather at x^n serves the switch and the update; the
                 // gradients are formed for the branch of the previous step
                 const bool prev = gca;
@@ -251,19 +272,20 @@ k_push3_tiled(ParticlePtrs3<R> in_arg, ParticlePtrs3<R> out_arg,
                     ++cnt_b;
                 }
             }
-            store_particle3(in, out, p, src, r, fl);
+            store_particle3(in, out, slot, src, r, fl);
         }
         __syncthreads();   // the queue is rebuilt for the next chunk
     }
     if (stats) flush_stats(stats, cnt_g, cnt_b, cnt_h, maxres);
 }
 
-template <typename R, typename T, int kMinWaves, int kVar>
+template <typename R, typename T, int kMinWaves, int kVar, bool kRec = false>
 hipError_t launch_push3_frame(const Push3Launch& L, const ParticlePtrs3<R>& in,
                               const ParticlePtrs3<R>& out, const PushConst3& pc,
                               hipStream_t stream) {
     const T* F = static_cast<const T*>(L.fields);
     if (L.kind == PushKind::Global) {
+        if (kRec) return hipErrorInvalidValue;   // records: the tiled kernel only
         const unsigned blocks = (unsigned)((L.n + kWG - 1) / kWG);
         const int ns = L.steps > 0 ? L.steps : 1;
         if (L.yee)
@@ -281,14 +303,14 @@ hipError_t launch_push3_frame(const Push3Launch& L, const ParticlePtrs3<R>& in,
     const int ns = L.steps > 0 ? L.steps : 1;
     const size_t lds = tiled3_lds_bytes(L.geom.window, sizeof(T));
     if (L.yee) {
-        auto kfn = k_push3_tiled<R, T, true, kMinWaves, kVar>;
+        auto kfn = k_push3_tiled<R, T, true, kMinWaves, kVar, kRec>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
                            L.tile_start, L.geom, chunk, F, pc, L.trace, L.n, ns, L.replay,
                            L.stats);
     } else {
-        auto kfn = k_push3_tiled<R, T, false, kMinWaves, kVar>;
+        auto kfn = k_push3_tiled<R, T, false, kMinWaves, kVar, kRec>;
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(kfn, dim3(8 * chunk), dim3(kWG), lds, stream, in, out, L.perm,
@@ -304,6 +326,17 @@ template <typename R, typename T, int kMinWaves>
 hipError_t launch_push3(const Push3Launch& L, const ParticlePtrs3<R>& in,
                         const ParticlePtrs3<R>& out, const PushConst3& pc, hipStream_t stream) {
     if (L.n == 0) return hipSuccess;
+    // start-state records (the adjoint's recomputation): instances of their
+    // own, in the binary64 parity arithmetic with the reduced frame only
+    if (in.b.rec) {
+        if constexpr (!kMixed<R> && GCB_FAST_ARITH == 0) {
+            if (L.exact || L.mirror || L.phase) return hipErrorInvalidValue;
+            return launch_push3_frame<R, T, kMinWaves, kVarReduced, true>(L, in, out, pc,
+                                                                          stream);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if constexpr (!kMixed<R>) {
         if (L.exact && pc.b.curvature)
             return launch_push3_frame<R, T, kMinWaves, kVarExactCurv>(L, in, out, pc, stream);

@@ -146,6 +146,26 @@ def test_multistep_3d(h32, kernel, sort_every, tile):
     assert st["max_fp_residual"] == float(rres.max())
 
 
+@pytest.mark.parametrize("kernel,sort_every,tile,steps", [(TILED, 4, 4, 10), (TILED, 3, 6, 7),
+                                                          (GLOBAL, 4, 0, 6), (AUTO, 1, 4, 3)])
+def test_keep_order_3d(h32, kernel, sort_every, tile, steps):
+    """keep_order in 3D: the particles are cell-sorted and pushed tile by
+    tile, but every one is written back to its own slot, so the arrays keep
+    their order and the switch trace is in slot order without ids.  The
+    state and the trace equal the oracle's in input order, bit for bit."""
+    cfg, F, run = h32
+    ens = cfg.particles(n=4096 + 37, seed_offset=11)
+    log(f"3d keep_order kernel={kernel} sort_every={sort_every} tile={tile} steps={steps}")
+    t = _state(ens, with_id=False)
+    tr, st = run.push(t, steps, trace=True, stats=True, kernel=kernel, sort_every=sort_every,
+                      tile=tile, keep_order=1)
+    ref, rtr, rres = run_oracle3(cfg, F, ens, steps, trace=True)
+    got = {k: v.cpu().numpy() for k, v in t.items() if v is not None}
+    _check(got, ref, cfg, "3d keep_order", tr, rtr)
+    assert st["gca_steps"] == int((rtr == 0).sum())
+    assert st["max_fp_residual"] == float(rres.max())
+
+
 VARIANTS = [
     dict(curvature=0),
     dict(n_iter=1),

@@ -69,6 +69,49 @@ def test_adjoint3_matches_oracle_gradient(curvature):
     assert err <= 2e-5
 
 
+def test_adjoint3_recomputation_kernels_agree():
+    """gcb_push_backward_3d recomputes a segment with the in-place tiled push
+    (sort_every > 0 and a window that fits) or one launch of the global
+    kernel per step (sort_every = 0); both run the parity arithmetic, so the
+    state cotangents are equal bit for bit and the binary32 field cotangents
+    to their accumulation order."""
+    from paper_2007_14401_amd import gcb, state
+    cfg = make_config3("harris3d32")
+    F = cfg.fields()
+    ens = cfg.particles(n=800 + 13, seed_offset=41)
+    steps = 9
+    ctx = gcb.gcb_create(0)
+    try:
+        desc = gcb.grid3_desc(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dz, cfg.stagger,
+                              gcb.GCB_F64)
+        gcb.gcb_load_fields_3d(ctx, desc, [F[0], F[1], F[2]], [F[3], F[4], F[5]])
+        t = state.to_device(ens, DEV, with_id=False)
+        rng = np.random.default_rng(3)
+        lam_end = [torch.as_tensor(rng.normal(size=ens.n), device=DEV) for _ in range(9)]
+        shape = (3, cfg.nz, cfg.ny, cfg.nx)
+        out = {}
+        for se, tile in ((0, 0), (4, 4), (3, 6)):
+            log(f"3d backward recomputation sort_every={se} tile={tile}")
+            lam = [torch.empty(ens.n, dtype=torch.float64, device=DEV) for _ in range(9)]
+            dE = torch.zeros(shape, dtype=torch.float32, device=DEV)
+            dB = torch.zeros(shape, dtype=torch.float32, device=DEV)
+            prm = gcb.params(dt=cfg.dt, c=cfg.c, qm=cfg.qm, f_rho=cfg.f_rho, f_E=cfg.f_E,
+                             curvature=cfg.curvature, n_iter=cfg.n_iter, sort_every=se,
+                             tile=tile)
+            gcb.gcb_push_backward_3d(ctx, gcb.particles3(t), prm, steps, lam_end, lam,
+                                     [dE[0], dE[1], dE[2]], [dB[0], dB[1], dB[2]])
+            torch.cuda.synchronize()
+            out[se] = ([v.cpu().numpy() for v in lam], torch.cat([dE, dB]).cpu().numpy())
+        base_l, base_f = out[0]
+        for se in (4, 3):
+            lam_s, f = out[se]
+            for a, b in zip(lam_s, base_l):
+                assert np.array_equal(a, b), se
+            assert np.max(np.abs(f - base_f)) <= 1e-5 * np.max(np.abs(base_f)), se
+    finally:
+        gcb.gcb_destroy(ctx)
+
+
 def test_adjoint3_checkpoint_segments_do_not_change_gradients():
     cfg = make_config3("harris3d32")
     F = cfg.fields()
