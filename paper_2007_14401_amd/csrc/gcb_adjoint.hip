@@ -1,16 +1,17 @@
 // Reverse-mode derivative of the binary64 push: gcb_push_backward.
 //
-// For a segment of n_steps steps starting from a caller-owned state, the
-// forward steps are recomputed (unsorted, one lane per particle, the same
-// arithmetic as gcb_push) while the start state of every step and its switch
-// decisions are kept; the decisions give each step the list of its
-// guiding-center particles; then, per step in reverse order, two kernels (one
-// per regime; the guiding-center one with one lane per list entry) map the
-// cotangents of the step outputs to those of its inputs and record every
-// gather point with its cotangents.  After a batch of steps a
-// scatter kernel spreads the recorded cotangents over the nodes of a binary32
-// node-interleaved grid (global atomics), which is finally added to the
-// caller's dE/dB arrays.
+// For a segment of n_steps steps starting from a caller-owned state (taken,
+// with its adjoint, into the tile order of the start positions), the host
+// recomputes the forward steps with the push kernels (the tiled push in
+// place when sorting is on, the same parity arithmetic as the forward pass),
+// keeping the start state of every step and its switch decisions; the
+// decisions give each step the list of its guiding-center particles; then,
+// per step in reverse order, two kernels (one per regime; the
+// guiding-center one with one lane per list entry) map the cotangents of the
+// step outputs to those of its inputs and record every gather point with its
+// cotangents.  After a batch of steps a scatter kernel spreads the recorded
+// cotangents over the nodes of a binary32 node-interleaved grid (global
+// atomics), which is finally added to the caller's dE/dB arrays.
 //
 // The scatter is a kernel of its own because atomics on this hardware count
 // against the same wait counter as loads: inside the register-heavy adjoint
