@@ -309,6 +309,29 @@ def test_argument_validation_3d(h32):
         gcb.gcb_destroy(ctx)
 
 
+def test_mixed_keep_order_equals_sorted_push_3d():
+    """keep_order in the 3D precision form: the same results as the
+    permuting sort (particles are independent), in input order without ids."""
+    from paper_2007_14401_amd import gcb, state
+    cfg = make_config3("harris3d32")
+    F = cfg.fields()
+    run = GpuRun3(cfg, F, dtype=gcb.GCB_F32)
+    try:
+        ens = cfg.particles(n=4096 + 37, seed_offset=12)
+        a = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED)
+        tr_a, _ = run.push(a, 8, trace=True, kernel=TILED, sort_every=4, tile=4,
+                           form=gcb.GCB_FORM_MIXED)
+        b = state.to_device(ens, "cuda:0", form=gcb.GCB_FORM_MIXED, with_id=False)
+        tr_b, _ = run.push(b, 8, trace=True, kernel=TILED, sort_every=4, tile=4,
+                           form=gcb.GCB_FORM_MIXED, keep_order=1)
+        ua = state.unsort(a)
+        for k in ("x", "y", "z", "xp", "yp", "zp", "ux", "uy", "uz", "status"):
+            assert np.array_equal(ua[k], b[k].cpu().numpy()), k
+        assert torch.equal(tr_a, tr_b)
+    finally:
+        run.close()
+
+
 @pytest.mark.parametrize("kernel,sort_every,tile", [(GLOBAL, 0, 0), (TILED, 2, 6)])
 def test_mixed_one_step_3d(kernel, sort_every, tile):
     """Mixed form against the binary64 oracle, one step: the bounds of the 2D
